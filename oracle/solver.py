@@ -1,0 +1,109 @@
+"""Fixed-iteration Jacobi-preconditioned CG and one reconstructor time step
+(Sec. 3.3, Algorithm 1 in open loop, with F = I).
+
+Readings:
+* The paper's preconditioner input J^{-1/2} (split form) and the textbook
+  form z = J^{-1} r give the same iterates in exact arithmetic; the textbook
+  form is used.
+* The augmented Krylov recycling of the previous search directions is not
+  specified in the paper (it cites another paper for it); the step uses the
+  warm restart only: initial guess c^(i), r_0 = (b^(i+1) - b^(i)) + r^(i).
+* r^(i) is the final recurrence residual of the previous step.
+* Open loop, a^(i+1) = (1 - gain) a^(i) + gain * F W^{-1} c^(i+1), F = I when
+  the reconstruction layers sit at the DM altitudes.
+"""
+
+import numpy as np
+
+
+def pcg(apply_M, x0, r0, Jdiag, iters, record=None):
+    """Textbook PCG for a fixed number of iterations (no convergence test).
+    Returns (x, r, history) with history the per-iteration (rho, pi); the
+    search directions are appended to ``record`` when it is a list."""
+    x = np.array(x0, dtype=np.float64, copy=True)
+    r = np.array(r0, dtype=np.float64, copy=True)
+    z = r / Jdiag
+    p = z.copy()
+    rho = r @ z
+    hist = []
+    for _ in range(iters):
+        if record is not None:
+            record.append(p.copy())
+        q = apply_M(p)
+        pi = p @ q
+        a = rho / pi
+        x += a * p
+        r -= a * q
+        z = r / Jdiag
+        rho_new = r @ z
+        hist.append((rho, pi))
+        beta = rho_new / rho
+        p = z + beta * p
+        rho = rho_new
+    return x, r, hist
+
+
+def pcg_to_tolerance(apply_M, b, Jdiag, rtol=1e-12, max_iters=100000, x0=None):
+    """PCG from x0 (default 0) until ||r|| <= rtol ||b|| (used as the exact
+    MAP solution c* = M^{-1} b for convergence checks)."""
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    r = b - apply_M(x) if x0 is not None else np.array(b, dtype=np.float64, copy=True)
+    z = r / Jdiag
+    p = z.copy()
+    rho = r @ z
+    nb = np.linalg.norm(b)
+    it = 0
+    while np.linalg.norm(r) > rtol * nb and it < max_iters:
+        q = apply_M(p)
+        a = rho / (p @ q)
+        x += a * p
+        r -= a * q
+        z = r / Jdiag
+        rho_new = r @ z
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+        it += 1
+    return x, it
+
+
+class State:
+    """Algorithm 1's state between frames: c, b, r, a^(i-1), a^(i)."""
+
+    def __init__(self, n_coeff, n_act):
+        self.c = np.zeros(n_coeff)
+        self.b = np.zeros(n_coeff)
+        self.r = np.zeros(n_coeff)
+        self.a_prev = np.zeros(n_act)
+        self.a = np.zeros(n_act)
+
+    def pack(self):
+        return np.concatenate([self.c, self.b, self.r, self.a_prev, self.a])
+
+    @classmethod
+    def unpack(cls, v, n_coeff, n_act):
+        st = cls(n_coeff, n_act)
+        v = np.asarray(v, dtype=np.float64)
+        o = 0
+        for name, n in (("c", n_coeff), ("b", n_coeff), ("r", n_coeff), ("a_prev", n_act), ("a", n_act)):
+            setattr(st, name, v[o:o + n].copy())
+            o += n
+        return st
+
+
+def frame(system, state, s, iters=None, gain=None):
+    """One open-loop time step; returns (new_state, layers phi = W^{-1} c)."""
+    cfg = system.cfg
+    iters = cfg["iters"] if iters is None else iters
+    gain = cfg["gain"] if gain is None else gain
+    b = system.rhs(s)
+    r0 = (b - state.b) + state.r
+    J = system.preconditioner()
+    x, r, _ = pcg(system.apply_M, state.c, r0, J, iters)
+    phi = system.W_inv(x)
+    new = State(len(x), len(state.a))
+    new.c = x
+    new.b = b
+    new.r = r
+    new.a_prev = state.a.copy()
+    new.a = (1.0 - gain) * state.a + gain * phi
+    return new, phi

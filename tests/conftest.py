@@ -1,0 +1,30 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (HIP device) and the built library")
+    config.addinivalue_line("markers", "slow: oracle work above a few seconds")
+
+
+@pytest.fixture(scope="session")
+def systems():
+    """Cache of oracle systems per configuration name."""
+    from oracle.operators import System
+    from synthetic import get_config
+
+    cache = {}
+
+    def get(name, **overrides):
+        key = (name, tuple(sorted((k, repr(v)) for k, v in overrides.items())))
+        if key not in cache:
+            cache[key] = System(get_config(name, **overrides))
+        return cache[key]
+
+    return get
