@@ -1,0 +1,219 @@
+/*
+ * fewha.h -- C ABI of libfewha, an MI355X (gfx950) implementation of the hot
+ * path of FEWHA, the Finite Element Wavelet Hybrid Algorithm for atmospheric
+ * tomography (Stadler & Ramlau, arXiv 2202.11945).
+ *
+ * The library solves, for every frame, the wavelet-domain MAP system
+ * (eq. fewha / eq. M):
+ *     M c = b,  M = W^{-T} A^T C_hat^{-1} A W^{-1} + alpha D,
+ *               b = W^{-T} A^T C_hat^{-1} s,
+ * with a fixed number of Jacobi-preconditioned CG iterations (eq. precond),
+ * warm-started from the previous frame (Sec. 3.3, Algorithm 1, open loop),
+ * and returns the layers W^{-1} c and the DM commands (F = I when the layers
+ * sit at the DM altitudes, Sec. 4.1).
+ *
+ * Conventions shared by every call:
+ *  - Sensor g has N_g x N_g subapertures of pitch d = D / N_g; its corners are
+ *    x_j = -D/2 + j d (j = 0..N_g), row index i = y, column index j = x.
+ *  - Slopes of sensor g: [s^x over its active subapertures in row-major
+ *    order; s^y in the same order] (Sec. 2); sensors concatenated in the
+ *    order given to fewha_set_wfs.  s^x, s^y are phase differences across a
+ *    subaperture (rad), the average slope of the bilinear wavefront (Sec. 2).
+ *  - Layer l: n_l x n_l nodes (n_l = 2^J_l, Sec. 3.1), row-major (rows = y),
+ *    on a centred square domain of side L shared by all layers; the node
+ *    spacing is delta_l = L / n_l.  Layers are concatenated in order.
+ *  - Wavelet coefficients: periodic Daubechies-3, Mallat layout per layer,
+ *    the same n_l x n_l footprint; W_l = delta_l W.
+ *  - All float* compute arguments are DEVICE pointers owned by the caller;
+ *    the library never frees them.  Compute calls are asynchronous on the
+ *    context's stream (fewha_set_stream; default: the null stream).
+ *  - Argument and state errors are returned before anything is enqueued.
+ *    A device error is returned as FEWHA_EDEVICE by the call that sees it.
+ *    No C++ exception crosses this interface.
+ *  - A context is not thread-safe; distinct contexts may be used from
+ *    distinct threads.
+ */
+#ifndef FEWHA_H
+#define FEWHA_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FEWHA_API __attribute__((visibility("default")))
+
+typedef struct fewha_ctx fewha_ctx;
+typedef struct fewha_batch fewha_batch;
+
+typedef enum {
+  FEWHA_OK = 0,
+  FEWHA_EINVAL = -1,   /* bad argument (null pointer, size, range)          */
+  FEWHA_ENOMEM = -2,   /* host or device allocation failed                  */
+  FEWHA_EDEVICE = -3,  /* HIP runtime error                                 */
+  FEWHA_ESTATE = -4,   /* call not valid in the context's current state     */
+  FEWHA_EGEOM = -5,    /* geometry rejected (footprint leaves a layer, ...)  */
+  FEWHA_ENUMERIC = -6  /* numerical breakdown (non-positive p^T M p)         */
+} fewha_status;
+
+enum { FEWHA_NGS = 0, FEWHA_LGS = 1 };
+
+/* One Shack-Hartmann wavefront sensor and its guide star (Sec. 2, Table 4). */
+typedef struct {
+  int kind;            /* FEWHA_NGS or FEWHA_LGS                                   */
+  int n_subap;         /* N: N x N subapertures, (N+1)^2 corners; 1..4096          */
+  double theta_x;      /* guide-star direction (rad)                               */
+  double theta_y;
+  double H;            /* LGS altitude (m), > every layer altitude; NGS: ignored   */
+  double sigma;        /* slope noise std (rad): C_g = sigma^2 I (eq. NGS-noise)   */
+  double launch_x;     /* LGS laser launch position in the pupil (m), used for the */
+  double launch_y;     /*   spot elongation of eq. (LGS-noise)                     */
+  int tt_removal;      /* LGS: 1 = C_hat_g^{-1} = (I-T) C_g^{-1} (I-T) (Sec. 3.2)  */
+  const unsigned char* mask; /* host N*N row-major active flags, or NULL for the
+                                annulus rule: active iff the subaperture centre
+                                lies in [sqrt(obstruction) D/2, D/2]. Copied.     */
+} fewha_wfs_desc;
+
+/* One reconstruction layer (Sec. 2 layered model, Table 2). */
+typedef struct {
+  double h;            /* altitude (m), >= 0                                       */
+  int n;               /* grid side, power of two, 8..2048                         */
+  int levels;          /* wavelet decomposition depth; n >> levels in [1, 128]     */
+  double cn2;          /* fractional turbulence weight gamma_l (> 0)               */
+} fewha_layer_desc;
+
+/* One deformable mirror for the fitting step (Sec. 4.1, Table 3). */
+typedef struct {
+  double h;            /* conjugation altitude (m)                                 */
+  int n_act;           /* n_act x n_act actuators, bilinear influence              */
+  double pitch;        /* actuator spacing (m); the grid is centred on the axis    */
+} fewha_dm_desc;
+
+/* ---- context set-up (host only; no device work until fewha_finalize) ---- */
+
+/* Create a context for HIP device `device`, or a host-only context when
+ * device < 0 (set-up and table queries only; compute calls then return
+ * FEWHA_ESTATE).  *out receives the context; FEWHA_EDEVICE if the device
+ * cannot be selected. */
+FEWHA_API fewha_status fewha_create(fewha_ctx** out, int device);
+
+/* Stream (a hipStream_t passed as void*) on which compute calls enqueue. */
+FEWHA_API fewha_status fewha_set_stream(fewha_ctx* ctx, void* hip_stream);
+
+/* Telescope diameter D (m) and obstructed area fraction in [0, 1). */
+FEWHA_API fewha_status fewha_set_pupil(fewha_ctx* ctx, double D, double obstruction);
+
+/* G >= 1 sensors, copied. Sec. 2: A = [Gamma_g P_g]. */
+FEWHA_API fewha_status fewha_set_wfs(fewha_ctx* ctx, int G, const fewha_wfs_desc* wfs);
+
+/* L >= 1 layers on a common square domain of side domain_side (m). */
+FEWHA_API fewha_status fewha_set_layers(fewha_ctx* ctx, int L, const fewha_layer_desc* layers,
+                                        double domain_side);
+
+/* Prior and preconditioner (eq. fewha, eq. precond): regularisation weight
+ * alpha > 0; Fried parameter r0 (m) and outer scale L0 (m) of the diagonal
+ * prior D; preconditioner threshold tau >= 0 (J = diag(data) + alpha max(D, tau)).
+ * D, per coefficient at level block size 2^j, is the inverse of the von Karman
+ * spectrum 0.023 gamma_l r0^{-5/3} ((2^j/L)^2 + L0^{-2})^{-11/6}. */
+FEWHA_API fewha_status fewha_set_prior(fewha_ctx* ctx, double alpha, double r0, double L0, double tau);
+
+/* LGS spot elongation (eq. LGS-noise): alpha_eta >= 0 (0 = no elongation),
+ * sodium-layer FWHM (m), non-elongated spot FWHM f (rad, > 0). */
+FEWHA_API fewha_status fewha_set_noise(fewha_ctx* ctx, double alpha_eta, double na_fwhm, double spot_fwhm);
+
+/* Open-loop gain of Algorithm 1 (gain control lines): a <- (1-gain) a + gain a~. */
+FEWHA_API fewha_status fewha_set_control(fewha_ctx* ctx, double gain);
+
+/* Validate the geometry and build every table: sensor masks, bilinear
+ * propagation tables, the prior D and the exact Jacobi diagonal J
+ * (eq. precond).  On a device context, upload the tables and allocate the
+ * device work space.  FEWHA_EGEOM if a sensor footprint leaves a layer
+ * (no periodic wrap in P) or a size is unsupported. */
+FEWHA_API fewha_status fewha_finalize(fewha_ctx* ctx);
+
+/* Sizes after finalize (any pointer may be NULL):
+ *   n_coeff     = N_c = sum_l n_l^2 (wavelet coefficients = layer nodes)
+ *   n_slopes    = sum_g 2 |M_g|
+ *   n_layer_pts = N_c
+ *   n_act       = number of DM commands (= N_c when F = I)
+ *   n_state     = 3 N_c + 2 n_act (layout of the reconstruct state below). */
+FEWHA_API fewha_status fewha_sizes(const fewha_ctx* ctx, long* n_coeff, long* n_slopes,
+                                   long* n_layer_pts, long* n_act, long* n_state);
+
+/* Host copies of set-up tables, for inspection and tests (after finalize):
+ *   FEWHA_TABLE_FILTER  : the 6 db3 lowpass taps                      (6)
+ *   FEWHA_TABLE_PRIOR   : D per coefficient                           (N_c)
+ *   FEWHA_TABLE_PRECOND : J per coefficient (eq. precond)             (N_c)
+ *   FEWHA_TABLE_MASK    : active flags of every sensor, concatenated  (sum N_g^2)
+ * `n` is the capacity of `out` (host); FEWHA_EINVAL if too small. */
+enum { FEWHA_TABLE_FILTER = 0, FEWHA_TABLE_PRIOR = 1, FEWHA_TABLE_PRECOND = 2, FEWHA_TABLE_MASK = 3 };
+FEWHA_API fewha_status fewha_get_table(const fewha_ctx* ctx, int which, double* out, long n);
+
+/* ---- compute (device pointers, asynchronous on the context stream) ---- */
+
+/* slopes = A phi (eq. atmo, s_g = Gamma_g P_g phi): layers (N_c floats, FE
+ * domain) -> slopes (n_slopes floats). */
+FEWHA_API fewha_status fewha_apply_A(fewha_ctx* ctx, const float* layers, float* slopes);
+
+/* layers = A^T slopes (plain transpose, no noise weighting). */
+FEWHA_API fewha_status fewha_apply_AT(fewha_ctx* ctx, const float* slopes, float* layers);
+
+/* Mc = M c (eq. M), wavelet domain, N_c floats each. */
+FEWHA_API fewha_status fewha_apply_M(fewha_ctx* ctx, const float* c, float* Mc);
+
+/* b = W^{-T} A^T C_hat^{-1} s (right-hand side of eq. fewha). */
+FEWHA_API fewha_status fewha_rhs(fewha_ctx* ctx, const float* slopes, float* b);
+
+/* One time step of Algorithm 1 (open loop, F = I, plain warm restart):
+ *   b' = rhs(slopes); r0 = (b' - b) + r; c <- PCG(c, r0, J, iters);
+ *   phi = W^{-1} c; a_prev <- a; a <- (1-gain) a + gain phi.
+ * state (in/out, n_state floats) = [c | b | r | a_prev | a]; an all-zero
+ * state starts a sequence (c = 0, r0 = b').  layers_out (N_c) and dm_out
+ * (n_act) may be NULL.  iters in [0, 256].  PCG inner products and the
+ * alpha/beta recurrences are computed in double precision. */
+FEWHA_API fewha_status fewha_reconstruct(fewha_ctx* ctx, const float* slopes, float* state,
+                                         float* layers_out, float* dm_out, int iters);
+
+/* ---- batches: many independent problems per launch ---- */
+
+/* Group n finalized device contexts (same device; geometries may differ)
+ * into a batch whose every stage is one launch over all problems.  The
+ * contexts must outlive the batch. */
+FEWHA_API fewha_status fewha_batch_create(fewha_batch** out, fewha_ctx* const* ctxs, int n);
+FEWHA_API fewha_status fewha_batch_set_stream(fewha_batch* b, void* hip_stream);
+
+/* fewha_reconstruct for every problem k with slopes[k], state[k],
+ * layers_out[k], dm_out[k] (host arrays of device pointers; the last two
+ * may be NULL or hold NULLs).  use_graph = 1 replays a HIP graph of the
+ * whole step (captured on first use for this iteration count). */
+FEWHA_API fewha_status fewha_batch_reconstruct(fewha_batch* b, const float* const* slopes,
+                                               float* const* state, float* const* layers_out,
+                                               float* const* dm_out, int iters, int use_graph);
+
+/* Stage identifiers for fewha_batch_time_stage. */
+enum {
+  FEWHA_STAGE_IDWT_RES = 0, FEWHA_STAGE_IDWT_GLOB = 1, FEWHA_STAGE_P_GAMMA = 2,
+  FEWHA_STAGE_GAMMA_T = 3, FEWHA_STAGE_P_T = 4, FEWHA_STAGE_FDWT_GLOB = 5,
+  FEWHA_STAGE_FDWT_RES = 6, FEWHA_STAGE_UPDATE = 7, FEWHA_STAGE_COUNT = 8
+};
+
+/* Average device time (microseconds) of `reps` back-to-back launches of one
+ * PCG-iteration stage over the whole batch, measured with HIP events on the
+ * batch stream, in the launch configuration used by batch_reconstruct.
+ * Must follow at least one fewha_batch_reconstruct (uses its buffers).
+ * Also returns the stage's launch geometry (workgroups). */
+FEWHA_API fewha_status fewha_batch_time_stage(fewha_batch* b, int stage, int reps, double* avg_us,
+                                              long* workgroups);
+
+FEWHA_API void fewha_batch_destroy(fewha_batch* b);
+
+/* Last error message of a context (never NULL). */
+FEWHA_API const char* fewha_last_error(const fewha_ctx* ctx);
+FEWHA_API const char* fewha_batch_last_error(const fewha_batch* b);
+
+FEWHA_API void fewha_destroy(fewha_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEWHA_H */

@@ -1,0 +1,875 @@
+// C ABI of libfewha: contexts (one configured problem), plans (device
+// tables, work buffers and tile work lists of one or many problems), the
+// launch sequences of every entry point, and HIP graph capture.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fewha_internal.h"
+#include "kernels.h"
+
+using namespace fewha;
+
+namespace {
+
+constexpr int kRing = 8;          // pinned staging slots for per-call I/O tables
+constexpr int kMaxIters = 256;    // PCG iterations per call
+
+int ilog2i(int n) {
+  int k = 0;
+  while ((1 << k) < n) ++k;
+  return k;
+}
+int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+struct Range {
+  int off = 0, n = 0;
+};
+
+// Device plan of one or more finalized problems.
+struct Plan {
+  int device = -1;
+  int nprob = 0;
+  std::vector<const HostModel*> models;
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  ProbDev* dP = nullptr;
+  LayerDev* dL = nullptr;
+  WfsDev* dW = nullptr;
+  IoDev* dIO = nullptr;
+  IoDev* dIOprof = nullptr;
+  Tile* dT = nullptr;
+  std::vector<ProbDev> hP;
+  std::vector<LayerDev> hL;
+  std::vector<WfsDev> hW;
+  std::vector<Tile> hT;
+  Range idwt_res, fdwt_res, pg, gt, pt, upd;
+  std::vector<Range> idwt_glob, fdwt_glob;
+  Filter F{};
+  IoDev* pinned[kRing] = {nullptr};
+  hipEvent_t ev[kRing] = {nullptr};
+  bool ev_used[kRing] = {false};
+  int ring = 0;
+  std::map<int, hipGraphExec_t> graphs;
+  std::map<int, hipGraph_t> graph_defs;
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  std::vector<float*> prof_state;
+  std::vector<long> n_state;
+  std::vector<IoDev> last_io;
+  bool ran = false;
+};
+
+#define HIP_TRY(expr)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      err = std::string(#expr) + ": " + hipGetErrorString(e_);                 \
+      return FEWHA_EDEVICE;                                                    \
+    }                                                                          \
+  } while (0)
+
+void destroy_plan(Plan* p) {
+  if (!p) return;
+  if (p->device >= 0) (void)hipSetDevice(p->device);
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : p->graph_defs) (void)hipGraphDestroy(kv.second);
+  for (int i = 0; i < kRing; ++i) {
+    if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
+    if (p->pinned[i]) (void)hipHostFree(p->pinned[i]);
+  }
+  for (float* s : p->prof_state)
+    if (s) (void)hipFree(s);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->t0) (void)hipEventDestroy(p->t0);
+  if (p->t1) (void)hipEventDestroy(p->t1);
+  if (p->arena) (void)hipFree(p->arena);
+  delete p;
+}
+
+// Byte-offset carving of the arena (256-byte aligned pieces).
+struct Carver {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    size_t o = off;
+    off += bytes;
+    return o;
+  }
+};
+
+fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models, int device, std::string& err) {
+  std::unique_ptr<Plan> pl(new (std::nothrow) Plan());
+  if (!pl) {
+    err = "out of host memory";
+    return FEWHA_ENOMEM;
+  }
+  Plan& P = *pl;
+  P.device = device;
+  P.nprob = (int)models.size();
+  P.models = models;
+  HIP_TRY(hipSetDevice(device));
+  {
+    const HostModel& m0 = *models[0];
+    for (int i = 0; i < 6; ++i) {
+      P.F.h[i] = (float)m0.h[i];
+      P.F.g[i] = (float)m0.g[i];
+    }
+  }
+  // ---- descriptors and tile lists ----
+  struct ProbLayout {
+    size_t phi, phiadj, tmpa, tmpb, sd, vadj, part, p0, p1, q, dots, jinv, itab, ftab, cmap, cinv;
+  };
+  std::vector<ProbLayout> lay(P.nprob);
+  Carver cv;
+  std::vector<Tile> t_idwt_res, t_fdwt_res, t_pg, t_gt, t_pt, t_upd;
+  std::vector<std::vector<Tile>> t_idwt_glob, t_fdwt_glob;
+  // host table images per problem (copied after allocation)
+  std::vector<std::vector<int>> itab(P.nprob), cmap(P.nprob);
+  std::vector<std::vector<float>> ftab(P.nprob), cinv(P.nprob), jinv(P.nprob);
+  for (int k = 0; k < P.nprob; ++k) {
+    const HostModel& m = *models[k];
+    ProbDev pd{};
+    const int L = (int)m.layers.size(), G = (int)m.wfs.size();
+    pd.L = L;
+    pd.G = G;
+    pd.layer0 = (int)P.hL.size();
+    pd.wfs0 = (int)P.hW.size();
+    pd.n_c = (int)m.n_c;
+    pd.n_slopes = (int)m.n_slopes;
+    pd.n_act = (int)m.n_c;
+    pd.gain = (float)m.gain;
+    int tmp_total = 0, nmax = 0;
+    for (int l = 0; l < L; ++l) {
+      const LayerHost& lh = m.layers[l];
+      LayerDev ld{};
+      ld.n = lh.d.n;
+      ld.log2n = ilog2i(ld.n);
+      ld.levels = lh.d.levels;
+      ld.res = std::min(ld.n, kResMax);
+      ld.off = m.layer_off[l];
+      ld.n_glob_levels = ilog2i(ld.n / ld.res);
+      ld.tmp_off = tmp_total;
+      if (ld.n > ld.res) tmp_total += ld.n * ld.n / 4;
+      ld.inv_delta = (float)(1.0 / lh.delta);
+      for (int j = 0; j < kMaxLevelsJ; ++j) ld.alpha_d[j] = (float)(m.alpha * lh.dtab[j]);
+      P.hL.push_back(ld);
+      nmax = std::max(nmax, ld.n);
+    }
+    int s_tot = 0, v_tot = 0, m_tot = 0, part_tot = 0, tab_tot = 0;
+    for (int g = 0; g < G; ++g) {
+      const WfsHost& wh = m.wfs[g];
+      WfsDev wd{};
+      wd.N = wh.d.n_subap;
+      wd.nc = wd.N + 1;
+      wd.lgs = wh.d.kind == FEWHA_LGS;
+      wd.tt = wd.lgs && wh.d.tt_removal;
+      wd.blocks = wd.lgs && m.alpha_eta > 0.0;
+      wd.n_active = wh.n_active;
+      wd.s_off = s_tot;
+      s_tot += 2 * wd.N * wd.N;
+      wd.v_off = v_tot;
+      v_tot += wd.nc * wd.nc;
+      wd.cs_off = m.slope_off[g];
+      wd.m_off = m_tot;
+      wd.cinv_off = 3 * m_tot;
+      m_tot += wd.N * wd.N;
+      wd.tiles_side = cdiv(wd.N, kTileS);
+      wd.n_tiles_s = wd.tiles_side * wd.tiles_side;
+      wd.part_off = part_tot;
+      part_tot += 4 * wd.n_tiles_s;
+      wd.tab_stride = 4 * wd.nc + 4 * nmax;
+      wd.tab_off = tab_tot;
+      tab_tot += L * wd.tab_stride;
+      wd.inv_sigma2 = (float)(1.0 / (wh.d.sigma * wh.d.sigma));
+      wd.inv_nM = (float)(1.0 / wh.n_active);
+      for (int v = 0; v < 4; ++v) wd.sum_cinv[v] = (float)wh.sum_cinv[v];
+      P.hW.push_back(wd);
+    }
+    // table images
+    itab[k].assign(tab_tot, 0);
+    ftab[k].assign(tab_tot, 0.f);
+    cmap[k].assign(m_tot, -1);
+    cinv[k].assign(3 * (size_t)m_tot, 0.f);
+    for (int g = 0; g < G; ++g) {
+      const WfsDev& wd = P.hW[pd.wfs0 + g];
+      const WfsHost& wh = m.wfs[g];
+      for (int e = 0; e < wd.N * wd.N; ++e) cmap[k][wd.m_off + e] = wh.cmap[e];
+      for (int e = 0; e < 3 * wd.N * wd.N; ++e) cinv[k][wd.cinv_off + e] = (float)wh.cinv[e];
+      for (int l = 0; l < L; ++l) {
+        const GLTables& t = m.tab[g][l];
+        const int base = wd.tab_off + l * wd.tab_stride, nc = wd.nc, n = m.layers[l].d.n;
+        for (int j = 0; j < nc; ++j) {
+          itab[k][base + j] = t.q0y[j];
+          itab[k][base + nc + j] = t.q0x[j];
+          ftab[k][base + 2 * nc + j] = (float)t.wy[j];
+          ftab[k][base + 3 * nc + j] = (float)t.wx[j];
+        }
+        for (int p = 0; p < n; ++p) {
+          itab[k][base + 4 * nc + p] = t.ay0[p];
+          itab[k][base + 4 * nc + n + p] = t.ayc[p];
+          itab[k][base + 4 * nc + 2 * n + p] = t.ax0[p];
+          itab[k][base + 4 * nc + 3 * n + p] = t.axc[p];
+        }
+      }
+    }
+    jinv[k].resize(m.n_c);
+    for (long e = 0; e < m.n_c; ++e) jinv[k][e] = (float)(1.0 / m.J[e]);
+    // tiles
+    int slot = 0;
+    int maxng = 0;
+    for (int l = 0; l < L; ++l) maxng = std::max(maxng, P.hL[pd.layer0 + l].n_glob_levels);
+    if ((int)t_fdwt_glob.size() < maxng) {
+      t_fdwt_glob.resize(maxng);
+      t_idwt_glob.resize(maxng);
+    }
+    for (int s = 0; s < maxng; ++s)
+      for (int l = 0; l < L; ++l) {
+        const LayerDev& ld = P.hL[pd.layer0 + l];
+        if (ld.n_glob_levels <= s) continue;
+        const int mf = ld.n >> s;  // forward: input side
+        const int tq = (mf / 2) / 16;
+        for (int ty = 0; ty < tq; ++ty)
+          for (int tx = 0; tx < tq; ++tx) t_fdwt_glob[s].push_back({k, l, ty, tx, slot++, ilog2i(mf), 0, 0});
+        const int mi = ld.res << (s + 1);  // inverse: output side
+        const int ti = mi / 32;
+        for (int ty = 0; ty < ti; ++ty)
+          for (int tx = 0; tx < ti; ++tx) t_idwt_glob[s].push_back({k, l, ty, tx, 0, ilog2i(mi), 0, 0});
+      }
+    for (int l = 0; l < L; ++l) {
+      t_idwt_res.push_back({k, l, 0, 0, 0, 0, 0, 0});
+      t_fdwt_res.push_back({k, l, 0, 0, slot++, 0, 0, 0});
+    }
+    pd.n_slots_fdwt = slot;
+    const int nupd = cdiv(pd.n_c, kUpdChunk);
+    for (int c = 0; c < nupd; ++c) t_upd.push_back({k, 0, c, 0, c, 0, 0, 0});
+    pd.n_slots_upd = nupd;
+    pd.n_dots = std::max(pd.n_slots_fdwt, pd.n_slots_upd);
+    for (int g = 0; g < G; ++g) {
+      const WfsDev& wd = P.hW[pd.wfs0 + g];
+      for (int ty = 0; ty < wd.tiles_side; ++ty)
+        for (int tx = 0; tx < wd.tiles_side; ++tx) t_pg.push_back({k, g, ty, tx, 0, 0, 0, 0});
+      const int tc = cdiv(wd.nc, kTileS);
+      for (int ty = 0; ty < tc; ++ty)
+        for (int tx = 0; tx < tc; ++tx) t_gt.push_back({k, g, ty, tx, 0, 0, 0, 0});
+    }
+    for (int l = 0; l < L; ++l) {
+      const int tn = cdiv(P.hL[pd.layer0 + l].n, kTileN);
+      for (int ty = 0; ty < tn; ++ty)
+        for (int tx = 0; tx < tn; ++tx) t_pt.push_back({k, l, ty, tx, 0, 0, 0, 0});
+    }
+    // buffer layout
+    ProbLayout& pl_ = lay[k];
+    const size_t nc4 = sizeof(float) * (size_t)pd.n_c;
+    pl_.phi = cv.take(nc4);
+    pl_.phiadj = cv.take(nc4);
+    pl_.tmpa = cv.take(sizeof(float) * std::max(tmp_total, 1));
+    pl_.tmpb = cv.take(sizeof(float) * std::max(tmp_total, 1));
+    pl_.sd = cv.take(sizeof(float) * s_tot);
+    pl_.vadj = cv.take(sizeof(float) * v_tot);
+    pl_.part = cv.take(sizeof(float) * part_tot);
+    pl_.p0 = cv.take(nc4);
+    pl_.p1 = cv.take(nc4);
+    pl_.q = cv.take(nc4);
+    pl_.dots = cv.take(sizeof(double) * (size_t)(2 * kMaxIters + 2) * pd.n_dots);
+    pl_.jinv = cv.take(nc4);
+    pl_.itab = cv.take(sizeof(int) * tab_tot);
+    pl_.ftab = cv.take(sizeof(float) * tab_tot);
+    pl_.cmap = cv.take(sizeof(int) * m_tot);
+    pl_.cinv = cv.take(sizeof(float) * 3 * (size_t)m_tot);
+    P.hP.push_back(pd);
+  }
+  // concatenated tile list
+  auto add = [&](std::vector<Tile>& v) {
+    Range r;
+    r.off = (int)P.hT.size();
+    r.n = (int)v.size();
+    P.hT.insert(P.hT.end(), v.begin(), v.end());
+    return r;
+  };
+  P.idwt_res = add(t_idwt_res);
+  P.fdwt_res = add(t_fdwt_res);
+  P.pg = add(t_pg);
+  P.gt = add(t_gt);
+  P.pt = add(t_pt);
+  P.upd = add(t_upd);
+  for (auto& v : t_idwt_glob) P.idwt_glob.push_back(add(v));
+  for (auto& v : t_fdwt_glob) P.fdwt_glob.push_back(add(v));
+  const size_t oP = cv.take(sizeof(ProbDev) * P.nprob);
+  const size_t oL = cv.take(sizeof(LayerDev) * P.hL.size());
+  const size_t oW = cv.take(sizeof(WfsDev) * P.hW.size());
+  const size_t oIO = cv.take(sizeof(IoDev) * P.nprob);
+  const size_t oIOp = cv.take(sizeof(IoDev) * P.nprob);
+  const size_t oT = cv.take(sizeof(Tile) * std::max<size_t>(P.hT.size(), 1));
+  P.arena_bytes = cv.off;
+  {
+    hipError_t e = hipMalloc(&P.arena, P.arena_bytes);
+    if (e != hipSuccess) {
+      err = std::string("device allocation of ") + std::to_string(P.arena_bytes) + " bytes failed";
+      return FEWHA_ENOMEM;
+    }
+  }
+  HIP_TRY(hipMemset(P.arena, 0, P.arena_bytes));
+  char* base = (char*)P.arena;
+  for (int k = 0; k < P.nprob; ++k) {
+    ProbDev& pd = P.hP[k];
+    const ProbLayout& l = lay[k];
+    pd.phi = (float*)(base + l.phi);
+    pd.phiadj = (float*)(base + l.phiadj);
+    pd.tmpa = (float*)(base + l.tmpa);
+    pd.tmpb = (float*)(base + l.tmpb);
+    pd.sd = (float*)(base + l.sd);
+    pd.vadj = (float*)(base + l.vadj);
+    pd.part = (float*)(base + l.part);
+    pd.pbuf0 = (float*)(base + l.p0);
+    pd.pbuf1 = (float*)(base + l.p1);
+    pd.q = (float*)(base + l.q);
+    pd.dots = (double*)(base + l.dots);
+    pd.jinv = (const float*)(base + l.jinv);
+    pd.itab = (const int*)(base + l.itab);
+    pd.ftab = (const float*)(base + l.ftab);
+    pd.cmap = (const int*)(base + l.cmap);
+    pd.cinv = (const float*)(base + l.cinv);
+    HIP_TRY(hipMemcpy(base + l.jinv, jinv[k].data(), sizeof(float) * jinv[k].size(), hipMemcpyHostToDevice));
+    if (!itab[k].empty()) {
+      HIP_TRY(hipMemcpy(base + l.itab, itab[k].data(), sizeof(int) * itab[k].size(), hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(base + l.ftab, ftab[k].data(), sizeof(float) * ftab[k].size(), hipMemcpyHostToDevice));
+    }
+    HIP_TRY(hipMemcpy(base + l.cmap, cmap[k].data(), sizeof(int) * cmap[k].size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(base + l.cinv, cinv[k].data(), sizeof(float) * cinv[k].size(), hipMemcpyHostToDevice));
+  }
+  P.dP = (ProbDev*)(base + oP);
+  P.dL = (LayerDev*)(base + oL);
+  P.dW = (WfsDev*)(base + oW);
+  P.dIO = (IoDev*)(base + oIO);
+  P.dIOprof = (IoDev*)(base + oIOp);
+  P.dT = (Tile*)(base + oT);
+  HIP_TRY(hipMemcpy(P.dP, P.hP.data(), sizeof(ProbDev) * P.nprob, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(P.dL, P.hL.data(), sizeof(LayerDev) * P.hL.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(P.dW, P.hW.data(), sizeof(WfsDev) * P.hW.size(), hipMemcpyHostToDevice));
+  if (!P.hT.empty()) HIP_TRY(hipMemcpy(P.dT, P.hT.data(), sizeof(Tile) * P.hT.size(), hipMemcpyHostToDevice));
+  for (int i = 0; i < kRing; ++i) {
+    HIP_TRY(hipHostMalloc((void**)&P.pinned[i], sizeof(IoDev) * P.nprob, hipHostMallocDefault));
+    HIP_TRY(hipEventCreateWithFlags(&P.ev[i], hipEventDisableTiming));
+  }
+  HIP_TRY(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreate(&P.t0));
+  HIP_TRY(hipEventCreate(&P.t1));
+  P.n_state.resize(P.nprob);
+  for (int k = 0; k < P.nprob; ++k) P.n_state[k] = 3L * P.hP[k].n_c + 2L * P.hP[k].n_act;
+  out = pl.release();
+  return FEWHA_OK;
+}
+
+// Stage the per-call I/O table and copy it to the device (stream ordered).
+fewha_status upload_io(Plan& P, const std::vector<IoDev>& io, hipStream_t s, IoDev* dst, std::string& err) {
+  const int slot = P.ring;
+  P.ring = (P.ring + 1) % kRing;
+  if (P.ev_used[slot]) HIP_TRY(hipEventSynchronize(P.ev[slot]));
+  std::memcpy(P.pinned[slot], io.data(), sizeof(IoDev) * P.nprob);
+  HIP_TRY(hipMemcpyAsync(dst, P.pinned[slot], sizeof(IoDev) * P.nprob, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(P.ev[slot], s));
+  P.ev_used[slot] = true;
+  return FEWHA_OK;
+}
+
+LaunchArgs args(const Plan& P, hipStream_t s, const IoDev* io) {
+  LaunchArgs a;
+  a.P = P.dP;
+  a.L = P.dL;
+  a.W = P.dW;
+  a.IO = io;
+  a.F = P.F;
+  a.stream = s;
+  return a;
+}
+
+const Tile* T(const Plan& P, const Range& r) { return P.dT + r.off; }
+
+void enq_idwt(const Plan& P, const LaunchArgs& a, int src, int out, int iter) {
+  launch_idwt_res(a, T(P, P.idwt_res), P.idwt_res.n, src, out, iter);
+  for (size_t s = 0; s < P.idwt_glob.size(); ++s)
+    launch_idwt_glob(a, T(P, P.idwt_glob[s]), P.idwt_glob[s].n, src, out, iter, (int)s);
+}
+void enq_fdwt(const Plan& P, const LaunchArgs& a, int epi, int iter) {
+  for (size_t s = 0; s < P.fdwt_glob.size(); ++s)
+    launch_fdwt_glob(a, T(P, P.fdwt_glob[s]), P.fdwt_glob[s].n, epi, iter, (int)s);
+  launch_fdwt_res(a, T(P, P.fdwt_res), P.fdwt_res.n, epi, iter);
+}
+// A^T C_hat^{-1} (dense slopes in the work buffer) -> phiadj
+void enq_adjoint(const Plan& P, const LaunchArgs& a, int gt_mode, int pt_mode) {
+  launch_gammaT(a, T(P, P.gt), P.gt.n, gt_mode);
+  launch_pT(a, T(P, P.pt), P.pt.n, pt_mode);
+}
+void enq_apply_M_core(const Plan& P, const LaunchArgs& a) {
+  launch_pgamma(a, T(P, P.pg), P.pg.n, PG_DENSE);
+  enq_adjoint(P, a, GT_WEIGHTED, PT_PHIADJ);
+}
+
+void enq_reconstruct(const Plan& P, const LaunchArgs& a, int iters) {
+  launch_slopes_in(a, T(P, P.pg), P.pg.n);
+  enq_adjoint(P, a, GT_WEIGHTED, PT_PHIADJ);
+  enq_fdwt(P, a, EPI_RHS, 0);
+  for (int k = 0; k < iters; ++k) {
+    enq_idwt(P, a, k == 0 ? SRC_PUPD0 : SRC_PUPD, OUT_PHI, k);
+    enq_apply_M_core(P, a);
+    enq_fdwt(P, a, EPI_PCG, k);
+    launch_update(a, T(P, P.upd), P.upd.n, k);
+  }
+  enq_idwt(P, a, SRC_STATE_C, OUT_FIT, 0);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ C ABI
+
+struct fewha_ctx {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  bool finalized = false;
+  std::string err;
+  HostModel m;
+  Plan* plan = nullptr;
+};
+
+struct fewha_batch {
+  std::vector<fewha_ctx*> ctxs;
+  Plan* plan = nullptr;
+  hipStream_t stream = nullptr;
+  std::string err;
+};
+
+#define CHECK_CTX(c)                 \
+  do {                               \
+    if (!(c)) return FEWHA_EINVAL;   \
+  } while (0)
+
+static fewha_status fail(fewha_ctx* c, fewha_status s, const std::string& msg) {
+  c->err = msg;
+  return s;
+}
+
+extern "C" {
+
+fewha_status fewha_create(fewha_ctx** out, int device) {
+  if (!out) return FEWHA_EINVAL;
+  *out = nullptr;
+  fewha_ctx* c = new (std::nothrow) fewha_ctx();
+  if (!c) return FEWHA_ENOMEM;
+  c->device = device;
+  if (device >= 0) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device >= n || hipSetDevice(device) != hipSuccess) {
+      delete c;
+      return FEWHA_EDEVICE;
+    }
+  }
+  *out = c;
+  return FEWHA_OK;
+}
+
+fewha_status fewha_set_stream(fewha_ctx* c, void* s) {
+  CHECK_CTX(c);
+  c->stream = (hipStream_t)s;
+  return FEWHA_OK;
+}
+
+fewha_status fewha_set_pupil(fewha_ctx* c, double D, double obs) {
+  CHECK_CTX(c);
+  if (c->finalized) return fail(c, FEWHA_ESTATE, "set_pupil after finalize");
+  if (!(D > 0.0) || !(obs >= 0.0 && obs < 1.0)) return fail(c, FEWHA_EINVAL, "set_pupil: need D > 0, 0 <= obstruction < 1");
+  c->m.D = D;
+  c->m.obs = obs;
+  c->m.have_pupil = true;
+  return FEWHA_OK;
+}
+
+fewha_status fewha_set_wfs(fewha_ctx* c, int G, const fewha_wfs_desc* w) {
+  CHECK_CTX(c);
+  if (c->finalized) return fail(c, FEWHA_ESTATE, "set_wfs after finalize");
+  if (G < 1 || G > 1024 || !w) return fail(c, FEWHA_EINVAL, "set_wfs: need 1 <= G <= 1024 and a descriptor array");
+  std::vector<WfsHost> v(G);
+  for (int g = 0; g < G; ++g) {
+    const fewha_wfs_desc& d = w[g];
+    if ((d.kind != FEWHA_NGS && d.kind != FEWHA_LGS) || d.n_subap < 1 || d.n_subap > 4096 || !(d.sigma > 0.0) ||
+        (d.kind == FEWHA_LGS && !(d.H > 0.0)))
+      return fail(c, FEWHA_EINVAL, "set_wfs: sensor " + std::to_string(g) + " has an invalid descriptor");
+    v[g].d = d;
+    v[g].d.mask = nullptr;
+    if (d.mask) v[g].mask.assign(d.mask, d.mask + (size_t)d.n_subap * d.n_subap);
+    for (auto& b : v[g].mask) b = b ? 1 : 0;
+  }
+  c->m.wfs = std::move(v);
+  c->m.have_wfs = true;
+  return FEWHA_OK;
+}
+
+fewha_status fewha_set_layers(fewha_ctx* c, int L, const fewha_layer_desc* l, double side) {
+  CHECK_CTX(c);
+  if (c->finalized) return fail(c, FEWHA_ESTATE, "set_layers after finalize");
+  if (L < 1 || L > 64 || !l || !(side > 0.0)) return fail(c, FEWHA_EINVAL, "set_layers: need 1 <= L <= 64, side > 0");
+  c->m.layers.assign(L, LayerHost());
+  for (int i = 0; i < L; ++i) c->m.layers[i].d = l[i];
+  c->m.L = side;
+  c->m.have_layers = true;
+  return FEWHA_OK;
+}
+
+fewha_status fewha_set_prior(fewha_ctx* c, double alpha, double r0, double L0, double tau) {
+  CHECK_CTX(c);
+  if (c->finalized) return fail(c, FEWHA_ESTATE, "set_prior after finalize");
+  if (!(alpha > 0.0) || !(r0 > 0.0) || !(L0 > 0.0) || !(tau >= 0.0))
+    return fail(c, FEWHA_EINVAL, "set_prior: need alpha, r0, L0 > 0 and tau >= 0");
+  c->m.alpha = alpha;
+  c->m.r0 = r0;
+  c->m.L0 = L0;
+  c->m.tau = tau;
+  return FEWHA_OK;
+}
+
+fewha_status fewha_set_noise(fewha_ctx* c, double alpha_eta, double na_fwhm, double spot_fwhm) {
+  CHECK_CTX(c);
+  if (c->finalized) return fail(c, FEWHA_ESTATE, "set_noise after finalize");
+  if (!(alpha_eta >= 0.0) || !(na_fwhm >= 0.0) || !(spot_fwhm > 0.0))
+    return fail(c, FEWHA_EINVAL, "set_noise: need alpha_eta >= 0, na_fwhm >= 0, spot_fwhm > 0");
+  c->m.alpha_eta = alpha_eta;
+  c->m.na_fwhm = na_fwhm;
+  c->m.spot_fwhm = spot_fwhm;
+  return FEWHA_OK;
+}
+
+fewha_status fewha_set_control(fewha_ctx* c, double gain) {
+  CHECK_CTX(c);
+  if (c->finalized) return fail(c, FEWHA_ESTATE, "set_control after finalize");
+  if (!(gain >= 0.0 && gain <= 1.0)) return fail(c, FEWHA_EINVAL, "set_control: gain must lie in [0, 1]");
+  c->m.gain = gain;
+  return FEWHA_OK;
+}
+
+fewha_status fewha_finalize(fewha_ctx* c) {
+  CHECK_CTX(c);
+  if (c->finalized) return fail(c, FEWHA_ESTATE, "finalize called twice");
+  fewha_status s = build_model(c->m, c->err);
+  if (s != FEWHA_OK) return s;
+  if (c->device >= 0) {
+    std::vector<const HostModel*> ms{&c->m};
+    s = build_plan(c->plan, ms, c->device, c->err);
+    if (s != FEWHA_OK) return s;
+  }
+  c->finalized = true;
+  return FEWHA_OK;
+}
+
+fewha_status fewha_sizes(const fewha_ctx* c, long* n_coeff, long* n_slopes, long* n_layer_pts, long* n_act,
+                         long* n_state) {
+  if (!c) return FEWHA_EINVAL;
+  if (!c->finalized) return FEWHA_ESTATE;
+  if (n_coeff) *n_coeff = c->m.n_c;
+  if (n_slopes) *n_slopes = c->m.n_slopes;
+  if (n_layer_pts) *n_layer_pts = c->m.n_c;
+  if (n_act) *n_act = c->m.n_c;
+  if (n_state) *n_state = 5L * c->m.n_c;
+  return FEWHA_OK;
+}
+
+fewha_status fewha_get_table(const fewha_ctx* c, int which, double* out, long n) {
+  if (!c || !out) return FEWHA_EINVAL;
+  if (!c->finalized) return FEWHA_ESTATE;
+  std::vector<double> v;
+  switch (which) {
+    case FEWHA_TABLE_FILTER:
+      v.assign(c->m.h, c->m.h + 6);
+      break;
+    case FEWHA_TABLE_PRIOR:
+      v = c->m.Dprior;
+      break;
+    case FEWHA_TABLE_PRECOND:
+      v = c->m.J;
+      break;
+    case FEWHA_TABLE_MASK:
+      for (const WfsHost& w : c->m.wfs)
+        for (uint8_t b : w.mask) v.push_back(b);
+      break;
+    default:
+      return FEWHA_EINVAL;
+  }
+  if (n < (long)v.size()) return FEWHA_EINVAL;
+  std::copy(v.begin(), v.end(), out);
+  return FEWHA_OK;
+}
+
+static fewha_status ready(fewha_ctx* c) {
+  if (!c) return FEWHA_EINVAL;
+  if (!c->finalized) return fail(c, FEWHA_ESTATE, "context not finalized");
+  if (c->device < 0 || !c->plan) return fail(c, FEWHA_ESTATE, "host-only context: no device");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, FEWHA_EDEVICE, "hipSetDevice failed");
+  return FEWHA_OK;
+}
+
+static fewha_status finish(fewha_ctx* c) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, FEWHA_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  return FEWHA_OK;
+}
+
+fewha_status fewha_apply_A(fewha_ctx* c, const float* layers, float* slopes) {
+  fewha_status s = ready(c);
+  if (s != FEWHA_OK) return s;
+  if (!layers || !slopes) return fail(c, FEWHA_EINVAL, "apply_A: null pointer");
+  Plan& P = *c->plan;
+  std::vector<IoDev> io(1);
+  io[0].in = layers;
+  io[0].out = slopes;
+  if ((s = upload_io(P, io, c->stream, P.dIO, c->err)) != FEWHA_OK) return s;
+  LaunchArgs a = args(P, c->stream, P.dIO);
+  launch_pgamma(a, T(P, P.pg), P.pg.n, PG_COMPACT);
+  return finish(c);
+}
+
+fewha_status fewha_apply_AT(fewha_ctx* c, const float* slopes, float* layers) {
+  fewha_status s = ready(c);
+  if (s != FEWHA_OK) return s;
+  if (!layers || !slopes) return fail(c, FEWHA_EINVAL, "apply_AT: null pointer");
+  Plan& P = *c->plan;
+  std::vector<IoDev> io(1);
+  io[0].in = slopes;
+  io[0].out = layers;
+  if ((s = upload_io(P, io, c->stream, P.dIO, c->err)) != FEWHA_OK) return s;
+  LaunchArgs a = args(P, c->stream, P.dIO);
+  launch_slopes_in(a, T(P, P.pg), P.pg.n);
+  enq_adjoint(P, a, GT_PLAIN, PT_USER);
+  return finish(c);
+}
+
+fewha_status fewha_apply_M(fewha_ctx* c, const float* x, float* Mx) {
+  fewha_status s = ready(c);
+  if (s != FEWHA_OK) return s;
+  if (!x || !Mx) return fail(c, FEWHA_EINVAL, "apply_M: null pointer");
+  Plan& P = *c->plan;
+  std::vector<IoDev> io(1);
+  io[0].in = x;
+  io[0].out = Mx;
+  if ((s = upload_io(P, io, c->stream, P.dIO, c->err)) != FEWHA_OK) return s;
+  LaunchArgs a = args(P, c->stream, P.dIO);
+  enq_idwt(P, a, SRC_IN, OUT_PHI, 0);
+  enq_apply_M_core(P, a);
+  enq_fdwt(P, a, EPI_APPLYM, 0);
+  return finish(c);
+}
+
+fewha_status fewha_rhs(fewha_ctx* c, const float* slopes, float* b) {
+  fewha_status s = ready(c);
+  if (s != FEWHA_OK) return s;
+  if (!slopes || !b) return fail(c, FEWHA_EINVAL, "rhs: null pointer");
+  Plan& P = *c->plan;
+  std::vector<IoDev> io(1);
+  io[0].in = slopes;
+  io[0].out = b;
+  if ((s = upload_io(P, io, c->stream, P.dIO, c->err)) != FEWHA_OK) return s;
+  LaunchArgs a = args(P, c->stream, P.dIO);
+  launch_slopes_in(a, T(P, P.pg), P.pg.n);
+  enq_adjoint(P, a, GT_WEIGHTED, PT_PHIADJ);
+  enq_fdwt(P, a, EPI_PLAIN, 0);
+  return finish(c);
+}
+
+fewha_status fewha_reconstruct(fewha_ctx* c, const float* slopes, float* state, float* layers_out, float* dm_out,
+                               int iters) {
+  fewha_status s = ready(c);
+  if (s != FEWHA_OK) return s;
+  if (!slopes || !state) return fail(c, FEWHA_EINVAL, "reconstruct: null slopes or state");
+  if (iters < 0 || iters > kMaxIters) return fail(c, FEWHA_EINVAL, "reconstruct: iters must lie in [0, 256]");
+  Plan& P = *c->plan;
+  std::vector<IoDev> io(1);
+  io[0].in = slopes;
+  io[0].state = state;
+  io[0].layers_out = layers_out;
+  io[0].dm_out = dm_out;
+  if ((s = upload_io(P, io, c->stream, P.dIO, c->err)) != FEWHA_OK) return s;
+  LaunchArgs a = args(P, c->stream, P.dIO);
+  enq_reconstruct(P, a, iters);
+  return finish(c);
+}
+
+// ---- batches ----
+
+static fewha_status bfail(fewha_batch* b, fewha_status s, const std::string& m) {
+  b->err = m;
+  return s;
+}
+
+fewha_status fewha_batch_create(fewha_batch** out, fewha_ctx* const* ctxs, int n) {
+  if (!out || !ctxs || n < 1) return FEWHA_EINVAL;
+  *out = nullptr;
+  int dev = -1;
+  std::vector<const HostModel*> ms;
+  for (int k = 0; k < n; ++k) {
+    if (!ctxs[k] || !ctxs[k]->finalized || ctxs[k]->device < 0) return FEWHA_ESTATE;
+    if (dev >= 0 && ctxs[k]->device != dev) return FEWHA_EINVAL;
+    dev = ctxs[k]->device;
+    ms.push_back(&ctxs[k]->m);
+  }
+  fewha_batch* b = new (std::nothrow) fewha_batch();
+  if (!b) return FEWHA_ENOMEM;
+  b->ctxs.assign(ctxs, ctxs + n);
+  fewha_status s = build_plan(b->plan, ms, dev, b->err);
+  if (s != FEWHA_OK) {
+    delete b;
+    return s;
+  }
+  *out = b;
+  return FEWHA_OK;
+}
+
+fewha_status fewha_batch_set_stream(fewha_batch* b, void* s) {
+  if (!b) return FEWHA_EINVAL;
+  b->stream = (hipStream_t)s;
+  return FEWHA_OK;
+}
+
+fewha_status fewha_batch_reconstruct(fewha_batch* b, const float* const* slopes, float* const* state,
+                                     float* const* layers_out, float* const* dm_out, int iters, int use_graph) {
+  if (!b) return FEWHA_EINVAL;
+  if (!slopes || !state) return bfail(b, FEWHA_EINVAL, "batch_reconstruct: null slopes or state array");
+  if (iters < 0 || iters > kMaxIters) return bfail(b, FEWHA_EINVAL, "batch_reconstruct: iters must lie in [0, 256]");
+  Plan& P = *b->plan;
+  std::string& err = b->err;
+  std::vector<IoDev> io(P.nprob);
+  for (int k = 0; k < P.nprob; ++k) {
+    if (!slopes[k] || !state[k]) return bfail(b, FEWHA_EINVAL, "batch_reconstruct: null pointer for problem " + std::to_string(k));
+    io[k].in = slopes[k];
+    io[k].state = state[k];
+    io[k].layers_out = layers_out ? layers_out[k] : nullptr;
+    io[k].dm_out = dm_out ? dm_out[k] : nullptr;
+  }
+  HIP_TRY(hipSetDevice(P.device));
+  fewha_status s = upload_io(P, io, b->stream, P.dIO, err);
+  if (s != FEWHA_OK) return s;
+  P.last_io = io;
+  P.ran = true;
+  if (!use_graph) {
+    enq_reconstruct(P, args(P, b->stream, P.dIO), iters);
+  } else {
+    auto it = P.graphs.find(iters);
+    if (it == P.graphs.end()) {
+      hipGraph_t g = nullptr;
+      hipGraphExec_t ge = nullptr;
+      HIP_TRY(hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal));
+      enq_reconstruct(P, args(P, P.cap_stream, P.dIO), iters);
+      HIP_TRY(hipStreamEndCapture(P.cap_stream, &g));
+      HIP_TRY(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+      P.graph_defs[iters] = g;
+      it = P.graphs.emplace(iters, ge).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second, b->stream));
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return bfail(b, FEWHA_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  return FEWHA_OK;
+}
+
+fewha_status fewha_batch_time_stage(fewha_batch* b, int stage, int reps, double* avg_us, long* workgroups) {
+  if (!b || !avg_us) return FEWHA_EINVAL;
+  if (stage < 0 || stage >= FEWHA_STAGE_COUNT || reps < 1) return bfail(b, FEWHA_EINVAL, "time_stage: bad stage or reps");
+  Plan& P = *b->plan;
+  if (!P.ran) return bfail(b, FEWHA_ESTATE, "time_stage: run batch_reconstruct first");
+  std::string& err = b->err;
+  HIP_TRY(hipSetDevice(P.device));
+  // private copies of the states so that timing never changes caller data
+  if (P.prof_state.empty()) {
+    P.prof_state.assign(P.nprob, nullptr);
+    for (int k = 0; k < P.nprob; ++k) HIP_TRY(hipMalloc(&P.prof_state[k], sizeof(float) * P.n_state[k]));
+  }
+  std::vector<IoDev> io = P.last_io;
+  for (int k = 0; k < P.nprob; ++k) {
+    HIP_TRY(hipMemcpyAsync(P.prof_state[k], io[k].state, sizeof(float) * P.n_state[k], hipMemcpyDeviceToDevice,
+                           b->stream));
+    io[k].state = P.prof_state[k];
+    io[k].layers_out = nullptr;
+    io[k].dm_out = nullptr;
+  }
+  fewha_status s = upload_io(P, io, b->stream, P.dIOprof, err);
+  if (s != FEWHA_OK) return s;
+  LaunchArgs a = args(P, b->stream, P.dIOprof);
+  const int it = 1;  // an inner iteration: fused p update with beta
+  long wg = 0;
+  auto run = [&]() {
+    switch (stage) {
+      case FEWHA_STAGE_IDWT_RES:
+        launch_idwt_res(a, T(P, P.idwt_res), P.idwt_res.n, SRC_PUPD, OUT_PHI, it);
+        wg = P.idwt_res.n;
+        break;
+      case FEWHA_STAGE_IDWT_GLOB:
+        wg = 0;
+        for (size_t st = 0; st < P.idwt_glob.size(); ++st) {
+          launch_idwt_glob(a, T(P, P.idwt_glob[st]), P.idwt_glob[st].n, SRC_PUPD, OUT_PHI, it, (int)st);
+          wg += P.idwt_glob[st].n;
+        }
+        break;
+      case FEWHA_STAGE_P_GAMMA:
+        launch_pgamma(a, T(P, P.pg), P.pg.n, PG_DENSE);
+        wg = P.pg.n;
+        break;
+      case FEWHA_STAGE_GAMMA_T:
+        launch_gammaT(a, T(P, P.gt), P.gt.n, GT_WEIGHTED);
+        wg = P.gt.n;
+        break;
+      case FEWHA_STAGE_P_T:
+        launch_pT(a, T(P, P.pt), P.pt.n, PT_PHIADJ);
+        wg = P.pt.n;
+        break;
+      case FEWHA_STAGE_FDWT_GLOB:
+        wg = 0;
+        for (size_t st = 0; st < P.fdwt_glob.size(); ++st) {
+          launch_fdwt_glob(a, T(P, P.fdwt_glob[st]), P.fdwt_glob[st].n, EPI_PCG, it, (int)st);
+          wg += P.fdwt_glob[st].n;
+        }
+        break;
+      case FEWHA_STAGE_FDWT_RES:
+        launch_fdwt_res(a, T(P, P.fdwt_res), P.fdwt_res.n, EPI_PCG, it);
+        wg = P.fdwt_res.n;
+        break;
+      case FEWHA_STAGE_UPDATE:
+        launch_update(a, T(P, P.upd), P.upd.n, it);
+        wg = P.upd.n;
+        break;
+    }
+  };
+  run();  // warm
+  HIP_TRY(hipEventRecord(P.t0, b->stream));
+  for (int r = 0; r < reps; ++r) run();
+  HIP_TRY(hipEventRecord(P.t1, b->stream));
+  HIP_TRY(hipEventSynchronize(P.t1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, P.t0, P.t1));
+  *avg_us = 1000.0 * ms / reps;
+  if (workgroups) *workgroups = wg;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return bfail(b, FEWHA_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  return FEWHA_OK;
+}
+
+void fewha_batch_destroy(fewha_batch* b) {
+  if (!b) return;
+  destroy_plan(b->plan);
+  delete b;
+}
+
+const char* fewha_last_error(const fewha_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* fewha_batch_last_error(const fewha_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+void fewha_destroy(fewha_ctx* c) {
+  if (!c) return;
+  destroy_plan(c->plan);
+  delete c;
+}
+
+}  // extern "C"

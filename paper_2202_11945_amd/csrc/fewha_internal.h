@@ -1,0 +1,162 @@
+// Internal data structures shared by the host set-up, the plan builder and
+// the gfx950 kernels.  Everything a kernel reads is flat POD in device
+// memory; per-problem buffers are carved out of one arena per plan.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fewha.h"
+
+namespace fewha {
+
+constexpr int kMaxLevelsJ = 16;   // j index range of the per-layer prior table
+constexpr int kResMax = 128;      // largest block kept resident in LDS by the DWT kernels
+constexpr int kTileS = 16;        // subaperture / corner tile side of the sensor stages
+constexpr int kTileN = 32;        // node tile side of the layer stages
+constexpr int kUpdChunk = 2048;   // coefficients per workgroup of the vector update
+
+// db3 analysis filters, passed by value to the transform kernels.
+struct Filter {
+  float h[6];
+  float g[6];
+};
+
+// One layer of one problem.
+struct LayerDev {
+  int n, log2n, levels, res;  // res = min(n, kResMax)
+  int off;                    // offset of the layer in N_c-sized vectors
+  int tmp_off;                // offset of the layer's coarse-block scratch
+  int n_glob_levels;          // levels with output side > kResMax
+  int pad0;
+  float inv_delta;            // 1 / delta_l
+  float alpha_d[kMaxLevelsJ]; // alpha * D_j, j = log2(block side)
+};
+
+// One sensor of one problem.
+struct WfsDev {
+  int N, nc;            // subapertures per side, corners per side
+  int lgs, tt;          // laser guide star, tip/tilt removal
+  int blocks;           // 1 = 2x2 block noise weights present
+  int n_active;
+  int s_off;            // dense slopes: [s^x N*N | s^y N*N] at s_off
+  int v_off;            // corner grids: nc*nc at v_off
+  int cs_off;           // compact slopes of this sensor within the problem's slope vector
+  int m_off;            // N*N compact-index map at m_off (-1 = inactive)
+  int cinv_off;         // 3 floats (a, b, c) per subaperture at cinv_off (blocks only)
+  int part_off;         // 4 floats per P-Gamma tile at part_off
+  int n_tiles_s;        // tiles of the subaperture grid (= partial slots)
+  int tiles_side;       // tiles per side of the subaperture grid
+  int tab_off;          // per layer: interp/adjacency tables at tab_off + l * tab_stride
+  int tab_stride;
+  float inv_sigma2;
+  float inv_nM;
+  float sum_cinv[4];    // sum over the mask of the 2x2 inverse blocks (row-major)
+};
+
+// Per-(sensor, layer) table layout inside the int/float table arrays, relative
+// to WfsDev::tab_off + l * tab_stride:
+//   int   q0y[nc], q0x[nc]                  bilinear cell of each corner row/column
+//   float wy[nc],  wx[nc]                   fractional offsets
+//   int   ay0[n], ayc[n], ax0[n], axc[n]    first corner row/column and count
+//                                           touching each layer node row/column
+// (n = the layer's grid side; the float array shares the offsets.)
+
+// One problem.
+struct ProbDev {
+  int L, G;
+  int layer0, wfs0;        // first LayerDev / WfsDev index
+  int n_c;                 // coefficients = layer nodes
+  int n_slopes;            // compact slopes
+  int n_act;
+  int n_dots;              // dot-product slots per group
+  int n_slots_fdwt;        // producers of rho_0 and pi_k
+  int n_slots_upd;         // producers of rho_{k+1}
+  int pad0, pad1;
+  float gain;
+  float pad2;
+  // internal buffers
+  float* phi;      // layers (FE domain) N_c
+  float* phiadj;   // A^T ... result N_c
+  float* tmpa;     // coarse-block scratch (ping)
+  float* tmpb;     // coarse-block scratch (pong)
+  float* sd;       // dense slopes
+  float* vadj;     // corner-grid adjoint values
+  float* part;     // tip/tilt partial sums
+  float* pbuf0;    // search direction (ping)
+  float* pbuf1;    // search direction (pong)
+  float* q;        // M p
+  double* dots;    // [group][n_dots] partial inner products
+  const float* jinv;     // 1 / J
+  const int* itab;       // int tables
+  const float* ftab;     // float tables
+  const int* cmap;       // compact-index maps
+  const float* cinv;     // 2x2 inverse noise blocks
+};
+
+// Per-call input/output pointers of one problem.
+struct IoDev {
+  const float* in;     // slopes (reconstruct, apply_AT, rhs), layers (apply_A), c (apply_M)
+  float* out;          // apply_* outputs
+  float* state;        // [c | b | r | a_prev | a]
+  float* layers_out;
+  float* dm_out;
+};
+
+// Work-list entry of a tiled stage: problem, item (layer or sensor), tile
+// row/column, and the slot of the partial it produces.
+struct Tile {
+  int prob, item, ty, tx;
+  int slot, level, pad0, pad1;
+};
+
+// ---- host-side description of one configured problem ----
+
+struct WfsHost {
+  fewha_wfs_desc d;
+  std::vector<uint8_t> mask;   // N*N
+  std::vector<int> cmap;       // N*N compact index or -1
+  int n_active = 0;
+  std::vector<double> cinv;    // 3 per subaperture (a, b, c), row-major N*N
+  double sum_cinv[4] = {0, 0, 0, 0};
+};
+
+struct LayerHost {
+  fewha_layer_desc d;
+  double delta = 0;
+  std::vector<double> dtab;  // D_j, j = 0..kMaxLevelsJ-1 (0 where unused)
+};
+
+struct GLTables {  // one (sensor, layer) pair
+  std::vector<int> q0y, q0x;   // nc
+  std::vector<double> wy, wx;  // nc
+  std::vector<int> ay0, ayc, ax0, axc;  // n
+};
+
+struct HostModel {
+  double D = 0, obs = 0;
+  std::vector<WfsHost> wfs;
+  std::vector<LayerHost> layers;
+  double L = 0;
+  double alpha = 1, r0 = 0.15, L0 = 25, tau = 0;
+  double alpha_eta = 0, na_fwhm = 11400, spot_fwhm = 4.85e-6;
+  double gain = 1;
+  bool have_pupil = false, have_wfs = false, have_layers = false;
+  // derived
+  double h[6] = {0}, g[6] = {0};
+  std::vector<std::vector<GLTables>> tab;  // [g][l]
+  std::vector<double> Dprior;              // N_c
+  std::vector<double> J;                   // N_c
+  std::vector<int> layer_off;
+  std::vector<int> slope_off;
+  long n_c = 0, n_slopes = 0;
+};
+
+// host set-up (setup.cpp); each returns FEWHA_OK or an error with a message
+fewha_status build_model(HostModel& m, std::string& err);
+void db3_filter(double h[6]);
+
+}  // namespace fewha

@@ -1,0 +1,198 @@
+"""Python binding of libfewha with the ABI's names: a context per configured
+problem, a batch of contexts, and calls on torch device tensors.  Only
+argument marshalling lives here; torch supplies device memory and streams.
+"""
+
+import ctypes
+from ctypes import byref, c_double, c_long, c_void_p
+
+import numpy as np
+
+from . import _abi
+from ._abi import FewhaError
+
+
+def _check(status, ctx_handle=None, batch_handle=None):
+    if status != _abi.FEWHA_OK:
+        msg = ""
+        if ctx_handle is not None:
+            msg = _abi.fewha_last_error(ctx_handle).decode()
+        elif batch_handle is not None:
+            msg = _abi.fewha_batch_last_error(batch_handle).decode()
+        raise FewhaError(status, msg)
+
+
+def _ptr(t, n=None, dtype=None):
+    """Device pointer of a contiguous CUDA float32 tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float32 device tensor")
+    if n is not None and t.numel() < n:
+        raise ValueError("tensor too small: %d < %d" % (t.numel(), n))
+    return c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """One configured FEWHA problem (fewha_create ... fewha_finalize).
+
+    ``cfg`` is a configuration dict (see ``synthetic.configs``); ``device``
+    is the HIP device index or -1 for a host-only context (tables only)."""
+
+    def __init__(self, cfg, device=0):
+        self.cfg = cfg
+        h = c_void_p()
+        _check(_abi.fewha_create(byref(h), int(device)))
+        self.h = h
+        self.device = device
+        try:
+            self._configure(cfg)
+        except Exception:
+            _abi.fewha_destroy(self.h)
+            self.h = None
+            raise
+        nc, ns, nl, na, nst = c_long(), c_long(), c_long(), c_long(), c_long()
+        _check(_abi.fewha_sizes(self.h, byref(nc), byref(ns), byref(nl), byref(na), byref(nst)), self.h)
+        self.n_coeff, self.n_slopes, self.n_layer_pts = nc.value, ns.value, nl.value
+        self.n_act, self.n_state = na.value, nst.value
+
+    def _configure(self, cfg):
+        _check(_abi.fewha_set_pupil(self.h, cfg["D"], cfg["obstruction"]), self.h)
+        ws = (_abi.fewha_wfs_desc * len(cfg["wfs"]))()
+        self._masks = []
+        for k, w in enumerate(cfg["wfs"]):
+            d = ws[k]
+            d.kind = _abi.FEWHA_LGS if w["kind"] == "lgs" else _abi.FEWHA_NGS
+            d.n_subap = w["n_subap"]
+            d.theta_x, d.theta_y = w["theta"]
+            d.H = w["H"] if w["H"] is not None else 0.0
+            d.sigma = w["sigma"]
+            d.launch_x, d.launch_y = w.get("launch", (0.0, 0.0))
+            d.tt_removal = 1 if w.get("tt_removal") else 0
+            if w.get("mask") is not None:
+                m = np.ascontiguousarray(np.asarray(w["mask"], dtype=np.uint8))
+                self._masks.append(m)
+                d.mask = m.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))
+        _check(_abi.fewha_set_wfs(self.h, len(cfg["wfs"]), ws), self.h)
+        ls = (_abi.fewha_layer_desc * len(cfg["layers"]))()
+        for k, l in enumerate(cfg["layers"]):
+            ls[k].h, ls[k].n, ls[k].levels, ls[k].cn2 = l["h"], l["n"], l["levels"], l["cn2"]
+        _check(_abi.fewha_set_layers(self.h, len(cfg["layers"]), ls, cfg["domain_side"]), self.h)
+        pr = cfg["prior"]
+        _check(_abi.fewha_set_prior(self.h, pr["alpha"], pr["r0"], pr["L0"], pr["tau"]), self.h)
+        no = cfg["noise"]
+        _check(_abi.fewha_set_noise(self.h, no["alpha_eta"], no["na_fwhm"], no["spot_fwhm"]), self.h)
+        _check(_abi.fewha_set_control(self.h, cfg.get("gain", 1.0)), self.h)
+        _check(_abi.fewha_finalize(self.h), self.h)
+
+    def close(self, _destroy=_abi.fewha_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    # ---- tables ----
+    def get_table(self, which):
+        n = {_abi.FEWHA_TABLE_FILTER: 6, _abi.FEWHA_TABLE_PRIOR: self.n_coeff,
+             _abi.FEWHA_TABLE_PRECOND: self.n_coeff,
+             _abi.FEWHA_TABLE_MASK: sum(w["n_subap"] ** 2 for w in self.cfg["wfs"])}[which]
+        out = np.zeros(n)
+        _check(_abi.fewha_get_table(self.h, which, out.ctypes.data_as(ctypes.POINTER(c_double)), n), self.h)
+        return out
+
+    # ---- compute ----
+    def _new(self, n):
+        import torch
+        return torch.empty(n, dtype=torch.float32, device="cuda:%d" % self.device)
+
+    def _sync_stream(self):
+        _check(_abi.fewha_set_stream(self.h, _stream()), self.h)
+
+    def fewha_apply_A(self, layers, slopes=None):
+        slopes = self._new(self.n_slopes) if slopes is None else slopes
+        self._sync_stream()
+        _check(_abi.fewha_apply_A(self.h, _ptr(layers, self.n_coeff), _ptr(slopes, self.n_slopes)), self.h)
+        return slopes
+
+    def fewha_apply_AT(self, slopes, layers=None):
+        layers = self._new(self.n_coeff) if layers is None else layers
+        self._sync_stream()
+        _check(_abi.fewha_apply_AT(self.h, _ptr(slopes, self.n_slopes), _ptr(layers, self.n_coeff)), self.h)
+        return layers
+
+    def fewha_apply_M(self, c, out=None):
+        out = self._new(self.n_coeff) if out is None else out
+        self._sync_stream()
+        _check(_abi.fewha_apply_M(self.h, _ptr(c, self.n_coeff), _ptr(out, self.n_coeff)), self.h)
+        return out
+
+    def fewha_rhs(self, slopes, out=None):
+        out = self._new(self.n_coeff) if out is None else out
+        self._sync_stream()
+        _check(_abi.fewha_rhs(self.h, _ptr(slopes, self.n_slopes), _ptr(out, self.n_coeff)), self.h)
+        return out
+
+    def fewha_reconstruct(self, slopes, state, layers_out=None, dm_out=None, iters=None):
+        iters = self.cfg["iters"] if iters is None else iters
+        self._sync_stream()
+        _check(_abi.fewha_reconstruct(self.h, _ptr(slopes, self.n_slopes), _ptr(state, self.n_state),
+                                      _ptr(layers_out, self.n_coeff), _ptr(dm_out, self.n_act), int(iters)),
+               self.h)
+
+    # short aliases
+    apply_A = fewha_apply_A
+    apply_AT = fewha_apply_AT
+    apply_M = fewha_apply_M
+    rhs = fewha_rhs
+    reconstruct = fewha_reconstruct
+
+
+class Batch:
+    """fewha_batch_create over finalized device contexts."""
+
+    def __init__(self, ctxs):
+        self.ctxs = list(ctxs)
+        arr = (c_void_p * len(self.ctxs))(*[c.h.value for c in self.ctxs])
+        h = c_void_p()
+        _check(_abi.fewha_batch_create(byref(h), arr, len(self.ctxs)))
+        self.h = h
+
+    def close(self, _destroy=_abi.fewha_batch_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def fewha_batch_reconstruct(self, slopes, states, layers_out=None, dm_out=None, iters=4, use_graph=True):
+        n = len(self.ctxs)
+
+        def arr(ts, sizes):
+            if ts is None:
+                return None
+            return (c_void_p * n)(*[(_ptr(t, s).value if t is not None else None) for t, s in zip(ts, sizes)])
+
+        _check(_abi.fewha_batch_set_stream(self.h, _stream()), batch_handle=self.h)
+        _check(_abi.fewha_batch_reconstruct(
+            self.h, arr(slopes, [c.n_slopes for c in self.ctxs]), arr(states, [c.n_state for c in self.ctxs]),
+            arr(layers_out, [c.n_coeff for c in self.ctxs]), arr(dm_out, [c.n_act for c in self.ctxs]),
+            int(iters), 1 if use_graph else 0), batch_handle=self.h)
+
+    def fewha_batch_time_stage(self, stage, reps=20):
+        us, wg = c_double(), c_long()
+        _check(_abi.fewha_batch_set_stream(self.h, _stream()), batch_handle=self.h)
+        _check(_abi.fewha_batch_time_stage(self.h, int(stage), int(reps), byref(us), byref(wg)),
+               batch_handle=self.h)
+        return us.value, wg.value
+
+    reconstruct = fewha_batch_reconstruct
+    time_stage = fewha_batch_time_stage

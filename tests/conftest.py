@@ -28,3 +28,26 @@ def systems():
         return cache[key]
 
     return get
+
+
+def _ensure_built():
+    here = os.path.join(ROOT, "paper_2202_11945_amd", "lib", "libfewha.so")
+    if not os.path.exists(here):
+        from paper_2202_11945_amd.build import build
+        build()
+
+
+@pytest.fixture(scope="session")
+def lib():
+    """The built library (built once if missing)."""
+    _ensure_built()
+    import paper_2202_11945_amd as pkg
+    return pkg
+
+
+@pytest.fixture(scope="session")
+def gpu_lib(lib):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("a GPU test ran without a HIP device")
+    return lib

@@ -1,0 +1,253 @@
+"""GPU parity of every entry point of libfewha against the FP64 oracle, on
+the same seeded FP32 inputs.  Tolerances: <= 1e-5 relative 2-norm per
+operator application, <= 1e-4 on the reconstructed layers after a fixed
+number of PCG iterations (norm-wise, per layer).  Integer/structural results
+(batch vs single, graph vs direct launches, repeat runs) are compared
+bitwise."""
+
+import numpy as np
+import pytest
+
+from oracle.solver import State, frame
+from synthetic import frozen_flow_frames, get_config, random_vector, slope_noise
+
+pytestmark = pytest.mark.gpu
+
+CONFIGS = ["tiny", "small", "mid", "maory_like"]
+OP_TOL = 1e-5
+LAYER_TOL = 1e-4
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def to_dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.float32))).cuda()
+
+
+def to_host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+_ctx_cache = {}
+
+
+def ctx_for(lib, name):
+    if name not in _ctx_cache:
+        print("\n[gpu] building context", name, flush=True)
+        _ctx_cache[name] = lib.Context(get_config(name), device=0)
+    return _ctx_cache[name]
+
+
+def synth_slopes(S, k, key=11):
+    true = next(frozen_flow_frames(S.cfg, 1, key, first=k))
+    phi = np.concatenate([p.astype(np.float64).ravel() for p in true])
+    s = S.apply_A(phi)
+    sig = [w["sigma"] for w in S.cfg["wfs"]]
+    return (s + slope_noise(S.geom.n_slopes, sig, key, k)).astype(np.float32)
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_apply_A(gpu_lib, systems, name):
+    S = systems(name)
+    ctx = ctx_for(gpu_lib, name)
+    x = random_vector(S.geom.n_coeff, 100, CONFIGS.index(name))
+    got = to_host(ctx.apply_A(to_dev(x)))
+    assert rel(got, S.apply_A(x)) <= OP_TOL
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_apply_AT(gpu_lib, systems, name):
+    S = systems(name)
+    ctx = ctx_for(gpu_lib, name)
+    y = random_vector(S.A.shape[0], 101, CONFIGS.index(name))
+    got = to_host(ctx.apply_AT(to_dev(y)))
+    assert rel(got, S.apply_AT(y)) <= OP_TOL
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_apply_M(gpu_lib, systems, name):
+    S = systems(name)
+    ctx = ctx_for(gpu_lib, name)
+    c = random_vector(S.geom.n_coeff, 102, CONFIGS.index(name))
+    got = to_host(ctx.apply_M(to_dev(c)))
+    ref = S.apply_M(c)
+    assert rel(got, ref) <= OP_TOL
+    # per layer as well (a small layer must not hide behind a big one)
+    for l in range(S.Lc):
+        o = S.geom.layer_off
+        assert rel(got[o[l]:o[l + 1]], ref[o[l]:o[l + 1]]) <= OP_TOL
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_rhs(gpu_lib, systems, name):
+    S = systems(name)
+    ctx = ctx_for(gpu_lib, name)
+    s = synth_slopes(S, 0)
+    got = to_host(ctx.rhs(to_dev(s)))
+    assert rel(got, S.rhs(s)) <= OP_TOL
+
+
+def _oracle_state(S, n_frames):
+    """Oracle-only warm-start chain; returns the FP32-rounded state after it."""
+    st = State(S.geom.n_coeff, S.geom.n_coeff)
+    for k in range(n_frames):
+        st, _ = frame(S, st, synth_slopes(S, k).astype(np.float64))
+    return st.pack().astype(np.float32)
+
+
+def _check_frame(gpu_lib, S, ctx, state32, s32, iters=None):
+    import torch
+    iters = S.cfg["iters"] if iters is None else iters
+    st_dev = to_dev(state32)
+    lay = torch.empty(S.geom.n_coeff, device="cuda", dtype=torch.float32)
+    dm = torch.empty(S.geom.n_coeff, device="cuda", dtype=torch.float32)
+    ctx.reconstruct(to_dev(s32), st_dev, lay, dm, iters=iters)
+    got_state, got_lay, got_dm = to_host(st_dev), to_host(lay), to_host(dm)
+    ref_st, ref_phi = frame(S, State.unpack(state32, S.geom.n_coeff, S.geom.n_coeff),
+                            s32.astype(np.float64), iters=iters)
+    o = S.geom.layer_off
+    for l in range(S.Lc):
+        assert rel(got_lay[o[l]:o[l + 1]], ref_phi[o[l]:o[l + 1]]) <= LAYER_TOL, ("layer", l)
+    g = State.unpack(got_state, S.geom.n_coeff, S.geom.n_coeff)
+    assert rel(g.c, ref_st.c) <= LAYER_TOL
+    assert rel(g.b, ref_st.b) <= OP_TOL
+    assert rel(g.r, ref_st.r) <= LAYER_TOL * 10
+    assert rel(g.a, ref_st.a) <= LAYER_TOL
+    n = S.geom.n_coeff
+    assert np.array_equal(g.a_prev, state32[4 * n:5 * n].astype(np.float64))  # a_prev <- a
+    assert np.array_equal(got_dm.astype(np.float32), g.a.astype(np.float32))
+    return g
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_reconstruct_first_frame(gpu_lib, systems, name):
+    S = systems(name)
+    ctx = ctx_for(gpu_lib, name)
+    state = np.zeros(5 * S.geom.n_coeff, dtype=np.float32)
+    _check_frame(gpu_lib, S, ctx, state, synth_slopes(S, 0))
+
+
+@pytest.mark.parametrize("name", ["small", "mid", "maory_like"])
+def test_reconstruct_warm_frame(gpu_lib, systems, name):
+    # identical input state for both sides: the oracle's own chain, rounded to FP32
+    S = systems(name)
+    ctx = ctx_for(gpu_lib, name)
+    state = _oracle_state(S, 3)
+    _check_frame(gpu_lib, S, ctx, state, synth_slopes(S, 3))
+
+
+def test_reconstruct_gain_and_iterations(gpu_lib, systems):
+    cfg = get_config("small", gain=0.6)
+    from oracle.operators import System
+    S = System(cfg)
+    ctx = gpu_lib.Context(cfg, device=0)
+    state = _oracle_state(systems("small"), 2)
+    for iters in (0, 1, 7):
+        _check_frame(gpu_lib, S, ctx, state, synth_slopes(S, 2), iters=iters)
+
+
+def test_zero_input_gives_zero(gpu_lib, systems):
+    S = systems("small")
+    ctx = ctx_for(gpu_lib, "small")
+    import torch
+    st = torch.zeros(5 * S.geom.n_coeff, device="cuda")
+    s = torch.zeros(S.A.shape[0], device="cuda")
+    ctx.reconstruct(s, st, iters=4)
+    assert float(torch.abs(st).max()) == 0.0
+
+
+def test_chain_drift(gpu_lib, systems):
+    # GPU-only warm-start chain vs the oracle's chain from the same zero state
+    S = systems("small")
+    ctx = ctx_for(gpu_lib, "small")
+    import torch
+    st_dev = torch.zeros(5 * S.geom.n_coeff, device="cuda")
+    lay = torch.empty(S.geom.n_coeff, device="cuda")
+    st = State(S.geom.n_coeff, S.geom.n_coeff)
+    worst = 0.0
+    for k in range(10):
+        s = synth_slopes(S, k)
+        ctx.reconstruct(to_dev(s), st_dev, lay, iters=S.cfg["iters"])
+        st, phi = frame(S, st, s.astype(np.float64))
+        worst = max(worst, rel(to_host(lay), phi))
+    print("\n[gpu] chained drift over 10 frames:", worst)
+    assert worst <= 1e-3
+
+
+def test_apply_M_symmetric_on_gpu(gpu_lib, systems):
+    S = systems("small")
+    ctx = ctx_for(gpu_lib, "small")
+    u = random_vector(S.geom.n_coeff, 103, 0)
+    v = random_vector(S.geom.n_coeff, 104, 0)
+    Mu = to_host(ctx.apply_M(to_dev(u)))
+    Mv = to_host(ctx.apply_M(to_dev(v)))
+    a, b = Mu @ v, u @ Mv
+    assert abs(a - b) <= 1e-5 * np.linalg.norm(Mu) * np.linalg.norm(v)
+
+
+def _batch_inputs(lib, systems, names):
+    import torch
+    ctxs, slopes, states = [], [], []
+    for k, nm in enumerate(names):
+        S = systems(nm)
+        ctxs.append(lib.Context(get_config(nm), device=0))
+        slopes.append(to_dev(synth_slopes(S, k)))
+        states.append(to_dev(_oracle_state(S, 1) if k % 2 else np.zeros(5 * S.geom.n_coeff, np.float32)))
+    return ctxs, slopes, states
+
+
+def test_batch_matches_single_bitwise(gpu_lib, systems):
+    import torch
+    names = ["small", "tiny", "mid", "small"]
+    ctxs, slopes, states = _batch_inputs(gpu_lib, systems, names)
+    singles = [s.clone() for s in states]
+    lay_single = [torch.empty(c.n_coeff, device="cuda") for c in ctxs]
+    for c, s, st, ly in zip(ctxs, slopes, singles, lay_single):
+        c.reconstruct(s, st, ly, iters=4)
+    batch = gpu_lib.Batch(ctxs)
+    bst = [s.clone() for s in states]
+    lay_b = [torch.empty(c.n_coeff, device="cuda") for c in ctxs]
+    batch.reconstruct(slopes, bst, lay_b, iters=4, use_graph=False)
+    torch.cuda.synchronize()
+    for a, b in zip(singles, bst):
+        assert torch.equal(a, b)
+    for a, b in zip(lay_single, lay_b):
+        assert torch.equal(a, b)
+
+
+def test_graph_replay_matches_direct_bitwise(gpu_lib, systems):
+    import torch
+    names = ["small", "mid"]
+    ctxs, slopes, states = _batch_inputs(gpu_lib, systems, names)
+    batch = gpu_lib.Batch(ctxs)
+    direct = [s.clone() for s in states]
+    graph = [s.clone() for s in states]
+    for rep in range(3):  # several frames: replays after the first reuse the graph
+        batch.reconstruct(slopes, direct, iters=4, use_graph=False)
+        torch.cuda.synchronize()
+        batch.reconstruct(slopes, graph, iters=4, use_graph=True)
+        torch.cuda.synchronize()
+        for a, b in zip(direct, graph):
+            assert torch.equal(a, b), rep
+
+
+def test_repeat_runs_bitwise(gpu_lib, systems):
+    import torch
+    S = systems("maory_like")
+    ctx = ctx_for(gpu_lib, "maory_like")
+    s = to_dev(synth_slopes(S, 5))
+    outs = []
+    for _ in range(2):
+        st = torch.zeros(5 * S.geom.n_coeff, device="cuda")
+        ctx.reconstruct(s, st, iters=4)
+        outs.append(st)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
