@@ -166,7 +166,7 @@ FEWHA_API fewha_status fewha_rhs(fewha_ctx* ctx, const float* slopes, float* b);
 /* One time step of Algorithm 1 (open loop, F = I, plain warm restart):
  *   b' = rhs(slopes); r0 = (b' - b) + r; c <- PCG(c, r0, J, iters);
  *   phi = W^{-1} c; a_prev <- a; a <- (1-gain) a + gain phi.
- * state (in/out, n_state floats) = [c | b | r | a_prev | a]; an all-zero
+ * state (in/out, n_state floats, 16-byte aligned) = [c | b | r | a_prev | a]; an all-zero
  * state starts a sequence (c = 0, r0 = b').  layers_out (N_c) and dm_out
  * (n_act) may be NULL.  iters in [0, 256].  PCG inner products and the
  * alpha/beta recurrences are computed in double precision. */

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -126,7 +127,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   }
   // ---- descriptors and tile lists ----
   struct ProbLayout {
-    size_t phi, phiadj, tmpa, tmpb, sd, vadj, part, p0, p1, q, dots, jinv, itab, ftab, cmap, cinv;
+    size_t phi, phiadj, tmpa, tmpb, sd, vadj, part, p0, p1, q, dots, jinv, itab, ftab, cmap, cinv, gl;
   };
   std::vector<ProbLayout> lay(P.nprob);
   Carver cv;
@@ -135,6 +136,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   // host table images per problem (copied after allocation)
   std::vector<std::vector<int>> itab(P.nprob), cmap(P.nprob);
   std::vector<std::vector<float>> ftab(P.nprob), cinv(P.nprob), jinv(P.nprob);
+  std::vector<std::vector<GLPar>> glp(P.nprob);
   for (int k = 0; k < P.nprob; ++k) {
     const HostModel& m = *models[k];
     ProbDev pd{};
@@ -147,7 +149,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     pd.n_slopes = (int)m.n_slopes;
     pd.n_act = (int)m.n_c;
     pd.gain = (float)m.gain;
-    int tmp_total = 0, nmax = 0;
+    int tmp_total = 0;
     for (int l = 0; l < L; ++l) {
       const LayerHost& lh = m.layers[l];
       LayerDev ld{};
@@ -162,7 +164,6 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
       ld.inv_delta = (float)(1.0 / lh.delta);
       for (int j = 0; j < kMaxLevelsJ; ++j) ld.alpha_d[j] = (float)(m.alpha * lh.dtab[j]);
       P.hL.push_back(ld);
-      nmax = std::max(nmax, ld.n);
     }
     int s_tot = 0, v_tot = 0, m_tot = 0, part_tot = 0, tab_tot = 0;
     for (int g = 0; g < G; ++g) {
@@ -186,7 +187,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
       wd.n_tiles_s = wd.tiles_side * wd.tiles_side;
       wd.part_off = part_tot;
       part_tot += 4 * wd.n_tiles_s;
-      wd.tab_stride = 4 * wd.nc + 4 * nmax;
+      wd.tab_stride = 4 * wd.nc;
       wd.tab_off = tab_tot;
       tab_tot += L * wd.tab_stride;
       wd.inv_sigma2 = (float)(1.0 / (wh.d.sigma * wh.d.sigma));
@@ -206,23 +207,34 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
       for (int e = 0; e < 3 * wd.N * wd.N; ++e) cinv[k][wd.cinv_off + e] = (float)wh.cinv[e];
       for (int l = 0; l < L; ++l) {
         const GLTables& t = m.tab[g][l];
-        const int base = wd.tab_off + l * wd.tab_stride, nc = wd.nc, n = m.layers[l].d.n;
+        const int base = wd.tab_off + l * wd.tab_stride, nc = wd.nc;
         for (int j = 0; j < nc; ++j) {
           itab[k][base + j] = t.q0y[j];
           itab[k][base + nc + j] = t.q0x[j];
           ftab[k][base + 2 * nc + j] = (float)t.wy[j];
           ftab[k][base + 3 * nc + j] = (float)t.wx[j];
         }
-        for (int p = 0; p < n; ++p) {
-          itab[k][base + 4 * nc + p] = t.ay0[p];
-          itab[k][base + 4 * nc + n + p] = t.ayc[p];
-          itab[k][base + 4 * nc + 2 * n + p] = t.ax0[p];
-          itab[k][base + 4 * nc + 3 * n + p] = t.axc[p];
-        }
       }
     }
     jinv[k].resize(m.n_c);
     for (long e = 0; e < m.n_c; ++e) jinv[k][e] = (float)(1.0 / m.J[e]);
+    // propagation-adjoint parameters per (sensor, layer)
+    glp[k].resize((size_t)G * L);
+    for (int g = 0; g < G; ++g)
+      for (int l = 0; l < L; ++l) {
+        const WfsHost& wh = m.wfs[g];
+        const LayerHost& lh = m.layers[l];
+        const double scale = (wh.d.kind == FEWHA_LGS) ? 1.0 - lh.d.h / wh.d.H : 1.0;
+        GLPar gp{};
+        gp.t0y = (scale * (-0.5 * m.D) + lh.d.h * wh.d.theta_y + 0.5 * m.L) / lh.delta;
+        gp.t0x = (scale * (-0.5 * m.D) + lh.d.h * wh.d.theta_x + 0.5 * m.L) / lh.delta;
+        gp.rho = scale * (m.D / wh.d.n_subap) / lh.delta;
+        gp.inv_rho = 1.0 / gp.rho;
+        gp.nc = wh.d.n_subap + 1;
+        gp.v_off = P.hW[pd.wfs0 + g].v_off;
+        gp.kmax = gp.rho >= 1.0 ? 2 : (gp.rho >= 2.0 / 3.0 ? 3 : 0);
+        glp[k][(size_t)g * L + l] = gp;
+      }
     // tiles
     int slot = 0;
     int maxng = 0;
@@ -262,9 +274,9 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
         for (int tx = 0; tx < tc; ++tx) t_gt.push_back({k, g, ty, tx, 0, 0, 0, 0});
     }
     for (int l = 0; l < L; ++l) {
-      const int tn = cdiv(P.hL[pd.layer0 + l].n, kTileN);
-      for (int ty = 0; ty < tn; ++ty)
-        for (int tx = 0; tx < tn; ++tx) t_pt.push_back({k, l, ty, tx, 0, 0, 0, 0});
+      const int nt = cdiv(P.hL[pd.layer0 + l].n, kTileN);
+      for (int ty = 0; ty < nt; ++ty)
+        for (int tx = 0; tx < nt; ++tx) t_pt.push_back({k, l, ty, tx, 0, 0, 0, 0});
     }
     // buffer layout
     ProbLayout& pl_ = lay[k];
@@ -285,6 +297,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     pl_.ftab = cv.take(sizeof(float) * tab_tot);
     pl_.cmap = cv.take(sizeof(int) * m_tot);
     pl_.cinv = cv.take(sizeof(float) * 3 * (size_t)m_tot);
+    pl_.gl = cv.take(sizeof(GLPar) * (size_t)G * L);
     P.hP.push_back(pd);
   }
   // concatenated tile list
@@ -338,6 +351,9 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     pd.ftab = (const float*)(base + l.ftab);
     pd.cmap = (const int*)(base + l.cmap);
     pd.cinv = (const float*)(base + l.cinv);
+    pd.gl = (const GLPar*)(base + l.gl);
+
+    HIP_TRY(hipMemcpy(base + l.gl, glp[k].data(), sizeof(GLPar) * glp[k].size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(base + l.jinv, jinv[k].data(), sizeof(float) * jinv[k].size(), hipMemcpyHostToDevice));
     if (!itab[k].empty()) {
       HIP_TRY(hipMemcpy(base + l.itab, itab[k].data(), sizeof(int) * itab[k].size(), hipMemcpyHostToDevice));
@@ -687,6 +703,7 @@ fewha_status fewha_reconstruct(fewha_ctx* c, const float* slopes, float* state, 
   if (s != FEWHA_OK) return s;
   if (!slopes || !state) return fail(c, FEWHA_EINVAL, "reconstruct: null slopes or state");
   if (iters < 0 || iters > kMaxIters) return fail(c, FEWHA_EINVAL, "reconstruct: iters must lie in [0, 256]");
+  if (((uintptr_t)state & 15) != 0) return fail(c, FEWHA_EINVAL, "reconstruct: state must be 16-byte aligned");
   Plan& P = *c->plan;
   std::vector<IoDev> io(1);
   io[0].in = slopes;
@@ -745,6 +762,8 @@ fewha_status fewha_batch_reconstruct(fewha_batch* b, const float* const* slopes,
   std::vector<IoDev> io(P.nprob);
   for (int k = 0; k < P.nprob; ++k) {
     if (!slopes[k] || !state[k]) return bfail(b, FEWHA_EINVAL, "batch_reconstruct: null pointer for problem " + std::to_string(k));
+    if (((uintptr_t)state[k] & 15) != 0)
+      return bfail(b, FEWHA_EINVAL, "batch_reconstruct: state must be 16-byte aligned (problem " + std::to_string(k) + ")");
     io[k].in = slopes[k];
     io[k].state = state[k];
     io[k].layers_out = layers_out ? layers_out[k] : nullptr;

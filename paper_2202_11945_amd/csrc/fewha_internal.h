@@ -16,7 +16,7 @@ namespace fewha {
 constexpr int kMaxLevelsJ = 16;   // j index range of the per-layer prior table
 constexpr int kResMax = 128;      // largest block kept resident in LDS by the DWT kernels
 constexpr int kTileS = 16;        // subaperture / corner tile side of the sensor stages
-constexpr int kTileN = 32;        // node tile side of the layer stages
+constexpr int kTileN = 32;        // node tile side of the propagation adjoint
 constexpr int kUpdChunk = 2048;   // coefficients per workgroup of the vector update
 
 // db3 analysis filters, passed by value to the transform kernels.
@@ -58,12 +58,19 @@ struct WfsDev {
 };
 
 // Per-(sensor, layer) table layout inside the int/float table arrays, relative
-// to WfsDev::tab_off + l * tab_stride:
-//   int   q0y[nc], q0x[nc]                  bilinear cell of each corner row/column
-//   float wy[nc],  wx[nc]                   fractional offsets
-//   int   ay0[n], ayc[n], ax0[n], axc[n]    first corner row/column and count
-//                                           touching each layer node row/column
-// (n = the layer's grid side; the float array shares the offsets.)
+// to WfsDev::tab_off + l * tab_stride (tab_stride = 4 nc):
+//   int   q0y[nc], q0x[nc]   bilinear cell of each corner row / column
+//   float wy[nc],  wx[nc]    fractional offsets (float slots [2nc, 4nc))
+
+// Propagation of one (sensor, layer) pair in node units: corner k of the
+// sensor sits at t = t0 + k rho along each axis (rho = cone factor x pitch /
+// layer spacing) and its bilinear weight on node p is the hat function
+// max(0, 1 - |t - p|).  kmax = most corners within one node spacing of a
+// node along an axis (2 when rho >= 1, 3 when rho >= 2/3, 0 = finer).
+struct GLPar {
+  double t0y, t0x, rho, inv_rho;
+  int nc, v_off, kmax, pad0;
+};
 
 // One problem.
 struct ProbDev {
@@ -95,6 +102,7 @@ struct ProbDev {
   const float* ftab;     // float tables
   const int* cmap;       // compact-index maps
   const float* cinv;     // 2x2 inverse noise blocks
+  const GLPar* gl;       // [sensor][layer] propagation parameters
 };
 
 // Per-call input/output pointers of one problem.
@@ -133,7 +141,6 @@ struct LayerHost {
 struct GLTables {  // one (sensor, layer) pair
   std::vector<int> q0y, q0x;   // nc
   std::vector<double> wy, wx;  // nc
-  std::vector<int> ay0, ayc, ax0, axc;  // n
 };
 
 struct HostModel {

@@ -3,6 +3,10 @@
 // whole batch.  Bulk arithmetic is FP32; PCG inner products are accumulated
 // in FP64 per workgroup and summed across workgroups in a fixed order
 // (deterministic: no atomics anywhere).
+//
+// Memory-level parallelism: the transform and vector kernels gather the
+// loads of several elements before their dependent stores (fetch / finish
+// pairs), so a thread keeps several global loads in flight.
 #include "kernels.h"
 
 namespace fewha {
@@ -17,6 +21,16 @@ __device__ __forceinline__ double wave_sum(double v) {
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
   return v;
 }
 
@@ -34,10 +48,13 @@ __device__ __forceinline__ T block_sum(T v, T* sh, int nthreads) {
   return r;
 }
 
-__device__ __forceinline__ double sum_slots(const double* s, int n) {
+// Sum of n slots by one wave in a fixed order (lane-strided partial sums,
+// then a fixed shuffle tree); the value of lane 0 is the result, identical in
+// every workgroup that sums the same slots.
+__device__ __forceinline__ double wave_sum_slots(const double* s, int n) {
   double a = 0.0;
-  for (int i = 0; i < n; ++i) a += s[i];
-  return a;
+  for (int i = threadIdx.x & 63; i < n; i += 64) a += s[i];
+  return wave_sum(a);
 }
 
 __device__ __forceinline__ const double* dot_group(const ProbDev& pr, int g) {
@@ -49,17 +66,16 @@ __device__ __forceinline__ int rho_count(const ProbDev& pr, int k) {
 
 // Search-direction source of the inverse transform (fused p update).
 struct PSrc {
-  const float* src;   // plain source (SRC_IN / SRC_STATE_C)
-  const float* r;
-  const float* jinv;
-  const float* pold;
-  float* pnew;
+  const float* __restrict__ src;  // plain source (SRC_IN / SRC_STATE_C)
+  const float* __restrict__ r;
+  const float* __restrict__ jinv;
+  const float* __restrict__ pold;
+  float* __restrict__ pnew;
   float beta;
   int mode;
 };
 
-__device__ __forceinline__ PSrc make_psrc(const ProbDev& pr, const IoDev& io, int mode, int iter,
-                                          const double* sbeta) {
+__device__ __forceinline__ PSrc make_psrc(const ProbDev& pr, const IoDev& io, int mode, int iter, float beta) {
   PSrc s;
   s.mode = mode;
   s.src = (mode == SRC_IN) ? io.in : io.state;  // state starts with c
@@ -67,35 +83,58 @@ __device__ __forceinline__ PSrc make_psrc(const ProbDev& pr, const IoDev& io, in
   s.jinv = pr.jinv;
   s.pnew = (iter & 1) ? pr.pbuf1 : pr.pbuf0;
   s.pold = (iter & 1) ? pr.pbuf0 : pr.pbuf1;
-  s.beta = (float)(*sbeta);
+  s.beta = beta;
   return s;
 }
 
-__device__ __forceinline__ float load_coef(const PSrc& s, int e, bool owner) {
-  if (s.mode == SRC_IN || s.mode == SRC_STATE_C) return s.src[e];
-  const float z = s.r[e] * s.jinv[e];
-  const float p = (s.mode == SRC_PUPD0) ? z : fmaf(s.beta, s.pold[e], z);
+struct CoefLoad {
+  float a, b, c;
+};
+__device__ __forceinline__ CoefLoad coef_fetch(const PSrc& s, int e) {
+  CoefLoad v{0.f, 0.f, 0.f};
+  if (s.mode == SRC_IN || s.mode == SRC_STATE_C) {
+    v.a = s.src[e];
+  } else {
+    v.a = s.r[e];
+    v.b = s.jinv[e];
+    if (s.mode == SRC_PUPD) v.c = s.pold[e];
+  }
+  return v;
+}
+// p = J^{-1} r (first iteration) or p = J^{-1} r + beta p_old; written once by its owner
+__device__ __forceinline__ float coef_finish(const PSrc& s, int e, const CoefLoad& v, bool owner) {
+  if (s.mode == SRC_IN || s.mode == SRC_STATE_C) return v.a;
+  const float z = v.a * v.b;
+  const float p = (s.mode == SRC_PUPD0) ? z : fmaf(s.beta, v.c, z);
   if (owner) s.pnew[e] = p;
   return p;
 }
 
-// beta_k = rho_k / rho_{k-1} (computed by thread 0, broadcast through LDS)
-__device__ __forceinline__ void compute_beta(const ProbDev& pr, int mode, int iter, double* sbeta) {
-  if (threadIdx.x == 0) {
-    double b = 0.0;
-    if (mode == SRC_PUPD) {
-      const double rk = sum_slots(dot_group(pr, 2 * iter), rho_count(pr, iter));
-      const double rkm = sum_slots(dot_group(pr, 2 * (iter - 1)), rho_count(pr, iter - 1));
-      b = (rkm != 0.0) ? rk / rkm : 0.0;
-    }
-    *sbeta = b;
+// beta_k = rho_k / rho_{k-1}, summed by wave 0 and broadcast through LDS
+__device__ __forceinline__ float compute_beta(const ProbDev& pr, int mode, int iter, double* sb) {
+  if (mode == SRC_PUPD && threadIdx.x < 64) {
+    const double rk = wave_sum_slots(dot_group(pr, 2 * iter), rho_count(pr, iter));
+    const double rkm = wave_sum_slots(dot_group(pr, 2 * (iter - 1)), rho_count(pr, iter - 1));
+    if (threadIdx.x == 0) *sb = (rkm != 0.0) ? rk / rkm : 0.0;
+  } else if (threadIdx.x == 0) {
+    *sb = 0.0;
   }
   __syncthreads();
+  return (float)(*sb);
 }
 
 // Final output of the inverse transform: phi = delta^{-1} W^T c, optionally
 // with the open-loop control update of Algorithm 1 (F = I).
-__device__ __forceinline__ void idwt_out(const ProbDev& pr, const IoDev& io, int out_mode, int e, float v) {
+struct OutLoad {
+  float a;
+};
+__device__ __forceinline__ OutLoad out_fetch(const ProbDev& pr, const IoDev& io, int out_mode, int e) {
+  OutLoad o{0.f};
+  if (out_mode == OUT_FIT) o.a = io.state[3L * pr.n_c + pr.n_act + e];
+  return o;
+}
+__device__ __forceinline__ void out_finish(const ProbDev& pr, const IoDev& io, int out_mode, int e, float v,
+                                           const OutLoad& o) {
   if (out_mode == OUT_PHI) {
     pr.phi[e] = v;
   } else if (out_mode == OUT_USER) {
@@ -104,17 +143,62 @@ __device__ __forceinline__ void idwt_out(const ProbDev& pr, const IoDev& io, int
     if (io.layers_out) io.layers_out[e] = v;
     float* aprev = io.state + 3L * pr.n_c;
     float* a = aprev + pr.n_act;
-    const float old = a[e];
-    const float nw = (1.0f - pr.gain) * old + pr.gain * v;
-    aprev[e] = old;
+    const float nw = (1.0f - pr.gain) * o.a + pr.gain * v;
+    aprev[e] = o.a;
     a[e] = nw;
     if (io.dm_out) io.dm_out[e] = nw;
   }
 }
 
+// Forward-transform epilogue at layer position e (level index j):
+// v = delta^{-1} (W x)_e, then
+//   EPI_APPLYM: out = v + alpha D x            (M x)
+//   EPI_PCG   : q = v + alpha D p, += p q      (M p and pi)
+//   EPI_RHS   : b' = v, r0 = (b' - b) + r      (warm restart), += r0 J^{-1} r0
+//   EPI_PLAIN : out = v                        (right-hand side only)
+struct EpiLoad {
+  float x0, x1, x2;
+};
+__device__ __forceinline__ EpiLoad epi_fetch(const ProbDev& pr, const IoDev& io, int epi, int iter, int e) {
+  EpiLoad l{0.f, 0.f, 0.f};
+  if (epi == EPI_APPLYM) {
+    l.x0 = io.in[e];
+  } else if (epi == EPI_PCG) {
+    l.x0 = ((iter & 1) ? pr.pbuf1 : pr.pbuf0)[e];
+  } else if (epi == EPI_RHS) {
+    l.x0 = io.state[pr.n_c + e];
+    l.x1 = io.state[2L * pr.n_c + e];
+    l.x2 = pr.jinv[e];
+  }
+  return l;
+}
+__device__ __forceinline__ void epi_finish(const ProbDev& pr, const LayerDev& ly, const IoDev& io, int epi, int e,
+                                           int j, float v, const EpiLoad& l, double& acc) {
+  const float ad = ly.alpha_d[j];
+  if (epi == EPI_APPLYM) {
+    io.out[e] = v + ad * l.x0;
+  } else if (epi == EPI_PCG) {
+    const float qe = v + ad * l.x0;
+    pr.q[e] = qe;
+    acc += (double)l.x0 * (double)qe;
+  } else if (epi == EPI_RHS) {
+    const float r0 = (v - l.x0) + l.x1;
+    io.state[pr.n_c + e] = v;
+    io.state[2L * pr.n_c + e] = r0;
+    acc += (double)r0 * (double)r0 * (double)l.x2;
+  } else {
+    io.out[e] = v;
+  }
+}
+
+__device__ __forceinline__ int dot_group_of(int epi, int iter) { return epi == EPI_PCG ? 2 * iter + 1 : 0; }
+
+constexpr int kU = 4;  // elements per thread with loads in flight together
+
 // ------------------------------------------------ inverse DWT, resident part
 // One workgroup per (problem, layer): all synthesis levels whose output side
-// is at most kResMax run in LDS.  Columns then rows, periodic, Mallat layout.
+// is at most kResMax run in LDS.  Columns then rows, periodic, Mallat layout:
+//   x_t = sum_{i = t mod 2} h_i a[(t-i)/2] + g_i d[(t-i)/2]   (indices mod m/2)
 __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
                                                    const Tile* tiles, Filter F, int src_mode, int out_mode,
                                                    int iter) {
@@ -125,23 +209,54 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[pr.layer0 + t.item];
   const IoDev& io = IO[t.prob];
-  compute_beta(pr, src_mode, iter, &sbeta);
-  const PSrc ps = make_psrc(pr, io, src_mode, iter, &sbeta);
+  const float beta = compute_beta(pr, src_mode, iter, &sbeta);
+  const PSrc ps = make_psrc(pr, io, src_mode, iter, beta);
   const int n = ly.n, R = ly.res, lr = __builtin_ctz(R);
-  const int m0 = n >> ly.levels;
+  const int m0 = n >> ly.levels, l0 = __builtin_ctz(m0);
   const int off = ly.off;
   const int nt = blockDim.x;
-  for (int e = threadIdx.x; e < m0 * m0; e += nt) {
-    const int r = e / m0, c = e - r * m0;
-    A[(r << lr) + c] = load_coef(ps, off + r * n + c, true);
+  // coarse block
+  for (int e0 = threadIdx.x; e0 < m0 * m0; e0 += kU * nt) {
+    CoefLoad v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * nt;
+      if (e < m0 * m0) v[u] = coef_fetch(ps, off + (e >> l0) * n + (e & (m0 - 1)));
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * nt;
+      if (e < m0 * m0) {
+        const int r = e >> l0, c = e & (m0 - 1);
+        A[(r << lr) + c] = coef_finish(ps, off + r * n + c, v[u], true);
+      }
+    }
   }
-  __syncthreads();
   for (int m = 2 * m0; m <= R; m <<= 1) {
-    const int half = m >> 1, lm = __builtin_ctz(m);
-    for (int e = threadIdx.x; e < m * m; e += nt) {
-      const int r = e >> lm, c = e & (m - 1);
-      if (r < half && c < half) continue;
-      A[(r << lr) + c] = load_coef(ps, off + r * n + c, true);
+    const int half = m >> 1, lh = __builtin_ctz(half), lm = lh + 1;
+    const int q2 = half * half, total = 3 * q2;
+    // detail quadrants: 0 = (rows < half, cols >= half), 1 = (>=, <), 2 = (>=, >=)
+    for (int f0 = threadIdx.x; f0 < total; f0 += kU * nt) {
+      CoefLoad v[kU];
+      int pos[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int f = f0 + u * nt;
+        pos[u] = -1;
+        if (f < total) {
+          const int qd = f >> (2 * lh), w = f & (q2 - 1);
+          const int r = (w >> lh) + (qd >= 1 ? half : 0), c = (w & (half - 1)) + (qd != 1 ? half : 0);
+          pos[u] = r * n + c;
+          v[u] = coef_fetch(ps, off + pos[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (pos[u] >= 0) {
+          const int r = pos[u] / n, c = pos[u] - r * n;
+          A[(r << lr) + c] = coef_finish(ps, off + pos[u], v[u], true);
+        }
+      }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < m * m; e += nt) {  // columns (along y)
@@ -165,10 +280,20 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
     }
     __syncthreads();
   }
+  if (m0 == R) __syncthreads();  // no synthesis level ran: order the coarse-block stores
   if (n == R) {
-    for (int e = threadIdx.x; e < R * R; e += nt) {
-      const int r = e >> lr, c = e & (R - 1);
-      idwt_out(pr, io, out_mode, off + r * n + c, A[e] * ly.inv_delta);
+    for (int e0 = threadIdx.x; e0 < R * R; e0 += kU * nt) {
+      OutLoad o[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int e = e0 + u * nt;
+        if (e < R * R) o[u] = out_fetch(pr, io, out_mode, off + e);  // n == R: row-major e
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int e = e0 + u * nt;
+        if (e < R * R) out_finish(pr, io, out_mode, off + e, A[e] * ly.inv_delta, o[u]);
+      }
     }
   } else {
     float* dst = pr.tmpa + ly.tmp_off;
@@ -194,8 +319,8 @@ __global__ __launch_bounds__(256) void k_idwt_glob(const ProbDev* P, const Layer
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[pr.layer0 + t.item];
   const IoDev& io = IO[t.prob];
-  compute_beta(pr, src_mode, iter, &sbeta);
-  const PSrc ps = make_psrc(pr, io, src_mode, iter, &sbeta);
+  const float beta = compute_beta(pr, src_mode, iter, &sbeta);
+  const PSrc ps = make_psrc(pr, io, src_mode, iter, beta);
   const int n = ly.n, off = ly.off;
   const int m = 1 << t.level, half = m >> 1;
   const int t0 = t.ty * kGT, s0 = t.tx * kGT;
@@ -203,22 +328,43 @@ __global__ __launch_bounds__(256) void k_idwt_glob(const ProbDev* P, const Layer
   float* nxt = ((step & 1) ? pr.tmpa : pr.tmpb) + ly.tmp_off;       // stride m
   const int kr0 = (t0 >> 1) - 2, kc0 = (s0 >> 1) - 2;
   const int W1 = kGW + 1;
-  for (int e = threadIdx.x; e < kGW * kGW; e += blockDim.x) {
-    const int ly_ = e / kGW, lx_ = e - ly_ * kGW;
-    const int by = ly_ >= kGH, bx = lx_ >= kGH;
-    const int iy = ly_ - by * kGH, ix = lx_ - bx * kGH;
-    const int kr = (kr0 + iy) & (half - 1), kc = (kc0 + ix) & (half - 1);
-    float v;
-    if (!by && !bx) {
-      v = ll[kr * half + kc];
-    } else {
-      const bool owner = iy >= 2 && ix >= 2;
-      v = load_coef(ps, off + (by * half + kr) * n + (bx * half + kc), owner);
+  const int nt = blockDim.x;
+  for (int e0 = threadIdx.x; e0 < kGW * kGW; e0 += kU * nt) {
+    CoefLoad v[kU];
+    int gpos[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * nt;
+      gpos[u] = -2;
+      if (e < kGW * kGW) {
+        const int ly_ = e / kGW, lx_ = e - ly_ * kGW;
+        const int by = ly_ >= kGH, bx = lx_ >= kGH;
+        const int iy = ly_ - by * kGH, ix = lx_ - bx * kGH;
+        const int kr = (kr0 + iy) & (half - 1), kc = (kc0 + ix) & (half - 1);
+        if (!by && !bx) {
+          gpos[u] = -1;
+          v[u].a = ll[kr * half + kc];
+        } else {
+          gpos[u] = (by * half + kr) * n + (bx * half + kc);
+          v[u] = coef_fetch(ps, off + gpos[u]);
+        }
+      }
     }
-    A[ly_ * W1 + lx_] = v;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * nt;
+      if (gpos[u] == -2) continue;
+      const int ly_ = e / kGW, lx_ = e - ly_ * kGW;
+      float val = v[u].a;
+      if (gpos[u] >= 0) {
+        const int iy = ly_ >= kGH ? ly_ - kGH : ly_, ix = lx_ >= kGH ? lx_ - kGH : lx_;
+        val = coef_finish(ps, off + gpos[u], v[u], iy >= 2 && ix >= 2);
+      }
+      A[ly_ * W1 + lx_] = val;
+    }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < kGT * kGW; e += blockDim.x) {  // columns
+  for (int e = threadIdx.x; e < kGT * kGW; e += nt) {  // columns
     const int lt = e / kGW, lx_ = e - lt * kGW;
     const int par = lt & 1, k = ((lt - par) >> 1) + 2;
     const float acc = F.h[par] * A[k * W1 + lx_] + F.h[par + 2] * A[(k - 1) * W1 + lx_] +
@@ -228,54 +374,37 @@ __global__ __launch_bounds__(256) void k_idwt_glob(const ProbDev* P, const Layer
   }
   __syncthreads();
   const bool final_level = (m == n);
-  for (int e = threadIdx.x; e < kGT * kGT; e += blockDim.x) {  // rows
-    const int lt = e >> 5, ls = e & 31;
-    const int par = ls & 1, k = ((ls - par) >> 1) + 2;
-    const float* Br = B + lt * W1;
-    const float acc = F.h[par] * Br[k] + F.h[par + 2] * Br[k - 1] + F.h[par + 4] * Br[k - 2] +
-                      F.g[par] * Br[kGH + k] + F.g[par + 2] * Br[kGH + k - 1] + F.g[par + 4] * Br[kGH + k - 2];
-    const int row = t0 + lt, col = s0 + ls;
-    if (final_level)
-      idwt_out(pr, io, out_mode, off + row * n + col, acc * ly.inv_delta);
-    else
-      nxt[row * m + col] = acc;
+  for (int e0 = threadIdx.x; e0 < kGT * kGT; e0 += kU * nt) {  // rows
+    OutLoad o[kU];
+    if (final_level) {
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int e = e0 + u * nt;
+        o[u] = out_fetch(pr, io, out_mode, off + (t0 + (e >> 5)) * n + s0 + (e & 31));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * nt;
+      const int lt = e >> 5, ls = e & 31;
+      const int par = ls & 1, k = ((ls - par) >> 1) + 2;
+      const float* Br = B + lt * W1;
+      const float acc = F.h[par] * Br[k] + F.h[par + 2] * Br[k - 1] + F.h[par + 4] * Br[k - 2] +
+                        F.g[par] * Br[kGH + k] + F.g[par + 2] * Br[kGH + k - 1] + F.g[par + 4] * Br[kGH + k - 2];
+      const int row = t0 + lt, col = s0 + ls;
+      if (final_level)
+        out_finish(pr, io, out_mode, off + row * n + col, acc * ly.inv_delta, o[u]);
+      else
+        nxt[row * m + col] = acc;
+    }
   }
-}
-
-// --------------------------------------------------- forward DWT epilogue
-// value v = delta^{-1} (W x)_e at layer position e with level index j.
-__device__ __forceinline__ void fdwt_out(const ProbDev& pr, const LayerDev& ly, const IoDev& io, int epi, int iter,
-                                         int e, int j, float v, double& acc) {
-  const float ad = ly.alpha_d[j];
-  if (epi == EPI_APPLYM) {
-    io.out[e] = v + ad * io.in[e];
-  } else if (epi == EPI_PCG) {
-    const float* p = (iter & 1) ? pr.pbuf1 : pr.pbuf0;
-    const float pe = p[e];
-    const float qe = v + ad * pe;
-    pr.q[e] = qe;
-    acc += (double)pe * (double)qe;
-  } else if (epi == EPI_RHS) {
-    float* b = io.state + pr.n_c;
-    float* r = io.state + 2L * pr.n_c;
-    const float r0 = (v - b[e]) + r[e];
-    b[e] = v;
-    r[e] = r0;
-    acc += (double)r0 * (double)r0 * (double)pr.jinv[e];
-  } else {  // EPI_PLAIN
-    io.out[e] = v;
-  }
-}
-
-__device__ __forceinline__ int dot_group_of(int epi, int iter) {
-  return epi == EPI_PCG ? 2 * iter + 1 : 0;
 }
 
 // ------------------------------------------------ forward DWT, one global level
 // Input side m = 2^t.level (> kResMax); output 16x16 coefficients of each of
 // the four quadrants per tile; input window 36x36 (2k .. 2k+5 per output).
-constexpr int kFT = 16;             // output coefficients per direction
-constexpr int kFW = 2 * kFT + 4;    // 36 input samples per direction
+constexpr int kFT = 16;           // output coefficients per direction
+constexpr int kFW = 2 * kFT + 4;  // 36 input samples per direction
 
 __global__ __launch_bounds__(256) void k_fdwt_glob(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
                                                    const Tile* tiles, Filter F, int epi, int iter, int step) {
@@ -289,16 +418,32 @@ __global__ __launch_bounds__(256) void k_fdwt_glob(const ProbDev* P, const Layer
   const int n = ly.n, off = ly.off;
   const int m = 1 << t.level, half = m >> 1;
   const float* in = (step == 0) ? pr.phiadj + off : (((step & 1) ? pr.tmpa : pr.tmpb) + ly.tmp_off);
+  const int istride = (step == 0) ? n : m;
   float* llout = ((step & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off;  // stride half
   const int k0 = t.ty * kFT, l0 = t.tx * kFT;
   const int XW = kFW + 1, RW = 2 * kFT + 1;
-  for (int e = threadIdx.x; e < kFW * kFW; e += blockDim.x) {
-    const int ry = e / kFW, rx = e - ry * kFW;
-    const int gy = (2 * k0 + ry) & (m - 1), gx = (2 * l0 + rx) & (m - 1);
-    X[ry * XW + rx] = in[gy * (step == 0 ? n : m) + gx];
+  const int nt = blockDim.x;
+  for (int e0 = threadIdx.x; e0 < kFW * kFW; e0 += kU * nt) {
+    float v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * nt;
+      if (e < kFW * kFW) {
+        const int ry = e / kFW, rx = e - ry * kFW;
+        v[u] = in[((2 * k0 + ry) & (m - 1)) * istride + ((2 * l0 + rx) & (m - 1))];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * nt;
+      if (e < kFW * kFW) {
+        const int ry = e / kFW, rx = e - ry * kFW;
+        X[ry * XW + rx] = v[u];
+      }
+    }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < kFW * kFT; e += blockDim.x) {  // rows (along x)
+  for (int e = threadIdx.x; e < kFW * kFT; e += nt) {  // rows (along x)
     const int ry = e / kFT, lk = e - ry * kFT;
     const float* xr = X + ry * XW + 2 * lk;
     float a = 0.f, d = 0.f;
@@ -313,27 +458,44 @@ __global__ __launch_bounds__(256) void k_fdwt_glob(const ProbDev* P, const Layer
   __syncthreads();
   double acc = 0.0;
   const int j = t.level - 1;  // detail blocks of this level have side half = 2^j
-  for (int e = threadIdx.x; e < kFT * 2 * kFT; e += blockDim.x) {  // columns (along y)
-    const int lk = e / (2 * kFT), lc = e - lk * (2 * kFT);
-    float a = 0.f, d = 0.f;
+  // 512 (row, column) pairs of the column pass, 2 per thread; each yields up to 2 outputs
+  {
+    int epos[4];
+    float eval[4];
+    EpiLoad el[4];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      const float v = Rw[(2 * lk + i) * RW + lc];
-      a += F.h[i] * v;
-      d += F.g[i] * v;
+    for (int u = 0; u < 2; ++u) {
+      const int e = threadIdx.x + u * nt;
+      const int lk = e / (2 * kFT), lc = e - lk * (2 * kFT);
+      float a = 0.f, d = 0.f;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        const float v = Rw[(2 * lk + i) * RW + lc];
+        a += F.h[i] * v;
+        d += F.g[i] * v;
+      }
+      const int row = k0 + lk;
+      const int xd = lc >= kFT;
+      const int col = l0 + lc - xd * kFT;
+      if (!xd) {
+        llout[row * half + col] = a;  // coarse block for the next level
+        epos[2 * u] = -1;
+      } else {
+        epos[2 * u] = off + row * n + (half + col);
+        eval[2 * u] = a * ly.inv_delta;
+      }
+      epos[2 * u + 1] = off + (half + row) * n + (xd * half + col);
+      eval[2 * u + 1] = d * ly.inv_delta;
     }
-    const int row = k0 + lk;
-    const int xd = lc >= kFT;
-    const int col = l0 + lc - xd * kFT;
-    if (!xd) {
-      llout[row * half + col] = a;  // coarse block for the next level
-    } else {
-      fdwt_out(pr, ly, io, epi, iter, off + row * n + (half + col), j, a * ly.inv_delta, acc);
-    }
-    fdwt_out(pr, ly, io, epi, iter, off + (half + row) * n + (xd * half + col), j, d * ly.inv_delta, acc);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (epos[k] >= 0) el[k] = epi_fetch(pr, io, epi, iter, epos[k]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (epos[k] >= 0) epi_finish(pr, ly, io, epi, epos[k], j, eval[k], el[k], acc);
   }
   if (epi == EPI_PCG || epi == EPI_RHS) {
-    const double s = block_sum(acc, sh, blockDim.x);
+    const double s = block_sum(acc, sh, nt);
     if (threadIdx.x == 0) pr.dots[(long)dot_group_of(epi, iter) * pr.n_dots + t.slot] = s;
   }
 }
@@ -353,9 +515,18 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
   const int ng = ly.n_glob_levels;
   const float* in = (ng == 0) ? pr.phiadj + off : ((((ng - 1) & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off);
   const int istride = (ng == 0) ? n : R;
-  for (int e = threadIdx.x; e < R * R; e += nt) {
-    const int r = e >> lr, c = e & (R - 1);
-    A[e] = in[r * istride + c];
+  for (int e0 = threadIdx.x; e0 < R * R; e0 += kU * nt) {
+    float v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * nt;
+      if (e < R * R) v[u] = in[(e >> lr) * istride + (e & (R - 1))];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * nt;
+      if (e < R * R) A[e] = v[u];
+    }
   }
   __syncthreads();
   double acc = 0.0;
@@ -377,25 +548,47 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
     }
     __syncthreads();
     const int j = lm - 1;
-    for (int e = threadIdx.x; e < half * m; e += nt) {  // columns: B -> A
-      const int k = e >> lm, c = e & (m - 1);
-      float a = 0.f, d = 0.f;
+    for (int e0 = threadIdx.x; e0 < half * m; e0 += 2 * nt) {  // columns: B -> A, 2 per thread
+      int epos[4];
+      float eval[4];
+      EpiLoad el[4];
 #pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        const float v = B[(((2 * k + i) & (m - 1)) << lr) + c];
-        a += F.h[i] * v;
-        d += F.g[i] * v;
+      for (int u = 0; u < 2; ++u) {
+        const int e = e0 + u * nt;
+        epos[2 * u] = epos[2 * u + 1] = -1;
+        if (e < half * m) {
+          const int k = e >> lm, c = e & (m - 1);
+          float a = 0.f, d = 0.f;
+#pragma unroll
+          for (int i = 0; i < 6; ++i) {
+            const float v = B[(((2 * k + i) & (m - 1)) << lr) + c];
+            a += F.h[i] * v;
+            d += F.g[i] * v;
+          }
+          if (c >= half) {
+            epos[2 * u] = off + k * n + c;
+            eval[2 * u] = a * ly.inv_delta;
+          }
+          epos[2 * u + 1] = off + (half + k) * n + c;
+          eval[2 * u + 1] = d * ly.inv_delta;
+          A[(k << lr) + c] = a;  // rows >= half of A are no longer read
+        }
       }
-      if (c >= half) fdwt_out(pr, ly, io, epi, iter, off + k * n + c, j, a * ly.inv_delta, acc);
-      fdwt_out(pr, ly, io, epi, iter, off + (half + k) * n + c, j, d * ly.inv_delta, acc);
-      A[(k << lr) + c] = a;  // rows >= half of A are no longer read
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (epos[k] >= 0) el[k] = epi_fetch(pr, io, epi, iter, epos[k]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (epos[k] >= 0) epi_finish(pr, ly, io, epi, epos[k], j, eval[k], el[k], acc);
     }
     __syncthreads();
   }
   const int jll = __builtin_ctz(m0);
   for (int e = threadIdx.x; e < m0 * m0; e += nt) {
     const int r = e / m0, c = e - r * m0;
-    fdwt_out(pr, ly, io, epi, iter, off + r * n + c, jll, A[(r << lr) + c] * ly.inv_delta, acc);
+    const int pos = off + r * n + c;
+    const EpiLoad l = epi_fetch(pr, io, epi, iter, pos);
+    epi_finish(pr, ly, io, epi, pos, jll, A[(r << lr) + c] * ly.inv_delta, l, acc);
   }
   if (epi == EPI_PCG || epi == EPI_RHS) {
     const double s = block_sum(acc, sh, nt);
@@ -537,53 +730,79 @@ __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* 
   const WfsDev& w = WD[pr.wfs0 + t.item];
   const int N = w.N, nc = w.nc;
   const bool weighted = mode == GT_WEIGHTED;
-  if (threadIdx.x == 0) {
-    float mx = 0.f, my = 0.f, m2x = 0.f, m2y = 0.f;
-    if (weighted && w.tt) {
+  if (weighted && w.tt) {
+    if (threadIdx.x < 64) {  // wave 0: tip/tilt means from the tile partials
       float sx = 0.f, sy = 0.f, scx = 0.f, scy = 0.f;
       const float* pp = pr.part + w.part_off;
-      for (int k = 0; k < w.n_tiles_s; ++k) {
+      for (int k = threadIdx.x; k < w.n_tiles_s; k += 64) {
         sx += pp[4 * k];
         sy += pp[4 * k + 1];
         scx += pp[4 * k + 2];
         scy += pp[4 * k + 3];
       }
-      mx = sx * w.inv_nM;
-      my = sy * w.inv_nM;
-      if (w.blocks) {
-        m2x = (scx - (w.sum_cinv[0] * mx + w.sum_cinv[1] * my)) * w.inv_nM;
-        m2y = (scy - (w.sum_cinv[2] * mx + w.sum_cinv[3] * my)) * w.inv_nM;
+      sx = wave_sum(sx);
+      sy = wave_sum(sy);
+      scx = wave_sum(scx);
+      scy = wave_sum(scy);
+      if (threadIdx.x == 0) {
+        const float mx = sx * w.inv_nM, my = sy * w.inv_nM;
+        mean[0] = mx;
+        mean[1] = my;
+        mean[2] = w.blocks ? (scx - (w.sum_cinv[0] * mx + w.sum_cinv[1] * my)) * w.inv_nM : 0.f;
+        mean[3] = w.blocks ? (scy - (w.sum_cinv[2] * mx + w.sum_cinv[3] * my)) * w.inv_nM : 0.f;
       }
     }
-    mean[0] = mx;
-    mean[1] = my;
-    mean[2] = m2x;
-    mean[3] = m2y;
+  } else if (threadIdx.x < 4) {
+    mean[threadIdx.x] = 0.f;
   }
   __syncthreads();
   const int ci0 = t.ty * kTileS, cj0 = t.tx * kTileS;
-  for (int e = threadIdx.x; e < SW * SW; e += blockDim.x) {
-    const int li = e / SW, lj = e - li * SW;
-    const int i = ci0 - 1 + li, j = cj0 - 1 + lj;  // subaperture
-    float yx = 0.f, yy = 0.f;
-    if (i >= 0 && j >= 0 && i < N && j < N && pr.cmap[w.m_off + i * N + j] >= 0) {
-      const float sx = pr.sd[w.s_off + i * N + j];
-      const float sy = pr.sd[w.s_off + N * N + i * N + j];
-      if (!weighted) {
-        yx = sx;
-        yy = sy;
-      } else if (w.blocks) {
-        const float* cb = pr.cinv + w.cinv_off + 3 * (i * N + j);
-        const float dx = sx - mean[0], dy = sy - mean[1];
-        yx = cb[0] * dx + cb[1] * dy - mean[2];
-        yy = cb[1] * dx + cb[2] * dy - mean[3];
-      } else {
-        yx = w.inv_sigma2 * (sx - mean[0]);
-        yy = w.inv_sigma2 * (sy - mean[1]);
+  const float m0 = mean[0], m1 = mean[1], m2 = mean[2], m3 = mean[3];
+  for (int e0 = threadIdx.x; e0 < SW * SW; e0 += 2 * blockDim.x) {
+    float sx[2], sy[2], cb0[2], cb1[2], cb2[2];
+    bool act[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = e0 + u * blockDim.x;
+      act[u] = false;
+      sx[u] = sy[u] = cb0[u] = cb1[u] = cb2[u] = 0.f;
+      if (e < SW * SW) {
+        const int li = e / SW, lj = e - li * SW;
+        const int i = ci0 - 1 + li, j = cj0 - 1 + lj;  // subaperture
+        if (i >= 0 && j >= 0 && i < N && j < N && pr.cmap[w.m_off + i * N + j] >= 0) {
+          act[u] = true;
+          sx[u] = pr.sd[w.s_off + i * N + j];
+          sy[u] = pr.sd[w.s_off + N * N + i * N + j];
+          if (weighted && w.blocks) {
+            const float* cb = pr.cinv + w.cinv_off + 3 * (i * N + j);
+            cb0[u] = cb[0];
+            cb1[u] = cb[1];
+            cb2[u] = cb[2];
+          }
+        }
       }
     }
-    YX[e] = yx;
-    YY[e] = yy;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = e0 + u * blockDim.x;
+      if (e >= SW * SW) continue;
+      float yx = 0.f, yy = 0.f;
+      if (act[u]) {
+        if (!weighted) {
+          yx = sx[u];
+          yy = sy[u];
+        } else if (w.blocks) {
+          const float dx = sx[u] - m0, dy = sy[u] - m1;
+          yx = cb0[u] * dx + cb1[u] * dy - m2;
+          yy = cb1[u] * dx + cb2[u] * dy - m3;
+        } else {
+          yx = w.inv_sigma2 * (sx[u] - m0);
+          yy = w.inv_sigma2 * (sy[u] - m1);
+        }
+      }
+      YX[e] = yx;
+      YY[e] = yy;
+    }
   }
   __syncthreads();
   const int li = threadIdx.x >> 4, lj = threadIdx.x & 15;
@@ -600,9 +819,70 @@ __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* 
 }
 
 // ------------------------------------------------ propagation adjoint (gather)
-// Tile of 32x32 nodes of one layer: each node gathers, from every sensor, the
-// corners whose bilinear cell touches it, with the forward weights.  No
-// atomics: each node is written by exactly one thread.
+// Node (p, q) of a layer gathers from every sensor the corners whose bilinear
+// cell touches it, weighted by the hat function of the forward interpolation:
+//   phi(p, q) = sum_g sum_{i,j} hat(t_i - p) hat(t_j - q) v_g(i, j),
+// t = t0 + rho k the corner coordinate in node units.  The corners of a node
+// are those strictly within one node spacing, found arithmetically (the
+// centre c = (p - t0) / rho in FP64, the weights 1 - rho |k - c| in FP32),
+// so every corner load is independent: no tables, no dependent chains.  At
+// most K = 2 (rho >= 1) or 3 (rho >= 2/3) corners per axis; finer sampling
+// takes a general loop.  Tile = 32x32 nodes, 4 per thread along a column.
+// No atomics: every node is written once.
+template <int K>
+struct Hat {
+  int lo, cnt;
+  float w[K];
+};
+
+template <int K>
+__device__ __forceinline__ Hat<K> hat(double t0, double rho, double inv_rho, int nc, int p) {
+  Hat<K> h;
+  const double c = ((double)p - t0) * inv_rho;
+  int lo = (int)floor(c - inv_rho) + 1, hi = (int)ceil(c + inv_rho) - 1;
+  lo = max(lo, 0);
+  hi = min(hi, nc - 1);
+  h.lo = lo;
+  h.cnt = max(0, min(hi - lo + 1, K));
+  const float r = (float)rho;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float d = (float)((double)(lo + k) - c);
+    h.w[k] = (k < h.cnt) ? fmaxf(0.f, 1.f - r * fabsf(d)) : 0.f;
+  }
+  return h;
+}
+
+template <int K>
+__device__ __forceinline__ void pt_sensor(const GLPar& gp, const float* vadj, int q, int pbase, float acc[4]) {
+  const Hat<K> hx = hat<K>(gp.t0x, gp.rho, gp.inv_rho, gp.nc, q);
+  if (hx.cnt == 0) return;
+  Hat<K> hy[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) hy[u] = hat<K>(gp.t0y, gp.rho, gp.inv_rho, gp.nc, pbase + 8 * u);
+  const float* va = vadj + gp.v_off + hx.lo;
+  float v[4][K][K];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int a = 0; a < K; ++a)
+#pragma unroll
+      for (int b = 0; b < K; ++b)
+        v[u][a][b] = (a < hy[u].cnt && b < hx.cnt) ? va[(hy[u].lo + a) * gp.nc + b] : 0.f;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    float s = 0.f;
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+      float r = 0.f;
+#pragma unroll
+      for (int b = 0; b < K; ++b) r += hx.w[b] * v[u][a][b];
+      s += hy[u].w[a] * r;
+    }
+    acc[u] += s;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD, const WfsDev* WD, const IoDev* IO,
                                             const Tile* tiles, int mode) {
   const Tile t = tiles[blockIdx.x];
@@ -612,77 +892,102 @@ __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD
   const int n = ly.n;
   const int q = t.tx * kTileN + (threadIdx.x & 31);
   const int pbase = t.ty * kTileN + (threadIdx.x >> 5);
-  if (q >= n) return;  // layers narrower than a tile (no barriers below)
+  if (q >= n) return;  // no barriers in this kernel
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   for (int g = 0; g < pr.G; ++g) {
-    const WfsDev& w = WD[pr.wfs0 + g];
-    const int nc = w.nc;
-    const int base = w.tab_off + t.item * w.tab_stride;
-    const int* it = pr.itab + base;
-    const float* ft = pr.ftab + base;
-    const int* ay0 = it + 4 * nc;  // int slots [2nc, 4nc) are the float weights' positions
-    const int* ayc = ay0 + n;
-    const int* ax0 = ayc + n;
-    const int* axc = ax0 + n;
-    const int* q0y = it;
-    const int* q0x = it + nc;
-    const float* wyv = ft + 2 * nc;
-    const float* wxv = ft + 3 * nc;
-    const float* va = pr.vadj + w.v_off;
-    const int jx0 = ax0[q], jxc = axc[q];
-    if (jxc == 0) continue;
+    const GLPar gp = pr.gl[g * pr.L + t.item];
+    if (gp.kmax == 2) {
+      pt_sensor<2>(gp, pr.vadj, q, pbase, acc);
+    } else if (gp.kmax == 3) {
+      pt_sensor<3>(gp, pr.vadj, q, pbase, acc);
+    } else {  // sensor sampling the layer finer than 2/3 of its spacing
+      const double cx = ((double)q - gp.t0x) * gp.inv_rho;
+      const int jlo = max((int)floor(cx - gp.inv_rho) + 1, 0), jhi = min((int)ceil(cx + gp.inv_rho) - 1, gp.nc - 1);
+      if (jhi < jlo) continue;
+      const float* va = pr.vadj + gp.v_off;
+      const float r = (float)gp.rho;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int p = pbase + 8 * u;
-      if (p >= n) continue;
-      const int iy0 = ay0[p], iyc = ayc[p];
-      float s = 0.f;
-      for (int a = 0; a < iyc; ++a) {
-        const int i = iy0 + a;
-        const float wy = (q0y[i] == p) ? 1.f - wyv[i] : wyv[i];
-        float r = 0.f;
-        for (int b = 0; b < jxc; ++b) {
-          const int j = jx0 + b;
-          const float wx = (q0x[j] == q) ? 1.f - wxv[j] : wxv[j];
-          r += wx * va[i * nc + j];
+      for (int u = 0; u < 4; ++u) {
+        const int p = pbase + 8 * u;
+        const double cy = ((double)p - gp.t0y) * gp.inv_rho;
+        const int ilo = max((int)floor(cy - gp.inv_rho) + 1, 0), ihi = min((int)ceil(cy + gp.inv_rho) - 1, gp.nc - 1);
+        float s = 0.f;
+        for (int i = ilo; i <= ihi; ++i) {
+          const float wy = fmaxf(0.f, 1.f - r * fabsf((float)((double)i - cy)));
+          float rr = 0.f;
+          for (int j = jlo; j <= jhi; ++j)
+            rr += fmaxf(0.f, 1.f - r * fabsf((float)((double)j - cx))) * va[i * gp.nc + j];
+          s += wy * rr;
         }
-        s += wy * r;
+        acc[u] += s;
       }
-      acc[u] += s;
     }
   }
   float* dst = (mode == PT_USER) ? io.out : pr.phiadj;
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-    if (pbase + 8 * u < n) dst[ly.off + (pbase + 8 * u) * n + q] = acc[u];
+  for (int u = 0; u < 4; ++u) {
+    const int p = pbase + 8 * u;
+    if (p < n) dst[ly.off + p * n + q] = acc[u];
+  }
 }
 
 // ------------------------------------------------------------ PCG update
 // a = rho_k / pi_k; x += a p; r -= a q; partial rho_{k+1} = r^T J^{-1} r.
+// 2048 coefficients per workgroup as float4: 2 per thread, loads first.
 __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* IO, const Tile* tiles, int iter) {
   __shared__ double sh[4];
   __shared__ double salpha;
   const Tile t = tiles[blockIdx.x];
   const ProbDev& pr = P[t.prob];
   const IoDev& io = IO[t.prob];
-  if (threadIdx.x == 0) {
-    const double rho = sum_slots(dot_group(pr, 2 * iter), rho_count(pr, iter));
-    const double pi = sum_slots(dot_group(pr, 2 * iter + 1), pr.n_slots_fdwt);
-    salpha = (pi > 0.0) ? rho / pi : 0.0;
+  if (threadIdx.x < 64) {
+    const double rho = wave_sum_slots(dot_group(pr, 2 * iter), rho_count(pr, iter));
+    const double pi = wave_sum_slots(dot_group(pr, 2 * iter + 1), pr.n_slots_fdwt);
+    if (threadIdx.x == 0) salpha = (pi > 0.0) ? rho / pi : 0.0;
   }
   __syncthreads();
   const float a = (float)salpha;
-  const float* p = (iter & 1) ? pr.pbuf1 : pr.pbuf0;
-  float* x = io.state;
-  float* r = io.state + 2L * pr.n_c;
-  const int e0 = t.ty * kUpdChunk;
-  const int e1 = min(e0 + kUpdChunk, pr.n_c);
+  const float4* p = (const float4*)((iter & 1) ? pr.pbuf1 : pr.pbuf0);
+  const float4* q = (const float4*)pr.q;
+  const float4* jv = (const float4*)pr.jinv;
+  float4* x = (float4*)io.state;
+  float4* r = (float4*)(io.state + 2L * pr.n_c);
+  const int e0 = t.ty * (kUpdChunk / 4);
+  const int e1 = min(e0 + kUpdChunk / 4, pr.n_c / 4);
   double acc = 0.0;
-  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    x[e] = fmaf(a, p[e], x[e]);
-    const float re = fmaf(-a, pr.q[e], r[e]);
-    r[e] = re;
-    acc += (double)re * (double)re * (double)pr.jinv[e];
+  constexpr int V = kUpdChunk / 4 / 256;  // float4 per thread
+  float4 xp[V], pp[V], rr[V], qq[V], jj[V];
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    const int e = e0 + threadIdx.x + u * 256;
+    if (e < e1) {
+      xp[u] = x[e];
+      pp[u] = p[e];
+      rr[u] = r[e];
+      qq[u] = q[e];
+      jj[u] = jv[e];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    const int e = e0 + threadIdx.x + u * 256;
+    if (e < e1) {
+      float4 xn, rn;
+      xn.x = fmaf(a, pp[u].x, xp[u].x);
+      xn.y = fmaf(a, pp[u].y, xp[u].y);
+      xn.z = fmaf(a, pp[u].z, xp[u].z);
+      xn.w = fmaf(a, pp[u].w, xp[u].w);
+      rn.x = fmaf(-a, qq[u].x, rr[u].x);
+      rn.y = fmaf(-a, qq[u].y, rr[u].y);
+      rn.z = fmaf(-a, qq[u].z, rr[u].z);
+      rn.w = fmaf(-a, qq[u].w, rr[u].w);
+      x[e] = xn;
+      r[e] = rn;
+      acc += (double)rn.x * (double)rn.x * (double)jj[u].x;
+      acc += (double)rn.y * (double)rn.y * (double)jj[u].y;
+      acc += (double)rn.z * (double)rn.z * (double)jj[u].z;
+      acc += (double)rn.w * (double)rn.w * (double)jj[u].w;
+    }
   }
   const double s = block_sum(acc, sh, blockDim.x);
   if (threadIdx.x == 0) pr.dots[(long)(2 * (iter + 1)) * pr.n_dots + t.slot] = s;

@@ -216,25 +216,6 @@ fewha_status build_model(HostModel& m, std::string& err) {
         t.q0y[j] = (int)fy;
         t.wy[j] = ty - fy;
       }
-      // adjacency: corners whose cell touches node p (q0 == p or q0 == p - 1)
-      auto adj = [&](const std::vector<int>& q0, std::vector<int>& first, std::vector<int>& count) {
-        first.assign(n, 0);
-        count.assign(n, 0);
-        for (int p = 0; p < n; ++p) {
-          int lo = -1, hi = -2;
-          for (int j = 0; j < nc; ++j)
-            if (q0[j] == p || q0[j] == p - 1) {
-              if (lo < 0) lo = j;
-              hi = j;
-            }
-          if (lo >= 0) {
-            first[p] = lo;
-            count[p] = hi - lo + 1;
-          }
-        }
-      };
-      adj(t.q0y, t.ay0, t.ayc);
-      adj(t.q0x, t.ax0, t.axc);
     }
   }
 
