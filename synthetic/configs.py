@@ -221,3 +221,27 @@ def sizes(cfg):
     n_c = sum(l["n"] ** 2 for l in cfg["layers"])
     corners = [(w["n_subap"] + 1) ** 2 for w in cfg["wfs"]]
     return n_c, corners
+
+
+def batch_mix(n_maory, n_vlt, *key):
+    """Independent reconstructions of uneven sizes for one batch: n_maory
+    MAORY-like and n_vlt VLT-like configurations, each with its own seeded
+    Cn2 profile (Dirichlet(1) weights), Fried parameter r0 ~ U[0.1, 0.2] m and
+    slope noise sigma ~ U[0.05, 0.3] rad, 6 PCG iterations each."""
+    import numpy as np
+    from .inputs import rng
+    g = rng(5, *key)
+    out = []
+    for k in range(n_maory + n_vlt):
+        cfg = maory_like() if k < n_maory else vlt_like()
+        w = g.dirichlet(np.ones(len(cfg["layers"])))
+        for layer, wk in zip(cfg["layers"], w):
+            layer["cn2"] = float(max(wk, 1e-3))
+        cfg["prior"]["r0"] = float(g.uniform(0.1, 0.2))
+        sigma = float(g.uniform(0.05, 0.3))
+        for s in cfg["wfs"]:
+            s["sigma"] = sigma
+        cfg["iters"] = 6
+        cfg["name"] = "%s_%d" % (cfg["name"], k)
+        out.append(cfg)
+    return out

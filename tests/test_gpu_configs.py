@@ -1,0 +1,93 @@
+"""GPU parity on the remaining workload shapes: 2x2 spot-elongation noise
+blocks, the paper's own MAORY geometry (sensors sampling two layers finer
+than their spacing), the VLT-like geometry, 9 layers with 256x256 grids and
+20 iterations, and a batch of independent problems of uneven sizes with
+their own priors and noise levels."""
+
+import numpy as np
+import pytest
+
+from oracle.operators import System
+from oracle.solver import State, frame
+from synthetic import get_config, random_vector
+from synthetic.configs import batch_mix
+
+from test_gpu_parity import LAYER_TOL, OP_TOL, _check_frame, rel, synth_slopes, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+_sys = {}
+
+
+def system(name, cfg):
+    if name not in _sys:
+        _sys[name] = (System(cfg), None)
+    return _sys[name][0]
+
+
+def _ops(gpu_lib, S, cfg, key):
+    ctx = gpu_lib.Context(cfg, device=0)
+    x = random_vector(S.geom.n_coeff, 200, key)
+    assert rel(to_host(ctx.apply_A(to_dev(x))), S.apply_A(x)) <= OP_TOL
+    y = random_vector(S.A.shape[0], 201, key)
+    assert rel(to_host(ctx.apply_AT(to_dev(y))), S.apply_AT(y)) <= OP_TOL
+    got = to_host(ctx.apply_M(to_dev(x)))
+    ref = S.apply_M(x)
+    o = S.geom.layer_off
+    for l in range(S.Lc):
+        assert rel(got[o[l]:o[l + 1]], ref[o[l]:o[l + 1]]) <= OP_TOL, l
+    s = synth_slopes(S, 0)
+    assert rel(to_host(ctx.rhs(to_dev(s))), S.rhs(s)) <= OP_TOL
+    return ctx
+
+
+def test_elongated_block_noise(gpu_lib):
+    cfg = get_config("small")
+    cfg["noise"]["alpha_eta"] = 0.6
+    S = system("small_elong", cfg)
+    ctx = _ops(gpu_lib, S, cfg, 1)
+    _check_frame(gpu_lib, S, ctx, np.zeros(5 * S.geom.n_coeff, np.float32), synth_slopes(S, 0))
+
+
+def test_paper_maory_geometry(gpu_lib):
+    cfg = get_config("paper_maory")
+    S = system("paper_maory", cfg)
+    ctx = _ops(gpu_lib, S, cfg, 2)
+    _check_frame(gpu_lib, S, ctx, np.zeros(5 * S.geom.n_coeff, np.float32), synth_slopes(S, 0))
+
+
+def test_vlt_like_geometry(gpu_lib):
+    cfg = get_config("vlt_like")
+    S = system("vlt_like", cfg)
+    ctx = _ops(gpu_lib, S, cfg, 3)
+    _check_frame(gpu_lib, S, ctx, np.zeros(5 * S.geom.n_coeff, np.float32), synth_slopes(S, 0))
+
+
+def test_large_nine_layers_with_elongation(gpu_lib):
+    cfg = get_config("large")
+    S = system("large", cfg)
+    ctx = _ops(gpu_lib, S, cfg, 4)
+    _check_frame(gpu_lib, S, ctx, np.zeros(5 * S.geom.n_coeff, np.float32), synth_slopes(S, 0))
+
+
+def test_uneven_batch_against_oracle(gpu_lib):
+    import torch
+    cfgs = batch_mix(1, 2, 9)
+    systems = [System(c) for c in cfgs]
+    ctxs = [gpu_lib.Context(c, device=0) for c in cfgs]
+    batch = gpu_lib.Batch(ctxs)
+    slopes = [to_dev(synth_slopes(S, k)) for k, S in enumerate(systems)]
+    states = [torch.zeros(c.n_state, device="cuda") for c in ctxs]
+    lays = [torch.empty(c.n_coeff, device="cuda") for c in ctxs]
+    for rep in range(2):  # two frames: the second is warm-started from the first
+        batch.reconstruct(slopes, states, lays, iters=6, use_graph=True)
+    torch.cuda.synchronize()
+    for k, S in enumerate(systems):
+        st = State(S.geom.n_coeff, S.geom.n_coeff)
+        s = synth_slopes(S, k).astype(np.float64)
+        for rep in range(2):
+            st, phi = frame(S, st, s, iters=6)
+        o = S.geom.layer_off
+        got = to_host(lays[k])
+        for l in range(S.Lc):
+            assert rel(got[o[l]:o[l + 1]], phi[o[l]:o[l + 1]]) <= 2 * LAYER_TOL, (k, l)
