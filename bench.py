@@ -112,6 +112,23 @@ def algorithmic_bytes(cfg, n_slopes_dense, n_corners):
     }
 
 
+def measured_traffic(stage, batch):
+    """Bytes per launch of a stage from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None when it was taken on other kernel code or
+    another batch size."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2202_11945_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    prof = os.path.join(ROOT, "profiles", "stages_maory_like_b64_bytes.md")
+    if not os.path.exists(prof):
+        return None
+    for line in open(prof):
+        f = line.split()
+        if len(f) == 5 and f[0] == "TRAFFIC" and f[1] == stage and int(f[2]) == batch and f[4] == sha:
+            return float(f[3])
+    return None
+
+
 def main():
     args = parse()
     if args.cpu_child:
@@ -139,8 +156,7 @@ def main():
 
     # ---- inputs: slopes of frozen-flow screens through A, plus noise ----
     sig = [w["sigma"] for w in cfg["wfs"]]
-    n_active = [c0.n_slopes]  # total only; noise per sensor needs per-sensor counts
-    mask = c0.get_table(fw._abi.FEWHA_TABLE_MASK)
+    mask = c0.get_table(fw._abi.FEWHA_TABLE_MASK)  # per-sensor slope counts for the noise
     per = []
     o = 0
     for w in cfg["wfs"]:
@@ -148,7 +164,6 @@ def main():
         per.append(2 * int(mask[o:o + nn].sum()))
         o += nn
     assert sum(per) == c0.n_slopes
-    del n_active
     pool = []
     t_in = time.time()
     for k in range(B):
@@ -246,13 +261,7 @@ def main():
     alg = algorithmic_bytes(cfg, n_sd, n_cor)
     dom_bytes = alg[dom] * B
     achieved = dom_bytes / (stage_us[dom][0] * 1e-6) / 1e9
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tfile):
-        tr = json.load(open(tfile))
-        ent = tr.get(dom)
-        if ent and ent.get("batch") == B:
-            traffic = ent.get("bytes_per_launch")
+    traffic = measured_traffic(dom, B)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
 

@@ -1,0 +1,52 @@
+"""Stage profiler: one batched step of a workload, then every PCG-iteration
+stage launched alone over the whole batch, then a plain 256 MiB device copy
+whose byte counters calibrate the hardware FETCH_SIZE / WRITE_SIZE reading.
+
+Run under rocprofv3, e.g.
+  rocprofv3 --pmc FETCH_SIZE -d OUT -o fetch --output-format csv -- \
+      python3 -m paper_2202_11945_amd.profile_stages --batch 64
+"""
+
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--config", default="maory_like")
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--iters", type=int, default=4)
+    ap.add_argument("--reps", type=int, default=5)
+    a = ap.parse_args()
+    import torch
+
+    import paper_2202_11945_amd as fw
+    from synthetic import get_config, random_vector
+
+    cfg = get_config(a.config)
+    ctxs = [fw.Context(cfg, device=0) for _ in range(a.batch)]
+    batch = fw.Batch(ctxs)
+    dev = torch.device("cuda:0")
+    slopes = [torch.from_numpy(random_vector(ctxs[0].n_slopes, 5, k)).to(dev) for k in range(a.batch)]
+    states = [torch.zeros(c.n_state, device=dev) for c in ctxs]
+    for _ in range(2):
+        batch.reconstruct(slopes, states, iters=a.iters, use_graph=False)
+    torch.cuda.synchronize()
+    for sid, name in enumerate(fw._abi.STAGES):
+        us, wg = batch.time_stage(sid, reps=a.reps)
+        print("stage %-10s %9.2f us  workgroups %d" % (name, us, wg), flush=True)
+    x = torch.empty(64 * 2 ** 20, dtype=torch.float32, device=dev).fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print("copy 256 MiB x3 done", flush=True)
+
+
+if __name__ == "__main__":
+    main()
