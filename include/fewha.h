@@ -81,7 +81,7 @@ typedef struct {
   double cn2;          /* fractional turbulence weight gamma_l (> 0)               */
 } fewha_layer_desc;
 
-/* One deformable mirror for the fitting step (Sec. 4.1, Table 3). */
+/* One deformable mirror for the fitting step (Sec. 4.1, Table 3); see fewha_set_fitting. */
 typedef struct {
   double h;            /* conjugation altitude (m)                                 */
   int n_act;           /* n_act x n_act actuators, bilinear influence              */
@@ -123,6 +123,22 @@ FEWHA_API fewha_status fewha_set_noise(fewha_ctx* ctx, double alpha_eta, double 
 /* Open-loop gain of Algorithm 1 (gain control lines): a <- (1-gain) a + gain a~. */
 FEWHA_API fewha_status fewha_set_control(fewha_ctx* ctx, double gain);
 
+/* DM fitting (Sec. 4.1: with the layers away from the DM altitudes, fitting
+ * the mirrors is an additional minimisation problem).  The commands a (the
+ * concatenated n_act x n_act grids of the n_dm DMs, bilinear influence,
+ * centred actuator grids) minimise
+ *     sum_k |M (B_k a - P_k phi)|^2 + eps |a|^2,
+ * phi = W^{-1} c the reconstructed layers, over n_dirs directions
+ * dirs_xy[2k], dirs_xy[2k+1] (rad); P_k, B_k propagate layers and DMs to the
+ * corners of an n_fit x n_fit subaperture grid on the pupil (no cone effect),
+ * M keeps the corners of its active subapertures (the pupil's annulus rule);
+ * eps = eps_rel * mean(diag(sum_k B_k^T M B_k)).  Solved by fit_iters CG
+ * iterations from a = 0 after every reconstruction; the control update of
+ * Algorithm 1 then uses the fitted commands.  Without this call F = I (DM
+ * commands = layers).  FEWHA_EGEOM at finalize if a direction leaves a DM. */
+FEWHA_API fewha_status fewha_set_fitting(fewha_ctx* ctx, int n_dm, const fewha_dm_desc* dms, int n_dirs,
+                                         const double* dirs_xy, int n_fit, int fit_iters, double eps_rel);
+
 /* Validate the geometry and build every table: sensor masks, bilinear
  * propagation tables, the prior D and the exact Jacobi diagonal J
  * (eq. precond).  On a device context, upload the tables and allocate the
@@ -134,7 +150,7 @@ FEWHA_API fewha_status fewha_finalize(fewha_ctx* ctx);
  *   n_coeff     = N_c = sum_l n_l^2 (wavelet coefficients = layer nodes)
  *   n_slopes    = sum_g 2 |M_g|
  *   n_layer_pts = N_c
- *   n_act       = number of DM commands (= N_c when F = I)
+ *   n_act       = number of DM commands (= N_c when F = I, else sum of n_act^2)
  *   n_state     = 3 N_c + 2 n_act (layout of the reconstruct state below). */
 FEWHA_API fewha_status fewha_sizes(const fewha_ctx* ctx, long* n_coeff, long* n_slopes,
                                    long* n_layer_pts, long* n_act, long* n_state);
@@ -168,7 +184,8 @@ FEWHA_API fewha_status fewha_rhs(fewha_ctx* ctx, const float* slopes, float* b);
  *   phi = W^{-1} c; a_prev <- a; a <- (1-gain) a + gain phi.
  * state (in/out, n_state floats, 16-byte aligned) = [c | b | r | a_prev | a]; an all-zero
  * state starts a sequence (c = 0, r0 = b').  layers_out (N_c) and dm_out
- * (n_act) may be NULL.  iters in [0, 256].  PCG inner products and the
+ * (n_act) may be NULL.  iters in [0, 256].  With fewha_set_fitting the DM
+ * commands are the fitted ones instead of phi.  PCG inner products and the
  * alpha/beta recurrences are computed in double precision. */
 FEWHA_API fewha_status fewha_reconstruct(fewha_ctx* ctx, const float* slopes, float* state,
                                          float* layers_out, float* dm_out, int iters);

@@ -60,6 +60,8 @@ _SIGS = {
     "fewha_set_prior": (c_int, [_P, c_double, c_double, c_double, c_double]),
     "fewha_set_noise": (c_int, [_P, c_double, c_double, c_double]),
     "fewha_set_control": (c_int, [_P, c_double]),
+    "fewha_set_fitting": (c_int, [_P, c_int, POINTER(fewha_dm_desc), c_int, POINTER(c_double), c_int, c_int,
+                                  c_double]),
     "fewha_finalize": (c_int, [_P]),
     "fewha_sizes": (c_int, [_P, POINTER(c_long), POINTER(c_long), POINTER(c_long), POINTER(c_long),
                             POINTER(c_long)]),

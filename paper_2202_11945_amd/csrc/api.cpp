@@ -54,6 +54,10 @@ struct Plan {
   std::vector<Tile> hT;
   Range idwt_res, fdwt_res, pg, gt, pt, upd;
   std::vector<Range> idwt_glob, fdwt_glob;
+  Range fit_fwdL, fit_fwdD, fit_pt, fit_cg;  // DM fitting (empty when no problem fits)
+  int nprob_all = 0;                         // problems plus two fitting views per fitted problem
+  FitDev* dF = nullptr;
+  int max_fit_iters = 0;
   Filter F{};
   IoDev* pinned[kRing] = {nullptr};
   hipEvent_t ev[kRing] = {nullptr};
@@ -147,7 +151,8 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     pd.wfs0 = (int)P.hW.size();
     pd.n_c = (int)m.n_c;
     pd.n_slopes = (int)m.n_slopes;
-    pd.n_act = (int)m.n_c;
+    pd.n_act = (int)m.n_act();
+    pd.fitted = m.fit.on ? 1 : 0;
     pd.gain = (float)m.gain;
     int tmp_total = 0;
     for (int l = 0; l < L; ++l) {
@@ -300,6 +305,125 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     pl_.gl = cv.take(sizeof(GLPar) * (size_t)G * L);
     P.hP.push_back(pd);
   }
+  // ---- DM fitting views: (directions x layers) and (directions x DMs) ----
+  struct FitLayout {
+    int k, pL, pD;
+    size_t u, x, r, p, adj, scal, itab, ftab, cmap, gl;
+    std::vector<int> it;
+    std::vector<float> ft;
+    std::vector<GLPar> glp;
+  };
+  std::vector<FitLayout> fits;
+  std::vector<Tile> t_ffL, t_ffD, t_fpt, t_fcg;
+  std::vector<FitDev> hF;
+  for (int k = 0; k < P.nprob; ++k) {
+    const HostModel& m = *models[k];
+    if (!m.fit.on) continue;
+    const FitHost& f = m.fit;
+    FitLayout fl;
+    fl.k = k;
+    const int K = (int)f.dirs.size() / 2, nc = f.N + 1, nd = (int)f.dms.size(), L = (int)m.layers.size();
+    P.max_fit_iters = std::max(P.max_fit_iters, f.iters);
+    // DM grids as layers of the second view
+    const int dm_layer0 = (int)P.hL.size();
+    for (int q = 0; q < nd; ++q) {
+      LayerDev ld{};
+      ld.n = f.dms[q].n_act;
+      ld.res = ld.n;
+      ld.off = f.dm_off[q];
+      P.hL.push_back(ld);
+    }
+    // direction "sensors" of the two views; tables [view][dir][grid] with stride 4 nc
+    int tab = 0;
+    auto add_dirs = [&](int ngrid, const std::vector<std::vector<GLTables>>& tb) {
+      const int w0 = (int)P.hW.size();
+      for (int d = 0; d < K; ++d) {
+        WfsDev wd{};
+        wd.N = f.N;
+        wd.nc = nc;
+        wd.v_off = d * nc * nc;
+        wd.m_off = 0;
+        wd.tab_stride = 4 * nc;
+        wd.tab_off = tab;
+        for (int g2 = 0; g2 < ngrid; ++g2) {
+          const GLTables& t = tb[d][g2];
+          const int base = tab + g2 * 4 * nc;
+          fl.it.resize(base + 4 * nc, 0);
+          fl.ft.resize(base + 4 * nc, 0.f);
+          for (int j = 0; j < nc; ++j) {
+            fl.it[base + j] = t.q0y[j];
+            fl.it[base + nc + j] = t.q0x[j];
+            fl.ft[base + 2 * nc + j] = (float)t.wy[j];
+            fl.ft[base + 3 * nc + j] = (float)t.wx[j];
+          }
+        }
+        tab += ngrid * 4 * nc;
+        P.hW.push_back(wd);
+      }
+      return w0;
+    };
+    const int wL = add_dirs(L, f.tabL);
+    const int wD = add_dirs(nd, f.tabD);
+    // adjoint-gather parameters of (direction, DM)
+    for (int d = 0; d < K; ++d)
+      for (int q = 0; q < nd; ++q) {
+        const fewha_dm_desc& dm = f.dms[q];
+        GLPar gp{};
+        gp.t0x = (-0.5 * m.D + dm.h * f.dirs[2 * d]) / dm.pitch + 0.5 * (dm.n_act - 1);
+        gp.t0y = (-0.5 * m.D + dm.h * f.dirs[2 * d + 1]) / dm.pitch + 0.5 * (dm.n_act - 1);
+        gp.rho = (m.D / f.N) / dm.pitch;
+        gp.inv_rho = 1.0 / gp.rho;
+        gp.nc = nc;
+        gp.v_off = d * nc * nc;
+        gp.kmax = gp.rho >= 1.0 ? 2 : (gp.rho >= 2.0 / 3.0 ? 3 : 0);
+        fl.glp.push_back(gp);
+      }
+    ProbDev vL{}, vD{};
+    vL.L = L;
+    vL.G = K;
+    vL.layer0 = P.hP[k].layer0;
+    vL.wfs0 = wL;
+    vD.L = nd;
+    vD.G = K;
+    vD.layer0 = dm_layer0;
+    vD.wfs0 = wD;
+    fl.pL = (int)P.hP.size();
+    P.hP.push_back(vL);
+    fl.pD = (int)P.hP.size();
+    P.hP.push_back(vD);
+    fl.u = cv.take(sizeof(float) * (size_t)K * nc * nc);
+    fl.x = cv.take(sizeof(float) * f.n_act);
+    fl.r = cv.take(sizeof(float) * f.n_act);
+    fl.p = cv.take(sizeof(float) * f.n_act);
+    fl.adj = cv.take(sizeof(float) * f.n_act);
+    fl.scal = cv.take(sizeof(double) * 4);
+    fl.itab = cv.take(sizeof(int) * fl.it.size());
+    fl.ftab = cv.take(sizeof(float) * fl.ft.size());
+    fl.cmap = cv.take(sizeof(int) * f.cmap.size());
+    fl.gl = cv.take(sizeof(GLPar) * fl.glp.size());
+    const int tc = cdiv(nc, kTileS);
+    for (int d = 0; d < K; ++d)
+      for (int ty = 0; ty < tc; ++ty)
+        for (int tx = 0; tx < tc; ++tx) {
+          t_ffL.push_back({fl.pL, d, ty, tx, 0, 0, 0, 0});
+          t_ffD.push_back({fl.pD, d, ty, tx, 0, 0, 0, 0});
+        }
+    for (int q = 0; q < nd; ++q) {
+      const int tn = cdiv(f.dms[q].n_act, kTileN);
+      for (int ty = 0; ty < tn; ++ty)
+        for (int tx = 0; tx < tn; ++tx) t_fpt.push_back({fl.pD, q, ty, tx, 0, 0, 0, 0});
+    }
+    t_fcg.push_back({(int)hF.size(), 0, 0, 0, 0, 0, 0, 0});
+    FitDev fd{};
+    fd.main = k;
+    fd.n_act = (int)f.n_act;
+    fd.eps = (float)f.eps;
+    fd.gain = (float)m.gain;
+    hF.push_back(fd);
+    fits.push_back(std::move(fl));
+  }
+  P.nprob_all = (int)P.hP.size();
+
   // concatenated tile list
   auto add = [&](std::vector<Tile>& v) {
     Range r;
@@ -316,11 +440,16 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   P.upd = add(t_upd);
   for (auto& v : t_idwt_glob) P.idwt_glob.push_back(add(v));
   for (auto& v : t_fdwt_glob) P.fdwt_glob.push_back(add(v));
-  const size_t oP = cv.take(sizeof(ProbDev) * P.nprob);
+  P.fit_fwdL = add(t_ffL);
+  P.fit_fwdD = add(t_ffD);
+  P.fit_pt = add(t_fpt);
+  P.fit_cg = add(t_fcg);
+  const size_t oP = cv.take(sizeof(ProbDev) * P.nprob_all);
   const size_t oL = cv.take(sizeof(LayerDev) * P.hL.size());
   const size_t oW = cv.take(sizeof(WfsDev) * P.hW.size());
-  const size_t oIO = cv.take(sizeof(IoDev) * P.nprob);
-  const size_t oIOp = cv.take(sizeof(IoDev) * P.nprob);
+  const size_t oIO = cv.take(sizeof(IoDev) * P.nprob_all);
+  const size_t oIOp = cv.take(sizeof(IoDev) * P.nprob_all);
+  const size_t oF = cv.take(sizeof(FitDev) * std::max<size_t>(hF.size(), 1));
   const size_t oT = cv.take(sizeof(Tile) * std::max<size_t>(P.hT.size(), 1));
   P.arena_bytes = cv.off;
   {
@@ -362,18 +491,47 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     HIP_TRY(hipMemcpy(base + l.cmap, cmap[k].data(), sizeof(int) * cmap[k].size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(base + l.cinv, cinv[k].data(), sizeof(float) * cinv[k].size(), hipMemcpyHostToDevice));
   }
+  for (size_t i = 0; i < fits.size(); ++i) {
+    const FitLayout& fl = fits[i];
+    const ProbDev& main = P.hP[fl.k];
+    ProbDev& vL = P.hP[fl.pL];
+    ProbDev& vD = P.hP[fl.pD];
+    float* u = (float*)(base + fl.u);
+    vL.phi = main.phi;  // layers of the reconstruction
+    vL.vadj = u;
+    vL.itab = vD.itab = (const int*)(base + fl.itab);
+    vL.ftab = vD.ftab = (const float*)(base + fl.ftab);
+    vL.cmap = vD.cmap = (const int*)(base + fl.cmap);
+    vD.phi = (float*)(base + fl.p);
+    vD.phiadj = (float*)(base + fl.adj);
+    vD.vadj = u;
+    vD.gl = (const GLPar*)(base + fl.gl);
+    FitDev& fd = hF[i];
+    fd.x = (float*)(base + fl.x);
+    fd.r = (float*)(base + fl.r);
+    fd.p = vD.phi;
+    fd.adj = vD.phiadj;
+    fd.scal = (double*)(base + fl.scal);
+    const FitHost& f = models[fl.k]->fit;
+    HIP_TRY(hipMemcpy(base + fl.itab, fl.it.data(), sizeof(int) * fl.it.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(base + fl.ftab, fl.ft.data(), sizeof(float) * fl.ft.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(base + fl.cmap, f.cmap.data(), sizeof(int) * f.cmap.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(base + fl.gl, fl.glp.data(), sizeof(GLPar) * fl.glp.size(), hipMemcpyHostToDevice));
+  }
+  P.dF = (FitDev*)(base + oF);
+  if (!hF.empty()) HIP_TRY(hipMemcpy(P.dF, hF.data(), sizeof(FitDev) * hF.size(), hipMemcpyHostToDevice));
   P.dP = (ProbDev*)(base + oP);
   P.dL = (LayerDev*)(base + oL);
   P.dW = (WfsDev*)(base + oW);
   P.dIO = (IoDev*)(base + oIO);
   P.dIOprof = (IoDev*)(base + oIOp);
   P.dT = (Tile*)(base + oT);
-  HIP_TRY(hipMemcpy(P.dP, P.hP.data(), sizeof(ProbDev) * P.nprob, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(P.dP, P.hP.data(), sizeof(ProbDev) * P.nprob_all, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(P.dL, P.hL.data(), sizeof(LayerDev) * P.hL.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(P.dW, P.hW.data(), sizeof(WfsDev) * P.hW.size(), hipMemcpyHostToDevice));
   if (!P.hT.empty()) HIP_TRY(hipMemcpy(P.dT, P.hT.data(), sizeof(Tile) * P.hT.size(), hipMemcpyHostToDevice));
   for (int i = 0; i < kRing; ++i) {
-    HIP_TRY(hipHostMalloc((void**)&P.pinned[i], sizeof(IoDev) * P.nprob, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&P.pinned[i], sizeof(IoDev) * P.nprob_all, hipHostMallocDefault));
     HIP_TRY(hipEventCreateWithFlags(&P.ev[i], hipEventDisableTiming));
   }
   HIP_TRY(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking));
@@ -390,8 +548,9 @@ fewha_status upload_io(Plan& P, const std::vector<IoDev>& io, hipStream_t s, IoD
   const int slot = P.ring;
   P.ring = (P.ring + 1) % kRing;
   if (P.ev_used[slot]) HIP_TRY(hipEventSynchronize(P.ev[slot]));
+  std::memset(P.pinned[slot], 0, sizeof(IoDev) * P.nprob_all);
   std::memcpy(P.pinned[slot], io.data(), sizeof(IoDev) * P.nprob);
-  HIP_TRY(hipMemcpyAsync(dst, P.pinned[slot], sizeof(IoDev) * P.nprob, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dst, P.pinned[slot], sizeof(IoDev) * P.nprob_all, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(P.ev[slot], s));
   P.ev_used[slot] = true;
   return FEWHA_OK;
@@ -441,6 +600,17 @@ void enq_reconstruct(const Plan& P, const LaunchArgs& a, int iters) {
     launch_update(a, T(P, P.upd), P.upd.n, k);
   }
   enq_idwt(P, a, SRC_STATE_C, OUT_FIT, 0);
+  if (P.fit_cg.n > 0) {  // DM fitting: CG on (sum_k B_k^T M B_k + eps I) a = sum_k B_k^T M P_k phi
+    launch_fit_fwd(a, T(P, P.fit_fwdL), P.fit_fwdL.n);
+    launch_pT(a, T(P, P.fit_pt), P.fit_pt.n, PT_PHIADJ);
+    launch_fit_cg(a, P.dF, P.fit_cg.n, FIT_INIT);
+    for (int k = 0; k < P.max_fit_iters; ++k) {
+      launch_fit_fwd(a, T(P, P.fit_fwdD), P.fit_fwdD.n);
+      launch_pT(a, T(P, P.fit_pt), P.fit_pt.n, PT_PHIADJ);
+      launch_fit_cg(a, P.dF, P.fit_cg.n, FIT_ITER);
+    }
+    launch_fit_cg(a, P.dF, P.fit_cg.n, FIT_FINAL);
+  }
 }
 
 }  // namespace
@@ -570,6 +740,26 @@ fewha_status fewha_set_control(fewha_ctx* c, double gain) {
   return FEWHA_OK;
 }
 
+fewha_status fewha_set_fitting(fewha_ctx* c, int n_dm, const fewha_dm_desc* dms, int n_dirs, const double* dirs_xy,
+                               int n_fit, int fit_iters, double eps_rel) {
+  CHECK_CTX(c);
+  if (c->finalized) return fail(c, FEWHA_ESTATE, "set_fitting after finalize");
+  if (n_dm < 1 || n_dm > 16 || !dms || n_dirs < 1 || n_dirs > 256 || !dirs_xy || n_fit < 1 || n_fit > 4096 ||
+      fit_iters < 0 || fit_iters > 256 || !(eps_rel >= 0.0))
+    return fail(c, FEWHA_EINVAL, "set_fitting: invalid argument");
+  for (int q = 0; q < n_dm; ++q)
+    if (dms[q].n_act < 2 || dms[q].n_act > 4096 || !(dms[q].pitch > 0.0))
+      return fail(c, FEWHA_EINVAL, "set_fitting: DM " + std::to_string(q) + " has an invalid descriptor");
+  FitHost& f = c->m.fit;
+  f.on = true;
+  f.dms.assign(dms, dms + n_dm);
+  f.dirs.assign(dirs_xy, dirs_xy + 2 * n_dirs);
+  f.N = n_fit;
+  f.iters = fit_iters;
+  f.eps_rel = eps_rel;
+  return FEWHA_OK;
+}
+
 fewha_status fewha_finalize(fewha_ctx* c) {
   CHECK_CTX(c);
   if (c->finalized) return fail(c, FEWHA_ESTATE, "finalize called twice");
@@ -591,8 +781,8 @@ fewha_status fewha_sizes(const fewha_ctx* c, long* n_coeff, long* n_slopes, long
   if (n_coeff) *n_coeff = c->m.n_c;
   if (n_slopes) *n_slopes = c->m.n_slopes;
   if (n_layer_pts) *n_layer_pts = c->m.n_c;
-  if (n_act) *n_act = c->m.n_c;
-  if (n_state) *n_state = 5L * c->m.n_c;
+  if (n_act) *n_act = c->m.n_act();
+  if (n_state) *n_state = 3L * c->m.n_c + 2L * c->m.n_act();
   return FEWHA_OK;
 }
 

@@ -82,7 +82,8 @@ struct ProbDev {
   int n_dots;              // dot-product slots per group
   int n_slots_fdwt;        // producers of rho_0 and pi_k
   int n_slots_upd;         // producers of rho_{k+1}
-  int pad0, pad1;
+  int fitted;              // 1 = the DM commands come from the fitting step
+  int pad1;
   float gain;
   float pad2;
   // internal buffers
@@ -143,6 +144,34 @@ struct GLTables {  // one (sensor, layer) pair
   std::vector<double> wy, wx;  // nc
 };
 
+// DM fitting (Sec. 4.1, layers not at the DM altitudes): directions, DMs,
+// the fitting pupil (corners of the active subapertures of an N x N grid).
+struct FitHost {
+  bool on = false;
+  std::vector<fewha_dm_desc> dms;
+  std::vector<double> dirs;   // x, y pairs (rad)
+  int N = 0, iters = 10;
+  double eps_rel = 1e-6;
+  // derived
+  std::vector<int> cmap;                    // (N+1)^2: >= 0 inside the fitting pupil
+  std::vector<std::vector<GLTables>> tabL;  // [dir][layer] layers -> pupil corners
+  std::vector<std::vector<GLTables>> tabD;  // [dir][dm]    DMs -> pupil corners
+  std::vector<int> dm_off;                  // offsets of the DM grids in the command vector
+  long n_act = 0;
+  double eps = 0;                           // eps_rel * mean(diag(sum_k B_k^T M B_k))
+};
+
+// Fitting work of one fitted problem (one workgroup runs its CG vector work).
+struct FitDev {
+  int main, n_act, pad0, pad1;
+  float eps, gain;
+  float* x;        // fitted commands
+  float* r;
+  float* p;        // search direction (the source of the DM propagation)
+  const float* adj;  // sum_k B_k^T M (B_k p or P_k phi)
+  double* scal;    // rho
+};
+
 struct HostModel {
   double D = 0, obs = 0;
   std::vector<WfsHost> wfs;
@@ -160,6 +189,8 @@ struct HostModel {
   std::vector<int> layer_off;
   std::vector<int> slope_off;
   long n_c = 0, n_slopes = 0;
+  FitHost fit;
+  long n_act() const { return fit.on ? fit.n_act : n_c; }
 };
 
 // host set-up (setup.cpp); each returns FEWHA_OK or an error with a message

@@ -17,6 +17,8 @@ enum { PG_COMPACT = 0, PG_DENSE = 1 };
 enum { GT_PLAIN = 0, GT_WEIGHTED = 1 };
 // propagation adjoint destination
 enum { PT_PHIADJ = 0, PT_USER = 1 };
+// DM fitting CG phases
+enum { FIT_INIT = 0, FIT_ITER = 1, FIT_FINAL = 2 };
 
 struct LaunchArgs {
   const ProbDev* P;
@@ -37,5 +39,7 @@ void launch_slopes_in(const LaunchArgs& a, const Tile* tiles, int ntiles);
 void launch_gammaT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode);
 void launch_pT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode);
 void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter);
+void launch_fit_fwd(const LaunchArgs& a, const Tile* tiles, int ntiles);
+void launch_fit_cg(const LaunchArgs& a, const FitDev* F, int nfit, int phase);
 
 }  // namespace fewha

@@ -130,7 +130,7 @@ struct OutLoad {
 };
 __device__ __forceinline__ OutLoad out_fetch(const ProbDev& pr, const IoDev& io, int out_mode, int e) {
   OutLoad o{0.f};
-  if (out_mode == OUT_FIT) o.a = io.state[3L * pr.n_c + pr.n_act + e];
+  if (out_mode == OUT_FIT && !pr.fitted) o.a = io.state[3L * pr.n_c + pr.n_act + e];
   return o;
 }
 __device__ __forceinline__ void out_finish(const ProbDev& pr, const IoDev& io, int out_mode, int e, float v,
@@ -139,7 +139,10 @@ __device__ __forceinline__ void out_finish(const ProbDev& pr, const IoDev& io, i
     pr.phi[e] = v;
   } else if (out_mode == OUT_USER) {
     io.out[e] = v;
-  } else {  // OUT_FIT
+  } else if (pr.fitted) {  // OUT_FIT, DM commands from the fitting step that follows
+    pr.phi[e] = v;
+    if (io.layers_out) io.layers_out[e] = v;
+  } else {  // OUT_FIT, F = I
     if (io.layers_out) io.layers_out[e] = v;
     float* aprev = io.state + 3L * pr.n_c;
     float* a = aprev + pr.n_act;
@@ -993,6 +996,100 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
   if (threadIdx.x == 0) pr.dots[(long)(2 * (iter + 1)) * pr.n_dots + t.slot] = s;
 }
 
+// ------------------------------------------------------------ DM fitting
+// Wavefront of a set of grids (layers of the reconstruction, or DMs) at the
+// fitting-pupil corners in one direction, bilinear, masked to the pupil:
+//   u_k = M sum_grid grid(x + h theta_k).   Tile = 16x16 corners.
+__global__ __launch_bounds__(256) void k_fit_fwd(const ProbDev* P, const LayerDev* LD, const WfsDev* WD,
+                                                 const Tile* tiles) {
+  const Tile t = tiles[blockIdx.x];
+  const ProbDev& pr = P[t.prob];
+  const WfsDev& w = WD[pr.wfs0 + t.item];
+  const int nc = w.nc;
+  const int i = t.ty * kTileS + (threadIdx.x >> 4), j = t.tx * kTileS + (threadIdx.x & 15);
+  if (i >= nc || j >= nc) return;
+  float v = 0.f;
+  if (pr.cmap[w.m_off + i * nc + j] >= 0) {
+    for (int l = 0; l < pr.L; ++l) {
+      const LayerDev& ly = LD[pr.layer0 + l];
+      const int base = w.tab_off + l * w.tab_stride;
+      const int qy = pr.itab[base + i], qx = pr.itab[base + nc + j];
+      const float wy = pr.ftab[base + 2 * nc + i], wx = pr.ftab[base + 3 * nc + j];
+      const float* ph = pr.phi + ly.off + qy * ly.n + qx;
+      const float top = (1.f - wx) * ph[0] + wx * ph[1];
+      const float bot = (1.f - wx) * ph[ly.n] + wx * ph[ly.n + 1];
+      v += (1.f - wy) * top + wy * bot;
+    }
+  }
+  pr.vadj[w.v_off + i * nc + j] = v;
+}
+
+// CG on the fitting normal equations, one workgroup per fitted problem; the
+// operator's data part sum_k B_k^T M B_k p arrives in adj (FIT_ITER), the
+// right-hand side sum_k B_k^T M P_k phi in adj (FIT_INIT).  FP64 inner
+// products, fixed-order block sums.  FIT_FINAL applies the open-loop control
+// of Algorithm 1 with the fitted commands.
+__global__ __launch_bounds__(1024) void k_fit_cg(const FitDev* F, const ProbDev* P, const IoDev* IO, int phase) {
+  __shared__ double sh[16];
+  __shared__ double s_val;
+  const FitDev& f = F[blockIdx.x];
+  const int n = f.n_act, nt = blockDim.x;
+  if (phase == FIT_INIT) {
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < n; e += nt) {
+      const float b = f.adj[e];
+      f.x[e] = 0.f;
+      f.r[e] = b;
+      f.p[e] = b;
+      acc += (double)b * (double)b;
+    }
+    const double rho = block_sum(acc, sh, nt);
+    if (threadIdx.x == 0) f.scal[0] = rho;
+    return;
+  }
+  if (phase == FIT_ITER) {
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < n; e += nt) {
+      const float q = f.adj[e] + f.eps * f.p[e];
+      acc += (double)f.p[e] * (double)q;
+    }
+    const double pi = block_sum(acc, sh, nt);
+    if (threadIdx.x == 0) s_val = pi;
+    __syncthreads();
+    const double rho = f.scal[0];
+    const float al = (float)((s_val > 0.0) ? rho / s_val : 0.0);
+    acc = 0.0;
+    for (int e = threadIdx.x; e < n; e += nt) {
+      const float pe = f.p[e];
+      const float q = f.adj[e] + f.eps * pe;
+      f.x[e] = fmaf(al, pe, f.x[e]);
+      const float re = fmaf(-al, q, f.r[e]);
+      f.r[e] = re;
+      acc += (double)re * (double)re;
+    }
+    const double rho2 = block_sum(acc, sh, nt);
+    if (threadIdx.x == 0) s_val = rho2;
+    __syncthreads();
+    const float be = (float)((rho > 0.0) ? s_val / rho : 0.0);
+    for (int e = threadIdx.x; e < n; e += nt) f.p[e] = fmaf(be, f.p[e], f.r[e]);
+    __syncthreads();
+    if (threadIdx.x == 0) f.scal[0] = s_val;
+    return;
+  }
+  // FIT_FINAL
+  const ProbDev& pr = P[f.main];
+  const IoDev& io = IO[f.main];
+  float* aprev = io.state + 3L * pr.n_c;
+  float* a = aprev + pr.n_act;
+  for (int e = threadIdx.x; e < n; e += nt) {
+    const float old = a[e];
+    const float nw = (1.0f - f.gain) * old + f.gain * f.x[e];
+    aprev[e] = old;
+    a[e] = nw;
+    if (io.dm_out) io.dm_out[e] = nw;
+  }
+}
+
 // ------------------------------------------------------------ launchers
 
 void launch_idwt_res(const LaunchArgs& a, const Tile* tiles, int ntiles, int src_mode, int out_mode, int iter) {
@@ -1024,6 +1121,12 @@ void launch_pT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
 }
 void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter) {
   if (ntiles > 0) k_update<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles, iter);
+}
+void launch_fit_fwd(const LaunchArgs& a, const Tile* tiles, int ntiles) {
+  if (ntiles > 0) k_fit_fwd<<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, tiles);
+}
+void launch_fit_cg(const LaunchArgs& a, const FitDev* F, int nfit, int phase) {
+  if (nfit > 0) k_fit_cg<<<nfit, 1024, 0, a.stream>>>(F, a.P, a.IO, phase);
 }
 
 }  // namespace fewha

@@ -219,6 +219,93 @@ fewha_status build_model(HostModel& m, std::string& err) {
     }
   }
 
+  // ---- DM fitting: pupil corners, propagation tables, regularisation ----
+  if (m.fit.on) {
+    FitHost& f = m.fit;
+    const int N = f.N, nc = N + 1;
+    const double d = D / N;
+    const double r_in = std::sqrt(m.obs) * 0.5 * D;
+    std::vector<uint8_t> sub(N * N, 0);
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) {
+        const double X = -0.5 * D + (j + 0.5) * d, Y = -0.5 * D + (i + 0.5) * d;
+        const double r = std::sqrt(X * X + Y * Y);
+        sub[i * N + j] = (r >= r_in && r <= 0.5 * D) ? 1 : 0;
+      }
+    f.cmap.assign(nc * nc, -1);
+    int cnt = 0;
+    for (int i = 0; i < nc; ++i)
+      for (int j = 0; j < nc; ++j) {
+        bool in = false;
+        for (int di = -1; di <= 0; ++di)
+          for (int dj = -1; dj <= 0; ++dj) {
+            const int a = i + di, b = j + dj;
+            if (a >= 0 && b >= 0 && a < N && b < N && sub[a * N + b]) in = true;
+          }
+        if (in) f.cmap[i * nc + j] = cnt++;
+      }
+    const int K = (int)f.dirs.size() / 2;
+    // layers -> corners (no cone effect), DMs -> corners (centred actuator grids)
+    // t = (x + shift + add) / spacing + offset, floor and fraction per corner row / column
+    auto table = [&](double shift_x, double shift_y, double add, double spacing, double offset, int n,
+                     GLTables& t) -> bool {
+      t.q0y.resize(nc);
+      t.q0x.resize(nc);
+      t.wy.resize(nc);
+      t.wx.resize(nc);
+      for (int j = 0; j < nc; ++j) {
+        const double x = -0.5 * D + j * (D / N);
+        const double tx = (x + shift_x + add) / spacing + offset;
+        const double ty = (x + shift_y + add) / spacing + offset;
+        const double fx = std::floor(tx), fy = std::floor(ty);
+        if (fx < 0 || fy < 0 || fx > n - 2 || fy > n - 2) return false;
+        t.q0x[j] = (int)fx;
+        t.wx[j] = tx - fx;
+        t.q0y[j] = (int)fy;
+        t.wy[j] = ty - fy;
+      }
+      return true;
+    };
+    f.tabL.assign(K, std::vector<GLTables>(L));
+    f.tabD.assign(K, std::vector<GLTables>(f.dms.size()));
+    f.dm_off.assign(f.dms.size() + 1, 0);
+    for (size_t q = 0; q < f.dms.size(); ++q) f.dm_off[q + 1] = f.dm_off[q] + f.dms[q].n_act * f.dms[q].n_act;
+    f.n_act = f.dm_off.back();
+    std::vector<double> diag(f.n_act, 0.0);
+    for (int k = 0; k < K; ++k) {
+      const double thx = f.dirs[2 * k], thy = f.dirs[2 * k + 1];
+      for (int l = 0; l < L; ++l) {
+        const LayerHost& lh = m.layers[l];
+        if (!table(lh.d.h * thx, lh.d.h * thy, 0.5 * m.L, lh.delta, 0.0, lh.d.n, f.tabL[k][l])) {
+          std::snprintf(buf, sizeof buf, "fitting direction %d leaves layer %d", k, l);
+          err = buf;
+          return FEWHA_EGEOM;
+        }
+      }
+      for (size_t q = 0; q < f.dms.size(); ++q) {
+        const fewha_dm_desc& dm = f.dms[q];
+        GLTables& t = f.tabD[k][q];
+        if (!table(dm.h * thx, dm.h * thy, 0.0, dm.pitch, 0.5 * (dm.n_act - 1), dm.n_act, t)) {
+          std::snprintf(buf, sizeof buf, "fitting direction %d leaves DM %d", k, (int)q);
+          err = buf;
+          return FEWHA_EGEOM;
+        }
+        for (int i = 0; i < nc; ++i)
+          for (int j = 0; j < nc; ++j) {
+            if (f.cmap[i * nc + j] < 0) continue;
+            const double wy[2] = {1.0 - t.wy[i], t.wy[i]}, wx[2] = {1.0 - t.wx[j], t.wx[j]};
+            for (int a = 0; a < 2; ++a)
+              for (int b = 0; b < 2; ++b)
+                diag[f.dm_off[q] + (t.q0y[i] + a) * dm.n_act + t.q0x[j] + b] += wy[a] * wy[a] * wx[b] * wx[b];
+          }
+      }
+    }
+    double mean = 0.0;
+    for (double v : diag) mean += v;
+    mean /= (double)f.n_act;
+    f.eps = f.eps_rel * mean;
+  }
+
   // ---- exact Jacobi diagonal, eq. (precond) ----
   // Every 2-D basis function is a product u(y) v(x) of 1-D periodic basis
   // functions of one level, so its propagated wavefront is U(i) V(j) and its

@@ -89,6 +89,15 @@ class Context:
         no = cfg["noise"]
         _check(_abi.fewha_set_noise(self.h, no["alpha_eta"], no["na_fwhm"], no["spot_fwhm"]), self.h)
         _check(_abi.fewha_set_control(self.h, cfg.get("gain", 1.0)), self.h)
+        if cfg.get("dms") and cfg.get("fit"):
+            dms = (_abi.fewha_dm_desc * len(cfg["dms"]))()
+            for k, dm in enumerate(cfg["dms"]):
+                dms[k].h, dms[k].n_act, dms[k].pitch = dm["h"], dm["n_act"], dm["pitch"]
+            fit = cfg["fit"]
+            dirs = (c_double * (2 * len(fit["directions"])))(*[v for d in fit["directions"] for v in d])
+            n_fit = fit.get("n_subap", cfg["wfs"][0]["n_subap"])
+            _check(_abi.fewha_set_fitting(self.h, len(cfg["dms"]), dms, len(fit["directions"]), dirs, n_fit,
+                                          fit["iters"], fit["eps_rel"]), self.h)
         _check(_abi.fewha_finalize(self.h), self.h)
 
     def close(self, _destroy=_abi.fewha_destroy):

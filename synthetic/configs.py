@@ -185,11 +185,25 @@ def large():
                     "cn2": w} for h, w in zip(heights, weights)],
         "noise": {"alpha_eta": 0.2, "na_fwhm": 11400.0, "spot_fwhm": 1.0 * ARCSEC},
         "iters": 20,
-        "dms": [{"h": 0.0, "n_act": 81, "pitch": D / 80},
+        "dms": [{"h": 0.0, "n_act": 83, "pitch": D / 80},
                 {"h": 4000.0, "n_act": 47, "pitch": 1.0},
                 {"h": 12700.0, "n_act": 47, "pitch": 1.0}],
         "fit": {"directions": [(x * ARCSEC, y * ARCSEC) for y in (-30.0, 0.0, 30.0)
                                for x in (-30.0, 0.0, 30.0)],
+                "iters": 10, "eps_rel": 1e-6},
+    })
+    return cfg
+
+
+def small_fit():
+    """``small`` with a fitting step onto 3 DMs over 4 directions."""
+    cfg = small()
+    cfg.update({
+        "name": "small_fit",
+        "dms": [{"h": 0.0, "n_act": 23, "pitch": 0.4},
+                {"h": 4000.0, "n_act": 13, "pitch": 0.8},
+                {"h": 12700.0, "n_act": 15, "pitch": 0.8}],
+        "fit": {"directions": [(x * ARCSEC, y * ARCSEC) for y in (-20.0, 20.0) for x in (-20.0, 20.0)],
                 "iters": 10, "eps_rel": 1e-6},
     })
     return cfg
@@ -203,6 +217,7 @@ CONFIGS = {
     "paper_maory": paper_maory,
     "vlt_like": vlt_like,
     "large": large,
+    "small_fit": small_fit,
 }
 
 
