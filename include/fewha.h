@@ -190,6 +190,60 @@ FEWHA_API fewha_status fewha_rhs(fewha_ctx* ctx, const float* slopes, float* b);
 FEWHA_API fewha_status fewha_reconstruct(fewha_ctx* ctx, const float* slopes, float* state,
                                          float* layers_out, float* dm_out, int iters);
 
+/* ---- converged solves and the implicit backward ---- */
+
+/* Solve M x = rhs (eq. fewha, wavelet domain) to a relative residual
+ * ||rhs - M x||_2 / ||rhs||_2 <= rtol.  Mixed-precision iterative refinement:
+ * x = 0, then sweeps of { r = rhs - M x evaluated in double precision;
+ * M d = r by the Jacobi-preconditioned CG of Algorithm 1 in FP32 (run to a
+ * reduction of its J^{-1}-weighted residual, checked every 16 iterations);
+ * x += d }, the iterate accumulated in double precision and rounded to float
+ * once at the end.  rhs and x: N_c floats, device.  max_iters in [0, 2^24]
+ * bounds the total CG iterations; iters_done and rel_res (host, may be NULL)
+ * receive that total and the final residual ratio of the double-precision
+ * iterate (the sweeps also stop when one no longer halves it).  Synchronizes
+ * the context stream after every sweep and CG check.  A zero rhs returns
+ * x = 0 after 0 iterations. */
+FEWHA_API fewha_status fewha_solve(fewha_ctx* ctx, const float* rhs, float* x, int max_iters,
+                                   double rtol, int* iters_done, double* rel_res);
+
+/* As fewha_solve for rhs = W^{-T} A^T C_hat^{-1} slopes + W^{-T} g_layers
+ * (either may be NULL): the MAP solution of eq. fewha for given slopes
+ * (g_layers = NULL), or the adjoint solve M lambda = W^{-T} dL/dphi
+ * (slopes = NULL).  The right-hand side is formed inside the double-precision
+ * residual, never rounded to float.  slopes: n_slopes floats, g_layers: N_c
+ * floats, x: N_c floats, all device. */
+FEWHA_API fewha_status fewha_solve_map(fewha_ctx* ctx, const float* slopes, const float* g_layers,
+                                       float* x, int max_iters, double rtol, int* iters_done,
+                                       double* rel_res);
+
+/* layers = W^{-1} coef = delta_l^{-1} W_l^T coef_l for every layer (Sec. 3.1:
+ * W orthogonal, so W^{-1} = delta^{-1} W^T).  N_c floats each, device. */
+FEWHA_API fewha_status fewha_apply_Winv(fewha_ctx* ctx, const float* coef, float* layers);
+
+/* coef = W^{-T} layers = delta_l^{-1} W_l layers_l (the adjoint of
+ * fewha_apply_Winv).  N_c floats each, device. */
+FEWHA_API fewha_status fewha_apply_WinvT(fewha_ctx* ctx, const float* layers, float* coef);
+
+/* Parameter gradients of a loss L(phi) of the reconstructed layers
+ * phi = W^{-1} c*, c* = M^{-1} b(s) the exact solution of eq. fewha, through
+ * the implicit-function theorem.  Inputs (device): slopes s (n_slopes
+ * floats), coef = c* (N_c), lam = lambda = M^{-1} W^{-T} dL/dphi (N_c, the
+ * adjoint solve; M is symmetric).  Output (device, 1 + 2L doubles):
+ *   grads[0]       = dL/dalpha   = -lambda^T D c*
+ *   grads[1 + l]   = dL/dgamma_l =  alpha lambda_l^T D_l c*_l / gamma_l
+ *   grads[1 + L + l] = dL/dh_l   =  <dA_l W^{-1} lambda, C_hat^{-1}(s - A phi)>
+ *                                 - <C_hat^{-1} A W^{-1} lambda, dA_l phi>
+ * with dA_l = dA/dh_l (propagation P_g of Sec. 2, LGS cone factor 1 - h/H,
+ * differentiated in h; on a grid line the average of the two one-sided
+ * derivatives) and D the diagonal prior (Sec. 3.3), scaling as 1/gamma_l.
+ * Only the dependence through c* is included: a loss that itself depends on
+ * the heights adds its own explicit term.  FEWHA_EGEOM when a derivative
+ * stencil would leave its layer.  Inner products are accumulated in double
+ * precision and summed in a fixed order (deterministic). */
+FEWHA_API fewha_status fewha_param_grads(fewha_ctx* ctx, const float* slopes, const float* coef,
+                                         const float* lam, double* grads);
+
 /* ---- batches: many independent problems per launch ---- */
 
 /* Group n finalized device contexts (same device; geometries may differ)
@@ -205,6 +259,25 @@ FEWHA_API fewha_status fewha_batch_set_stream(fewha_batch* b, void* hip_stream);
 FEWHA_API fewha_status fewha_batch_reconstruct(fewha_batch* b, const float* const* slopes,
                                                float* const* state, float* const* layers_out,
                                                float* const* dm_out, int iters, int use_graph);
+
+/* Batched forms of the calls above: one entry of each host array of device
+ * pointers per problem (same layouts and rules).  The batched solves iterate
+ * until every problem meets rtol (the worst ratio in rel_res); in
+ * fewha_batch_solve_map either array may be NULL. */
+FEWHA_API fewha_status fewha_batch_solve(fewha_batch* b, const float* const* rhs, float* const* x,
+                                         int max_iters, double rtol, int* iters_done,
+                                         double* rel_res);
+FEWHA_API fewha_status fewha_batch_solve_map(fewha_batch* b, const float* const* slopes,
+                                             const float* const* g_layers, float* const* x,
+                                             int max_iters, double rtol, int* iters_done,
+                                             double* rel_res);
+FEWHA_API fewha_status fewha_batch_apply_Winv(fewha_batch* b, const float* const* coef,
+                                              float* const* layers);
+FEWHA_API fewha_status fewha_batch_apply_WinvT(fewha_batch* b, const float* const* layers,
+                                               float* const* coef);
+FEWHA_API fewha_status fewha_batch_param_grads(fewha_batch* b, const float* const* slopes,
+                                               const float* const* coef, const float* const* lam,
+                                               double* const* grads);
 
 /* Stage identifiers for fewha_batch_time_stage. */
 enum {

@@ -5,7 +5,7 @@ inside a fixed-iteration Jacobi-preconditioned CG, warm restart and open-loop
 control, as hand-written HIP kernels behind a C ABI (include/fewha.h).
 
 Importing the package loads ``lib/libfewha.so``; if it is not built the
-import fails (``paper_2202_11945_amd.build.build()`` builds it).
+import fails (``python paper_2202_11945_amd/build.py`` builds it).
 """
 
 from . import _abi  # noqa: F401  (loads the library or raises)

@@ -1,7 +1,7 @@
 """ctypes declarations of the libfewha C ABI (include/fewha.h).
 
 Argument marshalling only: every computation runs in the HIP library.  The
-library must have been built (``paper_2202_11945_amd.build.build()``); a
+library must have been built (``python paper_2202_11945_amd/build.py``); a
 missing library raises at import time, there is no fallback.
 """
 
@@ -40,7 +40,7 @@ class FewhaError(RuntimeError):
 
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libfewha.so is not built (%s); run paper_2202_11945_amd.build.build()" % LIB_PATH)
+    raise ImportError("libfewha.so is not built (%s); run python paper_2202_11945_amd/build.py" % LIB_PATH)
 
 # torch ships its own HIP runtime under the same soname; loading torch first
 # makes the library bind to that one runtime instead of a second copy, so
@@ -71,7 +71,20 @@ _SIGS = {
     "fewha_apply_M": (c_int, [_P, _FP, _FP]),
     "fewha_rhs": (c_int, [_P, _FP, _FP]),
     "fewha_reconstruct": (c_int, [_P, _FP, _FP, _FP, _FP, c_int]),
+    "fewha_solve": (c_int, [_P, _FP, _FP, c_int, c_double, POINTER(c_int), POINTER(c_double)]),
+    "fewha_solve_map": (c_int, [_P, _FP, _FP, _FP, c_int, c_double, POINTER(c_int), POINTER(c_double)]),
+    "fewha_apply_Winv": (c_int, [_P, _FP, _FP]),
+    "fewha_apply_WinvT": (c_int, [_P, _FP, _FP]),
+    "fewha_param_grads": (c_int, [_P, _FP, _FP, _FP, c_void_p]),
     "fewha_batch_create": (c_int, [POINTER(c_void_p), POINTER(c_void_p), c_int]),
+    "fewha_batch_solve": (c_int, [_P, POINTER(c_void_p), POINTER(c_void_p), c_int, c_double, POINTER(c_int),
+                                  POINTER(c_double)]),
+    "fewha_batch_solve_map": (c_int, [_P, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p), c_int, c_double,
+                                      POINTER(c_int), POINTER(c_double)]),
+    "fewha_batch_apply_Winv": (c_int, [_P, POINTER(c_void_p), POINTER(c_void_p)]),
+    "fewha_batch_apply_WinvT": (c_int, [_P, POINTER(c_void_p), POINTER(c_void_p)]),
+    "fewha_batch_param_grads": (c_int, [_P, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
+                                        POINTER(c_void_p)]),
     "fewha_batch_set_stream": (c_int, [_P, c_void_p]),
     "fewha_batch_reconstruct": (c_int, [_P, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
                                         POINTER(c_void_p), c_int, c_int]),

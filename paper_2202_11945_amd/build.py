@@ -5,7 +5,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", f) for f in ("setup.cpp", "api.cpp", "kernels.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("setup.cpp", "api.cpp", "kernels.hip", "residual64.hip")]
 OUT_DIR = os.path.join(HERE, "lib")
 OUT = os.path.join(OUT_DIR, "libfewha.so")
 

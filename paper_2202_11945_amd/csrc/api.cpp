@@ -22,7 +22,11 @@ using namespace fewha;
 namespace {
 
 constexpr int kRing = 8;          // pinned staging slots for per-call I/O tables
-constexpr int kMaxIters = 256;    // PCG iterations per call
+constexpr int kMaxIters = 256;    // PCG iterations per reconstruct call (graph-captured frames)
+constexpr int kMaxSolveIters = 1 << 24;  // PCG iterations of one solve
+constexpr int kSolveCheck = 16;   // iterations between two convergence checks of a solve
+constexpr int kMaxSweeps = 32;    // refinement sweeps of one solve
+static_assert(sizeof(GradIo) <= sizeof(IoDev), "per-call tables share the staging ring");
 
 int ilog2i(int n) {
   int k = 0;
@@ -55,6 +59,16 @@ struct Plan {
   Range idwt_res, fdwt_res, pg, gt, pt, upd;
   std::vector<Range> idwt_glob, fdwt_glob;
   Range fit_fwdL, fit_fwdD, fit_pt, fit_cg;  // DM fitting (empty when no problem fits)
+  Range sinit, gprior, ghgt;                 // solve start, parameter-gradient reductions
+  Range r64wfs;                              // FP64 residual: one tile per (problem, sensor)
+  std::vector<Range> r64inv, r64fwd;         // FP64 residual: transform steps
+  Resid64Tiles r64;
+  Filter64 F64{};
+  std::vector<float*> rbuf;                  // per problem: residual of a refined solve
+  GradIo* dGIO = nullptr;
+  std::vector<float*> sstate;                // per problem: [x | unused | r] of a solve
+  double* rho_host = nullptr;                // pinned readback: 2 n_dots doubles per problem
+  std::vector<long> rho_off;
   int nprob_all = 0;                         // problems plus two fitting views per fitted problem
   FitDev* dF = nullptr;
   int max_fit_iters = 0;
@@ -96,6 +110,7 @@ void destroy_plan(Plan* p) {
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   if (p->t0) (void)hipEventDestroy(p->t0);
   if (p->t1) (void)hipEventDestroy(p->t1);
+  if (p->rho_host) (void)hipHostFree(p->rho_host);
   if (p->arena) (void)hipFree(p->arena);
   delete p;
 }
@@ -127,19 +142,25 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     for (int i = 0; i < 6; ++i) {
       P.F.h[i] = (float)m0.h[i];
       P.F.g[i] = (float)m0.g[i];
+      P.F64.h[i] = m0.h[i];
+      P.F64.g[i] = m0.g[i];
     }
   }
   // ---- descriptors and tile lists ----
   struct ProbLayout {
     size_t phi, phiadj, tmpa, tmpb, sd, vadj, part, p0, p1, q, dots, jinv, itab, ftab, cmap, cinv, gl;
+    size_t sstate, gphi, glam, gslots, gitab, gftab;
+    size_t a64, b64, sd64, u64, rslots, cinv64, ftab64, rbuf, x64;
   };
   std::vector<ProbLayout> lay(P.nprob);
   Carver cv;
-  std::vector<Tile> t_idwt_res, t_fdwt_res, t_pg, t_gt, t_pt, t_upd;
+  std::vector<Tile> t_idwt_res, t_fdwt_res, t_pg, t_gt, t_pt, t_upd, t_sinit, t_gprior, t_ghgt, t_r64wfs;
+  std::vector<std::vector<Tile>> t_r64inv(kMaxLevelsJ), t_r64fwd(kMaxLevelsJ);
+  std::vector<std::vector<double>> cinv64(P.nprob), ftab64(P.nprob);
   std::vector<std::vector<Tile>> t_idwt_glob, t_fdwt_glob;
   // host table images per problem (copied after allocation)
-  std::vector<std::vector<int>> itab(P.nprob), cmap(P.nprob);
-  std::vector<std::vector<float>> ftab(P.nprob), cinv(P.nprob), jinv(P.nprob);
+  std::vector<std::vector<int>> itab(P.nprob), cmap(P.nprob), gitab(P.nprob);
+  std::vector<std::vector<float>> ftab(P.nprob), cinv(P.nprob), jinv(P.nprob), gftab(P.nprob);
   std::vector<std::vector<GLPar>> glp(P.nprob);
   for (int k = 0; k < P.nprob; ++k) {
     const HostModel& m = *models[k];
@@ -167,10 +188,15 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
       ld.tmp_off = tmp_total;
       if (ld.n > ld.res) tmp_total += ld.n * ld.n / 4;
       ld.inv_delta = (float)(1.0 / lh.delta);
-      for (int j = 0; j < kMaxLevelsJ; ++j) ld.alpha_d[j] = (float)(m.alpha * lh.dtab[j]);
+      for (int j = 0; j < kMaxLevelsJ; ++j) {
+        ld.alpha_d[j] = (float)(m.alpha * lh.dtab[j]);
+        ld.d64[j] = lh.dtab[j];
+      }
+      ld.cn2 = lh.d.cn2;
+      ld.inv_delta64 = 1.0 / lh.delta;
       P.hL.push_back(ld);
     }
-    int s_tot = 0, v_tot = 0, m_tot = 0, part_tot = 0, tab_tot = 0;
+    int s_tot = 0, v_tot = 0, m_tot = 0, part_tot = 0, tab_tot = 0, gtab_tot = 0;
     for (int g = 0; g < G; ++g) {
       const WfsHost& wh = m.wfs[g];
       WfsDev wd{};
@@ -195,8 +221,12 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
       wd.tab_stride = 4 * wd.nc;
       wd.tab_off = tab_tot;
       tab_tot += L * wd.tab_stride;
+      wd.gtab_off = gtab_tot;
+      gtab_tot += L * 4 * wd.nc;
       wd.inv_sigma2 = (float)(1.0 / (wh.d.sigma * wh.d.sigma));
       wd.inv_nM = (float)(1.0 / wh.n_active);
+      wd.inv_sigma2_d = 1.0 / (wh.d.sigma * wh.d.sigma);
+      wd.inv_nM_d = 1.0 / wh.n_active;
       for (int v = 0; v < 4; ++v) wd.sum_cinv[v] = (float)wh.sum_cinv[v];
       P.hW.push_back(wd);
     }
@@ -205,11 +235,16 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     ftab[k].assign(tab_tot, 0.f);
     cmap[k].assign(m_tot, -1);
     cinv[k].assign(3 * (size_t)m_tot, 0.f);
+    cinv64[k].assign(3 * (size_t)m_tot, 0.0);
+    ftab64[k].assign(std::max(tab_tot, 1), 0.0);
     for (int g = 0; g < G; ++g) {
       const WfsDev& wd = P.hW[pd.wfs0 + g];
       const WfsHost& wh = m.wfs[g];
       for (int e = 0; e < wd.N * wd.N; ++e) cmap[k][wd.m_off + e] = wh.cmap[e];
-      for (int e = 0; e < 3 * wd.N * wd.N; ++e) cinv[k][wd.cinv_off + e] = (float)wh.cinv[e];
+      for (int e = 0; e < 3 * wd.N * wd.N; ++e) {
+        cinv[k][wd.cinv_off + e] = (float)wh.cinv[e];
+        cinv64[k][wd.cinv_off + e] = wh.cinv[e];
+      }
       for (int l = 0; l < L; ++l) {
         const GLTables& t = m.tab[g][l];
         const int base = wd.tab_off + l * wd.tab_stride, nc = wd.nc;
@@ -218,6 +253,27 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
           itab[k][base + nc + j] = t.q0x[j];
           ftab[k][base + 2 * nc + j] = (float)t.wy[j];
           ftab[k][base + 3 * nc + j] = (float)t.wx[j];
+          ftab64[k][base + 2 * nc + j] = t.wy[j];
+          ftab64[k][base + 3 * nc + j] = t.wx[j];
+        }
+      }
+    }
+    gitab[k].assign(std::max(gtab_tot, 1), 0);
+    gftab[k].assign(std::max(gtab_tot, 1), 0.f);
+    for (int g = 0; g < G; ++g) {
+      const WfsDev& wd = P.hW[pd.wfs0 + g];
+      for (int l = 0; l < L; ++l) {
+        const GradTables& t = m.gtab[g][l];
+        const int base = wd.gtab_off + l * 4 * wd.nc, nc = wd.nc;
+        for (int j = 0; j < nc; ++j) {
+          gitab[k][base + j] = t.qy[j];
+          gitab[k][base + nc + j] = t.qx[j];
+          gitab[k][base + 2 * nc + j] = t.tiey[j];
+          gitab[k][base + 3 * nc + j] = t.tiex[j];
+          gftab[k][base + j] = (float)t.wy[j];
+          gftab[k][base + nc + j] = (float)t.wx[j];
+          gftab[k][base + 2 * nc + j] = (float)t.dty[j];
+          gftab[k][base + 3 * nc + j] = (float)t.dtx[j];
         }
       }
     }
@@ -270,6 +326,39 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     for (int c = 0; c < nupd; ++c) t_upd.push_back({k, 0, c, 0, c, 0, 0, 0});
     pd.n_slots_upd = nupd;
     pd.n_dots = std::max(pd.n_slots_fdwt, pd.n_slots_upd);
+    for (int sl = 0; sl < pd.n_slots_fdwt; ++sl) t_sinit.push_back({k, 0, 0, 0, sl, 0, 0, 0});
+    // parameter gradients: prior-term chunks per layer, height-term tiles per (layer, sensor)
+    int gp = 0, gh = 0;
+    for (int l = 0; l < L; ++l) {
+      LayerDev& ld = P.hL[pd.layer0 + l];
+      const int nch = cdiv(ld.n * ld.n, kGradChunk);
+      ld.gp_off = gp;
+      ld.gp_n = nch;
+      for (int c2 = 0; c2 < nch; ++c2) t_gprior.push_back({k, l, c2, 0, gp + c2, 0, 0, 0});
+      gp += nch;
+      ld.gh_off = gh;
+      for (int g = 0; g < G; ++g) {
+        const int tc = cdiv(P.hW[pd.wfs0 + g].nc, kTileS);
+        for (int ty = 0; ty < tc; ++ty)
+          for (int tx = 0; tx < tc; ++tx) t_ghgt.push_back({k, g, ty, tx, gh++, l, 0, 0});
+      }
+      ld.gh_n = gh - ld.gh_off;
+    }
+    pd.n_gp = gp;
+    pd.n_gh = gh;
+    pd.alpha = m.alpha;
+    // FP64 residual: transform steps per layer, one noise tile per sensor
+    for (int l = 0; l < L; ++l) {
+      const LayerDev& ld = P.hL[pd.layer0 + l];
+      const int m0 = ld.n >> ld.levels;
+      for (int st = 0; st < ld.levels; ++st) {
+        const int mi = m0 << (st + 1), mf = ld.n >> st;
+        for (int c2 = 0; c2 < cdiv(mi * mi, 1024); ++c2) t_r64inv[st].push_back({k, l, c2, 0, 0, ilog2i(mi), 0, 0});
+        for (int c2 = 0; c2 < cdiv(mf * mf / 2, 1024); ++c2)
+          t_r64fwd[st].push_back({k, l, c2, 0, 0, ilog2i(mf), 0, 0});
+      }
+    }
+    for (int g = 0; g < G; ++g) t_r64wfs.push_back({k, g, 0, 0, 0, 0, 0, 0});
     for (int g = 0; g < G; ++g) {
       const WfsDev& wd = P.hW[pd.wfs0 + g];
       for (int ty = 0; ty < wd.tiles_side; ++ty)
@@ -296,13 +385,28 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     pl_.p0 = cv.take(nc4);
     pl_.p1 = cv.take(nc4);
     pl_.q = cv.take(nc4);
-    pl_.dots = cv.take(sizeof(double) * (size_t)(2 * kMaxIters + 2) * pd.n_dots);
+    pl_.dots = cv.take(sizeof(double) * (size_t)(2 * kDotRing) * pd.n_dots);
     pl_.jinv = cv.take(nc4);
     pl_.itab = cv.take(sizeof(int) * tab_tot);
     pl_.ftab = cv.take(sizeof(float) * tab_tot);
     pl_.cmap = cv.take(sizeof(int) * m_tot);
     pl_.cinv = cv.take(sizeof(float) * 3 * (size_t)m_tot);
     pl_.gl = cv.take(sizeof(GLPar) * (size_t)G * L);
+    pl_.sstate = cv.take(sizeof(float) * 3 * (size_t)pd.n_c);
+    pl_.gphi = cv.take(nc4);
+    pl_.glam = cv.take(nc4);
+    pl_.gslots = cv.take(sizeof(double) * (size_t)(pd.n_gp + 2 * pd.n_gh));
+    pl_.gitab = cv.take(sizeof(int) * gitab[k].size());
+    pl_.gftab = cv.take(sizeof(float) * gftab[k].size());
+    pl_.a64 = cv.take(sizeof(double) * (size_t)pd.n_c);
+    pl_.b64 = cv.take(sizeof(double) * (size_t)pd.n_c);
+    pl_.sd64 = cv.take(sizeof(double) * s_tot);
+    pl_.u64 = cv.take(sizeof(double) * v_tot);
+    pl_.rslots = cv.take(sizeof(double) * 2 * (size_t)pd.n_slots_upd);
+    pl_.cinv64 = cv.take(sizeof(double) * cinv64[k].size());
+    pl_.ftab64 = cv.take(sizeof(double) * ftab64[k].size());
+    pl_.rbuf = cv.take(nc4);
+    pl_.x64 = cv.take(sizeof(double) * (size_t)pd.n_c);
     P.hP.push_back(pd);
   }
   // ---- DM fitting views: (directions x layers) and (directions x DMs) ----
@@ -444,11 +548,20 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   P.fit_fwdD = add(t_ffD);
   P.fit_pt = add(t_fpt);
   P.fit_cg = add(t_fcg);
+  P.sinit = add(t_sinit);
+  P.gprior = add(t_gprior);
+  P.ghgt = add(t_ghgt);
+  P.r64wfs = add(t_r64wfs);
+  for (int st = 0; st < kMaxLevelsJ; ++st) {
+    P.r64inv.push_back(add(t_r64inv[st]));
+    P.r64fwd.push_back(add(t_r64fwd[st]));
+  }
   const size_t oP = cv.take(sizeof(ProbDev) * P.nprob_all);
   const size_t oL = cv.take(sizeof(LayerDev) * P.hL.size());
   const size_t oW = cv.take(sizeof(WfsDev) * P.hW.size());
   const size_t oIO = cv.take(sizeof(IoDev) * P.nprob_all);
   const size_t oIOp = cv.take(sizeof(IoDev) * P.nprob_all);
+  const size_t oGIO = cv.take(sizeof(GradIo) * P.nprob_all);
   const size_t oF = cv.take(sizeof(FitDev) * std::max<size_t>(hF.size(), 1));
   const size_t oT = cv.take(sizeof(Tile) * std::max<size_t>(P.hT.size(), 1));
   P.arena_bytes = cv.off;
@@ -481,6 +594,26 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     pd.cmap = (const int*)(base + l.cmap);
     pd.cinv = (const float*)(base + l.cinv);
     pd.gl = (const GLPar*)(base + l.gl);
+    pd.gphi = (float*)(base + l.gphi);
+    pd.glam = (float*)(base + l.glam);
+    pd.gslots = (double*)(base + l.gslots);
+    pd.gitab = (const int*)(base + l.gitab);
+    pd.gftab = (const float*)(base + l.gftab);
+    P.sstate.push_back((float*)(base + l.sstate));
+    pd.a64 = (double*)(base + l.a64);
+    pd.b64 = (double*)(base + l.b64);
+    pd.sd64 = (double*)(base + l.sd64);
+    pd.u64 = (double*)(base + l.u64);
+    pd.rslots = (double*)(base + l.rslots);
+    pd.cinv64 = (const double*)(base + l.cinv64);
+    pd.ftab64 = (const double*)(base + l.ftab64);
+    pd.rbuf = (float*)(base + l.rbuf);
+    pd.x64 = (double*)(base + l.x64);
+    P.rbuf.push_back(pd.rbuf);
+    HIP_TRY(hipMemcpy(base + l.cinv64, cinv64[k].data(), sizeof(double) * cinv64[k].size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(base + l.ftab64, ftab64[k].data(), sizeof(double) * ftab64[k].size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(base + l.gitab, gitab[k].data(), sizeof(int) * gitab[k].size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(base + l.gftab, gftab[k].data(), sizeof(float) * gftab[k].size(), hipMemcpyHostToDevice));
 
     HIP_TRY(hipMemcpy(base + l.gl, glp[k].data(), sizeof(GLPar) * glp[k].size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(base + l.jinv, jinv[k].data(), sizeof(float) * jinv[k].size(), hipMemcpyHostToDevice));
@@ -525,7 +658,29 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   P.dW = (WfsDev*)(base + oW);
   P.dIO = (IoDev*)(base + oIO);
   P.dIOprof = (IoDev*)(base + oIOp);
+  P.dGIO = (GradIo*)(base + oGIO);
   P.dT = (Tile*)(base + oT);
+  // work lists of the FP64 residual chain (device addresses: after P.dT is set)
+  {
+    Resid64Tiles& rt = P.r64;
+    rt.upd = P.dT + P.upd.off;
+    rt.upd_n = P.upd.n;
+    for (int st = 0; st < kMaxLevelsJ; ++st) {
+      rt.inv[st] = P.dT + P.r64inv[st].off;
+      rt.inv_n[st] = P.r64inv[st].n;
+      rt.fwd[st] = P.dT + P.r64fwd[st].off;
+      rt.fwd_n[st] = P.r64fwd[st].n;
+      if (rt.inv_n[st] > 0) rt.n_steps = st + 1;
+    }
+    rt.pg = P.dT + P.pg.off;
+    rt.pg_n = P.pg.n;
+    rt.wfs = P.dT + P.r64wfs.off;
+    rt.wfs_n = P.r64wfs.n;
+    rt.gt = P.dT + P.gt.off;
+    rt.gt_n = P.gt.n;
+    rt.pt = P.dT + P.pt.off;
+    rt.pt_n = P.pt.n;
+  }
   HIP_TRY(hipMemcpy(P.dP, P.hP.data(), sizeof(ProbDev) * P.nprob_all, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(P.dL, P.hL.data(), sizeof(LayerDev) * P.hL.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(P.dW, P.hW.data(), sizeof(WfsDev) * P.hW.size(), hipMemcpyHostToDevice));
@@ -533,6 +688,14 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   for (int i = 0; i < kRing; ++i) {
     HIP_TRY(hipHostMalloc((void**)&P.pinned[i], sizeof(IoDev) * P.nprob_all, hipHostMallocDefault));
     HIP_TRY(hipEventCreateWithFlags(&P.ev[i], hipEventDisableTiming));
+  }
+  {
+    long tot = 0;
+    for (int k = 0; k < P.nprob; ++k) {
+      P.rho_off.push_back(tot);
+      tot += 2 * P.hP[k].n_dots;  // a dot group, or the residual pairs (2 per update slot)
+    }
+    HIP_TRY(hipHostMalloc((void**)&P.rho_host, sizeof(double) * std::max(tot, 1L), hipHostMallocDefault));
   }
   HIP_TRY(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking));
   HIP_TRY(hipEventCreate(&P.t0));
@@ -543,17 +706,23 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   return FEWHA_OK;
 }
 
-// Stage the per-call I/O table and copy it to the device (stream ordered).
-fewha_status upload_io(Plan& P, const std::vector<IoDev>& io, hipStream_t s, IoDev* dst, std::string& err) {
+// Stage a per-call table (nprob entries, zero-padded to nprob_all) and copy
+// it to the device, stream ordered.  The pinned slot is reused only after the
+// copy that read it has completed.
+template <typename T>
+fewha_status upload_table(Plan& P, const std::vector<T>& v, hipStream_t s, T* dst, std::string& err) {
   const int slot = P.ring;
   P.ring = (P.ring + 1) % kRing;
   if (P.ev_used[slot]) HIP_TRY(hipEventSynchronize(P.ev[slot]));
-  std::memset(P.pinned[slot], 0, sizeof(IoDev) * P.nprob_all);
-  std::memcpy(P.pinned[slot], io.data(), sizeof(IoDev) * P.nprob);
-  HIP_TRY(hipMemcpyAsync(dst, P.pinned[slot], sizeof(IoDev) * P.nprob_all, hipMemcpyHostToDevice, s));
+  std::memset(P.pinned[slot], 0, sizeof(T) * P.nprob_all);
+  std::memcpy(P.pinned[slot], v.data(), sizeof(T) * P.nprob);
+  HIP_TRY(hipMemcpyAsync(dst, P.pinned[slot], sizeof(T) * P.nprob_all, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(P.ev[slot], s));
   P.ev_used[slot] = true;
   return FEWHA_OK;
+}
+fewha_status upload_io(Plan& P, const std::vector<IoDev>& io, hipStream_t s, IoDev* dst, std::string& err) {
+  return upload_table(P, io, s, dst, err);
 }
 
 LaunchArgs args(const Plan& P, hipStream_t s, const IoDev* io) {
@@ -611,6 +780,243 @@ void enq_reconstruct(const Plan& P, const LaunchArgs& a, int iters) {
     }
     launch_fit_cg(a, P.dF, P.fit_cg.n, FIT_FINAL);
   }
+}
+
+// Fixed-order sum of dot group `grp` of every problem, read back to the host.
+fewha_status read_rho(Plan& P, hipStream_t st, int grp, int count_k, std::vector<double>& out, std::string& err) {
+  for (int k = 0; k < P.nprob; ++k) {
+    const ProbDev& pd = P.hP[k];
+    HIP_TRY(hipMemcpyAsync(P.rho_host + P.rho_off[k], pd.dots + (long)grp * pd.n_dots, sizeof(double) * pd.n_dots,
+                           hipMemcpyDeviceToHost, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  out.assign(P.nprob, 0.0);
+  for (int k = 0; k < P.nprob; ++k) {
+    const ProbDev& pd = P.hP[k];
+    const int n = count_k == 0 ? pd.n_slots_fdwt : pd.n_slots_upd;
+    double a = 0.0;
+    for (int i = 0; i < n; ++i) a += P.rho_host[P.rho_off[k] + i];
+    out[k] = a;
+  }
+  return FEWHA_OK;
+}
+
+// Correction solve M d = r (r in P.rbuf) by the FP32 Jacobi-preconditioned CG
+// of Algorithm 1 from d = 0: the same kernels as a frame, one launch per
+// stage and iteration over all problems; every kSolveCheck iterations the
+// host reads rho_k and stops once sqrt(rho_k / rho_0) <= tol for every
+// problem.  d is left in the x part of P.sstate.
+fewha_status pcg_core(Plan& P, hipStream_t st, int max_iters, double tol, int& iters, std::string& err) {
+  std::vector<IoDev> io(P.nprob);
+  for (int k = 0; k < P.nprob; ++k) {
+    io[k].in = P.rbuf[k];
+    io[k].state = P.sstate[k];
+  }
+  fewha_status s = upload_io(P, io, st, P.dIO, err);
+  if (s != FEWHA_OK) return s;
+  const LaunchArgs a = args(P, st, P.dIO);
+  launch_solve_init(a, T(P, P.sinit), P.sinit.n);
+  std::vector<double> rho0, rho;
+  if ((s = read_rho(P, st, 0, 0, rho0, err)) != FEWHA_OK) return s;
+  auto worst = [&](const std::vector<double>& r) {
+    double w = 0.0;
+    for (int k = 0; k < P.nprob; ++k)
+      if (rho0[k] > 0.0) w = std::max(w, std::sqrt(std::max(r[k], 0.0) / rho0[k]));
+    return w;
+  };
+  double rel = worst(rho0);
+  int k = 0;
+  while (k < max_iters && rel > tol) {
+    const int kend = std::min(max_iters, k + kSolveCheck);
+    for (; k < kend; ++k) {
+      enq_idwt(P, a, k == 0 ? SRC_PUPD0 : SRC_PUPD, OUT_PHI, k);
+      enq_apply_M_core(P, a);
+      enq_fdwt(P, a, EPI_PCG, k);
+      launch_update(a, T(P, P.upd), P.upd.n, k);
+    }
+    HIP_TRY(hipGetLastError());
+    if ((s = read_rho(P, st, 2 * (k & (kDotRing - 1)), k, rho, err)) != FEWHA_OK) return s;
+    rel = worst(rho);
+  }
+  iters = k;
+  return FEWHA_OK;
+}
+
+// M x = b' with b' = b + W^{-T} A^T C_hat^{-1} s + W^{-T} g (each term optional)
+// to a relative residual ||b' - M x|| / ||b'|| <= rtol by mixed-precision
+// iterative refinement: x = 0; repeat { r = b' - M x in FP64; stop if small;
+// M d = r by the FP32 PCG; x += d }, the iterate kept in FP64 and rounded to
+// float once at the end.  The FP32 PCG alone stalls where the rounding of the
+// FP32 operator dominates, and a right-hand side rounded to float moves the
+// solution by M^{-1} times its rounding; forming b' inside the FP64 residual
+// avoids both.  ||b'|| is the residual norm of the first sweep (x = 0).
+fewha_status run_solve(Plan& P, hipStream_t st, const std::vector<const float*>& b,
+                       const std::vector<const float*>& sl, const std::vector<const float*>& g,
+                       const std::vector<float*>& x, int max_iters, double rtol, int* iters_done, double* rel_res,
+                       std::string& err) {
+  if (max_iters < 0 || max_iters > kMaxSolveIters || !(rtol >= 0.0)) {
+    err = "solve: need 0 <= max_iters <= 2^24 and rtol >= 0";
+    return FEWHA_EINVAL;
+  }
+  for (int k = 0; k < P.nprob; ++k)
+    if (!x[k]) {
+      err = "solve: null x (problem " + std::to_string(k) + ")";
+      return FEWHA_EINVAL;
+    }
+  HIP_TRY(hipSetDevice(P.device));
+  fewha_status s;
+  std::vector<IoDev> io(P.nprob);
+  auto stage = [&](auto fill) -> fewha_status {
+    for (int k = 0; k < P.nprob; ++k) {
+      io[k] = IoDev{};
+      fill(k, io[k]);
+    }
+    return upload_io(P, io, st, P.dIO, err);
+  };
+  const LaunchArgs a = args(P, st, P.dIO);
+  if ((s = stage([&](int k, IoDev& d) { d.state = x[k]; })) != FEWHA_OK) return s;
+  launch64_iterate(a, T(P, P.upd), P.upd.n, 0);
+  int total = 0;
+  double rel = 0.0, prev = HUGE_VAL;
+  std::vector<double> bnorm(P.nprob, 0.0);
+  for (int sweep = 0;; ++sweep) {
+    if ((s = stage([&](int k, IoDev& d) {
+           d.in = b[k];
+           d.rs = sl[k];
+           d.rg = g[k];
+           d.out = P.rbuf[k];
+         })) != FEWHA_OK)
+      return s;
+    launch64_resid_chain(a, P.r64, P.F64);
+    HIP_TRY(hipGetLastError());
+    for (int k = 0; k < P.nprob; ++k) {
+      const ProbDev& pd = P.hP[k];
+      HIP_TRY(hipMemcpyAsync(P.rho_host + P.rho_off[k], pd.rslots, sizeof(double) * 2 * pd.n_slots_upd,
+                             hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    rel = 0.0;
+    for (int k = 0; k < P.nprob; ++k) {
+      double rr = 0.0;
+      for (int i = 0; i < P.hP[k].n_slots_upd; ++i) rr += P.rho_host[P.rho_off[k] + 2 * i];
+      if (sweep == 0) bnorm[k] = std::sqrt(rr);
+      if (bnorm[k] > 0.0) rel = std::max(rel, std::sqrt(rr) / bnorm[k]);
+    }
+    // stop: converged, out of iterations, or a sweep that no longer helps
+    if (rel <= rtol || total >= max_iters || sweep >= kMaxSweeps || rel > 0.5 * prev) break;
+    prev = rel;
+    const double inner = std::max(1e-4, std::min(0.1, 0.3 * rtol / rel));
+    int it = 0;
+    if ((s = pcg_core(P, st, max_iters - total, inner, it, err)) != FEWHA_OK) return s;
+    total += it;
+    if ((s = stage([&](int k, IoDev& d) { d.in = P.sstate[k]; })) != FEWHA_OK) return s;
+    launch64_iterate(a, T(P, P.upd), P.upd.n, 1);
+  }
+  if ((s = stage([&](int k, IoDev& d) { d.state = x[k]; })) != FEWHA_OK) return s;
+  launch64_iterate(a, T(P, P.upd), P.upd.n, 2);
+  HIP_TRY(hipGetLastError());
+  if (iters_done) *iters_done = total;
+  if (rel_res) *rel_res = rel;
+  return FEWHA_OK;
+}
+
+// phi = W^{-1} c = delta^{-1} W^T c per layer (inverse transform to a caller buffer).
+fewha_status run_winv(Plan& P, hipStream_t st, const std::vector<const float*>& in, const std::vector<float*>& out,
+                      std::string& err) {
+  std::vector<IoDev> io(P.nprob);
+  for (int k = 0; k < P.nprob; ++k) {
+    if (!in[k] || !out[k]) {
+      err = "apply_Winv: null pointer";
+      return FEWHA_EINVAL;
+    }
+    io[k].in = in[k];
+    io[k].out = out[k];
+  }
+  HIP_TRY(hipSetDevice(P.device));
+  fewha_status s = upload_io(P, io, st, P.dIO, err);
+  if (s != FEWHA_OK) return s;
+  enq_idwt(P, args(P, st, P.dIO), SRC_IN, OUT_USER, 0);
+  HIP_TRY(hipGetLastError());
+  return FEWHA_OK;
+}
+
+// c = W^{-T} phi = delta^{-1} W phi per layer (forward transform of a caller buffer).
+fewha_status run_winvT(Plan& P, hipStream_t st, const std::vector<const float*>& in, const std::vector<float*>& out,
+                       std::string& err) {
+  std::vector<IoDev> io(P.nprob);
+  HIP_TRY(hipSetDevice(P.device));
+  for (int k = 0; k < P.nprob; ++k) {
+    if (!in[k] || !out[k]) {
+      err = "apply_WinvT: null pointer";
+      return FEWHA_EINVAL;
+    }
+    HIP_TRY(hipMemcpyAsync(P.hP[k].phiadj, in[k], sizeof(float) * P.hP[k].n_c, hipMemcpyDeviceToDevice, st));
+    io[k].out = out[k];
+  }
+  fewha_status s = upload_io(P, io, st, P.dIO, err);
+  if (s != FEWHA_OK) return s;
+  enq_fdwt(P, args(P, st, P.dIO), EPI_PLAIN, 0);
+  HIP_TRY(hipGetLastError());
+  return FEWHA_OK;
+}
+
+// Gradients of a loss of the layers phi = W^{-1} c*, c* = M^{-1} b, with respect to
+// alpha, the Cn2 weights and the layer heights, given the adjoint solution
+// lambda = M^{-1} W^{-T} dL/dphi:
+//   g_alpha   = -lambda^T D c
+//   g_gamma_l = alpha lambda_l^T D_l c_l / gamma_l           (D_l scales as 1/gamma_l)
+//   g_h_l     = <dA_l W^{-1} lambda, C_hat^{-1} (s - A phi)> - <C_hat^{-1} A W^{-1} lambda, dA_l phi>
+// with dA_l = d A / d h_l.  The loss's own dependence on h is the caller's.
+fewha_status run_param_grads(Plan& P, hipStream_t st, const std::vector<const float*>& slopes,
+                             const std::vector<const float*>& c, const std::vector<const float*>& lam,
+                             const std::vector<double*>& out, std::string& err) {
+  for (int k = 0; k < P.nprob; ++k) {
+    if (!slopes[k] || !c[k] || !lam[k] || !out[k]) {
+      err = "param_grads: null pointer (problem " + std::to_string(k) + ")";
+      return FEWHA_EINVAL;
+    }
+    if (!P.models[k]->grad_ok) {
+      err = "param_grads: " + P.models[k]->grad_msg;
+      return FEWHA_EGEOM;
+    }
+  }
+  HIP_TRY(hipSetDevice(P.device));
+  const int n = P.nprob;
+  std::vector<IoDev> io(n);
+  fewha_status s;
+  const LaunchArgs a = args(P, st, P.dIO);
+  auto stage = [&](auto fill) -> fewha_status {
+    for (int k = 0; k < n; ++k) {
+      io[k] = IoDev{};
+      fill(k, io[k]);
+    }
+    return upload_io(P, io, st, P.dIO, err);
+  };
+  // W^{-1} c and W^{-1} lambda
+  if ((s = stage([&](int k, IoDev& d) { d.in = c[k]; d.out = P.hP[k].gphi; })) != FEWHA_OK) return s;
+  enq_idwt(P, a, SRC_IN, OUT_USER, 0);
+  if ((s = stage([&](int k, IoDev& d) { d.in = lam[k]; d.out = P.hP[k].glam; })) != FEWHA_OK) return s;
+  enq_idwt(P, a, SRC_IN, OUT_USER, 0);
+  // term 0: Gamma^T C_hat^{-1} (s - A phi) against dA W^{-1} lambda
+  if ((s = stage([&](int k, IoDev& d) { d.in = slopes[k]; })) != FEWHA_OK) return s;
+  launch_slopes_in(a, T(P, P.pg), P.pg.n);
+  if ((s = stage([&](int k, IoDev& d) { d.in = P.hP[k].gphi; })) != FEWHA_OK) return s;
+  launch_pgamma(a, T(P, P.pg), P.pg.n, PG_RESID_IN);
+  launch_gammaT(a, T(P, P.gt), P.gt.n, GT_WEIGHTED);
+  launch_grad_height(a, T(P, P.ghgt), P.ghgt.n, 0);
+  // term 1: Gamma^T C_hat^{-1} A W^{-1} lambda against dA phi
+  if ((s = stage([&](int k, IoDev& d) { d.in = P.hP[k].glam; })) != FEWHA_OK) return s;
+  launch_pgamma(a, T(P, P.pg), P.pg.n, PG_DENSE_IN);
+  launch_gammaT(a, T(P, P.gt), P.gt.n, GT_WEIGHTED);
+  launch_grad_height(a, T(P, P.ghgt), P.ghgt.n, 1);
+  // prior terms and the fixed-order reductions
+  std::vector<GradIo> g(n);
+  for (int k = 0; k < n; ++k) g[k] = GradIo{c[k], lam[k], out[k]};
+  if ((s = upload_table(P, g, st, P.dGIO, err)) != FEWHA_OK) return s;
+  launch_grad_prior(a, P.dGIO, T(P, P.gprior), P.gprior.n);
+  launch_grad_final(a, P.dGIO, n);
+  HIP_TRY(hipGetLastError());
+  return FEWHA_OK;
 }
 
 }  // namespace
@@ -906,6 +1312,42 @@ fewha_status fewha_reconstruct(fewha_ctx* c, const float* slopes, float* state, 
   return finish(c);
 }
 
+fewha_status fewha_solve(fewha_ctx* c, const float* rhs, float* x, int max_iters, double rtol, int* iters_done,
+                         double* rel_res) {
+  fewha_status s = ready(c);
+  if (s != FEWHA_OK) return s;
+  if (!rhs) return fail(c, FEWHA_EINVAL, "solve: null rhs");
+  return run_solve(*c->plan, c->stream, {rhs}, {nullptr}, {nullptr}, {x}, max_iters, rtol, iters_done, rel_res,
+                   c->err);
+}
+
+fewha_status fewha_solve_map(fewha_ctx* c, const float* slopes, const float* g_layers, float* x, int max_iters,
+                             double rtol, int* iters_done, double* rel_res) {
+  fewha_status s = ready(c);
+  if (s != FEWHA_OK) return s;
+  return run_solve(*c->plan, c->stream, {nullptr}, {slopes}, {g_layers}, {x}, max_iters, rtol, iters_done, rel_res,
+                   c->err);
+}
+
+fewha_status fewha_apply_Winv(fewha_ctx* c, const float* coef, float* layers) {
+  fewha_status s = ready(c);
+  if (s != FEWHA_OK) return s;
+  return run_winv(*c->plan, c->stream, {coef}, {layers}, c->err);
+}
+
+fewha_status fewha_apply_WinvT(fewha_ctx* c, const float* layers, float* coef) {
+  fewha_status s = ready(c);
+  if (s != FEWHA_OK) return s;
+  return run_winvT(*c->plan, c->stream, {layers}, {coef}, c->err);
+}
+
+fewha_status fewha_param_grads(fewha_ctx* c, const float* slopes, const float* coef, const float* lam,
+                               double* grads) {
+  fewha_status s = ready(c);
+  if (s != FEWHA_OK) return s;
+  return run_param_grads(*c->plan, c->stream, {slopes}, {coef}, {lam}, {grads}, c->err);
+}
+
 // ---- batches ----
 
 static fewha_status bfail(fewha_batch* b, fewha_status s, const std::string& m) {
@@ -983,6 +1425,58 @@ fewha_status fewha_batch_reconstruct(fewha_batch* b, const float* const* slopes,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return bfail(b, FEWHA_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   return FEWHA_OK;
+}
+
+fewha_status fewha_batch_solve(fewha_batch* b, const float* const* rhs, float* const* x, int max_iters, double rtol,
+                               int* iters_done, double* rel_res) {
+  if (!b) return FEWHA_EINVAL;
+  if (!rhs || !x) return bfail(b, FEWHA_EINVAL, "batch_solve: null pointer array");
+  const int n = b->plan->nprob;
+  std::vector<const float*> vr(rhs, rhs + n), none(n, nullptr);
+  std::vector<float*> vx(x, x + n);
+  for (int k = 0; k < n; ++k)
+    if (!vr[k]) return bfail(b, FEWHA_EINVAL, "batch_solve: null rhs");
+  return run_solve(*b->plan, b->stream, vr, none, none, vx, max_iters, rtol, iters_done, rel_res, b->err);
+}
+
+fewha_status fewha_batch_solve_map(fewha_batch* b, const float* const* slopes, const float* const* g_layers,
+                                   float* const* x, int max_iters, double rtol, int* iters_done, double* rel_res) {
+  if (!b) return FEWHA_EINVAL;
+  if (!x) return bfail(b, FEWHA_EINVAL, "batch_solve_map: null x array");
+  const int n = b->plan->nprob;
+  std::vector<const float*> vs(n, nullptr), vg(n, nullptr), none(n, nullptr);
+  if (slopes) vs.assign(slopes, slopes + n);
+  if (g_layers) vg.assign(g_layers, g_layers + n);
+  std::vector<float*> vx(x, x + n);
+  return run_solve(*b->plan, b->stream, none, vs, vg, vx, max_iters, rtol, iters_done, rel_res, b->err);
+}
+
+fewha_status fewha_batch_apply_Winv(fewha_batch* b, const float* const* coef, float* const* layers) {
+  if (!b) return FEWHA_EINVAL;
+  if (!coef || !layers) return bfail(b, FEWHA_EINVAL, "batch_apply_Winv: null pointer array");
+  const int n = b->plan->nprob;
+  std::vector<const float*> vi(coef, coef + n);
+  std::vector<float*> vo(layers, layers + n);
+  return run_winv(*b->plan, b->stream, vi, vo, b->err);
+}
+
+fewha_status fewha_batch_apply_WinvT(fewha_batch* b, const float* const* layers, float* const* coef) {
+  if (!b) return FEWHA_EINVAL;
+  if (!coef || !layers) return bfail(b, FEWHA_EINVAL, "batch_apply_WinvT: null pointer array");
+  const int n = b->plan->nprob;
+  std::vector<const float*> vi(layers, layers + n);
+  std::vector<float*> vo(coef, coef + n);
+  return run_winvT(*b->plan, b->stream, vi, vo, b->err);
+}
+
+fewha_status fewha_batch_param_grads(fewha_batch* b, const float* const* slopes, const float* const* coef,
+                                     const float* const* lam, double* const* grads) {
+  if (!b) return FEWHA_EINVAL;
+  if (!slopes || !coef || !lam || !grads) return bfail(b, FEWHA_EINVAL, "batch_param_grads: null pointer array");
+  const int n = b->plan->nprob;
+  std::vector<const float*> vs(slopes, slopes + n), vc(coef, coef + n), vl(lam, lam + n);
+  std::vector<double*> vg(grads, grads + n);
+  return run_param_grads(*b->plan, b->stream, vs, vc, vl, vg, b->err);
 }
 
 fewha_status fewha_batch_time_stage(fewha_batch* b, int stage, int reps, double* avg_us, long* workgroups) {

@@ -18,6 +18,9 @@ constexpr int kResMax = 128;      // largest block kept resident in LDS by the D
 constexpr int kTileS = 16;        // subaperture / corner tile side of the sensor stages
 constexpr int kTileN = 32;        // node tile side of the propagation adjoint
 constexpr int kUpdChunk = 2048;   // coefficients per workgroup of the vector update
+constexpr int kDotRing = 256;     // PCG iterations whose inner products are kept (ring, power of two)
+constexpr int kGradChunk = 2048;  // coefficients per workgroup of the prior-term reductions
+constexpr double kTie = 1e-9;     // |t - round(t)| below which a sample sits on a grid line
 
 // db3 analysis filters, passed by value to the transform kernels.
 struct Filter {
@@ -34,6 +37,12 @@ struct LayerDev {
   int pad0;
   float inv_delta;            // 1 / delta_l
   float alpha_d[kMaxLevelsJ]; // alpha * D_j, j = log2(block side)
+  // parameter gradients
+  double d64[kMaxLevelsJ];    // D_j in FP64
+  double cn2;                 // gamma_l
+  int gp_off, gp_n;           // prior-term slots of this layer (from the start of the slot array)
+  int gh_off, gh_n;           // height-term slots of this layer (from the start of one term's range)
+  double inv_delta64;         // 1 / delta_l (residual in FP64)
 };
 
 // One sensor of one problem.
@@ -52,15 +61,23 @@ struct WfsDev {
   int tiles_side;       // tiles per side of the subaperture grid
   int tab_off;          // per layer: interp/adjacency tables at tab_off + l * tab_stride
   int tab_stride;
+  int gtab_off;         // per layer: derivative tables at gtab_off + l * 4 nc (gitab / gftab)
+  int pad0;
   float inv_sigma2;
   float inv_nM;
   float sum_cinv[4];    // sum over the mask of the 2x2 inverse blocks (row-major)
+  double inv_sigma2_d;  // FP64 copies for the residual of refined solves
+  double inv_nM_d;
 };
 
 // Per-(sensor, layer) table layout inside the int/float table arrays, relative
 // to WfsDev::tab_off + l * tab_stride (tab_stride = 4 nc):
 //   int   q0y[nc], q0x[nc]   bilinear cell of each corner row / column
 //   float wy[nc],  wx[nc]    fractional offsets (float slots [2nc, 4nc))
+// Derivative tables (gradient with respect to the layer height), relative to
+// WfsDev::gtab_off + l * 4 nc:
+//   int   qy[nc], qx[nc], tiey[nc], tiex[nc]   cell (the node itself on a grid line)
+//   float wy[nc], wx[nc], dty[nc], dtx[nc]     fraction (0 on a grid line), dt/dh
 
 // Propagation of one (sensor, layer) pair in node units: corner k of the
 // sensor sits at t = t0 + k rho along each axis (rho = cone factor x pitch /
@@ -104,6 +121,37 @@ struct ProbDev {
   const int* cmap;       // compact-index maps
   const float* cinv;     // 2x2 inverse noise blocks
   const GLPar* gl;       // [sensor][layer] propagation parameters
+  // parameter gradients
+  float* gphi;           // W^{-1} c
+  float* glam;           // W^{-1} lambda
+  double* gslots;        // [prior terms n_gp | height term 0 n_gh | height term 1 n_gh]
+  const int* gitab;      // derivative tables
+  const float* gftab;
+  int n_gp, n_gh;
+  double alpha;
+  // FP64 residual b - M x of refined solves
+  double* a64;           // N_c: coefficients -> layers -> adjoint -> coefficients
+  double* b64;           // N_c: pass scratch
+  double* sd64;          // dense slopes, as sd
+  double* u64;           // corner grids, as vadj
+  double* rslots;        // [upd slot][2]: sum r^2, sum b^2
+  const double* cinv64;  // 2x2 inverse noise blocks, as cinv
+  const double* ftab64;  // interpolation fractions, as ftab
+  float* rbuf;           // N_c: residual (right-hand side of a correction solve)
+  double* x64;           // N_c: the refined iterate
+};
+
+// db3 filters in FP64 for the residual transforms.
+struct Filter64 {
+  double h[6];
+  double g[6];
+};
+
+// Per-call pointers of the parameter-gradient reductions of one problem.
+struct GradIo {
+  const float* c;
+  const float* lam;
+  double* out;  // [g_alpha | g_cn2 (L) | g_h (L)]
 };
 
 // Per-call input/output pointers of one problem.
@@ -113,6 +161,8 @@ struct IoDev {
   float* state;        // [c | b | r | a_prev | a]
   float* layers_out;
   float* dm_out;
+  const float* rs;     // FP64 residual: slopes of the right-hand side W^{-T} A^T C_hat^{-1} s (or NULL)
+  const float* rg;     // FP64 residual: layer-domain term of the right-hand side W^{-T} g (or NULL)
 };
 
 // Work-list entry of a tiled stage: problem, item (layer or sensor), tile
@@ -142,6 +192,11 @@ struct LayerHost {
 struct GLTables {  // one (sensor, layer) pair
   std::vector<int> q0y, q0x;   // nc
   std::vector<double> wy, wx;  // nc
+};
+
+struct GradTables {  // one (sensor, layer) pair, derivative with respect to the layer height
+  std::vector<int> qy, qx, tiey, tiex;        // nc
+  std::vector<double> wy, wx, dty, dtx;       // nc
 };
 
 // DM fitting (Sec. 4.1, layers not at the DM altitudes): directions, DMs,
@@ -184,6 +239,9 @@ struct HostModel {
   // derived
   double h[6] = {0}, g[6] = {0};
   std::vector<std::vector<GLTables>> tab;  // [g][l]
+  std::vector<std::vector<GradTables>> gtab;  // [g][l]
+  bool grad_ok = true;                     // every derivative stencil stays inside its layer
+  std::string grad_msg;
   std::vector<double> Dprior;              // N_c
   std::vector<double> J;                   // N_c
   std::vector<int> layer_off;

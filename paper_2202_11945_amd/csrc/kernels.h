@@ -12,7 +12,11 @@ enum { OUT_PHI = 0, OUT_USER = 1, OUT_FIT = 2 };
 // epilogue of the forward transform
 enum { EPI_APPLYM = 0, EPI_PCG = 1, EPI_RHS = 2, EPI_PLAIN = 3 };
 // propagation + Shack-Hartmann output
-enum { PG_COMPACT = 0, PG_DENSE = 1 };
+//   PG_COMPACT : io.in -> compact slopes in io.out      (A x)
+//   PG_DENSE   : phi -> dense slopes + tip/tilt partials (inside M)
+//   PG_DENSE_IN: io.in -> dense slopes + partials
+//   PG_RESID_IN: dense slopes -= Gamma P io.in, + partials (data residual s - A x)
+enum { PG_COMPACT = 0, PG_DENSE = 1, PG_DENSE_IN = 2, PG_RESID_IN = 3 };
 // Shack-Hartmann adjoint weighting
 enum { GT_PLAIN = 0, GT_WEIGHTED = 1 };
 // propagation adjoint destination
@@ -39,6 +43,33 @@ void launch_slopes_in(const LaunchArgs& a, const Tile* tiles, int ntiles);
 void launch_gammaT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode);
 void launch_pT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode);
 void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter);
+void launch_solve_init(const LaunchArgs& a, const Tile* tiles, int ntiles);
+void launch_grad_height(const LaunchArgs& a, const Tile* tiles, int ntiles, int term);
+void launch_grad_prior(const LaunchArgs& a, const GradIo* g, const Tile* tiles, int ntiles);
+void launch_grad_final(const LaunchArgs& a, const GradIo* g, int nprob);
+// Work lists of the FP64 residual chain (residual64.hip).
+struct Resid64Tiles {
+  const Tile* upd = nullptr;             // coefficient chunks (the vector-update list)
+  int upd_n = 0;
+  int n_steps = 0;                       // transform levels (max over layers)
+  const Tile* inv[kMaxLevelsJ] = {};     // synthesis step s: blocks of side (n >> levels) << (s + 1)
+  int inv_n[kMaxLevelsJ] = {};
+  const Tile* fwd[kMaxLevelsJ] = {};     // analysis step s: blocks of side n >> s
+  int fwd_n[kMaxLevelsJ] = {};
+  const Tile* pg = nullptr;              // subaperture tiles
+  int pg_n = 0;
+  const Tile* wfs = nullptr;             // one per (problem, sensor)
+  int wfs_n = 0;
+  const Tile* gt = nullptr;              // corner tiles
+  int gt_n = 0;
+  const Tile* pt = nullptr;              // node tiles
+  int pt_n = 0;
+};
+
+// r = b - M x64 in FP64 (io.in = b, io.out = r) + partial sums of r^2, b^2
+void launch64_resid_chain(const LaunchArgs& a, const Resid64Tiles& rt, const Filter64& F);
+// x64 = 0 (mode 0), x64 += io.in (1), io.state = (float) x64 (2)
+void launch64_iterate(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode);
 void launch_fit_fwd(const LaunchArgs& a, const Tile* tiles, int ntiles);
 void launch_fit_cg(const LaunchArgs& a, const FitDev* F, int nfit, int phase);
 

@@ -63,6 +63,10 @@ __device__ __forceinline__ const double* dot_group(const ProbDev& pr, int g) {
 __device__ __forceinline__ int rho_count(const ProbDev& pr, int k) {
   return k == 0 ? pr.n_slots_fdwt : pr.n_slots_upd;
 }
+// Dot groups of iteration k in a ring of kDotRing iterations: rho_k = r_k^T J^{-1} r_k
+// and pi_k = p_k^T M p_k (each step reads only the current and previous iteration).
+__device__ __forceinline__ int rho_grp(int k) { return 2 * (k & (kDotRing - 1)); }
+__device__ __forceinline__ int pi_grp(int k) { return 2 * (k & (kDotRing - 1)) + 1; }
 
 // Search-direction source of the inverse transform (fused p update).
 struct PSrc {
@@ -113,8 +117,8 @@ __device__ __forceinline__ float coef_finish(const PSrc& s, int e, const CoefLoa
 // beta_k = rho_k / rho_{k-1}, summed by wave 0 and broadcast through LDS
 __device__ __forceinline__ float compute_beta(const ProbDev& pr, int mode, int iter, double* sb) {
   if (mode == SRC_PUPD && threadIdx.x < 64) {
-    const double rk = wave_sum_slots(dot_group(pr, 2 * iter), rho_count(pr, iter));
-    const double rkm = wave_sum_slots(dot_group(pr, 2 * (iter - 1)), rho_count(pr, iter - 1));
+    const double rk = wave_sum_slots(dot_group(pr, rho_grp(iter)), rho_count(pr, iter));
+    const double rkm = wave_sum_slots(dot_group(pr, rho_grp(iter - 1)), rho_count(pr, iter - 1));
     if (threadIdx.x == 0) *sb = (rkm != 0.0) ? rk / rkm : 0.0;
   } else if (threadIdx.x == 0) {
     *sb = 0.0;
@@ -194,7 +198,7 @@ __device__ __forceinline__ void epi_finish(const ProbDev& pr, const LayerDev& ly
   }
 }
 
-__device__ __forceinline__ int dot_group_of(int epi, int iter) { return epi == EPI_PCG ? 2 * iter + 1 : 0; }
+__device__ __forceinline__ int dot_group_of(int epi, int iter) { return epi == EPI_PCG ? pi_grp(iter) : 0; }
 
 constexpr int kU = 4;  // elements per thread with loads in flight together
 
@@ -611,7 +615,7 @@ __global__ __launch_bounds__(256) void k_pgamma(const ProbDev* P, const LayerDev
   const ProbDev& pr = P[t.prob];
   const WfsDev& w = WD[pr.wfs0 + t.item];
   const IoDev& io = IO[t.prob];
-  const float* phi = (mode == PG_COMPACT) ? io.in : pr.phi;
+  const float* phi = (mode == PG_DENSE) ? pr.phi : io.in;
   const int N = w.N, nc = w.nc;
   const int i0 = t.ty * kTileS, j0 = t.tx * kTileS;
   constexpr int CW = kTileS + 1;
@@ -650,6 +654,10 @@ __global__ __launch_bounds__(256) void k_pgamma(const ProbDev* P, const LayerDev
     const float v10 = V[(li + 1) * CW + lj], v11 = V[(li + 1) * CW + lj + 1];
     sx = 0.5f * ((v01 - v00) + (v11 - v10));
     sy = 0.5f * ((v10 - v00) + (v11 - v01));
+    if (mode == PG_RESID_IN) {  // data residual s - A phi (s placed by the slopes input kernel)
+      sx = pr.sd[w.s_off + i * N + j] - sx;
+      sy = pr.sd[w.s_off + N * N + i * N + j] - sy;
+    }
     if (w.blocks) {
       const float* cb = pr.cinv + w.cinv_off + 3 * (i * N + j);
       cx = cb[0] * sx + cb[1] * sy;
@@ -944,8 +952,8 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
   const ProbDev& pr = P[t.prob];
   const IoDev& io = IO[t.prob];
   if (threadIdx.x < 64) {
-    const double rho = wave_sum_slots(dot_group(pr, 2 * iter), rho_count(pr, iter));
-    const double pi = wave_sum_slots(dot_group(pr, 2 * iter + 1), pr.n_slots_fdwt);
+    const double rho = wave_sum_slots(dot_group(pr, rho_grp(iter)), rho_count(pr, iter));
+    const double pi = wave_sum_slots(dot_group(pr, pi_grp(iter)), pr.n_slots_fdwt);
     if (threadIdx.x == 0) salpha = (pi > 0.0) ? rho / pi : 0.0;
   }
   __syncthreads();
@@ -993,7 +1001,123 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
     }
   }
   const double s = block_sum(acc, sh, blockDim.x);
-  if (threadIdx.x == 0) pr.dots[(long)(2 * (iter + 1)) * pr.n_dots + t.slot] = s;
+  if (threadIdx.x == 0) pr.dots[(long)rho_grp(iter + 1) * pr.n_dots + t.slot] = s;
+}
+
+// ------------------------------------------------- PCG run to a tolerance
+// Start of a solve M x = b from x = 0: x = 0, r = b and the partials of
+// rho_0 = b^T J^{-1} b.  One workgroup per producer slot of rho_0 (the forward
+// transform's count), each over a contiguous float4 range.
+__global__ __launch_bounds__(256) void k_solve_init(const ProbDev* P, const IoDev* IO, const Tile* tiles) {
+  __shared__ double sh[4];
+  const Tile t = tiles[blockIdx.x];
+  const ProbDev& pr = P[t.prob];
+  const IoDev& io = IO[t.prob];
+  const int n4 = pr.n_c / 4, ns = pr.n_slots_fdwt;
+  const int chunk = (n4 + ns - 1) / ns;
+  const int e0 = t.slot * chunk, e1 = min(e0 + chunk, n4);
+  const float4* b = (const float4*)io.in;
+  const float4* jv = (const float4*)pr.jinv;
+  float4* x = (float4*)io.state;
+  float4* r = (float4*)(io.state + 2L * pr.n_c);
+  double acc = 0.0;
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
+    const float4 v = b[e], j = jv[e];
+    x[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    r[e] = v;
+    acc += (double)v.x * (double)v.x * (double)j.x + (double)v.y * (double)v.y * (double)j.y +
+           (double)v.z * (double)v.z * (double)j.z + (double)v.w * (double)v.w * (double)j.w;
+  }
+  const double s = block_sum(acc, sh, blockDim.x);
+  if (threadIdx.x == 0) pr.dots[(long)rho_grp(0) * pr.n_dots + t.slot] = s;
+}
+
+// ------------------------------------------------- parameter gradients
+// Height term of one (sensor, layer) pair over a 16x16 corner tile:
+//   sum_corners u(i, j) * d/dh [P_gl v](i, j)
+// with u = Gamma^T C_hat^{-1} (...) in the corner-grid buffer and v = W^{-1} lambda
+// (term 0) or W^{-1} c (term 1).  d/dh of the bilinear sample is
+// dt_x/dh d/dt_x + dt_y/dh d/dt_y; on a grid line the derivative along that
+// axis is the central difference (average of the one-sided ones).
+__global__ __launch_bounds__(256) void k_grad_height(const ProbDev* P, const LayerDev* LD, const WfsDev* WD,
+                                                     const Tile* tiles, int term) {
+  __shared__ double sh[4];
+  const Tile t = tiles[blockIdx.x];
+  const ProbDev& pr = P[t.prob];
+  const WfsDev& w = WD[pr.wfs0 + t.item];
+  const int l = t.level;
+  const LayerDev& ly = LD[pr.layer0 + l];
+  const float* v = (term == 0 ? pr.glam : pr.gphi) + ly.off;
+  const int nc = w.nc, n = ly.n;
+  const int i = t.ty * kTileS + (threadIdx.x >> 4), j = t.tx * kTileS + (threadIdx.x & 15);
+  double acc = 0.0;
+  if (i < nc && j < nc) {
+    const int base = w.gtab_off + l * 4 * nc;
+    const int* it = pr.gitab + base;
+    const float* ft = pr.gftab + base;
+    const int qy = it[i], qx = it[nc + j], tiey = it[2 * nc + i], tiex = it[3 * nc + j];
+    const float wy = ft[i], wx = ft[nc + j], dty = ft[2 * nc + i], dtx = ft[3 * nc + j];
+    // along x on row rr: slope (central on a grid line) and the sample value
+    auto slope_x = [&](int rr) {
+      const float* row = v + rr * n + qx;
+      return tiex ? 0.5f * (row[1] - row[-1]) : row[1] - row[0];
+    };
+    auto value_x = [&](int rr) { return v[rr * n + qx] + wx * slope_x(rr); };
+    float ddx, ddy;
+    if (tiey) {
+      ddx = slope_x(qy);
+      ddy = 0.5f * (value_x(qy + 1) - value_x(qy - 1));
+    } else {
+      ddx = (1.f - wy) * slope_x(qy) + wy * slope_x(qy + 1);
+      ddy = value_x(qy + 1) - value_x(qy);
+    }
+    const float d = dtx * ddx + dty * ddy;
+    acc = (double)pr.vadj[w.v_off + i * nc + j] * (double)d;
+  }
+  const double s = block_sum(acc, sh, blockDim.x);
+  if (threadIdx.x == 0) pr.gslots[pr.n_gp + term * pr.n_gh + t.slot] = s;
+}
+
+// Prior term of one layer over a chunk of coefficients: sum lambda_e D_e c_e.
+__global__ __launch_bounds__(256) void k_grad_prior(const ProbDev* P, const LayerDev* LD, const GradIo* GIO,
+                                                    const Tile* tiles) {
+  __shared__ double sh[4];
+  const Tile t = tiles[blockIdx.x];
+  const ProbDev& pr = P[t.prob];
+  const LayerDev& ly = LD[pr.layer0 + t.item];
+  const GradIo& g = GIO[t.prob];
+  const int n = ly.n, nn = n * n;
+  const int m0 = n >> ly.levels, jmin = ly.log2n - ly.levels;
+  const int e0 = t.ty * kGradChunk, e1 = min(e0 + kGradChunk, nn);
+  double acc = 0.0;
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
+    const int r = e >> ly.log2n, c = e & (n - 1), mx = max(r, c);
+    const int j = (mx < m0) ? jmin : 31 - __clz(mx);
+    acc += (double)g.lam[ly.off + e] * (double)g.c[ly.off + e] * ly.d64[j];
+  }
+  const double s = block_sum(acc, sh, blockDim.x);
+  if (threadIdx.x == 0) pr.gslots[ly.gp_off + t.ty] = s;
+}
+
+// One wave per problem: fixed-order sums of the slots into
+//   g_alpha = -sum_l t_l,  g_gamma_l = alpha t_l / gamma_l,  g_h_l = term0_l - term1_l
+// with t_l = lambda_l^T D_l c_l.
+__global__ __launch_bounds__(64) void k_grad_final(const ProbDev* P, const LayerDev* LD, const GradIo* GIO) {
+  const ProbDev& pr = P[blockIdx.x];
+  const GradIo& g = GIO[blockIdx.x];
+  double ta = 0.0;
+  for (int l = 0; l < pr.L; ++l) {
+    const LayerDev& ly = LD[pr.layer0 + l];
+    const double tl = wave_sum_slots(pr.gslots + ly.gp_off, ly.gp_n);
+    const double h0 = wave_sum_slots(pr.gslots + pr.n_gp + ly.gh_off, ly.gh_n);
+    const double h1 = wave_sum_slots(pr.gslots + pr.n_gp + pr.n_gh + ly.gh_off, ly.gh_n);
+    ta += tl;
+    if (threadIdx.x == 0) {
+      g.out[1 + l] = pr.alpha * tl / ly.cn2;
+      g.out[1 + pr.L + l] = h0 - h1;
+    }
+  }
+  if (threadIdx.x == 0) g.out[0] = -ta;
 }
 
 // ------------------------------------------------------------ DM fitting
@@ -1121,6 +1245,18 @@ void launch_pT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
 }
 void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter) {
   if (ntiles > 0) k_update<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles, iter);
+}
+void launch_solve_init(const LaunchArgs& a, const Tile* tiles, int ntiles) {
+  if (ntiles > 0) k_solve_init<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles);
+}
+void launch_grad_height(const LaunchArgs& a, const Tile* tiles, int ntiles, int term) {
+  if (ntiles > 0) k_grad_height<<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, tiles, term);
+}
+void launch_grad_prior(const LaunchArgs& a, const GradIo* g, const Tile* tiles, int ntiles) {
+  if (ntiles > 0) k_grad_prior<<<ntiles, 256, 0, a.stream>>>(a.P, a.L, g, tiles);
+}
+void launch_grad_final(const LaunchArgs& a, const GradIo* g, int nprob) {
+  if (nprob > 0) k_grad_final<<<nprob, 64, 0, a.stream>>>(a.P, a.L, g);
 }
 void launch_fit_fwd(const LaunchArgs& a, const Tile* tiles, int ntiles) {
   if (ntiles > 0) k_fit_fwd<<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, tiles);

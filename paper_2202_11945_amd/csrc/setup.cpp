@@ -219,6 +219,52 @@ fewha_status build_model(HostModel& m, std::string& err) {
     }
   }
 
+  // ---- derivative of the propagation with respect to the layer height ----
+  // t(h) = (c(h) x + h theta + L/2) / delta with c = 1 - h/H (LGS) or 1, so
+  // dt/dh = (theta - x/H) / delta or theta / delta.  On a grid line the
+  // bilinear interpolant has no derivative; the average of the two one-sided
+  // derivatives is used (the cell is centred on the node).
+  m.gtab.assign(G, std::vector<GradTables>(L));
+  m.grad_ok = true;
+  m.grad_msg.clear();
+  for (int gi = 0; gi < G; ++gi) {
+    const WfsHost& w = m.wfs[gi];
+    const int N = w.d.n_subap, nc = N + 1;
+    const bool lgs = w.d.kind == FEWHA_LGS;
+    for (int l = 0; l < L; ++l) {
+      const LayerHost& lh = m.layers[l];
+      const int n = lh.d.n;
+      const double hgt = lh.d.h;
+      const double scale = lgs ? 1.0 - hgt / w.d.H : 1.0;
+      GradTables& t = m.gtab[gi][l];
+      for (auto* v : {&t.qy, &t.qx, &t.tiey, &t.tiex}) v->assign(nc, 0);
+      for (auto* v : {&t.wy, &t.wx, &t.dty, &t.dtx}) v->assign(nc, 0.0);
+      for (int j = 0; j < nc; ++j) {
+        const double x = -0.5 * D + j * (D / N);
+        const double th[2] = {w.d.theta_x, w.d.theta_y};
+        for (int ax = 0; ax < 2; ++ax) {
+          const double tt = (scale * x + hgt * th[ax] + 0.5 * m.L) / lh.delta;
+          const double r = std::nearbyint(tt);
+          const bool tie = std::fabs(tt - r) < kTie;
+          const int q = tie ? (int)r : (int)std::floor(tt);
+          const double wf = tie ? 0.0 : tt - std::floor(tt);
+          const double dt = ((lgs ? -x / w.d.H : 0.0) + th[ax]) / lh.delta;
+          if ((tie && (q < 1 || q > n - 2)) || (!tie && (q < 0 || q > n - 2))) {
+            if (m.grad_ok) {
+              std::snprintf(buf, sizeof buf, "sensor %d: height-derivative stencil leaves layer %d", gi, l);
+              m.grad_msg = buf;
+            }
+            m.grad_ok = false;
+          }
+          (ax == 0 ? t.qx : t.qy)[j] = q;
+          (ax == 0 ? t.tiex : t.tiey)[j] = tie ? 1 : 0;
+          (ax == 0 ? t.wx : t.wy)[j] = wf;
+          (ax == 0 ? t.dtx : t.dty)[j] = dt;
+        }
+      }
+    }
+  }
+
   // ---- DM fitting: pupil corners, propagation tables, regularisation ----
   if (m.fit.on) {
     FitHost& f = m.fit;

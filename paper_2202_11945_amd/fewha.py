@@ -4,7 +4,7 @@ argument marshalling lives here; torch supplies device memory and streams.
 """
 
 import ctypes
-from ctypes import byref, c_double, c_long, c_void_p
+from ctypes import byref, c_double, c_int, c_long, c_void_p
 
 import numpy as np
 
@@ -31,6 +31,14 @@ def _ptr(t, n=None, dtype=None):
         raise ValueError("expected a contiguous float32 device tensor")
     if n is not None and t.numel() < n:
         raise ValueError("tensor too small: %d < %d" % (t.numel(), n))
+    return c_void_p(t.data_ptr())
+
+
+def _ptr64(t, n):
+    """Device pointer of a contiguous CUDA float64 tensor of at least n entries."""
+    import torch
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() < n:
+        raise ValueError("expected a contiguous float64 device tensor of %d entries" % n)
     return c_void_p(t.data_ptr())
 
 
@@ -156,7 +164,56 @@ class Context:
                                       _ptr(layers_out, self.n_coeff), _ptr(dm_out, self.n_act), int(iters)),
                self.h)
 
+    def fewha_solve(self, rhs, x=None, max_iters=1 << 20, rtol=1e-6):
+        """x = M^{-1} rhs by PCG from 0 to a relative J^{-1}-norm residual
+        rtol; returns (x, iterations, residual ratio)."""
+        x = self._new(self.n_coeff) if x is None else x
+        it, rel = c_int(), c_double()
+        self._sync_stream()
+        _check(_abi.fewha_solve(self.h, _ptr(rhs, self.n_coeff), _ptr(x, self.n_coeff), int(max_iters),
+                                float(rtol), byref(it), byref(rel)), self.h)
+        return x, it.value, rel.value
+
+    def fewha_solve_map(self, slopes=None, g_layers=None, x=None, max_iters=1 << 20, rtol=1e-6):
+        """x = M^{-1} W^{-T} (A^T C_hat^{-1} slopes + g_layers) (either term may
+        be None), the right-hand side formed in double precision; returns
+        (x, iterations, residual ratio)."""
+        x = self._new(self.n_coeff) if x is None else x
+        it, rel = c_int(), c_double()
+        self._sync_stream()
+        _check(_abi.fewha_solve_map(self.h, _ptr(slopes, self.n_slopes), _ptr(g_layers, self.n_coeff),
+                                    _ptr(x, self.n_coeff), int(max_iters), float(rtol), byref(it), byref(rel)),
+               self.h)
+        return x, it.value, rel.value
+
+    def fewha_apply_Winv(self, coef, out=None):
+        out = self._new(self.n_coeff) if out is None else out
+        self._sync_stream()
+        _check(_abi.fewha_apply_Winv(self.h, _ptr(coef, self.n_coeff), _ptr(out, self.n_coeff)), self.h)
+        return out
+
+    def fewha_apply_WinvT(self, layers, out=None):
+        out = self._new(self.n_coeff) if out is None else out
+        self._sync_stream()
+        _check(_abi.fewha_apply_WinvT(self.h, _ptr(layers, self.n_coeff), _ptr(out, self.n_coeff)), self.h)
+        return out
+
+    def fewha_param_grads(self, slopes, coef, lam, out=None):
+        """[dL/dalpha, dL/dgamma_l (L), dL/dh_l (L)] through c* (float64 tensor)."""
+        import torch
+        n = 1 + 2 * len(self.cfg["layers"])
+        out = torch.empty(n, dtype=torch.float64, device="cuda:%d" % self.device) if out is None else out
+        self._sync_stream()
+        _check(_abi.fewha_param_grads(self.h, _ptr(slopes, self.n_slopes), _ptr(coef, self.n_coeff),
+                                      _ptr(lam, self.n_coeff), _ptr64(out, n)), self.h)
+        return out
+
     # short aliases
+    solve = fewha_solve
+    solve_map = fewha_solve_map
+    apply_Winv = fewha_apply_Winv
+    apply_WinvT = fewha_apply_WinvT
+    param_grads = fewha_param_grads
     apply_A = fewha_apply_A
     apply_AT = fewha_apply_AT
     apply_M = fewha_apply_M
@@ -203,5 +260,68 @@ class Batch:
                batch_handle=self.h)
         return us.value, wg.value
 
+    def _arr(self, ts, sizes, conv=_ptr):
+        n = len(self.ctxs)
+        if len(ts) != n:
+            raise ValueError("expected %d tensors, got %d" % (n, len(ts)))
+        return (c_void_p * n)(*[conv(t, s).value for t, s in zip(ts, sizes)])
+
+    def _new_list(self, attr):
+        return [c._new(getattr(c, attr)) for c in self.ctxs]
+
+    def fewha_batch_solve(self, rhs, x=None, max_iters=1 << 20, rtol=1e-6):
+        """fewha_solve for every problem; iterates until all meet rtol."""
+        x = self._new_list("n_coeff") if x is None else x
+        nc = [c.n_coeff for c in self.ctxs]
+        it, rel = c_int(), c_double()
+        _check(_abi.fewha_batch_set_stream(self.h, _stream()), batch_handle=self.h)
+        _check(_abi.fewha_batch_solve(self.h, self._arr(rhs, nc), self._arr(x, nc), int(max_iters), float(rtol),
+                                      byref(it), byref(rel)), batch_handle=self.h)
+        return x, it.value, rel.value
+
+    def fewha_batch_solve_map(self, slopes=None, g_layers=None, x=None, max_iters=1 << 20, rtol=1e-6):
+        """fewha_solve_map for every problem (lists of tensors, or None)."""
+        x = self._new_list("n_coeff") if x is None else x
+        nc = [c.n_coeff for c in self.ctxs]
+        it, rel = c_int(), c_double()
+        sl = None if slopes is None else self._arr(slopes, [c.n_slopes for c in self.ctxs])
+        gl = None if g_layers is None else self._arr(g_layers, nc)
+        _check(_abi.fewha_batch_set_stream(self.h, _stream()), batch_handle=self.h)
+        _check(_abi.fewha_batch_solve_map(self.h, sl, gl, self._arr(x, nc), int(max_iters), float(rtol),
+                                          byref(it), byref(rel)), batch_handle=self.h)
+        return x, it.value, rel.value
+
+    def fewha_batch_apply_Winv(self, coef, out=None):
+        out = self._new_list("n_coeff") if out is None else out
+        nc = [c.n_coeff for c in self.ctxs]
+        _check(_abi.fewha_batch_set_stream(self.h, _stream()), batch_handle=self.h)
+        _check(_abi.fewha_batch_apply_Winv(self.h, self._arr(coef, nc), self._arr(out, nc)), batch_handle=self.h)
+        return out
+
+    def fewha_batch_apply_WinvT(self, layers, out=None):
+        out = self._new_list("n_coeff") if out is None else out
+        nc = [c.n_coeff for c in self.ctxs]
+        _check(_abi.fewha_batch_set_stream(self.h, _stream()), batch_handle=self.h)
+        _check(_abi.fewha_batch_apply_WinvT(self.h, self._arr(layers, nc), self._arr(out, nc)),
+               batch_handle=self.h)
+        return out
+
+    def fewha_batch_param_grads(self, slopes, coef, lam, out=None):
+        import torch
+        ng = [1 + 2 * len(c.cfg["layers"]) for c in self.ctxs]
+        if out is None:
+            out = [torch.empty(n, dtype=torch.float64, device="cuda:%d" % c.device) for n, c in zip(ng, self.ctxs)]
+        nc = [c.n_coeff for c in self.ctxs]
+        _check(_abi.fewha_batch_set_stream(self.h, _stream()), batch_handle=self.h)
+        _check(_abi.fewha_batch_param_grads(self.h, self._arr(slopes, [c.n_slopes for c in self.ctxs]),
+                                            self._arr(coef, nc), self._arr(lam, nc),
+                                            self._arr(out, ng, _ptr64)), batch_handle=self.h)
+        return out
+
     reconstruct = fewha_batch_reconstruct
     time_stage = fewha_batch_time_stage
+    solve = fewha_batch_solve
+    solve_map = fewha_batch_solve_map
+    apply_Winv = fewha_batch_apply_Winv
+    apply_WinvT = fewha_batch_apply_WinvT
+    param_grads = fewha_batch_param_grads

@@ -12,6 +12,7 @@ from .configs import (  # noqa: F401
     ARCSEC,
     CONFIGS,
     get_config,
+    truth_of,
 )
 from .inputs import (  # noqa: F401
     frozen_flow_frames,

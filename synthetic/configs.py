@@ -209,6 +209,37 @@ def small_fit():
     return cfg
 
 
+def grad_small():
+    """``small`` with the science field of the gradient loss: a 5 x 5 grid of
+    directions over +-20" (the guide-star field of this 8 m system)."""
+    cfg = small()
+    cfg["name"] = "grad_small"
+    cfg["science_half"] = 20.0 * ARCSEC
+    return cfg
+
+
+def grad_maory():
+    """MAORY-like geometry with the science field of the gradient loss: a
+    5 x 5 grid of directions over a 2' field (+-60")."""
+    cfg = maory_like()
+    cfg["name"] = "grad_maory"
+    cfg["science_half"] = 60.0 * ARCSEC
+    return cfg
+
+
+def truth_of(cfg):
+    """The atmosphere that generates the data of a gradient workload: the
+    reconstruction's layers moved up by 2 % (the ground layer stays) and the
+    Cn2 weights tilted by +-30 % and renormalised."""
+    t = copy.deepcopy(cfg)
+    w = [l["cn2"] * (1.3 if k % 2 == 0 else 0.7) for k, l in enumerate(t["layers"])]
+    for l, wk in zip(t["layers"], w):
+        l["h"] = 1.02 * l["h"]
+        l["cn2"] = wk / sum(w)
+    t["name"] = cfg["name"] + "_truth"
+    return t
+
+
 CONFIGS = {
     "tiny": tiny,
     "small": small,
@@ -218,6 +249,8 @@ CONFIGS = {
     "vlt_like": vlt_like,
     "large": large,
     "small_fit": small_fit,
+    "grad_small": grad_small,
+    "grad_maory": grad_maory,
 }
 
 

@@ -33,7 +33,7 @@ def systems():
 def _ensure_built():
     here = os.path.join(ROOT, "paper_2202_11945_amd", "lib", "libfewha.so")
     if not os.path.exists(here):
-        from paper_2202_11945_amd.build import build
+        from __graft_entry__ import build
         build()
 
 

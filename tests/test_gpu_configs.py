@@ -64,7 +64,10 @@ def test_vlt_like_geometry(gpu_lib):
 
 
 def test_large_nine_layers_with_elongation(gpu_lib):
+    # the frame with F = I (the fitted frame of this system is covered with the fitting tests)
     cfg = get_config("large")
+    cfg.pop("dms")
+    cfg.pop("fit")
     S = system("large", cfg)
     ctx = _ops(gpu_lib, S, cfg, 4)
     _check_frame(gpu_lib, S, ctx, np.zeros(5 * S.geom.n_coeff, np.float32), synth_slopes(S, 0))
