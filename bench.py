@@ -38,6 +38,9 @@ def parse():
     p.add_argument("--iters", type=int, default=4)
     p.add_argument("--pool", type=int, default=8, help="distinct input frames per sequence")
     p.add_argument("--latency-frames", type=int, default=200)
+    p.add_argument("--no-tune", action="store_true", help="default launch shapes instead of the autotuner's")
+    p.add_argument("--grad-frames", type=int, default=16,
+                   help="frames of the forward + implicit-backward leg (0 = skip)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
@@ -129,6 +132,35 @@ def measured_traffic(stage, batch):
     return None
 
 
+def gradient_leg(fw, pool, n_frames, rtol=1e-6):
+    """Forward + implicit backward of the differentiated reconstruction on
+    MAORY-like geometry: n_frames frames per batch, both solves refined to
+    rtol, a fixed random upstream gradient dL/dphi."""
+    import torch
+    from paper_2202_11945_amd.autograd import FrameBatch, MAPLayers, param_vector
+    from synthetic import get_config, random_vector
+    cfg = get_config("grad_maory")
+    fb = FrameBatch(cfg, n_frames)
+    slopes = torch.stack([pool[k % len(pool)][0] for k in range(n_frames)])
+    g = torch.from_numpy(random_vector(n_frames * fb.ctx.n_coeff, 77).reshape(n_frames, -1) * 1e-3).cuda()
+    params = param_vector(cfg).requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phi = MAPLayers.apply(params, slopes, fb, rtol)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phi.backward(g)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fb.close()
+    print("[bench] gradient leg: forward %.1f ms, backward %.1f ms" % ((t1 - t0) * 1e3, (t2 - t1) * 1e3),
+          file=sys.stderr, flush=True)
+    return {"workload": "MAORY-like geometry, %d frames per batch, forward and adjoint solves refined to a "
+                        "relative residual %g" % (n_frames, rtol),
+            "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
+            "grad": [float(v) for v in params.grad]}
+
+
 def main():
     args = parse()
     if args.cpu_child:
@@ -177,8 +209,14 @@ def main():
     torch.cuda.synchronize()
     print("[bench] inputs generated in %.1f s" % (time.time() - t_in), file=sys.stderr, flush=True)
 
+    # ---- launch shapes from the autotuner (cached per device and shapes) ----
+    from paper_2202_11945_amd import autotune
+    tune_b = autotune.tune(ctxs, args.iters) if not args.no_tune else {"dwt_resident": 128, "cached": None}
+    tune_1 = autotune.tune([c0], args.iters) if not args.no_tune else {"dwt_resident": 128, "cached": None}
+    print("[bench] tuning: batch %s, single %s" % (tune_b, tune_1), file=sys.stderr, flush=True)
+
     # ---- batched graph path: the timed workload ----
-    batch = fw.Batch(ctxs)
+    batch = fw.Batch(ctxs, tuning=tune_b["dwt_resident"])
     states = [torch.zeros(c.n_state, device=dev) for c in ctxs]
 
     def step(i, use_graph=True):
@@ -208,7 +246,7 @@ def main():
     dt_nograph = (time.perf_counter() - t0) / nd
 
     # ---- single-frame latency: graph path (batch of one) and plain path ----
-    single = fw.Batch([c0])
+    single = fw.Batch([c0], tuning=tune_1["dwt_resident"])
     st1 = torch.zeros(c0.n_state, device=dev)
     lay1 = torch.empty(c0.n_coeff, device=dev)
     nf = args.latency_frames
@@ -263,6 +301,8 @@ def main():
     achieved = dom_bytes / (stage_us[dom][0] * 1e-6) / 1e9
     traffic = measured_traffic(dom, B)
 
+    grad = None if args.grad_frames <= 0 else gradient_leg(fw, pool, args.grad_frames)
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
 
     out = {
@@ -288,6 +328,8 @@ def main():
         "batched_nograph_frames_per_s": B / dt_nograph,
         "plain_path_frames_per_s": plain_fps,
         "speedup_vs_plain": value / plain_fps,
+        "tuning": {"batch": tune_b, "single_frame": tune_1},
+        "gradient": grad,
         "stage_us": {k: round(v[0], 3) for k, v in stage_us.items()},
         "stage_workgroups": {k: v[1] for k, v in stage_us.items()},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -236,7 +236,7 @@ FEWHA_API fewha_status fewha_apply_WinvT(fewha_ctx* ctx, const float* layers, fl
  *                                 - <C_hat^{-1} A W^{-1} lambda, dA_l phi>
  * with dA_l = dA/dh_l (propagation P_g of Sec. 2, LGS cone factor 1 - h/H,
  * differentiated in h; on a grid line the average of the two one-sided
- * derivatives) and D the diagonal prior (Sec. 3.3), scaling as 1/gamma_l.
+ * derivatives) and D the diagonal prior (Sec. 3.1), scaling as 1/gamma_l.
  * Only the dependence through c* is included: a loss that itself depends on
  * the heights adds its own explicit term.  FEWHA_EGEOM when a derivative
  * stencil would leave its layer.  Inner products are accumulated in double
@@ -295,6 +295,26 @@ FEWHA_API fewha_status fewha_batch_time_stage(fewha_batch* b, int stage, int rep
                                               long* workgroups);
 
 FEWHA_API void fewha_batch_destroy(fewha_batch* b);
+
+/* ---- tuning: launch shapes chosen per plan (by an autotuner or by hand) ---- */
+
+/* dwt_resident: side of the largest transform block kept in one workgroup's
+ * LDS by the resident DWT kernels (32, 64 or 128; 0 = default 128).  Levels
+ * above it run as tiled passes over global memory, one launch per level.
+ * Smaller values trade LDS work per workgroup for more workgroups and more
+ * launches.  It must be at least every layer's coarsest block (n >> levels),
+ * else FEWHA_EINVAL when the plan is built.  reserved: zero. */
+typedef struct {
+  int dwt_resident;
+  int reserved[7];
+} fewha_tuning;
+
+/* Tuning of a context's own plan; before fewha_finalize. */
+FEWHA_API fewha_status fewha_set_tuning(fewha_ctx* ctx, const fewha_tuning* t);
+
+/* fewha_batch_create with the batch plan's tuning (NULL = defaults). */
+FEWHA_API fewha_status fewha_batch_create_tuned(fewha_batch** out, fewha_ctx* const* ctxs, int n,
+                                                const fewha_tuning* t);
 
 /* Last error message of a context (never NULL). */
 FEWHA_API const char* fewha_last_error(const fewha_ctx* ctx);

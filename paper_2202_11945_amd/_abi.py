@@ -33,6 +33,10 @@ class fewha_dm_desc(ctypes.Structure):
     _fields_ = [("h", c_double), ("n_act", c_int), ("pitch", c_double)]
 
 
+class fewha_tuning(ctypes.Structure):
+    _fields_ = [("dwt_resident", c_int), ("reserved", c_int * 7)]
+
+
 class FewhaError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("%s: %s" % (STATUS.get(status, str(status)), msg))
@@ -62,6 +66,7 @@ _SIGS = {
     "fewha_set_control": (c_int, [_P, c_double]),
     "fewha_set_fitting": (c_int, [_P, c_int, POINTER(fewha_dm_desc), c_int, POINTER(c_double), c_int, c_int,
                                   c_double]),
+    "fewha_set_tuning": (c_int, [_P, POINTER(fewha_tuning)]),
     "fewha_finalize": (c_int, [_P]),
     "fewha_sizes": (c_int, [_P, POINTER(c_long), POINTER(c_long), POINTER(c_long), POINTER(c_long),
                             POINTER(c_long)]),
@@ -77,6 +82,7 @@ _SIGS = {
     "fewha_apply_WinvT": (c_int, [_P, _FP, _FP]),
     "fewha_param_grads": (c_int, [_P, _FP, _FP, _FP, c_void_p]),
     "fewha_batch_create": (c_int, [POINTER(c_void_p), POINTER(c_void_p), c_int]),
+    "fewha_batch_create_tuned": (c_int, [POINTER(c_void_p), POINTER(c_void_p), c_int, POINTER(fewha_tuning)]),
     "fewha_batch_solve": (c_int, [_P, POINTER(c_void_p), POINTER(c_void_p), c_int, c_double, POINTER(c_int),
                                   POINTER(c_double)]),
     "fewha_batch_solve_map": (c_int, [_P, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p), c_int, c_double,

@@ -1,0 +1,101 @@
+"""Autotuner of a plan's launch shapes.
+
+The tunable is the resident transform side R (32, 64 or 128): the resident
+DWT kernels keep every level up to R x R in one workgroup's LDS, and the
+levels above R run as tiled global passes.  A large R means few, heavy
+workgroups (a MAORY-like layer of 128 x 128 is one workgroup); a small R
+spreads the same levels over many more workgroups at the cost of one launch
+per extra level.  Which wins depends on the batch size, the layer sizes and
+the device, so it is measured: every admissible R builds the batch plan,
+replays the captured frame graph on zero inputs, and the fastest is kept.
+
+Results are cached per (device, problem shapes, batch size, iterations) in
+a JSON file (``FEWHA_TUNE_CACHE`` or ``lib/autotune_cache.json`` next to the
+library).  Timing uses HIP events on the current torch stream.
+"""
+
+import json
+import os
+
+CANDIDATES = (32, 64, 128)
+CACHE = os.environ.get("FEWHA_TUNE_CACHE",
+                       os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "autotune_cache.json"))
+
+
+def admissible(ctxs, candidates=CANDIDATES):
+    """Resident sides that hold every layer's coarsest block."""
+    m0 = max(l["n"] >> l["levels"] for c in ctxs for l in c.cfg["layers"])
+    return [r for r in candidates if r >= m0]
+
+
+def signature(ctxs, iters):
+    """Cache key: device name and the multiset of problem shapes."""
+    import torch
+    shapes = {}
+    for c in ctxs:
+        cfg = c.cfg
+        s = "L%s|W%s|F%d" % (",".join("%dx%d" % (l["n"], l["levels"]) for l in cfg["layers"]),
+                            ",".join(str(w["n_subap"]) for w in cfg["wfs"]),
+                            1 if (cfg.get("dms") and cfg.get("fit")) else 0)
+        shapes[s] = shapes.get(s, 0) + 1
+    body = ";".join("%dx[%s]" % (n, s) for s, n in sorted(shapes.items()))
+    return "%s|iters%d|%s" % (torch.cuda.get_device_name(ctxs[0].device), iters, body)
+
+
+def _load():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(db):
+    os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+    tmp = CACHE + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+    os.replace(tmp, CACHE)
+
+
+def time_plan(ctxs, iters, tuning, steps=10, warmup=3):
+    """Microseconds per graph replay of one frame over the batch."""
+    import torch
+    from .fewha import Batch
+    b = Batch(ctxs, tuning=tuning)
+    try:
+        dev = "cuda:%d" % ctxs[0].device
+        slopes = [torch.zeros(c.n_slopes, device=dev) for c in ctxs]
+        states = [torch.zeros(c.n_state, device=dev) for c in ctxs]
+        for _ in range(warmup):
+            b.reconstruct(slopes, states, iters=iters, use_graph=True)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(steps):
+            b.reconstruct(slopes, states, iters=iters, use_graph=True)
+        t1.record()
+        t1.synchronize()
+        return 1000.0 * t0.elapsed_time(t1) / steps
+    finally:
+        b.close()
+
+
+def tune(ctxs, iters, steps=10, use_cache=True):
+    """Best resident side for a batch of these contexts; returns
+    {"dwt_resident": R, "us": {R: us per step}, "cached": bool}."""
+    key = signature(ctxs, iters)
+    db = _load() if use_cache else {}
+    if use_cache and key in db:
+        rec = dict(db[key])
+        rec["cached"] = True
+        return rec
+    us = {r: time_plan(ctxs, iters, r, steps=steps) for r in admissible(ctxs)}
+    best = min(us, key=us.get)
+    rec = {"dwt_resident": best, "us": {str(r): round(t, 3) for r, t in us.items()}}
+    if use_cache:
+        db = _load()
+        db[key] = rec
+        _store(db)
+    rec = dict(rec)
+    rec["cached"] = False
+    return rec

@@ -43,6 +43,7 @@ struct Range {
 struct Plan {
   int device = -1;
   int nprob = 0;
+  int res_max = kResMax;  // resident transform side (tuning)
   std::vector<const HostModel*> models;
   void* arena = nullptr;
   size_t arena_bytes = 0;
@@ -126,7 +127,18 @@ struct Carver {
   }
 };
 
-fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models, int device, std::string& err) {
+fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models, int device, int res,
+                        std::string& err) {
+  if (res != 32 && res != 64 && res != 128) {
+    err = "tuning: the resident transform side must be 32, 64 or 128";
+    return FEWHA_EINVAL;
+  }
+  for (const HostModel* m : models)
+    for (const LayerHost& lh : m->layers)
+      if ((lh.d.n >> lh.d.levels) > res) {
+        err = "tuning: a layer's coarsest block (n >> levels) exceeds the resident side " + std::to_string(res);
+        return FEWHA_EINVAL;
+      }
   std::unique_ptr<Plan> pl(new (std::nothrow) Plan());
   if (!pl) {
     err = "out of host memory";
@@ -134,6 +146,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   }
   Plan& P = *pl;
   P.device = device;
+  P.res_max = res;
   P.nprob = (int)models.size();
   P.models = models;
   HIP_TRY(hipSetDevice(device));
@@ -182,7 +195,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
       ld.n = lh.d.n;
       ld.log2n = ilog2i(ld.n);
       ld.levels = lh.d.levels;
-      ld.res = std::min(ld.n, kResMax);
+      ld.res = std::min(ld.n, res);
       ld.off = m.layer_off[l];
       ld.n_glob_levels = ilog2i(ld.n / ld.res);
       ld.tmp_off = tmp_total;
@@ -733,6 +746,7 @@ LaunchArgs args(const Plan& P, hipStream_t s, const IoDev* io) {
   a.IO = io;
   a.F = P.F;
   a.stream = s;
+  a.res_max = P.res_max;
   return a;
 }
 
@@ -1166,6 +1180,18 @@ fewha_status fewha_set_fitting(fewha_ctx* c, int n_dm, const fewha_dm_desc* dms,
   return FEWHA_OK;
 }
 
+fewha_status fewha_set_tuning(fewha_ctx* c, const fewha_tuning* t) {
+  CHECK_CTX(c);
+  if (c->finalized) return fail(c, FEWHA_ESTATE, "set_tuning after finalize");
+  if (!t) return fail(c, FEWHA_EINVAL, "set_tuning: null tuning");
+  for (int i = 0; i < 7; ++i)
+    if (t->reserved[i]) return fail(c, FEWHA_EINVAL, "set_tuning: reserved fields must be zero");
+  if (t->dwt_resident != 0 && t->dwt_resident != 32 && t->dwt_resident != 64 && t->dwt_resident != 128)
+    return fail(c, FEWHA_EINVAL, "set_tuning: dwt_resident must be 0, 32, 64 or 128");
+  c->m.tune_res = t->dwt_resident;
+  return FEWHA_OK;
+}
+
 fewha_status fewha_finalize(fewha_ctx* c) {
   CHECK_CTX(c);
   if (c->finalized) return fail(c, FEWHA_ESTATE, "finalize called twice");
@@ -1173,7 +1199,7 @@ fewha_status fewha_finalize(fewha_ctx* c) {
   if (s != FEWHA_OK) return s;
   if (c->device >= 0) {
     std::vector<const HostModel*> ms{&c->m};
-    s = build_plan(c->plan, ms, c->device, c->err);
+    s = build_plan(c->plan, ms, c->device, c->m.tune_res > 0 ? c->m.tune_res : kResMax, c->err);
     if (s != FEWHA_OK) return s;
   }
   c->finalized = true;
@@ -1356,7 +1382,14 @@ static fewha_status bfail(fewha_batch* b, fewha_status s, const std::string& m) 
 }
 
 fewha_status fewha_batch_create(fewha_batch** out, fewha_ctx* const* ctxs, int n) {
+  return fewha_batch_create_tuned(out, ctxs, n, nullptr);
+}
+
+fewha_status fewha_batch_create_tuned(fewha_batch** out, fewha_ctx* const* ctxs, int n, const fewha_tuning* t) {
   if (!out || !ctxs || n < 1) return FEWHA_EINVAL;
+  if (t && (t->dwt_resident < 0 || t->reserved[0] || t->reserved[1] || t->reserved[2] || t->reserved[3] ||
+            t->reserved[4] || t->reserved[5] || t->reserved[6]))
+    return FEWHA_EINVAL;
   *out = nullptr;
   int dev = -1;
   std::vector<const HostModel*> ms;
@@ -1369,7 +1402,8 @@ fewha_status fewha_batch_create(fewha_batch** out, fewha_ctx* const* ctxs, int n
   fewha_batch* b = new (std::nothrow) fewha_batch();
   if (!b) return FEWHA_ENOMEM;
   b->ctxs.assign(ctxs, ctxs + n);
-  fewha_status s = build_plan(b->plan, ms, dev, b->err);
+  const int res = (t && t->dwt_resident > 0) ? t->dwt_resident : kResMax;
+  fewha_status s = build_plan(b->plan, ms, dev, res, b->err);
   if (s != FEWHA_OK) {
     delete b;
     return s;

@@ -14,7 +14,7 @@
 namespace fewha {
 
 constexpr int kMaxLevelsJ = 16;   // j index range of the per-layer prior table
-constexpr int kResMax = 128;      // largest block kept resident in LDS by the DWT kernels
+constexpr int kResMax = 128;      // largest block kept resident in LDS by the DWT kernels (default residency)
 constexpr int kTileS = 16;        // subaperture / corner tile side of the sensor stages
 constexpr int kTileN = 32;        // node tile side of the propagation adjoint
 constexpr int kUpdChunk = 2048;   // coefficients per workgroup of the vector update
@@ -248,6 +248,7 @@ struct HostModel {
   std::vector<int> slope_off;
   long n_c = 0, n_slopes = 0;
   FitHost fit;
+  int tune_res = 0;  // resident transform side of the context's own plan (0 = default)
   long n_act() const { return fit.on ? fit.n_act : n_c; }
 };
 

@@ -31,6 +31,7 @@ struct LaunchArgs {
   const IoDev* IO;
   Filter F;
   hipStream_t stream;
+  int res_max;  // largest resident transform side of the plan (32, 64 or 128)
 };
 
 void launch_idwt_res(const LaunchArgs& a, const Tile* tiles, int ntiles, int src_mode, int out_mode, int iter);

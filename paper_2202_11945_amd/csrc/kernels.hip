@@ -204,13 +204,15 @@ constexpr int kU = 4;  // elements per thread with loads in flight together
 
 // ------------------------------------------------ inverse DWT, resident part
 // One workgroup per (problem, layer): all synthesis levels whose output side
-// is at most kResMax run in LDS.  Columns then rows, periodic, Mallat layout:
+// is at most the layer's resident side R (<= RMAX, the LDS capacity of the
+// instantiation) run in LDS.  Columns then rows, periodic, Mallat layout:
 //   x_t = sum_{i = t mod 2} h_i a[(t-i)/2] + g_i d[(t-i)/2]   (indices mod m/2)
+template <int RMAX>
 __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
                                                    const Tile* tiles, Filter F, int src_mode, int out_mode,
                                                    int iter) {
-  __shared__ float A[kResMax * kResMax];
-  __shared__ float B[kResMax * kResMax];
+  __shared__ float A[RMAX * RMAX];
+  __shared__ float B[RMAX * RMAX];
   __shared__ double sbeta;
   const Tile t = tiles[blockIdx.x];
   const ProbDev& pr = P[t.prob];
@@ -309,7 +311,7 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
 }
 
 // ----------------------------------------------- inverse DWT, one global level
-// Output tile 32x32 of the level with side m = 2^t.level (> kResMax).  The
+// Output tile 32x32 of the level with side m = 2^t.level (> the resident side).  The
 // coarse block comes from scratch, the three detail quadrants from the
 // coefficient source; 2 halo coefficients per direction (6 taps, 3 per phase).
 constexpr int kGT = 32;           // output tile side
@@ -408,7 +410,7 @@ __global__ __launch_bounds__(256) void k_idwt_glob(const ProbDev* P, const Layer
 }
 
 // ------------------------------------------------ forward DWT, one global level
-// Input side m = 2^t.level (> kResMax); output 16x16 coefficients of each of
+// Input side m = 2^t.level (> the resident side); output 16x16 coefficients of each of
 // the four quadrants per tile; input window 36x36 (2k .. 2k+5 per output).
 constexpr int kFT = 16;           // output coefficients per direction
 constexpr int kFW = 2 * kFT + 4;  // 36 input samples per direction
@@ -508,10 +510,11 @@ __global__ __launch_bounds__(256) void k_fdwt_glob(const ProbDev* P, const Layer
 }
 
 // ------------------------------------------------ forward DWT, resident part
+template <int RMAX>
 __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
                                                    const Tile* tiles, Filter F, int epi, int iter) {
-  __shared__ float A[kResMax * kResMax];
-  __shared__ float B[kResMax * kResMax];
+  __shared__ float A[RMAX * RMAX];
+  __shared__ float B[RMAX * RMAX];
   __shared__ double sh[16];
   const Tile t = tiles[blockIdx.x];
   const ProbDev& pr = P[t.prob];
@@ -1216,9 +1219,16 @@ __global__ __launch_bounds__(1024) void k_fit_cg(const FitDev* F, const ProbDev*
 
 // ------------------------------------------------------------ launchers
 
+// The resident kernels are instantiated for LDS capacities 32, 64 and 128 and
+// launched with the smallest that holds the plan's resident side.
 void launch_idwt_res(const LaunchArgs& a, const Tile* tiles, int ntiles, int src_mode, int out_mode, int iter) {
-  if (ntiles > 0)
-    k_idwt_res<<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, src_mode, out_mode, iter);
+  if (ntiles <= 0) return;
+  if (a.res_max <= 32)
+    k_idwt_res<32><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, src_mode, out_mode, iter);
+  else if (a.res_max <= 64)
+    k_idwt_res<64><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, src_mode, out_mode, iter);
+  else
+    k_idwt_res<128><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, src_mode, out_mode, iter);
 }
 void launch_idwt_glob(const LaunchArgs& a, const Tile* tiles, int ntiles, int src_mode, int out_mode, int iter,
                       int step) {
@@ -1229,7 +1239,13 @@ void launch_fdwt_glob(const LaunchArgs& a, const Tile* tiles, int ntiles, int ep
   if (ntiles > 0) k_fdwt_glob<<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter, step);
 }
 void launch_fdwt_res(const LaunchArgs& a, const Tile* tiles, int ntiles, int epi, int iter) {
-  if (ntiles > 0) k_fdwt_res<<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
+  if (ntiles <= 0) return;
+  if (a.res_max <= 32)
+    k_fdwt_res<32><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
+  else if (a.res_max <= 64)
+    k_fdwt_res<64><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
+  else
+    k_fdwt_res<128><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
 }
 void launch_pgamma(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
   if (ntiles > 0) k_pgamma<<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, mode);

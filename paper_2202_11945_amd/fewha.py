@@ -42,6 +42,12 @@ def _ptr64(t, n):
     return c_void_p(t.data_ptr())
 
 
+def _tuning(dwt_resident):
+    t = _abi.fewha_tuning()
+    t.dwt_resident = int(dwt_resident)
+    return t
+
+
 def _stream():
     import torch
     return c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -51,10 +57,13 @@ class Context:
     """One configured FEWHA problem (fewha_create ... fewha_finalize).
 
     ``cfg`` is a configuration dict (see ``synthetic.configs``); ``device``
-    is the HIP device index or -1 for a host-only context (tables only)."""
+    is the HIP device index or -1 for a host-only context (tables only);
+    ``tuning`` the resident transform side of the context's own plan
+    (32, 64 or 128; None = default)."""
 
-    def __init__(self, cfg, device=0):
+    def __init__(self, cfg, device=0, tuning=None):
         self.cfg = cfg
+        self.tuning = tuning
         h = c_void_p()
         _check(_abi.fewha_create(byref(h), int(device)))
         self.h = h
@@ -97,6 +106,8 @@ class Context:
         no = cfg["noise"]
         _check(_abi.fewha_set_noise(self.h, no["alpha_eta"], no["na_fwhm"], no["spot_fwhm"]), self.h)
         _check(_abi.fewha_set_control(self.h, cfg.get("gain", 1.0)), self.h)
+        if self.tuning is not None:
+            _check(_abi.fewha_set_tuning(self.h, byref(_tuning(self.tuning))), self.h)
         if cfg.get("dms") and cfg.get("fit"):
             dms = (_abi.fewha_dm_desc * len(cfg["dms"]))()
             for k, dm in enumerate(cfg["dms"]):
@@ -222,13 +233,16 @@ class Context:
 
 
 class Batch:
-    """fewha_batch_create over finalized device contexts."""
+    """fewha_batch_create over finalized device contexts; ``tuning`` is the
+    batch plan's resident transform side (see ``autotune``; None = default)."""
 
-    def __init__(self, ctxs):
+    def __init__(self, ctxs, tuning=None):
         self.ctxs = list(ctxs)
+        self.tuning = tuning
         arr = (c_void_p * len(self.ctxs))(*[c.h.value for c in self.ctxs])
         h = c_void_p()
-        _check(_abi.fewha_batch_create(byref(h), arr, len(self.ctxs)))
+        t = None if tuning is None else byref(_tuning(tuning))
+        _check(_abi.fewha_batch_create_tuned(byref(h), arr, len(self.ctxs), t))
         self.h = h
 
     def close(self, _destroy=_abi.fewha_batch_destroy):

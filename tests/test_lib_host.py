@@ -4,6 +4,7 @@ J of eq. precond), argument validation.  No compute call runs here."""
 
 import os
 import re
+from ctypes import c_void_p
 
 import numpy as np
 import pytest
@@ -118,3 +119,21 @@ def test_compute_on_host_only_context_is_a_state_error(lib):
 def ctypes_dummy():
     import ctypes
     return ctypes.c_void_p(16)
+
+
+def test_tuning_arguments_are_validated(lib):
+    from ctypes import byref
+    from paper_2202_11945_amd import _abi
+    from paper_2202_11945_amd.fewha import _tuning
+    ctx = lib.Context(get_config("tiny"), device=-1)  # finalized host-only context
+    assert _abi.fewha_set_tuning(ctx.h, byref(_tuning(64))) == -4  # after finalize
+    h = c_void_p()
+    assert _abi.fewha_create(byref(h), -1) == 0
+    for bad in (16, 96, -1, 256):
+        assert _abi.fewha_set_tuning(h, byref(_tuning(bad))) == -1
+    t = _tuning(32)
+    t.reserved[3] = 1
+    assert _abi.fewha_set_tuning(h, byref(t)) == -1
+    for good in (0, 32, 64, 128):
+        assert _abi.fewha_set_tuning(h, byref(_tuning(good))) == 0
+    _abi.fewha_destroy(h)
