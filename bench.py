@@ -115,19 +115,23 @@ def algorithmic_bytes(cfg, n_slopes_dense, n_corners):
     }
 
 
-def measured_traffic(stage, batch):
+def measured_traffic(stage, batch, tuning):
     """Bytes per launch of a stage from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary, or None when it was taken on other kernel code or
-    another batch size."""
+    WRITE_SIZE summary, or None when it was taken on other kernel code, another
+    batch size or other launch shapes."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2202_11945_amd", "csrc", "kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h", "fewha_internal.h", "api.cpp"):
+        h.update(open(os.path.join(ROOT, "paper_2202_11945_amd", "csrc", f), "rb").read())
+    sha = h.hexdigest()[:16]
+    tune = "%d/%d" % (tuning["dwt_resident"], tuning["pt_rows"])
     prof = os.path.join(ROOT, "profiles", "stages_maory_like_b64_bytes.md")
     if not os.path.exists(prof):
         return None
     for line in open(prof):
         f = line.split()
-        if len(f) == 5 and f[0] == "TRAFFIC" and f[1] == stage and int(f[2]) == batch and f[4] == sha:
+        if (len(f) == 6 and f[0] == "TRAFFIC" and f[1] == stage and int(f[2]) == batch and f[4] == sha
+                and f[5] == tune):
             return float(f[3])
     return None
 
@@ -211,12 +215,13 @@ def main():
 
     # ---- launch shapes from the autotuner (cached per device and shapes) ----
     from paper_2202_11945_amd import autotune
-    tune_b = autotune.tune(ctxs, args.iters) if not args.no_tune else {"dwt_resident": 128, "cached": None}
-    tune_1 = autotune.tune([c0], args.iters) if not args.no_tune else {"dwt_resident": 128, "cached": None}
+    default = {"dwt_resident": 128, "pt_rows": 4, "cached": None}
+    tune_b = autotune.tune(ctxs, args.iters) if not args.no_tune else default
+    tune_1 = autotune.tune([c0], args.iters) if not args.no_tune else default
     print("[bench] tuning: batch %s, single %s" % (tune_b, tune_1), file=sys.stderr, flush=True)
 
     # ---- batched graph path: the timed workload ----
-    batch = fw.Batch(ctxs, tuning=tune_b["dwt_resident"])
+    batch = fw.Batch(ctxs, tuning=tune_b)
     states = [torch.zeros(c.n_state, device=dev) for c in ctxs]
 
     def step(i, use_graph=True):
@@ -246,7 +251,7 @@ def main():
     dt_nograph = (time.perf_counter() - t0) / nd
 
     # ---- single-frame latency: graph path (batch of one) and plain path ----
-    single = fw.Batch([c0], tuning=tune_1["dwt_resident"])
+    single = fw.Batch([c0], tuning=tune_1)
     st1 = torch.zeros(c0.n_state, device=dev)
     lay1 = torch.empty(c0.n_coeff, device=dev)
     nf = args.latency_frames
@@ -299,7 +304,7 @@ def main():
     alg = algorithmic_bytes(cfg, n_sd, n_cor)
     dom_bytes = alg[dom] * B
     achieved = dom_bytes / (stage_us[dom][0] * 1e-6) / 1e9
-    traffic = measured_traffic(dom, B)
+    traffic = measured_traffic(dom, B, tune_b)
 
     grad = None if args.grad_frames <= 0 else gradient_leg(fw, pool, args.grad_frames)
 

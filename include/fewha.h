@@ -303,10 +303,15 @@ FEWHA_API void fewha_batch_destroy(fewha_batch* b);
  * above it run as tiled passes over global memory, one launch per level.
  * Smaller values trade LDS work per workgroup for more workgroups and more
  * launches.  It must be at least every layer's coarsest block (n >> levels),
- * else FEWHA_EINVAL when the plan is built.  reserved: zero. */
+ * else FEWHA_EINVAL when the plan is built.
+ * pt_rows: node rows per thread of the propagation adjoint P^T (4 or 8;
+ * 0 = default 4); a tile is 64 node columns by 4 * pt_rows rows.  More rows
+ * put more independent loads in flight per thread, at more registers.
+ * reserved: zero. */
 typedef struct {
   int dwt_resident;
-  int reserved[7];
+  int pt_rows;
+  int reserved[6];
 } fewha_tuning;
 
 /* Tuning of a context's own plan; before fewha_finalize. */

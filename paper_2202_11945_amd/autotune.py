@@ -1,13 +1,19 @@
 """Autotuner of a plan's launch shapes.
 
-The tunable is the resident transform side R (32, 64 or 128): the resident
-DWT kernels keep every level up to R x R in one workgroup's LDS, and the
-levels above R run as tiled global passes.  A large R means few, heavy
-workgroups (a MAORY-like layer of 128 x 128 is one workgroup); a small R
-spreads the same levels over many more workgroups at the cost of one launch
-per extra level.  Which wins depends on the batch size, the layer sizes and
-the device, so it is measured: every admissible R builds the batch plan,
-replays the captured frame graph on zero inputs, and the fastest is kept.
+Two tunables:
+
+* the resident transform side R (32, 64 or 128): the resident DWT kernels
+  keep every level up to R x R in one workgroup's LDS, and the levels above R
+  run as tiled global passes.  A large R means few, heavy workgroups (a
+  MAORY-like layer of 128 x 128 is one workgroup); a small R spreads the same
+  levels over many more workgroups at the cost of one launch per extra level.
+* the node rows per thread of the propagation adjoint (4 or 8): more rows
+  put more independent loads in flight per thread, at more registers.
+
+Which combination wins depends on the batch size, the layer sizes and the
+device, so it is measured: every admissible combination builds the batch
+plan, replays the captured frame graph on zero inputs, and the fastest is
+kept.
 
 Results are cached per (device, problem shapes, batch size, iterations) in
 a JSON file (``FEWHA_TUNE_CACHE`` or ``lib/autotune_cache.json`` next to the
@@ -18,6 +24,8 @@ import json
 import os
 
 CANDIDATES = (32, 64, 128)
+PT_ROWS = (4, 8)
+MARGIN = 0.02  # relative gain a non-default choice needs
 CACHE = os.environ.get("FEWHA_TUNE_CACHE",
                        os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "autotune_cache.json"))
 
@@ -59,7 +67,8 @@ def _store(db):
 
 
 def time_plan(ctxs, iters, tuning, steps=10, warmup=3):
-    """Microseconds per graph replay of one frame over the batch."""
+    """Microseconds per graph replay of one frame over the batch, for a
+    tuning as accepted by Batch."""
     import torch
     from .fewha import Batch
     b = Batch(ctxs, tuning=tuning)
@@ -81,17 +90,24 @@ def time_plan(ctxs, iters, tuning, steps=10, warmup=3):
 
 
 def tune(ctxs, iters, steps=10, use_cache=True):
-    """Best resident side for a batch of these contexts; returns
-    {"dwt_resident": R, "us": {R: us per step}, "cached": bool}."""
+    """Best launch shapes for a batch of these contexts; returns
+    {"dwt_resident": R, "pt_rows": r, "us": {"R/r": us per step}, "cached": bool}."""
     key = signature(ctxs, iters)
     db = _load() if use_cache else {}
     if use_cache and key in db:
         rec = dict(db[key])
         rec["cached"] = True
         return rec
-    us = {r: time_plan(ctxs, iters, r, steps=steps) for r in admissible(ctxs)}
+    us = {(r, pr): time_plan(ctxs, iters, {"dwt_resident": r, "pt_rows": pr}, steps=steps)
+          for r in admissible(ctxs) for pr in PT_ROWS}
     best = min(us, key=us.get)
-    rec = {"dwt_resident": best, "us": {str(r): round(t, 3) for r, t in us.items()}}
+    # keep the default shapes unless another choice is clearly faster: near
+    # ties would otherwise flip between runs on timing noise
+    default = (max(admissible(ctxs)), PT_ROWS[0])
+    if us[best] > (1.0 - MARGIN) * us[default]:
+        best = default
+    rec = {"dwt_resident": best[0], "pt_rows": best[1],
+           "us": {"%d/%d" % k: round(t, 3) for k, t in us.items()}}
     if use_cache:
         db = _load()
         db[key] = rec

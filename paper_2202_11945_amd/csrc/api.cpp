@@ -44,6 +44,7 @@ struct Plan {
   int device = -1;
   int nprob = 0;
   int res_max = kResMax;  // resident transform side (tuning)
+  int pt_rows = 4;        // node rows per thread of the propagation adjoint (tuning)
   std::vector<const HostModel*> models;
   void* arena = nullptr;
   size_t arena_bytes = 0;
@@ -62,11 +63,13 @@ struct Plan {
   Range fit_fwdL, fit_fwdD, fit_pt, fit_cg;  // DM fitting (empty when no problem fits)
   Range sinit, gprior, ghgt;                 // solve start, parameter-gradient reductions
   Range r64wfs;                              // FP64 residual: one tile per (problem, sensor)
+  Range r64pt;                               // FP64 residual: 32x32 node tiles of the adjoint
   std::vector<Range> r64inv, r64fwd;         // FP64 residual: transform steps
   Resid64Tiles r64;
   Filter64 F64{};
   std::vector<float*> rbuf;                  // per problem: residual of a refined solve
   GradIo* dGIO = nullptr;
+  const HatEnt* dHat = nullptr;              // hat tables of the propagation adjoint
   std::vector<float*> sstate;                // per problem: [x | unused | r] of a solve
   double* rho_host = nullptr;                // pinned readback: 2 n_dots doubles per problem
   std::vector<long> rho_off;
@@ -116,6 +119,38 @@ void destroy_plan(Plan* p) {
   delete p;
 }
 
+// Hat tables of one (sensor, layer) pair of the propagation adjoint: for every
+// node row, then every node column, the corners whose bilinear cell touches
+// the node (t = t0 + k rho within one node spacing, found in FP64) and their
+// weights 1 - rho |k - c| with c = (p - t0) / rho, the transpose of the
+// forward interpolation weights.
+void append_hats(GLPar& gp, int n, std::vector<HatEnt>& out) {
+  gp.hat_off = (int)out.size();
+  const int K = gp.kmax;
+  for (int axis = 0; axis < 2; ++axis) {
+    const double t0 = axis == 0 ? gp.t0y : gp.t0x;
+    for (int p = 0; p < n; ++p) {
+      const double c = ((double)p - t0) * gp.inv_rho;
+      const int lo = std::max((int)std::floor(c - gp.inv_rho) + 1, 0);
+      const int hi = std::min((int)std::ceil(c + gp.inv_rho) - 1, gp.nc - 1);
+      // no corner (outside the footprint, or between corners when rho > 2):
+      // weights 0 on the valid corners at floor(c), so that lo never
+      // decreases along the axis
+      HatEnt e{std::max(0, std::min((int)std::floor(c), gp.nc - K)), {0.f, 0.f, 0.f}};
+      if (hi >= lo) {
+        const int base = std::max(0, std::min(lo, gp.nc - K));
+        e.lo = base;
+        for (int k = 0; k < K; ++k) {
+          const int corner = base + k;
+          if (corner >= lo && corner <= hi)
+            e.w[k] = (float)std::max(0.0, 1.0 - gp.rho * std::fabs((double)corner - c));
+        }
+      }
+      out.push_back(e);
+    }
+  }
+}
+
 // Byte-offset carving of the arena (256-byte aligned pieces).
 struct Carver {
   size_t off = 0;
@@ -128,11 +163,16 @@ struct Carver {
 };
 
 fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models, int device, int res,
-                        std::string& err) {
+                        int pt_rows, std::string& err) {
   if (res != 32 && res != 64 && res != 128) {
     err = "tuning: the resident transform side must be 32, 64 or 128";
     return FEWHA_EINVAL;
   }
+  if (pt_rows != 4 && pt_rows != 8) {
+    err = "tuning: the propagation adjoint takes 4 or 8 node rows per thread";
+    return FEWHA_EINVAL;
+  }
+  const int kPtH = 4 * pt_rows;  // node rows of a propagation-adjoint tile
   for (const HostModel* m : models)
     for (const LayerHost& lh : m->layers)
       if ((lh.d.n >> lh.d.levels) > res) {
@@ -147,6 +187,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   Plan& P = *pl;
   P.device = device;
   P.res_max = res;
+  P.pt_rows = pt_rows;
   P.nprob = (int)models.size();
   P.models = models;
   HIP_TRY(hipSetDevice(device));
@@ -167,7 +208,8 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   };
   std::vector<ProbLayout> lay(P.nprob);
   Carver cv;
-  std::vector<Tile> t_idwt_res, t_fdwt_res, t_pg, t_gt, t_pt, t_upd, t_sinit, t_gprior, t_ghgt, t_r64wfs;
+  std::vector<Tile> t_idwt_res, t_fdwt_res, t_pg, t_gt, t_pt, t_upd, t_sinit, t_gprior, t_ghgt, t_r64wfs, t_r64pt;
+  std::vector<HatEnt> hats;  // hat tables of every problem and fitting view, one array per plan
   std::vector<std::vector<Tile>> t_r64inv(kMaxLevelsJ), t_r64fwd(kMaxLevelsJ);
   std::vector<std::vector<double>> cinv64(P.nprob), ftab64(P.nprob);
   std::vector<std::vector<Tile>> t_idwt_glob, t_fdwt_glob;
@@ -307,6 +349,9 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
         gp.nc = wh.d.n_subap + 1;
         gp.v_off = P.hW[pd.wfs0 + g].v_off;
         gp.kmax = gp.rho >= 1.0 ? 2 : (gp.rho >= 2.0 / 3.0 ? 3 : 0);
+        gp.hat_off = -1;
+        if (gp.kmax > 0 && gp.nc >= gp.kmax) append_hats(gp, lh.d.n, hats);
+        if (gp.kmax > 0 && gp.nc < gp.kmax) gp.kmax = 0;  // tiny sensor: general gather
         glp[k][(size_t)g * L + l] = gp;
       }
     // tiles
@@ -380,10 +425,28 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
       for (int ty = 0; ty < tc; ++ty)
         for (int tx = 0; tx < tc; ++tx) t_gt.push_back({k, g, ty, tx, 0, 0, 0, 0});
     }
+    // node tiles of the propagation adjoint (kPtH rows x kPtW columns) with the
+    // sensors whose footprint (corners t0 + k rho, k < nc, widened by one node
+    // and a margin) meets them; 32x32 tiles for the FP64 residual's adjoint
     for (int l = 0; l < L; ++l) {
-      const int nt = cdiv(P.hL[pd.layer0 + l].n, kTileN);
+      const int n = P.hL[pd.layer0 + l].n;
+      for (int ty = 0; ty < cdiv(n, kPtH); ++ty)
+        for (int tx = 0; tx < cdiv(n, kPtW); ++tx) {
+          int mask = 0;
+          for (int g = 0; g < G; ++g) {
+            const GLPar& gp = glp[k][(size_t)g * L + l];
+            const double span = (gp.nc - 1) * gp.rho;
+            auto meets = [&](double t0, int p0, int ext) {
+              return p0 + ext - 1 >= t0 - 2.0 && p0 <= t0 + span + 2.0;
+            };
+            if (meets(gp.t0y, ty * kPtH, kPtH) && meets(gp.t0x, tx * kPtW, kPtW)) mask |= (G <= 32) ? (1 << g) : 0;
+          }
+          if (G > 32) mask = -1;
+          t_pt.push_back({k, l, ty, tx, 0, 0, mask, 0});
+        }
+      const int nt = cdiv(n, kTileN);
       for (int ty = 0; ty < nt; ++ty)
-        for (int tx = 0; tx < nt; ++tx) t_pt.push_back({k, l, ty, tx, 0, 0, 0, 0});
+        for (int tx = 0; tx < nt; ++tx) t_r64pt.push_back({k, l, ty, tx, 0, 0, -1, 0});
     }
     // buffer layout
     ProbLayout& pl_ = lay[k];
@@ -493,6 +556,9 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
         gp.nc = nc;
         gp.v_off = d * nc * nc;
         gp.kmax = gp.rho >= 1.0 ? 2 : (gp.rho >= 2.0 / 3.0 ? 3 : 0);
+        gp.hat_off = -1;
+        if (gp.kmax > 0 && gp.nc >= gp.kmax) append_hats(gp, dm.n_act, hats);
+        if (gp.kmax > 0 && gp.nc < gp.kmax) gp.kmax = 0;
         fl.glp.push_back(gp);
       }
     ProbDev vL{}, vD{};
@@ -526,9 +592,9 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
           t_ffD.push_back({fl.pD, d, ty, tx, 0, 0, 0, 0});
         }
     for (int q = 0; q < nd; ++q) {
-      const int tn = cdiv(f.dms[q].n_act, kTileN);
-      for (int ty = 0; ty < tn; ++ty)
-        for (int tx = 0; tx < tn; ++tx) t_fpt.push_back({fl.pD, q, ty, tx, 0, 0, 0, 0});
+      const int na = f.dms[q].n_act;
+      for (int ty = 0; ty < cdiv(na, kPtH); ++ty)
+        for (int tx = 0; tx < cdiv(na, kPtW); ++tx) t_fpt.push_back({fl.pD, q, ty, tx, 0, 0, -1, 0});  // all directions
     }
     t_fcg.push_back({(int)hF.size(), 0, 0, 0, 0, 0, 0, 0});
     FitDev fd{};
@@ -565,6 +631,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   P.gprior = add(t_gprior);
   P.ghgt = add(t_ghgt);
   P.r64wfs = add(t_r64wfs);
+  P.r64pt = add(t_r64pt);
   for (int st = 0; st < kMaxLevelsJ; ++st) {
     P.r64inv.push_back(add(t_r64inv[st]));
     P.r64fwd.push_back(add(t_r64fwd[st]));
@@ -575,6 +642,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   const size_t oIO = cv.take(sizeof(IoDev) * P.nprob_all);
   const size_t oIOp = cv.take(sizeof(IoDev) * P.nprob_all);
   const size_t oGIO = cv.take(sizeof(GradIo) * P.nprob_all);
+  const size_t oHat = cv.take(sizeof(HatEnt) * std::max<size_t>(hats.size(), 1));
   const size_t oF = cv.take(sizeof(FitDev) * std::max<size_t>(hF.size(), 1));
   const size_t oT = cv.take(sizeof(Tile) * std::max<size_t>(P.hT.size(), 1));
   P.arena_bytes = cv.off;
@@ -612,6 +680,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     pd.gslots = (double*)(base + l.gslots);
     pd.gitab = (const int*)(base + l.gitab);
     pd.gftab = (const float*)(base + l.gftab);
+
     P.sstate.push_back((float*)(base + l.sstate));
     pd.a64 = (double*)(base + l.a64);
     pd.b64 = (double*)(base + l.b64);
@@ -652,6 +721,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     vD.phiadj = (float*)(base + fl.adj);
     vD.vadj = u;
     vD.gl = (const GLPar*)(base + fl.gl);
+
     FitDev& fd = hF[i];
     fd.x = (float*)(base + fl.x);
     fd.r = (float*)(base + fl.r);
@@ -672,6 +742,8 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   P.dIO = (IoDev*)(base + oIO);
   P.dIOprof = (IoDev*)(base + oIOp);
   P.dGIO = (GradIo*)(base + oGIO);
+  P.dHat = (const HatEnt*)(base + oHat);
+  if (!hats.empty()) HIP_TRY(hipMemcpy(base + oHat, hats.data(), sizeof(HatEnt) * hats.size(), hipMemcpyHostToDevice));
   P.dT = (Tile*)(base + oT);
   // work lists of the FP64 residual chain (device addresses: after P.dT is set)
   {
@@ -691,8 +763,8 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     rt.wfs_n = P.r64wfs.n;
     rt.gt = P.dT + P.gt.off;
     rt.gt_n = P.gt.n;
-    rt.pt = P.dT + P.pt.off;
-    rt.pt_n = P.pt.n;
+    rt.pt = P.dT + P.r64pt.off;
+    rt.pt_n = P.r64pt.n;
   }
   HIP_TRY(hipMemcpy(P.dP, P.hP.data(), sizeof(ProbDev) * P.nprob_all, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(P.dL, P.hL.data(), sizeof(LayerDev) * P.hL.size(), hipMemcpyHostToDevice));
@@ -747,6 +819,8 @@ LaunchArgs args(const Plan& P, hipStream_t s, const IoDev* io) {
   a.F = P.F;
   a.stream = s;
   a.res_max = P.res_max;
+  a.pt_rows = P.pt_rows;
+  a.hats = P.dHat;
   return a;
 }
 
@@ -1184,11 +1258,14 @@ fewha_status fewha_set_tuning(fewha_ctx* c, const fewha_tuning* t) {
   CHECK_CTX(c);
   if (c->finalized) return fail(c, FEWHA_ESTATE, "set_tuning after finalize");
   if (!t) return fail(c, FEWHA_EINVAL, "set_tuning: null tuning");
-  for (int i = 0; i < 7; ++i)
+  for (int i = 0; i < 6; ++i)
     if (t->reserved[i]) return fail(c, FEWHA_EINVAL, "set_tuning: reserved fields must be zero");
   if (t->dwt_resident != 0 && t->dwt_resident != 32 && t->dwt_resident != 64 && t->dwt_resident != 128)
     return fail(c, FEWHA_EINVAL, "set_tuning: dwt_resident must be 0, 32, 64 or 128");
+  if (t->pt_rows != 0 && t->pt_rows != 4 && t->pt_rows != 8)
+    return fail(c, FEWHA_EINVAL, "set_tuning: pt_rows must be 0, 4 or 8");
   c->m.tune_res = t->dwt_resident;
+  c->m.tune_pt_rows = t->pt_rows;
   return FEWHA_OK;
 }
 
@@ -1199,7 +1276,8 @@ fewha_status fewha_finalize(fewha_ctx* c) {
   if (s != FEWHA_OK) return s;
   if (c->device >= 0) {
     std::vector<const HostModel*> ms{&c->m};
-    s = build_plan(c->plan, ms, c->device, c->m.tune_res > 0 ? c->m.tune_res : kResMax, c->err);
+    s = build_plan(c->plan, ms, c->device, c->m.tune_res > 0 ? c->m.tune_res : kResMax,
+                   c->m.tune_pt_rows > 0 ? c->m.tune_pt_rows : 4, c->err);
     if (s != FEWHA_OK) return s;
   }
   c->finalized = true;
@@ -1387,8 +1465,8 @@ fewha_status fewha_batch_create(fewha_batch** out, fewha_ctx* const* ctxs, int n
 
 fewha_status fewha_batch_create_tuned(fewha_batch** out, fewha_ctx* const* ctxs, int n, const fewha_tuning* t) {
   if (!out || !ctxs || n < 1) return FEWHA_EINVAL;
-  if (t && (t->dwt_resident < 0 || t->reserved[0] || t->reserved[1] || t->reserved[2] || t->reserved[3] ||
-            t->reserved[4] || t->reserved[5] || t->reserved[6]))
+  if (t && (t->dwt_resident < 0 || t->pt_rows < 0 || t->reserved[0] || t->reserved[1] || t->reserved[2] ||
+            t->reserved[3] || t->reserved[4] || t->reserved[5]))
     return FEWHA_EINVAL;
   *out = nullptr;
   int dev = -1;
@@ -1403,7 +1481,8 @@ fewha_status fewha_batch_create_tuned(fewha_batch** out, fewha_ctx* const* ctxs,
   if (!b) return FEWHA_ENOMEM;
   b->ctxs.assign(ctxs, ctxs + n);
   const int res = (t && t->dwt_resident > 0) ? t->dwt_resident : kResMax;
-  fewha_status s = build_plan(b->plan, ms, dev, res, b->err);
+  const int rows = (t && t->pt_rows > 0) ? t->pt_rows : 4;
+  fewha_status s = build_plan(b->plan, ms, dev, res, rows, b->err);
   if (s != FEWHA_OK) {
     delete b;
     return s;

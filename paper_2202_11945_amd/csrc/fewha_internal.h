@@ -16,7 +16,9 @@ namespace fewha {
 constexpr int kMaxLevelsJ = 16;   // j index range of the per-layer prior table
 constexpr int kResMax = 128;      // largest block kept resident in LDS by the DWT kernels (default residency)
 constexpr int kTileS = 16;        // subaperture / corner tile side of the sensor stages
-constexpr int kTileN = 32;        // node tile side of the propagation adjoint
+constexpr int kTileN = 32;        // node tile side of the FP64 propagation adjoint
+constexpr int kPtW = 64;          // propagation adjoint tile: 64 node columns (one per lane) by
+                                  // 4 x rows-per-thread node rows (tuning: 4 or 8 rows per thread)
 constexpr int kUpdChunk = 2048;   // coefficients per workgroup of the vector update
 constexpr int kDotRing = 256;     // PCG iterations whose inner products are kept (ring, power of two)
 constexpr int kGradChunk = 2048;  // coefficients per workgroup of the prior-term reductions
@@ -86,7 +88,17 @@ struct WfsDev {
 // node along an axis (2 when rho >= 1, 3 when rho >= 2/3, 0 = finer).
 struct GLPar {
   double t0y, t0x, rho, inv_rho;
-  int nc, v_off, kmax, pad0;
+  int nc, v_off, kmax;
+  int hat_off;  // hat tables of this pair: [rows n][columns n] HatEnt in the plan's hat array
+};
+
+// The corners of one node along one axis: corner lo + k has weight w[k]
+// (k < K = kmax; lo clamped so that lo + K - 1 < nc, unused weights 0);
+// a node that no corner's cell touches has all weights 0 and lo =
+// clamp(floor(c), 0, nc - K), so lo never decreases along an axis.
+struct HatEnt {
+  int lo;
+  float w[3];
 };
 
 // One problem.
@@ -166,10 +178,12 @@ struct IoDev {
 };
 
 // Work-list entry of a tiled stage: problem, item (layer or sensor), tile
-// row/column, and the slot of the partial it produces.
+// row/column, and the slot of the partial it produces.  For the propagation
+// adjoint, mask has bit g set when sensor g's footprint can reach the tile
+// (all bits when the problem has more than 32 sensors).
 struct Tile {
   int prob, item, ty, tx;
-  int slot, level, pad0, pad1;
+  int slot, level, mask, pad1;
 };
 
 // ---- host-side description of one configured problem ----
@@ -249,6 +263,7 @@ struct HostModel {
   long n_c = 0, n_slopes = 0;
   FitHost fit;
   int tune_res = 0;  // resident transform side of the context's own plan (0 = default)
+  int tune_pt_rows = 0;  // node rows per thread of the propagation adjoint (0 = default)
   long n_act() const { return fit.on ? fit.n_act : n_c; }
 };
 

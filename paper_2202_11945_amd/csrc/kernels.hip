@@ -57,6 +57,22 @@ __device__ __forceinline__ double wave_sum_slots(const double* s, int n) {
   return wave_sum(a);
 }
 
+// XCD-aware work distribution.  Workgroups are dispatched round-robin over
+// the 8 XCDs (workgroup b runs on XCD b mod 8) and every XCD has its own L2.
+// Tile lists are ordered by problem, item and tile, so giving each XCD a
+// contiguous run of tiles keeps the data that neighbouring tiles share (a
+// problem's layers, corner grids, halos) in one L2 instead of eight.  A
+// bijection of [0, W): XCD x takes tiles [start_x, start_x + count_x).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int b, int W) {
+  const int x = b % kXcds, i = b / kXcds;
+  const int q = W / kXcds, r = W % kXcds;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+__device__ __forceinline__ const Tile& my_tile(const Tile* tiles) {
+  return tiles[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
+}
+
 __device__ __forceinline__ const double* dot_group(const ProbDev& pr, int g) {
   return pr.dots + (long)g * pr.n_dots;
 }
@@ -200,7 +216,12 @@ __device__ __forceinline__ void epi_finish(const ProbDev& pr, const LayerDev& ly
 
 __device__ __forceinline__ int dot_group_of(int epi, int iter) { return epi == EPI_PCG ? pi_grp(iter) : 0; }
 
+// Global-address-space view of a device pointer held in a struct (loads
+// through it compile to global, not flat, memory instructions).
+typedef const float __attribute__((address_space(1)))* gptr_f;
+
 constexpr int kU = 4;  // elements per thread with loads in flight together
+constexpr int kUG = 6; // ... for the 36 x 36 windows of the global transform levels (one round at 256 threads)
 
 // ------------------------------------------------ inverse DWT, resident part
 // One workgroup per (problem, layer): all synthesis levels whose output side
@@ -214,60 +235,36 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
   __shared__ float A[RMAX * RMAX];
   __shared__ float B[RMAX * RMAX];
   __shared__ double sbeta;
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[pr.layer0 + t.item];
   const IoDev& io = IO[t.prob];
   const float beta = compute_beta(pr, src_mode, iter, &sbeta);
   const PSrc ps = make_psrc(pr, io, src_mode, iter, beta);
   const int n = ly.n, R = ly.res, lr = __builtin_ctz(R);
-  const int m0 = n >> ly.levels, l0 = __builtin_ctz(m0);
+  const int m0 = n >> ly.levels;
   const int off = ly.off;
   const int nt = blockDim.x;
-  // coarse block
-  for (int e0 = threadIdx.x; e0 < m0 * m0; e0 += kU * nt) {
-    CoefLoad v[kU];
+  // every resident coefficient (the R x R top-left block of the Mallat layout:
+  // the coarse block and the detail quadrants of all resident levels) in one
+  // pass, so that all global loads of the block are in flight together
+  constexpr int kUL = 16;
+  for (int e0 = threadIdx.x; e0 < R * R; e0 += kUL * nt) {
+    CoefLoad v[kUL];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < kUL; ++u) {
       const int e = e0 + u * nt;
-      if (e < m0 * m0) v[u] = coef_fetch(ps, off + (e >> l0) * n + (e & (m0 - 1)));
+      if (e < R * R) v[u] = coef_fetch(ps, off + (e >> lr) * n + (e & (R - 1)));
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < kUL; ++u) {
       const int e = e0 + u * nt;
-      if (e < m0 * m0) {
-        const int r = e >> l0, c = e & (m0 - 1);
-        A[(r << lr) + c] = coef_finish(ps, off + r * n + c, v[u], true);
-      }
+      if (e < R * R) A[e] = coef_finish(ps, off + (e >> lr) * n + (e & (R - 1)), v[u], true);
     }
   }
+  __syncthreads();
   for (int m = 2 * m0; m <= R; m <<= 1) {
     const int half = m >> 1, lh = __builtin_ctz(half), lm = lh + 1;
-    const int q2 = half * half, total = 3 * q2;
-    // detail quadrants: 0 = (rows < half, cols >= half), 1 = (>=, <), 2 = (>=, >=)
-    for (int f0 = threadIdx.x; f0 < total; f0 += kU * nt) {
-      CoefLoad v[kU];
-      int pos[kU];
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const int f = f0 + u * nt;
-        pos[u] = -1;
-        if (f < total) {
-          const int qd = f >> (2 * lh), w = f & (q2 - 1);
-          const int r = (w >> lh) + (qd >= 1 ? half : 0), c = (w & (half - 1)) + (qd != 1 ? half : 0);
-          pos[u] = r * n + c;
-          v[u] = coef_fetch(ps, off + pos[u]);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        if (pos[u] >= 0) {
-          const int r = pos[u] / n, c = pos[u] - r * n;
-          A[(r << lr) + c] = coef_finish(ps, off + pos[u], v[u], true);
-        }
-      }
-    }
-    __syncthreads();
     for (int e = threadIdx.x; e < m * m; e += nt) {  // columns (along y)
       const int tt = e >> lm, c = e & (m - 1);
       const int par = tt & 1, k0 = (tt - par) >> 1;
@@ -289,7 +286,6 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
     }
     __syncthreads();
   }
-  if (m0 == R) __syncthreads();  // no synthesis level ran: order the coarse-block stores
   if (n == R) {
     for (int e0 = threadIdx.x; e0 < R * R; e0 += kU * nt) {
       OutLoad o[kU];
@@ -324,7 +320,7 @@ __global__ __launch_bounds__(256) void k_idwt_glob(const ProbDev* P, const Layer
   __shared__ float A[kGW * (kGW + 1)];
   __shared__ float B[kGT * (kGW + 1)];
   __shared__ double sbeta;
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[pr.layer0 + t.item];
   const IoDev& io = IO[t.prob];
@@ -338,11 +334,11 @@ __global__ __launch_bounds__(256) void k_idwt_glob(const ProbDev* P, const Layer
   const int kr0 = (t0 >> 1) - 2, kc0 = (s0 >> 1) - 2;
   const int W1 = kGW + 1;
   const int nt = blockDim.x;
-  for (int e0 = threadIdx.x; e0 < kGW * kGW; e0 += kU * nt) {
-    CoefLoad v[kU];
-    int gpos[kU];
+  for (int e0 = threadIdx.x; e0 < kGW * kGW; e0 += kUG * nt) {
+    CoefLoad v[kUG];
+    int gpos[kUG];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < kUG; ++u) {
       const int e = e0 + u * nt;
       gpos[u] = -2;
       if (e < kGW * kGW) {
@@ -360,7 +356,7 @@ __global__ __launch_bounds__(256) void k_idwt_glob(const ProbDev* P, const Layer
       }
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < kUG; ++u) {
       const int e = e0 + u * nt;
       if (gpos[u] == -2) continue;
       const int ly_ = e / kGW, lx_ = e - ly_ * kGW;
@@ -420,7 +416,7 @@ __global__ __launch_bounds__(256) void k_fdwt_glob(const ProbDev* P, const Layer
   __shared__ float X[kFW * (kFW + 1)];
   __shared__ float Rw[kFW * (2 * kFT + 1)];
   __shared__ double sh[4];
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[pr.layer0 + t.item];
   const IoDev& io = IO[t.prob];
@@ -432,10 +428,10 @@ __global__ __launch_bounds__(256) void k_fdwt_glob(const ProbDev* P, const Layer
   const int k0 = t.ty * kFT, l0 = t.tx * kFT;
   const int XW = kFW + 1, RW = 2 * kFT + 1;
   const int nt = blockDim.x;
-  for (int e0 = threadIdx.x; e0 < kFW * kFW; e0 += kU * nt) {
-    float v[kU];
+  for (int e0 = threadIdx.x; e0 < kFW * kFW; e0 += kUG * nt) {
+    float v[kUG];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < kUG; ++u) {
       const int e = e0 + u * nt;
       if (e < kFW * kFW) {
         const int ry = e / kFW, rx = e - ry * kFW;
@@ -443,7 +439,7 @@ __global__ __launch_bounds__(256) void k_fdwt_glob(const ProbDev* P, const Layer
       }
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < kUG; ++u) {
       const int e = e0 + u * nt;
       if (e < kFW * kFW) {
         const int ry = e / kFW, rx = e - ry * kFW;
@@ -516,7 +512,7 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
   __shared__ float A[RMAX * RMAX];
   __shared__ float B[RMAX * RMAX];
   __shared__ double sh[16];
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[pr.layer0 + t.item];
   const IoDev& io = IO[t.prob];
@@ -525,15 +521,16 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
   const int ng = ly.n_glob_levels;
   const float* in = (ng == 0) ? pr.phiadj + off : ((((ng - 1) & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off);
   const int istride = (ng == 0) ? n : R;
-  for (int e0 = threadIdx.x; e0 < R * R; e0 += kU * nt) {
-    float v[kU];
+  constexpr int kUL = 16;  // the whole block's loads in flight together
+  for (int e0 = threadIdx.x; e0 < R * R; e0 += kUL * nt) {
+    float v[kUL];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < kUL; ++u) {
       const int e = e0 + u * nt;
       if (e < R * R) v[u] = in[(e >> lr) * istride + (e & (R - 1))];
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < kUL; ++u) {
       const int e = e0 + u * nt;
       if (e < R * R) A[e] = v[u];
     }
@@ -541,8 +538,23 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
   __syncthreads();
   double acc = 0.0;
   const int m0 = n >> ly.levels;
+  // up to kEC column elements per thread per level (R <= 128, 1024 threads):
+  // element e = threadIdx.x + i nt of the half x m column pass, 2 outputs each
+  constexpr int kEC = RMAX * RMAX / 2 / 1024 > 0 ? RMAX * RMAX / 2 / 1024 : 1;
   for (int m = R; m > m0; m >>= 1) {
     const int half = m >> 1, lm = __builtin_ctz(m), lh = lm - 1;
+    // epilogue operands of this level's outputs, fetched before the passes so
+    // that their latency overlaps the LDS work
+    EpiLoad el[2 * kEC];
+#pragma unroll
+    for (int i = 0; i < kEC; ++i) {
+      const int e = threadIdx.x + i * nt;
+      if (e < half * m) {
+        const int k = e >> lm, c = e & (m - 1);
+        if (c >= half) el[2 * i] = epi_fetch(pr, io, epi, iter, off + k * n + c);
+        el[2 * i + 1] = epi_fetch(pr, io, epi, iter, off + (half + k) * n + c);
+      }
+    }
     for (int e = threadIdx.x; e < m * half; e += nt) {  // rows: A -> B
       const int r = e >> lh, k = e & (half - 1);
       const float* Ar = A + (r << lr);
@@ -558,38 +570,22 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
     }
     __syncthreads();
     const int j = lm - 1;
-    for (int e0 = threadIdx.x; e0 < half * m; e0 += 2 * nt) {  // columns: B -> A, 2 per thread
-      int epos[4];
-      float eval[4];
-      EpiLoad el[4];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int e = e0 + u * nt;
-        epos[2 * u] = epos[2 * u + 1] = -1;
-        if (e < half * m) {
-          const int k = e >> lm, c = e & (m - 1);
-          float a = 0.f, d = 0.f;
+    for (int i = 0; i < kEC; ++i) {  // columns: B -> A and the epilogue of both outputs
+      const int e = threadIdx.x + i * nt;
+      if (e < half * m) {
+        const int k = e >> lm, c = e & (m - 1);
+        float a = 0.f, d = 0.f;
 #pragma unroll
-          for (int i = 0; i < 6; ++i) {
-            const float v = B[(((2 * k + i) & (m - 1)) << lr) + c];
-            a += F.h[i] * v;
-            d += F.g[i] * v;
-          }
-          if (c >= half) {
-            epos[2 * u] = off + k * n + c;
-            eval[2 * u] = a * ly.inv_delta;
-          }
-          epos[2 * u + 1] = off + (half + k) * n + c;
-          eval[2 * u + 1] = d * ly.inv_delta;
-          A[(k << lr) + c] = a;  // rows >= half of A are no longer read
+        for (int q = 0; q < 6; ++q) {
+          const float v = B[(((2 * k + q) & (m - 1)) << lr) + c];
+          a += F.h[q] * v;
+          d += F.g[q] * v;
         }
+        if (c >= half) epi_finish(pr, ly, io, epi, off + k * n + c, j, a * ly.inv_delta, el[2 * i], acc);
+        epi_finish(pr, ly, io, epi, off + (half + k) * n + c, j, d * ly.inv_delta, el[2 * i + 1], acc);
+        A[(k << lr) + c] = a;  // rows >= half of A are no longer read
       }
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (epos[k] >= 0) el[k] = epi_fetch(pr, io, epi, iter, epos[k]);
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (epos[k] >= 0) epi_finish(pr, ly, io, epi, epos[k], j, eval[k], el[k], acc);
     }
     __syncthreads();
   }
@@ -614,7 +610,7 @@ __global__ __launch_bounds__(256) void k_pgamma(const ProbDev* P, const LayerDev
                                                 const IoDev* IO, const Tile* tiles, int mode) {
   __shared__ float V[(kTileS + 1) * (kTileS + 1)];
   __shared__ float sh[4 * 4];
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const WfsDev& w = WD[pr.wfs0 + t.item];
   const IoDev& io = IO[t.prob];
@@ -622,6 +618,7 @@ __global__ __launch_bounds__(256) void k_pgamma(const ProbDev* P, const LayerDev
   const int N = w.N, nc = w.nc;
   const int i0 = t.ty * kTileS, j0 = t.tx * kTileS;
   constexpr int CW = kTileS + 1;
+  typedef const int __attribute__((address_space(1)))* gptr_i;
   for (int e = threadIdx.x; e < CW * CW; e += blockDim.x) {
     const int li = e / CW, lj = e - li * CW;
     const int i = i0 + li, j = j0 + lj;
@@ -630,11 +627,11 @@ __global__ __launch_bounds__(256) void k_pgamma(const ProbDev* P, const LayerDev
       for (int l = 0; l < pr.L; ++l) {
         const LayerDev& ly = LD[pr.layer0 + l];
         const int base = w.tab_off + l * w.tab_stride;
-        const int* it = pr.itab + base;
-        const float* ft = pr.ftab + base;
+        const gptr_i it = (gptr_i)(pr.itab + base);
+        const gptr_f ft = (gptr_f)(pr.ftab + base);
         const int qy = it[i], qx = it[nc + j];
         const float wy = ft[2 * nc + i], wx = ft[3 * nc + j];
-        const float* ph = phi + ly.off + qy * ly.n + qx;
+        const gptr_f ph = (gptr_f)(phi + ly.off + qy * ly.n + qx);
         const float top = (1.f - wx) * ph[0] + wx * ph[1];
         const float bot = (1.f - wx) * ph[ly.n] + wx * ph[ly.n + 1];
         v += (1.f - wy) * top + wy * bot;
@@ -695,7 +692,7 @@ __global__ __launch_bounds__(256) void k_pgamma(const ProbDev* P, const LayerDev
 __global__ __launch_bounds__(256) void k_slopes_in(const ProbDev* P, const WfsDev* WD, const IoDev* IO,
                                                    const Tile* tiles) {
   __shared__ float sh[16];
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const WfsDev& w = WD[pr.wfs0 + t.item];
   const IoDev& io = IO[t.prob];
@@ -739,7 +736,7 @@ __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* 
   __shared__ float YX[SW * SW];
   __shared__ float YY[SW * SW];
   __shared__ float mean[4];
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const WfsDev& w = WD[pr.wfs0 + t.item];
   const int N = w.N, nc = w.nc;
@@ -834,113 +831,126 @@ __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* 
 
 // ------------------------------------------------ propagation adjoint (gather)
 // Node (p, q) of a layer gathers from every sensor the corners whose bilinear
-// cell touches it, weighted by the hat function of the forward interpolation:
-//   phi(p, q) = sum_g sum_{i,j} hat(t_i - p) hat(t_j - q) v_g(i, j),
-// t = t0 + rho k the corner coordinate in node units.  The corners of a node
-// are those strictly within one node spacing, found arithmetically (the
-// centre c = (p - t0) / rho in FP64, the weights 1 - rho |k - c| in FP32),
-// so every corner load is independent: no tables, no dependent chains.  At
-// most K = 2 (rho >= 1) or 3 (rho >= 2/3) corners per axis; finer sampling
-// takes a general loop.  Tile = 32x32 nodes, 4 per thread along a column.
+// cell touches it, weighted by the transpose of the forward interpolation:
+//   phi(p, q) = sum_g sum_{i,j} hat_y(i, p) hat_x(j, q) v_g(i, j).
+// The hats are precomputed per (sensor, layer) on the host (HatEnt: first
+// corner and K = 2 or 3 weights per node row and per node column), so the
+// kernel does no index arithmetic beyond the taps.  Tile = 4 RPT node rows x
+// 64 node columns: lane = column, wave w owns rows w + 4u (u < RPT, RPT = 4 or
+// 8 rows per thread), so a row's hat is uniform across the wave (scalar loads).  Sensors whose
+// footprint misses the tile are skipped (tile mask).  Sensors sampling the
+// layer finer than 2/3 of its spacing (kmax = 0) take a general loop.
 // No atomics: every node is written once.
-template <int K>
-struct Hat {
-  int lo, cnt;
-  float w[K];
-};
-
-template <int K>
-__device__ __forceinline__ Hat<K> hat(double t0, double rho, double inv_rho, int nc, int p) {
-  Hat<K> h;
-  const double c = ((double)p - t0) * inv_rho;
-  int lo = (int)floor(c - inv_rho) + 1, hi = (int)ceil(c + inv_rho) - 1;
-  lo = max(lo, 0);
-  hi = min(hi, nc - 1);
-  h.lo = lo;
-  h.cnt = max(0, min(hi - lo + 1, K));
-  const float r = (float)rho;
+template <int RPT>
+__device__ __forceinline__ void pt_general(const GLPar& gp, const float* vadj, int q, int p0, int n,
+                                           float acc[RPT]) {
+  const double cx = ((double)q - gp.t0x) * gp.inv_rho;
+  const int jlo = max((int)floor(cx - gp.inv_rho) + 1, 0), jhi = min((int)ceil(cx + gp.inv_rho) - 1, gp.nc - 1);
+  if (jhi < jlo) return;
+  const float* va = vadj + gp.v_off;
+  const float r = (float)gp.rho;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const float d = (float)((double)(lo + k) - c);
-    h.w[k] = (k < h.cnt) ? fmaxf(0.f, 1.f - r * fabsf(d)) : 0.f;
-  }
-  return h;
-}
-
-template <int K>
-__device__ __forceinline__ void pt_sensor(const GLPar& gp, const float* vadj, int q, int pbase, float acc[4]) {
-  const Hat<K> hx = hat<K>(gp.t0x, gp.rho, gp.inv_rho, gp.nc, q);
-  if (hx.cnt == 0) return;
-  Hat<K> hy[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) hy[u] = hat<K>(gp.t0y, gp.rho, gp.inv_rho, gp.nc, pbase + 8 * u);
-  const float* va = vadj + gp.v_off + hx.lo;
-  float v[4][K][K];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int a = 0; a < K; ++a)
-#pragma unroll
-      for (int b = 0; b < K; ++b)
-        v[u][a][b] = (a < hy[u].cnt && b < hx.cnt) ? va[(hy[u].lo + a) * gp.nc + b] : 0.f;
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < RPT; ++u) {
+    const int p = p0 + 4 * u;
+    if (p >= n) break;
+    const double cy = ((double)p - gp.t0y) * gp.inv_rho;
+    const int ilo = max((int)floor(cy - gp.inv_rho) + 1, 0), ihi = min((int)ceil(cy + gp.inv_rho) - 1, gp.nc - 1);
     float s = 0.f;
-#pragma unroll
-    for (int a = 0; a < K; ++a) {
-      float r = 0.f;
-#pragma unroll
-      for (int b = 0; b < K; ++b) r += hx.w[b] * v[u][a][b];
-      s += hy[u].w[a] * r;
+    for (int i = ilo; i <= ihi; ++i) {
+      const float wy = fmaxf(0.f, 1.f - r * fabsf((float)((double)i - cy)));
+      float rr = 0.f;
+      for (int j = jlo; j <= jhi; ++j) rr += fmaxf(0.f, 1.f - r * fabsf((float)((double)j - cx))) * va[i * gp.nc + j];
+      s += wy * rr;
     }
     acc[u] += s;
   }
 }
 
+
+// Wave-uniform read of propagation parameters, which no kernel writes while it
+// runs: through the constant address space, i.e. scalar loads.
+__device__ __forceinline__ GLPar load_glpar(const GLPar* p) {
+  typedef const __attribute__((address_space(4))) double* cdbl;
+  typedef const __attribute__((address_space(4))) int* cint;
+  const cdbl d = (cdbl)p;
+  const cint i = (cint)(d + 4);
+  GLPar g;
+  g.t0y = d[0];
+  g.t0x = d[1];
+  g.rho = d[2];
+  g.inv_rho = d[3];
+  g.nc = i[0];
+  g.v_off = i[1];
+  g.kmax = i[2];
+  g.hat_off = i[3];
+  return g;
+}
+
+// Taps of the RPT rows of this thread: every row's hat first (wave-uniform,
+// scalar loads), then all K x K corner loads of all rows, then the sums.
+template <int K, int RPT>
+__device__ __forceinline__ void pt_taps(const HatEnt* __restrict__ hy_tab, const HatEnt& hx, gptr_f va, int nc,
+                                        int p0, int n, float acc[RPT]) {
+  HatEnt hy[RPT];
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) hy[u] = hy_tab[min(p0 + 4 * u, n - 1)];
+  float v[RPT][K][K];
+#pragma unroll
+  for (int u = 0; u < RPT; ++u)
+#pragma unroll
+    for (int a = 0; a < K; ++a)
+#pragma unroll
+      for (int b = 0; b < K; ++b) v[u][a][b] = va[(hy[u].lo + a) * nc + b];
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    float s = 0.f;
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+      float r = 0.f;
+#pragma unroll
+      for (int b = 0; b < K; ++b) r = fmaf(hx.w[b], v[u][a][b], r);
+      s = fmaf(hy[u].w[a], r, s);
+    }
+    acc[u] += s;
+  }
+}
+
+// Tile = 4 RPT node rows x 64 node columns; sensors whose footprint misses
+// the tile are skipped (tile mask).
+template <int RPT>
 __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD, const WfsDev* WD, const IoDev* IO,
-                                            const Tile* tiles, int mode) {
-  const Tile t = tiles[blockIdx.x];
+                                            const Tile* tiles, const HatEnt* __restrict__ hats, int mode) {
+  const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[pr.layer0 + t.item];
   const IoDev& io = IO[t.prob];
   const int n = ly.n;
-  const int q = t.tx * kTileN + (threadIdx.x & 31);
-  const int pbase = t.ty * kTileN + (threadIdx.x >> 5);
+  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int q = t.tx * kPtW + (threadIdx.x & 63);
+  const int p0 = t.ty * 4 * RPT + wv;
   if (q >= n) return;  // no barriers in this kernel
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int g = 0; g < pr.G; ++g) {
-    const GLPar gp = pr.gl[g * pr.L + t.item];
-    if (gp.kmax == 2) {
-      pt_sensor<2>(gp, pr.vadj, q, pbase, acc);
-    } else if (gp.kmax == 3) {
-      pt_sensor<3>(gp, pr.vadj, q, pbase, acc);
-    } else {  // sensor sampling the layer finer than 2/3 of its spacing
-      const double cx = ((double)q - gp.t0x) * gp.inv_rho;
-      const int jlo = max((int)floor(cx - gp.inv_rho) + 1, 0), jhi = min((int)ceil(cx + gp.inv_rho) - 1, gp.nc - 1);
-      if (jhi < jlo) continue;
-      const float* va = pr.vadj + gp.v_off;
-      const float r = (float)gp.rho;
+  float acc[RPT];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int p = pbase + 8 * u;
-        const double cy = ((double)p - gp.t0y) * gp.inv_rho;
-        const int ilo = max((int)floor(cy - gp.inv_rho) + 1, 0), ihi = min((int)ceil(cy + gp.inv_rho) - 1, gp.nc - 1);
-        float s = 0.f;
-        for (int i = ilo; i <= ihi; ++i) {
-          const float wy = fmaxf(0.f, 1.f - r * fabsf((float)((double)i - cy)));
-          float rr = 0.f;
-          for (int j = jlo; j <= jhi; ++j)
-            rr += fmaxf(0.f, 1.f - r * fabsf((float)((double)j - cx))) * va[i * gp.nc + j];
-          s += wy * rr;
-        }
-        acc[u] += s;
-      }
+  for (int u = 0; u < RPT; ++u) acc[u] = 0.f;
+  for (int g = 0; g < pr.G; ++g) {
+    if (pr.G <= 32 && !((t.mask >> g) & 1)) continue;  // footprint misses the tile
+    const GLPar gp = load_glpar(pr.gl + g * pr.L + t.item);
+    if (gp.kmax == 0) {
+      pt_general<RPT>(gp, pr.vadj, q, p0, n, acc);
+      continue;
     }
+    const HatEnt* __restrict__ tb = hats + gp.hat_off;  // [rows n][columns n]
+    const HatEnt hx = tb[n + q];
+    const gptr_f va = (gptr_f)(pr.vadj + gp.v_off + hx.lo);
+    if (gp.kmax == 2)
+      pt_taps<2, RPT>(tb, hx, va, gp.nc, p0, n, acc);
+    else
+      pt_taps<3, RPT>(tb, hx, va, gp.nc, p0, n, acc);
   }
   float* dst = (mode == PT_USER) ? io.out : pr.phiadj;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int p = pbase + 8 * u;
+  for (int u = 0; u < RPT; ++u) {
+    const int p = p0 + 4 * u;
     if (p < n) dst[ly.off + p * n + q] = acc[u];
   }
 }
@@ -951,7 +961,7 @@ __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD
 __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* IO, const Tile* tiles, int iter) {
   __shared__ double sh[4];
   __shared__ double salpha;
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const IoDev& io = IO[t.prob];
   if (threadIdx.x < 64) {
@@ -1013,7 +1023,7 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
 // transform's count), each over a contiguous float4 range.
 __global__ __launch_bounds__(256) void k_solve_init(const ProbDev* P, const IoDev* IO, const Tile* tiles) {
   __shared__ double sh[4];
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const IoDev& io = IO[t.prob];
   const int n4 = pr.n_c / 4, ns = pr.n_slots_fdwt;
@@ -1045,7 +1055,7 @@ __global__ __launch_bounds__(256) void k_solve_init(const ProbDev* P, const IoDe
 __global__ __launch_bounds__(256) void k_grad_height(const ProbDev* P, const LayerDev* LD, const WfsDev* WD,
                                                      const Tile* tiles, int term) {
   __shared__ double sh[4];
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const WfsDev& w = WD[pr.wfs0 + t.item];
   const int l = t.level;
@@ -1085,7 +1095,7 @@ __global__ __launch_bounds__(256) void k_grad_height(const ProbDev* P, const Lay
 __global__ __launch_bounds__(256) void k_grad_prior(const ProbDev* P, const LayerDev* LD, const GradIo* GIO,
                                                     const Tile* tiles) {
   __shared__ double sh[4];
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[pr.layer0 + t.item];
   const GradIo& g = GIO[t.prob];
@@ -1129,7 +1139,7 @@ __global__ __launch_bounds__(64) void k_grad_final(const ProbDev* P, const Layer
 //   u_k = M sum_grid grid(x + h theta_k).   Tile = 16x16 corners.
 __global__ __launch_bounds__(256) void k_fit_fwd(const ProbDev* P, const LayerDev* LD, const WfsDev* WD,
                                                  const Tile* tiles) {
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const WfsDev& w = WD[pr.wfs0 + t.item];
   const int nc = w.nc;
@@ -1257,7 +1267,11 @@ void launch_gammaT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode)
   if (ntiles > 0) k_gammaT<<<ntiles, 256, 0, a.stream>>>(a.P, a.W, tiles, mode);
 }
 void launch_pT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
-  if (ntiles > 0) k_pT<<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, mode);
+  if (ntiles <= 0) return;
+  if (a.pt_rows == 8)
+    k_pT<8><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, mode);
+  else
+    k_pT<4><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, mode);
 }
 void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter) {
   if (ntiles > 0) k_update<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles, iter);

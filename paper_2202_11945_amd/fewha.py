@@ -42,9 +42,15 @@ def _ptr64(t, n):
     return c_void_p(t.data_ptr())
 
 
-def _tuning(dwt_resident):
+def _tuning(tuning):
+    """fewha_tuning from an int (the resident transform side) or a dict with
+    keys dwt_resident and pt_rows (missing = default)."""
     t = _abi.fewha_tuning()
-    t.dwt_resident = int(dwt_resident)
+    if isinstance(tuning, dict):
+        t.dwt_resident = int(tuning.get("dwt_resident", 0))
+        t.pt_rows = int(tuning.get("pt_rows", 0))
+    else:
+        t.dwt_resident = int(tuning)
     return t
 
 
@@ -58,8 +64,9 @@ class Context:
 
     ``cfg`` is a configuration dict (see ``synthetic.configs``); ``device``
     is the HIP device index or -1 for a host-only context (tables only);
-    ``tuning`` the resident transform side of the context's own plan
-    (32, 64 or 128; None = default)."""
+    ``tuning`` the launch shapes of the context's own plan: the resident
+    transform side (32, 64 or 128) or a dict {"dwt_resident", "pt_rows"}
+    (None = defaults)."""
 
     def __init__(self, cfg, device=0, tuning=None):
         self.cfg = cfg
@@ -234,7 +241,7 @@ class Context:
 
 class Batch:
     """fewha_batch_create over finalized device contexts; ``tuning`` is the
-    batch plan's resident transform side (see ``autotune``; None = default)."""
+    batch plan's launch shapes, as for Context (see ``autotune``)."""
 
     def __init__(self, ctxs, tuning=None):
         self.ctxs = list(ctxs)

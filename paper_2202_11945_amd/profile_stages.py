@@ -4,7 +4,7 @@ whose byte counters calibrate the hardware FETCH_SIZE / WRITE_SIZE reading.
 
 Run under rocprofv3, e.g.
   rocprofv3 --pmc FETCH_SIZE -d OUT -o fetch --output-format csv -- \
-      python3 -m paper_2202_11945_amd.profile_stages --batch 64
+      python3 paper_2202_11945_amd/profile_stages.py --batch 64 --tuned
 """
 
 import argparse
@@ -22,6 +22,9 @@ def main():
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--iters", type=int, default=4)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--res", type=int, default=0, help="resident transform side (0 = default)")
+    ap.add_argument("--pt-rows", type=int, default=0, help="node rows per thread of P^T (0 = default)")
+    ap.add_argument("--tuned", action="store_true", help="launch shapes from the autotuner (as bench.py)")
     a = ap.parse_args()
     import torch
 
@@ -30,7 +33,13 @@ def main():
 
     cfg = get_config(a.config)
     ctxs = [fw.Context(cfg, device=0) for _ in range(a.batch)]
-    batch = fw.Batch(ctxs)
+    tuning = {"dwt_resident": a.res, "pt_rows": a.pt_rows}
+    if a.tuned:
+        from paper_2202_11945_amd import autotune
+        rec = autotune.tune(ctxs, a.iters)
+        tuning = {"dwt_resident": rec["dwt_resident"], "pt_rows": rec["pt_rows"]}
+    print("tuning %d/%d" % (tuning["dwt_resident"] or 128, tuning["pt_rows"] or 4), flush=True)
+    batch = fw.Batch(ctxs, tuning=tuning)
     dev = torch.device("cuda:0")
     slopes = [torch.from_numpy(random_vector(ctxs[0].n_slopes, 5, k)).to(dev) for k in range(a.batch)]
     states = [torch.zeros(c.n_state, device=dev) for c in ctxs]

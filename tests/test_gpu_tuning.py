@@ -10,18 +10,21 @@ from oracle.operators import System
 from oracle.solver import State, frame
 from synthetic import get_config, random_vector
 from synthetic.configs import batch_mix
+from test_gpu_configs import check_frames
 from test_gpu_parity import LAYER_TOL, OP_TOL, rel, synth_slopes, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("name,res", [("small", 32), ("mid", 32), ("maory_like", 32), ("maory_like", 64)])
+@pytest.mark.parametrize("name,res", [("small", 32), ("mid", 32), ("maory_like", 32), ("maory_like", 64),
+                                      ("small", {"pt_rows": 8}), ("maory_like", {"dwt_resident": 64, "pt_rows": 8}),
+                                      ("small_fit", {"pt_rows": 8})])
 def test_frame_parity_with_resident_side(gpu_lib, systems, name, res):
     import torch
     S = systems(name)
     print("\n[gpu-tune]", name, "resident", res, flush=True)
     ctx = gpu_lib.Context(get_config(name), device=0, tuning=res)
-    x = random_vector(S.geom.n_coeff, 300, res)
+    x = random_vector(S.geom.n_coeff, 300, len(str(res)))
     assert rel(to_host(ctx.apply_M(to_dev(x))), S.apply_M(x)) <= OP_TOL
     st = torch.zeros(ctx.n_state, device="cuda")
     lay = torch.empty(ctx.n_coeff, device="cuda")
@@ -45,18 +48,13 @@ def test_tuned_mixed_batch(gpu_lib):
     slopes = [to_dev(synth_slopes(S, k)) for k, S in enumerate(systems)]
     states = [torch.zeros(c.n_state, device="cuda") for c in ctxs]
     lays = [torch.empty(c.n_coeff, device="cuda") for c in ctxs]
-    for _ in range(2):
+    # frame 1 from the zero state, frame 2 warm-started from the GPU's own state;
+    # each compared with the oracle's frame from the same (FP32) state
+    def run():
         batch.reconstruct(slopes, states, lays, iters=6, use_graph=True)
-    torch.cuda.synchronize()
-    for k, S in enumerate(systems):
-        st = State(S.geom.n_coeff, S.geom.n_coeff)
-        s = synth_slopes(S, k).astype(np.float64)
-        for _ in range(2):
-            st, phi = frame(S, st, s, iters=6)
-        got = to_host(lays[k])
-        o = S.geom.layer_off
-        for l in range(S.Lc):
-            assert rel(got[o[l]:o[l + 1]], phi[o[l]:o[l + 1]]) <= 2 * LAYER_TOL, (k, l)
+
+    check_frames(systems, slopes, states, lays, run)
+    check_frames(systems, slopes, states, lays, run)
     batch.close()
 
 
@@ -79,6 +77,7 @@ def test_autotuner_picks_admissible_side_and_caches(gpu_lib, tmp_path, monkeypat
     print("\n[gpu-tune] autotuner on 4 small problems", flush=True)
     rec = autotune.tune([ctx] * 4, 4, steps=3)
     assert rec["dwt_resident"] in autotune.admissible([ctx]) and not rec["cached"]
-    assert set(rec["us"]) == {str(r) for r in autotune.admissible([ctx])}
+    assert set(rec["us"]) == {"%d/%d" % (r, p) for r in autotune.admissible([ctx]) for p in autotune.PT_ROWS}
+    assert rec["pt_rows"] in autotune.PT_ROWS
     again = autotune.tune([ctx] * 4, 4, steps=3)
     assert again["cached"] and again["dwt_resident"] == rec["dwt_resident"]

@@ -134,6 +134,10 @@ def test_tuning_arguments_are_validated(lib):
     t = _tuning(32)
     t.reserved[3] = 1
     assert _abi.fewha_set_tuning(h, byref(t)) == -1
+    for bad_rows in (2, 6, 16, -4):
+        assert _abi.fewha_set_tuning(h, byref(_tuning({"pt_rows": bad_rows}))) == -1
     for good in (0, 32, 64, 128):
         assert _abi.fewha_set_tuning(h, byref(_tuning(good))) == 0
+    for rows in (0, 4, 8):
+        assert _abi.fewha_set_tuning(h, byref(_tuning({"dwt_resident": 64, "pt_rows": rows}))) == 0
     _abi.fewha_destroy(h)
