@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdint>
@@ -12,6 +13,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "fewha_internal.h"
@@ -70,6 +72,7 @@ struct Plan {
   std::vector<float*> rbuf;                  // per problem: residual of a refined solve
   GradIo* dGIO = nullptr;
   const HatEnt* dHat = nullptr;              // hat tables of the propagation adjoint
+  const BandRec* dBand = nullptr;            // band records of the propagation adjoint
   std::vector<float*> sstate;                // per problem: [x | unused | r] of a solve
   double* rho_host = nullptr;                // pinned readback: 2 n_dots doubles per problem
   std::vector<long> rho_off;
@@ -151,6 +154,72 @@ void append_hats(GLPar& gp, int n, std::vector<HatEnt>& out) {
   }
 }
 
+// Propagation-adjoint tables of one (sensor, layer) pair: hat tables with K =
+// 2 or 3 corners per node and axis when the corner spacing is at least 2/3 of
+// the node spacing, and one band record per kBandRows node rows, whose corner
+// rows must fit pt_band(K, kBandRows); otherwise kmax = 0, the general
+// gather.  Pairs of the same geometry (every problem of a batch of one
+// system) share one copy of the tables.
+struct HatTables {
+  std::vector<HatEnt> hats;
+  std::vector<BandRec> bands;
+  std::map<std::tuple<double, double, double, int, int>, std::array<int, 3>> seen;  // -> kmax, hat_off, band_off
+};
+
+void set_hats(GLPar& gp, int n, HatTables& T) {
+  gp.kmax = gp.rho >= 1.0 ? 2 : (gp.rho >= 2.0 / 3.0 ? 3 : 0);
+  gp.hat_off = gp.band_off = -1;
+  if (gp.kmax > 0 && gp.nc < gp.kmax) gp.kmax = 0;  // tiny sensor
+  if (gp.kmax == 0) return;
+  const auto key = std::make_tuple(gp.t0y, gp.t0x, gp.rho, gp.nc, n);
+  const auto hit = T.seen.find(key);
+  if (hit != T.seen.end()) {
+    gp.kmax = hit->second[0];
+    gp.hat_off = hit->second[1];
+    gp.band_off = hit->second[2];
+    return;
+  }
+  const int K = gp.kmax, SB = pt_band(K, kBandRows);
+  append_hats(gp, n, T.hats);
+  std::vector<BandRec> recs;
+  bool fits = true;
+  for (int p = 0; p < n && fits; p += kBandRows) {
+    const HatEnt* rows = T.hats.data() + gp.hat_off;
+    const int last = std::min(p + kBandRows - 1, n - 1);
+    const int ilo = rows[p].lo;
+    if (rows[last].lo + K - ilo > SB) {
+      fits = false;
+      break;
+    }
+    // first band row: the group's first corner, moved down so that all SB
+    // rows lie in the grid (a grid of fewer rows starts at 0 and repeats its
+    // last row)
+    const int base = gp.nc >= SB ? std::max(0, std::min(ilo, gp.nc - SB)) : 0;
+    BandRec r{};
+    for (int s = 0; s < kBandMax; ++s)
+      r.so[s] = std::min(base + std::min(s, SB - 1), gp.nc - 1) * gp.nc * (int)sizeof(float);
+    for (int u = 0; u < kBandRows && p + u < n; ++u)
+      for (int k = 0; k < K; ++k) {
+        const int s = rows[p + u].lo + k - base;
+        if (s < 0 || s >= SB || rows[p + u].lo + k > gp.nc - 1) {
+          fits = false;
+          break;
+        }
+        r.w[u][s] = rows[p + u].w[k];
+      }
+    recs.push_back(r);
+  }
+  if (!fits) {
+    T.hats.resize(gp.hat_off);
+    gp.kmax = 0;
+    gp.hat_off = -1;
+  } else {
+    gp.band_off = (int)T.bands.size();
+    T.bands.insert(T.bands.end(), recs.begin(), recs.end());
+  }
+  T.seen[key] = {gp.kmax, gp.hat_off, gp.band_off};
+}
+
 // Byte-offset carving of the arena (256-byte aligned pieces).
 struct Carver {
   size_t off = 0;
@@ -209,7 +278,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   std::vector<ProbLayout> lay(P.nprob);
   Carver cv;
   std::vector<Tile> t_idwt_res, t_fdwt_res, t_pg, t_gt, t_pt, t_upd, t_sinit, t_gprior, t_ghgt, t_r64wfs, t_r64pt;
-  std::vector<HatEnt> hats;  // hat tables of every problem and fitting view, one array per plan
+  HatTables hats;  // hat tables and band records of every problem and fitting view, one set per plan
   std::vector<std::vector<Tile>> t_r64inv(kMaxLevelsJ), t_r64fwd(kMaxLevelsJ);
   std::vector<std::vector<double>> cinv64(P.nprob), ftab64(P.nprob);
   std::vector<std::vector<Tile>> t_idwt_glob, t_fdwt_glob;
@@ -348,10 +417,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
         gp.inv_rho = 1.0 / gp.rho;
         gp.nc = wh.d.n_subap + 1;
         gp.v_off = P.hW[pd.wfs0 + g].v_off;
-        gp.kmax = gp.rho >= 1.0 ? 2 : (gp.rho >= 2.0 / 3.0 ? 3 : 0);
-        gp.hat_off = -1;
-        if (gp.kmax > 0 && gp.nc >= gp.kmax) append_hats(gp, lh.d.n, hats);
-        if (gp.kmax > 0 && gp.nc < gp.kmax) gp.kmax = 0;  // tiny sensor: general gather
+        set_hats(gp, lh.d.n, hats);
         glp[k][(size_t)g * L + l] = gp;
       }
     // tiles
@@ -555,10 +621,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
         gp.inv_rho = 1.0 / gp.rho;
         gp.nc = nc;
         gp.v_off = d * nc * nc;
-        gp.kmax = gp.rho >= 1.0 ? 2 : (gp.rho >= 2.0 / 3.0 ? 3 : 0);
-        gp.hat_off = -1;
-        if (gp.kmax > 0 && gp.nc >= gp.kmax) append_hats(gp, dm.n_act, hats);
-        if (gp.kmax > 0 && gp.nc < gp.kmax) gp.kmax = 0;
+        set_hats(gp, dm.n_act, hats);
         fl.glp.push_back(gp);
       }
     ProbDev vL{}, vD{};
@@ -642,7 +705,8 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   const size_t oIO = cv.take(sizeof(IoDev) * P.nprob_all);
   const size_t oIOp = cv.take(sizeof(IoDev) * P.nprob_all);
   const size_t oGIO = cv.take(sizeof(GradIo) * P.nprob_all);
-  const size_t oHat = cv.take(sizeof(HatEnt) * std::max<size_t>(hats.size(), 1));
+  const size_t oHat = cv.take(sizeof(HatEnt) * std::max<size_t>(hats.hats.size(), 1));
+  const size_t oBand = cv.take(sizeof(BandRec) * std::max<size_t>(hats.bands.size(), 1));
   const size_t oF = cv.take(sizeof(FitDev) * std::max<size_t>(hF.size(), 1));
   const size_t oT = cv.take(sizeof(Tile) * std::max<size_t>(P.hT.size(), 1));
   P.arena_bytes = cv.off;
@@ -743,7 +807,11 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   P.dIOprof = (IoDev*)(base + oIOp);
   P.dGIO = (GradIo*)(base + oGIO);
   P.dHat = (const HatEnt*)(base + oHat);
-  if (!hats.empty()) HIP_TRY(hipMemcpy(base + oHat, hats.data(), sizeof(HatEnt) * hats.size(), hipMemcpyHostToDevice));
+  P.dBand = (const BandRec*)(base + oBand);
+  if (!hats.hats.empty())
+    HIP_TRY(hipMemcpy(base + oHat, hats.hats.data(), sizeof(HatEnt) * hats.hats.size(), hipMemcpyHostToDevice));
+  if (!hats.bands.empty())
+    HIP_TRY(hipMemcpy(base + oBand, hats.bands.data(), sizeof(BandRec) * hats.bands.size(), hipMemcpyHostToDevice));
   P.dT = (Tile*)(base + oT);
   // work lists of the FP64 residual chain (device addresses: after P.dT is set)
   {
@@ -821,6 +889,7 @@ LaunchArgs args(const Plan& P, hipStream_t s, const IoDev* io) {
   a.res_max = P.res_max;
   a.pt_rows = P.pt_rows;
   a.hats = P.dHat;
+  a.bands = P.dBand;
   return a;
 }
 

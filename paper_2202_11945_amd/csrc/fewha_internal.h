@@ -19,6 +19,13 @@ constexpr int kTileS = 16;        // subaperture / corner tile side of the senso
 constexpr int kTileN = 32;        // node tile side of the FP64 propagation adjoint
 constexpr int kPtW = 64;          // propagation adjoint tile: 64 node columns (one per lane) by
                                   // 4 x rows-per-thread node rows (tuning: 4 or 8 rows per thread)
+// Corner rows (band) that rpt consecutive node rows of the propagation adjoint
+// may touch with K corners per node: consecutive first corners differ by at
+// most one (K = 2: corner spacing >= node spacing) or two (K = 3: spacing
+// >= 2/3 of it); the host checks every row group against this bound.
+constexpr int pt_band(int K, int rpt) { return K == 2 ? rpt + 2 : (3 * (rpt - 1)) / 2 + K + 2; }
+constexpr int kBandRows = 4;                    // node rows of one band record
+constexpr int kBandMax = pt_band(3, kBandRows);  // corner rows of the widest band
 constexpr int kUpdChunk = 2048;   // coefficients per workgroup of the vector update
 constexpr int kDotRing = 256;     // PCG iterations whose inner products are kept (ring, power of two)
 constexpr int kGradChunk = 2048;  // coefficients per workgroup of the prior-term reductions
@@ -89,7 +96,9 @@ struct WfsDev {
 struct GLPar {
   double t0y, t0x, rho, inv_rho;
   int nc, v_off, kmax;
-  int hat_off;  // hat tables of this pair: [rows n][columns n] HatEnt in the plan's hat array
+  int hat_off;   // hat tables of this pair: [rows n][columns n] HatEnt in the plan's hat array
+  int band_off;  // band records of this pair (one per kBandRows node rows) in the plan's band array
+  int pad_;
 };
 
 // The corners of one node along one axis: corner lo + k has weight w[k]
@@ -100,6 +109,17 @@ struct HatEnt {
   int lo;
   float w[3];
 };
+
+// Separable propagation adjoint of kBandRows consecutive node rows and one
+// (sensor, layer) pair: the corner rows of the band (byte offsets in the
+// sensor's corner grid, clamped to the grid, so extra rows repeat a valid
+// row) and, per node row, the y hat weight of every band row (0 off the hat).
+struct BandRec {
+  int so[kBandMax];
+  float w[kBandRows][kBandMax];
+  int pad_[3];
+};
+static_assert(sizeof(BandRec) == 192, "band record: 48 dwords");
 
 // One problem.
 struct ProbDev {

@@ -32,7 +32,8 @@ struct LaunchArgs {
   Filter F;
   hipStream_t stream;
   int res_max;  // largest resident transform side of the plan (32, 64 or 128)
-  const HatEnt* hats;  // hat tables of the propagation adjoint (plan-wide)
+  const HatEnt* hats;     // hat tables of the propagation adjoint (plan-wide)
+  const BandRec* bands;   // band records of the propagation adjoint (plan-wide)
   int pt_rows;         // node rows per thread of the propagation adjoint (4 or 8)
 };
 

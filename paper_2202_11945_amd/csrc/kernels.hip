@@ -836,11 +836,15 @@ __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* 
 // The hats are precomputed per (sensor, layer) on the host (HatEnt: first
 // corner and K = 2 or 3 weights per node row and per node column), so the
 // kernel does no index arithmetic beyond the taps.  Tile = 4 RPT node rows x
-// 64 node columns: lane = column, wave w owns rows w + 4u (u < RPT, RPT = 4 or
-// 8 rows per thread), so a row's hat is uniform across the wave (scalar loads).  Sensors whose
-// footprint misses the tile are skipped (tile mask).  Sensors sampling the
-// layer finer than 2/3 of its spacing (kmax = 0) take a general loop.
-// No atomics: every node is written once.
+// 64 node columns: lane = column, wave w owns the RPT consecutive rows
+// w RPT .. w RPT + RPT - 1 (RPT = 4 or 8), so a row's hat is uniform across
+// the wave (scalar loads).  The gather is separable: the corner rows that the
+// RPT node rows touch form one band (first corners never decrease along an
+// axis), each band row is interpolated along x once and reused by every node
+// row whose hat covers it.  Sensors whose footprint misses the tile are
+// skipped (tile mask).  Sensors sampling the layer finer than 2/3 of its
+// spacing, or whose band would exceed the register budget (kmax = 0), take a
+// general loop.  No atomics: every node is written once.
 template <int RPT>
 __device__ __forceinline__ void pt_general(const GLPar& gp, const float* vadj, int q, int p0, int n,
                                            float acc[RPT]) {
@@ -851,7 +855,7 @@ __device__ __forceinline__ void pt_general(const GLPar& gp, const float* vadj, i
   const float r = (float)gp.rho;
 #pragma unroll
   for (int u = 0; u < RPT; ++u) {
-    const int p = p0 + 4 * u;
+    const int p = p0 + u;
     if (p >= n) break;
     const double cy = ((double)p - gp.t0y) * gp.inv_rho;
     const int ilo = max((int)floor(cy - gp.inv_rho) + 1, 0), ihi = min((int)ceil(cy + gp.inv_rho) - 1, gp.nc - 1);
@@ -886,40 +890,160 @@ __device__ __forceinline__ GLPar load_glpar(const GLPar* p) {
   return g;
 }
 
-// Taps of the RPT rows of this thread: every row's hat first (wave-uniform,
-// scalar loads), then all K x K corner loads of all rows, then the sums.
-template <int K, int RPT>
-__device__ __forceinline__ void pt_taps(const HatEnt* __restrict__ hy_tab, const HatEnt& hx, gptr_f va, int nc,
-                                        int p0, int n, float acc[RPT]) {
-  HatEnt hy[RPT];
+// Integer part of GLPar (corner grid side, offset, K, table offsets), all the
+// fast path needs; scalar loads like load_glpar.
+struct PtPar {
+  int nc, v_off, kmax, hat_off, band_off;
+};
+static_assert(offsetof(GLPar, nc) == 32 && offsetof(GLPar, band_off) == 48, "GLPar layout");
+__device__ __forceinline__ PtPar load_ptpar(const GLPar* p) {
+  typedef const __attribute__((address_space(4))) double* cdbl;
+  typedef const __attribute__((address_space(4))) int* cint;
+  const cint i = (cint)((cdbl)p + 4);
+  return PtPar{i[0], i[1], i[2], i[3], i[4]};
+}
+
+// Next sensor after g whose footprint meets the tile (G when none is left).
+__device__ __forceinline__ int pt_next(unsigned mask, int G, int g) {
+  if (G > 32) return g + 1;
+  const int f = g + 1;
+  const unsigned rest = f >= 32 ? 0u : (mask >> f) << f;
+  return rest ? __builtin_ctz(rest) : G;
+}
+
+// Band-row byte offsets of one band record (scalar loads).
+struct BandRows {
+  int so[kBandMax];
+};
+__device__ __forceinline__ BandRows load_rows(const BandRec* rec) {
+  typedef const __attribute__((address_space(4))) int* cint;
+  const cint p = (cint)rec;
+  BandRows r;
 #pragma unroll
-  for (int u = 0; u < RPT; ++u) hy[u] = hy_tab[min(p0 + 4 * u, n - 1)];
-  float v[RPT][K][K];
+  for (int s = 0; s < kBandMax; ++s) r.so[s] = p[s];
+  return r;
+}
+
+// Loads of one band: every band row once, K corners per lane (raw buffer
+// loads: lane offset vo from the column hat, row offset from the record).
+template <int K>
+__device__ __forceinline__ void pt_band_load(__amdgpu_buffer_rsrc_t rs, int vo, const BandRows& so,
+                                             float v[pt_band(K, kBandRows)][K]) {
 #pragma unroll
-  for (int u = 0; u < RPT; ++u)
+  for (int s = 0; s < pt_band(K, kBandRows); ++s)
 #pragma unroll
-    for (int a = 0; a < K; ++a)
+    for (int b = 0; b < K; ++b)
+      v[s][b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo + b * (int)sizeof(float), so.so[s], 0));
+}
+
+// Separable sums of kBandRows node rows: each band row interpolated along x
+// with the column hat, then node row u takes sum_s w[u][s] r[s] with the
+// record's y weights as scalar operands.  The record's zero weights add exact
+// zeros, so each sum equals the K-term sum over the node's hat.
+template <int K>
+__device__ __forceinline__ void pt_band_sum(const BandRec* rec, const HatEnt& hx,
+                                            const float v[pt_band(K, kBandRows)][K], float acc[kBandRows]) {
+  constexpr int SB = pt_band(K, kBandRows);
+  typedef const __attribute__((address_space(4))) BandRec* crec;
+  const crec br = (crec)rec;
+  float r[SB];
 #pragma unroll
-      for (int b = 0; b < K; ++b) v[u][a][b] = va[(hy[u].lo + a) * nc + b];
+  for (int s = 0; s < SB; ++s) {
+    float t = 0.f;
 #pragma unroll
-  for (int u = 0; u < RPT; ++u) {
-    float s = 0.f;
+    for (int b = 0; b < K; ++b) t = fmaf(hx.w[b], v[s][b], t);
+    r[s] = t;
+  }
 #pragma unroll
-    for (int a = 0; a < K; ++a) {
-      float r = 0.f;
+  for (int u = 0; u < kBandRows; ++u) {
+    float t = 0.f;
 #pragma unroll
-      for (int b = 0; b < K; ++b) r = fmaf(hx.w[b], v[u][a][b], r);
-      s = fmaf(hy[u].w[a], r, s);
-    }
-    acc[u] += s;
+    for (int s = 0; s < SB; ++s) t = fmaf(br->w[u][s], r[s], t);
+    acc[u] += t;
   }
 }
 
-// Tile = 4 RPT node rows x 64 node columns; sensors whose footprint misses
-// the tile are skipped (tile mask).
+// A sensor of 3 x 3 corners (2 x 2 subapertures, K = 2): the whole corner
+// grid in scalar registers, each lane picks its two taps per corner row by
+// selects, no vector memory traffic beyond the column hat.  The band record
+// of such a grid starts at corner row 0 and weights only rows 0..2.
+__device__ __forceinline__ void pt_tiny3(const float* vsens, const BandRec* rec, const HatEnt& hx,
+                                         float acc[kBandRows]) {
+  typedef const __attribute__((address_space(4))) float* cflt;
+  typedef const __attribute__((address_space(4))) BandRec* crec;
+  const cflt gv = (cflt)vsens;
+  const crec br = (crec)rec;
+  float V[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) V[i][j] = gv[3 * i + j];
+  const bool lo0 = hx.lo == 0;  // first corner 0 or 1 (clamped to nc - K)
+  float r[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float a = lo0 ? V[i][0] : V[i][1];
+    const float b = lo0 ? V[i][1] : V[i][2];
+    r[i] = fmaf(hx.w[1], b, fmaf(hx.w[0], a, 0.f));
+  }
+#pragma unroll
+  for (int u = 0; u < kBandRows; ++u) {
+    float t = 0.f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) t = fmaf(br->w[u][i], r[i], t);
+    acc[u] += t;
+  }
+}
+
+// What the sensor loop prefetches one sensor ahead (column hat, band-row
+// offsets of the wave's first record) and two ahead (parameters).
+struct PtNext {
+  PtPar nn;
+  HatEnt hx;
+  BandRows so;
+};
+__device__ __forceinline__ void pt_prefetch(const GLPar* glb, int gnn, int G, int L, const PtPar& nxt,
+                                            const HatEnt* __restrict__ hats, const BandRec* __restrict__ bands,
+                                            int n, int q, int grp0, PtNext& f) {
+  if (nxt.kmax) f.hx = hats[nxt.hat_off + n + q];
+  f.nn = gnn < G ? load_ptpar(glb + gnn * L) : PtPar{0, 0, 0, -1, -1};
+  if (nxt.kmax) f.so = load_rows(bands + nxt.band_off + grp0);
+}
+
+// One sensor of the fast path: its first band's loads go out before the
+// prefetches of the next sensors (so that waiting for them does not wait for
+// the prefetches), then the sums; a second record (RPT = 8) follows.
+template <int K, int RPT>
+__device__ __forceinline__ void pt_sensor(const float* vsens, int nc, const BandRec* rec, const BandRows& so,
+                                          const HatEnt& hx, int ngrp, const GLPar* glb, int gnn, int G, int L,
+                                          const PtPar& nxt, const HatEnt* __restrict__ hats,
+                                          const BandRec* __restrict__ bands, int n, int q, int grp0, PtNext& f,
+                                          float acc[RPT]) {
+  constexpr int SB = pt_band(K, kBandRows);
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)vsens, (short)0, nc * nc * (int)sizeof(float), 0x00020000);
+  const int vo = hx.lo * (int)sizeof(float);
+  float v[SB][K];
+  pt_band_load<K>(rs, vo, so, v);
+  pt_prefetch(glb, gnn, G, L, nxt, hats, bands, n, q, grp0, f);
+  pt_band_sum<K>(rec, hx, v, acc);
+#pragma unroll
+  for (int j = 1; j < RPT / kBandRows; ++j) {
+    if (j >= ngrp) break;
+    pt_band_load<K>(rs, vo, load_rows(rec + j), v);
+    pt_band_sum<K>(rec + j, hx, v, acc + j * kBandRows);
+  }
+}
+
+// Tile = 4 RPT node rows x 64 node columns; wave w owns the RPT rows from
+// p0 = 4 RPT ty + RPT w (RPT / kBandRows band records).  Sensors whose
+// footprint misses the tile are skipped (tile mask).  The sensor loop is
+// software-pipelined so that one memory round trip per sensor is exposed.
 template <int RPT>
 __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD, const WfsDev* WD, const IoDev* IO,
-                                            const Tile* tiles, const HatEnt* __restrict__ hats, int mode) {
+                                            const Tile* tiles, const HatEnt* __restrict__ hats,
+                                            const BandRec* __restrict__ bands, int mode) {
+  static_assert(RPT % kBandRows == 0, "whole band records per wave");
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[pr.layer0 + t.item];
@@ -927,30 +1051,58 @@ __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD
   const int n = ly.n;
   const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int q = t.tx * kPtW + (threadIdx.x & 63);
-  const int p0 = t.ty * 4 * RPT + wv;
-  if (q >= n) return;  // no barriers in this kernel
+  const int p0 = t.ty * 4 * RPT + wv * RPT;
+  if (q >= n || p0 >= n) return;  // no barriers in this kernel
+  const int grp0 = p0 / kBandRows;
+  const int ngrp = min(RPT / kBandRows, (n - p0 + kBandRows - 1) / kBandRows);  // records inside the layer
   float acc[RPT];
 #pragma unroll
   for (int u = 0; u < RPT; ++u) acc[u] = 0.f;
-  for (int g = 0; g < pr.G; ++g) {
-    if (pr.G <= 32 && !((t.mask >> g) & 1)) continue;  // footprint misses the tile
-    const GLPar gp = load_glpar(pr.gl + g * pr.L + t.item);
-    if (gp.kmax == 0) {
-      pt_general<RPT>(gp, pr.vadj, q, p0, n, acc);
-      continue;
+  const int G = pr.G, L = pr.L;
+  const unsigned mask = (unsigned)t.mask;
+  const GLPar* glb = pr.gl + t.item;  // pair (g, this layer) at glb[g L]
+  const PtPar none{0, 0, 0, -1, -1};
+  int g = pt_next(mask, G, -1);
+  int gn = g < G ? pt_next(mask, G, g) : G;
+  PtPar cur = g < G ? load_ptpar(glb + g * L) : none;
+  PtNext f;
+  f.hx = HatEnt{0, {0.f, 0.f, 0.f}};
+  f.nn = gn < G ? load_ptpar(glb + gn * L) : none;
+  if (cur.kmax) {
+    f.hx = hats[cur.hat_off + n + q];
+    f.so = load_rows(bands + cur.band_off + grp0);
+  }
+  while (g < G) {
+    const PtPar nxt = f.nn;
+    const HatEnt hx = f.hx;
+    const BandRows so = f.so;
+    const int gnn = gn < G ? pt_next(mask, G, gn) : G;
+    if (cur.kmax == 0) {
+      pt_prefetch(glb, gnn, G, L, nxt, hats, bands, n, q, grp0, f);
+      pt_general<RPT>(load_glpar(glb + g * L), pr.vadj, q, p0, n, acc);
+    } else if (cur.nc == 3 && cur.kmax == 2) {  // 3 x 3 corner grid
+      pt_prefetch(glb, gnn, G, L, nxt, hats, bands, n, q, grp0, f);
+      const BandRec* rec = bands + cur.band_off + grp0;
+#pragma unroll
+      for (int j = 0; j < RPT / kBandRows; ++j) {
+        if (j >= ngrp) break;
+        pt_tiny3(pr.vadj + cur.v_off, rec + j, hx, acc + j * kBandRows);
+      }
+    } else if (cur.kmax == 2) {
+      pt_sensor<2, RPT>(pr.vadj + cur.v_off, cur.nc, bands + cur.band_off + grp0, so, hx, ngrp, glb, gnn, G, L,
+                        nxt, hats, bands, n, q, grp0, f, acc);
+    } else {
+      pt_sensor<3, RPT>(pr.vadj + cur.v_off, cur.nc, bands + cur.band_off + grp0, so, hx, ngrp, glb, gnn, G, L,
+                        nxt, hats, bands, n, q, grp0, f, acc);
     }
-    const HatEnt* __restrict__ tb = hats + gp.hat_off;  // [rows n][columns n]
-    const HatEnt hx = tb[n + q];
-    const gptr_f va = (gptr_f)(pr.vadj + gp.v_off + hx.lo);
-    if (gp.kmax == 2)
-      pt_taps<2, RPT>(tb, hx, va, gp.nc, p0, n, acc);
-    else
-      pt_taps<3, RPT>(tb, hx, va, gp.nc, p0, n, acc);
+    g = gn;
+    gn = gnn;
+    cur = nxt;
   }
   float* dst = (mode == PT_USER) ? io.out : pr.phiadj;
 #pragma unroll
   for (int u = 0; u < RPT; ++u) {
-    const int p = p0 + 4 * u;
+    const int p = p0 + u;
     if (p < n) dst[ly.off + p * n + q] = acc[u];
   }
 }
@@ -1269,9 +1421,9 @@ void launch_gammaT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode)
 void launch_pT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
   if (ntiles <= 0) return;
   if (a.pt_rows == 8)
-    k_pT<8><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, mode);
+    k_pT<8><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.bands, mode);
   else
-    k_pT<4><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, mode);
+    k_pT<4><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.bands, mode);
 }
 void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter) {
   if (ntiles > 0) k_update<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles, iter);
