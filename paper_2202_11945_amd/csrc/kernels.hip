@@ -603,13 +603,41 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
 }
 
 // ------------------------------------------- propagation + Shack-Hartmann
+// Sums of four values over a workgroup of nw waves, in wave order; result
+// valid in thread 0.  One barrier.
+__device__ __forceinline__ void block_sum4(float a[4], float* sh, int nw) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) a[k] = wave_sum(a[k]);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh[4 * w + k] = a[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float r = 0.f;
+      for (int i = 0; i < nw; ++i) r += sh[4 * i + k];
+      a[k] = r;
+    }
+}
+
+// Sensor-stage workgroup: 5 waves, one thread per corner (or subaperture) of
+// a 17 x 17 window, the first 256 threads also own one of its 16 x 16 tile.
+constexpr int kSensThreads = 320;
+static_assert((kTileS + 1) * (kTileS + 1) <= kSensThreads, "17 x 17 window in one pass");
+
 // Tile of 16x16 subapertures of one sensor: v on the 17x17 corners is the
 // sum over layers of the bilinear interpolant (LGS cone factor in the
-// tables), then s^x, s^y per active subaperture (Sec. 2).
-__global__ __launch_bounds__(256) void k_pgamma(const ProbDev* P, const LayerDev* LD, const WfsDev* WD,
-                                                const IoDev* IO, const Tile* tiles, int mode) {
-  __shared__ float V[(kTileS + 1) * (kTileS + 1)];
-  __shared__ float sh[4 * 4];
+// tables), then s^x, s^y per active subaperture (Sec. 2).  The subaperture
+// operands are requested first; the layers go in groups of four (all table
+// loads of a group, then all node loads), so a corner waits on two memory
+// round trips per four layers.
+__global__ __launch_bounds__(kSensThreads) void k_pgamma(const ProbDev* P, const LayerDev* LD, const WfsDev* WD,
+                                                         const IoDev* IO, const Tile* tiles, int mode) {
+  constexpr int CW = kTileS + 1;
+  __shared__ float V[CW * CW];
+  __shared__ float sh[4 * (kSensThreads / 64)];
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const WfsDev& w = WD[pr.wfs0 + t.item];
@@ -617,51 +645,91 @@ __global__ __launch_bounds__(256) void k_pgamma(const ProbDev* P, const LayerDev
   const float* phi = (mode == PG_DENSE) ? pr.phi : io.in;
   const int N = w.N, nc = w.nc;
   const int i0 = t.ty * kTileS, j0 = t.tx * kTileS;
-  constexpr int CW = kTileS + 1;
+  // subaperture owned by this thread and its operands
+  const int li = threadIdx.x >> 4, lj = threadIdx.x & 15;
+  const int i = i0 + li, j = j0 + lj;
+  const bool own = threadIdx.x < kTileS * kTileS && i < N && j < N;
   typedef const int __attribute__((address_space(1)))* gptr_i;
-  for (int e = threadIdx.x; e < CW * CW; e += blockDim.x) {
-    const int li = e / CW, lj = e - li * CW;
-    const int i = i0 + li, j = j0 + lj;
+  int ci = -1;
+  float dsx = 0.f, dsy = 0.f, cb0 = 0.f, cb1 = 0.f, cb2 = 0.f;
+  if (own) {
+    ci = ((gptr_i)pr.cmap)[w.m_off + i * N + j];
+    if (mode == PG_RESID_IN) {  // data residual s - A phi (s placed by the slopes input kernel)
+      const gptr_f sd = (gptr_f)(pr.sd + w.s_off);
+      dsx = sd[i * N + j];
+      dsy = sd[N * N + i * N + j];
+    }
+    if (w.blocks) {
+      const gptr_f cb = (gptr_f)(pr.cinv + w.cinv_off + 3 * (i * N + j));
+      cb0 = cb[0];
+      cb1 = cb[1];
+      cb2 = cb[2];
+    }
+  }
+  // corners
+  const int e = threadIdx.x;
+  if (e < CW * CW) {
+    const int lci = e / CW, lcj = e - lci * CW;
+    const int ic = i0 + lci, jc = j0 + lcj;
     float v = 0.f;
-    if (i < nc && j < nc) {
-      for (int l = 0; l < pr.L; ++l) {
-        const LayerDev& ly = LD[pr.layer0 + l];
-        const int base = w.tab_off + l * w.tab_stride;
-        const gptr_i it = (gptr_i)(pr.itab + base);
-        const gptr_f ft = (gptr_f)(pr.ftab + base);
-        const int qy = it[i], qx = it[nc + j];
-        const float wy = ft[2 * nc + i], wx = ft[3 * nc + j];
-        const gptr_f ph = (gptr_f)(phi + ly.off + qy * ly.n + qx);
-        const float top = (1.f - wx) * ph[0] + wx * ph[1];
-        const float bot = (1.f - wx) * ph[ly.n] + wx * ph[ly.n + 1];
-        v += (1.f - wy) * top + wy * bot;
+    if (ic < nc && jc < nc) {
+      const gptr_i it = (gptr_i)(pr.itab + w.tab_off);
+      const gptr_f ft = (gptr_f)(pr.ftab + w.tab_off);
+      for (int l0 = 0; l0 < pr.L; l0 += 4) {
+        int cell[4];
+        float wy[4], wx[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          cell[k] = 0;
+          wy[k] = wx[k] = 0.f;
+          const int l = l0 + k;
+          if (l < pr.L) {
+            const LayerDev& ly = LD[pr.layer0 + l];
+            const int tb = l * w.tab_stride;
+            cell[k] = ly.off + it[tb + ic] * ly.n + it[tb + nc + jc];
+            wy[k] = ft[tb + 2 * nc + ic];
+            wx[k] = ft[tb + 3 * nc + jc];
+          }
+        }
+        float nd[4][4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          nd[k][0] = nd[k][1] = nd[k][2] = nd[k][3] = 0.f;
+          if (l0 + k < pr.L) {
+            const int n = LD[pr.layer0 + l0 + k].n;
+            const gptr_f ph = (gptr_f)(phi + cell[k]);
+            nd[k][0] = ph[0];
+            nd[k][1] = ph[1];
+            nd[k][2] = ph[n];
+            nd[k][3] = ph[n + 1];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (l0 + k < pr.L) {
+            const float top = (1.f - wx[k]) * nd[k][0] + wx[k] * nd[k][1];
+            const float bot = (1.f - wx[k]) * nd[k][2] + wx[k] * nd[k][3];
+            v += (1.f - wy[k]) * top + wy[k] * bot;
+          }
       }
     }
     V[e] = v;
   }
   __syncthreads();
-  const int li = threadIdx.x >> 4, lj = threadIdx.x & 15;
-  const int i = i0 + li, j = j0 + lj;
   float sx = 0.f, sy = 0.f, cx = 0.f, cy = 0.f;
-  bool act = false;
-  int ci = -1;
-  if (i < N && j < N) {
-    ci = pr.cmap[w.m_off + i * N + j];
-    act = ci >= 0;
-  }
+  const bool act = own && ci >= 0;
   if (act) {
     const float v00 = V[li * CW + lj], v01 = V[li * CW + lj + 1];
     const float v10 = V[(li + 1) * CW + lj], v11 = V[(li + 1) * CW + lj + 1];
     sx = 0.5f * ((v01 - v00) + (v11 - v10));
     sy = 0.5f * ((v10 - v00) + (v11 - v01));
-    if (mode == PG_RESID_IN) {  // data residual s - A phi (s placed by the slopes input kernel)
-      sx = pr.sd[w.s_off + i * N + j] - sx;
-      sy = pr.sd[w.s_off + N * N + i * N + j] - sy;
+    if (mode == PG_RESID_IN) {
+      sx = dsx - sx;
+      sy = dsy - sy;
     }
     if (w.blocks) {
-      const float* cb = pr.cinv + w.cinv_off + 3 * (i * N + j);
-      cx = cb[0] * sx + cb[1] * sy;
-      cy = cb[1] * sx + cb[2] * sy;
+      cx = cb0 * sx + cb1 * sy;
+      cy = cb1 * sx + cb2 * sy;
     }
   }
   if (mode == PG_COMPACT) {
@@ -671,20 +739,18 @@ __global__ __launch_bounds__(256) void k_pgamma(const ProbDev* P, const LayerDev
     }
     return;
   }
-  if (i < N && j < N) {
+  if (own) {
     pr.sd[w.s_off + i * N + j] = sx;
     pr.sd[w.s_off + N * N + i * N + j] = sy;
   }
-  const float a0 = block_sum(sx, sh, blockDim.x);
-  const float a1 = block_sum(sy, sh + 4, blockDim.x);
-  const float a2 = block_sum(cx, sh + 8, blockDim.x);
-  const float a3 = block_sum(cy, sh + 12, blockDim.x);
+  float a[4] = {sx, sy, cx, cy};
+  block_sum4(a, sh, kSensThreads / 64);
   if (threadIdx.x == 0) {
     float* pp = pr.part + w.part_off + 4 * (t.ty * w.tiles_side + t.tx);
-    pp[0] = a0;
-    pp[1] = a1;
-    pp[2] = a2;
-    pp[3] = a3;
+    pp[0] = a[0];
+    pp[1] = a[1];
+    pp[2] = a[2];
+    pp[3] = a[3];
   }
 }
 
@@ -728,92 +794,95 @@ __global__ __launch_bounds__(256) void k_slopes_in(const ProbDev* P, const WfsDe
 
 // ------------------------------------- noise weighting + Shack-Hartmann adjoint
 // Tile of 16x16 corners; the weighted slopes of the 17x17 subapertures that
-// touch them are formed in LDS: C_hat^{-1} = (I - T) C^{-1} (I - T) for LGS
-// with tip/tilt removal (means from the per-tile partial sums, Sec. 3.2),
-// C^{-1} otherwise; GT_PLAIN applies Gamma^T alone.
+// touch them are formed in LDS (thread t takes window entries t and t + 256):
+// C_hat^{-1} = (I - T) C^{-1} (I - T) for LGS with tip/tilt removal (means
+// from the per-tile partial sums, Sec. 3.2), C^{-1} otherwise; GT_PLAIN
+// applies Gamma^T alone.  The subaperture operands are requested before the
+// means are reduced.
 __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* WD, const Tile* tiles, int mode) {
   constexpr int SW = kTileS + 1;
   __shared__ float YX[SW * SW];
   __shared__ float YY[SW * SW];
   __shared__ float mean[4];
+  typedef const int __attribute__((address_space(1)))* gptr_i;
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const WfsDev& w = WD[pr.wfs0 + t.item];
   const int N = w.N, nc = w.nc;
   const bool weighted = mode == GT_WEIGHTED;
+  const int ci0 = t.ty * kTileS, cj0 = t.tx * kTileS;
+  const gptr_f sd = (gptr_f)(pr.sd + w.s_off);
+  const gptr_i cmap = (gptr_i)(pr.cmap + w.m_off);
+  bool act[2];
+  float sx[2], sy[2], cb0[2], cb1[2], cb2[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = threadIdx.x + u * 256;
+    act[u] = false;
+    sx[u] = sy[u] = cb0[u] = cb1[u] = cb2[u] = 0.f;
+    if (e < SW * SW) {
+      const int li = e / SW, lj = e - li * SW;
+      const int i = ci0 - 1 + li, j = cj0 - 1 + lj;  // subaperture
+      if (i >= 0 && j >= 0 && i < N && j < N) {
+        act[u] = cmap[i * N + j] >= 0;
+        sx[u] = sd[i * N + j];
+        sy[u] = sd[N * N + i * N + j];
+        if (weighted && w.blocks) {
+          const gptr_f cb = (gptr_f)(pr.cinv + w.cinv_off + 3 * (i * N + j));
+          cb0[u] = cb[0];
+          cb1[u] = cb[1];
+          cb2[u] = cb[2];
+        }
+      }
+    }
+  }
   if (weighted && w.tt) {
     if (threadIdx.x < 64) {  // wave 0: tip/tilt means from the tile partials
-      float sx = 0.f, sy = 0.f, scx = 0.f, scy = 0.f;
-      const float* pp = pr.part + w.part_off;
+      float px = 0.f, py = 0.f, pcx = 0.f, pcy = 0.f;
+      const gptr_f pp = (gptr_f)(pr.part + w.part_off);
       for (int k = threadIdx.x; k < w.n_tiles_s; k += 64) {
-        sx += pp[4 * k];
-        sy += pp[4 * k + 1];
-        scx += pp[4 * k + 2];
-        scy += pp[4 * k + 3];
+        px += pp[4 * k];
+        py += pp[4 * k + 1];
+        pcx += pp[4 * k + 2];
+        pcy += pp[4 * k + 3];
       }
-      sx = wave_sum(sx);
-      sy = wave_sum(sy);
-      scx = wave_sum(scx);
-      scy = wave_sum(scy);
+      px = wave_sum(px);
+      py = wave_sum(py);
+      pcx = wave_sum(pcx);
+      pcy = wave_sum(pcy);
       if (threadIdx.x == 0) {
-        const float mx = sx * w.inv_nM, my = sy * w.inv_nM;
+        const float mx = px * w.inv_nM, my = py * w.inv_nM;
         mean[0] = mx;
         mean[1] = my;
-        mean[2] = w.blocks ? (scx - (w.sum_cinv[0] * mx + w.sum_cinv[1] * my)) * w.inv_nM : 0.f;
-        mean[3] = w.blocks ? (scy - (w.sum_cinv[2] * mx + w.sum_cinv[3] * my)) * w.inv_nM : 0.f;
+        mean[2] = w.blocks ? (pcx - (w.sum_cinv[0] * mx + w.sum_cinv[1] * my)) * w.inv_nM : 0.f;
+        mean[3] = w.blocks ? (pcy - (w.sum_cinv[2] * mx + w.sum_cinv[3] * my)) * w.inv_nM : 0.f;
       }
     }
   } else if (threadIdx.x < 4) {
     mean[threadIdx.x] = 0.f;
   }
   __syncthreads();
-  const int ci0 = t.ty * kTileS, cj0 = t.tx * kTileS;
   const float m0 = mean[0], m1 = mean[1], m2 = mean[2], m3 = mean[3];
-  for (int e0 = threadIdx.x; e0 < SW * SW; e0 += 2 * blockDim.x) {
-    float sx[2], sy[2], cb0[2], cb1[2], cb2[2];
-    bool act[2];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int e = e0 + u * blockDim.x;
-      act[u] = false;
-      sx[u] = sy[u] = cb0[u] = cb1[u] = cb2[u] = 0.f;
-      if (e < SW * SW) {
-        const int li = e / SW, lj = e - li * SW;
-        const int i = ci0 - 1 + li, j = cj0 - 1 + lj;  // subaperture
-        if (i >= 0 && j >= 0 && i < N && j < N && pr.cmap[w.m_off + i * N + j] >= 0) {
-          act[u] = true;
-          sx[u] = pr.sd[w.s_off + i * N + j];
-          sy[u] = pr.sd[w.s_off + N * N + i * N + j];
-          if (weighted && w.blocks) {
-            const float* cb = pr.cinv + w.cinv_off + 3 * (i * N + j);
-            cb0[u] = cb[0];
-            cb1[u] = cb[1];
-            cb2[u] = cb[2];
-          }
-        }
+  for (int u = 0; u < 2; ++u) {
+    const int e = threadIdx.x + u * 256;
+    if (e >= SW * SW) continue;
+    float yx = 0.f, yy = 0.f;
+    if (act[u]) {
+      if (!weighted) {
+        yx = sx[u];
+        yy = sy[u];
+      } else if (w.blocks) {
+        const float dx = sx[u] - m0, dy = sy[u] - m1;
+        yx = cb0[u] * dx + cb1[u] * dy - m2;
+        yy = cb1[u] * dx + cb2[u] * dy - m3;
+      } else {
+        yx = w.inv_sigma2 * (sx[u] - m0);
+        yy = w.inv_sigma2 * (sy[u] - m1);
       }
     }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int e = e0 + u * blockDim.x;
-      if (e >= SW * SW) continue;
-      float yx = 0.f, yy = 0.f;
-      if (act[u]) {
-        if (!weighted) {
-          yx = sx[u];
-          yy = sy[u];
-        } else if (w.blocks) {
-          const float dx = sx[u] - m0, dy = sy[u] - m1;
-          yx = cb0[u] * dx + cb1[u] * dy - m2;
-          yy = cb1[u] * dx + cb2[u] * dy - m3;
-        } else {
-          yx = w.inv_sigma2 * (sx[u] - m0);
-          yy = w.inv_sigma2 * (sy[u] - m1);
-        }
-      }
-      YX[e] = yx;
-      YY[e] = yy;
-    }
+    YX[e] = yx;
+    YY[e] = yy;
   }
   __syncthreads();
   const int li = threadIdx.x >> 4, lj = threadIdx.x & 15;
@@ -1410,7 +1479,7 @@ void launch_fdwt_res(const LaunchArgs& a, const Tile* tiles, int ntiles, int epi
     k_fdwt_res<128><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
 }
 void launch_pgamma(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
-  if (ntiles > 0) k_pgamma<<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, mode);
+  if (ntiles > 0) k_pgamma<<<ntiles, kSensThreads, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, mode);
 }
 void launch_slopes_in(const LaunchArgs& a, const Tile* tiles, int ntiles) {
   if (ntiles > 0) k_slopes_in<<<ntiles, 256, 0, a.stream>>>(a.P, a.W, a.IO, tiles);
