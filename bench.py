@@ -215,7 +215,7 @@ def main():
 
     # ---- launch shapes from the autotuner (cached per device and shapes) ----
     from paper_2202_11945_amd import autotune
-    default = {"dwt_resident": 128, "pt_rows": 4, "cached": None}
+    default = {"dwt_resident": 128, "pt_rows": 4, "streams": 1, "cached": None}
     tune_b = autotune.tune(ctxs, args.iters) if not args.no_tune else default
     tune_1 = autotune.tune([c0], args.iters) if not args.no_tune else default
     print("[bench] tuning: batch %s, single %s" % (tune_b, tune_1), file=sys.stderr, flush=True)

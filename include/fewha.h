@@ -307,11 +307,20 @@ FEWHA_API void fewha_batch_destroy(fewha_batch* b);
  * pt_rows: node rows per thread of the propagation adjoint P^T (4 or 8;
  * 0 = default 4); a tile is 64 node columns by 4 * pt_rows rows.  More rows
  * put more independent loads in flight per thread, at more registers.
+ * streams: batches only (a context takes 0 or 1).  fewha_batch_reconstruct
+ * runs the batch as this many contiguous parts of its problem list (1 to 4,
+ * at most the number of problems; 0 = default 1), each part on a stream of
+ * the library's own, forked from and joined back to the batch's stream by
+ * events, so that the stages of one part overlap those of another.  Results
+ * are identical to one part.  The parts' plans are built with the batch and
+ * take device memory of their own (about that of the batch plan).  Every
+ * other batch call runs the whole batch on the batch's stream.
  * reserved: zero. */
 typedef struct {
   int dwt_resident;
   int pt_rows;
-  int reserved[6];
+  int streams;
+  int reserved[5];
 } fewha_tuning;
 
 /* Tuning of a context's own plan; before fewha_finalize. */

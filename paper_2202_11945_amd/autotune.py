@@ -1,6 +1,6 @@
 """Autotuner of a plan's launch shapes.
 
-Two tunables:
+Three tunables:
 
 * the resident transform side R (32, 64 or 128): the resident DWT kernels
   keep every level up to R x R in one workgroup's LDS, and the levels above R
@@ -9,6 +9,9 @@ Two tunables:
   levels over many more workgroups at the cost of one launch per extra level.
 * the node rows per thread of the propagation adjoint (4 or 8): more rows
   put more independent loads in flight per thread, at more registers.
+* then, for the best of those, the number of streams a batch's frame runs on
+  (1 or 2 parts of the problem list, each on its own stream, so that the
+  stages of one part overlap those of the other).
 
 Which combination wins depends on the batch size, the layer sizes and the
 device, so it is measured: every admissible combination builds the batch
@@ -25,6 +28,7 @@ import os
 
 CANDIDATES = (32, 64, 128)
 PT_ROWS = (4, 8)
+STREAMS = (1, 2)
 MARGIN = 0.02  # relative gain a non-default choice needs
 CACHE = os.environ.get("FEWHA_TUNE_CACHE",
                        os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "autotune_cache.json"))
@@ -47,7 +51,7 @@ def signature(ctxs, iters):
                             1 if (cfg.get("dms") and cfg.get("fit")) else 0)
         shapes[s] = shapes.get(s, 0) + 1
     body = ";".join("%dx[%s]" % (n, s) for s, n in sorted(shapes.items()))
-    return "%s|iters%d|%s" % (torch.cuda.get_device_name(ctxs[0].device), iters, body)
+    return "%s|iters%d|%s|v2" % (torch.cuda.get_device_name(ctxs[0].device), iters, body)
 
 
 def _load():
@@ -91,7 +95,8 @@ def time_plan(ctxs, iters, tuning, steps=10, warmup=3):
 
 def tune(ctxs, iters, steps=10, use_cache=True):
     """Best launch shapes for a batch of these contexts; returns
-    {"dwt_resident": R, "pt_rows": r, "us": {"R/r": us per step}, "cached": bool}."""
+    {"dwt_resident": R, "pt_rows": r, "streams": s, "us": {"R/r": us per step},
+     "streams_us": {"s": us per step}, "cached": bool}."""
     key = signature(ctxs, iters)
     db = _load() if use_cache else {}
     if use_cache and key in db:
@@ -106,8 +111,17 @@ def tune(ctxs, iters, steps=10, use_cache=True):
     default = (max(admissible(ctxs)), PT_ROWS[0])
     if us[best] > (1.0 - MARGIN) * us[default]:
         best = default
-    rec = {"dwt_resident": best[0], "pt_rows": best[1],
-           "us": {"%d/%d" % k: round(t, 3) for k, t in us.items()}}
+    sus = {1: us[best]}
+    for ns in STREAMS[1:]:
+        if ns <= len(ctxs):
+            sus[ns] = time_plan(ctxs, iters, {"dwt_resident": best[0], "pt_rows": best[1], "streams": ns},
+                                steps=steps)
+    streams = min(sus, key=sus.get)
+    if sus[streams] > (1.0 - MARGIN) * sus[1]:
+        streams = 1
+    rec = {"dwt_resident": best[0], "pt_rows": best[1], "streams": streams,
+           "us": {"%d/%d" % k: round(t, 3) for k, t in us.items()},
+           "streams_us": {"%d" % k: round(t, 3) for k, t in sus.items()}}
     if use_cache:
         db = _load()
         db[key] = rec

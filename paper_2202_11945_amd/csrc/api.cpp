@@ -191,13 +191,24 @@ void set_hats(GLPar& gp, int n, HatTables& T) {
       fits = false;
       break;
     }
-    // first band row: the group's first corner, moved down so that all SB
-    // rows lie in the grid (a grid of fewer rows starts at 0 and repeats its
-    // last row)
-    const int base = gp.nc >= SB ? std::max(0, std::min(ilo, gp.nc - SB)) : 0;
+    // first band row: the group's first corner (a grid of fewer than SB rows
+    // starts at 0); rows past the grid repeat its last row, never weighted
+    const int base = gp.nc >= SB ? ilo : 0;
     BandRec r{};
     for (int s = 0; s < kBandMax; ++s)
       r.so[s] = std::min(base + std::min(s, SB - 1), gp.nc - 1) * gp.nc * (int)sizeof(float);
+    r.pat = -1;
+    if (K == 2 && base == ilo) {
+      int pat = 0;
+      for (int u = 1; u < kBandRows && pat >= 0; ++u) {
+        const int step = rows[std::min(p + u, n - 1)].lo - rows[std::min(p + u - 1, n - 1)].lo;
+        if (step == 1)
+          pat |= 1 << (u - 1);
+        else if (step != 0)
+          pat = -1;
+      }
+      r.pat = pat;
+    }
     for (int u = 0; u < kBandRows && p + u < n; ++u)
       for (int k = 0; k < K; ++k) {
         const int s = rows[p + u].lo + k - base;
@@ -1194,7 +1205,27 @@ struct fewha_batch {
   Plan* plan = nullptr;
   hipStream_t stream = nullptr;
   std::string err;
+  // frame path in parts (tuning streams > 1): contiguous slices of the
+  // problem list, each with its own plan and stream; fork / join events
+  std::vector<Plan*> parts;
+  std::vector<int> part_first;
+  std::vector<hipStream_t> part_stream;
+  std::vector<hipEvent_t> part_done;
+  hipEvent_t fork = nullptr;
 };
+
+static void destroy_batch_parts(fewha_batch* b) {
+  for (Plan*& q : b->parts) destroy_plan(q);
+  for (hipStream_t s : b->part_stream)
+    if (s) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : b->part_done)
+    if (e) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  b->parts.clear();
+  b->part_stream.clear();
+  b->part_done.clear();
+  b->fork = nullptr;
+}
 
 #define CHECK_CTX(c)                 \
   do {                               \
@@ -1327,8 +1358,10 @@ fewha_status fewha_set_tuning(fewha_ctx* c, const fewha_tuning* t) {
   CHECK_CTX(c);
   if (c->finalized) return fail(c, FEWHA_ESTATE, "set_tuning after finalize");
   if (!t) return fail(c, FEWHA_EINVAL, "set_tuning: null tuning");
-  for (int i = 0; i < 6; ++i)
+  for (int i = 0; i < 5; ++i)
     if (t->reserved[i]) return fail(c, FEWHA_EINVAL, "set_tuning: reserved fields must be zero");
+  if (t->streams != 0 && t->streams != 1)
+    return fail(c, FEWHA_EINVAL, "set_tuning: a context runs one stream (streams 0 or 1)");
   if (t->dwt_resident != 0 && t->dwt_resident != 32 && t->dwt_resident != 64 && t->dwt_resident != 128)
     return fail(c, FEWHA_EINVAL, "set_tuning: dwt_resident must be 0, 32, 64 or 128");
   if (t->pt_rows != 0 && t->pt_rows != 4 && t->pt_rows != 8)
@@ -1534,8 +1567,8 @@ fewha_status fewha_batch_create(fewha_batch** out, fewha_ctx* const* ctxs, int n
 
 fewha_status fewha_batch_create_tuned(fewha_batch** out, fewha_ctx* const* ctxs, int n, const fewha_tuning* t) {
   if (!out || !ctxs || n < 1) return FEWHA_EINVAL;
-  if (t && (t->dwt_resident < 0 || t->pt_rows < 0 || t->reserved[0] || t->reserved[1] || t->reserved[2] ||
-            t->reserved[3] || t->reserved[4] || t->reserved[5]))
+  if (t && (t->dwt_resident < 0 || t->pt_rows < 0 || t->streams < 0 || t->streams > 4 || t->streams > n ||
+            t->reserved[0] || t->reserved[1] || t->reserved[2] || t->reserved[3] || t->reserved[4]))
     return FEWHA_EINVAL;
   *out = nullptr;
   int dev = -1;
@@ -1556,6 +1589,29 @@ fewha_status fewha_batch_create_tuned(fewha_batch** out, fewha_ctx* const* ctxs,
     delete b;
     return s;
   }
+  const int parts = (t && t->streams > 1) ? t->streams : 1;
+  if (parts > 1) {
+    auto undo = [&](fewha_status st) {
+      destroy_batch_parts(b);
+      destroy_plan(b->plan);
+      delete b;
+      return st;
+    };
+    b->parts.assign(parts, nullptr);
+    b->part_stream.assign(parts, nullptr);
+    b->part_done.assign(parts, nullptr);
+    if (hipSetDevice(dev) != hipSuccess || hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
+      return undo(FEWHA_EDEVICE);
+    for (int q = 0; q < parts; ++q) {
+      const int k0 = (int)((long)n * q / parts), k1 = (int)((long)n * (q + 1) / parts);
+      b->part_first.push_back(k0);
+      std::vector<const HostModel*> mq(ms.begin() + k0, ms.begin() + k1);
+      if ((s = build_plan(b->parts[q], mq, dev, res, rows, b->err)) != FEWHA_OK) return undo(s);
+      if (hipStreamCreateWithFlags(&b->part_stream[q], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&b->part_done[q], hipEventDisableTiming) != hipSuccess)
+        return undo(FEWHA_EDEVICE);
+    }
+  }
   *out = b;
   return FEWHA_OK;
 }
@@ -1563,6 +1619,34 @@ fewha_status fewha_batch_create_tuned(fewha_batch** out, fewha_ctx* const* ctxs,
 fewha_status fewha_batch_set_stream(fewha_batch* b, void* s) {
   if (!b) return FEWHA_EINVAL;
   b->stream = (hipStream_t)s;
+  return FEWHA_OK;
+}
+
+// One frame of every problem of plan P on stream st: the I/O table, then the
+// captured graph of `iters` iterations (captured on first use) or the plain
+// launches.
+static fewha_status run_frame(Plan& P, hipStream_t st, const std::vector<IoDev>& io, int iters, int use_graph,
+                              std::string& err) {
+  fewha_status s = upload_io(P, io, st, P.dIO, err);
+  if (s != FEWHA_OK) return s;
+  P.last_io = io;
+  P.ran = true;
+  if (!use_graph) {
+    enq_reconstruct(P, args(P, st, P.dIO), iters);
+    return FEWHA_OK;
+  }
+  auto it = P.graphs.find(iters);
+  if (it == P.graphs.end()) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    HIP_TRY(hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal));
+    enq_reconstruct(P, args(P, P.cap_stream, P.dIO), iters);
+    HIP_TRY(hipStreamEndCapture(P.cap_stream, &g));
+    HIP_TRY(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    P.graph_defs[iters] = g;
+    it = P.graphs.emplace(iters, ge).first;
+  }
+  HIP_TRY(hipGraphLaunch(it->second, st));
   return FEWHA_OK;
 }
 
@@ -1584,25 +1668,23 @@ fewha_status fewha_batch_reconstruct(fewha_batch* b, const float* const* slopes,
     io[k].dm_out = dm_out ? dm_out[k] : nullptr;
   }
   HIP_TRY(hipSetDevice(P.device));
-  fewha_status s = upload_io(P, io, b->stream, P.dIO, err);
-  if (s != FEWHA_OK) return s;
-  P.last_io = io;
-  P.ran = true;
-  if (!use_graph) {
-    enq_reconstruct(P, args(P, b->stream, P.dIO), iters);
+  fewha_status s;
+  if (b->parts.empty()) {
+    if ((s = run_frame(P, b->stream, io, iters, use_graph, err)) != FEWHA_OK) return s;
   } else {
-    auto it = P.graphs.find(iters);
-    if (it == P.graphs.end()) {
-      hipGraph_t g = nullptr;
-      hipGraphExec_t ge = nullptr;
-      HIP_TRY(hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal));
-      enq_reconstruct(P, args(P, P.cap_stream, P.dIO), iters);
-      HIP_TRY(hipStreamEndCapture(P.cap_stream, &g));
-      HIP_TRY(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-      P.graph_defs[iters] = g;
-      it = P.graphs.emplace(iters, ge).first;
+    // fork: every part waits for the work queued before this call
+    HIP_TRY(hipEventRecord(b->fork, b->stream));
+    for (size_t q = 0; q < b->parts.size(); ++q) {
+      Plan& Q = *b->parts[q];
+      const std::vector<IoDev> ioq(io.begin() + b->part_first[q], io.begin() + b->part_first[q] + Q.nprob);
+      HIP_TRY(hipStreamWaitEvent(b->part_stream[q], b->fork, 0));
+      if ((s = run_frame(Q, b->part_stream[q], ioq, iters, use_graph, err)) != FEWHA_OK) return s;
+      HIP_TRY(hipEventRecord(b->part_done[q], b->part_stream[q]));
     }
-    HIP_TRY(hipGraphLaunch(it->second, b->stream));
+    // join: work queued after this call waits for every part
+    for (size_t q = 0; q < b->parts.size(); ++q) HIP_TRY(hipStreamWaitEvent(b->stream, b->part_done[q], 0));
+    P.last_io = io;  // stage timing runs the whole batch's plan on these buffers
+    P.ran = true;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return bfail(b, FEWHA_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
@@ -1744,6 +1826,7 @@ fewha_status fewha_batch_time_stage(fewha_batch* b, int stage, int reps, double*
 
 void fewha_batch_destroy(fewha_batch* b) {
   if (!b) return;
+  destroy_batch_parts(b);
   destroy_plan(b->plan);
   delete b;
 }

@@ -114,10 +114,14 @@ struct HatEnt {
 // (sensor, layer) pair: the corner rows of the band (byte offsets in the
 // sensor's corner grid, clamped to the grid, so extra rows repeat a valid
 // row) and, per node row, the y hat weight of every band row (0 off the hat).
+// pat (K = 2, band starting at the group's first corner): bit u - 1 is the
+// step of the first corner from node row u - 1 to u (0 or 1); -1 = no such
+// pattern (dense sums).
 struct BandRec {
   int so[kBandMax];
   float w[kBandRows][kBandMax];
-  int pad_[3];
+  int pat;
+  int pad_[2];
 };
 static_assert(sizeof(BandRec) == 192, "band record: 48 dwords");
 

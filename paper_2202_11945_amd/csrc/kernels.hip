@@ -13,6 +13,15 @@ namespace fewha {
 
 // ---------------------------------------------------------------- helpers
 
+// Global-address-space view of a device pointer held in a struct (loads
+// through it compile to global, not flat, memory instructions).
+typedef const float __attribute__((address_space(1)))* gptr_f;
+// 16-byte global loads and stores (clang vector type; HIP's float4 has no
+// assignment from a global-space reference).
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef const v4f __attribute__((address_space(1)))* gptr_f4;
+typedef v4f __attribute__((address_space(1)))* gptr_w4;
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -113,11 +122,11 @@ struct CoefLoad {
 __device__ __forceinline__ CoefLoad coef_fetch(const PSrc& s, int e) {
   CoefLoad v{0.f, 0.f, 0.f};
   if (s.mode == SRC_IN || s.mode == SRC_STATE_C) {
-    v.a = s.src[e];
+    v.a = ((gptr_f)s.src)[e];
   } else {
-    v.a = s.r[e];
-    v.b = s.jinv[e];
-    if (s.mode == SRC_PUPD) v.c = s.pold[e];
+    v.a = ((gptr_f)s.r)[e];
+    v.b = ((gptr_f)s.jinv)[e];
+    if (s.mode == SRC_PUPD) v.c = ((gptr_f)s.pold)[e];
   }
   return v;
 }
@@ -130,17 +139,14 @@ __device__ __forceinline__ float coef_finish(const PSrc& s, int e, const CoefLoa
   return p;
 }
 
-// beta_k = rho_k / rho_{k-1}, summed by wave 0 and broadcast through LDS
-__device__ __forceinline__ float compute_beta(const ProbDev& pr, int mode, int iter, double* sb) {
-  if (mode == SRC_PUPD && threadIdx.x < 64) {
-    const double rk = wave_sum_slots(dot_group(pr, rho_grp(iter)), rho_count(pr, iter));
-    const double rkm = wave_sum_slots(dot_group(pr, rho_grp(iter - 1)), rho_count(pr, iter - 1));
-    if (threadIdx.x == 0) *sb = (rkm != 0.0) ? rk / rkm : 0.0;
-  } else if (threadIdx.x == 0) {
-    *sb = 0.0;
-  }
-  __syncthreads();
-  return (float)(*sb);
+// beta_k = rho_k / rho_{k-1}, summed by every wave itself in the same fixed
+// order (no barrier, identical in every wave); called after the wave's
+// coefficient loads are in flight, so both latencies overlap
+__device__ __forceinline__ float wave_beta(const ProbDev& pr, int mode, int iter) {
+  if (mode != SRC_PUPD) return 0.f;
+  const double rk = wave_sum_slots(dot_group(pr, rho_grp(iter)), rho_count(pr, iter));
+  const double rkm = wave_sum_slots(dot_group(pr, rho_grp(iter - 1)), rho_count(pr, iter - 1));
+  return (float)((rkm != 0.0) ? rk / rkm : 0.0);
 }
 
 // Final output of the inverse transform: phi = delta^{-1} W^T c, optionally
@@ -150,7 +156,7 @@ struct OutLoad {
 };
 __device__ __forceinline__ OutLoad out_fetch(const ProbDev& pr, const IoDev& io, int out_mode, int e) {
   OutLoad o{0.f};
-  if (out_mode == OUT_FIT && !pr.fitted) o.a = io.state[3L * pr.n_c + pr.n_act + e];
+  if (out_mode == OUT_FIT && !pr.fitted) o.a = ((gptr_f)io.state)[3L * pr.n_c + pr.n_act + e];
   return o;
 }
 __device__ __forceinline__ void out_finish(const ProbDev& pr, const IoDev& io, int out_mode, int e, float v,
@@ -185,13 +191,13 @@ struct EpiLoad {
 __device__ __forceinline__ EpiLoad epi_fetch(const ProbDev& pr, const IoDev& io, int epi, int iter, int e) {
   EpiLoad l{0.f, 0.f, 0.f};
   if (epi == EPI_APPLYM) {
-    l.x0 = io.in[e];
+    l.x0 = ((gptr_f)io.in)[e];
   } else if (epi == EPI_PCG) {
-    l.x0 = ((iter & 1) ? pr.pbuf1 : pr.pbuf0)[e];
+    l.x0 = ((gptr_f)((iter & 1) ? pr.pbuf1 : pr.pbuf0))[e];
   } else if (epi == EPI_RHS) {
-    l.x0 = io.state[pr.n_c + e];
-    l.x1 = io.state[2L * pr.n_c + e];
-    l.x2 = pr.jinv[e];
+    l.x0 = ((gptr_f)io.state)[pr.n_c + e];
+    l.x1 = ((gptr_f)io.state)[2L * pr.n_c + e];
+    l.x2 = ((gptr_f)pr.jinv)[e];
   }
   return l;
 }
@@ -216,32 +222,76 @@ __device__ __forceinline__ void epi_finish(const ProbDev& pr, const LayerDev& ly
 
 __device__ __forceinline__ int dot_group_of(int epi, int iter) { return epi == EPI_PCG ? pi_grp(iter) : 0; }
 
-// Global-address-space view of a device pointer held in a struct (loads
-// through it compile to global, not flat, memory instructions).
-typedef const float __attribute__((address_space(1)))* gptr_f;
-
 constexpr int kU = 4;  // elements per thread with loads in flight together
 constexpr int kUG = 6; // ... for the 36 x 36 windows of the global transform levels (one round at 256 threads)
 
 // ------------------------------------------------ inverse DWT, resident part
+// One line of a synthesis pass: outputs 2 K0 .. 2 (K0 + NP) - 1 of a line
+// whose coarse half sits at src[k S] (k < half) and detail half at
+// src[(half + k) S], written to dst[0 ..]; periodic:
+//   x_t = sum_{i = t mod 2} h_i a[(t-i)/2] + g_i d[(t-i)/2]   (indices mod half)
+// Consecutive output pairs share four of their six taps, so the NP + 2 taps
+// of each half are read once into registers.
+template <int NP>
+__device__ __forceinline__ void syn_line(const float* src, int S, int half, int K0, const Filter& F, float* dst) {
+  float a[NP + 2], d[NP + 2];
+#pragma unroll
+  for (int i = 0; i < NP + 2; ++i) {
+    const int k = (K0 - 2 + i) & (half - 1);
+    a[i] = src[k * S];
+    d[i] = src[(half + k) * S];
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {  // a[p + 2] = a[k0], a[p + 1] = a[k0 - 1], a[p] = a[k0 - 2]
+    dst[2 * p] = F.h[0] * a[p + 2] + F.h[2] * a[p + 1] + F.h[4] * a[p] + F.g[0] * d[p + 2] + F.g[2] * d[p + 1] +
+                 F.g[4] * d[p];
+    dst[2 * p + 1] = F.h[1] * a[p + 2] + F.h[3] * a[p + 1] + F.h[5] * a[p] + F.g[1] * d[p + 2] +
+                     F.g[3] * d[p + 1] + F.g[5] * d[p];
+  }
+}
+
+// A synthesis pass over m lines of side m: line l (one per lane position)
+// reads src + l (stride S along the line) and writes dst + l S.  Each thread
+// takes np consecutive output pairs of one line (np = m^2 / 2 / threads,
+// at least 1), so neighbouring lanes touch neighbouring LDS words.
+__device__ __forceinline__ void syn_pass(const float* src, float* dst, int S, int m, const Filter& F) {
+  const int half = m >> 1, nt = blockDim.x;
+  const int np = max(1, m * half / nt), nch = half / np, lm = __builtin_ctz(m);
+  for (int task = threadIdx.x; task < m * nch; task += nt) {
+    const int l = task & (m - 1), K0 = (task >> lm) * np;
+    for (int p0 = 0; p0 < np; p0 += 8) {
+      const int k = K0 + p0, c = min(np - p0, 8);
+      float* o = dst + l * S + 2 * k;
+      if (c == 8)
+        syn_line<8>(src + l, S, half, k, F, o);
+      else if (c == 4)
+        syn_line<4>(src + l, S, half, k, F, o);
+      else if (c == 2)
+        syn_line<2>(src + l, S, half, k, F, o);
+      else
+        syn_line<1>(src + l, S, half, k, F, o);
+    }
+  }
+}
+
 // One workgroup per (problem, layer): all synthesis levels whose output side
 // is at most the layer's resident side R (<= RMAX, the LDS capacity of the
-// instantiation) run in LDS.  Columns then rows, periodic, Mallat layout:
-//   x_t = sum_{i = t mod 2} h_i a[(t-i)/2] + g_i d[(t-i)/2]   (indices mod m/2)
+// instantiation) run in LDS.  Columns then rows, periodic, Mallat layout.
+// The LDS rows have the odd stride S = R + 1 and the column pass writes its
+// result transposed (Bt[c][t] = x[t][c]), so both passes walk their lines
+// with lanes on consecutive words and strided writes free of bank conflicts.
 template <int RMAX>
 __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
                                                    const Tile* tiles, Filter F, int src_mode, int out_mode,
                                                    int iter) {
-  __shared__ float A[RMAX * RMAX];
-  __shared__ float B[RMAX * RMAX];
-  __shared__ double sbeta;
+  __shared__ float A[RMAX * (RMAX + 1)];
+  __shared__ float B[RMAX * (RMAX + 1)];
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[pr.layer0 + t.item];
   const IoDev& io = IO[t.prob];
-  const float beta = compute_beta(pr, src_mode, iter, &sbeta);
-  const PSrc ps = make_psrc(pr, io, src_mode, iter, beta);
-  const int n = ly.n, R = ly.res, lr = __builtin_ctz(R);
+  PSrc ps = make_psrc(pr, io, src_mode, iter, 0.f);
+  const int n = ly.n, R = ly.res, lr = __builtin_ctz(R), S = R + 1;
   const int m0 = n >> ly.levels;
   const int off = ly.off;
   const int nt = blockDim.x;
@@ -256,34 +306,18 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
       const int e = e0 + u * nt;
       if (e < R * R) v[u] = coef_fetch(ps, off + (e >> lr) * n + (e & (R - 1)));
     }
+    if (e0 == threadIdx.x) ps.beta = wave_beta(pr, src_mode, iter);
 #pragma unroll
     for (int u = 0; u < kUL; ++u) {
       const int e = e0 + u * nt;
-      if (e < R * R) A[e] = coef_finish(ps, off + (e >> lr) * n + (e & (R - 1)), v[u], true);
+      if (e < R * R) A[(e >> lr) * S + (e & (R - 1))] = coef_finish(ps, off + (e >> lr) * n + (e & (R - 1)), v[u], true);
     }
   }
   __syncthreads();
   for (int m = 2 * m0; m <= R; m <<= 1) {
-    const int half = m >> 1, lh = __builtin_ctz(half), lm = lh + 1;
-    for (int e = threadIdx.x; e < m * m; e += nt) {  // columns (along y)
-      const int tt = e >> lm, c = e & (m - 1);
-      const int par = tt & 1, k0 = (tt - par) >> 1;
-      const int ka = k0 & (half - 1), kb = (k0 - 1) & (half - 1), kc = (k0 - 2) & (half - 1);
-      const float acc = F.h[par] * A[(ka << lr) + c] + F.h[par + 2] * A[(kb << lr) + c] +
-                        F.h[par + 4] * A[(kc << lr) + c] + F.g[par] * A[((half + ka) << lr) + c] +
-                        F.g[par + 2] * A[((half + kb) << lr) + c] + F.g[par + 4] * A[((half + kc) << lr) + c];
-      B[(tt << lr) + c] = acc;
-    }
+    syn_pass(A, B, S, m, F);  // columns (along y): A[t][c] -> B[c][t]
     __syncthreads();
-    for (int e = threadIdx.x; e < m * m; e += nt) {  // rows (along x)
-      const int r = e >> lm, tt = e & (m - 1);
-      const int par = tt & 1, k0 = (tt - par) >> 1;
-      const int ka = k0 & (half - 1), kb = (k0 - 1) & (half - 1), kc = (k0 - 2) & (half - 1);
-      const float* Br = B + (r << lr);
-      const float acc = F.h[par] * Br[ka] + F.h[par + 2] * Br[kb] + F.h[par + 4] * Br[kc] +
-                        F.g[par] * Br[half + ka] + F.g[par + 2] * Br[half + kb] + F.g[par + 4] * Br[half + kc];
-      A[(r << lr) + tt] = acc;
-    }
+    syn_pass(B, A, S, m, F);  // rows (along x): B[c][r] = row r of the level -> A[r][c]
     __syncthreads();
   }
   if (n == R) {
@@ -297,12 +331,12 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int e = e0 + u * nt;
-        if (e < R * R) out_finish(pr, io, out_mode, off + e, A[e] * ly.inv_delta, o[u]);
+        if (e < R * R) out_finish(pr, io, out_mode, off + e, A[(e >> lr) * S + (e & (R - 1))] * ly.inv_delta, o[u]);
       }
     }
   } else {
     float* dst = pr.tmpa + ly.tmp_off;
-    for (int e = threadIdx.x; e < R * R; e += nt) dst[e] = A[e];
+    for (int e = threadIdx.x; e < R * R; e += nt) dst[e] = A[(e >> lr) * S + (e & (R - 1))];
   }
 }
 
@@ -319,17 +353,15 @@ __global__ __launch_bounds__(256) void k_idwt_glob(const ProbDev* P, const Layer
                                                    int iter, int step) {
   __shared__ float A[kGW * (kGW + 1)];
   __shared__ float B[kGT * (kGW + 1)];
-  __shared__ double sbeta;
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[pr.layer0 + t.item];
   const IoDev& io = IO[t.prob];
-  const float beta = compute_beta(pr, src_mode, iter, &sbeta);
-  const PSrc ps = make_psrc(pr, io, src_mode, iter, beta);
+  PSrc ps = make_psrc(pr, io, src_mode, iter, 0.f);
   const int n = ly.n, off = ly.off;
   const int m = 1 << t.level, half = m >> 1;
   const int t0 = t.ty * kGT, s0 = t.tx * kGT;
-  const float* ll = ((step & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off;  // stride half
+  const gptr_f ll = (gptr_f)(((step & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off);  // stride half
   float* nxt = ((step & 1) ? pr.tmpa : pr.tmpb) + ly.tmp_off;       // stride m
   const int kr0 = (t0 >> 1) - 2, kc0 = (s0 >> 1) - 2;
   const int W1 = kGW + 1;
@@ -355,6 +387,7 @@ __global__ __launch_bounds__(256) void k_idwt_glob(const ProbDev* P, const Layer
         }
       }
     }
+    if (e0 == threadIdx.x) ps.beta = wave_beta(pr, src_mode, iter);
 #pragma unroll
     for (int u = 0; u < kUG; ++u) {
       const int e = e0 + u * nt;
@@ -422,7 +455,7 @@ __global__ __launch_bounds__(256) void k_fdwt_glob(const ProbDev* P, const Layer
   const IoDev& io = IO[t.prob];
   const int n = ly.n, off = ly.off;
   const int m = 1 << t.level, half = m >> 1;
-  const float* in = (step == 0) ? pr.phiadj + off : (((step & 1) ? pr.tmpa : pr.tmpb) + ly.tmp_off);
+  const gptr_f in = (gptr_f)((step == 0) ? pr.phiadj + off : (((step & 1) ? pr.tmpa : pr.tmpb) + ly.tmp_off));
   const int istride = (step == 0) ? n : m;
   float* llout = ((step & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off;  // stride half
   const int k0 = t.ty * kFT, l0 = t.tx * kFT;
@@ -506,20 +539,95 @@ __global__ __launch_bounds__(256) void k_fdwt_glob(const ProbDev* P, const Layer
 }
 
 // ------------------------------------------------ forward DWT, resident part
+// One line of an analysis pass: output pairs K0 .. K0 + NP - 1 of a periodic
+// line of side m read at src[x str]:
+//   a_k = sum_i h_i x[(2k + i) mod m],  d_k = sum_i g_i x[(2k + i) mod m]
+// Consecutive pairs share four of their six taps: 2 NP + 4 reads per line.
+template <int NP>
+__device__ __forceinline__ void ana_line(const float* src, int str, int m, int K0, const Filter& F, float a[NP],
+                                         float d[NP]) {
+  float x[2 * NP + 4];
+#pragma unroll
+  for (int i = 0; i < 2 * NP + 4; ++i) x[i] = src[((2 * K0 + i) & (m - 1)) * str];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    a[p] = 0.f;
+    d[p] = 0.f;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      a[p] += F.h[i] * x[2 * p + i];
+      d[p] += F.g[i] * x[2 * p + i];
+    }
+  }
+}
+
+// One analysis level of side m in LDS (A and B with row stride S), NP output
+// pairs per thread and line: rows A -> B (lanes on rows), then columns B -> A
+// (lanes on consecutive columns) with the epilogue of every detail output;
+// the coarse block stays in A for the next level.  The epilogue operands are
+// requested before the passes, so their latency overlaps the LDS work.
+template <int NP>
+__device__ __forceinline__ void ana_level(const ProbDev& pr, const LayerDev& ly, const IoDev& io, int epi, int iter,
+                                          float* A, float* B, int S, int m, const Filter& F, double& acc) {
+  const int half = m >> 1, lm = __builtin_ctz(m), nt = blockDim.x, n = ly.n, off = ly.off;
+  const int tasks = m * (half / NP);
+  const int j = lm - 1;  // detail blocks of this level have side half = 2^j
+  // column-pass outputs of this thread: column c, pairs K0 .. K0 + NP - 1
+  const int task = threadIdx.x;
+  const bool mine = task < tasks;  // tasks <= threads (NP = m half / threads, at least 1)
+  const int c = task & (m - 1), K0 = (task >> lm) * NP;
+  EpiLoad el[2 * NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    if (mine) {
+      const int k = K0 + p;
+      if (c >= half) el[2 * p] = epi_fetch(pr, io, epi, iter, off + k * n + c);
+      el[2 * p + 1] = epi_fetch(pr, io, epi, iter, off + (half + k) * n + c);
+    }
+  }
+  if (mine) {  // rows: line r = c of this task's numbering
+    float a[NP], d[NP];
+    ana_line<NP>(A + c * S, 1, m, K0, F, a, d);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      B[c * S + K0 + p] = a[p];
+      B[c * S + half + K0 + p] = d[p];
+    }
+  }
+  __syncthreads();
+  if (mine) {  // columns
+    float a[NP], d[NP];
+    ana_line<NP>(B + c, S, m, K0, F, a, d);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const int k = K0 + p;
+      if (c >= half) epi_finish(pr, ly, io, epi, off + k * n + c, j, a[p] * ly.inv_delta, el[2 * p], acc);
+      epi_finish(pr, ly, io, epi, off + (half + k) * n + c, j, d[p] * ly.inv_delta, el[2 * p + 1], acc);
+      A[k * S + c] = a[p];  // rows >= half of A are no longer read
+    }
+  }
+  __syncthreads();
+}
+
+// One workgroup per (problem, layer): all analysis levels from the resident
+// side R down to the coarsest block run in LDS, rows then columns, with the
+// epilogue of every output.  LDS rows have the odd stride S = R + 1 (strided
+// lane access free of bank conflicts).
 template <int RMAX>
 __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
                                                    const Tile* tiles, Filter F, int epi, int iter) {
-  __shared__ float A[RMAX * RMAX];
-  __shared__ float B[RMAX * RMAX];
+  static_assert(RMAX * RMAX / 2 <= 8 * 1024, "at most 8 output pairs per thread and line at 1024 threads");
+  __shared__ float A[RMAX * (RMAX + 1)];
+  __shared__ float B[RMAX * (RMAX + 1)];
   __shared__ double sh[16];
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[pr.layer0 + t.item];
   const IoDev& io = IO[t.prob];
-  const int n = ly.n, R = ly.res, lr = __builtin_ctz(R), off = ly.off;
+  const int n = ly.n, R = ly.res, lr = __builtin_ctz(R), off = ly.off, S = R + 1;
   const int nt = blockDim.x;
   const int ng = ly.n_glob_levels;
-  const float* in = (ng == 0) ? pr.phiadj + off : ((((ng - 1) & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off);
+  const gptr_f in = (gptr_f)((ng == 0) ? pr.phiadj + off : ((((ng - 1) & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off));
   const int istride = (ng == 0) ? n : R;
   constexpr int kUL = 16;  // the whole block's loads in flight together
   for (int e0 = threadIdx.x; e0 < R * R; e0 += kUL * nt) {
@@ -532,69 +640,29 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
 #pragma unroll
     for (int u = 0; u < kUL; ++u) {
       const int e = e0 + u * nt;
-      if (e < R * R) A[e] = v[u];
+      if (e < R * R) A[(e >> lr) * S + (e & (R - 1))] = v[u];
     }
   }
   __syncthreads();
   double acc = 0.0;
   const int m0 = n >> ly.levels;
-  // up to kEC column elements per thread per level (R <= 128, 1024 threads):
-  // element e = threadIdx.x + i nt of the half x m column pass, 2 outputs each
-  constexpr int kEC = RMAX * RMAX / 2 / 1024 > 0 ? RMAX * RMAX / 2 / 1024 : 1;
   for (int m = R; m > m0; m >>= 1) {
-    const int half = m >> 1, lm = __builtin_ctz(m), lh = lm - 1;
-    // epilogue operands of this level's outputs, fetched before the passes so
-    // that their latency overlaps the LDS work
-    EpiLoad el[2 * kEC];
-#pragma unroll
-    for (int i = 0; i < kEC; ++i) {
-      const int e = threadIdx.x + i * nt;
-      if (e < half * m) {
-        const int k = e >> lm, c = e & (m - 1);
-        if (c >= half) el[2 * i] = epi_fetch(pr, io, epi, iter, off + k * n + c);
-        el[2 * i + 1] = epi_fetch(pr, io, epi, iter, off + (half + k) * n + c);
-      }
-    }
-    for (int e = threadIdx.x; e < m * half; e += nt) {  // rows: A -> B
-      const int r = e >> lh, k = e & (half - 1);
-      const float* Ar = A + (r << lr);
-      float a = 0.f, d = 0.f;
-#pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        const float v = Ar[(2 * k + i) & (m - 1)];
-        a += F.h[i] * v;
-        d += F.g[i] * v;
-      }
-      B[(r << lr) + k] = a;
-      B[(r << lr) + half + k] = d;
-    }
-    __syncthreads();
-    const int j = lm - 1;
-#pragma unroll
-    for (int i = 0; i < kEC; ++i) {  // columns: B -> A and the epilogue of both outputs
-      const int e = threadIdx.x + i * nt;
-      if (e < half * m) {
-        const int k = e >> lm, c = e & (m - 1);
-        float a = 0.f, d = 0.f;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-          const float v = B[(((2 * k + q) & (m - 1)) << lr) + c];
-          a += F.h[q] * v;
-          d += F.g[q] * v;
-        }
-        if (c >= half) epi_finish(pr, ly, io, epi, off + k * n + c, j, a * ly.inv_delta, el[2 * i], acc);
-        epi_finish(pr, ly, io, epi, off + (half + k) * n + c, j, d * ly.inv_delta, el[2 * i + 1], acc);
-        A[(k << lr) + c] = a;  // rows >= half of A are no longer read
-      }
-    }
-    __syncthreads();
+    const int np = max(1, m * (m >> 1) / nt);  // output pairs per thread and line: 1, 2, 4 or 8
+    if (np >= 8)
+      ana_level<8>(pr, ly, io, epi, iter, A, B, S, m, F, acc);
+    else if (np == 4)
+      ana_level<4>(pr, ly, io, epi, iter, A, B, S, m, F, acc);
+    else if (np == 2)
+      ana_level<2>(pr, ly, io, epi, iter, A, B, S, m, F, acc);
+    else
+      ana_level<1>(pr, ly, io, epi, iter, A, B, S, m, F, acc);
   }
   const int jll = __builtin_ctz(m0);
   for (int e = threadIdx.x; e < m0 * m0; e += nt) {
     const int r = e / m0, c = e - r * m0;
     const int pos = off + r * n + c;
     const EpiLoad l = epi_fetch(pr, io, epi, iter, pos);
-    epi_finish(pr, ly, io, epi, pos, jll, A[(r << lr) + c] * ly.inv_delta, l, acc);
+    epi_finish(pr, ly, io, epi, pos, jll, A[r * S + c] * ly.inv_delta, l, acc);
   }
   if (epi == EPI_PCG || epi == EPI_RHS) {
     const double s = block_sum(acc, sh, nt);
@@ -1064,6 +1132,39 @@ __device__ __forceinline__ void pt_tiny3(const float* vsens, const BandRec* rec,
   }
 }
 
+// K = 2 sums for a band record with step pattern (D1, D2 - D1, D3 - D2)
+// (first corners of node rows 1..3 at band rows D1, D2, D3; row 0 at 0): the
+// band rows 0 .. D3 + 1 interpolated along x, then 2 y taps per node row.
+// Same products and order as the dense sums without their zero terms.
+template <int D1, int D2, int D3>
+__device__ __forceinline__ void pt_sum2(const BandRec* rec, const HatEnt& hx, const float v[pt_band(2, kBandRows)][2],
+                                        float acc[kBandRows]) {
+  typedef const __attribute__((address_space(4))) BandRec* crec;
+  const crec br = (crec)rec;
+  constexpr int NB = D3 + 2;
+  float r[NB];
+#pragma unroll
+  for (int s = 0; s < NB; ++s) r[s] = fmaf(hx.w[1], v[s][1], fmaf(hx.w[0], v[s][0], 0.f));
+  constexpr int d[kBandRows] = {0, D1, D2, D3};
+#pragma unroll
+  for (int u = 0; u < kBandRows; ++u)
+    acc[u] += fmaf(br->w[u][d[u] + 1], r[d[u] + 1], fmaf(br->w[u][d[u]], r[d[u]], 0.f));
+}
+__device__ __forceinline__ void pt_sum2_pat(int pat, const BandRec* rec, const HatEnt& hx,
+                                            const float v[pt_band(2, kBandRows)][2], float acc[kBandRows]) {
+  switch (pat) {
+    case 0: pt_sum2<0, 0, 0>(rec, hx, v, acc); break;
+    case 1: pt_sum2<1, 1, 1>(rec, hx, v, acc); break;
+    case 2: pt_sum2<0, 1, 1>(rec, hx, v, acc); break;
+    case 3: pt_sum2<1, 2, 2>(rec, hx, v, acc); break;
+    case 4: pt_sum2<0, 0, 1>(rec, hx, v, acc); break;
+    case 5: pt_sum2<1, 1, 2>(rec, hx, v, acc); break;
+    case 6: pt_sum2<0, 1, 2>(rec, hx, v, acc); break;
+    case 7: pt_sum2<1, 2, 3>(rec, hx, v, acc); break;
+    default: pt_band_sum<2>(rec, hx, v, acc); break;
+  }
+}
+
 // What the sensor loop prefetches one sensor ahead (column hat, band-row
 // offsets of the wave's first record) and two ahead (parameters).
 struct PtNext {
@@ -1092,15 +1193,22 @@ __device__ __forceinline__ void pt_sensor(const float* vsens, int nc, const Band
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc((void*)vsens, (short)0, nc * nc * (int)sizeof(float), 0x00020000);
   const int vo = hx.lo * (int)sizeof(float);
+  typedef const __attribute__((address_space(4))) int* cint;
   float v[SB][K];
   pt_band_load<K>(rs, vo, so, v);
   pt_prefetch(glb, gnn, G, L, nxt, hats, bands, n, q, grp0, f);
-  pt_band_sum<K>(rec, hx, v, acc);
+  if (K == 2)
+    pt_sum2_pat(*(cint)&rec->pat, rec, hx, (const float(*)[2])v, acc);
+  else
+    pt_band_sum<K>(rec, hx, v, acc);
 #pragma unroll
   for (int j = 1; j < RPT / kBandRows; ++j) {
     if (j >= ngrp) break;
     pt_band_load<K>(rs, vo, load_rows(rec + j), v);
-    pt_band_sum<K>(rec + j, hx, v, acc + j * kBandRows);
+    if (K == 2)
+      pt_sum2_pat(*(cint)&rec[j].pat, rec + j, hx, (const float(*)[2])v, acc + j * kBandRows);
+    else
+      pt_band_sum<K>(rec + j, hx, v, acc + j * kBandRows);
   }
 }
 
@@ -1181,27 +1289,19 @@ __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD
 // 2048 coefficients per workgroup as float4: 2 per thread, loads first.
 __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* IO, const Tile* tiles, int iter) {
   __shared__ double sh[4];
-  __shared__ double salpha;
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const IoDev& io = IO[t.prob];
-  if (threadIdx.x < 64) {
-    const double rho = wave_sum_slots(dot_group(pr, rho_grp(iter)), rho_count(pr, iter));
-    const double pi = wave_sum_slots(dot_group(pr, pi_grp(iter)), pr.n_slots_fdwt);
-    if (threadIdx.x == 0) salpha = (pi > 0.0) ? rho / pi : 0.0;
-  }
-  __syncthreads();
-  const float a = (float)salpha;
-  const float4* p = (const float4*)((iter & 1) ? pr.pbuf1 : pr.pbuf0);
-  const float4* q = (const float4*)pr.q;
-  const float4* jv = (const float4*)pr.jinv;
-  float4* x = (float4*)io.state;
-  float4* r = (float4*)(io.state + 2L * pr.n_c);
+  const gptr_f4 p = (gptr_f4)((iter & 1) ? pr.pbuf1 : pr.pbuf0);
+  const gptr_f4 q = (gptr_f4)pr.q;
+  const gptr_f4 jv = (gptr_f4)pr.jinv;
+  const gptr_w4 x = (gptr_w4)io.state;
+  const gptr_w4 r = (gptr_w4)(io.state + 2L * pr.n_c);
   const int e0 = t.ty * (kUpdChunk / 4);
   const int e1 = min(e0 + kUpdChunk / 4, pr.n_c / 4);
   double acc = 0.0;
   constexpr int V = kUpdChunk / 4 / 256;  // float4 per thread
-  float4 xp[V], pp[V], rr[V], qq[V], jj[V];
+  v4f xp[V], pp[V], rr[V], qq[V], jj[V];
 #pragma unroll
   for (int u = 0; u < V; ++u) {
     const int e = e0 + threadIdx.x + u * 256;
@@ -1213,11 +1313,16 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
       jj[u] = jv[e];
     }
   }
+  // alpha = rho_k / pi_k, summed by every wave itself in the same fixed order
+  // (no barrier) while its loads are in flight
+  const double rho = wave_sum_slots(dot_group(pr, rho_grp(iter)), rho_count(pr, iter));
+  const double pi = wave_sum_slots(dot_group(pr, pi_grp(iter)), pr.n_slots_fdwt);
+  const float a = (float)((pi > 0.0) ? rho / pi : 0.0);
 #pragma unroll
   for (int u = 0; u < V; ++u) {
     const int e = e0 + threadIdx.x + u * 256;
     if (e < e1) {
-      float4 xn, rn;
+      v4f xn, rn;
       xn.x = fmaf(a, pp[u].x, xp[u].x);
       xn.y = fmaf(a, pp[u].y, xp[u].y);
       xn.z = fmaf(a, pp[u].z, xp[u].z);

@@ -15,12 +15,14 @@ def tuner(lib, tmp_path, monkeypatch):
     return autotune
 
 
-def fake_times(table):
+def fake_times(table, streams=None):
+    """Stand-in timer: table[(R, rows)] for one stream, streams[s] for s > 1."""
     calls = []
 
     def time_plan(ctxs, iters, tuning, steps=10, warmup=3):
-        calls.append((tuning["dwt_resident"], tuning["pt_rows"]))
-        return table[(tuning["dwt_resident"], tuning["pt_rows"])]
+        ns = tuning.get("streams", 1)
+        calls.append((tuning["dwt_resident"], tuning["pt_rows"], ns))
+        return table[(tuning["dwt_resident"], tuning["pt_rows"])] if ns == 1 else streams[ns]
     return time_plan, calls
 
 
@@ -45,3 +47,21 @@ def test_near_tie_keeps_the_default(tuner, monkeypatch):
     monkeypatch.setattr(tuner, "time_plan", tp)
     rec = tuner.tune([None], 4, use_cache=False)
     assert (rec["dwt_resident"], rec["pt_rows"]) == (128, 4)
+
+
+def test_streams_are_tuned_after_the_shapes(tuner, monkeypatch):
+    table = {(r, p): 1000.0 for r in (32, 64, 128) for p in (4, 8)}
+    # a clear gain from two streams is taken, for the best shapes only
+    tp, calls = fake_times(table, {2: 900.0})
+    monkeypatch.setattr(tuner, "time_plan", tp)
+    rec = tuner.tune([None, None], 4, use_cache=False)
+    assert (rec["dwt_resident"], rec["pt_rows"], rec["streams"]) == (128, 4, 2)
+    assert calls[-1] == (128, 4, 2) and len(calls) == 7
+    assert rec["streams_us"] == {"1": 1000.0, "2": 900.0}
+    # a near tie keeps one stream; a single problem is not split at all
+    tp, _ = fake_times(table, {2: 995.0})
+    monkeypatch.setattr(tuner, "time_plan", tp)
+    assert tuner.tune([None, None], 4, use_cache=False)["streams"] == 1
+    tp, calls = fake_times(table)
+    monkeypatch.setattr(tuner, "time_plan", tp)
+    assert tuner.tune([None], 4, use_cache=False)["streams"] == 1 and len(calls) == 6

@@ -58,6 +58,37 @@ def test_tuned_mixed_batch(gpu_lib):
     batch.close()
 
 
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_streams_split_matches_one_stream_bitwise(gpu_lib, use_graph):
+    # uneven batch (2 MAORY-like + 3 VLT-like) in 2 and 4 parts against one
+    # part: every frame's state and layers bitwise equal; a copy queued on the
+    # caller's stream right after the call sees the finished frame (join)
+    import torch
+    cfgs = batch_mix(2, 3, 9)
+    systems = [System(c) for c in cfgs]
+    ctxs = [gpu_lib.Context(c, device=0) for c in cfgs]
+    slopes = [to_dev(synth_slopes(S, k)) for k, S in enumerate(systems)]
+    one = gpu_lib.Batch(ctxs)
+    for streams in (2, 4):
+        print("\n[gpu-tune] streams", streams, "graph", use_graph, flush=True)
+        split = gpu_lib.Batch(ctxs, tuning={"streams": streams})
+        st1 = [torch.zeros(c.n_state, device="cuda") for c in ctxs]
+        st2 = [torch.zeros(c.n_state, device="cuda") for c in ctxs]
+        l1 = [torch.empty(c.n_coeff, device="cuda") for c in ctxs]
+        l2 = [torch.full((c.n_coeff,), float("nan"), device="cuda") for c in ctxs]
+        for f in range(3):
+            one.reconstruct(slopes, st1, l1, iters=6, use_graph=use_graph)
+            split.reconstruct(slopes, st2, l2, iters=6, use_graph=use_graph)
+            snap = [t.clone() for t in l2]
+            torch.cuda.synchronize()
+            for k in range(len(ctxs)):
+                assert torch.equal(st1[k], st2[k]), (streams, f, k)
+                assert torch.equal(l1[k], l2[k]), (streams, f, k)
+                assert torch.equal(snap[k], l1[k]), (streams, f, k)
+        split.close()
+    one.close()
+
+
 def test_resident_side_below_coarse_block_is_rejected(gpu_lib):
     cfg = get_config("tiny")
     for l in cfg["layers"]:

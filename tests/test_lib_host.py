@@ -140,4 +140,16 @@ def test_tuning_arguments_are_validated(lib):
         assert _abi.fewha_set_tuning(h, byref(_tuning(good))) == 0
     for rows in (0, 4, 8):
         assert _abi.fewha_set_tuning(h, byref(_tuning({"dwt_resident": 64, "pt_rows": rows}))) == 0
+    # a context runs one stream
+    assert _abi.fewha_set_tuning(h, byref(_tuning({"streams": 2}))) == -1
+    for one in (0, 1):
+        assert _abi.fewha_set_tuning(h, byref(_tuning({"streams": one}))) == 0
     _abi.fewha_destroy(h)
+    # a batch takes 1..4 streams, at most one per problem; the tuning is checked
+    # before the contexts (these are host-only, so a valid tuning gets ESTATE)
+    arr = (c_void_p * 2)(ctx.h.value, ctx.h.value)
+    b = c_void_p()
+    for bad in (-1, 3, 5):
+        assert _abi.fewha_batch_create_tuned(byref(b), arr, 2, byref(_tuning({"streams": bad}))) == -1
+    for ok in (0, 1, 2):
+        assert _abi.fewha_batch_create_tuned(byref(b), arr, 2, byref(_tuning({"streams": ok}))) == -4
