@@ -38,7 +38,7 @@ def main():
         from paper_2202_11945_amd import autotune
         rec = autotune.tune(ctxs, a.iters)
         tuning = {"dwt_resident": rec["dwt_resident"], "pt_rows": rec["pt_rows"]}
-    print("tuning %d/%d" % (tuning["dwt_resident"] or 128, tuning["pt_rows"] or 4), flush=True)
+    print("tuning %d/%d batch %d" % (tuning["dwt_resident"] or 128, tuning["pt_rows"] or 4, a.batch), flush=True)
     batch = fw.Batch(ctxs, tuning=tuning)
     dev = torch.device("cuda:0")
     slopes = [torch.from_numpy(random_vector(ctxs[0].n_slopes, 5, k)).to(dev) for k in range(a.batch)]
