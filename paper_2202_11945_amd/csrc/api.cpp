@@ -73,6 +73,7 @@ struct Plan {
   GradIo* dGIO = nullptr;
   const HatEnt* dHat = nullptr;              // hat tables of the propagation adjoint
   const BandRec* dBand = nullptr;            // band records of the propagation adjoint
+  const PtEnt* dPtE = nullptr;               // sensor lists of the propagation-adjoint tiles
   std::vector<float*> sstate;                // per problem: [x | unused | r] of a solve
   double* rho_host = nullptr;                // pinned readback: 2 n_dots doubles per problem
   std::vector<long> rho_off;
@@ -231,6 +232,37 @@ void set_hats(GLPar& gp, int n, HatTables& T) {
   T.seen[key] = {gp.kmax, gp.hat_off, gp.band_off};
 }
 
+// Sensor lists of propagation-adjoint tiles, one copy per distinct list.
+struct PtLists {
+  std::vector<PtEnt> ents;
+  std::map<std::vector<int>, int> seen;
+  // tile (ty, tx) of a layer with n node rows and columns, pair parameters
+  // gl[g * L + item] for the sensors g in `use`: returns {offset, count}
+  std::pair<int, int> add(const std::vector<GLPar>& gl, int L, int item, const std::vector<int>& use, int n,
+                          int ty, int tx, int pt_rows) {
+    std::vector<int> key;
+    if (use.size() > 63) return {-1, 0};  // a wave reads its tile's list (and the pad) from 64 lanes
+    for (int g : use) {
+      const GLPar& gp = gl[(size_t)g * L + item];
+      PtEnt e{gp.v_off, gp.nc << 2 | gp.kmax, 0, 0};
+      if (gp.kmax > 0) {
+        e.hx = gp.hat_off + n + tx * kPtW;
+        e.band = gp.band_off + ty * pt_rows;  // kBandRows rows per record, 4 pt_rows rows per tile
+      } else {
+        e.nck = (g * L + item) << 2;
+      }
+      key.insert(key.end(), {e.v_off, e.nck, e.hx, e.band});
+    }
+    key.insert(key.end(), {0, 2, 0, 0});  // the pad entry
+    auto it = seen.find(key);
+    if (it != seen.end()) return {it->second, (int)use.size()};
+    const int off = (int)ents.size();
+    for (size_t i = 0; i < key.size(); i += 4) ents.push_back(PtEnt{key[i], key[i + 1], key[i + 2], key[i + 3]});
+    seen[key] = off;
+    return {off, (int)use.size()};
+  }
+};
+
 // Byte-offset carving of the arena (256-byte aligned pieces).
 struct Carver {
   size_t off = 0;
@@ -290,6 +322,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   Carver cv;
   std::vector<Tile> t_idwt_res, t_fdwt_res, t_pg, t_gt, t_pt, t_upd, t_sinit, t_gprior, t_ghgt, t_r64wfs, t_r64pt;
   HatTables hats;  // hat tables and band records of every problem and fitting view, one set per plan
+  PtLists ptl;     // sensor lists of the propagation-adjoint tiles
   std::vector<std::vector<Tile>> t_r64inv(kMaxLevelsJ), t_r64fwd(kMaxLevelsJ);
   std::vector<std::vector<double>> cinv64(P.nprob), ftab64(P.nprob);
   std::vector<std::vector<Tile>> t_idwt_glob, t_fdwt_glob;
@@ -509,17 +542,21 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
       const int n = P.hL[pd.layer0 + l].n;
       for (int ty = 0; ty < cdiv(n, kPtH); ++ty)
         for (int tx = 0; tx < cdiv(n, kPtW); ++tx) {
-          int mask = 0;
+          std::vector<int> use;
           for (int g = 0; g < G; ++g) {
             const GLPar& gp = glp[k][(size_t)g * L + l];
             const double span = (gp.nc - 1) * gp.rho;
             auto meets = [&](double t0, int p0, int ext) {
               return p0 + ext - 1 >= t0 - 2.0 && p0 <= t0 + span + 2.0;
             };
-            if (meets(gp.t0y, ty * kPtH, kPtH) && meets(gp.t0x, tx * kPtW, kPtW)) mask |= (G <= 32) ? (1 << g) : 0;
+            if (meets(gp.t0y, ty * kPtH, kPtH) && meets(gp.t0x, tx * kPtW, kPtW)) use.push_back(g);
           }
-          if (G > 32) mask = -1;
-          t_pt.push_back({k, l, ty, tx, 0, 0, mask, 0});
+          const auto li = ptl.add(glp[k], L, l, use, n, ty, tx, pt_rows);
+          if (li.first < 0) {
+            err = "more than 63 sensors meet one propagation-adjoint tile";
+            return FEWHA_EINVAL;
+          }
+          t_pt.push_back({k, l, ty, tx, li.first, li.second, 0, 0});
         }
       const int nt = cdiv(n, kTileN);
       for (int ty = 0; ty < nt; ++ty)
@@ -665,10 +702,19 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
           t_ffL.push_back({fl.pL, d, ty, tx, 0, 0, 0, 0});
           t_ffD.push_back({fl.pD, d, ty, tx, 0, 0, 0, 0});
         }
+    std::vector<int> alld(K);
+    for (int d = 0; d < K; ++d) alld[d] = d;
     for (int q = 0; q < nd; ++q) {
       const int na = f.dms[q].n_act;
       for (int ty = 0; ty < cdiv(na, kPtH); ++ty)
-        for (int tx = 0; tx < cdiv(na, kPtW); ++tx) t_fpt.push_back({fl.pD, q, ty, tx, 0, 0, -1, 0});  // all directions
+        for (int tx = 0; tx < cdiv(na, kPtW); ++tx) {  // all directions
+          const auto li = ptl.add(fl.glp, nd, q, alld, na, ty, tx, pt_rows);
+          if (li.first < 0) {
+            err = "more than 63 fitting directions";
+            return FEWHA_EINVAL;
+          }
+          t_fpt.push_back({fl.pD, q, ty, tx, li.first, li.second, 0, 0});
+        }
     }
     t_fcg.push_back({(int)hF.size(), 0, 0, 0, 0, 0, 0, 0});
     FitDev fd{};
@@ -716,8 +762,12 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   const size_t oIO = cv.take(sizeof(IoDev) * P.nprob_all);
   const size_t oIOp = cv.take(sizeof(IoDev) * P.nprob_all);
   const size_t oGIO = cv.take(sizeof(GradIo) * P.nprob_all);
-  const size_t oHat = cv.take(sizeof(HatEnt) * std::max<size_t>(hats.hats.size(), 1));
-  const size_t oBand = cv.take(sizeof(BandRec) * std::max<size_t>(hats.bands.size(), 1));
+  // at least 64 hat entries and 8 band records: the padded prefetch addresses
+  hats.hats.resize(std::max<size_t>(hats.hats.size(), 64), HatEnt{0, {0.f, 0.f, 0.f}});
+  hats.bands.resize(std::max<size_t>(hats.bands.size(), 8), BandRec{});
+  const size_t oHat = cv.take(sizeof(HatEnt) * hats.hats.size());
+  const size_t oBand = cv.take(sizeof(BandRec) * hats.bands.size());
+  const size_t oPtE = cv.take(sizeof(PtEnt) * std::max<size_t>(ptl.ents.size(), 1));
   const size_t oF = cv.take(sizeof(FitDev) * std::max<size_t>(hF.size(), 1));
   const size_t oT = cv.take(sizeof(Tile) * std::max<size_t>(P.hT.size(), 1));
   P.arena_bytes = cv.off;
@@ -823,6 +873,9 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     HIP_TRY(hipMemcpy(base + oHat, hats.hats.data(), sizeof(HatEnt) * hats.hats.size(), hipMemcpyHostToDevice));
   if (!hats.bands.empty())
     HIP_TRY(hipMemcpy(base + oBand, hats.bands.data(), sizeof(BandRec) * hats.bands.size(), hipMemcpyHostToDevice));
+  P.dPtE = (const PtEnt*)(base + oPtE);
+  if (!ptl.ents.empty())
+    HIP_TRY(hipMemcpy(base + oPtE, ptl.ents.data(), sizeof(PtEnt) * ptl.ents.size(), hipMemcpyHostToDevice));
   P.dT = (Tile*)(base + oT);
   // work lists of the FP64 residual chain (device addresses: after P.dT is set)
   {
@@ -901,6 +954,7 @@ LaunchArgs args(const Plan& P, hipStream_t s, const IoDev* io) {
   a.pt_rows = P.pt_rows;
   a.hats = P.dHat;
   a.bands = P.dBand;
+  a.pents = P.dPtE;
   return a;
 }
 

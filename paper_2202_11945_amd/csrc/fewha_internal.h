@@ -125,6 +125,21 @@ struct BandRec {
 };
 static_assert(sizeof(BandRec) == 192, "band record: 48 dwords");
 
+// One sensor of a propagation-adjoint tile's list (the sensors whose
+// footprint meets the tile, in sensor order), all a wave needs for it:
+//   v_off : the sensor's corner grid in the problem's corner array
+//   nck   : K > 0: corner grid side nc << 2 | K;
+//           K = 0 (general gather): index of the pair's GLPar << 2
+//   hx    : K > 0: hat-table index of the tile's first node column, else 0
+//   band  : K > 0: band record of the tile's first kBandRows node rows, else 0
+// Every list ends with one more entry {0, 2, 0, 0} that is never run (the
+// sensor loop prefetches one entry ahead); the hat and band arrays hold at
+// least 64 and 8 entries, so every prefetch address is valid.
+struct PtEnt {
+  int v_off, nck, hx, band;
+};
+static_assert(sizeof(PtEnt) == 16, "one 16-byte scalar load per sensor");
+
 // One problem.
 struct ProbDev {
   int L, G;

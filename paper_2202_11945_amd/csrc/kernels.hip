@@ -988,7 +988,7 @@ __device__ __forceinline__ void pt_general(const GLPar& gp, const float* vadj, i
   const double cx = ((double)q - gp.t0x) * gp.inv_rho;
   const int jlo = max((int)floor(cx - gp.inv_rho) + 1, 0), jhi = min((int)ceil(cx + gp.inv_rho) - 1, gp.nc - 1);
   if (jhi < jlo) return;
-  const float* va = vadj + gp.v_off;
+  const gptr_f va = (gptr_f)(vadj + gp.v_off);
   const float r = (float)gp.rho;
 #pragma unroll
   for (int u = 0; u < RPT; ++u) {
@@ -1027,25 +1027,11 @@ __device__ __forceinline__ GLPar load_glpar(const GLPar* p) {
   return g;
 }
 
-// Integer part of GLPar (corner grid side, offset, K, table offsets), all the
-// fast path needs; scalar loads like load_glpar.
-struct PtPar {
-  int nc, v_off, kmax, hat_off, band_off;
-};
-static_assert(offsetof(GLPar, nc) == 32 && offsetof(GLPar, band_off) == 48, "GLPar layout");
-__device__ __forceinline__ PtPar load_ptpar(const GLPar* p) {
-  typedef const __attribute__((address_space(4))) double* cdbl;
+// One entry of a tile's sensor list, by scalar loads.
+__device__ __forceinline__ PtEnt load_ent(const PtEnt* p) {
   typedef const __attribute__((address_space(4))) int* cint;
-  const cint i = (cint)((cdbl)p + 4);
-  return PtPar{i[0], i[1], i[2], i[3], i[4]};
-}
-
-// Next sensor after g whose footprint meets the tile (G when none is left).
-__device__ __forceinline__ int pt_next(unsigned mask, int G, int g) {
-  if (G > 32) return g + 1;
-  const int f = g + 1;
-  const unsigned rest = f >= 32 ? 0u : (mask >> f) << f;
-  return rest ? __builtin_ctz(rest) : G;
+  const cint i = (cint)p;
+  return PtEnt{i[0], i[1], i[2], i[3]};
 }
 
 // Band-row byte offsets of one band record (scalar loads).
@@ -1063,14 +1049,18 @@ __device__ __forceinline__ BandRows load_rows(const BandRec* rec) {
 
 // Loads of one band: every band row once, K corners per lane (raw buffer
 // loads: lane offset vo from the column hat, row offset from the record).
+// The row offsets are wave-uniform; readfirstlane states it where register
+// pressure left them in vector registers (else each load became a loop).
 template <int K>
 __device__ __forceinline__ void pt_band_load(__amdgpu_buffer_rsrc_t rs, int vo, const BandRows& so,
                                              float v[pt_band(K, kBandRows)][K]) {
 #pragma unroll
-  for (int s = 0; s < pt_band(K, kBandRows); ++s)
+  for (int s = 0; s < pt_band(K, kBandRows); ++s) {
+    const int off = __builtin_amdgcn_readfirstlane(so.so[s]);
 #pragma unroll
     for (int b = 0; b < K; ++b)
-      v[s][b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo + b * (int)sizeof(float), so.so[s], 0));
+      v[s][b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo + b * (int)sizeof(float), off, 0));
+  }
 }
 
 // Separable sums of kBandRows node rows: each band row interpolated along x
@@ -1165,38 +1155,20 @@ __device__ __forceinline__ void pt_sum2_pat(int pat, const BandRec* rec, const H
   }
 }
 
-// What the sensor loop prefetches one sensor ahead (column hat, band-row
-// offsets of the wave's first record) and two ahead (parameters).
-struct PtNext {
-  PtPar nn;
-  HatEnt hx;
-  BandRows so;
-};
-__device__ __forceinline__ void pt_prefetch(const GLPar* glb, int gnn, int G, int L, const PtPar& nxt,
-                                            const HatEnt* __restrict__ hats, const BandRec* __restrict__ bands,
-                                            int n, int q, int grp0, PtNext& f) {
-  if (nxt.kmax) f.hx = hats[nxt.hat_off + n + q];
-  f.nn = gnn < G ? load_ptpar(glb + gnn * L) : PtPar{0, 0, 0, -1, -1};
-  if (nxt.kmax) f.so = load_rows(bands + nxt.band_off + grp0);
-}
-
 // One sensor of the fast path: its first band's loads go out before the
-// prefetches of the next sensors (so that waiting for them does not wait for
-// the prefetches), then the sums; a second record (RPT = 8) follows.
-template <int K, int RPT>
+// prefetches of the next sensor (`pre`), so that waiting for the band does
+// not wait for them; then the sums; a second record (RPT = 8) follows.
+template <int K, int RPT, class Pre>
 __device__ __forceinline__ void pt_sensor(const float* vsens, int nc, const BandRec* rec, const BandRows& so,
-                                          const HatEnt& hx, int ngrp, const GLPar* glb, int gnn, int G, int L,
-                                          const PtPar& nxt, const HatEnt* __restrict__ hats,
-                                          const BandRec* __restrict__ bands, int n, int q, int grp0, PtNext& f,
-                                          float acc[RPT]) {
+                                          const HatEnt& hx, int ngrp, float acc[RPT], Pre pre) {
   constexpr int SB = pt_band(K, kBandRows);
+  typedef const __attribute__((address_space(4))) int* cint;
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc((void*)vsens, (short)0, nc * nc * (int)sizeof(float), 0x00020000);
   const int vo = hx.lo * (int)sizeof(float);
-  typedef const __attribute__((address_space(4))) int* cint;
   float v[SB][K];
   pt_band_load<K>(rs, vo, so, v);
-  pt_prefetch(glb, gnn, G, L, nxt, hats, bands, n, q, grp0, f);
+  pre();
   if (K == 2)
     pt_sum2_pat(*(cint)&rec->pat, rec, hx, (const float(*)[2])v, acc);
   else
@@ -1213,69 +1185,81 @@ __device__ __forceinline__ void pt_sensor(const float* vsens, int nc, const Band
 }
 
 // Tile = 4 RPT node rows x 64 node columns; wave w owns the RPT rows from
-// p0 = 4 RPT ty + RPT w (RPT / kBandRows band records).  Sensors whose
-// footprint misses the tile are skipped (tile mask).  The sensor loop is
-// software-pipelined so that one memory round trip per sensor is exposed.
+// p0 = 4 RPT ty + RPT w (RPT / kBandRows band records).  The tile's sensor
+// list (the sensors whose footprint meets it, at most 63, built on the host,
+// then a pad entry) is loaded once, entry i in lane i, and read back with
+// readlane.  The sensor loop is software-pipelined: the column hat and
+// band-row offsets of the next sensor are requested, unconditionally, before
+// the current sensor's band.
 template <int RPT>
 __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD, const WfsDev* WD, const IoDev* IO,
                                             const Tile* tiles, const HatEnt* __restrict__ hats,
-                                            const BandRec* __restrict__ bands, int mode) {
+                                            const BandRec* __restrict__ bands, const PtEnt* __restrict__ ents,
+                                            int mode) {
   static_assert(RPT % kBandRows == 0, "whole band records per wave");
+  typedef const int __attribute__((address_space(1)))* gptr_i;
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[pr.layer0 + t.item];
-  const IoDev& io = IO[t.prob];
   const int n = ly.n;
+  const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  const int q = t.tx * kPtW + (threadIdx.x & 63);
+  const int ne = t.level;  // sensors in the tile's list (<= 63; the pad entry follows)
+  // the list, entry i in lane i (loaded by every lane, before any returns)
+  int m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+  if (lane <= ne) {
+    const gptr_i e = (gptr_i)(ents + t.slot + lane);
+    m0 = e[0];
+    m1 = e[1];
+    m2 = e[2];
+    m3 = e[3];
+  }
+  auto ent = [&](int i) {
+    return PtEnt{__builtin_amdgcn_readlane(m0, i), __builtin_amdgcn_readlane(m1, i),
+                 __builtin_amdgcn_readlane(m2, i), __builtin_amdgcn_readlane(m3, i)};
+  };
+  const int q = t.tx * kPtW + lane;
   const int p0 = t.ty * 4 * RPT + wv * RPT;
   if (q >= n || p0 >= n) return;  // no barriers in this kernel
-  const int grp0 = p0 / kBandRows;
+  const int wrec = wv * (RPT / kBandRows);  // this wave's first record past the tile's
   const int ngrp = min(RPT / kBandRows, (n - p0 + kBandRows - 1) / kBandRows);  // records inside the layer
   float acc[RPT];
 #pragma unroll
   for (int u = 0; u < RPT; ++u) acc[u] = 0.f;
-  const int G = pr.G, L = pr.L;
-  const unsigned mask = (unsigned)t.mask;
-  const GLPar* glb = pr.gl + t.item;  // pair (g, this layer) at glb[g L]
-  const PtPar none{0, 0, 0, -1, -1};
-  int g = pt_next(mask, G, -1);
-  int gn = g < G ? pt_next(mask, G, g) : G;
-  PtPar cur = g < G ? load_ptpar(glb + g * L) : none;
-  PtNext f;
-  f.hx = HatEnt{0, {0.f, 0.f, 0.f}};
-  f.nn = gn < G ? load_ptpar(glb + gn * L) : none;
-  if (cur.kmax) {
-    f.hx = hats[cur.hat_off + n + q];
-    f.so = load_rows(bands + cur.band_off + grp0);
-  }
-  while (g < G) {
-    const PtPar nxt = f.nn;
-    const HatEnt hx = f.hx;
-    const BandRows so = f.so;
-    const int gnn = gn < G ? pt_next(mask, G, gn) : G;
-    if (cur.kmax == 0) {
-      pt_prefetch(glb, gnn, G, L, nxt, hats, bands, n, q, grp0, f);
-      pt_general<RPT>(load_glpar(glb + g * L), pr.vadj, q, p0, n, acc);
-    } else if (cur.nc == 3 && cur.kmax == 2) {  // 3 x 3 corner grid
-      pt_prefetch(glb, gnn, G, L, nxt, hats, bands, n, q, grp0, f);
-      const BandRec* rec = bands + cur.band_off + grp0;
+  auto fetch = [&](const PtEnt& e, HatEnt& hx, BandRows& so) {  // valid for every entry (see PtEnt)
+    hx = hats[e.hx + lane];
+    so = load_rows(bands + e.band + wrec);
+  };
+  // one sensor: its band, the next sensor's prefetch (`pre`), the sums
+  auto sensor = [&](const PtEnt& cur, const HatEnt& hx, const BandRows& so, auto pre) {
+    const int K = cur.nck & 3, nc = cur.nck >> 2;
+    const float* vs = pr.vadj + cur.v_off;
+    const BandRec* rec = bands + cur.band + wrec;
+    if (K == 0) {
+      pre();
+      pt_general<RPT>(load_glpar(pr.gl + (cur.nck >> 2)), pr.vadj, q, p0, n, acc);
+    } else if (nc == 3 && K == 2) {  // 3 x 3 corner grid
+      pre();
 #pragma unroll
       for (int j = 0; j < RPT / kBandRows; ++j) {
         if (j >= ngrp) break;
-        pt_tiny3(pr.vadj + cur.v_off, rec + j, hx, acc + j * kBandRows);
+        pt_tiny3(vs, rec + j, hx, acc + j * kBandRows);
       }
-    } else if (cur.kmax == 2) {
-      pt_sensor<2, RPT>(pr.vadj + cur.v_off, cur.nc, bands + cur.band_off + grp0, so, hx, ngrp, glb, gnn, G, L,
-                        nxt, hats, bands, n, q, grp0, f, acc);
+    } else if (K == 2) {
+      pt_sensor<2, RPT>(vs, nc, rec, so, hx, ngrp, acc, pre);
     } else {
-      pt_sensor<3, RPT>(pr.vadj + cur.v_off, cur.nc, bands + cur.band_off + grp0, so, hx, ngrp, glb, gnn, G, L,
-                        nxt, hats, bands, n, q, grp0, f, acc);
+      pt_sensor<3, RPT>(vs, nc, rec, so, hx, ngrp, acc, pre);
     }
-    g = gn;
-    gn = gnn;
-    cur = nxt;
+  };
+  HatEnt hx, hxn;
+  BandRows so, son;
+  fetch(ent(0), hx, so);
+  for (int i = 0; i < ne; ++i) {
+    sensor(ent(i), hx, so, [&]() { fetch(ent(i + 1), hxn, son); });
+    hx = hxn;
+    so = son;
   }
+  const IoDev& io = IO[t.prob];
   float* dst = (mode == PT_USER) ? io.out : pr.phiadj;
 #pragma unroll
   for (int u = 0; u < RPT; ++u) {
@@ -1595,9 +1579,9 @@ void launch_gammaT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode)
 void launch_pT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
   if (ntiles <= 0) return;
   if (a.pt_rows == 8)
-    k_pT<8><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.bands, mode);
+    k_pT<8><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.bands, a.pents, mode);
   else
-    k_pT<4><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.bands, mode);
+    k_pT<4><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.bands, a.pents, mode);
 }
 void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter) {
   if (ntiles > 0) k_update<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles, iter);
