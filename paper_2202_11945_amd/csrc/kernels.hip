@@ -274,6 +274,43 @@ __device__ __forceinline__ void syn_pass(const float* src, float* dst, int S, in
   }
 }
 
+// The last synthesis pass (rows) written straight to global memory:
+// g[l gs + t] = scale x_t for line l, each thread its run of 2 np outputs
+// (float4 stores when `vec`: g, gs and the runs 16-byte aligned).
+__device__ __forceinline__ void syn_pass_out(const float* src, int S, int m, const Filter& F, float* g, int gs,
+                                             float scale, bool vec) {
+  const int half = m >> 1, nt = blockDim.x;
+  const int np = max(1, m * half / nt), nch = half / np, lm = __builtin_ctz(m);
+  typedef v4f __attribute__((address_space(1)))* gw4;
+  typedef float __attribute__((address_space(1)))* gw1;
+  for (int task = threadIdx.x; task < m * nch; task += nt) {
+    const int l = task & (m - 1), K0 = (task >> lm) * np;
+    for (int p0 = 0; p0 < np; p0 += 8) {
+      const int k = K0 + p0, c = min(np - p0, 8);
+      float o[16];
+      if (c == 8)
+        syn_line<8>(src + l, S, half, k, F, o);
+      else if (c == 4)
+        syn_line<4>(src + l, S, half, k, F, o);
+      else if (c == 2)
+        syn_line<2>(src + l, S, half, k, F, o);
+      else
+        syn_line<1>(src + l, S, half, k, F, o);
+      float* dst = g + (long)l * gs + 2 * k;
+      if (vec && c >= 2) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (4 * i < 2 * c)
+            ((gw4)dst)[i] = v4f{o[4 * i] * scale, o[4 * i + 1] * scale, o[4 * i + 2] * scale, o[4 * i + 3] * scale};
+      } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (i < 2 * c) ((gw1)dst)[i] = o[i] * scale;
+      }
+    }
+  }
+}
+
 // One workgroup per (problem, layer): all synthesis levels whose output side
 // is at most the layer's resident side R (<= RMAX, the LDS capacity of the
 // instantiation) run in LDS.  Columns then rows, periodic, Mallat layout.
@@ -314,12 +351,25 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
     }
   }
   __syncthreads();
+  // the last rows pass stores the output itself (layers, caller buffer, or
+  // the coarse block of the first global level); the control update of a
+  // frame's final transform keeps the separate output phase
+  const bool plain_out = n != R || out_mode == OUT_PHI || out_mode == OUT_USER;
+  const bool direct = plain_out && 2 * m0 <= R;
+  float* gout = n != R ? pr.tmpa + ly.tmp_off : ((out_mode == OUT_PHI ? pr.phi : io.out) + off);
+  const int gs = n != R ? R : n;
+  const bool vec = (((uintptr_t)gout) & 15) == 0;
   for (int m = 2 * m0; m <= R; m <<= 1) {
     syn_pass(A, B, S, m, F);  // columns (along y): A[t][c] -> B[c][t]
     __syncthreads();
-    syn_pass(B, A, S, m, F);  // rows (along x): B[c][r] = row r of the level -> A[r][c]
-    __syncthreads();
+    if (m == R && direct) {
+      syn_pass_out(B, S, m, F, gout, gs, n != R ? 1.f : ly.inv_delta, vec);
+    } else {
+      syn_pass(B, A, S, m, F);  // rows (along x): B[c][r] = row r of the level -> A[r][c]
+      __syncthreads();
+    }
   }
+  if (direct) return;
   if (n == R) {
     for (int e0 = threadIdx.x; e0 < R * R; e0 += kU * nt) {
       OutLoad o[kU];
@@ -609,11 +659,91 @@ __device__ __forceinline__ void ana_level(const ProbDev& pr, const LayerDev& ly,
   __syncthreads();
 }
 
+// Output pairs per thread and line of an analysis level of side m at 1024
+// threads (at least 1).
+constexpr int ana_np(int m) { return m * (m / 2) / 1024 > 1 ? m * (m / 2) / 1024 : 1; }
+constexpr int ilog2c(int m) { return m <= 1 ? 0 : 1 + ilog2c(m / 2); }
+
+// The PCG epilogue's one operand (p) at every output of this thread, for the
+// levels of side M and below, held in registers so that all of them are
+// requested when the workgroup starts.
+template <int M>
+struct PcgOps {
+  float p[2 * ana_np(M)];
+  PcgOps<M / 2> next;
+};
+template <>
+struct PcgOps<1> {};
+
+template <int M>
+__device__ __forceinline__ void pcg_fetch(gptr_f pb, int off, int n, int R, int m0, PcgOps<M>& o) {
+  constexpr int NP = ana_np(M), half = M / 2;
+  if (M <= R && M > m0 && (int)threadIdx.x < M * (half / NP)) {
+    const int c = threadIdx.x & (M - 1), K0 = ((int)threadIdx.x >> ilog2c(M)) * NP;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const int k = K0 + p;
+      o.p[2 * p] = c >= half ? pb[off + k * n + c] : 0.f;
+      o.p[2 * p + 1] = pb[off + (half + k) * n + c];
+    }
+  }
+  if constexpr (M > 2) pcg_fetch<M / 2>(pb, off, n, R, m0, o.next);
+}
+
+// One analysis level of side M with the PCG epilogue (q = delta^{-1} W p +
+// alpha D p, += p q) from operands already in registers: the same passes,
+// products and order as ana_level with EPI_PCG.
+template <int M>
+__device__ __forceinline__ void pcg_level(const ProbDev& pr, const LayerDev& ly, float* A, float* B, int S,
+                                          const Filter& F, const float* op, double& acc) {
+  constexpr int NP = ana_np(M), half = M / 2, lm = ilog2c(M);
+  const int n = ly.n, off = ly.off;
+  const bool mine = (int)threadIdx.x < M * (half / NP);
+  const int c = threadIdx.x & (M - 1), K0 = ((int)threadIdx.x >> lm) * NP;
+  const float ad = ly.alpha_d[lm - 1];
+  if (mine) {  // rows
+    float a[NP], d[NP];
+    ana_line<NP>(A + c * S, 1, M, K0, F, a, d);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      B[c * S + K0 + p] = a[p];
+      B[c * S + half + K0 + p] = d[p];
+    }
+  }
+  __syncthreads();
+  if (mine) {  // columns and the epilogue
+    float a[NP], d[NP];
+    ana_line<NP>(B + c, S, M, K0, F, a, d);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const int k = K0 + p;
+      if (c >= half) {
+        const float qe = a[p] * ly.inv_delta + ad * op[2 * p];
+        pr.q[off + k * n + c] = qe;
+        acc += (double)op[2 * p] * (double)qe;
+      }
+      const float qd = d[p] * ly.inv_delta + ad * op[2 * p + 1];
+      pr.q[off + (half + k) * n + c] = qd;
+      acc += (double)op[2 * p + 1] * (double)qd;
+      A[k * S + c] = a[p];
+    }
+  }
+  __syncthreads();
+}
+
+template <int M>
+__device__ __forceinline__ void pcg_levels(const ProbDev& pr, const LayerDev& ly, float* A, float* B, int S, int R,
+                                           int m0, const Filter& F, const PcgOps<M>& o, double& acc) {
+  if (M <= R && M > m0) pcg_level<M>(pr, ly, A, B, S, F, o.p, acc);
+  if constexpr (M > 2) pcg_levels<M / 2>(pr, ly, A, B, S, R, m0, F, o.next, acc);
+}
+
 // One workgroup per (problem, layer): all analysis levels from the resident
 // side R down to the coarsest block run in LDS, rows then columns, with the
 // epilogue of every output.  LDS rows have the odd stride S = R + 1 (strided
-// lane access free of bank conflicts).
-template <int RMAX>
+// lane access free of bank conflicts).  PCG = the EPI_PCG instantiation,
+// whose epilogue operands for every level are requested with the input.
+template <int RMAX, bool PCG>
 __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
                                                    const Tile* tiles, Filter F, int epi, int iter) {
   static_assert(RMAX * RMAX / 2 <= 8 * 1024, "at most 8 output pairs per thread and line at 1024 threads");
@@ -629,6 +759,8 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
   const int ng = ly.n_glob_levels;
   const gptr_f in = (gptr_f)((ng == 0) ? pr.phiadj + off : ((((ng - 1) & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off));
   const int istride = (ng == 0) ? n : R;
+  const int m0 = n >> ly.levels;
+  PcgOps<PCG ? RMAX : 1> ops;  // the PCG epilogue's operands of every level
   constexpr int kUL = 16;  // the whole block's loads in flight together
   for (int e0 = threadIdx.x; e0 < R * R; e0 += kUL * nt) {
     float v[kUL];
@@ -643,10 +775,12 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
       if (e < R * R) A[(e >> lr) * S + (e & (R - 1))] = v[u];
     }
   }
-  __syncthreads();
+  // requested before the barrier: one memory round trip for every level
+  if constexpr (PCG) pcg_fetch<RMAX>((gptr_f)((iter & 1) ? pr.pbuf1 : pr.pbuf0), off, n, R, m0, ops);
   double acc = 0.0;
-  const int m0 = n >> ly.levels;
-  for (int m = R; m > m0; m >>= 1) {
+  __syncthreads();
+  if constexpr (PCG) pcg_levels<RMAX>(pr, ly, A, B, S, R, m0, F, ops, acc);
+  for (int m = R; m > m0 && !PCG; m >>= 1) {
     const int np = max(1, m * (m >> 1) / nt);  // output pairs per thread and line: 1, 2, 4 or 8
     if (np >= 8)
       ana_level<8>(pr, ly, io, epi, iter, A, B, S, m, F, acc);
@@ -1560,12 +1694,23 @@ void launch_fdwt_glob(const LaunchArgs& a, const Tile* tiles, int ntiles, int ep
 }
 void launch_fdwt_res(const LaunchArgs& a, const Tile* tiles, int ntiles, int epi, int iter) {
   if (ntiles <= 0) return;
-  if (a.res_max <= 32)
-    k_fdwt_res<32><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
-  else if (a.res_max <= 64)
-    k_fdwt_res<64><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
-  else
-    k_fdwt_res<128><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
+  const bool pcg = epi == EPI_PCG;
+  if (a.res_max <= 32) {
+    if (pcg)
+      k_fdwt_res<32, true><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
+    else
+      k_fdwt_res<32, false><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
+  } else if (a.res_max <= 64) {
+    if (pcg)
+      k_fdwt_res<64, true><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
+    else
+      k_fdwt_res<64, false><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
+  } else {
+    if (pcg)
+      k_fdwt_res<128, true><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
+    else
+      k_fdwt_res<128, false><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
+  }
 }
 void launch_pgamma(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
   if (ntiles > 0) k_pgamma<<<ntiles, kSensThreads, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, mode);
