@@ -390,6 +390,29 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
   }
 }
 
+// A run of NP synthesis output pairs from a window that holds its halo (no
+// wrap): pair p takes coarse taps a[base + p + 2], a[base + p + 1],
+// a[base + p] and the same detail taps (rows of stride S from a_src, d_src);
+// outputs 2p and 2p + 1 go to dst[2p ds], dst[(2p + 1) ds].  The same products
+// and order as the per-output form.
+template <int NP>
+__device__ __forceinline__ void syn_run(const float* a_src, const float* d_src, int S, int base, const Filter& F,
+                                        float* dst, int ds) {
+  float a[NP + 2], d[NP + 2];
+#pragma unroll
+  for (int i = 0; i < NP + 2; ++i) {
+    a[i] = a_src[(base + i) * S];
+    d[i] = d_src[(base + i) * S];
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    dst[(2 * p) * ds] = F.h[0] * a[p + 2] + F.h[2] * a[p + 1] + F.h[4] * a[p] + F.g[0] * d[p + 2] +
+                        F.g[2] * d[p + 1] + F.g[4] * d[p];
+    dst[(2 * p + 1) * ds] = F.h[1] * a[p + 2] + F.h[3] * a[p + 1] + F.h[5] * a[p] + F.g[1] * d[p + 2] +
+                            F.g[3] * d[p + 1] + F.g[5] * d[p];
+  }
+}
+
 // ----------------------------------------------- inverse DWT, one global level
 // Output tile 32x32 of the level with side m = 2^t.level (> the resident side).  The
 // coarse block comes from scratch, the three detail quadrants from the
@@ -452,13 +475,12 @@ __global__ __launch_bounds__(256) void k_idwt_glob(const ProbDev* P, const Layer
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < kGT * kGW; e += nt) {  // columns
-    const int lt = e / kGW, lx_ = e - lt * kGW;
-    const int par = lt & 1, k = ((lt - par) >> 1) + 2;
-    const float acc = F.h[par] * A[k * W1 + lx_] + F.h[par + 2] * A[(k - 1) * W1 + lx_] +
-                      F.h[par + 4] * A[(k - 2) * W1 + lx_] + F.g[par] * A[(kGH + k) * W1 + lx_] +
-                      F.g[par + 2] * A[(kGH + k - 1) * W1 + lx_] + F.g[par + 4] * A[(kGH + k - 2) * W1 + lx_];
-    B[lt * W1 + lx_] = acc;
+  // columns: one input column and a run of 4 output pairs per task (the
+  // taps of consecutive pairs overlap, so a run reads 12 taps, not 48)
+  constexpr int kRun = 4;
+  for (int task = threadIdx.x; task < kGW * (kGT / 2 / kRun); task += nt) {
+    const int lx_ = task % kGW, t0p = (task / kGW) * kRun;
+    syn_run<kRun>(A + lx_, A + kGH * W1 + lx_, W1, t0p, F, B + 2 * t0p * W1 + lx_, W1);
   }
   __syncthreads();
   const bool final_level = (m == n);
@@ -511,6 +533,24 @@ __global__ __launch_bounds__(256) void k_fdwt_glob(const ProbDev* P, const Layer
   const int k0 = t.ty * kFT, l0 = t.tx * kFT;
   const int XW = kFW + 1, RW = 2 * kFT + 1;
   const int nt = blockDim.x;
+  // epilogue positions and operands of this thread's outputs (the 512
+  // (row, column) pairs of the column pass, 2 per thread, up to 2 outputs
+  // each), requested before the input window so both latencies overlap
+  int epos[4];
+  EpiLoad el[4];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = threadIdx.x + u * nt;
+    const int lk = e / (2 * kFT), lc = e - lk * (2 * kFT);
+    const int row = k0 + lk;
+    const int xd = lc >= kFT;
+    const int col = l0 + lc - xd * kFT;
+    epos[2 * u] = xd ? off + row * n + (half + col) : -1;  // the a output is a detail only right of the coarse block
+    epos[2 * u + 1] = off + (half + row) * n + (xd * half + col);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (epos[k] >= 0) el[k] = epi_fetch(pr, io, epi, iter, epos[k]);
   for (int e0 = threadIdx.x; e0 < kFW * kFW; e0 += kUG * nt) {
     float v[kUG];
 #pragma unroll
@@ -548,9 +588,7 @@ __global__ __launch_bounds__(256) void k_fdwt_glob(const ProbDev* P, const Layer
   const int j = t.level - 1;  // detail blocks of this level have side half = 2^j
   // 512 (row, column) pairs of the column pass, 2 per thread; each yields up to 2 outputs
   {
-    int epos[4];
     float eval[4];
-    EpiLoad el[4];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int e = threadIdx.x + u * nt;
@@ -565,19 +603,12 @@ __global__ __launch_bounds__(256) void k_fdwt_glob(const ProbDev* P, const Layer
       const int row = k0 + lk;
       const int xd = lc >= kFT;
       const int col = l0 + lc - xd * kFT;
-      if (!xd) {
+      if (!xd)
         llout[row * half + col] = a;  // coarse block for the next level
-        epos[2 * u] = -1;
-      } else {
-        epos[2 * u] = off + row * n + (half + col);
+      else
         eval[2 * u] = a * ly.inv_delta;
-      }
-      epos[2 * u + 1] = off + (half + row) * n + (xd * half + col);
       eval[2 * u + 1] = d * ly.inv_delta;
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (epos[k] >= 0) el[k] = epi_fetch(pr, io, epi, iter, epos[k]);
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       if (epos[k] >= 0) epi_finish(pr, ly, io, epi, epos[k], j, eval[k], el[k], acc);
