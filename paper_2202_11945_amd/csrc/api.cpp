@@ -556,7 +556,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
             err = "more than 63 sensors meet one propagation-adjoint tile";
             return FEWHA_EINVAL;
           }
-          t_pt.push_back({k, l, ty, tx, li.first, li.second, 0, 0});
+          t_pt.push_back({k, l, ty, tx, li.first, li.second, n, P.hL[pd.layer0 + l].off});
         }
       const int nt = cdiv(n, kTileN);
       for (int ty = 0; ty < nt; ++ty)
@@ -713,7 +713,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
             err = "more than 63 fitting directions";
             return FEWHA_EINVAL;
           }
-          t_fpt.push_back({fl.pD, q, ty, tx, li.first, li.second, 0, 0});
+          t_fpt.push_back({fl.pD, q, ty, tx, li.first, li.second, na, P.hL[dm_layer0 + q].off});
         }
     }
     t_fcg.push_back({(int)hF.size(), 0, 0, 0, 0, 0, 0, 0});

@@ -220,6 +220,9 @@ struct IoDev {
 // row/column, and the slot of the partial it produces.  For the propagation
 // adjoint, mask has bit g set when sensor g's footprint can reach the tile
 // (all bits when the problem has more than 32 sensors).
+// Work item of a tiled launch.  Propagation-adjoint tiles use slot / level
+// for their sensor list (offset, count) and mask / pad1 for the layer's side
+// and offset.
 struct Tile {
   int prob, item, ty, tx;
   int slot, level, mask, pad1;

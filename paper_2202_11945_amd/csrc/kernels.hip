@@ -1365,8 +1365,7 @@ __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD
   typedef const int __attribute__((address_space(1)))* gptr_i;
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
-  const LayerDev& ly = LD[pr.layer0 + t.item];
-  const int n = ly.n;
+  const int n = t.mask, loff = t.pad1;  // the layer's side and offset, carried by the tile
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int ne = t.level;  // sensors in the tile's list (<= 63; the pad entry follows)
@@ -1429,7 +1428,7 @@ __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD
 #pragma unroll
   for (int u = 0; u < RPT; ++u) {
     const int p = p0 + u;
-    if (p < n) dst[ly.off + p * n + q] = acc[u];
+    if (p < n) dst[loff + p * n + q] = acc[u];
   }
 }
 
