@@ -530,10 +530,10 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     for (int g = 0; g < G; ++g) {
       const WfsDev& wd = P.hW[pd.wfs0 + g];
       for (int ty = 0; ty < wd.tiles_side; ++ty)
-        for (int tx = 0; tx < wd.tiles_side; ++tx) t_pg.push_back({k, g, ty, tx, 0, 0, 0, 0});
+        for (int tx = 0; tx < wd.tiles_side; ++tx) t_pg.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
       const int tc = cdiv(wd.nc, kTileS);
       for (int ty = 0; ty < tc; ++ty)
-        for (int tx = 0; tx < tc; ++tx) t_gt.push_back({k, g, ty, tx, 0, 0, 0, 0});
+        for (int tx = 0; tx < tc; ++tx) t_gt.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
     }
     // node tiles of the propagation adjoint (kPtH rows x kPtW columns) with the
     // sensors whose footprint (corners t0 + k rho, k < nc, widened by one node

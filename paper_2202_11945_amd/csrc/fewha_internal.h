@@ -222,7 +222,9 @@ struct IoDev {
 // (all bits when the problem has more than 32 sensors).
 // Work item of a tiled launch.  Propagation-adjoint tiles use slot / level
 // for their sensor list (offset, count) and mask / pad1 for the layer's side
-// and offset.
+// and offset; the sensor-stage tiles carry the sensor's descriptor index in
+// slot and the problem's first layer descriptor in mask (so that those loads
+// need not wait for the problem's descriptor).
 struct Tile {
   int prob, item, ty, tx;
   int slot, level, mask, pad1;

@@ -873,7 +873,7 @@ __global__ __launch_bounds__(kSensThreads) void k_pgamma(const ProbDev* P, const
   __shared__ float sh[4 * (kSensThreads / 64)];
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
-  const WfsDev& w = WD[pr.wfs0 + t.item];
+  const WfsDev& w = WD[t.slot];
   const IoDev& io = IO[t.prob];
   const float* phi = (mode == PG_DENSE) ? pr.phi : io.in;
   const int N = w.N, nc = w.nc;
@@ -917,7 +917,7 @@ __global__ __launch_bounds__(kSensThreads) void k_pgamma(const ProbDev* P, const
           wy[k] = wx[k] = 0.f;
           const int l = l0 + k;
           if (l < pr.L) {
-            const LayerDev& ly = LD[pr.layer0 + l];
+            const LayerDev& ly = LD[t.mask + l];
             const int tb = l * w.tab_stride;
             cell[k] = ly.off + it[tb + ic] * ly.n + it[tb + nc + jc];
             wy[k] = ft[tb + 2 * nc + ic];
@@ -929,7 +929,7 @@ __global__ __launch_bounds__(kSensThreads) void k_pgamma(const ProbDev* P, const
         for (int k = 0; k < 4; ++k) {
           nd[k][0] = nd[k][1] = nd[k][2] = nd[k][3] = 0.f;
           if (l0 + k < pr.L) {
-            const int n = LD[pr.layer0 + l0 + k].n;
+            const int n = LD[t.mask + l0 + k].n;
             const gptr_f ph = (gptr_f)(phi + cell[k]);
             nd[k][0] = ph[0];
             nd[k][1] = ph[1];
@@ -993,7 +993,7 @@ __global__ __launch_bounds__(256) void k_slopes_in(const ProbDev* P, const WfsDe
   __shared__ float sh[16];
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
-  const WfsDev& w = WD[pr.wfs0 + t.item];
+  const WfsDev& w = WD[t.slot];
   const IoDev& io = IO[t.prob];
   const int N = w.N;
   const int i = t.ty * kTileS + (threadIdx.x >> 4), j = t.tx * kTileS + (threadIdx.x & 15);
@@ -1040,7 +1040,7 @@ __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* 
   typedef const int __attribute__((address_space(1)))* gptr_i;
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
-  const WfsDev& w = WD[pr.wfs0 + t.item];
+  const WfsDev& w = WD[t.slot];
   const int N = w.N, nc = w.nc;
   const bool weighted = mode == GT_WEIGHTED;
   const int ci0 = t.ty * kTileS, cj0 = t.tx * kTileS;
