@@ -63,6 +63,33 @@ def test_vlt_like_geometry(gpu_lib):
     _check_frame(gpu_lib, S, ctx, np.zeros(5 * S.geom.n_coeff, np.float32), synth_slopes(S, 0))
 
 
+def _many_ngs(n):
+    """The 8 m two-layer system with n NGS on three rings, alternately 2x2
+    (3x3 corners) and 4x4 subapertures: every sensor meets every
+    propagation-adjoint tile, so a tile's sensor list holds all n."""
+    import math
+    from synthetic.configs import ARCSEC, _ngs
+    cfg = get_config("tiny")
+    cfg["wfs"] = []
+    for k in range(n):
+        r, az = (10.0 + 15.0 * (k % 3)) * ARCSEC, 2.0 * math.pi * k / n
+        cfg["wfs"].append(_ngs((r * math.cos(az), r * math.sin(az)), 2 if k % 2 == 0 else 4, 0.1))
+    return cfg
+
+
+def test_forty_sensors_per_tile(gpu_lib):
+    cfg = _many_ngs(40)
+    S = system("many_ngs_40", cfg)
+    ctx = _ops(gpu_lib, S, cfg, 5)
+    _check_frame(gpu_lib, S, ctx, np.zeros(5 * S.geom.n_coeff, np.float32), synth_slopes(S, 0))
+
+
+def test_more_than_63_sensors_per_tile_is_refused(gpu_lib):
+    with pytest.raises(gpu_lib.FewhaError) as e:
+        gpu_lib.Context(_many_ngs(70), device=0)
+    assert e.value.status == -1
+
+
 def test_large_nine_layers_with_elongation(gpu_lib):
     # the frame with F = I (the fitted frame of this system is covered with the fitting tests)
     cfg = get_config("large")
