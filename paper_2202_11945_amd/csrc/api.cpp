@@ -72,6 +72,7 @@ struct Plan {
   std::vector<float*> rbuf;                  // per problem: residual of a refined solve
   GradIo* dGIO = nullptr;
   const HatEnt* dHat = nullptr;              // hat tables of the propagation adjoint
+  int nHat = 0;                              // entries of dHat
   const BandRec* dBand = nullptr;            // band records of the propagation adjoint
   const PtEnt* dPtE = nullptr;               // sensor lists of the propagation-adjoint tiles
   std::vector<float*> sstate;                // per problem: [x | unused | r] of a solve
@@ -192,31 +193,34 @@ void set_hats(GLPar& gp, int n, HatTables& T) {
       fits = false;
       break;
     }
-    // first band row: the group's first corner (a grid of fewer than SB rows
-    // starts at 0); rows past the grid repeat its last row, never weighted
-    const int base = gp.nc >= SB ? ilo : 0;
+    const int cnt = std::min(kBandRows, n - p);  // node rows of the group inside the layer
     BandRec r{};
-    for (int s = 0; s < kBandMax; ++s)
-      r.so[s] = std::min(base + std::min(s, SB - 1), gp.nc - 1) * gp.nc * (int)sizeof(float);
-    r.pat = -1;
-    if (K == 2 && base == ilo) {
-      int pat = 0;
-      for (int u = 1; u < kBandRows && pat >= 0; ++u) {
-        const int step = rows[std::min(p + u, n - 1)].lo - rows[std::min(p + u - 1, n - 1)].lo;
-        if (step == 1)
-          pat |= 1 << (u - 1);
-        else if (step != 0)
-          pat = -1;
-      }
-      r.pat = pat;
+    bool zero = true;
+    for (int u = 0; u < cnt; ++u)
+      for (int k = 0; k < K; ++k) zero = zero && rows[p + u].w[k] == 0.f;
+    // step pattern: every node row inside the layer, steps of K - 2 or K - 1
+    int pat = cnt == kBandRows ? 0 : -1;
+    for (int u = 1; u < kBandRows && pat >= 0; ++u) {
+      const int step = rows[p + u].lo - rows[p + u - 1].lo - (K - 2);
+      if (step == 1)
+        pat |= 1 << (u - 1);
+      else if (step != 0)
+        pat = -1;
     }
-    for (int u = 0; u < kBandRows && p + u < n; ++u)
+    // first band row: the group's first corner, or (dense records) moved up
+    // so that the band stays inside the grid where it can
+    const int base = pat >= 0 ? ilo : std::max(0, std::min(ilo, gp.nc - SB));
+    r.so0 = base * gp.nc * (int)sizeof(float);
+    r.pat = zero ? kPatZero : (pat >= 0 ? pat : kPatDense);
+    r.nrows = std::min(SB, gp.nc - base);
+    for (int u = 0; u < cnt; ++u)
       for (int k = 0; k < K; ++k) {
         const int s = rows[p + u].lo + k - base;
-        if (s < 0 || s >= SB || rows[p + u].lo + k > gp.nc - 1) {
+        if (s < 0 || s >= r.nrows) {
           fits = false;
           break;
         }
+        r.wk[u][k] = rows[p + u].w[k];
         r.w[u][s] = rows[p + u].w[k];
       }
     recs.push_back(r);
@@ -230,6 +234,29 @@ void set_hats(GLPar& gp, int n, HatTables& T) {
     T.bands.insert(T.bands.end(), recs.begin(), recs.end());
   }
   T.seen[key] = {gp.kmax, gp.hat_off, gp.band_off};
+}
+
+// Does (sensor, layer) pair gp add anything to the node tile of rows p0 ..
+// p0 + ph - 1 and columns q0 .. q0 + qw - 1 of an n x n layer?  With hat
+// tables: some row and some column of the tile have a nonzero hat (the
+// gather is separable, so the tile's sum is zero otherwise; a sparse sensor,
+// whose corners lie more than two node spacings apart, touches few node rows
+// and columns inside its footprint).  Without (general gather): the tile
+// meets the footprint, the corners t0 + k rho widened by two nodes.
+bool pair_meets_tile(const GLPar& gp, const HatTables& T, int n, int p0, int ph, int q0, int qw) {
+  if (gp.kmax == 0) {
+    const double span = (gp.nc - 1) * gp.rho;
+    auto meets = [&](double t0, int a, int ext) { return a + ext - 1 >= t0 - 2.0 && a <= t0 + span + 2.0; };
+    return meets(gp.t0y, p0, ph) && meets(gp.t0x, q0, qw);
+  }
+  auto any = [&](int first, int a, int ext) {
+    for (int p = a; p < std::min(a + ext, n); ++p) {
+      const HatEnt& e = T.hats[(size_t)first + p];
+      if (e.w[0] != 0.f || e.w[1] != 0.f || e.w[2] != 0.f) return true;
+    }
+    return false;
+  };
+  return any(gp.hat_off, p0, ph) && any(gp.hat_off + n, q0, qw);
 }
 
 // Sensor lists of propagation-adjoint tiles, one copy per distinct list.
@@ -536,21 +563,15 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
         for (int tx = 0; tx < tc; ++tx) t_gt.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
     }
     // node tiles of the propagation adjoint (kPtH rows x kPtW columns) with the
-    // sensors whose footprint (corners t0 + k rho, k < nc, widened by one node
-    // and a margin) meets them; 32x32 tiles for the FP64 residual's adjoint
+    // sensors that add to them; 32x32 tiles for the FP64 residual's adjoint
     for (int l = 0; l < L; ++l) {
       const int n = P.hL[pd.layer0 + l].n;
       for (int ty = 0; ty < cdiv(n, kPtH); ++ty)
         for (int tx = 0; tx < cdiv(n, kPtW); ++tx) {
           std::vector<int> use;
-          for (int g = 0; g < G; ++g) {
-            const GLPar& gp = glp[k][(size_t)g * L + l];
-            const double span = (gp.nc - 1) * gp.rho;
-            auto meets = [&](double t0, int p0, int ext) {
-              return p0 + ext - 1 >= t0 - 2.0 && p0 <= t0 + span + 2.0;
-            };
-            if (meets(gp.t0y, ty * kPtH, kPtH) && meets(gp.t0x, tx * kPtW, kPtW)) use.push_back(g);
-          }
+          for (int g = 0; g < G; ++g)
+            if (pair_meets_tile(glp[k][(size_t)g * L + l], hats, n, ty * kPtH, kPtH, tx * kPtW, kPtW))
+              use.push_back(g);
           const auto li = ptl.add(glp[k], L, l, use, n, ty, tx, pt_rows);
           if (li.first < 0) {
             err = "more than 63 sensors meet one propagation-adjoint tile";
@@ -702,13 +723,15 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
           t_ffL.push_back({fl.pL, d, ty, tx, 0, 0, 0, 0});
           t_ffD.push_back({fl.pD, d, ty, tx, 0, 0, 0, 0});
         }
-    std::vector<int> alld(K);
-    for (int d = 0; d < K; ++d) alld[d] = d;
     for (int q = 0; q < nd; ++q) {
       const int na = f.dms[q].n_act;
       for (int ty = 0; ty < cdiv(na, kPtH); ++ty)
-        for (int tx = 0; tx < cdiv(na, kPtW); ++tx) {  // all directions
-          const auto li = ptl.add(fl.glp, nd, q, alld, na, ty, tx, pt_rows);
+        for (int tx = 0; tx < cdiv(na, kPtW); ++tx) {  // the directions that add to the tile
+          std::vector<int> use;
+          for (int d = 0; d < K; ++d)
+            if (pair_meets_tile(fl.glp[(size_t)d * nd + q], hats, na, ty * kPtH, kPtH, tx * kPtW, kPtW))
+              use.push_back(d);
+          const auto li = ptl.add(fl.glp, nd, q, use, na, ty, tx, pt_rows);
           if (li.first < 0) {
             err = "more than 63 fitting directions";
             return FEWHA_EINVAL;
@@ -868,6 +891,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   P.dIOprof = (IoDev*)(base + oIOp);
   P.dGIO = (GradIo*)(base + oGIO);
   P.dHat = (const HatEnt*)(base + oHat);
+  P.nHat = (int)hats.hats.size();
   P.dBand = (const BandRec*)(base + oBand);
   if (!hats.hats.empty())
     HIP_TRY(hipMemcpy(base + oHat, hats.hats.data(), sizeof(HatEnt) * hats.hats.size(), hipMemcpyHostToDevice));
@@ -953,6 +977,7 @@ LaunchArgs args(const Plan& P, hipStream_t s, const IoDev* io) {
   a.res_max = P.res_max;
   a.pt_rows = P.pt_rows;
   a.hats = P.dHat;
+  a.n_hats = P.nHat;
   a.bands = P.dBand;
   a.pents = P.dPtE;
   return a;

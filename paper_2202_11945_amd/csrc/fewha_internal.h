@@ -109,21 +109,29 @@ struct HatEnt {
   int lo;
   float w[3];
 };
+static_assert(sizeof(HatEnt) == 16, "one 16-byte load per lane");
 
 // Separable propagation adjoint of kBandRows consecutive node rows and one
-// (sensor, layer) pair: the corner rows of the band (byte offsets in the
-// sensor's corner grid, clamped to the grid, so extra rows repeat a valid
-// row) and, per node row, the y hat weight of every band row (0 off the hat).
-// pat (K = 2, band starting at the group's first corner): bit u - 1 is the
-// step of the first corner from node row u - 1 to u (0 or 1); -1 = no such
-// pattern (dense sums).
+// (sensor, layer) pair.  The band is a run of consecutive corner rows of the
+// sensor's grid starting at row base (so0 = base nc 4, its byte offset).
+// pat says how the first corners of the node rows step:
+//   0 .. 7    : a step pattern.  base is the first node row's first corner;
+//               bit u - 1 of pat is the step from node row u - 1 to u less
+//               its least value (K = 2: steps 0 or 1, K = 3: 1 or 2), so node
+//               row u reads the K band rows from d_u = sum of the steps, with
+//               the weights wk[u][0 .. K - 1] (its y hat).
+//   kPatZero  : every weight is zero (the rows lie outside the sensor's reach).
+//   kPatDense : any other steps (grid edges, a short last group); band rows
+//               base .. base + nrows - 1, all inside the grid, and node row u
+//               weights band row s by w[u][s].
+constexpr int kPatZero = 8, kPatDense = 9;
 struct BandRec {
-  int so[kBandMax];
+  int so0, pat, nrows, pad_;
+  float wk[kBandRows][3];
   float w[kBandRows][kBandMax];
-  int pat;
-  int pad_[2];
+  int pad2_[12];
 };
-static_assert(sizeof(BandRec) == 192, "band record: 48 dwords");
+static_assert(sizeof(BandRec) == 256, "band record: 64 dwords");
 
 // One sensor of a propagation-adjoint tile's list (the sensors whose
 // footprint meets the tile, in sensor order), all a wave needs for it:

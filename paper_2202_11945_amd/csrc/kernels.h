@@ -33,6 +33,7 @@ struct LaunchArgs {
   hipStream_t stream;
   int res_max;  // largest resident transform side of the plan (32, 64 or 128)
   const HatEnt* hats;     // hat tables of the propagation adjoint (plan-wide)
+  int n_hats;             // entries of hats
   const BandRec* bands;   // band records of the propagation adjoint (plan-wide)
   const PtEnt* pents;     // sensor lists of the propagation-adjoint tiles (plan-wide)
   int pt_rows;         // node rows per thread of the propagation adjoint (4 or 8)

@@ -1192,60 +1192,85 @@ __device__ __forceinline__ GLPar load_glpar(const GLPar* p) {
   return g;
 }
 
-// One entry of a tile's sensor list, by scalar loads.
-__device__ __forceinline__ PtEnt load_ent(const PtEnt* p) {
-  typedef const __attribute__((address_space(4))) int* cint;
-  const cint i = (cint)p;
-  return PtEnt{i[0], i[1], i[2], i[3]};
-}
-
-// Band-row byte offsets of one band record (scalar loads).
-struct BandRows {
-  int so[kBandMax];
+// Head of a band record (scalar loads): first band row, pattern, dense rows.
+struct BandHdr {
+  int so0, pat, nrows;
 };
-__device__ __forceinline__ BandRows load_rows(const BandRec* rec) {
+__device__ __forceinline__ BandHdr load_hdr(const BandRec* rec) {
   typedef const __attribute__((address_space(4))) int* cint;
   const cint p = (cint)rec;
-  BandRows r;
-#pragma unroll
-  for (int s = 0; s < kBandMax; ++s) r.so[s] = p[s];
-  return r;
+  return BandHdr{p[0], p[1], p[2]};
 }
 
-// Loads of one band: every band row once, K corners per lane (raw buffer
-// loads: lane offset vo from the column hat, row offset from the record).
-// The row offsets are wave-uniform; readfirstlane states it where register
-// pressure left them in vector registers (else each load became a loop).
+// One band row, K corners per lane: raw buffer loads with the lane's column
+// offset vo (from the column hat) and the wave-uniform row offset off.
 template <int K>
-__device__ __forceinline__ void pt_band_load(__amdgpu_buffer_rsrc_t rs, int vo, const BandRows& so,
-                                             float v[pt_band(K, kBandRows)][K]) {
+__device__ __forceinline__ void pt_row(__amdgpu_buffer_rsrc_t rs, int vo, int off, float v[K]) {
 #pragma unroll
-  for (int s = 0; s < pt_band(K, kBandRows); ++s) {
-    const int off = __builtin_amdgcn_readfirstlane(so.so[s]);
+  for (int b = 0; b < K; ++b)
+    v[b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo + b * (int)sizeof(float), off, 0));
+}
+
+// One band record with step pattern PAT: the band rows that its node rows
+// read (d_3 + K of them), each interpolated along x with the column hat; node
+// row u takes its K y taps from band row d_u on.
+template <int K, int PAT>
+__device__ __forceinline__ void pt_pattern(__amdgpu_buffer_rsrc_t rs, int vo, int so0, int rowb, const BandRec* rec,
+                                           const HatEnt& hx, float acc[kBandRows]) {
+  typedef const __attribute__((address_space(4))) BandRec* crec;
+  constexpr int s0 = K == 3 ? 1 : 0;  // least step
+  constexpr int d1 = s0 + (PAT & 1), d2 = d1 + s0 + ((PAT >> 1) & 1), d3 = d2 + s0 + ((PAT >> 2) & 1);
+  constexpr int NB = d3 + K;
+  static_assert(NB <= pt_band(K, kBandRows), "pattern inside the band");
+  float v[NB][K];
 #pragma unroll
-    for (int b = 0; b < K; ++b)
-      v[s][b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo + b * (int)sizeof(float), off, 0));
+  for (int s = 0; s < NB; ++s) pt_row<K>(rs, vo, so0 + s * rowb, v[s]);
+  float r[NB];
+#pragma unroll
+  for (int s = 0; s < NB; ++s) {
+    float t = hx.w[0] * v[s][0];
+#pragma unroll
+    for (int b = 1; b < K; ++b) t = fmaf(hx.w[b], v[s][b], t);
+    r[s] = t;
+  }
+  const crec br = (crec)rec;
+  constexpr int d[kBandRows] = {0, d1, d2, d3};
+#pragma unroll
+  for (int u = 0; u < kBandRows; ++u) {
+    float t = br->wk[u][0] * r[d[u]];
+#pragma unroll
+    for (int k = 1; k < K; ++k) t = fmaf(br->wk[u][k], r[d[u] + k], t);
+    acc[u] += t;
   }
 }
 
-// Separable sums of kBandRows node rows: each band row interpolated along x
-// with the column hat, then node row u takes sum_s w[u][s] r[s] with the
-// record's y weights as scalar operands.  The record's zero weights add exact
-// zeros, so each sum equals the K-term sum over the node's hat.
+// A band record without a step pattern: its nrows band rows (the rest of the
+// band lies past the grid and has zero weights), then dense sums with the
+// record's y weights as scalar operands.
 template <int K>
-__device__ __forceinline__ void pt_band_sum(const BandRec* rec, const HatEnt& hx,
-                                            const float v[pt_band(K, kBandRows)][K], float acc[kBandRows]) {
-  constexpr int SB = pt_band(K, kBandRows);
+__device__ __forceinline__ void pt_dense(__amdgpu_buffer_rsrc_t rs, int vo, const BandHdr& h, int rowb,
+                                         const BandRec* rec, const HatEnt& hx, float acc[kBandRows]) {
   typedef const __attribute__((address_space(4))) BandRec* crec;
-  const crec br = (crec)rec;
+  constexpr int SB = pt_band(K, kBandRows);
+  float v[SB][K];
+#pragma unroll
+  for (int s = 0; s < SB; ++s) {
+    if (s < h.nrows) {
+      pt_row<K>(rs, vo, h.so0 + s * rowb, v[s]);
+    } else {
+#pragma unroll
+      for (int b = 0; b < K; ++b) v[s][b] = 0.f;
+    }
+  }
   float r[SB];
 #pragma unroll
   for (int s = 0; s < SB; ++s) {
-    float t = 0.f;
+    float t = hx.w[0] * v[s][0];
 #pragma unroll
-    for (int b = 0; b < K; ++b) t = fmaf(hx.w[b], v[s][b], t);
+    for (int b = 1; b < K; ++b) t = fmaf(hx.w[b], v[s][b], t);
     r[s] = t;
   }
+  const crec br = (crec)rec;
 #pragma unroll
   for (int u = 0; u < kBandRows; ++u) {
     float t = 0.f;
@@ -1255,97 +1280,38 @@ __device__ __forceinline__ void pt_band_sum(const BandRec* rec, const HatEnt& hx
   }
 }
 
-// A sensor of 3 x 3 corners (2 x 2 subapertures, K = 2): the whole corner
-// grid in scalar registers, each lane picks its two taps per corner row by
-// selects, no vector memory traffic beyond the column hat.  The band record
-// of such a grid starts at corner row 0 and weights only rows 0..2.
-__device__ __forceinline__ void pt_tiny3(const float* vsens, const BandRec* rec, const HatEnt& hx,
-                                         float acc[kBandRows]) {
-  typedef const __attribute__((address_space(4))) float* cflt;
-  typedef const __attribute__((address_space(4))) BandRec* crec;
-  const cflt gv = (cflt)vsens;
-  const crec br = (crec)rec;
-  float V[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) V[i][j] = gv[3 * i + j];
-  const bool lo0 = hx.lo == 0;  // first corner 0 or 1 (clamped to nc - K)
-  float r[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const float a = lo0 ? V[i][0] : V[i][1];
-    const float b = lo0 ? V[i][1] : V[i][2];
-    r[i] = fmaf(hx.w[1], b, fmaf(hx.w[0], a, 0.f));
-  }
-#pragma unroll
-  for (int u = 0; u < kBandRows; ++u) {
-    float t = 0.f;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) t = fmaf(br->w[u][i], r[i], t);
-    acc[u] += t;
+// One band record of one sensor, by its pattern; a record of zero weights
+// issues nothing.
+template <int K>
+__device__ __forceinline__ void pt_record(__amdgpu_buffer_rsrc_t rs, int vo, int rowb, const BandHdr& h,
+                                          const BandRec* rec, const HatEnt& hx, float acc[kBandRows]) {
+  switch (h.pat) {
+    case 0: pt_pattern<K, 0>(rs, vo, h.so0, rowb, rec, hx, acc); break;
+    case 1: pt_pattern<K, 1>(rs, vo, h.so0, rowb, rec, hx, acc); break;
+    case 2: pt_pattern<K, 2>(rs, vo, h.so0, rowb, rec, hx, acc); break;
+    case 3: pt_pattern<K, 3>(rs, vo, h.so0, rowb, rec, hx, acc); break;
+    case 4: pt_pattern<K, 4>(rs, vo, h.so0, rowb, rec, hx, acc); break;
+    case 5: pt_pattern<K, 5>(rs, vo, h.so0, rowb, rec, hx, acc); break;
+    case 6: pt_pattern<K, 6>(rs, vo, h.so0, rowb, rec, hx, acc); break;
+    case 7: pt_pattern<K, 7>(rs, vo, h.so0, rowb, rec, hx, acc); break;
+    case kPatZero: break;
+    default: pt_dense<K>(rs, vo, h, rowb, rec, hx, acc); break;
   }
 }
 
-// K = 2 sums for a band record with step pattern (D1, D2 - D1, D3 - D2)
-// (first corners of node rows 1..3 at band rows D1, D2, D3; row 0 at 0): the
-// band rows 0 .. D3 + 1 interpolated along x, then 2 y taps per node row.
-// Same products and order as the dense sums without their zero terms.
-template <int D1, int D2, int D3>
-__device__ __forceinline__ void pt_sum2(const BandRec* rec, const HatEnt& hx, const float v[pt_band(2, kBandRows)][2],
-                                        float acc[kBandRows]) {
-  typedef const __attribute__((address_space(4))) BandRec* crec;
-  const crec br = (crec)rec;
-  constexpr int NB = D3 + 2;
-  float r[NB];
-#pragma unroll
-  for (int s = 0; s < NB; ++s) r[s] = fmaf(hx.w[1], v[s][1], fmaf(hx.w[0], v[s][0], 0.f));
-  constexpr int d[kBandRows] = {0, D1, D2, D3};
-#pragma unroll
-  for (int u = 0; u < kBandRows; ++u)
-    acc[u] += fmaf(br->w[u][d[u] + 1], r[d[u] + 1], fmaf(br->w[u][d[u]], r[d[u]], 0.f));
-}
-__device__ __forceinline__ void pt_sum2_pat(int pat, const BandRec* rec, const HatEnt& hx,
-                                            const float v[pt_band(2, kBandRows)][2], float acc[kBandRows]) {
-  switch (pat) {
-    case 0: pt_sum2<0, 0, 0>(rec, hx, v, acc); break;
-    case 1: pt_sum2<1, 1, 1>(rec, hx, v, acc); break;
-    case 2: pt_sum2<0, 1, 1>(rec, hx, v, acc); break;
-    case 3: pt_sum2<1, 2, 2>(rec, hx, v, acc); break;
-    case 4: pt_sum2<0, 0, 1>(rec, hx, v, acc); break;
-    case 5: pt_sum2<1, 1, 2>(rec, hx, v, acc); break;
-    case 6: pt_sum2<0, 1, 2>(rec, hx, v, acc); break;
-    case 7: pt_sum2<1, 2, 3>(rec, hx, v, acc); break;
-    default: pt_band_sum<2>(rec, hx, v, acc); break;
-  }
-}
-
-// One sensor of the fast path: its first band's loads go out before the
-// prefetches of the next sensor (`pre`), so that waiting for the band does
-// not wait for them; then the sums; a second record (RPT = 8) follows.
-template <int K, int RPT, class Pre>
-__device__ __forceinline__ void pt_sensor(const float* vsens, int nc, const BandRec* rec, const BandRows& so,
-                                          const HatEnt& hx, int ngrp, float acc[RPT], Pre pre) {
-  constexpr int SB = pt_band(K, kBandRows);
-  typedef const __attribute__((address_space(4))) int* cint;
+// One sensor of the fast path: a wave's one or two (RPT = 8) band records.
+template <int K, int RPT>
+__device__ __forceinline__ void pt_sensor(const float* vsens, int nc, const BandRec* rec, const BandHdr& h,
+                                          const HatEnt& hx, int ngrp, float acc[RPT]) {
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc((void*)vsens, (short)0, nc * nc * (int)sizeof(float), 0x00020000);
   const int vo = hx.lo * (int)sizeof(float);
-  float v[SB][K];
-  pt_band_load<K>(rs, vo, so, v);
-  pre();
-  if (K == 2)
-    pt_sum2_pat(*(cint)&rec->pat, rec, hx, (const float(*)[2])v, acc);
-  else
-    pt_band_sum<K>(rec, hx, v, acc);
+  const int rowb = nc * (int)sizeof(float);
+  pt_record<K>(rs, vo, rowb, h, rec, hx, acc);
 #pragma unroll
   for (int j = 1; j < RPT / kBandRows; ++j) {
     if (j >= ngrp) break;
-    pt_band_load<K>(rs, vo, load_rows(rec + j), v);
-    if (K == 2)
-      pt_sum2_pat(*(cint)&rec[j].pat, rec + j, hx, (const float(*)[2])v, acc + j * kBandRows);
-    else
-      pt_band_sum<K>(rec + j, hx, v, acc + j * kBandRows);
+    pt_record<K>(rs, vo, rowb, load_hdr(rec + j), rec + j, hx, acc + j * kBandRows);
   }
 }
 
@@ -1354,11 +1320,11 @@ __device__ __forceinline__ void pt_sensor(const float* vsens, int nc, const Band
 // list (the sensors whose footprint meets it, at most 63, built on the host,
 // then a pad entry) is loaded once, entry i in lane i, and read back with
 // readlane.  The sensor loop is software-pipelined: the column hat and
-// band-row offsets of the next sensor are requested, unconditionally, before
-// the current sensor's band.
+// band-record head of the next sensor are requested, unconditionally, before
+// the current sensor's loads.
 template <int RPT>
 __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD, const WfsDev* WD, const IoDev* IO,
-                                            const Tile* tiles, const HatEnt* __restrict__ hats,
+                                            const Tile* tiles, const HatEnt* __restrict__ hats, int n_hats,
                                             const BandRec* __restrict__ bands, const PtEnt* __restrict__ ents,
                                             int mode) {
   static_assert(RPT % kBandRows == 0, "whole band records per wave");
@@ -1390,38 +1356,37 @@ __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD
   float acc[RPT];
 #pragma unroll
   for (int u = 0; u < RPT; ++u) acc[u] = 0.f;
-  auto fetch = [&](const PtEnt& e, HatEnt& hx, BandRows& so) {  // valid for every entry (see PtEnt)
-    hx = hats[e.hx + lane];
-    so = load_rows(bands + e.band + wrec);
+  // column hats by buffer loads: lane offset fixed, entry offset wave-uniform
+  const __amdgpu_buffer_rsrc_t hrs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)hats, (short)0, n_hats * (int)sizeof(HatEnt), 0x00020000);
+  const int hlane = lane * (int)sizeof(HatEnt);
+  auto fetch = [&](const PtEnt& e, HatEnt& hx, BandHdr& hd) {  // valid for every entry (see PtEnt)
+    const auto h = __builtin_amdgcn_raw_buffer_load_b128(hrs, hlane, e.hx * (int)sizeof(HatEnt), 0);
+    hx.lo = (int)h[0];
+    hx.w[0] = __uint_as_float(h[1]);
+    hx.w[1] = __uint_as_float(h[2]);
+    hx.w[2] = __uint_as_float(h[3]);
+    hd = load_hdr(bands + e.band + wrec);
   };
-  // one sensor: its band, the next sensor's prefetch (`pre`), the sums
-  auto sensor = [&](const PtEnt& cur, const HatEnt& hx, const BandRows& so, auto pre) {
+  auto sensor = [&](const PtEnt& cur, const HatEnt& hx, const BandHdr& hd) {
     const int K = cur.nck & 3, nc = cur.nck >> 2;
     const float* vs = pr.vadj + cur.v_off;
     const BandRec* rec = bands + cur.band + wrec;
-    if (K == 0) {
-      pre();
+    if (K == 0)
       pt_general<RPT>(load_glpar(pr.gl + (cur.nck >> 2)), pr.vadj, q, p0, n, acc);
-    } else if (nc == 3 && K == 2) {  // 3 x 3 corner grid
-      pre();
-#pragma unroll
-      for (int j = 0; j < RPT / kBandRows; ++j) {
-        if (j >= ngrp) break;
-        pt_tiny3(vs, rec + j, hx, acc + j * kBandRows);
-      }
-    } else if (K == 2) {
-      pt_sensor<2, RPT>(vs, nc, rec, so, hx, ngrp, acc, pre);
-    } else {
-      pt_sensor<3, RPT>(vs, nc, rec, so, hx, ngrp, acc, pre);
-    }
+    else if (K == 2)
+      pt_sensor<2, RPT>(vs, nc, rec, hd, hx, ngrp, acc);
+    else
+      pt_sensor<3, RPT>(vs, nc, rec, hd, hx, ngrp, acc);
   };
   HatEnt hx, hxn;
-  BandRows so, son;
-  fetch(ent(0), hx, so);
+  BandHdr hd, hdn;
+  fetch(ent(0), hx, hd);
   for (int i = 0; i < ne; ++i) {
-    sensor(ent(i), hx, so, [&]() { fetch(ent(i + 1), hxn, son); });
+    fetch(ent(i + 1), hxn, hdn);  // issued first: the waits for this sensor's loads cover it
+    sensor(ent(i), hx, hd);
     hx = hxn;
-    so = son;
+    hd = hdn;
   }
   const IoDev& io = IO[t.prob];
   float* dst = (mode == PT_USER) ? io.out : pr.phiadj;
@@ -1754,9 +1719,9 @@ void launch_gammaT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode)
 void launch_pT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
   if (ntiles <= 0) return;
   if (a.pt_rows == 8)
-    k_pT<8><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.bands, a.pents, mode);
+    k_pT<8><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.n_hats, a.bands, a.pents, mode);
   else
-    k_pT<4><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.bands, a.pents, mode);
+    k_pT<4><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.n_hats, a.bands, a.pents, mode);
 }
 void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter) {
   if (ntiles > 0) k_update<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles, iter);
