@@ -231,15 +231,23 @@ constexpr int kUG = 6; // ... for the 36 x 36 windows of the global transform le
 // src[(half + k) S], written to dst[0 ..]; periodic:
 //   x_t = sum_{i = t mod 2} h_i a[(t-i)/2] + g_i d[(t-i)/2]   (indices mod half)
 // Consecutive output pairs share four of their six taps, so the NP + 2 taps
-// of each half are read once into registers.
-template <int NP>
-__device__ __forceinline__ void syn_line(const float* src, int S, int half, int K0, const Filter& F, float* dst) {
+// of each half are read once into registers.  Only the taps K0 - 2 and
+// K0 - 1 can wrap (K0 + NP <= half); the others are read at fixed offsets
+// from the line position (the stride S is a compile-time constant).
+template <int NP, int S>
+__device__ __forceinline__ void syn_line(const float* src, int half, int K0, const Filter& F, float* dst) {
   float a[NP + 2], d[NP + 2];
+  const int i0 = K0 >= 2 ? K0 - 2 : K0 - 2 + half, i1 = K0 >= 1 ? K0 - 1 : K0 - 1 + half;
+  a[0] = src[i0 * S];
+  d[0] = src[(half + i0) * S];
+  a[1] = src[i1 * S];
+  d[1] = src[(half + i1) * S];
+  const float* b = src + K0 * S;
+  const float* bd = b + half * S;
 #pragma unroll
-  for (int i = 0; i < NP + 2; ++i) {
-    const int k = (K0 - 2 + i) & (half - 1);
-    a[i] = src[k * S];
-    d[i] = src[(half + k) * S];
+  for (int i = 0; i < NP; ++i) {
+    a[i + 2] = b[i * S];
+    d[i + 2] = bd[i * S];
   }
 #pragma unroll
   for (int p = 0; p < NP; ++p) {  // a[p + 2] = a[k0], a[p + 1] = a[k0 - 1], a[p] = a[k0 - 2]
@@ -254,7 +262,8 @@ __device__ __forceinline__ void syn_line(const float* src, int S, int half, int 
 // reads src + l (stride S along the line) and writes dst + l S.  Each thread
 // takes np consecutive output pairs of one line (np = m^2 / 2 / threads,
 // at least 1), so neighbouring lanes touch neighbouring LDS words.
-__device__ __forceinline__ void syn_pass(const float* src, float* dst, int S, int m, const Filter& F) {
+template <int S>
+__device__ __forceinline__ void syn_pass(const float* src, float* dst, int m, const Filter& F) {
   const int half = m >> 1, nt = blockDim.x;
   const int np = max(1, m * half / nt), nch = half / np, lm = __builtin_ctz(m);
   for (int task = threadIdx.x; task < m * nch; task += nt) {
@@ -263,13 +272,13 @@ __device__ __forceinline__ void syn_pass(const float* src, float* dst, int S, in
       const int k = K0 + p0, c = min(np - p0, 8);
       float* o = dst + l * S + 2 * k;
       if (c == 8)
-        syn_line<8>(src + l, S, half, k, F, o);
+        syn_line<8, S>(src + l, half, k, F, o);
       else if (c == 4)
-        syn_line<4>(src + l, S, half, k, F, o);
+        syn_line<4, S>(src + l, half, k, F, o);
       else if (c == 2)
-        syn_line<2>(src + l, S, half, k, F, o);
+        syn_line<2, S>(src + l, half, k, F, o);
       else
-        syn_line<1>(src + l, S, half, k, F, o);
+        syn_line<1, S>(src + l, half, k, F, o);
     }
   }
 }
@@ -277,7 +286,8 @@ __device__ __forceinline__ void syn_pass(const float* src, float* dst, int S, in
 // The last synthesis pass (rows) written straight to global memory:
 // g[l gs + t] = scale x_t for line l, each thread its run of 2 np outputs
 // (float4 stores when `vec`: g, gs and the runs 16-byte aligned).
-__device__ __forceinline__ void syn_pass_out(const float* src, int S, int m, const Filter& F, float* g, int gs,
+template <int S>
+__device__ __forceinline__ void syn_pass_out(const float* src, int m, const Filter& F, float* g, int gs,
                                              float scale, bool vec) {
   const int half = m >> 1, nt = blockDim.x;
   const int np = max(1, m * half / nt), nch = half / np, lm = __builtin_ctz(m);
@@ -289,13 +299,13 @@ __device__ __forceinline__ void syn_pass_out(const float* src, int S, int m, con
       const int k = K0 + p0, c = min(np - p0, 8);
       float o[16];
       if (c == 8)
-        syn_line<8>(src + l, S, half, k, F, o);
+        syn_line<8, S>(src + l, half, k, F, o);
       else if (c == 4)
-        syn_line<4>(src + l, S, half, k, F, o);
+        syn_line<4, S>(src + l, half, k, F, o);
       else if (c == 2)
-        syn_line<2>(src + l, S, half, k, F, o);
+        syn_line<2, S>(src + l, half, k, F, o);
       else
-        syn_line<1>(src + l, S, half, k, F, o);
+        syn_line<1, S>(src + l, half, k, F, o);
       float* dst = g + (long)l * gs + 2 * k;
       if (vec && c >= 2) {
 #pragma unroll
@@ -314,7 +324,7 @@ __device__ __forceinline__ void syn_pass_out(const float* src, int S, int m, con
 // One workgroup per (problem, layer): all synthesis levels whose output side
 // is at most the layer's resident side R (<= RMAX, the LDS capacity of the
 // instantiation) run in LDS.  Columns then rows, periodic, Mallat layout.
-// The LDS rows have the odd stride S = R + 1 and the column pass writes its
+// The LDS rows have the odd stride S = RMAX + 1 and the column pass writes its
 // result transposed (Bt[c][t] = x[t][c]), so both passes walk their lines
 // with lanes on consecutive words and strided writes free of bank conflicts.
 template <int RMAX>
@@ -328,7 +338,8 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
   const LayerDev& ly = LD[pr.layer0 + t.item];
   const IoDev& io = IO[t.prob];
   PSrc ps = make_psrc(pr, io, src_mode, iter, 0.f);
-  const int n = ly.n, R = ly.res, lr = __builtin_ctz(R), S = R + 1;
+  const int n = ly.n, R = ly.res, lr = __builtin_ctz(R);
+  constexpr int S = RMAX + 1;
   const int m0 = n >> ly.levels;
   const int off = ly.off;
   const int nt = blockDim.x;
@@ -360,12 +371,12 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
   const int gs = n != R ? R : n;
   const bool vec = (((uintptr_t)gout) & 15) == 0;
   for (int m = 2 * m0; m <= R; m <<= 1) {
-    syn_pass(A, B, S, m, F);  // columns (along y): A[t][c] -> B[c][t]
+    syn_pass<S>(A, B, m, F);  // columns (along y): A[t][c] -> B[c][t]
     __syncthreads();
     if (m == R && direct) {
-      syn_pass_out(B, S, m, F, gout, gs, n != R ? 1.f : ly.inv_delta, vec);
+      syn_pass_out<S>(B, m, F, gout, gs, n != R ? 1.f : ly.inv_delta, vec);
     } else {
-      syn_pass(B, A, S, m, F);  // rows (along x): B[c][r] = row r of the level -> A[r][c]
+      syn_pass<S>(B, A, m, F);  // rows (along x): B[c][r] = row r of the level -> A[r][c]
       __syncthreads();
     }
   }
@@ -624,12 +635,16 @@ __global__ __launch_bounds__(256) void k_fdwt_glob(const ProbDev* P, const Layer
 // line of side m read at src[x str]:
 //   a_k = sum_i h_i x[(2k + i) mod m],  d_k = sum_i g_i x[(2k + i) mod m]
 // Consecutive pairs share four of their six taps: 2 NP + 4 reads per line.
-template <int NP>
-__device__ __forceinline__ void ana_line(const float* src, int str, int m, int K0, const Filter& F, float a[NP],
-                                         float d[NP]) {
+// The first 2 NP taps never wrap (K0 + NP <= m / 2) and are read at fixed
+// offsets (the stride STR is a compile-time constant); the last four may.
+template <int NP, int STR>
+__device__ __forceinline__ void ana_line(const float* src, int m, int K0, const Filter& F, float a[NP], float d[NP]) {
   float x[2 * NP + 4];
+  const float* b = src + 2 * K0 * STR;
 #pragma unroll
-  for (int i = 0; i < 2 * NP + 4; ++i) x[i] = src[((2 * K0 + i) & (m - 1)) * str];
+  for (int i = 0; i < 2 * NP; ++i) x[i] = b[i * STR];
+#pragma unroll
+  for (int i = 2 * NP; i < 2 * NP + 4; ++i) x[i] = src[((2 * K0 + i) & (m - 1)) * STR];
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     a[p] = 0.f;
@@ -647,9 +662,9 @@ __device__ __forceinline__ void ana_line(const float* src, int str, int m, int K
 // (lanes on consecutive columns) with the epilogue of every detail output;
 // the coarse block stays in A for the next level.  The epilogue operands are
 // requested before the passes, so their latency overlaps the LDS work.
-template <int NP>
+template <int NP, int S>
 __device__ __forceinline__ void ana_level(const ProbDev& pr, const LayerDev& ly, const IoDev& io, int epi, int iter,
-                                          float* A, float* B, int S, int m, const Filter& F, double& acc) {
+                                          float* A, float* B, int m, const Filter& F, double& acc) {
   const int half = m >> 1, lm = __builtin_ctz(m), nt = blockDim.x, n = ly.n, off = ly.off;
   const int tasks = m * (half / NP);
   const int j = lm - 1;  // detail blocks of this level have side half = 2^j
@@ -668,7 +683,7 @@ __device__ __forceinline__ void ana_level(const ProbDev& pr, const LayerDev& ly,
   }
   if (mine) {  // rows: line r = c of this task's numbering
     float a[NP], d[NP];
-    ana_line<NP>(A + c * S, 1, m, K0, F, a, d);
+    ana_line<NP, 1>(A + c * S, m, K0, F, a, d);
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       B[c * S + K0 + p] = a[p];
@@ -678,7 +693,7 @@ __device__ __forceinline__ void ana_level(const ProbDev& pr, const LayerDev& ly,
   __syncthreads();
   if (mine) {  // columns
     float a[NP], d[NP];
-    ana_line<NP>(B + c, S, m, K0, F, a, d);
+    ana_line<NP, S>(B + c, m, K0, F, a, d);
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       const int k = K0 + p;
@@ -724,8 +739,8 @@ __device__ __forceinline__ void pcg_fetch(gptr_f pb, int off, int n, int R, int 
 // One analysis level of side M with the PCG epilogue (q = delta^{-1} W p +
 // alpha D p, += p q) from operands already in registers: the same passes,
 // products and order as ana_level with EPI_PCG.
-template <int M>
-__device__ __forceinline__ void pcg_level(const ProbDev& pr, const LayerDev& ly, float* A, float* B, int S,
+template <int M, int S>
+__device__ __forceinline__ void pcg_level(const ProbDev& pr, const LayerDev& ly, float* A, float* B,
                                           const Filter& F, const float* op, double& acc) {
   constexpr int NP = ana_np(M), half = M / 2, lm = ilog2c(M);
   const int n = ly.n, off = ly.off;
@@ -734,7 +749,7 @@ __device__ __forceinline__ void pcg_level(const ProbDev& pr, const LayerDev& ly,
   const float ad = ly.alpha_d[lm - 1];
   if (mine) {  // rows
     float a[NP], d[NP];
-    ana_line<NP>(A + c * S, 1, M, K0, F, a, d);
+    ana_line<NP, 1>(A + c * S, M, K0, F, a, d);
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       B[c * S + K0 + p] = a[p];
@@ -744,7 +759,7 @@ __device__ __forceinline__ void pcg_level(const ProbDev& pr, const LayerDev& ly,
   __syncthreads();
   if (mine) {  // columns and the epilogue
     float a[NP], d[NP];
-    ana_line<NP>(B + c, S, M, K0, F, a, d);
+    ana_line<NP, S>(B + c, M, K0, F, a, d);
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       const int k = K0 + p;
@@ -762,16 +777,16 @@ __device__ __forceinline__ void pcg_level(const ProbDev& pr, const LayerDev& ly,
   __syncthreads();
 }
 
-template <int M>
-__device__ __forceinline__ void pcg_levels(const ProbDev& pr, const LayerDev& ly, float* A, float* B, int S, int R,
+template <int M, int S>
+__device__ __forceinline__ void pcg_levels(const ProbDev& pr, const LayerDev& ly, float* A, float* B, int R,
                                            int m0, const Filter& F, const PcgOps<M>& o, double& acc) {
-  if (M <= R && M > m0) pcg_level<M>(pr, ly, A, B, S, F, o.p, acc);
-  if constexpr (M > 2) pcg_levels<M / 2>(pr, ly, A, B, S, R, m0, F, o.next, acc);
+  if (M <= R && M > m0) pcg_level<M, S>(pr, ly, A, B, F, o.p, acc);
+  if constexpr (M > 2) pcg_levels<M / 2, S>(pr, ly, A, B, R, m0, F, o.next, acc);
 }
 
 // One workgroup per (problem, layer): all analysis levels from the resident
 // side R down to the coarsest block run in LDS, rows then columns, with the
-// epilogue of every output.  LDS rows have the odd stride S = R + 1 (strided
+// epilogue of every output.  LDS rows have the odd stride S = RMAX + 1 (strided
 // lane access free of bank conflicts).  PCG = the EPI_PCG instantiation,
 // whose epilogue operands for every level are requested with the input.
 template <int RMAX, bool PCG>
@@ -785,7 +800,8 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[pr.layer0 + t.item];
   const IoDev& io = IO[t.prob];
-  const int n = ly.n, R = ly.res, lr = __builtin_ctz(R), off = ly.off, S = R + 1;
+  const int n = ly.n, R = ly.res, lr = __builtin_ctz(R), off = ly.off;
+  constexpr int S = RMAX + 1;
   const int nt = blockDim.x;
   const int ng = ly.n_glob_levels;
   const gptr_f in = (gptr_f)((ng == 0) ? pr.phiadj + off : ((((ng - 1) & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off));
@@ -810,17 +826,17 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
   if constexpr (PCG) pcg_fetch<RMAX>((gptr_f)((iter & 1) ? pr.pbuf1 : pr.pbuf0), off, n, R, m0, ops);
   double acc = 0.0;
   __syncthreads();
-  if constexpr (PCG) pcg_levels<RMAX>(pr, ly, A, B, S, R, m0, F, ops, acc);
+  if constexpr (PCG) pcg_levels<RMAX, S>(pr, ly, A, B, R, m0, F, ops, acc);
   for (int m = R; m > m0 && !PCG; m >>= 1) {
     const int np = max(1, m * (m >> 1) / nt);  // output pairs per thread and line: 1, 2, 4 or 8
     if (np >= 8)
-      ana_level<8>(pr, ly, io, epi, iter, A, B, S, m, F, acc);
+      ana_level<8, S>(pr, ly, io, epi, iter, A, B, m, F, acc);
     else if (np == 4)
-      ana_level<4>(pr, ly, io, epi, iter, A, B, S, m, F, acc);
+      ana_level<4, S>(pr, ly, io, epi, iter, A, B, m, F, acc);
     else if (np == 2)
-      ana_level<2>(pr, ly, io, epi, iter, A, B, S, m, F, acc);
+      ana_level<2, S>(pr, ly, io, epi, iter, A, B, m, F, acc);
     else
-      ana_level<1>(pr, ly, io, epi, iter, A, B, S, m, F, acc);
+      ana_level<1, S>(pr, ly, io, epi, iter, A, B, m, F, acc);
   }
   const int jll = __builtin_ctz(m0);
   for (int e = threadIdx.x; e < m0 * m0; e += nt) {
@@ -1143,10 +1159,11 @@ __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* 
 // the wave (scalar loads).  The gather is separable: the corner rows that the
 // RPT node rows touch form one band (first corners never decrease along an
 // axis), each band row is interpolated along x once and reused by every node
-// row whose hat covers it.  Sensors whose footprint misses the tile are
-// skipped (tile mask).  Sensors sampling the layer finer than 2/3 of its
-// spacing, or whose band would exceed the register budget (kmax = 0), take a
-// general loop.  No atomics: every node is written once.
+// row whose hat covers it; a record's step pattern fixes at compile time
+// which band rows each node row reads.  A tile lists only the sensors with a
+// nonzero hat in its rows and columns.  Sensors sampling the layer finer than
+// 2/3 of its spacing, or whose band would exceed the register budget (kmax =
+// 0), take a general loop.  No atomics: every node is written once.
 template <int RPT>
 __device__ __forceinline__ void pt_general(const GLPar& gp, const float* vadj, int q, int p0, int n,
                                            float acc[RPT]) {
