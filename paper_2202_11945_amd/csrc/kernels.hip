@@ -425,6 +425,8 @@ __device__ __forceinline__ void syn_run(const float* a_src, const float* d_src, 
 }
 
 // ----------------------------------------------- inverse DWT, one global level
+// (Both global-level kernels are held to 64 VGPRs, 8 waves per SIMD: a batch
+// launch of 2048 tiles then runs in a single round of workgroups.)
 // Output tile 32x32 of the level with side m = 2^t.level (> the resident side).  The
 // coarse block comes from scratch, the three detail quadrants from the
 // coefficient source; 2 halo coefficients per direction (6 taps, 3 per phase).
@@ -432,7 +434,7 @@ constexpr int kGT = 32;           // output tile side
 constexpr int kGH = kGT / 2 + 2;  // coefficients per band and direction (18)
 constexpr int kGW = 2 * kGH;      // 36
 
-__global__ __launch_bounds__(256) void k_idwt_glob(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_idwt_glob(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
                                                    const Tile* tiles, Filter F, int src_mode, int out_mode,
                                                    int iter, int step) {
   __shared__ float A[kGW * (kGW + 1)];
@@ -527,7 +529,7 @@ __global__ __launch_bounds__(256) void k_idwt_glob(const ProbDev* P, const Layer
 constexpr int kFT = 16;           // output coefficients per direction
 constexpr int kFW = 2 * kFT + 4;  // 36 input samples per direction
 
-__global__ __launch_bounds__(256) void k_fdwt_glob(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_fdwt_glob(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
                                                    const Tile* tiles, Filter F, int epi, int iter, int step) {
   __shared__ float X[kFW * (kFW + 1)];
   __shared__ float Rw[kFW * (2 * kFT + 1)];
