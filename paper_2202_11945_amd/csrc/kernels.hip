@@ -452,39 +452,50 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   const int kr0 = (t0 >> 1) - 2, kc0 = (s0 >> 1) - 2;
   const int W1 = kGW + 1;
   const int nt = blockDim.x;
-  for (int e0 = threadIdx.x; e0 < kGW * kGW; e0 += kUG * nt) {
-    CoefLoad v[kUG];
-    int gpos[kUG];
+  // the window's four bands, one per wave (so no wave mixes the coarse
+  // block with the coefficient source): wave 0 the coarse block (scratch),
+  // waves 1 .. 3 the detail quadrants (by, bx) = (0, 1), (1, 0), (1, 1)
+  constexpr int kBand = kGH * kGH, kRounds = (kBand + 63) / 64;
+  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int by = wv >> 1, bx = wv & 1;
+  float val[kRounds];
+  if (wv == 0) {
 #pragma unroll
-    for (int u = 0; u < kUG; ++u) {
-      const int e = e0 + u * nt;
-      gpos[u] = -2;
-      if (e < kGW * kGW) {
-        const int ly_ = e / kGW, lx_ = e - ly_ * kGW;
-        const int by = ly_ >= kGH, bx = lx_ >= kGH;
-        const int iy = ly_ - by * kGH, ix = lx_ - bx * kGH;
-        const int kr = (kr0 + iy) & (half - 1), kc = (kc0 + ix) & (half - 1);
-        if (!by && !bx) {
-          gpos[u] = -1;
-          v[u].a = ll[kr * half + kc];
-        } else {
-          gpos[u] = (by * half + kr) * n + (bx * half + kc);
-          v[u] = coef_fetch(ps, off + gpos[u]);
-        }
+    for (int u = 0; u < kRounds; ++u) {
+      const int e = lane + 64 * u;
+      if (e < kBand) {
+        const int iy = e / kGH, ix = e - iy * kGH;
+        val[u] = ll[((kr0 + iy) & (half - 1)) * half + ((kc0 + ix) & (half - 1))];
       }
     }
-    if (e0 == threadIdx.x) ps.beta = wave_beta(pr, src_mode, iter);
+  } else {
+    CoefLoad v[kRounds];
+    int gpos[kRounds];
 #pragma unroll
-    for (int u = 0; u < kUG; ++u) {
-      const int e = e0 + u * nt;
-      if (gpos[u] == -2) continue;
-      const int ly_ = e / kGW, lx_ = e - ly_ * kGW;
-      float val = v[u].a;
-      if (gpos[u] >= 0) {
-        const int iy = ly_ >= kGH ? ly_ - kGH : ly_, ix = lx_ >= kGH ? lx_ - kGH : lx_;
-        val = coef_finish(ps, off + gpos[u], v[u], iy >= 2 && ix >= 2);
+    for (int u = 0; u < kRounds; ++u) {
+      const int e = lane + 64 * u;
+      if (e < kBand) {
+        const int iy = e / kGH, ix = e - iy * kGH;
+        gpos[u] = off + (by * half + ((kr0 + iy) & (half - 1))) * n + bx * half + ((kc0 + ix) & (half - 1));
+        v[u] = coef_fetch(ps, gpos[u]);
       }
-      A[ly_ * W1 + lx_] = val;
+    }
+    ps.beta = wave_beta(pr, src_mode, iter);
+#pragma unroll
+    for (int u = 0; u < kRounds; ++u) {
+      const int e = lane + 64 * u;
+      if (e < kBand) {
+        const int iy = e / kGH, ix = e - iy * kGH;
+        val[u] = coef_finish(ps, gpos[u], v[u], iy >= 2 && ix >= 2);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kRounds; ++u) {
+    const int e = lane + 64 * u;
+    if (e < kBand) {
+      const int iy = e / kGH, ix = e - iy * kGH;
+      A[(by * kGH + iy) * W1 + bx * kGH + ix] = val[u];
     }
   }
   __syncthreads();
@@ -924,22 +935,33 @@ __global__ __launch_bounds__(kSensThreads) void k_pgamma(const ProbDev* P, const
     const int ic = i0 + lci, jc = j0 + lcj;
     float v = 0.f;
     if (ic < nc && jc < nc) {
-      const gptr_i it = (gptr_i)(pr.itab + w.tab_off);
-      const gptr_f ft = (gptr_f)(pr.ftab + w.tab_off);
+      // raw buffer loads: lane offsets from the corner (ic, jc) and the cell,
+      // wave-uniform offsets from the layer, so no per-load address arithmetic
+      // (no range limit: the tables and cells are valid by construction)
+      const __amdgpu_buffer_rsrc_t irs =
+          __builtin_amdgcn_make_buffer_rsrc((void*)(pr.itab + w.tab_off), (short)0, 0x7fffffff, 0x00020000);
+      const __amdgpu_buffer_rsrc_t frs =
+          __builtin_amdgcn_make_buffer_rsrc((void*)(pr.ftab + w.tab_off), (short)0, 0x7fffffff, 0x00020000);
+      const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc((void*)phi, (short)0, 0x7fffffff, 0x00020000);
+      const int vi = ic * (int)sizeof(float), vj = jc * (int)sizeof(float);
+      auto ld = [](__amdgpu_buffer_rsrc_t rs, int vo, int so) {  // so: wave-uniform (stated, or the
+        return __builtin_amdgcn_raw_buffer_load_b32(rs, vo, __builtin_amdgcn_readfirstlane(so), 0);  // load loops)
+      };
       for (int l0 = 0; l0 < pr.L; l0 += 4) {
-        int cell[4];
+        int cell[4], nl[4];
         float wy[4], wx[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          cell[k] = 0;
+          cell[k] = nl[k] = 0;
           wy[k] = wx[k] = 0.f;
           const int l = l0 + k;
           if (l < pr.L) {
             const LayerDev& ly = LD[t.mask + l];
-            const int tb = l * w.tab_stride;
-            cell[k] = ly.off + it[tb + ic] * ly.n + it[tb + nc + jc];
-            wy[k] = ft[tb + 2 * nc + ic];
-            wx[k] = ft[tb + 3 * nc + jc];
+            const int tb = l * w.tab_stride * (int)sizeof(float);
+            nl[k] = ly.n;
+            cell[k] = ly.off + (int)ld(irs, vi, tb) * ly.n + (int)ld(irs, vj, tb + nc * (int)sizeof(float));
+            wy[k] = __uint_as_float(ld(frs, vi, tb + 2 * nc * (int)sizeof(float)));
+            wx[k] = __uint_as_float(ld(frs, vj, tb + 3 * nc * (int)sizeof(float)));
           }
         }
         float nd[4][4];
@@ -947,12 +969,11 @@ __global__ __launch_bounds__(kSensThreads) void k_pgamma(const ProbDev* P, const
         for (int k = 0; k < 4; ++k) {
           nd[k][0] = nd[k][1] = nd[k][2] = nd[k][3] = 0.f;
           if (l0 + k < pr.L) {
-            const int n = LD[t.mask + l0 + k].n;
-            const gptr_f ph = (gptr_f)(phi + cell[k]);
-            nd[k][0] = ph[0];
-            nd[k][1] = ph[1];
-            nd[k][2] = ph[n];
-            nd[k][3] = ph[n + 1];
+            const int vo = cell[k] * (int)sizeof(float), so = nl[k] * (int)sizeof(float);
+            nd[k][0] = __uint_as_float(ld(prs, vo, 0));
+            nd[k][1] = __uint_as_float(ld(prs, vo + (int)sizeof(float), 0));
+            nd[k][2] = __uint_as_float(ld(prs, vo, so));
+            nd[k][3] = __uint_as_float(ld(prs, vo + (int)sizeof(float), so));
           }
         }
 #pragma unroll
