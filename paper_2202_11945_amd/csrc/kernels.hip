@@ -670,96 +670,62 @@ __device__ __forceinline__ void ana_line(const float* src, int m, int K0, const 
   }
 }
 
-// One analysis level of side m in LDS (A and B with row stride S), NP output
-// pairs per thread and line: rows A -> B (lanes on rows), then columns B -> A
-// (lanes on consecutive columns) with the epilogue of every detail output;
-// the coarse block stays in A for the next level.  The epilogue operands are
-// requested before the passes, so their latency overlaps the LDS work.
-template <int NP, int S>
-__device__ __forceinline__ void ana_level(const ProbDev& pr, const LayerDev& ly, const IoDev& io, int epi, int iter,
-                                          float* A, float* B, int m, const Filter& F, double& acc) {
-  const int half = m >> 1, lm = __builtin_ctz(m), nt = blockDim.x, n = ly.n, off = ly.off;
-  const int tasks = m * (half / NP);
-  const int j = lm - 1;  // detail blocks of this level have side half = 2^j
-  // column-pass outputs of this thread: column c, pairs K0 .. K0 + NP - 1
-  const int task = threadIdx.x;
-  const bool mine = task < tasks;  // tasks <= threads (NP = m half / threads, at least 1)
-  const int c = task & (m - 1), K0 = (task >> lm) * NP;
-  EpiLoad el[2 * NP];
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    if (mine) {
-      const int k = K0 + p;
-      if (c >= half) el[2 * p] = epi_fetch(pr, io, epi, iter, off + k * n + c);
-      el[2 * p + 1] = epi_fetch(pr, io, epi, iter, off + (half + k) * n + c);
-    }
-  }
-  if (mine) {  // rows: line r = c of this task's numbering
-    float a[NP], d[NP];
-    ana_line<NP, 1>(A + c * S, m, K0, F, a, d);
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      B[c * S + K0 + p] = a[p];
-      B[c * S + half + K0 + p] = d[p];
-    }
-  }
-  __syncthreads();
-  if (mine) {  // columns
-    float a[NP], d[NP];
-    ana_line<NP, S>(B + c, m, K0, F, a, d);
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const int k = K0 + p;
-      if (c >= half) epi_finish(pr, ly, io, epi, off + k * n + c, j, a[p] * ly.inv_delta, el[2 * p], acc);
-      epi_finish(pr, ly, io, epi, off + (half + k) * n + c, j, d[p] * ly.inv_delta, el[2 * p + 1], acc);
-      A[k * S + c] = a[p];  // rows >= half of A are no longer read
-    }
-  }
-  __syncthreads();
-}
-
 // Output pairs per thread and line of an analysis level of side m at 1024
 // threads (at least 1).
 constexpr int ana_np(int m) { return m * (m / 2) / 1024 > 1 ? m * (m / 2) / 1024 : 1; }
 constexpr int ilog2c(int m) { return m <= 1 ? 0 : 1 + ilog2c(m / 2); }
 
-// The PCG epilogue's one operand (p) at every output of this thread, for the
-// levels of side M and below, held in registers so that all of them are
-// requested when the workgroup starts.
+// The epilogue operands of every output of this thread at the levels of side
+// M and below (LevelOps) or at level M alone (OneLevelOps), in registers, so
+// that they are requested long before the level needs them.  Operands an
+// epilogue does not read stay constant zeros and take no registers.
 template <int M>
-struct PcgOps {
-  float p[2 * ana_np(M)];
-  PcgOps<M / 2> next;
+struct OneLevelOps {
+  EpiLoad l[2 * ana_np(M)];
+};
+template <int M>
+struct LevelOps {
+  EpiLoad l[2 * ana_np(M)];
+  LevelOps<M / 2> next;
 };
 template <>
-struct PcgOps<1> {};
+struct LevelOps<1> {};
 
-template <int M>
-__device__ __forceinline__ void pcg_fetch(gptr_f pb, int off, int n, int R, int m0, PcgOps<M>& o) {
+// Level M's operands: thread task = column c, output pairs K0 .. K0 + NP - 1
+// of the column pass (as in epi_level).
+template <int M, int EPI>
+__device__ __forceinline__ void epi_fetch_level(const ProbDev& pr, const IoDev& io, int iter, int off, int n, int R,
+                                                int m0, EpiLoad* l) {
   constexpr int NP = ana_np(M), half = M / 2;
-  if (M <= R && M > m0 && (int)threadIdx.x < M * (half / NP)) {
+  if (EPI != EPI_PLAIN && M <= R && M > m0 && (int)threadIdx.x < M * (half / NP)) {
     const int c = threadIdx.x & (M - 1), K0 = ((int)threadIdx.x >> ilog2c(M)) * NP;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       const int k = K0 + p;
-      o.p[2 * p] = c >= half ? pb[off + k * n + c] : 0.f;
-      o.p[2 * p + 1] = pb[off + (half + k) * n + c];
+      l[2 * p] = c >= half ? epi_fetch(pr, io, EPI, iter, off + k * n + c) : EpiLoad{0.f, 0.f, 0.f};
+      l[2 * p + 1] = epi_fetch(pr, io, EPI, iter, off + (half + k) * n + c);
     }
   }
-  if constexpr (M > 2) pcg_fetch<M / 2>(pb, off, n, R, m0, o.next);
+}
+template <int M, int EPI>
+__device__ __forceinline__ void epi_fetch_levels(const ProbDev& pr, const IoDev& io, int iter, int off, int n, int R,
+                                                 int m0, LevelOps<M>& o) {
+  epi_fetch_level<M, EPI>(pr, io, iter, off, n, R, m0, o.l);
+  if constexpr (M > 2) epi_fetch_levels<M / 2, EPI>(pr, io, iter, off, n, R, m0, o.next);
 }
 
-// One analysis level of side M with the PCG epilogue (q = delta^{-1} W p +
-// alpha D p, += p q) from operands already in registers: the same passes,
-// products and order as ana_level with EPI_PCG.
-template <int M, int S>
-__device__ __forceinline__ void pcg_level(const ProbDev& pr, const LayerDev& ly, float* A, float* B,
-                                          const Filter& F, const float* op, double& acc) {
+// One analysis level of side M in LDS (A and B with row stride S), NP output
+// pairs per thread and line: rows A -> B (lanes on rows), then columns B -> A
+// (lanes on consecutive columns) with the epilogue of every detail output
+// from operands already in registers; the coarse block stays in A for the
+// next level.
+template <int M, int S, int EPI>
+__device__ __forceinline__ void epi_level(const ProbDev& pr, const LayerDev& ly, const IoDev& io, float* A, float* B,
+                                          const Filter& F, const EpiLoad* el, double& acc) {
   constexpr int NP = ana_np(M), half = M / 2, lm = ilog2c(M);
   const int n = ly.n, off = ly.off;
   const bool mine = (int)threadIdx.x < M * (half / NP);
   const int c = threadIdx.x & (M - 1), K0 = ((int)threadIdx.x >> lm) * NP;
-  const float ad = ly.alpha_d[lm - 1];
   if (mine) {  // rows
     float a[NP], d[NP];
     ana_line<NP, 1>(A + c * S, M, K0, F, a, d);
@@ -776,35 +742,31 @@ __device__ __forceinline__ void pcg_level(const ProbDev& pr, const LayerDev& ly,
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       const int k = K0 + p;
-      if (c >= half) {
-        const float qe = a[p] * ly.inv_delta + ad * op[2 * p];
-        pr.q[off + k * n + c] = qe;
-        acc += (double)op[2 * p] * (double)qe;
-      }
-      const float qd = d[p] * ly.inv_delta + ad * op[2 * p + 1];
-      pr.q[off + (half + k) * n + c] = qd;
-      acc += (double)op[2 * p + 1] * (double)qd;
-      A[k * S + c] = a[p];
+      if (c >= half) epi_finish(pr, ly, io, EPI, off + k * n + c, lm - 1, a[p] * ly.inv_delta, el[2 * p], acc);
+      epi_finish(pr, ly, io, EPI, off + (half + k) * n + c, lm - 1, d[p] * ly.inv_delta, el[2 * p + 1], acc);
+      A[k * S + c] = a[p];  // rows >= half of A are no longer read
     }
   }
   __syncthreads();
 }
 
-template <int M, int S>
-__device__ __forceinline__ void pcg_levels(const ProbDev& pr, const LayerDev& ly, float* A, float* B, int R,
-                                           int m0, const Filter& F, const PcgOps<M>& o, double& acc) {
-  if (M <= R && M > m0) pcg_level<M, S>(pr, ly, A, B, F, o.p, acc);
-  if constexpr (M > 2) pcg_levels<M / 2, S>(pr, ly, A, B, R, m0, F, o.next, acc);
+template <int M, int S, int EPI>
+__device__ __forceinline__ void epi_levels(const ProbDev& pr, const LayerDev& ly, const IoDev& io, float* A, float* B,
+                                           int R, int m0, const Filter& F, const LevelOps<M>& o, double& acc) {
+  if (M <= R && M > m0) epi_level<M, S, EPI>(pr, ly, io, A, B, F, o.l, acc);
+  if constexpr (M > 2) epi_levels<M / 2, S, EPI>(pr, ly, io, A, B, R, m0, F, o.next, acc);
 }
 
 // One workgroup per (problem, layer): all analysis levels from the resident
 // side R down to the coarsest block run in LDS, rows then columns, with the
-// epilogue of every output.  LDS rows have the odd stride S = RMAX + 1 (strided
-// lane access free of bank conflicts).  PCG = the EPI_PCG instantiation,
-// whose epilogue operands for every level are requested with the input.
-template <int RMAX, bool PCG>
+// epilogue EPI of every output.  LDS rows have the odd stride S = RMAX + 1
+// (strided lane access free of bank conflicts).  The PCG epilogue's operand
+// (p) for every level is requested with the input; the others (up to three
+// operands per output) request the top level's with the input and all lower
+// levels' once the top level is done, so that the registers hold one set.
+template <int RMAX, int EPI>
 __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
-                                                   const Tile* tiles, Filter F, int epi, int iter) {
+                                                   const Tile* tiles, Filter F, int iter) {
   static_assert(RMAX * RMAX / 2 <= 8 * 1024, "at most 8 output pairs per thread and line at 1024 threads");
   __shared__ float A[RMAX * (RMAX + 1)];
   __shared__ float B[RMAX * (RMAX + 1)];
@@ -820,7 +782,6 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
   const gptr_f in = (gptr_f)((ng == 0) ? pr.phiadj + off : ((((ng - 1) & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off));
   const int istride = (ng == 0) ? n : R;
   const int m0 = n >> ly.levels;
-  PcgOps<PCG ? RMAX : 1> ops;  // the PCG epilogue's operands of every level
   constexpr int kUL = 16;  // the whole block's loads in flight together
   for (int e0 = threadIdx.x; e0 < R * R; e0 += kUL * nt) {
     float v[kUL];
@@ -835,32 +796,35 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
       if (e < R * R) A[(e >> lr) * S + (e & (R - 1))] = v[u];
     }
   }
-  // requested before the barrier: one memory round trip for every level
-  if constexpr (PCG) pcg_fetch<RMAX>((gptr_f)((iter & 1) ? pr.pbuf1 : pr.pbuf0), off, n, R, m0, ops);
   double acc = 0.0;
-  __syncthreads();
-  if constexpr (PCG) pcg_levels<RMAX, S>(pr, ly, A, B, R, m0, F, ops, acc);
-  for (int m = R; m > m0 && !PCG; m >>= 1) {
-    const int np = max(1, m * (m >> 1) / nt);  // output pairs per thread and line: 1, 2, 4 or 8
-    if (np >= 8)
-      ana_level<8, S>(pr, ly, io, epi, iter, A, B, m, F, acc);
-    else if (np == 4)
-      ana_level<4, S>(pr, ly, io, epi, iter, A, B, m, F, acc);
-    else if (np == 2)
-      ana_level<2, S>(pr, ly, io, epi, iter, A, B, m, F, acc);
-    else
-      ana_level<1, S>(pr, ly, io, epi, iter, A, B, m, F, acc);
+  if constexpr (EPI == EPI_PCG) {
+    LevelOps<RMAX> ops;  // requested before the barrier: one memory round trip for every level
+    epi_fetch_levels<RMAX, EPI>(pr, io, iter, off, n, R, m0, ops);
+    __syncthreads();
+    epi_levels<RMAX, S, EPI>(pr, ly, io, A, B, R, m0, F, ops, acc);
+  } else {
+    {
+      OneLevelOps<RMAX> top;
+      epi_fetch_level<RMAX, EPI>(pr, io, iter, off, n, R, m0, top.l);
+      __syncthreads();
+      if (RMAX <= R && RMAX > m0) epi_level<RMAX, S, EPI>(pr, ly, io, A, B, F, top.l, acc);
+    }
+    if constexpr (RMAX > 2) {
+      LevelOps<RMAX / 2> rest;
+      epi_fetch_levels<RMAX / 2, EPI>(pr, io, iter, off, n, R, m0, rest);
+      epi_levels<RMAX / 2, S, EPI>(pr, ly, io, A, B, R, m0, F, rest, acc);
+    }
   }
   const int jll = __builtin_ctz(m0);
   for (int e = threadIdx.x; e < m0 * m0; e += nt) {
     const int r = e / m0, c = e - r * m0;
     const int pos = off + r * n + c;
-    const EpiLoad l = epi_fetch(pr, io, epi, iter, pos);
-    epi_finish(pr, ly, io, epi, pos, jll, A[r * S + c] * ly.inv_delta, l, acc);
+    const EpiLoad l = epi_fetch(pr, io, EPI, iter, pos);
+    epi_finish(pr, ly, io, EPI, pos, jll, A[r * S + c] * ly.inv_delta, l, acc);
   }
-  if (epi == EPI_PCG || epi == EPI_RHS) {
+  if (EPI == EPI_PCG || EPI == EPI_RHS) {
     const double s = block_sum(acc, sh, nt);
-    if (threadIdx.x == 0) pr.dots[(long)dot_group_of(epi, iter) * pr.n_dots + t.slot] = s;
+    if (threadIdx.x == 0) pr.dots[(long)dot_group_of(EPI, iter) * pr.n_dots + t.slot] = s;
   }
 }
 
@@ -1727,25 +1691,23 @@ void launch_idwt_glob(const LaunchArgs& a, const Tile* tiles, int ntiles, int sr
 void launch_fdwt_glob(const LaunchArgs& a, const Tile* tiles, int ntiles, int epi, int iter, int step) {
   if (ntiles > 0) k_fdwt_glob<<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter, step);
 }
+template <int RMAX>
+static void launch_fdwt_res_r(const LaunchArgs& a, const Tile* tiles, int ntiles, int epi, int iter) {
+  switch (epi) {
+    case EPI_APPLYM: k_fdwt_res<RMAX, EPI_APPLYM><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, iter); break;
+    case EPI_PCG: k_fdwt_res<RMAX, EPI_PCG><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, iter); break;
+    case EPI_RHS: k_fdwt_res<RMAX, EPI_RHS><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, iter); break;
+    default: k_fdwt_res<RMAX, EPI_PLAIN><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, iter); break;
+  }
+}
 void launch_fdwt_res(const LaunchArgs& a, const Tile* tiles, int ntiles, int epi, int iter) {
   if (ntiles <= 0) return;
-  const bool pcg = epi == EPI_PCG;
-  if (a.res_max <= 32) {
-    if (pcg)
-      k_fdwt_res<32, true><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
-    else
-      k_fdwt_res<32, false><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
-  } else if (a.res_max <= 64) {
-    if (pcg)
-      k_fdwt_res<64, true><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
-    else
-      k_fdwt_res<64, false><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
-  } else {
-    if (pcg)
-      k_fdwt_res<128, true><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
-    else
-      k_fdwt_res<128, false><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter);
-  }
+  if (a.res_max <= 32)
+    launch_fdwt_res_r<32>(a, tiles, ntiles, epi, iter);
+  else if (a.res_max <= 64)
+    launch_fdwt_res_r<64>(a, tiles, ntiles, epi, iter);
+  else
+    launch_fdwt_res_r<128>(a, tiles, ntiles, epi, iter);
 }
 void launch_pgamma(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
   if (ntiles > 0) k_pgamma<<<ntiles, kSensThreads, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, mode);
