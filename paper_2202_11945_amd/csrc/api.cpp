@@ -558,7 +558,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
       const WfsDev& wd = P.hW[pd.wfs0 + g];
       for (int ty = 0; ty < wd.tiles_side; ++ty)
         for (int tx = 0; tx < wd.tiles_side; ++tx) t_pg.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
-      const int tc = cdiv(wd.nc, kTileS);
+      const int tc = cdiv(wd.nc, kGtS);
       for (int ty = 0; ty < tc; ++ty)
         for (int tx = 0; tx < tc; ++tx) t_gt.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
     }

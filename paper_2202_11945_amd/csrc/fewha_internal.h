@@ -16,6 +16,7 @@ namespace fewha {
 constexpr int kMaxLevelsJ = 16;   // j index range of the per-layer prior table
 constexpr int kResMax = 128;      // largest block kept resident in LDS by the DWT kernels (default residency)
 constexpr int kTileS = 16;        // subaperture / corner tile side of the sensor stages
+constexpr int kGtS = 32;          // corner tile side of the noise-weighted sensor adjoint (4 corners per thread)
 constexpr int kTileN = 32;        // node tile side of the FP64 propagation adjoint
 constexpr int kPtW = 64;          // propagation adjoint tile: 64 node columns (one per lane) by
                                   // 4 x rows-per-thread node rows (tuning: 4 or 8 rows per thread)

@@ -201,22 +201,34 @@ __device__ __forceinline__ EpiLoad epi_fetch(const ProbDev& pr, const IoDev& io,
   }
   return l;
 }
-__device__ __forceinline__ void epi_finish(const ProbDev& pr, const LayerDev& ly, const IoDev& io, int epi, int e,
-                                           int j, float v, const EpiLoad& l, double& acc) {
-  const float ad = ly.alpha_d[j];
+// The epilogue's destinations, read from the problem once per kernel (a
+// store through them could alias the problem record, so reading them at
+// every output would reload them after every store); ad = alpha D of the
+// output's level, likewise passed in.
+struct EpiDst {
+  float* q;    // EPI_PCG
+  float* out;  // EPI_APPLYM, EPI_PLAIN
+  float* b;    // EPI_RHS: b' and r0 in the state
+  float* r;
+};
+__device__ __forceinline__ EpiDst epi_dst(const ProbDev& pr, const IoDev& io) {
+  return EpiDst{pr.q, io.out, io.state + pr.n_c, io.state + 2L * pr.n_c};
+}
+__device__ __forceinline__ void epi_finish(const EpiDst& dst, int epi, int e, float ad, float v, const EpiLoad& l,
+                                           double& acc) {
   if (epi == EPI_APPLYM) {
-    io.out[e] = v + ad * l.x0;
+    dst.out[e] = v + ad * l.x0;
   } else if (epi == EPI_PCG) {
     const float qe = v + ad * l.x0;
-    pr.q[e] = qe;
+    dst.q[e] = qe;
     acc += (double)l.x0 * (double)qe;
   } else if (epi == EPI_RHS) {
     const float r0 = (v - l.x0) + l.x1;
-    io.state[pr.n_c + e] = v;
-    io.state[2L * pr.n_c + e] = r0;
+    dst.b[e] = v;
+    dst.r[e] = r0;
     acc += (double)r0 * (double)r0 * (double)l.x2;
   } else {
-    io.out[e] = v;
+    dst.out[e] = v;
   }
 }
 
@@ -609,7 +621,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   }
   __syncthreads();
   double acc = 0.0;
-  const int j = t.level - 1;  // detail blocks of this level have side half = 2^j
+  const float ad = ly.alpha_d[t.level - 1];  // detail blocks of this level have side half = 2^(level - 1)
+  const EpiDst dst = epi_dst(pr, io);
   // 512 (row, column) pairs of the column pass, 2 per thread; each yields up to 2 outputs
   {
     float eval[4];
@@ -635,7 +648,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      if (epos[k] >= 0) epi_finish(pr, ly, io, epi, epos[k], j, eval[k], el[k], acc);
+      if (epos[k] >= 0) epi_finish(dst, epi, epos[k], ad, eval[k], el[k], acc);
   }
   if (epi == EPI_PCG || epi == EPI_RHS) {
     const double s = block_sum(acc, sh, nt);
@@ -720,10 +733,11 @@ __device__ __forceinline__ void epi_fetch_levels(const ProbDev& pr, const IoDev&
 // from operands already in registers; the coarse block stays in A for the
 // next level.
 template <int M, int S, int EPI>
-__device__ __forceinline__ void epi_level(const ProbDev& pr, const LayerDev& ly, const IoDev& io, float* A, float* B,
-                                          const Filter& F, const EpiLoad* el, double& acc) {
+__device__ __forceinline__ void epi_level(const LayerDev& ly, const EpiDst& dst, float* A, float* B, const Filter& F,
+                                          const EpiLoad* el, double& acc) {
   constexpr int NP = ana_np(M), half = M / 2, lm = ilog2c(M);
   const int n = ly.n, off = ly.off;
+  const float ad = ly.alpha_d[lm - 1], inv_delta = ly.inv_delta;
   const bool mine = (int)threadIdx.x < M * (half / NP);
   const int c = threadIdx.x & (M - 1), K0 = ((int)threadIdx.x >> lm) * NP;
   if (mine) {  // rows
@@ -742,8 +756,8 @@ __device__ __forceinline__ void epi_level(const ProbDev& pr, const LayerDev& ly,
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       const int k = K0 + p;
-      if (c >= half) epi_finish(pr, ly, io, EPI, off + k * n + c, lm - 1, a[p] * ly.inv_delta, el[2 * p], acc);
-      epi_finish(pr, ly, io, EPI, off + (half + k) * n + c, lm - 1, d[p] * ly.inv_delta, el[2 * p + 1], acc);
+      if (c >= half) epi_finish(dst, EPI, off + k * n + c, ad, a[p] * inv_delta, el[2 * p], acc);
+      epi_finish(dst, EPI, off + (half + k) * n + c, ad, d[p] * inv_delta, el[2 * p + 1], acc);
       A[k * S + c] = a[p];  // rows >= half of A are no longer read
     }
   }
@@ -751,10 +765,10 @@ __device__ __forceinline__ void epi_level(const ProbDev& pr, const LayerDev& ly,
 }
 
 template <int M, int S, int EPI>
-__device__ __forceinline__ void epi_levels(const ProbDev& pr, const LayerDev& ly, const IoDev& io, float* A, float* B,
-                                           int R, int m0, const Filter& F, const LevelOps<M>& o, double& acc) {
-  if (M <= R && M > m0) epi_level<M, S, EPI>(pr, ly, io, A, B, F, o.l, acc);
-  if constexpr (M > 2) epi_levels<M / 2, S, EPI>(pr, ly, io, A, B, R, m0, F, o.next, acc);
+__device__ __forceinline__ void epi_levels(const LayerDev& ly, const EpiDst& dst, float* A, float* B, int R, int m0,
+                                           const Filter& F, const LevelOps<M>& o, double& acc) {
+  if (M <= R && M > m0) epi_level<M, S, EPI>(ly, dst, A, B, F, o.l, acc);
+  if constexpr (M > 2) epi_levels<M / 2, S, EPI>(ly, dst, A, B, R, m0, F, o.next, acc);
 }
 
 // One workgroup per (problem, layer): all analysis levels from the resident
@@ -797,30 +811,31 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
     }
   }
   double acc = 0.0;
+  const EpiDst dst = epi_dst(pr, io);
   if constexpr (EPI == EPI_PCG) {
     LevelOps<RMAX> ops;  // requested before the barrier: one memory round trip for every level
     epi_fetch_levels<RMAX, EPI>(pr, io, iter, off, n, R, m0, ops);
     __syncthreads();
-    epi_levels<RMAX, S, EPI>(pr, ly, io, A, B, R, m0, F, ops, acc);
+    epi_levels<RMAX, S, EPI>(ly, dst, A, B, R, m0, F, ops, acc);
   } else {
     {
       OneLevelOps<RMAX> top;
       epi_fetch_level<RMAX, EPI>(pr, io, iter, off, n, R, m0, top.l);
       __syncthreads();
-      if (RMAX <= R && RMAX > m0) epi_level<RMAX, S, EPI>(pr, ly, io, A, B, F, top.l, acc);
+      if (RMAX <= R && RMAX > m0) epi_level<RMAX, S, EPI>(ly, dst, A, B, F, top.l, acc);
     }
     if constexpr (RMAX > 2) {
       LevelOps<RMAX / 2> rest;
       epi_fetch_levels<RMAX / 2, EPI>(pr, io, iter, off, n, R, m0, rest);
-      epi_levels<RMAX / 2, S, EPI>(pr, ly, io, A, B, R, m0, F, rest, acc);
+      epi_levels<RMAX / 2, S, EPI>(ly, dst, A, B, R, m0, F, rest, acc);
     }
   }
-  const int jll = __builtin_ctz(m0);
+  const float adll = ly.alpha_d[__builtin_ctz(m0)];
   for (int e = threadIdx.x; e < m0 * m0; e += nt) {
     const int r = e / m0, c = e - r * m0;
     const int pos = off + r * n + c;
     const EpiLoad l = epi_fetch(pr, io, EPI, iter, pos);
-    epi_finish(pr, ly, io, EPI, pos, jll, A[r * S + c] * ly.inv_delta, l, acc);
+    epi_finish(dst, EPI, pos, adll, A[r * S + c] * ly.inv_delta, l, acc);
   }
   if (EPI == EPI_PCG || EPI == EPI_RHS) {
     const double s = block_sum(acc, sh, nt);
@@ -1029,14 +1044,17 @@ __global__ __launch_bounds__(256) void k_slopes_in(const ProbDev* P, const WfsDe
 }
 
 // ------------------------------------- noise weighting + Shack-Hartmann adjoint
-// Tile of 16x16 corners; the weighted slopes of the 17x17 subapertures that
-// touch them are formed in LDS (thread t takes window entries t and t + 256):
+// Tile of 32x32 corners (4 per thread); the weighted slopes of the 33x33
+// subapertures that touch them are formed in LDS (thread t takes window
+// entries t, t + 256, ...), all their loads in flight together:
 // C_hat^{-1} = (I - T) C^{-1} (I - T) for LGS with tip/tilt removal (means
 // from the per-tile partial sums, Sec. 3.2), C^{-1} otherwise; GT_PLAIN
 // applies Gamma^T alone.  The subaperture operands are requested before the
 // means are reduced.
 __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* WD, const Tile* tiles, int mode) {
-  constexpr int SW = kTileS + 1;
+  constexpr int SW = kGtS + 1;                    // subaperture window of the tile
+  constexpr int kR = (SW * SW + 255) / 256;       // window elements per thread
+  constexpr int kC = kGtS * kGtS / 256;           // corners per thread
   __shared__ float YX[SW * SW];
   __shared__ float YY[SW * SW];
   __shared__ float mean[4];
@@ -1046,13 +1064,13 @@ __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* 
   const WfsDev& w = WD[t.slot];
   const int N = w.N, nc = w.nc;
   const bool weighted = mode == GT_WEIGHTED;
-  const int ci0 = t.ty * kTileS, cj0 = t.tx * kTileS;
+  const int ci0 = t.ty * kGtS, cj0 = t.tx * kGtS;
   const gptr_f sd = (gptr_f)(pr.sd + w.s_off);
   const gptr_i cmap = (gptr_i)(pr.cmap + w.m_off);
-  bool act[2];
-  float sx[2], sy[2], cb0[2], cb1[2], cb2[2];
+  bool act[kR];
+  float sx[kR], sy[kR], cb0[kR], cb1[kR], cb2[kR];
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
+  for (int u = 0; u < kR; ++u) {
     const int e = threadIdx.x + u * 256;
     act[u] = false;
     sx[u] = sy[u] = cb0[u] = cb1[u] = cb2[u] = 0.f;
@@ -1100,7 +1118,7 @@ __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* 
   __syncthreads();
   const float m0 = mean[0], m1 = mean[1], m2 = mean[2], m3 = mean[3];
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
+  for (int u = 0; u < kR; ++u) {
     const int e = threadIdx.x + u * 256;
     if (e >= SW * SW) continue;
     float yx = 0.f, yy = 0.f;
@@ -1121,16 +1139,20 @@ __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* 
     YY[e] = yy;
   }
   __syncthreads();
-  const int li = threadIdx.x >> 4, lj = threadIdx.x & 15;
-  const int i = ci0 + li, j = cj0 + lj;
-  if (i < nc && j < nc) {
-    // subapertures (i-1, j-1), (i-1, j), (i, j-1), (i, j) sit at local (li, lj) .. (li+1, lj+1)
-    const float xa = YX[li * SW + lj], xb = YX[li * SW + lj + 1];
-    const float xc = YX[(li + 1) * SW + lj], xd = YX[(li + 1) * SW + lj + 1];
-    const float ya = YY[li * SW + lj], yb = YY[li * SW + lj + 1];
-    const float yc = YY[(li + 1) * SW + lj], yd = YY[(li + 1) * SW + lj + 1];
-    const float v = 0.5f * ((xc - xd) + (xa - xb)) + 0.5f * ((ya + yb) - (yc + yd));
-    pr.vadj[w.v_off + i * nc + j] = v;
+#pragma unroll
+  for (int u = 0; u < kC; ++u) {
+    const int e = threadIdx.x + u * 256;
+    const int li = e / kGtS, lj = e % kGtS;
+    const int i = ci0 + li, j = cj0 + lj;
+    if (i < nc && j < nc) {
+      // subapertures (i-1, j-1), (i-1, j), (i, j-1), (i, j) sit at local (li, lj) .. (li+1, lj+1)
+      const float xa = YX[li * SW + lj], xb = YX[li * SW + lj + 1];
+      const float xc = YX[(li + 1) * SW + lj], xd = YX[(li + 1) * SW + lj + 1];
+      const float ya = YY[li * SW + lj], yb = YY[li * SW + lj + 1];
+      const float yc = YY[(li + 1) * SW + lj], yd = YY[(li + 1) * SW + lj + 1];
+      const float v = 0.5f * ((xc - xd) + (xa - xb)) + 0.5f * ((ya + yb) - (yc + yd));
+      pr.vadj[w.v_off + i * nc + j] = v;
+    }
   }
 }
 
