@@ -61,6 +61,7 @@ struct Plan {
   std::vector<WfsDev> hW;
   std::vector<Tile> hT;
   Range idwt_res, fdwt_res, pg, gt, pt, upd;
+  Range sin;  // slopes input: 2 x 2 groups of the propagation stage's subaperture tiles
   std::vector<Range> idwt_glob, fdwt_glob;
   Range fit_fwdL, fit_fwdD, fit_pt, fit_cg;  // DM fitting (empty when no problem fits)
   Range sinit, gprior, ghgt;                 // solve start, parameter-gradient reductions
@@ -347,6 +348,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   };
   std::vector<ProbLayout> lay(P.nprob);
   Carver cv;
+  std::vector<Tile> t_sin;
   std::vector<Tile> t_idwt_res, t_fdwt_res, t_pg, t_gt, t_pt, t_upd, t_sinit, t_gprior, t_ghgt, t_r64wfs, t_r64pt;
   HatTables hats;  // hat tables and band records of every problem and fitting view, one set per plan
   PtLists ptl;     // sensor lists of the propagation-adjoint tiles
@@ -558,6 +560,9 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
       const WfsDev& wd = P.hW[pd.wfs0 + g];
       for (int ty = 0; ty < wd.tiles_side; ++ty)
         for (int tx = 0; tx < wd.tiles_side; ++tx) t_pg.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
+      const int sg = cdiv(wd.tiles_side, 2);
+      for (int ty = 0; ty < sg; ++ty)
+        for (int tx = 0; tx < sg; ++tx) t_sin.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
       const int tc = cdiv(wd.nc, kGtS);
       for (int ty = 0; ty < tc; ++ty)
         for (int tx = 0; tx < tc; ++tx) t_gt.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
@@ -761,6 +766,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   P.idwt_res = add(t_idwt_res);
   P.fdwt_res = add(t_fdwt_res);
   P.pg = add(t_pg);
+  P.sin = add(t_sin);
   P.gt = add(t_gt);
   P.pt = add(t_pt);
   P.upd = add(t_upd);
@@ -1006,7 +1012,7 @@ void enq_apply_M_core(const Plan& P, const LaunchArgs& a) {
 }
 
 void enq_reconstruct(const Plan& P, const LaunchArgs& a, int iters) {
-  launch_slopes_in(a, T(P, P.pg), P.pg.n);
+  launch_slopes_in(a, T(P, P.sin), P.sin.n);
   enq_adjoint(P, a, GT_WEIGHTED, PT_PHIADJ);
   enq_fdwt(P, a, EPI_RHS, 0);
   for (int k = 0; k < iters; ++k) {
@@ -1246,7 +1252,7 @@ fewha_status run_param_grads(Plan& P, hipStream_t st, const std::vector<const fl
   enq_idwt(P, a, SRC_IN, OUT_USER, 0);
   // term 0: Gamma^T C_hat^{-1} (s - A phi) against dA W^{-1} lambda
   if ((s = stage([&](int k, IoDev& d) { d.in = slopes[k]; })) != FEWHA_OK) return s;
-  launch_slopes_in(a, T(P, P.pg), P.pg.n);
+  launch_slopes_in(a, T(P, P.sin), P.sin.n);
   if ((s = stage([&](int k, IoDev& d) { d.in = P.hP[k].gphi; })) != FEWHA_OK) return s;
   launch_pgamma(a, T(P, P.pg), P.pg.n, PG_RESID_IN);
   launch_gammaT(a, T(P, P.gt), P.gt.n, GT_WEIGHTED);
@@ -1541,7 +1547,7 @@ fewha_status fewha_apply_AT(fewha_ctx* c, const float* slopes, float* layers) {
   io[0].out = layers;
   if ((s = upload_io(P, io, c->stream, P.dIO, c->err)) != FEWHA_OK) return s;
   LaunchArgs a = args(P, c->stream, P.dIO);
-  launch_slopes_in(a, T(P, P.pg), P.pg.n);
+  launch_slopes_in(a, T(P, P.sin), P.sin.n);
   enq_adjoint(P, a, GT_PLAIN, PT_USER);
   return finish(c);
 }
@@ -1572,7 +1578,7 @@ fewha_status fewha_rhs(fewha_ctx* c, const float* slopes, float* b) {
   io[0].out = b;
   if ((s = upload_io(P, io, c->stream, P.dIO, c->err)) != FEWHA_OK) return s;
   LaunchArgs a = args(P, c->stream, P.dIO);
-  launch_slopes_in(a, T(P, P.pg), P.pg.n);
+  launch_slopes_in(a, T(P, P.sin), P.sin.n);
   enq_adjoint(P, a, GT_WEIGHTED, PT_PHIADJ);
   enq_fdwt(P, a, EPI_PLAIN, 0);
   return finish(c);

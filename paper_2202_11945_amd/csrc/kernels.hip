@@ -154,28 +154,50 @@ __device__ __forceinline__ float wave_beta(const ProbDev& pr, int mode, int iter
 struct OutLoad {
   float a;
 };
-__device__ __forceinline__ OutLoad out_fetch(const ProbDev& pr, const IoDev& io, int out_mode, int e) {
+// The output's destinations and constants, read from the problem once per
+// kernel (a store through them could alias the problem record).
+struct OutDst {
+  float* phi;
+  float* out;
+  float* layers_out;
+  float* aprev;  // F = I control update: previous and new commands in the state
+  float* a;
+  float* dm_out;
+  float gain;
+  int mode;  // out_mode, with OUT_FIT split by pr.fitted
+};
+enum { OUTD_PHI, OUTD_USER, OUTD_FITTED, OUTD_CONTROL };
+__device__ __forceinline__ OutDst out_dst(const ProbDev& pr, const IoDev& io, int out_mode) {
+  OutDst d;
+  d.phi = pr.phi;
+  d.out = io.out;
+  d.layers_out = io.layers_out;
+  d.aprev = io.state + 3L * pr.n_c;
+  d.a = d.aprev + pr.n_act;
+  d.dm_out = io.dm_out;
+  d.gain = pr.gain;
+  d.mode = out_mode == OUT_PHI ? OUTD_PHI : out_mode == OUT_USER ? OUTD_USER : pr.fitted ? OUTD_FITTED : OUTD_CONTROL;
+  return d;
+}
+__device__ __forceinline__ OutLoad out_fetch(const OutDst& d, int e) {
   OutLoad o{0.f};
-  if (out_mode == OUT_FIT && !pr.fitted) o.a = ((gptr_f)io.state)[3L * pr.n_c + pr.n_act + e];
+  if (d.mode == OUTD_CONTROL) o.a = ((gptr_f)d.a)[e];
   return o;
 }
-__device__ __forceinline__ void out_finish(const ProbDev& pr, const IoDev& io, int out_mode, int e, float v,
-                                           const OutLoad& o) {
-  if (out_mode == OUT_PHI) {
-    pr.phi[e] = v;
-  } else if (out_mode == OUT_USER) {
-    io.out[e] = v;
-  } else if (pr.fitted) {  // OUT_FIT, DM commands from the fitting step that follows
-    pr.phi[e] = v;
-    if (io.layers_out) io.layers_out[e] = v;
+__device__ __forceinline__ void out_finish(const OutDst& d, int e, float v, const OutLoad& o) {
+  if (d.mode == OUTD_PHI) {
+    d.phi[e] = v;
+  } else if (d.mode == OUTD_USER) {
+    d.out[e] = v;
+  } else if (d.mode == OUTD_FITTED) {  // OUT_FIT, DM commands from the fitting step that follows
+    d.phi[e] = v;
+    if (d.layers_out) d.layers_out[e] = v;
   } else {  // OUT_FIT, F = I
-    if (io.layers_out) io.layers_out[e] = v;
-    float* aprev = io.state + 3L * pr.n_c;
-    float* a = aprev + pr.n_act;
-    const float nw = (1.0f - pr.gain) * o.a + pr.gain * v;
-    aprev[e] = o.a;
-    a[e] = nw;
-    if (io.dm_out) io.dm_out[e] = nw;
+    if (d.layers_out) d.layers_out[e] = v;
+    const float nw = (1.0f - d.gain) * o.a + d.gain * v;
+    d.aprev[e] = o.a;
+    d.a[e] = nw;
+    if (d.dm_out) d.dm_out[e] = nw;
   }
 }
 
@@ -394,17 +416,18 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
   }
   if (direct) return;
   if (n == R) {
+    const OutDst od = out_dst(pr, io, out_mode);
     for (int e0 = threadIdx.x; e0 < R * R; e0 += kU * nt) {
       OutLoad o[kU];
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int e = e0 + u * nt;
-        if (e < R * R) o[u] = out_fetch(pr, io, out_mode, off + e);  // n == R: row-major e
+        if (e < R * R) o[u] = out_fetch(od, off + e);  // n == R: row-major e
       }
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int e = e0 + u * nt;
-        if (e < R * R) out_finish(pr, io, out_mode, off + e, A[(e >> lr) * S + (e & (R - 1))] * ly.inv_delta, o[u]);
+        if (e < R * R) out_finish(od, off + e, A[(e >> lr) * S + (e & (R - 1))] * ly.inv_delta, o[u]);
       }
     }
   } else {
@@ -520,13 +543,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   }
   __syncthreads();
   const bool final_level = (m == n);
+  const OutDst od = out_dst(pr, io, out_mode);
   for (int e0 = threadIdx.x; e0 < kGT * kGT; e0 += kU * nt) {  // rows
     OutLoad o[kU];
     if (final_level) {
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int e = e0 + u * nt;
-        o[u] = out_fetch(pr, io, out_mode, off + (t0 + (e >> 5)) * n + s0 + (e & 31));
+        o[u] = out_fetch(od, off + (t0 + (e >> 5)) * n + s0 + (e & 31));
       }
     }
 #pragma unroll
@@ -539,7 +563,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                         F.g[par] * Br[kGH + k] + F.g[par + 2] * Br[kGH + k - 1] + F.g[par + 4] * Br[kGH + k - 2];
       const int row = t0 + lt, col = s0 + ls;
       if (final_level)
-        out_finish(pr, io, out_mode, off + row * n + col, acc * ly.inv_delta, o[u]);
+        out_finish(od, off + row * n + col, acc * ly.inv_delta, o[u]);
       else
         nxt[row * m + col] = acc;
     }
@@ -844,24 +868,27 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
 }
 
 // ------------------------------------------- propagation + Shack-Hartmann
-// Sums of four values over a workgroup of nw waves, in wave order; result
-// valid in thread 0.  One barrier.
-__device__ __forceinline__ void block_sum4(float a[4], float* sh, int nw) {
+// Sums of K values over a workgroup of nw waves, in wave order (each as
+// block_sum would form it); result valid in thread 0.  One barrier; sh holds
+// K nw floats.
+template <int K>
+__device__ __forceinline__ void block_sumk(float a[K], float* sh, int nw) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) a[k] = wave_sum(a[k]);
+  for (int k = 0; k < K; ++k) a[k] = wave_sum(a[k]);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) sh[4 * w + k] = a[k];
+    for (int k = 0; k < K; ++k) sh[K * w + k] = a[k];
   __syncthreads();
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < K; ++k) {
       float r = 0.f;
-      for (int i = 0; i < nw; ++i) r += sh[4 * i + k];
+      for (int i = 0; i < nw; ++i) r += sh[K * i + k];
       a[k] = r;
     }
 }
+__device__ __forceinline__ void block_sum4(float a[4], float* sh, int nw) { block_sumk<4>(a, sh, nw); }
 
 // Sensor-stage workgroup: 5 waves, one thread per corner (or subaperture) of
 // a 17 x 17 window, the first 256 threads also own one of its 16 x 16 tile.
@@ -1005,42 +1032,72 @@ __global__ __launch_bounds__(kSensThreads) void k_pgamma(const ProbDev* P, const
   }
 }
 
-// compact input slopes -> dense grid + tip/tilt partial sums
+// Compact input slopes -> dense grid, and the tip/tilt partial sums of every
+// 16 x 16 subaperture tile (the tiles of the propagation stage, whose sums
+// the sensor adjoint reads).  A workgroup takes 2 x 2 such tiles, thread t
+// subaperture (t / 16, t mod 16) of each, so all its loads are in flight
+// together; each tile's sums are formed as over a workgroup of its own.
 __global__ __launch_bounds__(256) void k_slopes_in(const ProbDev* P, const WfsDev* WD, const IoDev* IO,
                                                    const Tile* tiles) {
-  __shared__ float sh[16];
+  __shared__ float sh[16 * 4];
+  typedef const int __attribute__((address_space(1)))* gptr_i;
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const WfsDev& w = WD[t.slot];
   const IoDev& io = IO[t.prob];
-  const int N = w.N;
-  const int i = t.ty * kTileS + (threadIdx.x >> 4), j = t.tx * kTileS + (threadIdx.x & 15);
-  float sx = 0.f, sy = 0.f, cx = 0.f, cy = 0.f;
-  if (i < N && j < N) {
-    const int ci = pr.cmap[w.m_off + i * N + j];
-    if (ci >= 0) {
-      sx = io.in[w.cs_off + ci];
-      sy = io.in[w.cs_off + w.n_active + ci];
+  const int N = w.N, ts = w.tiles_side;
+  const int li = threadIdx.x >> 4, lj = threadIdx.x & 15;
+  const gptr_i cmap = (gptr_i)(pr.cmap + w.m_off);
+  const gptr_f in = (gptr_f)io.in;
+  const gptr_f cinv = (gptr_f)(pr.cinv + w.cinv_off);
+  float* sd = pr.sd + w.s_off;
+  const int cs0 = w.cs_off, cs1 = w.cs_off + w.n_active;
+  int pos[4], ci[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = (2 * t.ty + (u >> 1)) * kTileS + li, j = (2 * t.tx + (u & 1)) * kTileS + lj;
+    pos[u] = (i < N && j < N) ? i * N + j : -1;
+    ci[u] = pos[u] >= 0 ? cmap[pos[u]] : -1;
+  }
+  float sx[4], sy[4], c0[4], c1[4], c2[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    sx[u] = sy[u] = c0[u] = c1[u] = c2[u] = 0.f;
+    if (ci[u] >= 0) {
+      sx[u] = in[cs0 + ci[u]];
+      sy[u] = in[cs1 + ci[u]];
       if (w.blocks) {
-        const float* cb = pr.cinv + w.cinv_off + 3 * (i * N + j);
-        cx = cb[0] * sx + cb[1] * sy;
-        cy = cb[1] * sx + cb[2] * sy;
+        c0[u] = cinv[3 * pos[u]];
+        c1[u] = cinv[3 * pos[u] + 1];
+        c2[u] = cinv[3 * pos[u] + 2];
       }
     }
-    pr.sd[w.s_off + i * N + j] = sx;
-    pr.sd[w.s_off + N * N + i * N + j] = sy;
   }
-  const float a0 = block_sum(sx, sh, blockDim.x);
-  const float a1 = block_sum(sy, sh + 4, blockDim.x);
-  const float a2 = block_sum(cx, sh + 8, blockDim.x);
-  const float a3 = block_sum(cy, sh + 12, blockDim.x);
-  if (threadIdx.x == 0) {
-    float* pp = pr.part + w.part_off + 4 * (t.ty * w.tiles_side + t.tx);
-    pp[0] = a0;
-    pp[1] = a1;
-    pp[2] = a2;
-    pp[3] = a3;
+  float a[16];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    a[4 * u] = sx[u];
+    a[4 * u + 1] = sy[u];
+    a[4 * u + 2] = c0[u] * sx[u] + c1[u] * sy[u];
+    a[4 * u + 3] = c1[u] * sx[u] + c2[u] * sy[u];
+    if (pos[u] >= 0) {
+      sd[pos[u]] = sx[u];
+      sd[N * N + pos[u]] = sy[u];
+    }
   }
+  block_sumk<16>(a, sh, 4);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int ty = 2 * t.ty + (u >> 1), tx = 2 * t.tx + (u & 1);
+      if (ty < ts && tx < ts) {
+        float* pp = pr.part + w.part_off + 4 * (ty * ts + tx);
+        pp[0] = a[4 * u];
+        pp[1] = a[4 * u + 1];
+        pp[2] = a[4 * u + 2];
+        pp[3] = a[4 * u + 3];
+      }
+    }
 }
 
 // ------------------------------------- noise weighting + Shack-Hartmann adjoint
