@@ -260,6 +260,22 @@ bool pair_meets_tile(const GLPar& gp, const HatTables& T, int n, int p0, int ph,
   return any(gp.hat_off, p0, ph) && any(gp.hat_off + n, q0, qw);
 }
 
+// Longest first within each XCD's run of a launch's tiles: workgroup b runs
+// on XCD b mod 8 and each XCD takes a contiguous run of the list in order
+// (the device-side mapping), so sorting every run by descending sensor count
+// (Tile::level of a propagation-adjoint tile) starts the longest workgroups
+// first and shortens the tail.  The runs keep their tiles, so what an XCD's
+// L2 holds does not change.
+void sort_xcd_runs_by_count(std::vector<Tile>& v) {
+  const int W = (int)v.size(), q = W / 8, r = W % 8;
+  for (int x = 0; x < 8; ++x) {
+    const int start = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+    const int len = q + (x < r ? 1 : 0);
+    std::stable_sort(v.begin() + start, v.begin() + start + len,
+                     [](const Tile& a, const Tile& b) { return a.level > b.level; });
+  }
+}
+
 // Sensor lists of propagation-adjoint tiles, one copy per distinct list.
 struct PtLists {
   std::vector<PtEnt> ents;
@@ -768,12 +784,14 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   P.pg = add(t_pg);
   P.sin = add(t_sin);
   P.gt = add(t_gt);
+  sort_xcd_runs_by_count(t_pt);
   P.pt = add(t_pt);
   P.upd = add(t_upd);
   for (auto& v : t_idwt_glob) P.idwt_glob.push_back(add(v));
   for (auto& v : t_fdwt_glob) P.fdwt_glob.push_back(add(v));
   P.fit_fwdL = add(t_ffL);
   P.fit_fwdD = add(t_ffD);
+  sort_xcd_runs_by_count(t_fpt);
   P.fit_pt = add(t_fpt);
   P.fit_cg = add(t_fcg);
   P.sinit = add(t_sinit);
