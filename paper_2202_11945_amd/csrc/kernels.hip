@@ -890,10 +890,11 @@ __device__ __forceinline__ void block_sumk(float a[K], float* sh, int nw) {
 }
 __device__ __forceinline__ void block_sum4(float a[4], float* sh, int nw) { block_sumk<4>(a, sh, nw); }
 
-// Sensor-stage workgroup: 5 waves, one thread per corner (or subaperture) of
-// a 17 x 17 window, the first 256 threads also own one of its 16 x 16 tile.
-constexpr int kSensThreads = 320;
-static_assert((kTileS + 1) * (kTileS + 1) <= kSensThreads, "17 x 17 window in one pass");
+// Sensor-stage workgroup: 4 waves, one thread per subaperture of a 16 x 16
+// tile and one or two corners of its 17 x 17 corner window (8 workgroups fit
+// a CU, where 5-wave ones fit 6).
+constexpr int kSensThreads = 256;
+static_assert((kTileS + 1) * (kTileS + 1) <= 2 * kSensThreads, "17 x 17 window in two corners per thread");
 
 // Tile of 16x16 subapertures of one sensor: v on the 17x17 corners is the
 // sum over layers of the bilinear interpolant (LGS cone factor in the
@@ -901,7 +902,7 @@ static_assert((kTileS + 1) * (kTileS + 1) <= kSensThreads, "17 x 17 window in on
 // operands are requested first; the layers go in groups of four (all table
 // loads of a group, then all node loads), so a corner waits on two memory
 // round trips per four layers.
-__global__ __launch_bounds__(kSensThreads) void k_pgamma(const ProbDev* P, const LayerDev* LD, const WfsDev* WD,
+__global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_pgamma(const ProbDev* P, const LayerDev* LD, const WfsDev* WD,
                                                          const IoDev* IO, const Tile* tiles, int mode) {
   constexpr int CW = kTileS + 1;
   __shared__ float V[CW * CW];
@@ -934,64 +935,86 @@ __global__ __launch_bounds__(kSensThreads) void k_pgamma(const ProbDev* P, const
       cb2 = cb[2];
     }
   }
-  // corners
-  const int e = threadIdx.x;
-  if (e < CW * CW) {
+  // corners: thread t takes window corners t and t + 256 (the second only for
+  // t < 33); the loads of both go out together.  Raw buffer loads: lane
+  // offsets from the corner (ic, jc) and the cell, wave-uniform offsets from
+  // the layer, so no per-load address arithmetic (no range limit: the tables
+  // and cells are valid by construction).
+  constexpr int kCorn = (CW * CW + kSensThreads - 1) / kSensThreads;
+  int vi[kCorn], vj[kCorn];
+  bool cin[kCorn];
+#pragma unroll
+  for (int u = 0; u < kCorn; ++u) {
+    const int e = threadIdx.x + u * kSensThreads;
     const int lci = e / CW, lcj = e - lci * CW;
     const int ic = i0 + lci, jc = j0 + lcj;
-    float v = 0.f;
-    if (ic < nc && jc < nc) {
-      // raw buffer loads: lane offsets from the corner (ic, jc) and the cell,
-      // wave-uniform offsets from the layer, so no per-load address arithmetic
-      // (no range limit: the tables and cells are valid by construction)
-      const __amdgpu_buffer_rsrc_t irs =
-          __builtin_amdgcn_make_buffer_rsrc((void*)(pr.itab + w.tab_off), (short)0, 0x7fffffff, 0x00020000);
-      const __amdgpu_buffer_rsrc_t frs =
-          __builtin_amdgcn_make_buffer_rsrc((void*)(pr.ftab + w.tab_off), (short)0, 0x7fffffff, 0x00020000);
-      const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc((void*)phi, (short)0, 0x7fffffff, 0x00020000);
-      const int vi = ic * (int)sizeof(float), vj = jc * (int)sizeof(float);
-      auto ld = [](__amdgpu_buffer_rsrc_t rs, int vo, int so) {  // so: wave-uniform (stated, or the
-        return __builtin_amdgcn_raw_buffer_load_b32(rs, vo, __builtin_amdgcn_readfirstlane(so), 0);  // load loops)
-      };
-      for (int l0 = 0; l0 < pr.L; l0 += 4) {
-        int cell[4], nl[4];
-        float wy[4], wx[4];
+    cin[u] = e < CW * CW && ic < nc && jc < nc;
+    vi[u] = ic * (int)sizeof(float);
+    vj[u] = jc * (int)sizeof(float);
+  }
+  const __amdgpu_buffer_rsrc_t irs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(pr.itab + w.tab_off), (short)0, 0x7fffffff, 0x00020000);
+  const __amdgpu_buffer_rsrc_t frs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(pr.ftab + w.tab_off), (short)0, 0x7fffffff, 0x00020000);
+  const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc((void*)phi, (short)0, 0x7fffffff, 0x00020000);
+  auto ld = [](__amdgpu_buffer_rsrc_t rs, int vo, int so) {  // so: wave-uniform (stated, or the
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, vo, __builtin_amdgcn_readfirstlane(so), 0);  // load loops)
+  };
+  float v[kCorn];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          cell[k] = nl[k] = 0;
-          wy[k] = wx[k] = 0.f;
-          const int l = l0 + k;
-          if (l < pr.L) {
-            const LayerDev& ly = LD[t.mask + l];
-            const int tb = l * w.tab_stride * (int)sizeof(float);
-            nl[k] = ly.n;
-            cell[k] = ly.off + (int)ld(irs, vi, tb) * ly.n + (int)ld(irs, vj, tb + nc * (int)sizeof(float));
-            wy[k] = __uint_as_float(ld(frs, vi, tb + 2 * nc * (int)sizeof(float)));
-            wx[k] = __uint_as_float(ld(frs, vj, tb + 3 * nc * (int)sizeof(float)));
-          }
-        }
-        float nd[4][4];
+  for (int u = 0; u < kCorn; ++u) v[u] = 0.f;
+  for (int l0 = 0; l0 < pr.L; l0 += 4) {
+    int lof[4], nl[4], tb[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          nd[k][0] = nd[k][1] = nd[k][2] = nd[k][3] = 0.f;
-          if (l0 + k < pr.L) {
-            const int vo = cell[k] * (int)sizeof(float), so = nl[k] * (int)sizeof(float);
-            nd[k][0] = __uint_as_float(ld(prs, vo, 0));
-            nd[k][1] = __uint_as_float(ld(prs, vo + (int)sizeof(float), 0));
-            nd[k][2] = __uint_as_float(ld(prs, vo, so));
-            nd[k][3] = __uint_as_float(ld(prs, vo + (int)sizeof(float), so));
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if (l0 + k < pr.L) {
-            const float top = (1.f - wx[k]) * nd[k][0] + wx[k] * nd[k][1];
-            const float bot = (1.f - wx[k]) * nd[k][2] + wx[k] * nd[k][3];
-            v += (1.f - wy[k]) * top + wy[k] * bot;
-          }
-      }
+    for (int k = 0; k < 4; ++k) {
+      const int l = min(l0 + k, pr.L - 1);
+      const LayerDev& ly = LD[t.mask + l];
+      lof[k] = ly.off;
+      nl[k] = ly.n;
+      tb[k] = l * w.tab_stride * (int)sizeof(float);
     }
-    V[e] = v;
+    int cell[kCorn][4];
+    float wy[kCorn][4], wx[kCorn][4];
+#pragma unroll
+    for (int u = 0; u < kCorn; ++u)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        cell[u][k] = 0;
+        wy[u][k] = wx[u][k] = 0.f;
+        if (cin[u] && l0 + k < pr.L) {
+          cell[u][k] = lof[k] + (int)ld(irs, vi[u], tb[k]) * nl[k] + (int)ld(irs, vj[u], tb[k] + nc * (int)sizeof(float));
+          wy[u][k] = __uint_as_float(ld(frs, vi[u], tb[k] + 2 * nc * (int)sizeof(float)));
+          wx[u][k] = __uint_as_float(ld(frs, vj[u], tb[k] + 3 * nc * (int)sizeof(float)));
+        }
+      }
+    float nd[kCorn][4][4];
+#pragma unroll
+    for (int u = 0; u < kCorn; ++u)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        nd[u][k][0] = nd[u][k][1] = nd[u][k][2] = nd[u][k][3] = 0.f;
+        if (cin[u] && l0 + k < pr.L) {
+          const int vo = cell[u][k] * (int)sizeof(float), so = nl[k] * (int)sizeof(float);
+          nd[u][k][0] = __uint_as_float(ld(prs, vo, 0));
+          nd[u][k][1] = __uint_as_float(ld(prs, vo + (int)sizeof(float), 0));
+          nd[u][k][2] = __uint_as_float(ld(prs, vo, so));
+          nd[u][k][3] = __uint_as_float(ld(prs, vo + (int)sizeof(float), so));
+        }
+      }
+#pragma unroll
+    for (int u = 0; u < kCorn; ++u)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (cin[u] && l0 + k < pr.L) {
+          const float top = (1.f - wx[u][k]) * nd[u][k][0] + wx[u][k] * nd[u][k][1];
+          const float bot = (1.f - wx[u][k]) * nd[u][k][2] + wx[u][k] * nd[u][k][3];
+          v[u] += (1.f - wy[u][k]) * top + wy[u][k] * bot;
+        }
+  }
+#pragma unroll
+  for (int u = 0; u < kCorn; ++u) {
+    const int e = threadIdx.x + u * kSensThreads;
+    if (e < CW * CW) V[e] = v[u];
   }
   __syncthreads();
   float sx = 0.f, sy = 0.f, cx = 0.f, cy = 0.f;
