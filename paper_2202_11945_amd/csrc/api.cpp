@@ -67,6 +67,7 @@ struct Plan {
   Range sinit, gprior, ghgt;                 // solve start, parameter-gradient reductions
   Range r64wfs;                              // FP64 residual: one tile per (problem, sensor)
   Range r64pt;                               // FP64 residual: 32x32 node tiles of the adjoint
+  Range r64gt;                               // FP64 residual: 16x16 corner tiles of the sensor adjoint
   std::vector<Range> r64inv, r64fwd;         // FP64 residual: transform steps
   Resid64Tiles r64;
   Filter64 F64{};
@@ -364,7 +365,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   };
   std::vector<ProbLayout> lay(P.nprob);
   Carver cv;
-  std::vector<Tile> t_sin;
+  std::vector<Tile> t_sin, t_r64gt;
   std::vector<Tile> t_idwt_res, t_fdwt_res, t_pg, t_gt, t_pt, t_upd, t_sinit, t_gprior, t_ghgt, t_r64wfs, t_r64pt;
   HatTables hats;  // hat tables and band records of every problem and fitting view, one set per plan
   PtLists ptl;     // sensor lists of the propagation-adjoint tiles
@@ -582,6 +583,9 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
       const int tc = cdiv(wd.nc, kGtS);
       for (int ty = 0; ty < tc; ++ty)
         for (int tx = 0; tx < tc; ++tx) t_gt.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
+      const int tc16 = cdiv(wd.nc, kTileS);
+      for (int ty = 0; ty < tc16; ++ty)
+        for (int tx = 0; tx < tc16; ++tx) t_r64gt.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
     }
     // node tiles of the propagation adjoint (kPtH rows x kPtW columns) with the
     // sensors that add to them; 32x32 tiles for the FP64 residual's adjoint
@@ -799,6 +803,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   P.ghgt = add(t_ghgt);
   P.r64wfs = add(t_r64wfs);
   P.r64pt = add(t_r64pt);
+  P.r64gt = add(t_r64gt);
   for (int st = 0; st < kMaxLevelsJ; ++st) {
     P.r64inv.push_back(add(t_r64inv[st]));
     P.r64fwd.push_back(add(t_r64fwd[st]));
@@ -941,8 +946,8 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     rt.pg_n = P.pg.n;
     rt.wfs = P.dT + P.r64wfs.off;
     rt.wfs_n = P.r64wfs.n;
-    rt.gt = P.dT + P.gt.off;
-    rt.gt_n = P.gt.n;
+    rt.gt = P.dT + P.r64gt.off;  // the FP64 sensor adjoint's own 16 x 16 corner tiles
+    rt.gt_n = P.r64gt.n;
     rt.pt = P.dT + P.r64pt.off;
     rt.pt_n = P.r64pt.n;
   }
