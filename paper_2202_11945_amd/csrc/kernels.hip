@@ -266,12 +266,13 @@ constexpr int kUG = 6; // ... for the 36 x 36 windows of the global transform le
 //   x_t = sum_{i = t mod 2} h_i a[(t-i)/2] + g_i d[(t-i)/2]   (indices mod half)
 // Consecutive output pairs share four of their six taps, so the NP + 2 taps
 // of each half are read once into registers.  Only the taps K0 - 2 and
-// K0 - 1 can wrap (K0 + NP <= half); the others are read at fixed offsets
-// from the line position (the stride S is a compile-time constant).
+// K0 - 1 can wrap (K0 + NP <= half; with half = 1 or 2 they wrap more than
+// once, hence the mask); the others are read at fixed offsets from the line
+// position (the stride S is a compile-time constant).
 template <int NP, int S>
 __device__ __forceinline__ void syn_line(const float* src, int half, int K0, const Filter& F, float* dst) {
   float a[NP + 2], d[NP + 2];
-  const int i0 = K0 >= 2 ? K0 - 2 : K0 - 2 + half, i1 = K0 >= 1 ? K0 - 1 : K0 - 1 + half;
+  const int i0 = (K0 - 2) & (half - 1), i1 = (K0 - 1) & (half - 1);
   a[0] = src[i0 * S];
   d[0] = src[(half + i0) * S];
   a[1] = src[i1 * S];

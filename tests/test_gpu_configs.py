@@ -90,6 +90,35 @@ def test_more_than_63_sensors_per_tile_is_refused(gpu_lib):
     assert e.value.status == -1
 
 
+def _small_grids(levels0):
+    """Coarse layers (8 x 8 with `levels0` levels, 16 x 16) under three NGS of
+    4 x 4, 5 x 5 and 10 x 10 subapertures: corner grids smaller than the
+    propagation adjoint's 6- or 9-row band, K = 3 sensors whose band records
+    fall back to dense sums near the grid edges, and a pair sampling a layer
+    finer than 2/3 of its spacing (general gather)."""
+    from synthetic.configs import ARCSEC, _ngs
+    cfg = get_config("tiny")
+    cfg["layers"] = [{"h": 0.0, "n": 8, "levels": levels0, "cn2": 0.8},
+                     {"h": 6000.0, "n": 16, "levels": 2, "cn2": 0.2}]
+    cfg["wfs"] = [_ngs((0.0, 0.0), 4, 0.1), _ngs((20 * ARCSEC, -10 * ARCSEC), 5, 0.1),
+                  _ngs((-15 * ARCSEC, 25 * ARCSEC), 10, 0.1)]
+    return cfg
+
+
+def test_small_grids_and_single_node_coarse_block(gpu_lib):
+    # operators down to a 1 x 1 coarsest block (synthesis lines of half
+    # length 1); the frame on a 2 x 2 one: a 1 x 1 coarsest coefficient is
+    # the layer's piston, which no slope sees, so its Jacobi entry is the
+    # prior's alone (1.7e-4 against about 10 for the rest) and ten FP32
+    # iterations amplify rounding in that one mode beyond the frame tolerance
+    cfg = _small_grids(3)
+    _ops(gpu_lib, system("small_grids_3", cfg), cfg, 6)
+    cfg = _small_grids(2)
+    S = system("small_grids_2", cfg)
+    ctx = _ops(gpu_lib, S, cfg, 7)
+    _check_frame(gpu_lib, S, ctx, np.zeros(5 * S.geom.n_coeff, np.float32), synth_slopes(S, 0))
+
+
 def test_large_nine_layers_with_elongation(gpu_lib):
     # the frame with F = I (the fitted frame of this system is covered with the fitting tests)
     cfg = get_config("large")
