@@ -22,15 +22,44 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef const v4f __attribute__((address_space(1)))* gptr_f4;
 typedef v4f __attribute__((address_space(1)))* gptr_w4;
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Wave sums by DPP moves inside the vector ALU (no LDS crossbar round
+// trips): pair and quad swaps, the half-row and row mirrors give every lane
+// its 16-lane row sum; row_bcast:15 and row_bcast:31 then carry rows 0-2
+// into row 3, and lane 63's total is returned to every lane.  Every lane of
+// the wave must be active (the moves read the source lanes whatever the
+// exec mask).  Fixed order: ((R3 + R2) + (R1 + R0)) of the row sums.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
 }
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140, kDppBcast15 = 0x142,
+              kDppBcast31 = 0x143;
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_f<kDppXor1, 0xF>(v);
+  v += dpp_f<kDppXor2, 0xF>(v);
+  v += dpp_f<kDppHalfMirror, 0xF>(v);
+  v += dpp_f<kDppMirror, 0xF>(v);
+  v += dpp_f<kDppBcast15, 0xA>(v);
+  v += dpp_f<kDppBcast31, 0xC>(v);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<kDppXor1, 0xF>(v);
+  v += dpp_d<kDppXor2, 0xF>(v);
+  v += dpp_d<kDppHalfMirror, 0xF>(v);
+  v += dpp_d<kDppMirror, 0xF>(v);
+  v += dpp_d<kDppBcast15, 0xA>(v);
+  v += dpp_d<kDppBcast31, 0xC>(v);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 __device__ __forceinline__ int wave_min(int v) {
 #pragma unroll
