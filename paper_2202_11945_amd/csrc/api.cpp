@@ -525,15 +525,17 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
         const int mf = ld.n >> s;  // forward: input side
         const int tq = (mf / 2) / 16;
         for (int ty = 0; ty < tq; ++ty)
-          for (int tx = 0; tx < tq; ++tx) t_fdwt_glob[s].push_back({k, l, ty, tx, slot++, ilog2i(mf), 0, 0});
+          for (int tx = 0; tx < tq; ++tx) t_fdwt_glob[s].push_back({k, l, ty, tx, slot++, ilog2i(mf), pd.layer0 + l, 0});
         const int mi = ld.res << (s + 1);  // inverse: output side
         const int ti = mi / 32;
         for (int ty = 0; ty < ti; ++ty)
-          for (int tx = 0; tx < ti; ++tx) t_idwt_glob[s].push_back({k, l, ty, tx, 0, ilog2i(mi), 0, 0});
+          for (int tx = 0; tx < ti; ++tx) t_idwt_glob[s].push_back({k, l, ty, tx, 0, ilog2i(mi), pd.layer0 + l, 0});
       }
     for (int l = 0; l < L; ++l) {
-      t_idwt_res.push_back({k, l, 0, 0, 0, 0, 0, 0});
-      t_fdwt_res.push_back({k, l, 0, 0, slot++, 0, 0, 0});
+      // transform tiles carry the global layer index (mask), so that the
+      // layer and problem records load in parallel
+      t_idwt_res.push_back({k, l, 0, 0, 0, 0, pd.layer0 + l, 0});
+      t_fdwt_res.push_back({k, l, 0, 0, slot++, 0, pd.layer0 + l, 0});
     }
     pd.n_slots_fdwt = slot;
     const int nupd = cdiv(pd.n_c, kUpdChunk);

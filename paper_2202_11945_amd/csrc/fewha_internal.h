@@ -225,15 +225,14 @@ struct IoDev {
   const float* rg;     // FP64 residual: layer-domain term of the right-hand side W^{-T} g (or NULL)
 };
 
-// Work-list entry of a tiled stage: problem, item (layer or sensor), tile
-// row/column, and the slot of the partial it produces.  For the propagation
-// adjoint, mask has bit g set when sensor g's footprint can reach the tile
-// (all bits when the problem has more than 32 sensors).
-// Work item of a tiled launch.  Propagation-adjoint tiles use slot / level
-// for their sensor list (offset, count) and mask / pad1 for the layer's side
-// and offset; the sensor-stage tiles carry the sensor's descriptor index in
-// slot and the problem's first layer descriptor in mask (so that those loads
-// need not wait for the problem's descriptor).
+// Work item of a tiled launch: problem, item (layer or sensor), tile
+// row/column, and the slot of the partial it produces.  Some kinds carry
+// more, so that their descriptor loads need not wait for the problem's:
+// propagation-adjoint tiles use slot / level for their sensor list (offset,
+// count) and mask / pad1 for the layer's side and offset; the sensor-stage
+// tiles carry the sensor's descriptor index in slot and the problem's first
+// layer descriptor in mask; the transform tiles carry their layer's
+// descriptor index in mask (and the global levels their level in level).
 struct Tile {
   int prob, item, ty, tx;
   int slot, level, mask, pad1;

@@ -399,7 +399,7 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
   __shared__ float B[RMAX * (RMAX + 1)];
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
-  const LayerDev& ly = LD[pr.layer0 + t.item];
+  const LayerDev& ly = LD[t.mask];  // the global layer index, carried by the tile
   const IoDev& io = IO[t.prob];
   PSrc ps = make_psrc(pr, io, src_mode, iter, 0.f);
   const int n = ly.n, R = ly.res, lr = __builtin_ctz(R);
@@ -506,7 +506,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   __shared__ float B[kGT * (kGW + 1)];
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
-  const LayerDev& ly = LD[pr.layer0 + t.item];
+  const LayerDev& ly = LD[t.mask];  // the global layer index, carried by the tile
   const IoDev& io = IO[t.prob];
   PSrc ps = make_psrc(pr, io, src_mode, iter, 0.f);
   const int n = ly.n, off = ly.off;
@@ -613,7 +613,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   __shared__ double sh[4];
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
-  const LayerDev& ly = LD[pr.layer0 + t.item];
+  const LayerDev& ly = LD[t.mask];  // the global layer index, carried by the tile
   const IoDev& io = IO[t.prob];
   const int n = ly.n, off = ly.off;
   const int m = 1 << t.level, half = m >> 1;
@@ -841,7 +841,7 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
   __shared__ double sh[16];
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
-  const LayerDev& ly = LD[pr.layer0 + t.item];
+  const LayerDev& ly = LD[t.mask];  // the global layer index, carried by the tile
   const IoDev& io = IO[t.prob];
   const int n = ly.n, R = ly.res, lr = __builtin_ctz(R), off = ly.off;
   constexpr int S = RMAX + 1;
