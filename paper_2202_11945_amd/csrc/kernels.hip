@@ -21,6 +21,12 @@ typedef const float __attribute__((address_space(1)))* gptr_f;
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef const v4f __attribute__((address_space(1)))* gptr_f4;
 typedef v4f __attribute__((address_space(1)))* gptr_w4;
+// Stores and FP64 accesses likewise.  A flat access also counts against the
+// LDS / scalar-load wait counter, so a later LDS wait or barrier would wait
+// for it to reach memory.
+typedef float __attribute__((address_space(1)))* gptr_w;
+typedef const double __attribute__((address_space(1)))* gptr_d;
+typedef double __attribute__((address_space(1)))* gptr_wd;
 
 // Wave sums by DPP moves inside the vector ALU (no LDS crossbar round
 // trips): pair and quad swaps, the half-row and row mirrors give every lane
@@ -81,7 +87,7 @@ __device__ __forceinline__ T block_sum(T v, T* sh, int nthreads) {
 // every workgroup that sums the same slots.
 __device__ __forceinline__ double wave_sum_slots(const double* s, int n) {
   double a = 0.0;
-  for (int i = threadIdx.x & 63; i < n; i += 64) a += s[i];
+  for (int i = threadIdx.x & 63; i < n; i += 64) a += ((gptr_d)s)[i];
   return wave_sum(a);
 }
 
@@ -154,7 +160,7 @@ __device__ __forceinline__ float coef_finish(const PSrc& s, int e, const CoefLoa
   if (s.mode == SRC_IN || s.mode == SRC_STATE_C) return v.a;
   const float z = v.a * v.b;
   const float p = (s.mode == SRC_PUPD0) ? z : fmaf(s.beta, v.c, z);
-  if (owner) s.pnew[e] = p;
+  if (owner) ((gptr_w)s.pnew)[e] = p;
   return p;
 }
 
@@ -176,24 +182,24 @@ struct OutLoad {
 // The output's destinations and constants, read from the problem once per
 // kernel (a store through them could alias the problem record).
 struct OutDst {
-  float* phi;
-  float* out;
-  float* layers_out;
-  float* aprev;  // F = I control update: previous and new commands in the state
-  float* a;
-  float* dm_out;
+  gptr_w phi;
+  gptr_w out;
+  gptr_w layers_out;
+  gptr_w aprev;  // F = I control update: previous and new commands in the state
+  gptr_w a;
+  gptr_w dm_out;
   float gain;
   int mode;  // out_mode, with OUT_FIT split by pr.fitted
 };
 enum { OUTD_PHI, OUTD_USER, OUTD_FITTED, OUTD_CONTROL };
 __device__ __forceinline__ OutDst out_dst(const ProbDev& pr, const IoDev& io, int out_mode) {
   OutDst d;
-  d.phi = pr.phi;
-  d.out = io.out;
-  d.layers_out = io.layers_out;
-  d.aprev = io.state + 3L * pr.n_c;
+  d.phi = (gptr_w)pr.phi;
+  d.out = (gptr_w)io.out;
+  d.layers_out = (gptr_w)io.layers_out;
+  d.aprev = (gptr_w)(io.state + 3L * pr.n_c);
   d.a = d.aprev + pr.n_act;
-  d.dm_out = io.dm_out;
+  d.dm_out = (gptr_w)io.dm_out;
   d.gain = pr.gain;
   d.mode = out_mode == OUT_PHI ? OUTD_PHI : out_mode == OUT_USER ? OUTD_USER : pr.fitted ? OUTD_FITTED : OUTD_CONTROL;
   return d;
@@ -247,13 +253,13 @@ __device__ __forceinline__ EpiLoad epi_fetch(const ProbDev& pr, const IoDev& io,
 // every output would reload them after every store); ad = alpha D of the
 // output's level, likewise passed in.
 struct EpiDst {
-  float* q;    // EPI_PCG
-  float* out;  // EPI_APPLYM, EPI_PLAIN
-  float* b;    // EPI_RHS: b' and r0 in the state
-  float* r;
+  gptr_w q;    // EPI_PCG
+  gptr_w out;  // EPI_APPLYM, EPI_PLAIN
+  gptr_w b;    // EPI_RHS: b' and r0 in the state
+  gptr_w r;
 };
 __device__ __forceinline__ EpiDst epi_dst(const ProbDev& pr, const IoDev& io) {
-  return EpiDst{pr.q, io.out, io.state + pr.n_c, io.state + 2L * pr.n_c};
+  return EpiDst{(gptr_w)pr.q, (gptr_w)io.out, (gptr_w)(io.state + pr.n_c), (gptr_w)(io.state + 2L * pr.n_c)};
 }
 __device__ __forceinline__ void epi_finish(const EpiDst& dst, int epi, int e, float ad, float v, const EpiLoad& l,
                                            double& acc) {
@@ -451,7 +457,7 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
       }
     }
   } else {
-    float* dst = pr.tmpa + ly.tmp_off;
+    const gptr_w dst = (gptr_w)(pr.tmpa + ly.tmp_off);
     for (int e = threadIdx.x; e < R * R; e += nt) dst[e] = A[(e >> lr) * S + (e & (R - 1))];
   }
 }
@@ -503,7 +509,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   const int m = 1 << t.level, half = m >> 1;
   const int t0 = t.ty * kGT, s0 = t.tx * kGT;
   const gptr_f ll = (gptr_f)(((step & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off);  // stride half
-  float* nxt = ((step & 1) ? pr.tmpa : pr.tmpb) + ly.tmp_off;       // stride m
+  const gptr_w nxt = (gptr_w)(((step & 1) ? pr.tmpa : pr.tmpb) + ly.tmp_off);  // stride m
   const int kr0 = (t0 >> 1) - 2, kc0 = (s0 >> 1) - 2;
   const int W1 = kGW + 1;
   const int nt = blockDim.x;
@@ -609,7 +615,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   const int m = 1 << t.level, half = m >> 1;
   const gptr_f in = (gptr_f)((step == 0) ? pr.phiadj + off : (((step & 1) ? pr.tmpa : pr.tmpb) + ly.tmp_off));
   const int istride = (step == 0) ? n : m;
-  float* llout = ((step & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off;  // stride half
+  const gptr_w llout = (gptr_w)(((step & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off);  // stride half
   const int k0 = t.ty * kFT, l0 = t.tx * kFT;
   const int XW = kFW + 1, RW = 2 * kFT + 1;
   const int nt = blockDim.x;
@@ -696,7 +702,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   }
   if (epi == EPI_PCG || epi == EPI_RHS) {
     const double s = block_sum(acc, sh, nt);
-    if (threadIdx.x == 0) pr.dots[(long)dot_group_of(epi, iter) * pr.n_dots + t.slot] = s;
+    if (threadIdx.x == 0) ((gptr_wd)pr.dots)[(long)dot_group_of(epi, iter) * pr.n_dots + t.slot] = s;
   }
 }
 
@@ -883,7 +889,7 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
   }
   if (EPI == EPI_PCG || EPI == EPI_RHS) {
     const double s = block_sum(acc, sh, nt);
-    if (threadIdx.x == 0) pr.dots[(long)dot_group_of(EPI, iter) * pr.n_dots + t.slot] = s;
+    if (threadIdx.x == 0) ((gptr_wd)pr.dots)[(long)dot_group_of(EPI, iter) * pr.n_dots + t.slot] = s;
   }
 }
 
@@ -1055,19 +1061,19 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
   }
   if (mode == PG_COMPACT) {
     if (act) {
-      io.out[w.cs_off + ci] = sx;
-      io.out[w.cs_off + w.n_active + ci] = sy;
+      ((gptr_w)io.out)[w.cs_off + ci] = sx;
+      ((gptr_w)io.out)[w.cs_off + w.n_active + ci] = sy;
     }
     return;
   }
   if (own) {
-    pr.sd[w.s_off + i * N + j] = sx;
-    pr.sd[w.s_off + N * N + i * N + j] = sy;
+    ((gptr_w)pr.sd)[w.s_off + i * N + j] = sx;
+    ((gptr_w)pr.sd)[w.s_off + N * N + i * N + j] = sy;
   }
   float a[4] = {sx, sy, cx, cy};
   block_sum4(a, sh, kSensThreads / 64);
   if (threadIdx.x == 0) {
-    float* pp = pr.part + w.part_off + 4 * (t.ty * w.tiles_side + t.tx);
+    const gptr_w pp = (gptr_w)(pr.part + w.part_off + 4 * (t.ty * w.tiles_side + t.tx));
     pp[0] = a[0];
     pp[1] = a[1];
     pp[2] = a[2];
@@ -1093,7 +1099,7 @@ __global__ __launch_bounds__(256) void k_slopes_in(const ProbDev* P, const WfsDe
   const gptr_i cmap = (gptr_i)(pr.cmap + w.m_off);
   const gptr_f in = (gptr_f)io.in;
   const gptr_f cinv = (gptr_f)(pr.cinv + w.cinv_off);
-  float* sd = pr.sd + w.s_off;
+  const gptr_w sd = (gptr_w)(pr.sd + w.s_off);
   const int cs0 = w.cs_off, cs1 = w.cs_off + w.n_active;
   int pos[4], ci[4];
 #pragma unroll
@@ -1134,7 +1140,7 @@ __global__ __launch_bounds__(256) void k_slopes_in(const ProbDev* P, const WfsDe
     for (int u = 0; u < 4; ++u) {
       const int ty = 2 * t.ty + (u >> 1), tx = 2 * t.tx + (u & 1);
       if (ty < ts && tx < ts) {
-        float* pp = pr.part + w.part_off + 4 * (ty * ts + tx);
+        const gptr_w pp = (gptr_w)(pr.part + w.part_off + 4 * (ty * ts + tx));
         pp[0] = a[4 * u];
         pp[1] = a[4 * u + 1];
         pp[2] = a[4 * u + 2];
@@ -1251,7 +1257,7 @@ __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* 
       const float ya = YY[li * SW + lj], yb = YY[li * SW + lj + 1];
       const float yc = YY[(li + 1) * SW + lj], yd = YY[(li + 1) * SW + lj + 1];
       const float v = 0.5f * ((xc - xd) + (xa - xb)) + 0.5f * ((ya + yb) - (yc + yd));
-      pr.vadj[w.v_off + i * nc + j] = v;
+      ((gptr_w)pr.vadj)[w.v_off + i * nc + j] = v;
     }
   }
 }
@@ -1515,7 +1521,7 @@ __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD
     hd = hdn;
   }
   const IoDev& io = IO[t.prob];
-  float* dst = (mode == PT_USER) ? io.out : pr.phiadj;
+  const gptr_w dst = (gptr_w)((mode == PT_USER) ? io.out : pr.phiadj);
 #pragma unroll
   for (int u = 0; u < RPT; ++u) {
     const int p = p0 + u;
@@ -1579,7 +1585,7 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
     }
   }
   const double s = block_sum(acc, sh, blockDim.x);
-  if (threadIdx.x == 0) pr.dots[(long)rho_grp(iter + 1) * pr.n_dots + t.slot] = s;
+  if (threadIdx.x == 0) ((gptr_wd)pr.dots)[(long)rho_grp(iter + 1) * pr.n_dots + t.slot] = s;
 }
 
 // ------------------------------------------------- PCG run to a tolerance
