@@ -1,0 +1,58 @@
+"""bench.py's host-side contract (no GPU): the multi-GPU refusal, the
+algorithmic bytes the roofline divides by, and the rule that a measured
+traffic figure is reported only for the kernel sources and launch shapes it
+was taken on."""
+
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from synthetic import get_config  # noqa: E402
+
+
+def _maory_bytes():
+    cfg = get_config("maory_like")
+    n_sd = sum(2 * w["n_subap"] ** 2 for w in cfg["wfs"])
+    n_cor = sum((w["n_subap"] + 1) ** 2 for w in cfg["wfs"])
+    return cfg, bench.algorithmic_bytes(cfg, n_sd, n_cor)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_algorithmic_bytes_of_the_maory_like_problem():
+    cfg, alg = _maory_bytes()
+    assert set(alg) == set(bench.STAGES)
+    n_c = sum(l["n"] ** 2 for l in cfg["layers"])
+    assert n_c == 98304
+    # P_T reads every corner value once and writes every node once (FP32)
+    assert alg["P_T"] == 4 * (39393 + n_c) == 550788
+    # the update reads p, q, x, r, J^{-1} and writes x, r
+    assert alg["UPDATE"] == 4 * 7 * n_c
+    assert all(v > 0 for v in alg.values())
+
+
+def test_traffic_only_for_matching_sources_and_shapes():
+    prof = os.path.join(ROOT, "profiles", "stages_maory_like_b32_bytes.md")
+    if not os.path.exists(prof):
+        pytest.skip("no committed traffic summary")
+    tune = {"dwt_resident": 128, "pt_rows": 4}
+    rows = [l.split() for l in open(prof) if l.split()[:1] == ["TRAFFIC"]]
+    assert {r[1] for r in rows} == set(bench.STAGES)
+    got = bench.measured_traffic("P_T", 32, tune)
+    expected = [float(r[3]) for r in rows if r[1] == "P_T" and r[5] == "128/4"]
+    # the summary is taken on the committed kernel sources: then it is reported
+    assert got is None or [got] == expected
+    # other launch shapes or batch sizes never borrow it
+    assert bench.measured_traffic("P_T", 32, {"dwt_resident": 64, "pt_rows": 8}) is None
+    assert bench.measured_traffic("P_T", 48, tune) is None
