@@ -223,6 +223,35 @@ def test_batch_matches_single_bitwise(gpu_lib, systems):
         assert torch.equal(a, b)
 
 
+def test_timed_launch_matches_single_bitwise(gpu_lib, systems):
+    # the launch bench.py times: 32 MAORY-like problems in one batch, resident
+    # side 128, 4 node rows per thread, one graph replay per frame; every
+    # problem's state and layers equal its own single-context frame (those
+    # are checked against the oracle above)
+    import torch
+    S = systems("maory_like")
+    ctxs = [gpu_lib.Context(get_config("maory_like"), device=0) for _ in range(32)]
+    slopes = [to_dev(synth_slopes(S, k)) for k in range(32)]
+    states = [torch.zeros(5 * S.geom.n_coeff, device="cuda") for _ in range(32)]
+    singles = [s.clone() for s in states]
+    lay_single = [torch.empty(S.geom.n_coeff, device="cuda") for _ in range(32)]
+    for c, s, st, ly in zip(ctxs, slopes, singles, lay_single):
+        c.reconstruct(s, st, ly, iters=4)
+    batch = gpu_lib.Batch(ctxs, tuning={"dwt_resident": 128, "pt_rows": 4})
+    try:
+        bst = [s.clone() for s in states]
+        lay_b = [torch.empty(S.geom.n_coeff, device="cuda") for _ in range(32)]
+        batch.reconstruct(slopes, bst, lay_b, iters=4, use_graph=True)
+        torch.cuda.synchronize()
+        for k in range(32):
+            assert torch.equal(singles[k], bst[k]), k
+            assert torch.equal(lay_single[k], lay_b[k]), k
+    finally:
+        batch.close()
+        for c in ctxs:
+            c.close()
+
+
 def test_graph_replay_matches_direct_bitwise(gpu_lib, systems):
     import torch
     names = ["small", "mid"]
