@@ -9,6 +9,10 @@ Readings:
   specified in the paper (it cites another paper for it); the step uses the
   warm restart only: initial guess c^(i), r_0 = (b^(i+1) - b^(i)) + r^(i).
 * r^(i) is the final recurrence residual of the previous step.
+* A residual that vanishes exactly (a zero right-hand side) gives p = 0 and
+  p^T M p = 0: the step then keeps the iterate (alpha = 0, and beta = 0 when
+  the previous rho is 0), i.e. CG stops at the exact solution instead of
+  dividing 0 by 0.
 * Open loop, a^(i+1) = (1 - gain) a^(i) + gain * F W^{-1} c^(i+1), F = I when
   the reconstruction layers sit at the DM altitudes.
 """
@@ -31,13 +35,13 @@ def pcg(apply_M, x0, r0, Jdiag, iters, record=None):
             record.append(p.copy())
         q = apply_M(p)
         pi = p @ q
-        a = rho / pi
+        a = rho / pi if pi > 0.0 else 0.0
         x += a * p
         r -= a * q
         z = r / Jdiag
         rho_new = r @ z
         hist.append((rho, pi))
-        beta = rho_new / rho
+        beta = rho_new / rho if rho != 0.0 else 0.0
         p = z + beta * p
         rho = rho_new
     return x, r, hist

@@ -96,3 +96,25 @@ def test_gain_blend_and_history(systems):
     v = st2.pack()
     st3 = State.unpack(v, S.geom.n_coeff, S.geom.n_coeff)
     assert np.array_equal(st3.pack(), v)
+
+
+def test_pcg_stops_at_an_exact_solution():
+    # M diagonal with power-of-two entries and J = diag(M): the first step is
+    # exact (z = M^{-1} r, alpha = 1, x1 = M^{-1} b, r1 = 0 with no rounding),
+    # so the later steps meet p = 0, p^T M p = 0 and rho = 0; CG must keep the
+    # exact solution M^{-1} b rather than divide 0 by 0
+    d = 2.0 ** np.arange(-3, 5)
+    b = np.linspace(-1.0, 2.0, len(d))
+    x, r, hist = pcg(lambda v: d * v, np.zeros_like(b), b, d, 4)
+    assert np.array_equal(x, b / d)
+    assert np.array_equal(r, np.zeros_like(b))
+    assert hist[1] == (0.0, 0.0) and all(np.isfinite(v).all() for v in (x, r))
+
+
+def test_zero_right_hand_side_gives_zero(systems):
+    # M c = 0 has the unique solution c = 0 (M is positive definite): a frame
+    # with zero slopes from the zero state stays exactly zero
+    S = systems("small")
+    st = State(S.geom.n_coeff, S.geom.n_coeff)
+    st1, phi = frame(S, st, np.zeros(S.A.shape[0]), iters=4)
+    assert not np.any(st1.pack()) and not np.any(phi)
