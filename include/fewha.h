@@ -30,6 +30,14 @@
  *  - Argument and state errors are returned before anything is enqueued.
  *    A device error is returned as FEWHA_EDEVICE by the call that sees it.
  *    No C++ exception crosses this interface.
+ *  - Numerical breakdown: M is symmetric positive definite (Sec. 3.1), so a
+ *    PCG step meets p^T M p <= 0 with a nonzero residual, or a non-finite or
+ *    negative inner product, only on non-finite or overflowing inputs.  The
+ *    step then leaves its iterate unchanged (alpha = 0; a zero residual with
+ *    p = 0 is exact convergence, not a breakdown) and sets a flag of the
+ *    context (or batch); the next compute call on it, once that work has
+ *    finished, returns FEWHA_ENUMERIC without enqueuing anything and clears
+ *    the flag: results of the earlier calls are not valid.
  *  - A context is not thread-safe; distinct contexts may be used from
  *    distinct threads.
  */
@@ -52,7 +60,7 @@ typedef enum {
   FEWHA_EDEVICE = -3,  /* HIP runtime error                                 */
   FEWHA_ESTATE = -4,   /* call not valid in the context's current state     */
   FEWHA_EGEOM = -5,    /* geometry rejected (footprint leaves a layer, ...)  */
-  FEWHA_ENUMERIC = -6  /* numerical breakdown (non-positive p^T M p)         */
+  FEWHA_ENUMERIC = -6  /* numerical breakdown in earlier work (see below)    */
 } fewha_status;
 
 enum { FEWHA_NGS = 0, FEWHA_LGS = 1 };

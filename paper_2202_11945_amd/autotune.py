@@ -40,18 +40,35 @@ def admissible(ctxs, candidates=CANDIDATES):
     return [r for r in candidates if r >= m0]
 
 
-def signature(ctxs, iters):
-    """Cache key: device name and the multiset of problem shapes."""
-    import torch
+def source_hash():
+    """sha256 prefix of the library's sources: a cached choice is kept only
+    for the kernels it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    for f in sorted(os.listdir(src)):
+        with open(os.path.join(src, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def signature(ctxs, iters, device_name=None):
+    """Cache key: device name, library sources and the multiset of problem
+    shapes (layer sides, levels and heights; each sensor's kind, size,
+    altitude and direction, which set the propagation adjoint's paths)."""
+    if device_name is None:
+        import torch
+        device_name = torch.cuda.get_device_name(ctxs[0].device)
     shapes = {}
     for c in ctxs:
         cfg = c.cfg
-        s = "L%s|W%s|F%d" % (",".join("%dx%d" % (l["n"], l["levels"]) for l in cfg["layers"]),
-                            ",".join(str(w["n_subap"]) for w in cfg["wfs"]),
+        s = "L%s|W%s|F%d" % (",".join("%dx%d@%.6g" % (l["n"], l["levels"], l["h"]) for l in cfg["layers"]),
+                            ",".join("%s%d@%s:%.9g,%.9g" % (w["kind"], w["n_subap"], w["H"], w["theta"][0],
+                                                            w["theta"][1]) for w in cfg["wfs"]),
                             1 if (cfg.get("dms") and cfg.get("fit")) else 0)
         shapes[s] = shapes.get(s, 0) + 1
     body = ";".join("%dx[%s]" % (n, s) for s, n in sorted(shapes.items()))
-    return "%s|iters%d|%s|v2" % (torch.cuda.get_device_name(ctxs[0].device), iters, body)
+    return "%s|iters%d|%s|src%s" % (device_name, iters, body, source_hash())
 
 
 def _load():

@@ -96,6 +96,8 @@ struct Plan {
   std::vector<long> n_state;
   std::vector<IoDev> last_io;
   bool ran = false;
+  int* numflag = nullptr;                    // breakdown flag (host-mapped pinned memory)
+  int* numflag_dev = nullptr;                // its device address
 };
 
 #define HIP_TRY(expr)                                                          \
@@ -122,6 +124,7 @@ void destroy_plan(Plan* p) {
   if (p->t0) (void)hipEventDestroy(p->t0);
   if (p->t1) (void)hipEventDestroy(p->t1);
   if (p->rho_host) (void)hipHostFree(p->rho_host);
+  if (p->numflag) (void)hipHostFree(p->numflag);
   if (p->arena) (void)hipFree(p->arena);
   delete p;
 }
@@ -833,6 +836,11 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     }
   }
   HIP_TRY(hipMemset(P.arena, 0, P.arena_bytes));
+  HIP_TRY(hipHostMalloc((void**)&P.numflag, sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+  *(volatile int*)P.numflag = 0;
+  HIP_TRY(hipHostGetDevicePointer((void**)&P.numflag_dev, P.numflag, 0));
+  for (ProbDev& pd : P.hP) pd.numflag = P.numflag_dev;
+  for (FitDev& fd : hF) fd.numflag = P.numflag_dev;
   char* base = (char*)P.arena;
   for (int k = 0; k < P.nprob; ++k) {
     ProbDev& pd = P.hP[k];
@@ -995,6 +1003,20 @@ fewha_status upload_table(Plan& P, const std::vector<T>& v, hipStream_t s, T* ds
 }
 fewha_status upload_io(Plan& P, const std::vector<IoDev>& io, hipStream_t s, IoDev* dst, std::string& err) {
   return upload_table(P, io, s, dst, err);
+}
+
+// The breakdown flag of plan P, read and cleared: FEWHA_ENUMERIC when a PCG
+// step of earlier work on the plan (finished by now) found p^T M p <= 0 with
+// a nonzero residual or a non-finite inner product.  Work still running is
+// seen by a later call.
+fewha_status take_numeric(Plan& P, std::string& err) {
+  volatile int* f = P.numflag;
+  const int v = f ? *f : 0;
+  if (v == 0) return FEWHA_OK;
+  *f = 0;
+  err = "numerical breakdown in earlier work: PCG met p^T M p <= 0 with a nonzero residual, or a non-finite "
+        "inner product, in problem " + std::to_string(v - 1) + " (its results are not valid)";
+  return FEWHA_ENUMERIC;
 }
 
 LaunchArgs args(const Plan& P, hipStream_t s, const IoDev* io) {
@@ -1539,7 +1561,7 @@ static fewha_status ready(fewha_ctx* c) {
   if (!c->finalized) return fail(c, FEWHA_ESTATE, "context not finalized");
   if (c->device < 0 || !c->plan) return fail(c, FEWHA_ESTATE, "host-only context: no device");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, FEWHA_EDEVICE, "hipSetDevice failed");
-  return FEWHA_OK;
+  return take_numeric(*c->plan, c->err);
 }
 
 static fewha_status finish(fewha_ctx* c) {
@@ -1671,6 +1693,14 @@ static fewha_status bfail(fewha_batch* b, fewha_status s, const std::string& m) 
   return s;
 }
 
+// Breakdown flags of the batch plan and of its stream parts.
+static fewha_status bready(fewha_batch* b) {
+  fewha_status s = take_numeric(*b->plan, b->err);
+  for (Plan* q : b->parts)
+    if (s == FEWHA_OK) s = take_numeric(*q, b->err);
+  return s;
+}
+
 fewha_status fewha_batch_create(fewha_batch** out, fewha_ctx* const* ctxs, int n) {
   return fewha_batch_create_tuned(out, ctxs, n, nullptr);
 }
@@ -1763,6 +1793,7 @@ static fewha_status run_frame(Plan& P, hipStream_t st, const std::vector<IoDev>&
 fewha_status fewha_batch_reconstruct(fewha_batch* b, const float* const* slopes, float* const* state,
                                      float* const* layers_out, float* const* dm_out, int iters, int use_graph) {
   if (!b) return FEWHA_EINVAL;
+  if (fewha_status s0 = bready(b); s0 != FEWHA_OK) return s0;
   if (!slopes || !state) return bfail(b, FEWHA_EINVAL, "batch_reconstruct: null slopes or state array");
   if (iters < 0 || iters > kMaxIters) return bfail(b, FEWHA_EINVAL, "batch_reconstruct: iters must lie in [0, 256]");
   Plan& P = *b->plan;
@@ -1804,6 +1835,7 @@ fewha_status fewha_batch_reconstruct(fewha_batch* b, const float* const* slopes,
 fewha_status fewha_batch_solve(fewha_batch* b, const float* const* rhs, float* const* x, int max_iters, double rtol,
                                int* iters_done, double* rel_res) {
   if (!b) return FEWHA_EINVAL;
+  if (fewha_status s0 = bready(b); s0 != FEWHA_OK) return s0;
   if (!rhs || !x) return bfail(b, FEWHA_EINVAL, "batch_solve: null pointer array");
   const int n = b->plan->nprob;
   std::vector<const float*> vr(rhs, rhs + n), none(n, nullptr);
@@ -1816,6 +1848,7 @@ fewha_status fewha_batch_solve(fewha_batch* b, const float* const* rhs, float* c
 fewha_status fewha_batch_solve_map(fewha_batch* b, const float* const* slopes, const float* const* g_layers,
                                    float* const* x, int max_iters, double rtol, int* iters_done, double* rel_res) {
   if (!b) return FEWHA_EINVAL;
+  if (fewha_status s0 = bready(b); s0 != FEWHA_OK) return s0;
   if (!x) return bfail(b, FEWHA_EINVAL, "batch_solve_map: null x array");
   const int n = b->plan->nprob;
   std::vector<const float*> vs(n, nullptr), vg(n, nullptr), none(n, nullptr);
@@ -1827,6 +1860,7 @@ fewha_status fewha_batch_solve_map(fewha_batch* b, const float* const* slopes, c
 
 fewha_status fewha_batch_apply_Winv(fewha_batch* b, const float* const* coef, float* const* layers) {
   if (!b) return FEWHA_EINVAL;
+  if (fewha_status s0 = bready(b); s0 != FEWHA_OK) return s0;
   if (!coef || !layers) return bfail(b, FEWHA_EINVAL, "batch_apply_Winv: null pointer array");
   const int n = b->plan->nprob;
   std::vector<const float*> vi(coef, coef + n);
@@ -1836,6 +1870,7 @@ fewha_status fewha_batch_apply_Winv(fewha_batch* b, const float* const* coef, fl
 
 fewha_status fewha_batch_apply_WinvT(fewha_batch* b, const float* const* layers, float* const* coef) {
   if (!b) return FEWHA_EINVAL;
+  if (fewha_status s0 = bready(b); s0 != FEWHA_OK) return s0;
   if (!coef || !layers) return bfail(b, FEWHA_EINVAL, "batch_apply_WinvT: null pointer array");
   const int n = b->plan->nprob;
   std::vector<const float*> vi(layers, layers + n);
@@ -1846,6 +1881,7 @@ fewha_status fewha_batch_apply_WinvT(fewha_batch* b, const float* const* layers,
 fewha_status fewha_batch_param_grads(fewha_batch* b, const float* const* slopes, const float* const* coef,
                                      const float* const* lam, double* const* grads) {
   if (!b) return FEWHA_EINVAL;
+  if (fewha_status s0 = bready(b); s0 != FEWHA_OK) return s0;
   if (!slopes || !coef || !lam || !grads) return bfail(b, FEWHA_EINVAL, "batch_param_grads: null pointer array");
   const int n = b->plan->nprob;
   std::vector<const float*> vs(slopes, slopes + n), vc(coef, coef + n), vl(lam, lam + n);

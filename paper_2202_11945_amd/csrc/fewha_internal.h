@@ -199,6 +199,10 @@ struct ProbDev {
   const double* ftab64;  // interpolation fractions, as ftab
   float* rbuf;           // N_c: residual (right-hand side of a correction solve)
   double* x64;           // N_c: the refined iterate
+  // numerical-breakdown flag of the plan (host-mapped pinned memory): a
+  // PCG step that finds p^T M p <= 0 with a nonzero residual, or a
+  // non-finite or negative inner product, stores the problem index + 1
+  int* numflag;
 };
 
 // db3 filters in FP64 for the residual transforms.
@@ -291,6 +295,7 @@ struct FitDev {
   float* p;        // search direction (the source of the DM propagation)
   const float* adj;  // sum_k B_k^T M (B_k p or P_k phi)
   double* scal;    // rho
+  int* numflag;    // the plan's breakdown flag (see ProbDev)
 };
 
 struct HostModel {

@@ -1482,7 +1482,11 @@ __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD
   };
   const int q = t.tx * kPtW + lane;
   const int p0 = t.ty * 4 * RPT + wv * RPT;
-  if (q >= n || p0 >= n) return;  // no barriers in this kernel
+  if (p0 >= n) return;  // wave-uniform (no barriers in this kernel)
+  // lanes past the layer's last column run the sensor loop on that column
+  // (every lane stays active for the readlane reads of the list) and store
+  // nothing
+  const int qc = min(q, n - 1);
   const int wrec = wv * (RPT / kBandRows);  // this wave's first record past the tile's
   const int ngrp = min(RPT / kBandRows, (n - p0 + kBandRows - 1) / kBandRows);  // records inside the layer
   float acc[RPT];
@@ -1491,7 +1495,7 @@ __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD
   // column hats by buffer loads: lane offset fixed, entry offset wave-uniform
   const __amdgpu_buffer_rsrc_t hrs =
       __builtin_amdgcn_make_buffer_rsrc((void*)hats, (short)0, n_hats * (int)sizeof(HatEnt), 0x00020000);
-  const int hlane = lane * (int)sizeof(HatEnt);
+  const int hlane = (qc - t.tx * kPtW) * (int)sizeof(HatEnt);
   auto fetch = [&](const PtEnt& e, HatEnt& hx, BandHdr& hd) {  // valid for every entry (see PtEnt)
     const auto h = __builtin_amdgcn_raw_buffer_load_b128(hrs, hlane, e.hx * (int)sizeof(HatEnt), 0);
     hx.lo = (int)h[0];
@@ -1505,7 +1509,7 @@ __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD
     const float* vs = pr.vadj + cur.v_off;
     const BandRec* rec = bands + cur.band + wrec;
     if (K == 0)
-      pt_general<RPT>(load_glpar(pr.gl + (cur.nck >> 2)), pr.vadj, q, p0, n, acc);
+      pt_general<RPT>(load_glpar(pr.gl + (cur.nck >> 2)), pr.vadj, qc, p0, n, acc);
     else if (K == 2)
       pt_sensor<2, RPT>(vs, nc, rec, hd, hx, ngrp, acc);
     else
@@ -1522,10 +1526,12 @@ __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD
   }
   const IoDev& io = IO[t.prob];
   const gptr_w dst = (gptr_w)((mode == PT_USER) ? io.out : pr.phiadj);
+  if (q < n) {
 #pragma unroll
-  for (int u = 0; u < RPT; ++u) {
-    const int p = p0 + u;
-    if (p < n) dst[loff + p * n + q] = acc[u];
+    for (int u = 0; u < RPT; ++u) {
+      const int p = p0 + u;
+      if (p < n) dst[loff + p * n + q] = acc[u];
+    }
   }
 }
 
@@ -1563,6 +1569,12 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
   const double rho = wave_sum_slots(dot_group(pr, rho_grp(iter)), rho_count(pr, iter));
   const double pi = wave_sum_slots(dot_group(pr, pi_grp(iter)), pr.n_slots_fdwt);
   const float a = (float)((pi > 0.0) ? rho / pi : 0.0);
+  // breakdown: a nonzero residual with p^T M p <= 0 (M is positive definite,
+  // so only rounding or non-finite inputs get here), or a negative or
+  // non-finite rho; the step then leaves x and r unchanged (alpha = 0) and
+  // the next call on the plan reports it
+  if (threadIdx.x == 0 && t.ty == 0 && ((!(pi > 0.0) && rho != 0.0) || !(rho >= 0.0)))
+    __hip_atomic_store(pr.numflag, t.prob + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 #pragma unroll
   for (int u = 0; u < V; ++u) {
     const int e = e0 + threadIdx.x + u * 256;
@@ -1766,6 +1778,8 @@ __global__ __launch_bounds__(1024) void k_fit_cg(const FitDev* F, const ProbDev*
     __syncthreads();
     const double rho = f.scal[0];
     const float al = (float)((s_val > 0.0) ? rho / s_val : 0.0);
+    if (threadIdx.x == 0 && ((!(s_val > 0.0) && rho != 0.0) || !(rho >= 0.0)))
+      __hip_atomic_store(f.numflag, f.main + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     acc = 0.0;
     for (int e = threadIdx.x; e < n; e += nt) {
       const float pe = f.p[e];

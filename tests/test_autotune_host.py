@@ -65,3 +65,24 @@ def test_streams_are_tuned_after_the_shapes(tuner, monkeypatch):
     tp, calls = fake_times(table)
     monkeypatch.setattr(tuner, "time_plan", tp)
     assert tuner.tune([None], 4, use_cache=False)["streams"] == 1 and len(calls) == 6
+
+
+def test_cache_key_follows_geometry_and_sources(lib, monkeypatch):
+    # a cached choice must not survive a change of sensor geometry (which
+    # sets the propagation adjoint's paths) or of the kernel sources
+    from types import SimpleNamespace
+    from paper_2202_11945_amd import autotune
+    from synthetic import get_config
+
+    def key(cfg):
+        return autotune.signature([SimpleNamespace(cfg=cfg, device=0)], 4, device_name="dev")
+
+    base = key(get_config("small"))
+    assert base == key(get_config("small"))
+    moved = get_config("small")
+    moved["wfs"][0]["theta"] = (moved["wfs"][0]["theta"][0] + 1e-6, moved["wfs"][0]["theta"][1])
+    higher = get_config("small")
+    higher["layers"][1]["h"] += 100.0
+    assert len({base, key(moved), key(higher)}) == 3
+    monkeypatch.setattr(autotune, "source_hash", lambda: "0" * 16)
+    assert key(get_config("small")) != base

@@ -12,7 +12,8 @@ from oracle.solver import State, frame
 from synthetic import get_config, random_vector
 from synthetic.configs import batch_mix
 
-from test_gpu_parity import LAYER_TOL, OP_TOL, _check_frame, rel, synth_slopes, to_dev, to_host
+from parity import check_blocks
+from test_gpu_parity import FRAME_ETOL, LAYER_TOL, OP_TOL, _check_frame, synth_slopes, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -28,16 +29,13 @@ def system(name, cfg):
 def _ops(gpu_lib, S, cfg, key):
     ctx = gpu_lib.Context(cfg, device=0)
     x = random_vector(S.geom.n_coeff, 200, key)
-    assert rel(to_host(ctx.apply_A(to_dev(x))), S.apply_A(x)) <= OP_TOL
+    o, so = S.geom.layer_off, S.geom.slope_off
+    check_blocks(to_host(ctx.apply_A(to_dev(x))), S.apply_A(x), so, OP_TOL, "A x sensor")
     y = random_vector(S.A.shape[0], 201, key)
-    assert rel(to_host(ctx.apply_AT(to_dev(y))), S.apply_AT(y)) <= OP_TOL
-    got = to_host(ctx.apply_M(to_dev(x)))
-    ref = S.apply_M(x)
-    o = S.geom.layer_off
-    for l in range(S.Lc):
-        assert rel(got[o[l]:o[l + 1]], ref[o[l]:o[l + 1]]) <= OP_TOL, l
+    check_blocks(to_host(ctx.apply_AT(to_dev(y))), S.apply_AT(y), o, OP_TOL, "A^T y layer")
+    check_blocks(to_host(ctx.apply_M(to_dev(x))), S.apply_M(x), o, OP_TOL, "M x layer")
     s = synth_slopes(S, 0)
-    assert rel(to_host(ctx.rhs(to_dev(s))), S.rhs(s)) <= OP_TOL
+    check_blocks(to_host(ctx.rhs(to_dev(s))), S.rhs(s), o, OP_TOL, "b layer")
     return ctx
 
 
@@ -139,10 +137,7 @@ def check_frames(systems, slopes, states, lays, run_frame, iters=6):
     for k, S in enumerate(systems):
         st = State.unpack(before[k], S.geom.n_coeff, S.geom.n_coeff)
         _, phi = frame(S, st, to_host(slopes[k]), iters=iters)
-        got = to_host(lays[k])
-        o = S.geom.layer_off
-        for l in range(S.Lc):
-            assert rel(got[o[l]:o[l + 1]], phi[o[l]:o[l + 1]]) <= LAYER_TOL, (k, l)
+        check_blocks(to_host(lays[k]), phi, S.geom.layer_off, LAYER_TOL, "problem %d layer" % k, FRAME_ETOL)
 
 
 def test_uneven_batch_against_oracle(gpu_lib):

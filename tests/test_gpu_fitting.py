@@ -9,7 +9,8 @@ from oracle.operators import System
 from oracle.solver import State
 from synthetic import get_config
 
-from test_gpu_parity import LAYER_TOL, rel, synth_slopes, to_dev, to_host
+from parity import check_blocks
+from test_gpu_parity import FRAME_ETOL, LAYER_TOL, synth_slopes, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -28,15 +29,14 @@ def test_fitted_frame(gpu_lib, name):
     s = synth_slopes(S, 0)
     ctx.reconstruct(to_dev(s), st, lay, dm, iters=cfg["iters"])
     ref_st, ref_phi = frame_fitted(S, F, State(S.geom.n_coeff, F.n_act), s.astype(np.float64))
-    o = S.geom.layer_off
-    got_lay = to_host(lay)
-    for l in range(S.Lc):
-        assert rel(got_lay[o[l]:o[l + 1]], ref_phi[o[l]:o[l + 1]]) <= LAYER_TOL, l
+    check_blocks(to_host(lay), ref_phi, S.geom.layer_off, LAYER_TOL, "layers", FRAME_ETOL)
     got = to_host(st)
     n = S.geom.n_coeff
     a = got[3 * n + F.n_act:]
-    print("\n[gpu] fitted commands rel. error:", rel(a, ref_st.a))
-    assert rel(a, ref_st.a) <= 10 * LAYER_TOL
+    # each DM's commands at the layer tolerance
+    dm_off = np.cumsum([0] + [dm["n_act"] ** 2 for dm in cfg["dms"]])
+    m = check_blocks(a, ref_st.a, dm_off, LAYER_TOL, "DM", FRAME_ETOL)
+    print("\n[gpu] fitted commands:", m)
     assert np.array_equal(to_host(dm), a)
     # fitted commands reproduce the layers' wavefront in the fitting directions
     # better than zero commands do

@@ -84,8 +84,10 @@ def test_winv_and_winvT(gpu_lib, systems, name):
     ctx = ctx_for(gpu_lib, name)
     x = random_vector(S.geom.n_coeff, 500)
     step("W^-1 / W^-T " + name)
-    assert rel(to_host(ctx.apply_Winv(to_dev(x))), S.W_inv(x)) <= OP_TOL
-    assert rel(to_host(ctx.apply_WinvT(to_dev(x))), S.W_invT(x)) <= OP_TOL
+    from parity import check_blocks
+    o = S.geom.layer_off
+    check_blocks(to_host(ctx.apply_Winv(to_dev(x))), S.W_inv(x), o, OP_TOL, "W^-1 x layer")
+    check_blocks(to_host(ctx.apply_WinvT(to_dev(x))), S.W_invT(x), o, OP_TOL, "W^-T x layer")
 
 
 def test_solve_matches_cholesky_past_the_dot_ring(gpu_lib, small_case):

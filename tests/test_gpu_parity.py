@@ -1,12 +1,16 @@
 """GPU parity of every entry point of libfewha against the FP64 oracle, on
-the same seeded FP32 inputs.  Tolerances: <= 1e-5 relative 2-norm per
-operator application, <= 1e-4 on the reconstructed layers after a fixed
-number of PCG iterations (norm-wise, per layer).  Integer/structural results
-(batch vs single, graph vs direct launches, repeat runs) are compared
-bitwise."""
+the same seeded FP32 inputs.  Tolerances: 1e-5 per operator application,
+1e-4 on the reconstructed layers after a fixed number of PCG iterations,
+each checked per block (sensor or layer) norm-wise, as the largest entry
+error against the block's largest entry, and entry by entry against the
+entry's size with the block's RMS as floor (tests/parity.py).  Structural
+results (batch vs single, graph vs direct launches, repeat runs) are
+compared bitwise."""
 
 import numpy as np
 import pytest
+
+from parity import check, check_blocks
 
 from oracle.solver import State, frame
 from synthetic import frozen_flow_frames, get_config, random_vector, slope_noise
@@ -16,6 +20,14 @@ pytestmark = pytest.mark.gpu
 CONFIGS = ["tiny", "small", "mid", "maory_like"]
 OP_TOL = 1e-5
 LAYER_TOL = 1e-4
+# Entry-wise bound of the frame's outputs (layers, c, r, a), against
+# |ref_i| + rms(ref) of the block.  After k FP32 PCG iterations the error
+# is a sum of many rounding contributions, spread unevenly over the
+# coefficients: at the norm-wise 1e-4 it reaches 4e-4 of (|ref_i| + rms) at
+# single entries (9 layers, 20 iterations); 1e-3 keeps a margin over that
+# and still fails a single entry off by 0.3 % of the RMS.  Norm-wise and
+# max-abs stay at LAYER_TOL.
+FRAME_ETOL = 1e-3
 
 
 def rel(a, b):
@@ -60,7 +72,7 @@ def test_apply_A(gpu_lib, systems, name):
     ctx = ctx_for(gpu_lib, name)
     x = random_vector(S.geom.n_coeff, 100, CONFIGS.index(name))
     got = to_host(ctx.apply_A(to_dev(x)))
-    assert rel(got, S.apply_A(x)) <= OP_TOL
+    check_blocks(got, S.apply_A(x), S.geom.slope_off, OP_TOL, "A x %s sensor" % name)
 
 
 @pytest.mark.parametrize("name", CONFIGS)
@@ -69,7 +81,7 @@ def test_apply_AT(gpu_lib, systems, name):
     ctx = ctx_for(gpu_lib, name)
     y = random_vector(S.A.shape[0], 101, CONFIGS.index(name))
     got = to_host(ctx.apply_AT(to_dev(y)))
-    assert rel(got, S.apply_AT(y)) <= OP_TOL
+    check_blocks(got, S.apply_AT(y), S.geom.layer_off, OP_TOL, "A^T y %s layer" % name)
 
 
 @pytest.mark.parametrize("name", CONFIGS)
@@ -79,11 +91,9 @@ def test_apply_M(gpu_lib, systems, name):
     c = random_vector(S.geom.n_coeff, 102, CONFIGS.index(name))
     got = to_host(ctx.apply_M(to_dev(c)))
     ref = S.apply_M(c)
-    assert rel(got, ref) <= OP_TOL
+    check(got, ref, OP_TOL, "M c %s" % name)
     # per layer as well (a small layer must not hide behind a big one)
-    for l in range(S.Lc):
-        o = S.geom.layer_off
-        assert rel(got[o[l]:o[l + 1]], ref[o[l]:o[l + 1]]) <= OP_TOL
+    check_blocks(got, ref, S.geom.layer_off, OP_TOL, "M c %s layer" % name)
 
 
 @pytest.mark.parametrize("name", CONFIGS)
@@ -92,7 +102,7 @@ def test_rhs(gpu_lib, systems, name):
     ctx = ctx_for(gpu_lib, name)
     s = synth_slopes(S, 0)
     got = to_host(ctx.rhs(to_dev(s)))
-    assert rel(got, S.rhs(s)) <= OP_TOL
+    check_blocks(got, S.rhs(s), S.geom.layer_off, OP_TOL, "b %s layer" % name)
 
 
 def _oracle_state(S, n_frames):
@@ -114,13 +124,12 @@ def _check_frame(gpu_lib, S, ctx, state32, s32, iters=None):
     ref_st, ref_phi = frame(S, State.unpack(state32, S.geom.n_coeff, S.geom.n_coeff),
                             s32.astype(np.float64), iters=iters)
     o = S.geom.layer_off
-    for l in range(S.Lc):
-        assert rel(got_lay[o[l]:o[l + 1]], ref_phi[o[l]:o[l + 1]]) <= LAYER_TOL, ("layer", l)
+    check_blocks(got_lay, ref_phi, o, LAYER_TOL, "layers", FRAME_ETOL)
     g = State.unpack(got_state, S.geom.n_coeff, S.geom.n_coeff)
-    assert rel(g.c, ref_st.c) <= LAYER_TOL
-    assert rel(g.b, ref_st.b) <= OP_TOL
-    assert rel(g.r, ref_st.r) <= LAYER_TOL * 10
-    assert rel(g.a, ref_st.a) <= LAYER_TOL
+    check_blocks(g.c, ref_st.c, o, LAYER_TOL, "c", FRAME_ETOL)
+    check_blocks(g.b, ref_st.b, o, OP_TOL, "b")
+    check_blocks(g.r, ref_st.r, o, LAYER_TOL, "r", FRAME_ETOL)
+    check_blocks(g.a, ref_st.a, o, LAYER_TOL, "a", FRAME_ETOL)
     n = S.geom.n_coeff
     assert np.array_equal(g.a_prev, state32[4 * n:5 * n].astype(np.float64))  # a_prev <- a
     assert np.array_equal(got_dm.astype(np.float32), g.a.astype(np.float32))
@@ -162,6 +171,43 @@ def test_zero_input_gives_zero(gpu_lib, systems):
     s = torch.zeros(S.A.shape[0], device="cuda")
     ctx.reconstruct(s, st, iters=4)
     assert float(torch.abs(st).max()) == 0.0
+
+
+def test_nonfinite_slopes_report_a_breakdown(gpu_lib):
+    # NaN slopes (a dead sensor) make rho non-finite: the PCG step sets the
+    # context's breakdown flag, the next call returns FEWHA_ENUMERIC without
+    # running, and the call after it runs normally
+    import torch
+    ctx = gpu_lib.Context(get_config("small"), device=0)
+    st = torch.zeros(ctx.n_state, device="cuda")
+    ctx.reconstruct(torch.full((ctx.n_slopes,), float("nan"), device="cuda"), st, iters=2)
+    torch.cuda.synchronize()
+    zs = torch.zeros(ctx.n_slopes, device="cuda")
+    st2 = torch.full((ctx.n_state,), 5.0, device="cuda")
+    with pytest.raises(gpu_lib.FewhaError) as e:
+        ctx.reconstruct(zs, st2, iters=2)
+    assert e.value.status == -6
+    torch.cuda.synchronize()
+    assert float(st2.min()) == 5.0 and float(st2.max()) == 5.0  # nothing ran
+    st2.zero_()
+    ctx.reconstruct(zs, st2, iters=2)
+    torch.cuda.synchronize()
+    assert float(st2.abs().max()) == 0.0
+    # a batch reports it the same way
+    ok = gpu_lib.Context(get_config("small"), device=0)
+    b = gpu_lib.Batch([ok, ctx])
+    sts = [torch.zeros(ctx.n_state, device="cuda") for _ in range(2)]
+    b.reconstruct([zs, torch.full_like(zs, float("nan"))], sts, iters=2, use_graph=False)
+    torch.cuda.synchronize()
+    with pytest.raises(gpu_lib.FewhaError) as e:
+        b.reconstruct([zs, zs], sts, iters=2, use_graph=False)
+    assert e.value.status == -6 and "problem 1" in str(e.value)
+    b.reconstruct([zs, zs], [s.zero_() for s in sts], iters=2, use_graph=False)
+    torch.cuda.synchronize()
+    assert all(float(s.abs().max()) == 0.0 for s in sts)
+    b.close()
+    ok.close()
+    ctx.close()
 
 
 def test_chain_drift(gpu_lib, systems):

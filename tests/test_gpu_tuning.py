@@ -11,7 +11,8 @@ from oracle.solver import State, frame
 from synthetic import get_config, random_vector
 from synthetic.configs import batch_mix
 from test_gpu_configs import check_frames
-from test_gpu_parity import LAYER_TOL, OP_TOL, rel, synth_slopes, to_dev, to_host
+from parity import check_blocks
+from test_gpu_parity import FRAME_ETOL, LAYER_TOL, OP_TOL, synth_slopes, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -25,16 +26,13 @@ def test_frame_parity_with_resident_side(gpu_lib, systems, name, res):
     print("\n[gpu-tune]", name, "resident", res, flush=True)
     ctx = gpu_lib.Context(get_config(name), device=0, tuning=res)
     x = random_vector(S.geom.n_coeff, 300, len(str(res)))
-    assert rel(to_host(ctx.apply_M(to_dev(x))), S.apply_M(x)) <= OP_TOL
+    check_blocks(to_host(ctx.apply_M(to_dev(x))), S.apply_M(x), S.geom.layer_off, OP_TOL, "M x layer")
     st = torch.zeros(ctx.n_state, device="cuda")
     lay = torch.empty(ctx.n_coeff, device="cuda")
     s = synth_slopes(S, 0)
     ctx.reconstruct(to_dev(s), st, lay, iters=S.cfg["iters"])
     _, ref = frame(S, State(S.geom.n_coeff, S.geom.n_coeff), s.astype(np.float64))
-    got = to_host(lay)
-    o = S.geom.layer_off
-    for l in range(S.Lc):
-        assert rel(got[o[l]:o[l + 1]], ref[o[l]:o[l + 1]]) <= LAYER_TOL, l
+    check_blocks(to_host(lay), ref, S.geom.layer_off, LAYER_TOL, "layers", FRAME_ETOL)
     ctx.close()
 
 
