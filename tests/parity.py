@@ -28,14 +28,15 @@ import os
 import numpy as np
 
 
-def metrics(got, ref):
+def metrics(got, ref, scale=None):
     g = np.asarray(got, dtype=np.float64).ravel()
     r = np.asarray(ref, dtype=np.float64).ravel()
     assert g.shape == r.shape, (g.shape, r.shape)
+    sc = r if scale is None else np.asarray(scale, dtype=np.float64).ravel()
     d = np.abs(g - r)
-    nr = np.linalg.norm(r)
-    mx = np.abs(r).max() if r.size else 0.0
-    rms = nr / np.sqrt(max(r.size, 1))
+    nr = np.linalg.norm(sc)
+    mx = np.abs(sc).max() if sc.size else 0.0
+    rms = nr / np.sqrt(max(sc.size, 1))
     out = {"n": int(r.size), "norm": float(np.linalg.norm(g - r) / nr) if nr > 0 else float(np.linalg.norm(g)),
            "maxabs": float(d.max() / mx) if mx > 0 else float(d.max() if d.size else 0.0)}
     if r.size:
@@ -56,8 +57,8 @@ def _log(what, m, tol, etol):
             f.write(json.dumps(dict(m, what=str(what), tol=tol, etol=etol)) + "\n")
 
 
-def _eval(got, ref, tol, what, etol):
-    m = metrics(got, ref)
+def _eval(got, ref, tol, what, etol, scale=None):
+    m = metrics(got, ref, scale)
     _log(what, m, tol, etol)
     bad = []
     if not m["norm"] <= tol:
@@ -77,16 +78,19 @@ def check(got, ref, tol, what, etol=None):
     return m
 
 
-def check_blocks(got, ref, offsets, tol, what, etol=None):
+def check_blocks(got, ref, offsets, tol, what, etol=None, scale=None):
     """The three bounds on every block [offsets[k], offsets[k+1]) (layers,
     sensors); every block is evaluated before the assertion names the
-    failing ones."""
+    failing ones.  `scale` (same layout as ref) replaces ref as the size
+    the bounds are relative to (its norm, largest entry and RMS)."""
     g = np.asarray(got, dtype=np.float64).ravel()
     r = np.asarray(ref, dtype=np.float64).ravel()
+    sc = None if scale is None else np.asarray(scale, dtype=np.float64).ravel()
     out, bad = [], []
     for k in range(len(offsets) - 1):
         a, b = int(offsets[k]), int(offsets[k + 1])
-        m, why = _eval(g[a:b], r[a:b], tol, "%s[%d]" % (what, k), tol if etol is None else etol)
+        m, why = _eval(g[a:b], r[a:b], tol, "%s[%d]" % (what, k), tol if etol is None else etol,
+                       None if sc is None else sc[a:b])
         out.append(m)
         if why:
             bad.append(why)

@@ -113,7 +113,7 @@ def _oracle_state(S, n_frames):
     return st.pack().astype(np.float32)
 
 
-def _check_frame(gpu_lib, S, ctx, state32, s32, iters=None):
+def _check_frame(gpu_lib, S, ctx, state32, s32, iters=None, c_etol=FRAME_ETOL):
     import torch
     iters = S.cfg["iters"] if iters is None else iters
     st_dev = to_dev(state32)
@@ -126,9 +126,12 @@ def _check_frame(gpu_lib, S, ctx, state32, s32, iters=None):
     o = S.geom.layer_off
     check_blocks(got_lay, ref_phi, o, LAYER_TOL, "layers", FRAME_ETOL)
     g = State.unpack(got_state, S.geom.n_coeff, S.geom.n_coeff)
-    check_blocks(g.c, ref_st.c, o, LAYER_TOL, "c", FRAME_ETOL)
+    check_blocks(g.c, ref_st.c, o, LAYER_TOL, "c", c_etol)
     check_blocks(g.b, ref_st.b, o, OP_TOL, "b")
-    check_blocks(g.r, ref_st.r, o, LAYER_TOL, "r", FRAME_ETOL)
+    # the recurrence residual: its FP32 rounding error scales with the size of
+    # the right-hand side it is a difference of (b - M c), not with its own
+    # size, which shrinks with every iteration (attainable accuracy of CG)
+    check_blocks(g.r, ref_st.r, o, LAYER_TOL, "r", FRAME_ETOL, scale=ref_st.b)
     check_blocks(g.a, ref_st.a, o, LAYER_TOL, "a", FRAME_ETOL)
     n = S.geom.n_coeff
     assert np.array_equal(g.a_prev, state32[4 * n:5 * n].astype(np.float64))  # a_prev <- a
