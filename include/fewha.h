@@ -198,6 +198,25 @@ FEWHA_API fewha_status fewha_rhs(fewha_ctx* ctx, const float* slopes, float* b);
 FEWHA_API fewha_status fewha_reconstruct(fewha_ctx* ctx, const float* slopes, float* state,
                                          float* layers_out, float* dm_out, int iters);
 
+/* fewha_reconstruct without any allocation in the call, for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight
+ * real-time serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * kernels and results (bitwise) as fewha_reconstruct; the frame's work
+ * buffers (layers, adjoint, dense slopes, corner grids, search directions,
+ * M p, inner-product slots) and the per-call pointer table live in one
+ * static device array of the library (16 MiB, one copy per device, held
+ * until the process ends) instead of the context's work space.  The call
+ * makes no device or host allocation.  Every call on a device shares that
+ * array, which keeps the last call's contents (every buffer is written
+ * before it is read within a frame, so nothing needs clearing): calls that
+ * overlap on one device (other streams, other threads, other contexts) race
+ * and must be ordered by the caller.  FEWHA_EINVAL if the context's frame
+ * needs more than 16 MiB of work buffers (about 2.9 MB for the 39 m
+ * MAORY-like system, 8.6 MB for 9 layers of up to 256 x 256) or uses the
+ * DM fitting step. */
+FEWHA_API fewha_status fewha_reconstruct_noalloc(fewha_ctx* ctx, const float* slopes, float* state,
+                                                 float* layers_out, float* dm_out, int iters);
+
 /* ---- converged solves and the implicit backward ---- */
 
 /* Solve M x = rhs (eq. fewha, wavelet domain) to a relative residual

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -98,6 +99,11 @@ struct Plan {
   bool ran = false;
   int* numflag = nullptr;                    // breakdown flag (host-mapped pinned memory)
   int* numflag_dev = nullptr;                // its device address
+  // allocation-free frame: problem records whose work buffers live in the
+  // library's static device scratch (see fewha_reconstruct_noalloc)
+  ProbDev* dPna = nullptr;                   // in the arena, nprob_all records
+  IoDev* na_io = nullptr;                    // per-call table at the start of the scratch
+  size_t na_bytes = 0;                       // scratch the plan's frame needs
 };
 
 #define HIP_TRY(expr)                                                          \
@@ -826,6 +832,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   const size_t oBand = cv.take(sizeof(BandRec) * hats.bands.size());
   const size_t oPtE = cv.take(sizeof(PtEnt) * std::max<size_t>(ptl.ents.size(), 1));
   const size_t oF = cv.take(sizeof(FitDev) * std::max<size_t>(hF.size(), 1));
+  const size_t oPna = cv.take(sizeof(ProbDev) * P.nprob_all);
   const size_t oT = cv.take(sizeof(Tile) * std::max<size_t>(P.hT.size(), 1));
   P.arena_bytes = cv.off;
   {
@@ -922,6 +929,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     HIP_TRY(hipMemcpy(base + fl.gl, fl.glp.data(), sizeof(GLPar) * fl.glp.size(), hipMemcpyHostToDevice));
   }
   P.dF = (FitDev*)(base + oF);
+  P.dPna = (ProbDev*)(base + oPna);
   if (!hF.empty()) HIP_TRY(hipMemcpy(P.dF, hF.data(), sizeof(FitDev) * hF.size(), hipMemcpyHostToDevice));
   P.dP = (ProbDev*)(base + oP);
   P.dL = (LayerDev*)(base + oL);
@@ -983,6 +991,87 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   P.n_state.resize(P.nprob);
   for (int k = 0; k < P.nprob; ++k) P.n_state[k] = 3L * P.hP[k].n_c + 2L * P.hP[k].n_act;
   out = pl.release();
+  return FEWHA_OK;
+}
+
+// ---- the allocation-free frame ----
+// The work buffers of fewha_reconstruct_noalloc live in this array, one copy
+// per device, for the life of the process.  Host code never uses its name
+// as an address: each device's copy is looked up once (noalloc_scratch) and
+// that address is what kernels and copies receive.
+constexpr size_t kNoAllocBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Device address of `scratch` on `device` (current), looked up once per device.
+fewha_status noalloc_scratch(int device, unsigned char** out, std::string& err) {
+  static std::mutex mu;
+  static std::map<int, unsigned char*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it == addr.end()) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return FEWHA_EDEVICE;
+    }
+    it = addr.emplace(device, (unsigned char*)ptr).first;
+  }
+  *out = it->second;
+  return FEWHA_OK;
+}
+
+// Problem records of plan P whose frame work buffers (layers, adjoint,
+// coarse-block scratch, dense slopes, corner grids, tip/tilt partials,
+// search directions, M p, inner-product slots) are carved from the static
+// scratch after a 256-byte per-call table; the tables stay in the arena.
+// Every buffer is written before it is read within a frame, so the scratch
+// needs no clearing.  Called at set-up with the plan's device current.
+fewha_status setup_noalloc(Plan& P, std::string& err) {
+  unsigned char* base = nullptr;
+  fewha_status s = noalloc_scratch(P.device, &base, err);
+  if (s != FEWHA_OK) return s;
+  std::vector<ProbDev> v(P.hP);
+  size_t off = 256;  // the per-call IoDev table
+  static_assert(sizeof(IoDev) <= 256, "one per-call table in the scratch head");
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return base + o;
+  };
+  for (int k = 0; k < P.nprob; ++k) {
+    ProbDev& pd = v[k];
+    const size_t nc4 = sizeof(float) * (size_t)pd.n_c;
+    size_t tmp = 4, sd = 4, vadj = 4, part = 4;
+    for (int l = 0; l < pd.L; ++l) {
+      const LayerDev& ld = P.hL[pd.layer0 + l];
+      if (ld.n > ld.res) tmp = std::max(tmp, sizeof(float) * (size_t)(ld.tmp_off + ld.n * ld.n / 4));
+    }
+    for (int g = 0; g < pd.G; ++g) {
+      const WfsDev& wd = P.hW[pd.wfs0 + g];
+      sd = std::max(sd, sizeof(float) * (size_t)(wd.s_off + 2 * wd.N * wd.N));
+      vadj = std::max(vadj, sizeof(float) * (size_t)(wd.v_off + wd.nc * wd.nc));
+      part = std::max(part, sizeof(float) * (size_t)(wd.part_off + 4 * wd.n_tiles_s));
+    }
+    pd.phi = (float*)take(nc4);
+    pd.phiadj = (float*)take(nc4);
+    pd.tmpa = (float*)take(tmp);
+    pd.tmpb = (float*)take(tmp);
+    pd.sd = (float*)take(sd);
+    pd.vadj = (float*)take(vadj);
+    pd.part = (float*)take(part);
+    pd.pbuf0 = (float*)take(nc4);
+    pd.pbuf1 = (float*)take(nc4);
+    pd.q = (float*)take(nc4);
+    pd.dots = (double*)take(sizeof(double) * (size_t)(2 * kDotRing) * pd.n_dots);
+  }
+  if (sizeof(IoDev) * (size_t)P.nprob_all > 256) {
+    err = "allocation-free frame: per-call table larger than the scratch head";
+    return FEWHA_EINVAL;
+  }
+  P.na_bytes = off;
+  P.na_io = (IoDev*)base;
+  HIP_TRY(hipMemcpy(P.dPna, v.data(), sizeof(ProbDev) * v.size(), hipMemcpyHostToDevice));
   return FEWHA_OK;
 }
 
@@ -1513,6 +1602,11 @@ fewha_status fewha_finalize(fewha_ctx* c) {
     s = build_plan(c->plan, ms, c->device, c->m.tune_res > 0 ? c->m.tune_res : kResMax,
                    c->m.tune_pt_rows > 0 ? c->m.tune_pt_rows : 4, c->err);
     if (s != FEWHA_OK) return s;
+    if ((s = setup_noalloc(*c->plan, c->err)) != FEWHA_OK) {
+      destroy_plan(c->plan);
+      c->plan = nullptr;
+      return s;
+    }
   }
   c->finalized = true;
   return FEWHA_OK;
@@ -1646,6 +1740,39 @@ fewha_status fewha_reconstruct(fewha_ctx* c, const float* slopes, float* state, 
   io[0].dm_out = dm_out;
   if ((s = upload_io(P, io, c->stream, P.dIO, c->err)) != FEWHA_OK) return s;
   LaunchArgs a = args(P, c->stream, P.dIO);
+  enq_reconstruct(P, a, iters);
+  return finish(c);
+}
+
+fewha_status fewha_reconstruct_noalloc(fewha_ctx* c, const float* slopes, float* state, float* layers_out,
+                                       float* dm_out, int iters) {
+  fewha_status s = ready(c);
+  if (s != FEWHA_OK) return s;
+  if (!slopes || !state) return fail(c, FEWHA_EINVAL, "reconstruct_noalloc: null slopes or state");
+  if (iters < 0 || iters > kMaxIters) return fail(c, FEWHA_EINVAL, "reconstruct_noalloc: iters must lie in [0, 256]");
+  if (((uintptr_t)state & 15) != 0) return fail(c, FEWHA_EINVAL, "reconstruct_noalloc: state must be 16-byte aligned");
+  Plan& P = *c->plan;
+  if (c->m.fit.on) return fail(c, FEWHA_EINVAL, "reconstruct_noalloc: not available with the DM fitting step");
+  if (P.na_bytes > kNoAllocBytes)
+    return fail(c, FEWHA_EINVAL, "reconstruct_noalloc: the frame needs " + std::to_string(P.na_bytes) +
+                                     " bytes of scratch; the static scratch holds " + std::to_string(kNoAllocBytes));
+  // the per-call table through a pinned slot of the ring (no host or device allocation)
+  const int slot = P.ring;
+  P.ring = (P.ring + 1) % kRing;
+  if (P.ev_used[slot] && hipEventSynchronize(P.ev[slot]) != hipSuccess)
+    return fail(c, FEWHA_EDEVICE, "reconstruct_noalloc: staging event failed");
+  IoDev* io = P.pinned[slot];
+  std::memset(io, 0, sizeof(IoDev) * P.nprob_all);
+  io[0].in = slopes;
+  io[0].state = state;
+  io[0].layers_out = layers_out;
+  io[0].dm_out = dm_out;
+  if (hipMemcpyAsync(P.na_io, io, sizeof(IoDev) * P.nprob_all, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipEventRecord(P.ev[slot], c->stream) != hipSuccess)
+    return fail(c, FEWHA_EDEVICE, "reconstruct_noalloc: staging copy failed");
+  P.ev_used[slot] = true;
+  LaunchArgs a = args(P, c->stream, P.na_io);
+  a.P = P.dPna;
   enq_reconstruct(P, a, iters);
   return finish(c);
 }

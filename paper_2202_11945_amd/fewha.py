@@ -183,6 +183,15 @@ class Context:
                                       _ptr(layers_out, self.n_coeff), _ptr(dm_out, self.n_act), int(iters)),
                self.h)
 
+    def fewha_reconstruct_noalloc(self, slopes, state, layers_out=None, dm_out=None, iters=None):
+        """fewha_reconstruct with the work buffers in the library's static
+        device scratch (no allocation in the call)."""
+        iters = self.cfg["iters"] if iters is None else iters
+        self._sync_stream()
+        _check(_abi.fewha_reconstruct_noalloc(self.h, _ptr(slopes, self.n_slopes), _ptr(state, self.n_state),
+                                              _ptr(layers_out, self.n_coeff), _ptr(dm_out, self.n_act),
+                                              int(iters)), self.h)
+
     def fewha_solve(self, rhs, x=None, max_iters=1 << 20, rtol=1e-6):
         """x = M^{-1} rhs by PCG from 0 to a relative J^{-1}-norm residual
         rtol; returns (x, iterations, residual ratio)."""
@@ -238,6 +247,7 @@ class Context:
     apply_M = fewha_apply_M
     rhs = fewha_rhs
     reconstruct = fewha_reconstruct
+    reconstruct_noalloc = fewha_reconstruct_noalloc
 
 
 class Batch:
