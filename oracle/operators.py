@@ -10,7 +10,8 @@
   with c_gl = 1 - h_l/H for a laser guide star at altitude H and 1 for a
   natural guide star; phi_l is the bilinear interpolant of the layer nodes.
 * A = [Gamma_g P_gl] (eq. atmo).
-* C_g (eq. NGS-noise, eq. LGS-noise): sigma^2 I, or 2x2 blocks
+* C_g (eq. NGS-noise, eq. LGS-noise): sigma^2 I (sigma^2 = 1/n_photons when
+  the photon count is given), or 2x2 blocks
   sigma^2 (I + alpha_eta^2/f^2 beta beta^T) with the elongation
   beta = FWHM/H^2 (midpoint - launch) per subaperture.
 * C_hat_g^{-1} = (I - T) C_g^{-1} (I - T) for laser guide stars, T the
@@ -85,11 +86,20 @@ def propagation_matrix(D, wfs, layer, L):
     return sp.csr_matrix((vals, (rows, cols)), shape=(nc * nc, n * n))
 
 
+def noise_variance(w):
+    """Variance of one slope measurement of sensor w: 1 / n_photons when the
+    sensor states its photon count per subaperture and frame (eq. NGS-noise,
+    eq. LGS-noise), else sigma^2."""
+    if w.get("photons") is not None:
+        return 1.0 / float(w["photons"])
+    return float(w["sigma"]) ** 2
+
+
 def noise_blocks(cfg, geom, g):
     """Per active subaperture the 2x2 covariance C_ij (rows = (x, y))."""
     w = cfg["wfs"][g]
     mask = geom.masks[g]
-    s2 = w["sigma"] ** 2
+    s2 = noise_variance(w)
     nM = int(mask.sum())
     C = np.zeros((nM, 2, 2))
     C[:, 0, 0] = s2

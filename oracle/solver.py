@@ -15,6 +15,12 @@ Readings:
   dividing 0 by 0.
 * Open loop, a^(i+1) = (1 - gain) a^(i) + gain * F W^{-1} c^(i+1), F = I when
   the reconstruction layers sit at the DM altitudes.
+* Closed loop (cfg["loop"] == "closed"), with the two-step delay of
+  Algorithm 1: the measurement of step i+1 was taken with the commands
+  a^(i-1) on the mirrors, so the pseudo-open-loop slopes are
+  s + Gamma a^(i-1), Gamma being the mirrors' slope response; with F = I the
+  mirrors are the reconstruction layers and that response is A itself.  The
+  control is a^(i+1) = a^(i) + gain (a~ - a^(i-1)).
 """
 
 import numpy as np
@@ -95,10 +101,14 @@ class State:
 
 
 def frame(system, state, s, iters=None, gain=None):
-    """One open-loop time step; returns (new_state, layers phi = W^{-1} c)."""
+    """One time step (open or closed loop, F = I); returns (new_state,
+    layers phi = W^{-1} c)."""
     cfg = system.cfg
     iters = cfg["iters"] if iters is None else iters
     gain = cfg["gain"] if gain is None else gain
+    closed = cfg.get("loop", "open") == "closed"
+    if closed:  # pseudo-open-loop measurement (two-step delay)
+        s = np.asarray(s, dtype=np.float64) + system.apply_A(state.a_prev)
     b = system.rhs(s)
     r0 = (b - state.b) + state.r
     J = system.preconditioner()
@@ -109,5 +119,8 @@ def frame(system, state, s, iters=None, gain=None):
     new.b = b
     new.r = r
     new.a_prev = state.a.copy()
-    new.a = (1.0 - gain) * state.a + gain * phi
+    if closed:
+        new.a = state.a + gain * (phi - state.a_prev)
+    else:
+        new.a = (1.0 - gain) * state.a + gain * phi
     return new, phi
