@@ -128,8 +128,24 @@ FEWHA_API fewha_status fewha_set_prior(fewha_ctx* ctx, double alpha, double r0, 
  * sodium-layer FWHM (m), non-elongated spot FWHM f (rad, > 0). */
 FEWHA_API fewha_status fewha_set_noise(fewha_ctx* ctx, double alpha_eta, double na_fwhm, double spot_fwhm);
 
-/* Open-loop gain of Algorithm 1 (gain control lines): a <- (1-gain) a + gain a~. */
+/* Gain of Algorithm 1's control lines, in [0, 1]: open loop
+ * a <- (1-gain) a + gain a~; closed loop (fewha_set_loop) see there. */
 FEWHA_API fewha_status fewha_set_control(fewha_ctx* ctx, double gain);
+
+/* Open (closed = 0, the default) or closed loop (closed = 1), Algorithm 1.
+ * Closed loop, with the two-step delay: the slopes passed to a frame were
+ * measured with the commands a^(i-1) (the state's a_prev) on the mirrors,
+ * so the frame reconstructs from the pseudo-open-loop slopes
+ * s + Gamma a^(i-1), Gamma being the mirrors' slope response (A, since with
+ * F = I the mirrors are the reconstruction layers), and applies
+ * a^(i+1) = a^(i) + gain (a~ - a^(i-1)).  F = I only: FEWHA_EINVAL at
+ * fewha_finalize with fewha_set_fitting. */
+FEWHA_API fewha_status fewha_set_loop(fewha_ctx* ctx, int closed);
+
+/* Noise level from photon counts (eq. NGS-noise, eq. LGS-noise): sigma_g^2 =
+ * 1 / n_photons[g], the photons per subaperture and frame of sensor g (> 0),
+ * replacing the sigma of fewha_set_wfs (call after it; G = its count). */
+FEWHA_API fewha_status fewha_set_photons(fewha_ctx* ctx, int G, const double* n_photons);
 
 /* DM fitting (Sec. 4.1: with the layers away from the DM altitudes, fitting
  * the mirrors is an additional minimisation problem).  The commands a (the

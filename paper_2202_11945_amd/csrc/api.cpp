@@ -63,6 +63,7 @@ struct Plan {
   std::vector<Tile> hT;
   Range idwt_res, fdwt_res, pg, gt, pt, upd;
   Range sin;  // slopes input: 2 x 2 groups of the propagation stage's subaperture tiles
+  Range sin_frame, pg_pol;  // a frame's slope input: open-loop problems / closed-loop problems
   std::vector<Range> idwt_glob, fdwt_glob;
   Range fit_fwdL, fit_fwdD, fit_pt, fit_cg;  // DM fitting (empty when no problem fits)
   Range sinit, gprior, ghgt;                 // solve start, parameter-gradient reductions
@@ -374,7 +375,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   };
   std::vector<ProbLayout> lay(P.nprob);
   Carver cv;
-  std::vector<Tile> t_sin, t_r64gt;
+  std::vector<Tile> t_sin, t_sinf, t_pgpol, t_r64gt;
   std::vector<Tile> t_idwt_res, t_fdwt_res, t_pg, t_gt, t_pt, t_upd, t_sinit, t_gprior, t_ghgt, t_r64wfs, t_r64pt;
   HatTables hats;  // hat tables and band records of every problem and fitting view, one set per plan
   PtLists ptl;     // sensor lists of the propagation-adjoint tiles
@@ -397,6 +398,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     pd.n_slopes = (int)m.n_slopes;
     pd.n_act = (int)m.n_act();
     pd.fitted = m.fit.on ? 1 : 0;
+    pd.closed = m.closed ? 1 : 0;
     pd.gain = (float)m.gain;
     int tmp_total = 0;
     for (int l = 0; l < L; ++l) {
@@ -587,10 +589,16 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     for (int g = 0; g < G; ++g) {
       const WfsDev& wd = P.hW[pd.wfs0 + g];
       for (int ty = 0; ty < wd.tiles_side; ++ty)
-        for (int tx = 0; tx < wd.tiles_side; ++tx) t_pg.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
+        for (int tx = 0; tx < wd.tiles_side; ++tx) {
+          t_pg.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
+          if (m.closed) t_pgpol.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
+        }
       const int sg = cdiv(wd.tiles_side, 2);
       for (int ty = 0; ty < sg; ++ty)
-        for (int tx = 0; tx < sg; ++tx) t_sin.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
+        for (int tx = 0; tx < sg; ++tx) {
+          t_sin.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
+          if (!m.closed) t_sinf.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
+        }
       const int tc = cdiv(wd.nc, kGtS);
       for (int ty = 0; ty < tc; ++ty)
         for (int tx = 0; tx < tc; ++tx) t_gt.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
@@ -798,6 +806,8 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   P.fdwt_res = add(t_fdwt_res);
   P.pg = add(t_pg);
   P.sin = add(t_sin);
+  P.sin_frame = add(t_sinf);
+  P.pg_pol = add(t_pgpol);
   P.gt = add(t_gt);
   sort_xcd_runs_by_count(t_pt);
   P.pt = add(t_pt);
@@ -1148,7 +1158,8 @@ void enq_apply_M_core(const Plan& P, const LaunchArgs& a) {
 }
 
 void enq_reconstruct(const Plan& P, const LaunchArgs& a, int iters) {
-  launch_slopes_in(a, T(P, P.sin), P.sin.n);
+  launch_slopes_in(a, T(P, P.sin_frame), P.sin_frame.n);  // open loop: the measured slopes
+  launch_pgamma(a, T(P, P.pg_pol), P.pg_pol.n, PG_POL_IN);  // closed loop: s + Gamma P a^(i-1)
   enq_adjoint(P, a, GT_WEIGHTED, PT_PHIADJ);
   enq_fdwt(P, a, EPI_RHS, 0);
   for (int k = 0; k < iters; ++k) {
@@ -1555,6 +1566,27 @@ fewha_status fewha_set_control(fewha_ctx* c, double gain) {
   return FEWHA_OK;
 }
 
+fewha_status fewha_set_loop(fewha_ctx* c, int closed) {
+  CHECK_CTX(c);
+  if (c->finalized) return fail(c, FEWHA_ESTATE, "set_loop after finalize");
+  if (closed != 0 && closed != 1) return fail(c, FEWHA_EINVAL, "set_loop: closed must be 0 or 1");
+  c->m.closed = closed == 1;
+  return FEWHA_OK;
+}
+
+fewha_status fewha_set_photons(fewha_ctx* c, int G, const double* n_photons) {
+  CHECK_CTX(c);
+  if (c->finalized) return fail(c, FEWHA_ESTATE, "set_photons after finalize");
+  if (!c->m.have_wfs) return fail(c, FEWHA_ESTATE, "set_photons: call fewha_set_wfs first");
+  if (G != (int)c->m.wfs.size() || !n_photons)
+    return fail(c, FEWHA_EINVAL, "set_photons: need one photon count per sensor");
+  for (int g = 0; g < G; ++g)
+    if (!(n_photons[g] > 0.0) || !std::isfinite(n_photons[g]))
+      return fail(c, FEWHA_EINVAL, "set_photons: sensor " + std::to_string(g) + " needs a positive photon count");
+  for (int g = 0; g < G; ++g) c->m.wfs[g].d.sigma = 1.0 / std::sqrt(n_photons[g]);
+  return FEWHA_OK;
+}
+
 fewha_status fewha_set_fitting(fewha_ctx* c, int n_dm, const fewha_dm_desc* dms, int n_dirs, const double* dirs_xy,
                                int n_fit, int fit_iters, double eps_rel) {
   CHECK_CTX(c);
@@ -1595,6 +1627,8 @@ fewha_status fewha_set_tuning(fewha_ctx* c, const fewha_tuning* t) {
 fewha_status fewha_finalize(fewha_ctx* c) {
   CHECK_CTX(c);
   if (c->finalized) return fail(c, FEWHA_ESTATE, "finalize called twice");
+  if (c->m.closed && c->m.fit.on)
+    return fail(c, FEWHA_EINVAL, "closed loop needs F = I (the layers at the DM altitudes): no fitting step");
   fewha_status s = build_model(c->m, c->err);
   if (s != FEWHA_OK) return s;
   if (c->device >= 0) {

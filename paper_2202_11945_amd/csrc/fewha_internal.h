@@ -160,7 +160,7 @@ struct ProbDev {
   int n_slots_fdwt;        // producers of rho_0 and pi_k
   int n_slots_upd;         // producers of rho_{k+1}
   int fitted;              // 1 = the DM commands come from the fitting step
-  int pad1;
+  int closed;              // 1 = closed loop (pseudo-open-loop slopes, closed-loop control)
   float gain;
   float pad2;
   // internal buffers
@@ -306,6 +306,7 @@ struct HostModel {
   double alpha = 1, r0 = 0.15, L0 = 25, tau = 0;
   double alpha_eta = 0, na_fwhm = 11400, spot_fwhm = 4.85e-6;
   double gain = 1;
+  bool closed = false;  // closed-loop control (Algorithm 1), F = I only
   bool have_pupil = false, have_wfs = false, have_layers = false;
   // derived
   double h[6] = {0}, g[6] = {0};

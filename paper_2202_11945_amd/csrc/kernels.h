@@ -16,7 +16,9 @@ enum { EPI_APPLYM = 0, EPI_PCG = 1, EPI_RHS = 2, EPI_PLAIN = 3 };
 //   PG_DENSE   : phi -> dense slopes + tip/tilt partials (inside M)
 //   PG_DENSE_IN: io.in -> dense slopes + partials
 //   PG_RESID_IN: dense slopes -= Gamma P io.in, + partials (data residual s - A x)
-enum { PG_COMPACT = 0, PG_DENSE = 1, PG_DENSE_IN = 2, PG_RESID_IN = 3 };
+//   PG_POL_IN  : dense slopes = compact io.in + Gamma P a_prev (state), + partials
+//                (closed loop: pseudo-open-loop slopes, two-step delay)
+enum { PG_COMPACT = 0, PG_DENSE = 1, PG_DENSE_IN = 2, PG_RESID_IN = 3, PG_POL_IN = 4 };
 // Shack-Hartmann adjoint weighting
 enum { GT_PLAIN = 0, GT_WEIGHTED = 1 };
 // propagation adjoint destination

@@ -177,7 +177,7 @@ __device__ __forceinline__ float wave_beta(const ProbDev& pr, int mode, int iter
 // Final output of the inverse transform: phi = delta^{-1} W^T c, optionally
 // with the open-loop control update of Algorithm 1 (F = I).
 struct OutLoad {
-  float a;
+  float a, ap;
 };
 // The output's destinations and constants, read from the problem once per
 // kernel (a store through them could alias the problem record).
@@ -191,7 +191,7 @@ struct OutDst {
   float gain;
   int mode;  // out_mode, with OUT_FIT split by pr.fitted
 };
-enum { OUTD_PHI, OUTD_USER, OUTD_FITTED, OUTD_CONTROL };
+enum { OUTD_PHI, OUTD_USER, OUTD_FITTED, OUTD_CONTROL, OUTD_CLOSED };
 __device__ __forceinline__ OutDst out_dst(const ProbDev& pr, const IoDev& io, int out_mode) {
   OutDst d;
   d.phi = (gptr_w)pr.phi;
@@ -201,12 +201,17 @@ __device__ __forceinline__ OutDst out_dst(const ProbDev& pr, const IoDev& io, in
   d.a = d.aprev + pr.n_act;
   d.dm_out = (gptr_w)io.dm_out;
   d.gain = pr.gain;
-  d.mode = out_mode == OUT_PHI ? OUTD_PHI : out_mode == OUT_USER ? OUTD_USER : pr.fitted ? OUTD_FITTED : OUTD_CONTROL;
+  d.mode = out_mode == OUT_PHI    ? OUTD_PHI
+           : out_mode == OUT_USER ? OUTD_USER
+           : pr.fitted            ? OUTD_FITTED
+           : pr.closed            ? OUTD_CLOSED
+                                  : OUTD_CONTROL;
   return d;
 }
 __device__ __forceinline__ OutLoad out_fetch(const OutDst& d, int e) {
-  OutLoad o{0.f};
-  if (d.mode == OUTD_CONTROL) o.a = ((gptr_f)d.a)[e];
+  OutLoad o{0.f, 0.f};
+  if (d.mode == OUTD_CONTROL || d.mode == OUTD_CLOSED) o.a = ((gptr_f)d.a)[e];
+  if (d.mode == OUTD_CLOSED) o.ap = ((gptr_f)d.aprev)[e];
   return o;
 }
 __device__ __forceinline__ void out_finish(const OutDst& d, int e, float v, const OutLoad& o) {
@@ -217,9 +222,9 @@ __device__ __forceinline__ void out_finish(const OutDst& d, int e, float v, cons
   } else if (d.mode == OUTD_FITTED) {  // OUT_FIT, DM commands from the fitting step that follows
     d.phi[e] = v;
     if (d.layers_out) d.layers_out[e] = v;
-  } else {  // OUT_FIT, F = I
+  } else {  // OUT_FIT, F = I: open-loop or closed-loop control of Algorithm 1
     if (d.layers_out) d.layers_out[e] = v;
-    const float nw = (1.0f - d.gain) * o.a + d.gain * v;
+    const float nw = d.mode == OUTD_CLOSED ? o.a + d.gain * (v - o.ap) : (1.0f - d.gain) * o.a + d.gain * v;
     d.aprev[e] = o.a;
     d.a[e] = nw;
     if (d.dm_out) d.dm_out[e] = nw;
@@ -937,7 +942,7 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
   const ProbDev& pr = P[t.prob];
   const WfsDev& w = WD[t.slot];
   const IoDev& io = IO[t.prob];
-  const float* phi = (mode == PG_DENSE) ? pr.phi : io.in;
+  const float* phi = (mode == PG_DENSE) ? pr.phi : (mode == PG_POL_IN) ? io.state + 3L * pr.n_c : io.in;
   const int N = w.N, nc = w.nc;
   const int i0 = t.ty * kTileS, j0 = t.tx * kTileS;
   // subaperture owned by this thread and its operands
@@ -953,6 +958,9 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
       const gptr_f sd = (gptr_f)(pr.sd + w.s_off);
       dsx = sd[i * N + j];
       dsy = sd[N * N + i * N + j];
+    } else if (mode == PG_POL_IN && ci >= 0) {  // measured slopes of the active subaperture
+      dsx = ((gptr_f)io.in)[w.cs_off + ci];
+      dsy = ((gptr_f)io.in)[w.cs_off + w.n_active + ci];
     }
     if (w.blocks) {
       const gptr_f cb = (gptr_f)(pr.cinv + w.cinv_off + 3 * (i * N + j));
@@ -1053,6 +1061,9 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
     if (mode == PG_RESID_IN) {
       sx = dsx - sx;
       sy = dsy - sy;
+    } else if (mode == PG_POL_IN) {  // s + Gamma P a^(i-1)
+      sx = dsx + sx;
+      sy = dsy + sy;
     }
     if (w.blocks) {
       cx = cb0 * sx + cb1 * sy;

@@ -105,6 +105,11 @@ class Context:
                 self._masks.append(m)
                 d.mask = m.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))
         _check(_abi.fewha_set_wfs(self.h, len(cfg["wfs"]), ws), self.h)
+        if any(w.get("photons") is not None for w in cfg["wfs"]):
+            if not all(w.get("photons") is not None for w in cfg["wfs"]):
+                raise ValueError("photon counts must be given for every sensor or none")
+            ph = (c_double * len(cfg["wfs"]))(*[float(w["photons"]) for w in cfg["wfs"]])
+            _check(_abi.fewha_set_photons(self.h, len(cfg["wfs"]), ph), self.h)
         ls = (_abi.fewha_layer_desc * len(cfg["layers"]))()
         for k, l in enumerate(cfg["layers"]):
             ls[k].h, ls[k].n, ls[k].levels, ls[k].cn2 = l["h"], l["n"], l["levels"], l["cn2"]
@@ -114,6 +119,10 @@ class Context:
         no = cfg["noise"]
         _check(_abi.fewha_set_noise(self.h, no["alpha_eta"], no["na_fwhm"], no["spot_fwhm"]), self.h)
         _check(_abi.fewha_set_control(self.h, cfg.get("gain", 1.0)), self.h)
+        loop = cfg.get("loop", "open")
+        if loop not in ("open", "closed"):
+            raise ValueError("loop must be 'open' or 'closed'")
+        _check(_abi.fewha_set_loop(self.h, 1 if loop == "closed" else 0), self.h)
         if self.tuning is not None:
             _check(_abi.fewha_set_tuning(self.h, byref(_tuning(self.tuning))), self.h)
         if cfg.get("dms") and cfg.get("fit"):

@@ -153,3 +153,40 @@ def test_tuning_arguments_are_validated(lib):
         assert _abi.fewha_batch_create_tuned(byref(b), arr, 2, byref(_tuning({"streams": bad}))) == -1
     for ok in (0, 1, 2):
         assert _abi.fewha_batch_create_tuned(byref(b), arr, 2, byref(_tuning({"streams": ok}))) == -4
+
+
+def test_photon_counts_set_the_noise(lib):
+    # sigma_g^2 = 1 / n_photons (eq. NGS-noise, eq. LGS-noise): the exact
+    # Jacobi diagonal, which depends on every sensor's noise weight, matches
+    # the oracle's for a photon-count configuration (lowflux LGS, highflux NGS)
+    from oracle.operators import System
+    cfg = get_config("small")
+    for w in cfg["wfs"]:
+        w["photons"] = 500.0 if w["kind"] == "lgs" else 10000.0
+        w["sigma"] = 123.0  # replaced by the photon counts
+    S = System(cfg)
+    ctx = lib.Context(cfg, device=-1)
+    assert np.allclose(ctx.get_table(lib._abi.FEWHA_TABLE_PRECOND), S.preconditioner(), rtol=1e-10, atol=0)
+
+
+def test_loop_and_photon_arguments(lib):
+    from ctypes import byref, c_double
+    a = lib._abi
+    h = c_void_p()
+    assert a.fewha_create(byref(h), -1) == 0
+    two = (c_double * 2)(100.0, 100.0)
+    assert a.fewha_set_photons(h, 2, two) == -4  # before set_wfs
+    assert a.fewha_set_loop(h, 2) == -1
+    assert a.fewha_set_loop(h, 1) == 0
+    a.fewha_destroy(h)
+    cfg = get_config("small_fit", loop="closed")
+    with pytest.raises(lib.FewhaError) as e:
+        lib.Context(cfg, device=-1)
+    assert e.value.status == -1 and "F = I" in str(e.value)
+    cfg = get_config("small")
+    cfg["wfs"][0]["photons"] = 0.0
+    for w in cfg["wfs"][1:]:
+        w["photons"] = 100.0
+    with pytest.raises(lib.FewhaError) as e:
+        lib.Context(cfg, device=-1)
+    assert e.value.status == -1
