@@ -214,6 +214,20 @@ FEWHA_API fewha_status fewha_rhs(fewha_ctx* ctx, const float* slopes, float* b);
 FEWHA_API fewha_status fewha_reconstruct(fewha_ctx* ctx, const float* slopes, float* state,
                                          float* layers_out, float* dm_out, int iters);
 
+/* fewha_reconstruct for slopes in HOST memory that arrive sensor group by
+ * sensor group (pipelining, Sec. 4.3): the sensors are split into `chunks`
+ * contiguous groups (1 <= chunks <= min(G, 64)); each group's slopes are
+ * copied to the device on a copy stream of the context, and the frame takes
+ * in each group (dense grid, tip/tilt partial sums) as soon as its copy is
+ * done.  In closed loop the mirrors' part of the pseudo-open-loop slopes,
+ * Gamma a^(i-1), needs no measurement and runs while the copies are in
+ * flight.  Results are bitwise those of fewha_reconstruct on the same
+ * slopes in device memory.  host_slopes (n_slopes floats; pinned memory
+ * lets the copies run asynchronously) must stay valid and unchanged until
+ * the frame's work on the context stream has completed. */
+FEWHA_API fewha_status fewha_reconstruct_streamed(fewha_ctx* ctx, const float* host_slopes, float* state,
+                                                  float* layers_out, float* dm_out, int iters, int chunks);
+
 /* fewha_reconstruct without any allocation in the call, for callers that
  * cannot allocate device memory: code under HIP graph capture, tight
  * real-time serving loops, harnesses that forbid hipMalloc.  Same arguments,

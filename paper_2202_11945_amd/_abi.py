@@ -79,6 +79,7 @@ _SIGS = {
     "fewha_rhs": (c_int, [_P, _FP, _FP]),
     "fewha_reconstruct": (c_int, [_P, _FP, _FP, _FP, _FP, c_int]),
     "fewha_reconstruct_noalloc": (c_int, [_P, _FP, _FP, _FP, _FP, c_int]),
+    "fewha_reconstruct_streamed": (c_int, [_P, c_void_p, _FP, _FP, _FP, c_int, c_int]),
     "fewha_solve": (c_int, [_P, _FP, _FP, c_int, c_double, POINTER(c_int), POINTER(c_double)]),
     "fewha_solve_map": (c_int, [_P, _FP, _FP, _FP, c_int, c_double, POINTER(c_int), POINTER(c_double)]),
     "fewha_apply_Winv": (c_int, [_P, _FP, _FP]),

@@ -102,6 +102,12 @@ struct Plan {
   int* numflag_dev = nullptr;                // its device address
   // allocation-free frame: problem records whose work buffers live in the
   // library's static device scratch (see fewha_reconstruct_noalloc)
+  // streamed frames (context plans): the host slopes arrive by sensor groups
+  std::vector<int> sin_g;                    // problem 0: start of sensor g's tiles in the sin list (G + 1)
+  float* dslopes = nullptr;                  // device copy of the streamed slopes
+  hipStream_t copy_stream = nullptr;
+  hipEvent_t copy_start = nullptr;
+  std::vector<hipEvent_t> chunk_ev;
   ProbDev* dPna = nullptr;                   // in the arena, nprob_all records
   IoDev* na_io = nullptr;                    // per-call table at the start of the scratch
   size_t na_bytes = 0;                       // scratch the plan's frame needs
@@ -128,6 +134,11 @@ void destroy_plan(Plan* p) {
   for (float* s : p->prof_state)
     if (s) (void)hipFree(s);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->copy_stream) (void)hipStreamDestroy(p->copy_stream);
+  if (p->copy_start) (void)hipEventDestroy(p->copy_start);
+  for (hipEvent_t e : p->chunk_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (p->dslopes) (void)hipFree(p->dslopes);
   if (p->t0) (void)hipEventDestroy(p->t0);
   if (p->t1) (void)hipEventDestroy(p->t1);
   if (p->rho_host) (void)hipHostFree(p->rho_host);
@@ -594,6 +605,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
           if (m.closed) t_pgpol.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
         }
       const int sg = cdiv(wd.tiles_side, 2);
+      if (k == 0) P.sin_g.push_back((int)t_sin.size());
       for (int ty = 0; ty < sg; ++ty)
         for (int tx = 0; tx < sg; ++tx) {
           t_sin.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
@@ -606,6 +618,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
       for (int ty = 0; ty < tc16; ++ty)
         for (int tx = 0; tx < tc16; ++tx) t_r64gt.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
     }
+    if (k == 0) P.sin_g.push_back((int)t_sin.size());
     // node tiles of the propagation adjoint (kPtH rows x kPtW columns) with the
     // sensors that add to them; 32x32 tiles for the FP64 residual's adjoint
     for (int l = 0; l < L; ++l) {
@@ -1085,6 +1098,18 @@ fewha_status setup_noalloc(Plan& P, std::string& err) {
   return FEWHA_OK;
 }
 
+// Streamed frames of a context plan: the device slope buffer, a copy stream
+// and one event per sensor group (at most kMaxChunks groups).
+constexpr int kMaxChunks = 64;
+fewha_status setup_streamed(Plan& P, long n_slopes, int G, std::string& err) {
+  HIP_TRY(hipMalloc(&P.dslopes, sizeof(float) * std::max(n_slopes, 1L)));
+  HIP_TRY(hipStreamCreateWithFlags(&P.copy_stream, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&P.copy_start, hipEventDisableTiming));
+  P.chunk_ev.assign(std::min(G, kMaxChunks), nullptr);
+  for (hipEvent_t& e : P.chunk_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return FEWHA_OK;
+}
+
 // Stage a per-call table (nprob entries, zero-padded to nprob_all) and copy
 // it to the device, stream ordered.  The pinned slot is reused only after the
 // copy that read it has completed.
@@ -1157,9 +1182,16 @@ void enq_apply_M_core(const Plan& P, const LaunchArgs& a) {
   enq_adjoint(P, a, GT_WEIGHTED, PT_PHIADJ);
 }
 
+// One frame after its slopes are in the dense grid with their tip/tilt partials.
+void enq_frame_body(const Plan& P, const LaunchArgs& a, int iters);
+
 void enq_reconstruct(const Plan& P, const LaunchArgs& a, int iters) {
   launch_slopes_in(a, T(P, P.sin_frame), P.sin_frame.n);  // open loop: the measured slopes
   launch_pgamma(a, T(P, P.pg_pol), P.pg_pol.n, PG_POL_IN);  // closed loop: s + Gamma P a^(i-1)
+  enq_frame_body(P, a, iters);
+}
+
+void enq_frame_body(const Plan& P, const LaunchArgs& a, int iters) {
   enq_adjoint(P, a, GT_WEIGHTED, PT_PHIADJ);
   enq_fdwt(P, a, EPI_RHS, 0);
   for (int k = 0; k < iters; ++k) {
@@ -1636,7 +1668,8 @@ fewha_status fewha_finalize(fewha_ctx* c) {
     s = build_plan(c->plan, ms, c->device, c->m.tune_res > 0 ? c->m.tune_res : kResMax,
                    c->m.tune_pt_rows > 0 ? c->m.tune_pt_rows : 4, c->err);
     if (s != FEWHA_OK) return s;
-    if ((s = setup_noalloc(*c->plan, c->err)) != FEWHA_OK) {
+    if ((s = setup_noalloc(*c->plan, c->err)) != FEWHA_OK ||
+        (s = setup_streamed(*c->plan, c->m.n_slopes, (int)c->m.wfs.size(), c->err)) != FEWHA_OK) {
       destroy_plan(c->plan);
       c->plan = nullptr;
       return s;
@@ -1808,6 +1841,49 @@ fewha_status fewha_reconstruct_noalloc(fewha_ctx* c, const float* slopes, float*
   LaunchArgs a = args(P, c->stream, P.na_io);
   a.P = P.dPna;
   enq_reconstruct(P, a, iters);
+  return finish(c);
+}
+
+fewha_status fewha_reconstruct_streamed(fewha_ctx* c, const float* host_slopes, float* state, float* layers_out,
+                                        float* dm_out, int iters, int chunks) {
+  fewha_status s = ready(c);
+  if (s != FEWHA_OK) return s;
+  if (!host_slopes || !state) return fail(c, FEWHA_EINVAL, "reconstruct_streamed: null slopes or state");
+  if (iters < 0 || iters > kMaxIters) return fail(c, FEWHA_EINVAL, "reconstruct_streamed: iters must lie in [0, 256]");
+  if (((uintptr_t)state & 15) != 0) return fail(c, FEWHA_EINVAL, "reconstruct_streamed: state must be 16-byte aligned");
+  Plan& P = *c->plan;
+  const HostModel& m = c->m;
+  const int G = (int)m.wfs.size();
+  if (chunks < 1 || chunks > (int)P.chunk_ev.size())
+    return fail(c, FEWHA_EINVAL, "reconstruct_streamed: chunks must lie in [1, min(sensors, 64)]");
+  std::string& err = c->err;
+  const hipStream_t st = c->stream;
+  // the copies wait for earlier work on the stream (the previous frame reads the buffer)
+  HIP_TRY(hipEventRecord(P.copy_start, st));
+  HIP_TRY(hipStreamWaitEvent(P.copy_stream, P.copy_start, 0));
+  auto soff = [&](int g) { return g < G ? (long)m.slope_off[g] : m.n_slopes; };
+  for (int q = 0; q < chunks; ++q) {
+    const int g0 = (int)((long)G * q / chunks), g1 = (int)((long)G * (q + 1) / chunks);
+    const long o = soff(g0), n = soff(g1) - o;
+    if (n > 0)
+      HIP_TRY(hipMemcpyAsync(P.dslopes + o, host_slopes + o, sizeof(float) * n, hipMemcpyHostToDevice, P.copy_stream));
+    HIP_TRY(hipEventRecord(P.chunk_ev[q], P.copy_stream));
+  }
+  std::vector<IoDev> io(1);
+  io[0].in = P.dslopes;
+  io[0].state = state;
+  io[0].layers_out = layers_out;
+  io[0].dm_out = dm_out;
+  if ((s = upload_io(P, io, st, P.dIO, err)) != FEWHA_OK) return s;
+  const LaunchArgs a = args(P, st, P.dIO);
+  // closed loop: the mirrors' part of the pseudo-open-loop slopes while the measurement arrives
+  if (m.closed) launch_pgamma(a, T(P, P.pg), P.pg.n, PG_APREV);
+  for (int q = 0; q < chunks; ++q) {
+    const int g0 = (int)((long)G * q / chunks), g1 = (int)((long)G * (q + 1) / chunks);
+    HIP_TRY(hipStreamWaitEvent(st, P.chunk_ev[q], 0));
+    launch_slopes_in(a, T(P, P.sin) + P.sin_g[g0], P.sin_g[g1] - P.sin_g[g0], m.closed ? 1 : 0);
+  }
+  enq_frame_body(P, a, iters);
   return finish(c);
 }
 

@@ -18,7 +18,9 @@ enum { EPI_APPLYM = 0, EPI_PCG = 1, EPI_RHS = 2, EPI_PLAIN = 3 };
 //   PG_RESID_IN: dense slopes -= Gamma P io.in, + partials (data residual s - A x)
 //   PG_POL_IN  : dense slopes = compact io.in + Gamma P a_prev (state), + partials
 //                (closed loop: pseudo-open-loop slopes, two-step delay)
-enum { PG_COMPACT = 0, PG_DENSE = 1, PG_DENSE_IN = 2, PG_RESID_IN = 3, PG_POL_IN = 4 };
+//   PG_APREV   : dense slopes = Gamma P a_prev (state), + partials (the mirrors'
+//                part of the pseudo-open-loop slopes, before the measurement arrives)
+enum { PG_COMPACT = 0, PG_DENSE = 1, PG_DENSE_IN = 2, PG_RESID_IN = 3, PG_POL_IN = 4, PG_APREV = 5 };
 // Shack-Hartmann adjoint weighting
 enum { GT_PLAIN = 0, GT_WEIGHTED = 1 };
 // propagation adjoint destination
@@ -47,7 +49,9 @@ void launch_idwt_glob(const LaunchArgs& a, const Tile* tiles, int ntiles, int sr
 void launch_fdwt_glob(const LaunchArgs& a, const Tile* tiles, int ntiles, int epi, int iter, int step);
 void launch_fdwt_res(const LaunchArgs& a, const Tile* tiles, int ntiles, int epi, int iter);
 void launch_pgamma(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode);
-void launch_slopes_in(const LaunchArgs& a, const Tile* tiles, int ntiles);
+// compact slopes io.in -> dense grid + tip/tilt partials; add = 1: added to the
+// dense grid's current values (closed loop after PG_APREV)
+void launch_slopes_in(const LaunchArgs& a, const Tile* tiles, int ntiles, int add = 0);
 void launch_gammaT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode);
 void launch_pT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode);
 void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter);

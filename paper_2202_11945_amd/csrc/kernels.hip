@@ -942,7 +942,9 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
   const ProbDev& pr = P[t.prob];
   const WfsDev& w = WD[t.slot];
   const IoDev& io = IO[t.prob];
-  const float* phi = (mode == PG_DENSE) ? pr.phi : (mode == PG_POL_IN) ? io.state + 3L * pr.n_c : io.in;
+  const float* phi = (mode == PG_DENSE)                          ? pr.phi
+                     : (mode == PG_POL_IN || mode == PG_APREV) ? io.state + 3L * pr.n_c
+                                                               : io.in;
   const int N = w.N, nc = w.nc;
   const int i0 = t.ty * kTileS, j0 = t.tx * kTileS;
   // subaperture owned by this thread and its operands
@@ -1098,7 +1100,7 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
 // subaperture (t / 16, t mod 16) of each, so all its loads are in flight
 // together; each tile's sums are formed as over a workgroup of its own.
 __global__ __launch_bounds__(256) void k_slopes_in(const ProbDev* P, const WfsDev* WD, const IoDev* IO,
-                                                   const Tile* tiles) {
+                                                   const Tile* tiles, int add) {
   __shared__ float sh[16 * 4];
   typedef const int __attribute__((address_space(1)))* gptr_i;
   const Tile t = my_tile(tiles);
@@ -1119,11 +1121,15 @@ __global__ __launch_bounds__(256) void k_slopes_in(const ProbDev* P, const WfsDe
     pos[u] = (i < N && j < N) ? i * N + j : -1;
     ci[u] = pos[u] >= 0 ? cmap[pos[u]] : -1;
   }
-  float sx[4], sy[4], c0[4], c1[4], c2[4];
+  float sx[4], sy[4], c0[4], c1[4], c2[4], ox[4], oy[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    sx[u] = sy[u] = c0[u] = c1[u] = c2[u] = 0.f;
+    sx[u] = sy[u] = c0[u] = c1[u] = c2[u] = ox[u] = oy[u] = 0.f;
     if (ci[u] >= 0) {
+      if (add) {  // the mirrors' slope response already in the dense grid (closed loop)
+        ox[u] = ((gptr_f)sd)[pos[u]];
+        oy[u] = ((gptr_f)sd)[N * N + pos[u]];
+      }
       sx[u] = in[cs0 + ci[u]];
       sy[u] = in[cs1 + ci[u]];
       if (w.blocks) {
@@ -1136,6 +1142,10 @@ __global__ __launch_bounds__(256) void k_slopes_in(const ProbDev* P, const WfsDe
   float a[16];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
+    if (add) {  // s + Gamma P a^(i-1), the sum the propagation kernel forms in one pass
+      sx[u] = sx[u] + ox[u];
+      sy[u] = sy[u] + oy[u];
+    }
     a[4 * u] = sx[u];
     a[4 * u + 1] = sy[u];
     a[4 * u + 2] = c0[u] * sx[u] + c1[u] * sy[u];
@@ -1865,8 +1875,8 @@ void launch_fdwt_res(const LaunchArgs& a, const Tile* tiles, int ntiles, int epi
 void launch_pgamma(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
   if (ntiles > 0) k_pgamma<<<ntiles, kSensThreads, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, mode);
 }
-void launch_slopes_in(const LaunchArgs& a, const Tile* tiles, int ntiles) {
-  if (ntiles > 0) k_slopes_in<<<ntiles, 256, 0, a.stream>>>(a.P, a.W, a.IO, tiles);
+void launch_slopes_in(const LaunchArgs& a, const Tile* tiles, int ntiles, int add) {
+  if (ntiles > 0) k_slopes_in<<<ntiles, 256, 0, a.stream>>>(a.P, a.W, a.IO, tiles, add);
 }
 void launch_gammaT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
   if (ntiles > 0) k_gammaT<<<ntiles, 256, 0, a.stream>>>(a.P, a.W, tiles, mode);

@@ -192,6 +192,21 @@ class Context:
                                       _ptr(layers_out, self.n_coeff), _ptr(dm_out, self.n_act), int(iters)),
                self.h)
 
+    def fewha_reconstruct_streamed(self, host_slopes, state, layers_out=None, dm_out=None, iters=None, chunks=1):
+        """fewha_reconstruct from slopes in a host float32 tensor (pinned for
+        asynchronous copies), taken in by `chunks` sensor groups as they
+        arrive.  The host tensor must stay unchanged until the stream's work
+        is done."""
+        import torch
+        if host_slopes.is_cuda or host_slopes.dtype != torch.float32 or not host_slopes.is_contiguous() \
+                or host_slopes.numel() < self.n_slopes:
+            raise ValueError("expected a contiguous float32 host tensor of n_slopes entries")
+        iters = self.cfg["iters"] if iters is None else iters
+        self._sync_stream()
+        _check(_abi.fewha_reconstruct_streamed(self.h, c_void_p(host_slopes.data_ptr()), _ptr(state, self.n_state),
+                                               _ptr(layers_out, self.n_coeff), _ptr(dm_out, self.n_act),
+                                               int(iters), int(chunks)), self.h)
+
     def fewha_reconstruct_noalloc(self, slopes, state, layers_out=None, dm_out=None, iters=None):
         """fewha_reconstruct with the work buffers in the library's static
         device scratch (no allocation in the call)."""
@@ -257,6 +272,7 @@ class Context:
     rhs = fewha_rhs
     reconstruct = fewha_reconstruct
     reconstruct_noalloc = fewha_reconstruct_noalloc
+    reconstruct_streamed = fewha_reconstruct_streamed
 
 
 class Batch:

@@ -83,3 +83,38 @@ def test_batch_mixing_open_and_closed_loops(gpu_lib):
     batch.close()
     for c in ctxs:
         c.close()
+
+
+@pytest.mark.parametrize("loop", ["open", "closed"])
+def test_streamed_frames_match_device_slopes(gpu_lib, loop):
+    # slopes from pinned host memory, taken in by sensor groups as their
+    # copies land (closed loop: the mirrors' slope response computed while
+    # they are in flight); two frames in a row, so the second frame's copies
+    # must wait for the first frame's reads of the device buffer.  Bitwise
+    # the frames of fewha_reconstruct on the same slopes in device memory.
+    import torch
+    print("\n[gpu-control] streamed", loop, flush=True)
+    cfg = get_config("maory_like", loop=loop, gain=0.6)
+    ctx = gpu_lib.Context(cfg, device=0)
+    state0 = to_dev(random_vector(ctx.n_state, 70, 1) * 0.1)
+    host = [torch.from_numpy(random_vector(ctx.n_slopes, 71, k)).pin_memory() for k in range(2)]
+    dev = [h.cuda() for h in host]
+
+    def chain(run):
+        st = state0.clone()
+        lay = torch.empty(ctx.n_coeff, device="cuda")
+        outs = []
+        for k in range(2):
+            run(k, st, lay)
+            outs.append(lay.clone())
+        torch.cuda.synchronize()
+        return [st] + outs
+
+    ref = chain(lambda k, st, lay: ctx.reconstruct(dev[k], st, lay, iters=4))
+    for chunks in (1, 3, 9):
+        got = chain(lambda k, st, lay: ctx.reconstruct_streamed(host[k], st, lay, iters=4, chunks=chunks))
+        for a, b in zip(ref, got):
+            assert torch.equal(a, b), (loop, chunks)
+    with pytest.raises(gpu_lib.FewhaError):
+        ctx.reconstruct_streamed(host[0], state0.clone(), iters=4, chunks=10)  # 9 sensors
+    ctx.close()
