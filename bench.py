@@ -43,25 +43,36 @@ def parse():
                    help="frames of the forward + implicit-backward leg (0 = skip)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
-    p.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
+    p.add_argument("--cpu-child", default=None, help=argparse.SUPPRESS)
+    p.add_argument("--no-extra", action="store_true",
+                   help="skip the legs beyond the timed workload (batched 64 uneven, large, paper MAORY, "
+                        "streamed slopes, bandwidth probes)")
     return p.parse_args()
 
 
 # ------------------------------------------------------------ CPU oracle leg
 
-def cpu_child(seconds):
+def cpu_child(workload, seconds):
     """Runs in a single-threaded child process: times the oracle's time step
-    on MAORY-like frames (set-up excluded) and prints frames/s as JSON."""
+    on consecutive frames of a workload (set-up excluded) and prints
+    frames/s as JSON.  maory_like: RHS, warm restart, 4 PCG iterations, W^-1
+    and control; large: 20 PCG iterations and the fitting CG."""
     import numpy as np
     from oracle.operators import System
     from oracle.solver import State, frame
     from synthetic import frozen_flow_frames, get_config, slope_noise
 
-    cfg = get_config(WORKLOAD)
+    cfg = get_config(workload)
+    t0 = time.perf_counter()
     S = System(cfg)
     S.preconditioner()
+    fit = None
+    if cfg.get("fit"):
+        from oracle.fitting import Fitting, frame_fitted
+        fit = Fitting(cfg)
+    setup = time.perf_counter() - t0
     sig = [w["sigma"] for w in cfg["wfs"]]
-    st = State(S.geom.n_coeff, S.geom.n_coeff)
+    st = State(S.geom.n_coeff, fit.n_act if fit else S.geom.n_coeff)
     gen = frozen_flow_frames(cfg, 10 ** 6, 77)
     n, spent = 0, 0.0
     while spent < seconds and n < 1000:
@@ -69,48 +80,79 @@ def cpu_child(seconds):
         s = S.apply_A(np.concatenate([p.astype(np.float64).ravel() for p in true]))
         s = s + slope_noise(S.geom.n_slopes, sig, 77, n)
         t0 = time.perf_counter()
-        st, _ = frame(S, st, s)
+        st, _ = frame_fitted(S, fit, st, s) if fit else frame(S, st, s)
         spent += time.perf_counter() - t0
         n += 1
-    print(json.dumps({"frames": n, "seconds": spent}))
+    print(json.dumps({"frames": n, "seconds": spent, "setup_s": setup}))
 
 
-def cpu_baseline(seconds):
+def cpu_start(workload, seconds):
+    """Starts the oracle timing child (one thread) so that it runs while the
+    GPU legs run on the device."""
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
         env[k] = "1"
-    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-child", "--cpu-seconds", str(seconds)],
-                         env=env, capture_output=True, text=True, timeout=600)
-    if out.returncode != 0:
-        sys.stderr.write(out.stderr)
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-child", workload, "--cpu-seconds",
+                             str(seconds)], env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+
+
+def cpu_host():
+    """The host CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def cpu_finish(proc, workload, iters_text):
+    try:
+        out, err = proc.communicate(timeout=900)
+    except subprocess.TimeoutExpired:
+        proc.kill()
         return None
-    r = json.loads(out.stdout.strip().splitlines()[-1])
+    if proc.returncode != 0:
+        sys.stderr.write(err)
+        return None
+    r = json.loads(out.strip().splitlines()[-1])
+    model, ncore = cpu_host()
     return {"value": r["frames"] / r["seconds"], "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": "%d consecutive MAORY-like frames (RHS, warm restart, %d PCG iterations, W^-1 and "
-                      "control) of the FP64 scipy oracle, single-threaded, %.1f s of CPU time; set-up "
-                      "(operators, exact J) excluded" % (r["frames"], 4, r["seconds"])}
+            "cpu_model": model, "cores_available": ncore,
+            "sample": "%d consecutive %s frames (%s) of the FP64 scipy oracle, one thread (OMP/BLAS 1), "
+                      "%.1f s of CPU time, run beside the GPU legs on a core of its own; set-up (operators, exact "
+                      "J%s) %.1f s, excluded" % (r["frames"], workload, iters_text, r["seconds"],
+                                                 ", fitting operators" if workload == "large" else "",
+                                                 r["setup_s"])}
 
 
 # ------------------------------------------------------------ GPU legs
 
-def algorithmic_bytes(cfg, n_slopes_dense, n_corners):
+def algorithmic_bytes(cfg, n_slopes, n_corners, res=128):
     """Bytes each stage moves per problem when every operand is read once
-    and every result written once (FP32)."""
-    R = 128
+    and every result written once (FP32), with resident transform side res.
+    n_slopes counts the active subapertures' slopes (sum over sensors of
+    2 |M_g|), n_corners the sensors' corner grids."""
     n_c = sum(l["n"] ** 2 for l in cfg["layers"])
-    n_res = sum(min(l["n"], R) ** 2 for l in cfg["layers"])
-    glob = [l["n"] for l in cfg["layers"] if l["n"] > R]
-    idwt_glob = sum(17 * (m // 2) ** 2 for n in glob for m in [n])  # one global level per layer here
-    fdwt_glob = sum(11 * (n // 2) ** 2 for n in glob)
-    res_in = sum(min(l["n"], R) ** 2 for l in cfg["layers"])
+    n_res = sum(min(l["n"], res) ** 2 for l in cfg["layers"])
+    # global levels: output (inverse) / input (forward) sides 2 res .. n
+    glob = [m for l in cfg["layers"] for m in (2 ** k for k in range(1, 16)) if res < m <= l["n"]]
     return {
-        "IDWT_RES": 4 * (4 * n_res + res_in),
-        "IDWT_GLOB": 4 * idwt_glob,
-        "P_GAMMA": 4 * (n_c + n_slopes_dense),
-        "GAMMA_T": 4 * (n_slopes_dense + n_corners),
+        # r, J^{-1}, p_old read, p_new and the output written per coefficient
+        "IDWT_RES": 4 * 5 * n_res,
+        # coarse block + 3 detail quadrants x (r, J^{-1}, p_old) read, p_new and the output written
+        "IDWT_GLOB": 4 * sum(17 * (m // 2) ** 2 for m in glob),
+        "P_GAMMA": 4 * (n_c + n_slopes),
+        "GAMMA_T": 4 * (n_slopes + n_corners),
         "P_T": 4 * (n_corners + n_c),
-        "FDWT_GLOB": 4 * fdwt_glob,
-        "FDWT_RES": 4 * (res_in + 2 * n_res),
+        # input read, coarse block written, epilogue p read and q written for 3 quadrants
+        "FDWT_GLOB": 4 * sum(11 * (m // 2) ** 2 for m in glob),
+        # input read, epilogue p read and q written per coefficient
+        "FDWT_RES": 4 * 3 * n_res,
+        # x, p, r, q, J^{-1} read, x and r written
         "UPDATE": 4 * 7 * n_c,
     }
 
@@ -134,6 +176,255 @@ def measured_traffic(stage, batch, tuning):
                 and f[5] == tune):
             return float(f[3])
     return None
+
+
+def pool_index(i, n):
+    """Frame of an n-frame pool used at step i: forward then backward through
+    the pool (0, 1, .., n-1, n-2, .., 1, 0, 1, ..), so that consecutive steps
+    always use frames one frozen-flow step apart and the warm start never
+    jumps across the pool."""
+    if n <= 1:
+        return 0
+    k = i % (2 * n - 2)
+    return k if k < n else 2 * n - 2 - k
+
+
+def measure_peaks():
+    """Achievable bandwidths of this device, measured with torch's copy and
+    sum kernels: a 1 GiB copy (HBM, read + write) and a 1 GiB sum (HBM read),
+    and the same on 32 MiB buffers replayed hot (a 64 MiB copy working set,
+    held by the 256 MB MALL).  GB/s = bytes moved / time, HIP events."""
+    import torch
+    out = {}
+    for name, nbytes, reps in (("hbm", 1 << 30, 20), ("mall", 32 << 20, 400)):
+        n = nbytes // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty(n, device="cuda")
+        for kind in ("copy", "read"):
+            run = (lambda: dst.copy_(src)) if kind == "copy" else (lambda: src.sum())
+            for _ in range(3):
+                run()
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(reps):
+                run()
+            t1.record()
+            t1.synchronize()
+            moved = nbytes * (2 if kind == "copy" else 1)
+            out["%s_%s_GBs" % (name, kind)] = moved * reps / (t0.elapsed_time(t1) * 1e-3) / 1e9
+        del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
+def problem_bytes(fw, ctx, res):
+    """algorithmic_bytes of a context's configuration, with its active slope count."""
+    cfg = ctx.cfg
+    n_cor = sum((w["n_subap"] + 1) ** 2 for w in cfg["wfs"])
+    return algorithmic_bytes(cfg, ctx.n_slopes, n_cor, res)
+
+
+def stage_roofline(fw, batch, ctxs, tuning, iters, peaks, reps=50):
+    """Per-stage launch times of a batch (HIP events on its stream), the
+    stage with the largest share of a frame and its roofline figures."""
+    stage_us = {}
+    for sid, name in enumerate(STAGES):
+        stage_us[name] = batch.time_stage(sid, reps=reps)
+    launches = {"IDWT_RES": iters + 1, "IDWT_GLOB": iters + 1, "P_GAMMA": iters, "GAMMA_T": iters + 1,
+                "P_T": iters + 1, "FDWT_GLOB": iters + 1, "FDWT_RES": iters + 1, "UPDATE": iters}
+    share = {k: stage_us[k][0] * launches[k] for k in STAGES if stage_us[k][1] > 0}
+    dom = max(share, key=share.get)
+    per = [problem_bytes(fw, c, tuning["dwt_resident"]) for c in ctxs]
+    dom_bytes = sum(b[dom] for b in per)
+    us = stage_us[dom][0]
+    achieved = dom_bytes / (us * 1e-6) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": dom_bytes,
+            "problems_per_launch": len(ctxs), "avg_launch_us": us}
+    if peaks:
+        roof["frac_of_measured_hbm_copy"] = achieved / peaks["hbm_copy_GBs"]
+        roof["frac_of_measured_mall_copy"] = achieved / peaks["mall_copy_GBs"]
+    stage_frac = {k: (sum(b[k] for b in per) / (stage_us[k][0] * 1e-6) / 1e9) / HBM_PEAK_GBS
+                  for k in STAGES if stage_us[k][1] > 0}
+    return stage_us, roof, stage_frac
+
+
+def config3_leg(fw, peaks, replays=100):
+    """The batched workload of uneven sizes: 64 independent reconstructions
+    (32 MAORY-like, 32 VLT-like, each with its own Cn2 weights, r0 and sigma),
+    6 PCG iterations, one graph replay per step, autotuned launch shapes."""
+    import numpy as np
+    import torch
+    from paper_2202_11945_amd import autotune
+    from synthetic import frozen_flow_frames, slope_noise
+    from synthetic.configs import batch_mix
+    cfgs = batch_mix(32, 32, 3)
+    ctxs = [fw.Context(c, device=0) for c in cfgs]
+    pool = []
+    for k, (c, cfg) in enumerate(zip(ctxs, cfgs)):
+        mask = c.get_table(fw._abi.FEWHA_TABLE_MASK)
+        per, o = [], 0
+        for w in cfg["wfs"]:
+            per.append(2 * int(mask[o:o + w["n_subap"] ** 2].sum()))
+            o += w["n_subap"] ** 2
+        frames = []
+        for f, true in enumerate(frozen_flow_frames(cfg, 4, 3000 + k)):
+            phi = torch.from_numpy(np.concatenate([p.ravel() for p in true])).cuda()
+            s = c.apply_A(phi)
+            s += torch.from_numpy(slope_noise(per, [w["sigma"] for w in cfg["wfs"]], 3000 + k, f)).cuda()
+            frames.append(s)
+        pool.append(frames)
+    tune = autotune.tune(ctxs, 6)
+    batch = fw.Batch(ctxs, tuning=tune)
+    states = [torch.zeros(c.n_state, device="cuda") for c in ctxs]
+
+    def step(i):
+        batch.reconstruct([pool[k][pool_index(i, 4)] for k in range(len(ctxs))], states, iters=6, use_graph=True)
+
+    for i in range(10):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(replays):
+        step(10 + i)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / replays
+    # the same frames as 64 sequential plain-path reconstructions
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(3):
+        for k, c in enumerate(ctxs):
+            c.reconstruct(pool[k][pool_index(i, 4)], states[k], iters=6)
+    torch.cuda.synchronize()
+    plain = 3 * len(ctxs) / (time.perf_counter() - t0)
+    tb = batch if tune.get("streams", 1) == 1 else None
+    out = {"workload": "64 independent reconstructions: 32 MAORY-like + 32 VLT-like (8 m, 4 LGS 40x40, 5 layers "
+                       "64x64), own Cn2 / r0 / sigma each, 6 PCG iterations, one graph replay per step",
+           "frames_per_s": len(ctxs) / dt, "ms_per_step": dt * 1e3, "steps": replays,
+           "plain_path_frames_per_s": plain, "speedup_vs_plain": len(ctxs) / dt / plain, "tuning": tune}
+    if tb is None:  # stage times need the single-stream plan: time a copy built with streams = 1
+        tb = fw.Batch(ctxs, tuning=dict(tune, streams=1))
+        tb.reconstruct([pool[k][0] for k in range(len(ctxs))], [s.clone() for s in states], iters=6,
+                       use_graph=True)
+    stage_us, roof, frac = stage_roofline(fw, tb, ctxs, tune, 6, peaks)
+    out["stage_us"] = {k: round(v[0], 3) for k, v in stage_us.items()}
+    out["stage_hbm_frac"] = {k: round(v, 3) for k, v in frac.items()}
+    out["roofline"] = roof
+    if tb is not batch:
+        tb.close()
+    batch.close()
+    for c in ctxs:
+        c.close()
+    return out
+
+
+def config5_leg(fw, replays=5, B=32):
+    """The large workload: 9 layers (0-20 km, 256 x 256 above 10 km), 6 LGS
+    80x80 with 2x2 spot-elongation noise blocks, 20 PCG iterations, then the
+    fitting CG onto 3 DMs over 9 directions; 32 independent frame sequences
+    of the same system per graph replay."""
+    import numpy as np
+    import torch
+    from synthetic import frozen_flow_frames, get_config
+    cfg = get_config("large")
+    t0 = time.time()
+    ctx = fw.Context(cfg, device=0)
+    setup_s = time.time() - t0
+    batch = fw.Batch([ctx] * B)
+    slopes = []
+    for k, true in enumerate(frozen_flow_frames(cfg, 2, 5000)):
+        phi = torch.from_numpy(np.concatenate([p.ravel() for p in true])).cuda()
+        slopes.append(ctx.apply_A(phi))
+    states = [torch.zeros(ctx.n_state, device="cuda") for _ in range(B)]
+    for i in range(2):
+        batch.reconstruct([slopes[(i + k) % 2] for k in range(B)], states, iters=20, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(replays):
+        batch.reconstruct([slopes[(i + k) % 2] for k in range(B)], states, iters=20, use_graph=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / replays
+    batch.close()
+    ctx.close()
+    return {"workload": "9 layers (0-20 km; 128x128 up to 10 km, 256x256 above), 6 LGS 80x80 with 2x2 "
+                        "elongation noise blocks, 20 PCG iterations, fitting CG (10 iterations) onto 3 DMs over "
+                        "9 directions; %d sequences per graph replay" % B,
+            "frames_per_s": B / dt, "ms_per_step": dt * 1e3, "steps": replays, "context_setup_s": setup_s}
+
+
+def latency(run, nf):
+    """p50 / p99 of per-call device time (HIP events around each call on the
+    current stream, synchronized after each) and the back-to-back rate."""
+    import torch
+    for i in range(10):
+        run(i)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nf)]
+    for i in range(nf):
+        ev[i][0].record()
+        run(i)
+        ev[i][1].record()
+        torch.cuda.synchronize()
+    per_frame = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(nf):
+        run(i)
+    torch.cuda.synchronize()
+    return {"p50_us": per_frame[len(per_frame) // 2], "p99_us": per_frame[int(0.99 * (len(per_frame) - 1))],
+            "back_to_back_us": (time.perf_counter() - t0) / nf * 1e6}
+
+
+def paper_maory_leg(fw, nf=100):
+    """The paper's own MAORY system (37 m, 11 % obstruction, 6 LGS 74x74 + 3
+    NGS, layers 128/64/64 at 0/4/12.7 km): single-frame latency of the graph
+    path (autotuned) at 2 and 4 PCG iterations, beside the paper's 1.48 ms."""
+    import numpy as np
+    import torch
+    from paper_2202_11945_amd import autotune
+    from synthetic import frozen_flow_frames, get_config
+    cfg = get_config("paper_maory")
+    ctx = fw.Context(cfg, device=0)
+    slopes = []
+    for true in frozen_flow_frames(cfg, 4, 6000):
+        phi = torch.from_numpy(np.concatenate([p.ravel() for p in true])).cuda()
+        slopes.append(ctx.apply_A(phi))
+    out = {"workload": "paper MAORY: 37 m, 6 LGS 74x74 + 3 NGS 2x2, layers 128/64/64, single frame, graph path",
+           "paper_us_per_frame_2_iters": 1480.0}
+    for iters in (2, 4):
+        tune = autotune.tune([ctx], iters)
+        b = fw.Batch([ctx], tuning=tune)
+        st = torch.zeros(ctx.n_state, device="cuda")
+        lay = torch.empty(ctx.n_coeff, device="cuda")
+        out["iters_%d" % iters] = dict(latency(lambda i: b.reconstruct([slopes[pool_index(i, 4)]], [st], [lay],
+                                                                       iters=iters, use_graph=True), nf),
+                                       tuning={k: tune[k] for k in ("dwt_resident", "pt_rows")})
+        b.close()
+    ctx.close()
+    return out
+
+
+def streamed_leg(fw, c0, pool_host, iters, nf=100):
+    """Single-frame latency with the slopes in pinned host memory: the frame
+    takes them in by sensor groups as their host-to-device copies land
+    (1 group = copy then frame), open and closed loop; PCIe included."""
+    import torch
+    from synthetic import get_config
+    out = {}
+    st = torch.zeros(c0.n_state, device="cuda")
+    lay = torch.empty(c0.n_coeff, device="cuda")
+    for chunks in (1, 3, 9):
+        out["open_%d_groups" % chunks] = latency(
+            lambda i: c0.reconstruct_streamed(pool_host[pool_index(i, len(pool_host))], st, lay, iters=iters,
+                                              chunks=chunks), nf)
+    cl = fw.Context(get_config("maory_like", loop="closed", gain=0.5), device=0)
+    stc = torch.zeros(cl.n_state, device="cuda")
+    for chunks in (1, 3, 9):
+        out["closed_%d_groups" % chunks] = latency(
+            lambda i: cl.reconstruct_streamed(pool_host[pool_index(i, len(pool_host))], stc, lay, iters=iters,
+                                              chunks=chunks), nf)
+    cl.close()
+    return out
 
 
 def gradient_leg(fw, pool, n_frames, rtol=1e-6):
@@ -168,13 +459,16 @@ def gradient_leg(fw, pool, n_frames, rtol=1e-6):
 def main():
     args = parse()
     if args.cpu_child:
-        cpu_child(args.cpu_seconds)
+        cpu_child(args.cpu_child, args.cpu_seconds)
         return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
               "(the batch of independent frame sequences is the unit that would shard across GPUs)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    # the oracle's timing runs on host cores of its own while the GPU legs run
+    cpu_jobs = {} if args.no_cpu_baseline else {w: cpu_start(w, args.cpu_seconds) for w in ("maory_like", "large")}
 
     import numpy as np
     import torch
@@ -238,15 +532,15 @@ def main():
                   (fw.Batch(ctxs[H:], tuning=tune_h), H, B, torch.cuda.Stream())]
 
     def step_one(i, use_graph=True):
-        batch.reconstruct([pool[k][i % args.pool] for k in range(B)], states, iters=args.iters,
+        batch.reconstruct([pool[k][pool_index(i, args.pool)] for k in range(B)], states, iters=args.iters,
                           use_graph=use_graph)
 
     def step_two(i, use_graph=True):
         for hb, k0, k1, st in halves:
             st.wait_stream(torch.cuda.current_stream())
             with torch.cuda.stream(st):
-                hb.reconstruct([pool[k][i % args.pool] for k in range(k0, k1)], states[k0:k1], iters=args.iters,
-                               use_graph=use_graph)
+                hb.reconstruct([pool[k][pool_index(i, args.pool)] for k in range(k0, k1)], states[k0:k1],
+                               iters=args.iters, use_graph=use_graph)
 
     def rate(run, n, first):
         for i in range(5):
@@ -294,28 +588,9 @@ def main():
     lay1 = torch.empty(c0.n_coeff, device=dev)
     nf = args.latency_frames
 
-    def lat(run):
-        for i in range(10):
-            run(i)
-        torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nf)]
-        for i in range(nf):
-            ev[i][0].record()
-            run(i)
-            ev[i][1].record()
-            torch.cuda.synchronize()
-        per_frame = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(nf):
-            run(i)
-        torch.cuda.synchronize()
-        return {"p50_us": per_frame[len(per_frame) // 2], "p99_us": per_frame[int(0.99 * (len(per_frame) - 1))],
-                "back_to_back_us": (time.perf_counter() - t0) / nf * 1e6}
-
-    lat_graph = lat(lambda i: single.reconstruct([pool[0][i % args.pool]], [st1], [lay1], iters=args.iters,
-                                                 use_graph=True))
-    lat_plain = lat(lambda i: c0.reconstruct(pool[0][i % args.pool], st1, lay1, iters=args.iters))
+    lat_graph = latency(lambda i: single.reconstruct([pool[0][pool_index(i, args.pool)]], [st1], [lay1],
+                                                     iters=args.iters, use_graph=True), nf)
+    lat_plain = latency(lambda i: c0.reconstruct(pool[0][pool_index(i, args.pool)], st1, lay1, iters=args.iters), nf)
 
     # plain path over the whole batch: B sequential unbatched, ungraphed frames
     torch.cuda.synchronize()
@@ -323,32 +598,37 @@ def main():
     npl = 5
     for i in range(npl):
         for k in range(B):
-            ctxs[k].reconstruct(pool[k][i % args.pool], states[k], iters=args.iters)
+            ctxs[k].reconstruct(pool[k][pool_index(i, args.pool)], states[k], iters=args.iters)
     torch.cuda.synchronize()
     plain_fps = B * npl / (time.perf_counter() - t0)
 
     # ---- per-stage kernel time (HIP events on the batch stream), in the
     # launch configuration of the timed step (one launch per batch) ----
-    stage_us = {}
-    tb, nb_prob, tune_t = (halves[0][0], H, tune_h) if two else (batch, B, tune_b)
-    for sid, name in enumerate(STAGES):
-        us, wg = tb.time_stage(sid, reps=50)
-        stage_us[name] = (us, wg)
-    launches = {"IDWT_RES": args.iters + 1, "IDWT_GLOB": args.iters + 1, "P_GAMMA": args.iters,
-                "GAMMA_T": args.iters + 1, "P_T": args.iters + 1, "FDWT_GLOB": args.iters + 1,
-                "FDWT_RES": args.iters + 1, "UPDATE": args.iters}
-    share = {k: stage_us[k][0] * launches[k] for k in STAGES}
-    dom = max(share, key=share.get)
-    n_sd = sum(2 * w["n_subap"] ** 2 for w in cfg["wfs"])
-    n_cor = sum((w["n_subap"] + 1) ** 2 for w in cfg["wfs"])
-    alg = algorithmic_bytes(cfg, n_sd, n_cor)
-    dom_bytes = alg[dom] * nb_prob
-    achieved = dom_bytes / (stage_us[dom][0] * 1e-6) / 1e9
-    traffic = measured_traffic(dom, nb_prob, tune_t)
+    peaks = None if args.no_extra else measure_peaks()
+    print("[bench] measured peaks: %s" % peaks, file=sys.stderr, flush=True)
+    tb, tb_ctxs, tune_t = (halves[0][0], ctxs[:H], tune_h) if two else (batch, ctxs, tune_b)
+    nb_prob = len(tb_ctxs)
+    stage_us, roof, stage_frac = stage_roofline(fw, tb, tb_ctxs, tune_t, args.iters, peaks)
+    dom = roof["kernel"]
+    roof["traffic"] = measured_traffic(dom, nb_prob, tune_t)
+
+    extra = {}
+    if not args.no_extra:
+        pool_host = [pool[0][f].cpu().pin_memory() for f in range(args.pool)]
+        for name, leg in (("streamed_slopes_us", lambda: streamed_leg(fw, c0, pool_host, args.iters)),
+                          ("paper_maory", lambda: paper_maory_leg(fw)),
+                          ("batched_uneven_64", lambda: config3_leg(fw, peaks)),
+                          ("large_9_layers", lambda: config5_leg(fw))):
+            t_leg = time.time()
+            extra[name] = leg()
+            print("[bench] %s leg: %.1f s" % (name, time.time() - t_leg), file=sys.stderr, flush=True)
 
     grad = None if args.grad_frames <= 0 else gradient_leg(fw, pool, args.grad_frames)
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
+    cpu = cpu_finish(cpu_jobs["maory_like"], "MAORY-like", "RHS, warm restart, 4 PCG iterations, W^-1, control") \
+        if cpu_jobs else None
+    cpu5 = cpu_finish(cpu_jobs["large"], "large 9-layer", "20 PCG iterations, fitting CG onto 3 DMs") \
+        if cpu_jobs else None
 
     out = {
         "metric": "FEWHA µs/frame and batched frames/s, MAORY-like FP32 vs plain GPU path",
@@ -379,15 +659,16 @@ def main():
         "gradient": grad,
         "stage_us": {k: round(v[0], 3) for k, v in stage_us.items()},
         "stage_workgroups": {k: v[1] for k, v in stage_us.items()},
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": dom_bytes, "problems_per_launch": nb_prob,
-                     "avg_launch_us": stage_us[dom][0]},
+        "stage_hbm_frac": {k: round(v, 3) for k, v in stage_frac.items()},
+        "measured_peaks_GBs": peaks,
+        "roofline": roof,
         "cpu_baseline": cpu,
+        "cpu_baseline_large": cpu5,
         "paper_context": {"us_per_frame": 1480.0, "hardware": "2x Xeon E5-2630v3, 9 OpenMP threads + AVX2",
                           "workload": "paper MAORY (37 m, 6 LGS 74x74, layers 128/64/64), 2 augmented-PCG "
                                       "iterations"},
     }
+    out.update(extra)
     print(json.dumps(out))
 
 

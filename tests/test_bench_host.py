@@ -16,11 +16,10 @@ import bench  # noqa: E402
 from synthetic import get_config  # noqa: E402
 
 
-def _maory_bytes():
+def _maory_bytes(res=128):
     cfg = get_config("maory_like")
-    n_sd = sum(2 * w["n_subap"] ** 2 for w in cfg["wfs"])
     n_cor = sum((w["n_subap"] + 1) ** 2 for w in cfg["wfs"])
-    return cfg, bench.algorithmic_bytes(cfg, n_sd, n_cor)
+    return cfg, bench.algorithmic_bytes(cfg, 53736, n_cor, res)
 
 
 def test_more_than_one_gpu_is_refused():
@@ -39,7 +38,29 @@ def test_algorithmic_bytes_of_the_maory_like_problem():
     assert alg["P_T"] == 4 * (39393 + n_c) == 550788
     # the update reads p, q, x, r, J^{-1} and writes x, r
     assert alg["UPDATE"] == 4 * 7 * n_c
+    # the sensor stages count the active subapertures' slopes (sum 2 |M_g|), not the dense grids
+    assert alg["P_GAMMA"] == 4 * (n_c + 53736)
+    assert alg["GAMMA_T"] == 4 * (53736 + 39393)
     assert all(v > 0 for v in alg.values())
+    # resident side 128: only the 256 x 256 layer's top level is global
+    assert alg["IDWT_GLOB"] == 4 * 17 * 128 ** 2 and alg["IDWT_RES"] == 4 * 5 * 3 * 128 ** 2
+    # resident side 64: the 128 x 128 layers' top level and two of the 256 layer's go global
+    _, alg64 = _maory_bytes(64)
+    assert alg64["IDWT_GLOB"] == 4 * 17 * (3 * 64 ** 2 + 128 ** 2)
+    assert alg64["FDWT_GLOB"] == 4 * 11 * (3 * 64 ** 2 + 128 ** 2)
+    assert alg64["IDWT_RES"] == 4 * 5 * 3 * 64 ** 2
+
+
+def test_active_slope_count_of_the_maory_like_problem(lib):
+    ctx = lib.Context(get_config("maory_like"), device=-1)
+    assert ctx.n_slopes == 53736
+
+
+def test_pool_frames_stay_adjacent_in_time():
+    seq = [bench.pool_index(i, 8) for i in range(40)]
+    assert seq[:16] == [0, 1, 2, 3, 4, 5, 6, 7, 6, 5, 4, 3, 2, 1, 0, 1]
+    assert all(abs(a - b) == 1 for a, b in zip(seq, seq[1:]))
+    assert [bench.pool_index(i, 1) for i in range(3)] == [0, 0, 0]
 
 
 def test_traffic_only_for_matching_sources_and_shapes():

@@ -242,3 +242,18 @@ def test_J_tau_threshold():
     S0 = System(cfg0)
     data = S0.preconditioner() - S0.D
     assert np.allclose(S.preconditioner(), data + np.maximum(S.D, 5.0), rtol=1e-12)
+
+
+def test_data_diagonal_scales_with_the_noise_variance():
+    # C_hat^{-1} = (I - T) sigma^{-2} (I - T) (or sigma^{-2} I) is linear in
+    # sigma^{-2}, so the data part of J scales with it when every sensor has
+    # the same diagonal noise
+    from oracle.operators import System
+    from synthetic import get_config
+    cfg = get_config("small")
+    for w in cfg["wfs"]:
+        w["sigma"] = 1.0
+    unit = System(cfg).data_diagonal()
+    for w in cfg["wfs"]:
+        w["sigma"] = 0.3
+    assert np.allclose(System(cfg).data_diagonal(), unit / 0.09, rtol=1e-13, atol=0)
