@@ -5,9 +5,9 @@ Readings:
 * The paper's preconditioner input J^{-1/2} (split form) and the textbook
   form z = J^{-1} r give the same iterates in exact arithmetic; the textbook
   form is used.
-* The augmented Krylov recycling of the previous search directions is not
-  specified in the paper (it cites another paper for it); the step uses the
-  warm restart only: initial guess c^(i), r_0 = (b^(i+1) - b^(i)) + r^(i).
+* Warm restart: initial guess c^(i), r_0 = (b^(i+1) - b^(i)) + r^(i); with
+  cfg["augment"] = m > 0 the step runs the augmented PCG of augmented.py
+  with the previous step's first m search directions (Sec. 3.3).
 * r^(i) is the final recurrence residual of the previous step.
 * A residual that vanishes exactly (a zero right-hand side) gives p = 0 and
   p^T M p = 0: the step then keeps the iterate (alpha = 0, and beta = 0 when
@@ -77,26 +77,45 @@ def pcg_to_tolerance(apply_M, b, Jdiag, rtol=1e-12, max_iters=100000, x0=None):
 
 
 class State:
-    """Algorithm 1's state between frames: c, b, r, a^(i-1), a^(i)."""
+    """Algorithm 1's state between frames: c, b, r, a^(i-1), a^(i) and, for
+    the augmented PCG, the previous step's search directions P and their
+    images Q = M P (at most `keep` of each).
 
-    def __init__(self, n_coeff, n_act):
+    Packed layout: [c | b | r | a_prev | a], then with keep > 0
+    [P_0 .. P_{keep-1} | Q_0 .. Q_{keep-1} | count, 0, 0, 0], the directions
+    past `count` zero."""
+
+    def __init__(self, n_coeff, n_act, keep=0):
         self.c = np.zeros(n_coeff)
         self.b = np.zeros(n_coeff)
         self.r = np.zeros(n_coeff)
         self.a_prev = np.zeros(n_act)
         self.a = np.zeros(n_act)
+        self.keep = keep
+        self.P = []
+        self.Q = []
 
     def pack(self):
-        return np.concatenate([self.c, self.b, self.r, self.a_prev, self.a])
+        parts = [self.c, self.b, self.r, self.a_prev, self.a]
+        if self.keep:
+            n = len(self.c)
+            pad = [np.zeros(n)] * (self.keep - len(self.P))
+            parts += list(self.P) + pad + list(self.Q) + pad + [np.array([len(self.P), 0.0, 0.0, 0.0])]
+        return np.concatenate(parts)
 
     @classmethod
-    def unpack(cls, v, n_coeff, n_act):
-        st = cls(n_coeff, n_act)
+    def unpack(cls, v, n_coeff, n_act, keep=0):
+        st = cls(n_coeff, n_act, keep)
         v = np.asarray(v, dtype=np.float64)
         o = 0
         for name, n in (("c", n_coeff), ("b", n_coeff), ("r", n_coeff), ("a_prev", n_act), ("a", n_act)):
             setattr(st, name, v[o:o + n].copy())
             o += n
+        if keep:
+            count = int(v[o + 2 * keep * n_coeff])
+            st.P = [v[o + k * n_coeff:o + (k + 1) * n_coeff].copy() for k in range(count)]
+            o += keep * n_coeff
+            st.Q = [v[o + k * n_coeff:o + (k + 1) * n_coeff].copy() for k in range(count)]
         return st
 
 
@@ -112,9 +131,14 @@ def frame(system, state, s, iters=None, gain=None):
     b = system.rhs(s)
     r0 = (b - state.b) + state.r
     J = system.preconditioner()
-    x, r, _ = pcg(system.apply_M, state.c, r0, J, iters)
+    keep = cfg.get("augment", 0)
+    new = State(len(state.c), len(state.a), keep)
+    if keep:  # augmented PCG with the previous step's directions (Sec. 3.3)
+        from .augmented import aug_pcg
+        x, r, new.P, new.Q, _ = aug_pcg(system.apply_M, state.c, r0, J, iters, state.P, state.Q, keep)
+    else:
+        x, r, _ = pcg(system.apply_M, state.c, r0, J, iters)
     phi = system.W_inv(x)
-    new = State(len(x), len(state.a))
     new.c = x
     new.b = b
     new.r = r
