@@ -142,6 +142,22 @@ FEWHA_API fewha_status fewha_set_control(fewha_ctx* ctx, double gain);
  * fewha_finalize with fewha_set_fitting. */
 FEWHA_API fewha_status fewha_set_loop(fewha_ctx* ctx, int closed);
 
+/* Augmented PCG (Sec. 3.3; Algorithm 1's augPCG line): every frame's PCG
+ * reuses the previous frame's first `keep` search directions W = P^(i) and
+ * their images A W = Q^(i) = M P^(i) (keep in [0, 4]; 0 = plain PCG, the
+ * default).  The paper defines the method by reference to another paper;
+ * this is the deflated CG of Saad, Yeung, Erhel & Guyomarc'h (2000) with
+ * the Jacobi preconditioner: the warm-start iterate and residual are
+ * projected so that W^T r_0 = 0 (x_0 = c + W G^{-1} W^T r_0,
+ * r_0 <- r_0 - A W G^{-1} W^T r_0, G = W^T A W), and each direction is
+ * p_j = J^{-1} r_j + beta p_{j-1} - W G^{-1} (A W)^T J^{-1} r_j.  G is
+ * factored by Cholesky in double precision; a direction with a non-positive
+ * pivot is dropped.  The state grows by 2 keep N_c + 4 floats: after
+ * [c | b | r | a_prev | a] come the keep directions, their images and the
+ * count of valid ones (an all-zero state has none: the first frame is the
+ * plain PCG).  Not available in fewha_reconstruct_noalloc. */
+FEWHA_API fewha_status fewha_set_augmentation(fewha_ctx* ctx, int keep);
+
 /* Noise level from photon counts (eq. NGS-noise, eq. LGS-noise): sigma_g^2 =
  * 1 / n_photons[g], the photons per subaperture and frame of sensor g (> 0),
  * replacing the sigma of fewha_set_wfs (call after it; G = its count). */
@@ -175,7 +191,8 @@ FEWHA_API fewha_status fewha_finalize(fewha_ctx* ctx);
  *   n_slopes    = sum_g 2 |M_g|
  *   n_layer_pts = N_c
  *   n_act       = number of DM commands (= N_c when F = I, else sum of n_act^2)
- *   n_state     = 3 N_c + 2 n_act (layout of the reconstruct state below). */
+ *   n_state     = 3 N_c + 2 n_act (layout of the reconstruct state below),
+ *                 plus 2 keep N_c + 4 with fewha_set_augmentation. */
 FEWHA_API fewha_status fewha_sizes(const fewha_ctx* ctx, long* n_coeff, long* n_slopes,
                                    long* n_layer_pts, long* n_act, long* n_state);
 

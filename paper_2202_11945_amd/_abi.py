@@ -65,6 +65,7 @@ _SIGS = {
     "fewha_set_noise": (c_int, [_P, c_double, c_double, c_double]),
     "fewha_set_control": (c_int, [_P, c_double]),
     "fewha_set_loop": (c_int, [_P, c_int]),
+    "fewha_set_augmentation": (c_int, [_P, c_int]),
     "fewha_set_photons": (c_int, [_P, c_int, POINTER(c_double)]),
     "fewha_set_fitting": (c_int, [_P, c_int, POINTER(fewha_dm_desc), c_int, POINTER(c_double), c_int, c_int,
                                   c_double]),

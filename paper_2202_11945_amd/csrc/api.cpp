@@ -64,6 +64,7 @@ struct Plan {
   Range idwt_res, fdwt_res, pg, gt, pt, upd;
   Range sin;  // slopes input: 2 x 2 groups of the propagation stage's subaperture tiles
   Range sin_frame, pg_pol;  // a frame's slope input: open-loop problems / closed-loop problems
+  Range aug;                // augmented PCG: vector-update chunks of the problems with augmentation
   std::vector<Range> idwt_glob, fdwt_glob;
   Range fit_fwdL, fit_fwdD, fit_pt, fit_cg;  // DM fitting (empty when no problem fits)
   Range sinit, gprior, ghgt;                 // solve start, parameter-gradient reductions
@@ -383,10 +384,11 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     size_t phi, phiadj, tmpa, tmpb, sd, vadj, part, p0, p1, q, dots, jinv, itab, ftab, cmap, cinv, gl;
     size_t sstate, gphi, glam, gslots, gitab, gftab;
     size_t a64, b64, sd64, u64, rslots, cinv64, ftab64, rbuf, x64;
+    size_t apdir, aqdir, aslots, afac;
   };
   std::vector<ProbLayout> lay(P.nprob);
   Carver cv;
-  std::vector<Tile> t_sin, t_sinf, t_pgpol, t_r64gt;
+  std::vector<Tile> t_sin, t_sinf, t_pgpol, t_aug, t_r64gt;
   std::vector<Tile> t_idwt_res, t_fdwt_res, t_pg, t_gt, t_pt, t_upd, t_sinit, t_gprior, t_ghgt, t_r64wfs, t_r64pt;
   HatTables hats;  // hat tables and band records of every problem and fitting view, one set per plan
   PtLists ptl;     // sensor lists of the propagation-adjoint tiles
@@ -410,6 +412,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     pd.n_act = (int)m.n_act();
     pd.fitted = m.fit.on ? 1 : 0;
     pd.closed = m.closed ? 1 : 0;
+    pd.aug_keep = m.aug_keep;
     pd.gain = (float)m.gain;
     int tmp_total = 0;
     for (int l = 0; l < L; ++l) {
@@ -561,7 +564,10 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     }
     pd.n_slots_fdwt = slot;
     const int nupd = cdiv(pd.n_c, kUpdChunk);
-    for (int c = 0; c < nupd; ++c) t_upd.push_back({k, 0, c, 0, c, 0, 0, 0});
+    for (int c = 0; c < nupd; ++c) {
+      t_upd.push_back({k, 0, c, 0, c, 0, 0, 0});
+      if (m.aug_keep > 0) t_aug.push_back({k, 0, c, 0, c, 0, 0, 0});
+    }
     pd.n_slots_upd = nupd;
     pd.n_dots = std::max(pd.n_slots_fdwt, pd.n_slots_upd);
     for (int sl = 0; sl < pd.n_slots_fdwt; ++sl) t_sinit.push_back({k, 0, 0, 0, sl, 0, 0, 0});
@@ -675,6 +681,10 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     pl_.ftab64 = cv.take(sizeof(double) * ftab64[k].size());
     pl_.rbuf = cv.take(nc4);
     pl_.x64 = cv.take(sizeof(double) * (size_t)pd.n_c);
+    pl_.apdir = cv.take(nc4 * std::max(pd.aug_keep, 1));
+    pl_.aqdir = cv.take(nc4 * std::max(pd.aug_keep, 1));
+    pl_.aslots = cv.take(sizeof(double) * (size_t)kAugGroups * pd.n_slots_upd);
+    pl_.afac = cv.take(sizeof(double) * kAugFac);
     P.hP.push_back(pd);
   }
   // ---- DM fitting views: (directions x layers) and (directions x DMs) ----
@@ -821,6 +831,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   P.sin = add(t_sin);
   P.sin_frame = add(t_sinf);
   P.pg_pol = add(t_pgpol);
+  P.aug = add(t_aug);
   P.gt = add(t_gt);
   sort_xcd_runs_by_count(t_pt);
   P.pt = add(t_pt);
@@ -908,6 +919,10 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     pd.ftab64 = (const double*)(base + l.ftab64);
     pd.rbuf = (float*)(base + l.rbuf);
     pd.x64 = (double*)(base + l.x64);
+    pd.aug_pdir = (float*)(base + l.apdir);
+    pd.aug_qdir = (float*)(base + l.aqdir);
+    pd.aug_slots = (double*)(base + l.aslots);
+    pd.aug_fac = (double*)(base + l.afac);
     P.rbuf.push_back(pd.rbuf);
     HIP_TRY(hipMemcpy(base + l.cinv64, cinv64[k].data(), sizeof(double) * cinv64[k].size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(base + l.ftab64, ftab64[k].data(), sizeof(double) * ftab64[k].size(), hipMemcpyHostToDevice));
@@ -1012,7 +1027,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   HIP_TRY(hipEventCreate(&P.t0));
   HIP_TRY(hipEventCreate(&P.t1));
   P.n_state.resize(P.nprob);
-  for (int k = 0; k < P.nprob; ++k) P.n_state[k] = 3L * P.hP[k].n_c + 2L * P.hP[k].n_act;
+  for (int k = 0; k < P.nprob; ++k) P.n_state[k] = models[k]->n_state();
   out = pl.release();
   return FEWHA_OK;
 }
@@ -1194,12 +1209,17 @@ void enq_reconstruct(const Plan& P, const LaunchArgs& a, int iters) {
 void enq_frame_body(const Plan& P, const LaunchArgs& a, int iters) {
   enq_adjoint(P, a, GT_WEIGHTED, PT_PHIADJ);
   enq_fdwt(P, a, EPI_RHS, 0);
+  // augmented PCG (Sec. 3.3): start projected against the previous frame's directions
+  launch_aug_gram(a, T(P, P.aug), P.aug.n);
+  launch_aug_init(a, T(P, P.aug), P.aug.n);
   for (int k = 0; k < iters; ++k) {
+    launch_aug_p(a, T(P, P.aug), P.aug.n, k);  // p_k of the problems with augmentation
     enq_idwt(P, a, k == 0 ? SRC_PUPD0 : SRC_PUPD, OUT_PHI, k);
     enq_apply_M_core(P, a);
     enq_fdwt(P, a, EPI_PCG, k);
     launch_update(a, T(P, P.upd), P.upd.n, k);
   }
+  launch_aug_store(a, T(P, P.aug), P.aug.n, iters);  // the next frame's W and A W
   enq_idwt(P, a, SRC_STATE_C, OUT_FIT, 0);
   if (P.fit_cg.n > 0) {  // DM fitting: CG on (sum_k B_k^T M B_k + eps I) a = sum_k B_k^T M P_k phi
     launch_fit_fwd(a, T(P, P.fit_fwdL), P.fit_fwdL.n);
@@ -1606,6 +1626,15 @@ fewha_status fewha_set_loop(fewha_ctx* c, int closed) {
   return FEWHA_OK;
 }
 
+fewha_status fewha_set_augmentation(fewha_ctx* c, int keep) {
+  CHECK_CTX(c);
+  if (c->finalized) return fail(c, FEWHA_ESTATE, "set_augmentation after finalize");
+  if (keep < 0 || keep > kAugMax)
+    return fail(c, FEWHA_EINVAL, "set_augmentation: keep must lie in [0, " + std::to_string(kAugMax) + "]");
+  c->m.aug_keep = keep;
+  return FEWHA_OK;
+}
+
 fewha_status fewha_set_photons(fewha_ctx* c, int G, const double* n_photons) {
   CHECK_CTX(c);
   if (c->finalized) return fail(c, FEWHA_ESTATE, "set_photons after finalize");
@@ -1687,7 +1716,7 @@ fewha_status fewha_sizes(const fewha_ctx* c, long* n_coeff, long* n_slopes, long
   if (n_slopes) *n_slopes = c->m.n_slopes;
   if (n_layer_pts) *n_layer_pts = c->m.n_c;
   if (n_act) *n_act = c->m.n_act();
-  if (n_state) *n_state = 3L * c->m.n_c + 2L * c->m.n_act();
+  if (n_state) *n_state = c->m.n_state();
   return FEWHA_OK;
 }
 
@@ -1819,7 +1848,8 @@ fewha_status fewha_reconstruct_noalloc(fewha_ctx* c, const float* slopes, float*
   if (iters < 0 || iters > kMaxIters) return fail(c, FEWHA_EINVAL, "reconstruct_noalloc: iters must lie in [0, 256]");
   if (((uintptr_t)state & 15) != 0) return fail(c, FEWHA_EINVAL, "reconstruct_noalloc: state must be 16-byte aligned");
   Plan& P = *c->plan;
-  if (c->m.fit.on) return fail(c, FEWHA_EINVAL, "reconstruct_noalloc: not available with the DM fitting step");
+  if (c->m.fit.on || c->m.aug_keep > 0)
+    return fail(c, FEWHA_EINVAL, "reconstruct_noalloc: not available with the DM fitting step or augmentation");
   if (P.na_bytes > kNoAllocBytes)
     return fail(c, FEWHA_EINVAL, "reconstruct_noalloc: the frame needs " + std::to_string(P.na_bytes) +
                                      " bytes of scratch; the static scratch holds " + std::to_string(kNoAllocBytes));

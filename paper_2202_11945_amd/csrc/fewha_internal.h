@@ -31,6 +31,18 @@ constexpr int kUpdChunk = 2048;   // coefficients per workgroup of the vector up
 constexpr int kDotRing = 256;     // PCG iterations whose inner products are kept (ring, power of two)
 constexpr int kGradChunk = 2048;  // coefficients per workgroup of the prior-term reductions
 constexpr double kTie = 1e-9;     // |t - round(t)| below which a sample sits on a grid line
+// Augmented PCG: at most kAugMax previous search directions per problem.
+// FP64 partial-sum groups (one slot per vector-update chunk) of a frame:
+// W^T r_0 (kAugMax), the lower triangle of W^T A W (row r, column k <= r:
+// group r (r + 1) / 2 + k), rho_0 of the projected residual, and
+// (A W)^T z_j for the two iteration parities.
+constexpr int kAugMax = 4;
+constexpr int kAugD = 0;
+constexpr int kAugG = kAugD + kAugMax;
+constexpr int kAugRho0 = kAugG + kAugMax * (kAugMax + 1) / 2;
+constexpr int kAugT = kAugRho0 + 1;
+constexpr int kAugGroups = kAugT + 2 * kAugMax;
+constexpr int kAugFac = kAugMax * kAugMax + kAugMax;  // doubles: Cholesky factor, then the kept flags
 
 // db3 analysis filters, passed by value to the transform kernels.
 struct Filter {
@@ -203,6 +215,16 @@ struct ProbDev {
   // PCG step that finds p^T M p <= 0 with a nonzero residual, or a
   // non-finite or negative inner product, stores the problem index + 1
   int* numflag;
+  // augmented PCG (Sec. 3.3): directions of the previous frame in the state
+  // after a_prev / a (aug_keep of them, then their images, then a count),
+  // this frame's first aug_keep directions and images, FP64 partial sums and
+  // the factor of W^T A W
+  int aug_keep;            // 0 = plain PCG
+  int aug_pad;
+  float* aug_pdir;         // aug_keep x N_c
+  float* aug_qdir;         // aug_keep x N_c
+  double* aug_slots;       // kAugGroups x n_slots_upd
+  double* aug_fac;         // kAugFac
 };
 
 // db3 filters in FP64 for the residual transforms.
@@ -307,6 +329,7 @@ struct HostModel {
   double alpha_eta = 0, na_fwhm = 11400, spot_fwhm = 4.85e-6;
   double gain = 1;
   bool closed = false;  // closed-loop control (Algorithm 1), F = I only
+  int aug_keep = 0;     // augmented PCG: previous search directions kept (0 = plain PCG)
   bool have_pupil = false, have_wfs = false, have_layers = false;
   // derived
   double h[6] = {0}, g[6] = {0};
@@ -323,6 +346,9 @@ struct HostModel {
   int tune_res = 0;  // resident transform side of the context's own plan (0 = default)
   int tune_pt_rows = 0;  // node rows per thread of the propagation adjoint (0 = default)
   long n_act() const { return fit.on ? fit.n_act : n_c; }
+  // [c | b | r | a_prev | a], then with augmentation the previous directions,
+  // their images and a count (4 floats, keeping 16-byte alignment)
+  long n_state() const { return 3L * n_c + 2L * n_act() + (aug_keep > 0 ? 2L * aug_keep * n_c + 4 : 0); }
 };
 
 // host set-up (setup.cpp); each returns FEWHA_OK or an error with a message

@@ -5,8 +5,10 @@
 
 namespace fewha {
 
-// source of the inverse transform
-enum { SRC_IN = 0, SRC_STATE_C = 1, SRC_PUPD0 = 2, SRC_PUPD = 3 };
+// source of the inverse transform (SRC_PJ: the search direction p_j as
+// formed by the augmented PCG's direction kernel; problems with augmentation
+// take it in place of SRC_PUPD0 / SRC_PUPD)
+enum { SRC_IN = 0, SRC_STATE_C = 1, SRC_PUPD0 = 2, SRC_PUPD = 3, SRC_PJ = 4 };
 // destination of the inverse transform
 enum { OUT_PHI = 0, OUT_USER = 1, OUT_FIT = 2 };
 // epilogue of the forward transform
@@ -82,6 +84,13 @@ struct Resid64Tiles {
 void launch64_resid_chain(const LaunchArgs& a, const Resid64Tiles& rt, const Filter64& F);
 // x64 = 0 (mode 0), x64 += io.in (1), io.state = (float) x64 (2)
 void launch64_iterate(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode);
+// augmented PCG over the vector-update chunks of augmented problems:
+// partial sums of W^T r_0 and W^T A W; the projected start (x_0, r_0, rho_0,
+// (A W)^T z_0); the direction p_j; the frame's directions into the state
+void launch_aug_gram(const LaunchArgs& a, const Tile* tiles, int ntiles);
+void launch_aug_init(const LaunchArgs& a, const Tile* tiles, int ntiles);
+void launch_aug_p(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter);
+void launch_aug_store(const LaunchArgs& a, const Tile* tiles, int ntiles, int iters);
 void launch_fit_fwd(const LaunchArgs& a, const Tile* tiles, int ntiles);
 void launch_fit_cg(const LaunchArgs& a, const FitDev* F, int nfit, int phase);
 

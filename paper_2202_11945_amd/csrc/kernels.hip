@@ -118,6 +118,23 @@ __device__ __forceinline__ int rho_count(const ProbDev& pr, int k) {
 __device__ __forceinline__ int rho_grp(int k) { return 2 * (k & (kDotRing - 1)); }
 __device__ __forceinline__ int pi_grp(int k) { return 2 * (k & (kDotRing - 1)) + 1; }
 
+// Search direction p_j and its image M p_j of iteration j: the augmented
+// PCG keeps its first aug_keep of each (the next frame's W and A W); later
+// ones, and those of the plain PCG, alternate between two buffers.
+__device__ __forceinline__ float* p_loc(const ProbDev& pr, int j) {
+  return pr.aug_keep > j ? pr.aug_pdir + (long)j * pr.n_c : ((j & 1) ? pr.pbuf1 : pr.pbuf0);
+}
+__device__ __forceinline__ float* q_loc(const ProbDev& pr, int j) {
+  return pr.aug_keep > j ? pr.aug_qdir + (long)j * pr.n_c : pr.q;
+}
+// rho_k = r_k^T J^{-1} r_k, summed by a wave in a fixed order; a problem with
+// augmentation forms rho_0 of its projected residual in slots of its own.
+__device__ __forceinline__ double rho_sum(const ProbDev& pr, int k) {
+  if (k == 0 && pr.aug_keep > 0)
+    return wave_sum_slots(pr.aug_slots + (long)kAugRho0 * pr.n_slots_upd, pr.n_slots_upd);
+  return wave_sum_slots(dot_group(pr, rho_grp(k)), rho_count(pr, k));
+}
+
 // Search-direction source of the inverse transform (fused p update).
 struct PSrc {
   const float* __restrict__ src;  // plain source (SRC_IN / SRC_STATE_C)
@@ -131,12 +148,13 @@ struct PSrc {
 
 __device__ __forceinline__ PSrc make_psrc(const ProbDev& pr, const IoDev& io, int mode, int iter, float beta) {
   PSrc s;
+  if (pr.aug_keep > 0 && (mode == SRC_PUPD0 || mode == SRC_PUPD)) mode = SRC_PJ;  // p_j formed by k_aug_p
   s.mode = mode;
-  s.src = (mode == SRC_IN) ? io.in : io.state;  // state starts with c
+  s.src = (mode == SRC_IN) ? io.in : (mode == SRC_PJ) ? p_loc(pr, iter) : io.state;  // state starts with c
   s.r = io.state + 2L * pr.n_c;
   s.jinv = pr.jinv;
-  s.pnew = (iter & 1) ? pr.pbuf1 : pr.pbuf0;
-  s.pold = (iter & 1) ? pr.pbuf0 : pr.pbuf1;
+  s.pnew = p_loc(pr, iter);
+  s.pold = p_loc(pr, iter - 1);
   s.beta = beta;
   return s;
 }
@@ -146,7 +164,7 @@ struct CoefLoad {
 };
 __device__ __forceinline__ CoefLoad coef_fetch(const PSrc& s, int e) {
   CoefLoad v{0.f, 0.f, 0.f};
-  if (s.mode == SRC_IN || s.mode == SRC_STATE_C) {
+  if (s.mode == SRC_IN || s.mode == SRC_STATE_C || s.mode == SRC_PJ) {
     v.a = ((gptr_f)s.src)[e];
   } else {
     v.a = ((gptr_f)s.r)[e];
@@ -157,7 +175,7 @@ __device__ __forceinline__ CoefLoad coef_fetch(const PSrc& s, int e) {
 }
 // p = J^{-1} r (first iteration) or p = J^{-1} r + beta p_old; written once by its owner
 __device__ __forceinline__ float coef_finish(const PSrc& s, int e, const CoefLoad& v, bool owner) {
-  if (s.mode == SRC_IN || s.mode == SRC_STATE_C) return v.a;
+  if (s.mode == SRC_IN || s.mode == SRC_STATE_C || s.mode == SRC_PJ) return v.a;
   const float z = v.a * v.b;
   const float p = (s.mode == SRC_PUPD0) ? z : fmaf(s.beta, v.c, z);
   if (owner) ((gptr_w)s.pnew)[e] = p;
@@ -169,8 +187,8 @@ __device__ __forceinline__ float coef_finish(const PSrc& s, int e, const CoefLoa
 // coefficient loads are in flight, so both latencies overlap
 __device__ __forceinline__ float wave_beta(const ProbDev& pr, int mode, int iter) {
   if (mode != SRC_PUPD) return 0.f;
-  const double rk = wave_sum_slots(dot_group(pr, rho_grp(iter)), rho_count(pr, iter));
-  const double rkm = wave_sum_slots(dot_group(pr, rho_grp(iter - 1)), rho_count(pr, iter - 1));
+  const double rk = rho_sum(pr, iter);
+  const double rkm = rho_sum(pr, iter - 1);
   return (float)((rkm != 0.0) ? rk / rkm : 0.0);
 }
 
@@ -245,7 +263,7 @@ __device__ __forceinline__ EpiLoad epi_fetch(const ProbDev& pr, const IoDev& io,
   if (epi == EPI_APPLYM) {
     l.x0 = ((gptr_f)io.in)[e];
   } else if (epi == EPI_PCG) {
-    l.x0 = ((gptr_f)((iter & 1) ? pr.pbuf1 : pr.pbuf0))[e];
+    l.x0 = ((gptr_f)p_loc(pr, iter))[e];
   } else if (epi == EPI_RHS) {
     l.x0 = ((gptr_f)io.state)[pr.n_c + e];
     l.x1 = ((gptr_f)io.state)[2L * pr.n_c + e];
@@ -263,8 +281,9 @@ struct EpiDst {
   gptr_w b;    // EPI_RHS: b' and r0 in the state
   gptr_w r;
 };
-__device__ __forceinline__ EpiDst epi_dst(const ProbDev& pr, const IoDev& io) {
-  return EpiDst{(gptr_w)pr.q, (gptr_w)io.out, (gptr_w)(io.state + pr.n_c), (gptr_w)(io.state + 2L * pr.n_c)};
+__device__ __forceinline__ EpiDst epi_dst(const ProbDev& pr, const IoDev& io, int iter) {
+  return EpiDst{(gptr_w)q_loc(pr, iter), (gptr_w)io.out, (gptr_w)(io.state + pr.n_c),
+                (gptr_w)(io.state + 2L * pr.n_c)};
 }
 __device__ __forceinline__ void epi_finish(const EpiDst& dst, int epi, int e, float ad, float v, const EpiLoad& l,
                                            double& acc) {
@@ -419,7 +438,7 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
       const int e = e0 + u * nt;
       if (e < R * R) v[u] = coef_fetch(ps, off + (e >> lr) * n + (e & (R - 1)));
     }
-    if (e0 == threadIdx.x) ps.beta = wave_beta(pr, src_mode, iter);
+    if (e0 == threadIdx.x) ps.beta = wave_beta(pr, ps.mode, iter);
 #pragma unroll
     for (int u = 0; u < kUL; ++u) {
       const int e = e0 + u * nt;
@@ -546,7 +565,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         v[u] = coef_fetch(ps, gpos[u]);
       }
     }
-    ps.beta = wave_beta(pr, src_mode, iter);
+    ps.beta = wave_beta(pr, ps.mode, iter);
 #pragma unroll
     for (int u = 0; u < kRounds; ++u) {
       const int e = lane + 64 * u;
@@ -677,7 +696,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   __syncthreads();
   double acc = 0.0;
   const float ad = ly.alpha_d[t.level - 1];  // detail blocks of this level have side half = 2^(level - 1)
-  const EpiDst dst = epi_dst(pr, io);
+  const EpiDst dst = epi_dst(pr, io, iter);
   // 512 (row, column) pairs of the column pass, 2 per thread; each yields up to 2 outputs
   {
     float eval[4];
@@ -866,7 +885,7 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
     }
   }
   double acc = 0.0;
-  const EpiDst dst = epi_dst(pr, io);
+  const EpiDst dst = epi_dst(pr, io, iter);
   if constexpr (EPI == EPI_PCG) {
     LevelOps<RMAX> ops;  // requested before the barrier: one memory round trip for every level
     epi_fetch_levels<RMAX, EPI>(pr, io, iter, off, n, R, m0, ops);
@@ -1556,6 +1575,285 @@ __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD
   }
 }
 
+// ------------------------------------------------------- augmented PCG
+// The previous frame's directions W (m of them) and A W in the state, after
+// a_prev and a; their count follows them.
+struct AugView {
+  const float* P;
+  const float* Q;
+  int m;
+};
+__device__ __forceinline__ AugView aug_view(const ProbDev& pr, const IoDev& io) {
+  const float* base = io.state + 3L * pr.n_c + 2L * pr.n_act;
+  AugView v;
+  v.P = base;
+  v.Q = base + (long)pr.aug_keep * pr.n_c;
+  const float cnt = ((gptr_f)(base + 2L * pr.aug_keep * pr.n_c))[0];
+  v.m = (cnt >= 1.f && cnt <= (float)pr.aug_keep) ? (int)cnt : 0;
+  return v;
+}
+
+// Sums of K doubles over a workgroup of nw waves in wave order; result in
+// thread 0's a[].
+template <int K>
+__device__ __forceinline__ void block_sumk_d(double a[K], double* sh, int nw) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) a[k] = wave_sum(a[k]);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[K * w + k] = a[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double r = 0.0;
+      for (int i = 0; i < nw; ++i) r += sh[K * i + k];
+      a[k] = r;
+    }
+  __syncthreads();
+}
+
+// Cholesky factor of the m x m Gram matrix W^T A W (lower triangle in g,
+// g[r][k] = W_r . (A W)_k for k <= r); a direction whose pivot is not
+// positive is dropped (kept = 0, its row and column unused).  Every lane
+// computes the same factor.
+struct AugFactor {
+  double L[kAugMax][kAugMax];
+  int kept[kAugMax];
+};
+__device__ __forceinline__ void aug_factor(const double g[kAugMax][kAugMax], int m, AugFactor& f) {
+#pragma unroll
+  for (int k = 0; k < kAugMax; ++k) {
+    f.kept[k] = 0;
+#pragma unroll
+    for (int i = 0; i < kAugMax; ++i) f.L[k][i] = 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < kAugMax; ++k) {
+    if (k >= m) break;
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < k; ++i)
+      if (f.kept[i]) acc += f.L[k][i] * f.L[k][i];
+    const double d = g[k][k] - acc;
+    if (!(d > 0.0) || !(d < INFINITY)) continue;
+    f.kept[k] = 1;
+    f.L[k][k] = sqrt(d);
+#pragma unroll
+    for (int r = k + 1; r < kAugMax; ++r) {
+      if (r >= m) break;
+      double a2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < k; ++i)
+        if (f.kept[i]) a2 += f.L[r][i] * f.L[k][i];
+      f.L[r][k] = (g[r][k] - a2) / f.L[k][k];
+    }
+  }
+}
+// x = (W^T A W)^{-1} v on the kept directions (0 on dropped ones).
+__device__ __forceinline__ void aug_solve(const AugFactor& f, int m, const double v[kAugMax], double x[kAugMax]) {
+  double y[kAugMax];
+#pragma unroll
+  for (int k = 0; k < kAugMax; ++k) y[k] = x[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < kAugMax; ++k)
+    if (k < m && f.kept[k]) {
+      double a = 0.0;
+#pragma unroll
+      for (int i = 0; i < k; ++i)
+        if (f.kept[i]) a += f.L[k][i] * y[i];
+      y[k] = (v[k] - a) / f.L[k][k];
+    }
+#pragma unroll
+  for (int k = kAugMax - 1; k >= 0; --k)
+    if (k < m && f.kept[k]) {
+      double a = 0.0;
+#pragma unroll
+      for (int i = k + 1; i < kAugMax; ++i)
+        if (i < m && f.kept[i]) a += f.L[i][k] * x[i];
+      x[k] = (y[k] - a) / f.L[k][k];
+    }
+}
+__device__ __forceinline__ double aug_group_sum(const ProbDev& pr, int g) {
+  return wave_sum_slots(pr.aug_slots + (long)g * pr.n_slots_upd, pr.n_slots_upd);
+}
+
+// Partial sums of W^T r_0 and of the lower triangle of W^T A W over one
+// chunk of coefficients (r_0: the warm-start residual in the state).
+__global__ __launch_bounds__(256) void k_aug_gram(const ProbDev* P, const IoDev* IO, const Tile* tiles) {
+  __shared__ double sh[(kAugMax + kAugMax * (kAugMax + 1) / 2) * 4];
+  const Tile t = my_tile(tiles);
+  const ProbDev& pr = P[t.prob];
+  const IoDev& io = IO[t.prob];
+  const AugView w = aug_view(pr, io);
+  constexpr int NG = kAugMax + kAugMax * (kAugMax + 1) / 2;
+  double a[NG];
+#pragma unroll
+  for (int k = 0; k < NG; ++k) a[k] = 0.0;
+  const int e0 = t.ty * kUpdChunk, e1 = min(e0 + kUpdChunk, pr.n_c);
+  const gptr_f r = (gptr_f)(io.state + 2L * pr.n_c);
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
+    const double re = r[e];
+    double qv[kAugMax];
+#pragma unroll
+    for (int l = 0; l < kAugMax; ++l) qv[l] = l < w.m ? (double)((gptr_f)(w.Q + (long)l * pr.n_c))[e] : 0.0;
+#pragma unroll
+    for (int k = 0; k < kAugMax; ++k) {
+      if (k >= w.m) break;
+      const double pk = ((gptr_f)(w.P + (long)k * pr.n_c))[e];
+      a[kAugD + k] += pk * re;
+#pragma unroll
+      for (int l = 0; l <= k; ++l) a[kAugMax + k * (k + 1) / 2 + l] += pk * qv[l];  // row k, column l
+    }
+  }
+  block_sumk_d<NG>(a, sh, 4);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < NG; ++k) ((gptr_wd)pr.aug_slots)[(long)(kAugD + k) * pr.n_slots_upd + t.slot] = a[k];
+}
+
+// The projected start of the augmented PCG: y = G^{-1} W^T r_0,
+// x_0 = c + W y, r_0 <- r_0 - (A W) y (in the state), and the partial sums
+// of rho_0 = r_0^T J^{-1} r_0 and of (A W)^T J^{-1} r_0.  The first chunk also
+// stores the factor of G for the direction kernel.
+__global__ __launch_bounds__(256) void k_aug_init(const ProbDev* P, const IoDev* IO, const Tile* tiles) {
+  __shared__ double sh[(kAugMax + 1) * 4];
+  __shared__ double ys[kAugMax];
+  const Tile t = my_tile(tiles);
+  const ProbDev& pr = P[t.prob];
+  const IoDev& io = IO[t.prob];
+  const AugView w = aug_view(pr, io);
+  if (threadIdx.x < 64) {  // wave 0: the small system (every lane the same)
+    double g[kAugMax][kAugMax], d[kAugMax], y[kAugMax];
+#pragma unroll
+    for (int k = 0; k < kAugMax; ++k) {
+      d[k] = k < w.m ? aug_group_sum(pr, kAugD + k) : 0.0;
+#pragma unroll
+      for (int l = 0; l < kAugMax; ++l) g[k][l] = (l <= k && k < w.m) ? aug_group_sum(pr, kAugG + k * (k + 1) / 2 + l) : 0.0;
+    }
+    AugFactor f;
+    aug_factor(g, w.m, f);
+    aug_solve(f, w.m, d, y);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < kAugMax; ++k) ys[k] = y[k];
+      if (t.ty == 0) {
+#pragma unroll
+        for (int k = 0; k < kAugMax; ++k) {
+#pragma unroll
+          for (int l = 0; l < kAugMax; ++l) ((gptr_wd)pr.aug_fac)[k * kAugMax + l] = f.L[k][l];
+          ((gptr_wd)pr.aug_fac)[kAugMax * kAugMax + k] = (double)f.kept[k];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int e0 = t.ty * kUpdChunk, e1 = min(e0 + kUpdChunk, pr.n_c);
+  const gptr_w x = (gptr_w)io.state;
+  const gptr_w r = (gptr_w)(io.state + 2L * pr.n_c);
+  const gptr_f jv = (gptr_f)pr.jinv;
+  float yk[kAugMax];
+#pragma unroll
+  for (int k = 0; k < kAugMax; ++k) yk[k] = (float)ys[k];
+  double a[kAugMax + 1] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
+    float xe = x[e], re = r[e];
+    float qv[kAugMax];
+#pragma unroll
+    for (int k = 0; k < kAugMax; ++k) {
+      qv[k] = 0.f;
+      if (k < w.m) {
+        qv[k] = ((gptr_f)(w.Q + (long)k * pr.n_c))[e];
+        xe = fmaf(yk[k], ((gptr_f)(w.P + (long)k * pr.n_c))[e], xe);
+        re = fmaf(-yk[k], qv[k], re);
+      }
+    }
+    x[e] = xe;
+    r[e] = re;
+    const double z = (double)re * (double)jv[e];
+    a[0] += (double)re * z;
+#pragma unroll
+    for (int k = 0; k < kAugMax; ++k)
+      if (k < w.m) a[1 + k] += (double)qv[k] * z;
+  }
+  block_sumk_d<kAugMax + 1>(a, sh, 4);
+  if (threadIdx.x == 0) {
+    ((gptr_wd)pr.aug_slots)[(long)kAugRho0 * pr.n_slots_upd + t.slot] = a[0];
+#pragma unroll
+    for (int k = 0; k < kAugMax; ++k)
+      if (k < w.m) ((gptr_wd)pr.aug_slots)[(long)(kAugT + k) * pr.n_slots_upd + t.slot] = a[1 + k];
+  }
+}
+
+// Direction j of the augmented PCG: z_j = J^{-1} r_j, beta = rho_j / rho_{j-1}
+// (0 at j = 0), mu = G^{-1} (A W)^T z_j, p_j = z_j + beta p_{j-1} - W mu.
+__global__ __launch_bounds__(256) void k_aug_p(const ProbDev* P, const IoDev* IO, const Tile* tiles, int iter) {
+  __shared__ float cs[kAugMax + 1];
+  const Tile t = my_tile(tiles);
+  const ProbDev& pr = P[t.prob];
+  const IoDev& io = IO[t.prob];
+  const AugView w = aug_view(pr, io);
+  if (threadIdx.x < 64) {
+    AugFactor f;
+#pragma unroll
+    for (int k = 0; k < kAugMax; ++k) {
+#pragma unroll
+      for (int l = 0; l < kAugMax; ++l) f.L[k][l] = ((gptr_d)pr.aug_fac)[k * kAugMax + l];
+      f.kept[k] = ((gptr_d)pr.aug_fac)[kAugMax * kAugMax + k] != 0.0;
+    }
+    double tv[kAugMax], mu[kAugMax];
+#pragma unroll
+    for (int k = 0; k < kAugMax; ++k) tv[k] = k < w.m ? aug_group_sum(pr, kAugT + (iter & 1) * kAugMax + k) : 0.0;
+    aug_solve(f, w.m, tv, mu);
+    double beta = 0.0;
+    if (iter > 0) {
+      const double rk = rho_sum(pr, iter), rkm = rho_sum(pr, iter - 1);
+      beta = rkm != 0.0 ? rk / rkm : 0.0;
+    }
+    if (threadIdx.x == 0) {
+      cs[0] = (float)beta;
+#pragma unroll
+      for (int k = 0; k < kAugMax; ++k) cs[1 + k] = (float)mu[k];
+    }
+  }
+  __syncthreads();
+  const float beta = cs[0];
+  const int e0 = t.ty * kUpdChunk, e1 = min(e0 + kUpdChunk, pr.n_c);
+  const gptr_f r = (gptr_f)(io.state + 2L * pr.n_c);
+  const gptr_f jv = (gptr_f)pr.jinv;
+  const gptr_f pold = (gptr_f)p_loc(pr, iter - 1);
+  const gptr_w pnew = (gptr_w)p_loc(pr, iter);
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
+    const float z = r[e] * jv[e];
+    float pe = iter > 0 ? fmaf(beta, pold[e], z) : z;
+#pragma unroll
+    for (int k = 0; k < kAugMax; ++k)
+      if (k < w.m) pe = fmaf(-cs[1 + k], ((gptr_f)(w.P + (long)k * pr.n_c))[e], pe);
+    pnew[e] = pe;
+  }
+}
+
+// The frame's first min(iters, aug_keep) directions and images become the
+// state's W and A W for the next frame (count after them).
+__global__ __launch_bounds__(256) void k_aug_store(const ProbDev* P, const IoDev* IO, const Tile* tiles, int iters) {
+  const Tile t = my_tile(tiles);
+  const ProbDev& pr = P[t.prob];
+  const IoDev& io = IO[t.prob];
+  const int kd = min(iters, pr.aug_keep);
+  float* base = io.state + 3L * pr.n_c + 2L * pr.n_act;
+  const int e0 = t.ty * kUpdChunk, e1 = min(e0 + kUpdChunk, pr.n_c);
+  for (int k = 0; k < kd; ++k) {
+    const gptr_f ps = (gptr_f)(pr.aug_pdir + (long)k * pr.n_c), qs = (gptr_f)(pr.aug_qdir + (long)k * pr.n_c);
+    const gptr_w pd = (gptr_w)(base + (long)k * pr.n_c), qd = (gptr_w)(base + (long)(pr.aug_keep + k) * pr.n_c);
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
+      pd[e] = ps[e];
+      qd[e] = qs[e];
+    }
+  }
+  if (t.ty == 0 && threadIdx.x == 0) ((gptr_w)(base + 2L * pr.aug_keep * pr.n_c))[0] = (float)kd;
+}
+
 // ------------------------------------------------------------ PCG update
 // a = rho_k / pi_k; x += a p; r -= a q; partial rho_{k+1} = r^T J^{-1} r.
 // 2048 coefficients per workgroup as float4: 2 per thread, loads first.
@@ -1564,8 +1862,8 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
   const IoDev& io = IO[t.prob];
-  const gptr_f4 p = (gptr_f4)((iter & 1) ? pr.pbuf1 : pr.pbuf0);
-  const gptr_f4 q = (gptr_f4)pr.q;
+  const gptr_f4 p = (gptr_f4)p_loc(pr, iter);
+  const gptr_f4 q = (gptr_f4)q_loc(pr, iter);
   const gptr_f4 jv = (gptr_f4)pr.jinv;
   const gptr_w4 x = (gptr_w4)io.state;
   const gptr_w4 r = (gptr_w4)(io.state + 2L * pr.n_c);
@@ -1573,7 +1871,7 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
   const int e1 = min(e0 + kUpdChunk / 4, pr.n_c / 4);
   double acc = 0.0;
   constexpr int V = kUpdChunk / 4 / 256;  // float4 per thread
-  v4f xp[V], pp[V], rr[V], qq[V], jj[V];
+  v4f xp[V], pp[V], rr[V], qq[V], jj[V], rnv[V];
 #pragma unroll
   for (int u = 0; u < V; ++u) {
     const int e = e0 + threadIdx.x + u * 256;
@@ -1587,7 +1885,7 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
   }
   // alpha = rho_k / pi_k, summed by every wave itself in the same fixed order
   // (no barrier) while its loads are in flight
-  const double rho = wave_sum_slots(dot_group(pr, rho_grp(iter)), rho_count(pr, iter));
+  const double rho = rho_sum(pr, iter);
   const double pi = wave_sum_slots(dot_group(pr, pi_grp(iter)), pr.n_slots_fdwt);
   const float a = (float)((pi > 0.0) ? rho / pi : 0.0);
   // breakdown: a nonzero residual with p^T M p <= 0 (M is positive definite,
@@ -1611,14 +1909,44 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
       rn.w = fmaf(-a, qq[u].w, rr[u].w);
       x[e] = xn;
       r[e] = rn;
+      rnv[u] = rn;
       acc += (double)rn.x * (double)rn.x * (double)jj[u].x;
       acc += (double)rn.y * (double)rn.y * (double)jj[u].y;
       acc += (double)rn.z * (double)rn.z * (double)jj[u].z;
       acc += (double)rn.w * (double)rn.w * (double)jj[u].w;
     }
   }
-  const double s = block_sum(acc, sh, blockDim.x);
-  if (threadIdx.x == 0) ((gptr_wd)pr.dots)[(long)rho_grp(iter + 1) * pr.n_dots + t.slot] = s;
+  if (pr.aug_keep == 0) {
+    const double s = block_sum(acc, sh, blockDim.x);
+    if (threadIdx.x == 0) ((gptr_wd)pr.dots)[(long)rho_grp(iter + 1) * pr.n_dots + t.slot] = s;
+    return;
+  }
+  // augmented PCG: also (A W)^T z_{j+1}, z = J^{-1} r, for the next direction
+  const AugView w = aug_view(pr, io);
+  double tk[kAugMax + 1] = {acc, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < kAugMax; ++k) {
+    if (k >= w.m) break;
+    const gptr_f4 qk = (gptr_f4)(w.Q + (long)k * pr.n_c);
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int e = e0 + threadIdx.x + u * 256;
+      if (e < e1) {
+        const v4f a4 = qk[e], r4 = rnv[u];
+        tk[1 + k] += (double)a4.x * ((double)r4.x * (double)jj[u].x) + (double)a4.y * ((double)r4.y * (double)jj[u].y) +
+                     (double)a4.z * ((double)r4.z * (double)jj[u].z) + (double)a4.w * ((double)r4.w * (double)jj[u].w);
+      }
+    }
+  }
+  __shared__ double shk[(kAugMax + 1) * 4];
+  block_sumk_d<kAugMax + 1>(tk, shk, blockDim.x >> 6);
+  if (threadIdx.x == 0) {
+    ((gptr_wd)pr.dots)[(long)rho_grp(iter + 1) * pr.n_dots + t.slot] = tk[0];
+#pragma unroll
+    for (int k = 0; k < kAugMax; ++k)
+      if (k < w.m)
+        ((gptr_wd)pr.aug_slots)[(long)(kAugT + ((iter + 1) & 1) * kAugMax + k) * pr.n_slots_upd + t.slot] = tk[1 + k];
+  }
 }
 
 // ------------------------------------------------- PCG run to a tolerance
@@ -1902,6 +2230,18 @@ void launch_grad_prior(const LaunchArgs& a, const GradIo* g, const Tile* tiles, 
 }
 void launch_grad_final(const LaunchArgs& a, const GradIo* g, int nprob) {
   if (nprob > 0) k_grad_final<<<nprob, 64, 0, a.stream>>>(a.P, a.L, g);
+}
+void launch_aug_gram(const LaunchArgs& a, const Tile* tiles, int ntiles) {
+  if (ntiles > 0) k_aug_gram<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles);
+}
+void launch_aug_init(const LaunchArgs& a, const Tile* tiles, int ntiles) {
+  if (ntiles > 0) k_aug_init<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles);
+}
+void launch_aug_p(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter) {
+  if (ntiles > 0) k_aug_p<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles, iter);
+}
+void launch_aug_store(const LaunchArgs& a, const Tile* tiles, int ntiles, int iters) {
+  if (ntiles > 0) k_aug_store<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles, iters);
 }
 void launch_fit_fwd(const LaunchArgs& a, const Tile* tiles, int ntiles) {
   if (ntiles > 0) k_fit_fwd<<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, tiles);

@@ -123,6 +123,7 @@ class Context:
         if loop not in ("open", "closed"):
             raise ValueError("loop must be 'open' or 'closed'")
         _check(_abi.fewha_set_loop(self.h, 1 if loop == "closed" else 0), self.h)
+        _check(_abi.fewha_set_augmentation(self.h, int(cfg.get("augment", 0))), self.h)
         if self.tuning is not None:
             _check(_abi.fewha_set_tuning(self.h, byref(_tuning(self.tuning))), self.h)
         if cfg.get("dms") and cfg.get("fit"):
