@@ -427,6 +427,44 @@ def streamed_leg(fw, c0, pool_host, iters, nf=100):
     return out
 
 
+def augmentation_leg(fw, cfg, pool_dev, n_frames=16, iters=2, keep=2, nf=100):
+    """Warm-started frames at `iters` PCG iterations with and without the
+    augmented PCG (Sec. 3.3), on one MAORY-like frozen-flow sequence: the
+    M-norm error of c against the converged MAP solution of each frame
+    (fewha_solve_map, refined to 1e-7), and the single-frame latency of both
+    (graph path)."""
+    import torch
+    ctx_p = fw.Context(dict(cfg, iters=iters), device=0)
+    ctx_a = fw.Context(dict(cfg, iters=iters, augment=keep), device=0)
+    st_p = torch.zeros(ctx_p.n_state, device="cuda")
+    st_a = torch.zeros(ctx_a.n_state, device="cuda")
+    n = ctx_p.n_coeff
+    err = {"plain": [], "augmented": []}
+    for k in range(n_frames):
+        s = pool_dev[pool_index(k, len(pool_dev))]
+        ctx_p.reconstruct(s, st_p, iters=iters)
+        ctx_a.reconstruct(s, st_a, iters=iters)
+        cstar, _, _ = ctx_p.solve_map(slopes=s, rtol=1e-7, max_iters=20000)
+        mstar = ctx_p.apply_M(cstar)
+        norm = float(torch.dot(cstar.double(), mstar.double()))
+        for name, st in (("plain", st_p), ("augmented", st_a)):
+            e = st[:n] - cstar
+            err[name].append((float(torch.dot(e.double(), ctx_p.apply_M(e).double())) / norm) ** 0.5)
+    out = {"workload": "MAORY-like, one frozen-flow sequence of %d frames, %d warm PCG iterations per frame; "
+                       "augmented: the previous frame's %d directions" % (n_frames, iters, keep),
+           "m_norm_error_plain": err["plain"], "m_norm_error_augmented": err["augmented"],
+           "mean_error_frames_4_on": {k: sum(v[4:]) / len(v[4:]) for k, v in err.items()}}
+    for name, c in (("plain", ctx_p), ("augmented", ctx_a)):
+        b = fw.Batch([c])
+        st = torch.zeros(c.n_state, device="cuda")
+        out["latency_us_" + name] = latency(lambda i: b.reconstruct([pool_dev[pool_index(i, len(pool_dev))]], [st],
+                                                                    iters=iters, use_graph=True), nf)
+        b.close()
+    ctx_p.close()
+    ctx_a.close()
+    return out
+
+
 def gradient_leg(fw, pool, n_frames, rtol=1e-6):
     """Forward + implicit backward of the differentiated reconstruction on
     MAORY-like geometry: n_frames frames per batch, both solves refined to
@@ -615,7 +653,8 @@ def main():
     extra = {}
     if not args.no_extra:
         pool_host = [pool[0][f].cpu().pin_memory() for f in range(args.pool)]
-        for name, leg in (("streamed_slopes_us", lambda: streamed_leg(fw, c0, pool_host, args.iters)),
+        for name, leg in (("augmented_pcg", lambda: augmentation_leg(fw, cfg, pool[0])),
+                          ("streamed_slopes_us", lambda: streamed_leg(fw, c0, pool_host, args.iters)),
                           ("paper_maory", lambda: paper_maory_leg(fw)),
                           ("batched_uneven_64", lambda: config3_leg(fw, peaks)),
                           ("large_9_layers", lambda: config5_leg(fw))):

@@ -389,12 +389,19 @@ FEWHA_API void fewha_batch_destroy(fewha_batch* b);
  * are identical to one part.  The parts' plans are built with the batch and
  * take device memory of their own (about that of the batch plan).  Every
  * other batch call runs the whole batch on the batch's stream.
+ * res_split: the resident inverse levels run as one workgroup per (problem,
+ * layer) (0 = default, or 1) or as four (4), each synthesizing the levels
+ * below the top one itself and the top level for one quadrant of the
+ * output, so that a launch spreads over more compute units; 4 needs every
+ * layer's resident side to be at least 16 with at least one resident level
+ * (else FEWHA_EINVAL when the plan is built).
  * reserved: zero. */
 typedef struct {
   int dwt_resident;
   int pt_rows;
   int streams;
-  int reserved[5];
+  int res_split;
+  int reserved[4];
 } fewha_tuning;
 
 /* Tuning of a context's own plan; before fewha_finalize. */

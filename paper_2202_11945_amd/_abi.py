@@ -34,7 +34,8 @@ class fewha_dm_desc(ctypes.Structure):
 
 
 class fewha_tuning(ctypes.Structure):
-    _fields_ = [("dwt_resident", c_int), ("pt_rows", c_int), ("streams", c_int), ("reserved", c_int * 5)]
+    _fields_ = [("dwt_resident", c_int), ("pt_rows", c_int), ("streams", c_int), ("res_split", c_int),
+                ("reserved", c_int * 4)]
 
 
 class FewhaError(RuntimeError):

@@ -1,6 +1,6 @@
 """Autotuner of a plan's launch shapes.
 
-Three tunables:
+Four tunables:
 
 * the resident transform side R (32, 64 or 128): the resident DWT kernels
   keep every level up to R x R in one workgroup's LDS, and the levels above R
@@ -9,7 +9,10 @@ Three tunables:
   levels over many more workgroups at the cost of one launch per extra level.
 * the node rows per thread of the propagation adjoint (4 or 8): more rows
   put more independent loads in flight per thread, at more registers.
-* then, for the best of those, the number of streams a batch's frame runs on
+* for the best of those, the resident inverse levels in one workgroup per
+  layer (the default) or in four (each synthesizing the lower levels itself
+  and one quadrant of the top level);
+* then the number of streams a batch's frame runs on
   (1 or 2 parts of the problem list, each on its own stream, so that the
   stages of one part overlap those of the other).
 
@@ -50,6 +53,18 @@ def source_hash():
         with open(os.path.join(src, f), "rb") as fh:
             h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
+
+
+def split_allowed(ctxs, res):
+    """Whether the resident inverse levels can run in quarters (the library's
+    rule): every layer has a resident side min(n, res) of at least 16 and
+    at least one resident level."""
+    for c in ctxs:
+        for l in c.cfg["layers"]:
+            R = min(l["n"], res)
+            if R < 16 or R < 2 * (l["n"] >> l["levels"]):
+                return False
+    return True
 
 
 def signature(ctxs, iters, device_name=None):
@@ -128,16 +143,25 @@ def tune(ctxs, iters, steps=10, use_cache=True):
     default = (max(admissible(ctxs)), PT_ROWS[0])
     if us[best] > (1.0 - MARGIN) * us[default]:
         best = default
-    sus = {1: us[best]}
+    shape = {"dwt_resident": best[0], "pt_rows": best[1]}
+    # then the resident inverse levels in four workgroups per layer against
+    # the default one
+    split_us = {0: us[best]}
+    if split_allowed(ctxs, best[0]):
+        split_us[4] = time_plan(ctxs, iters, dict(shape, res_split=4), steps=steps)
+    split = min(split_us, key=split_us.get)
+    if split_us[split] > (1.0 - MARGIN) * split_us[0]:
+        split = 0
+    sus = {1: split_us[split]}
     for ns in STREAMS[1:]:
         if ns <= len(ctxs):
-            sus[ns] = time_plan(ctxs, iters, {"dwt_resident": best[0], "pt_rows": best[1], "streams": ns},
-                                steps=steps)
+            sus[ns] = time_plan(ctxs, iters, dict(shape, res_split=split, streams=ns), steps=steps)
     streams = min(sus, key=sus.get)
     if sus[streams] > (1.0 - MARGIN) * sus[1]:
         streams = 1
-    rec = {"dwt_resident": best[0], "pt_rows": best[1], "streams": streams,
+    rec = {"dwt_resident": best[0], "pt_rows": best[1], "res_split": split, "streams": streams,
            "us": {"%d/%d" % k: round(t, 3) for k, t in us.items()},
+           "split_us": {"%d" % k: round(t, 3) for k, t in split_us.items()},
            "streams_us": {"%d" % k: round(t, 3) for k, t in sus.items()}}
     if use_cache:
         db = _load()

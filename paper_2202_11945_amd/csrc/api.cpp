@@ -62,6 +62,8 @@ struct Plan {
   std::vector<WfsDev> hW;
   std::vector<Tile> hT;
   Range idwt_res, fdwt_res, pg, gt, pt, upd;
+  Range idwt_res4;          // the resident inverse levels in quarters (four tiles per layer)
+  bool idwt_split = false;  // launch them instead of one workgroup per layer
   Range sin;  // slopes input: 2 x 2 groups of the propagation stage's subaperture tiles
   Range sin_frame, pg_pol;  // a frame's slope input: open-loop problems / closed-loop problems
   Range aug;                // augmented PCG: vector-update chunks of the problems with augmentation
@@ -342,13 +344,24 @@ struct Carver {
 };
 
 fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models, int device, int res,
-                        int pt_rows, std::string& err) {
+                        int pt_rows, int split, std::string& err) {
   if (res != 32 && res != 64 && res != 128) {
     err = "tuning: the resident transform side must be 32, 64 or 128";
     return FEWHA_EINVAL;
   }
   if (pt_rows != 4 && pt_rows != 8) {
     err = "tuning: the propagation adjoint takes 4 or 8 node rows per thread";
+    return FEWHA_EINVAL;
+  }
+  // quarters need at least one resident level of output side >= 16 on every layer
+  bool split_ok = true;
+  for (const HostModel* m : models)
+    for (const LayerHost& lh : m->layers) {
+      const int R = std::min(lh.d.n, res);
+      if (R < 16 || R < 2 * (lh.d.n >> lh.d.levels)) split_ok = false;
+    }
+  if (split == 4 && !split_ok) {
+    err = "tuning: four workgroups per layer need every layer's resident side >= 16 and >= 2 (n >> levels)";
     return FEWHA_EINVAL;
   }
   const int kPtH = 4 * pt_rows;  // node rows of a propagation-adjoint tile
@@ -367,6 +380,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   P.device = device;
   P.res_max = res;
   P.pt_rows = pt_rows;
+  P.idwt_split = split == 4;
   P.nprob = (int)models.size();
   P.models = models;
   HIP_TRY(hipSetDevice(device));
@@ -389,7 +403,8 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   std::vector<ProbLayout> lay(P.nprob);
   Carver cv;
   std::vector<Tile> t_sin, t_sinf, t_pgpol, t_aug, t_r64gt;
-  std::vector<Tile> t_idwt_res, t_fdwt_res, t_pg, t_gt, t_pt, t_upd, t_sinit, t_gprior, t_ghgt, t_r64wfs, t_r64pt;
+  std::vector<Tile> t_idwt_res, t_idwt_res4, t_fdwt_res, t_pg, t_gt, t_pt, t_upd, t_sinit, t_gprior, t_ghgt, t_r64wfs,
+      t_r64pt;
   HatTables hats;  // hat tables and band records of every problem and fitting view, one set per plan
   PtLists ptl;     // sensor lists of the propagation-adjoint tiles
   std::vector<std::vector<Tile>> t_r64inv(kMaxLevelsJ), t_r64fwd(kMaxLevelsJ);
@@ -560,6 +575,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
       // transform tiles carry the global layer index (mask), so that the
       // layer and problem records load in parallel
       t_idwt_res.push_back({k, l, 0, 0, 0, 0, pd.layer0 + l, 0});
+      for (int q = 0; q < 4; ++q) t_idwt_res4.push_back({k, l, 0, q, 0, 0, pd.layer0 + l, 0});
       t_fdwt_res.push_back({k, l, 0, 0, slot++, 0, pd.layer0 + l, 0});
     }
     pd.n_slots_fdwt = slot;
@@ -826,6 +842,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     return r;
   };
   P.idwt_res = add(t_idwt_res);
+  P.idwt_res4 = add(t_idwt_res4);
   P.fdwt_res = add(t_fdwt_res);
   P.pg = add(t_pg);
   P.sin = add(t_sin);
@@ -1178,7 +1195,10 @@ LaunchArgs args(const Plan& P, hipStream_t s, const IoDev* io) {
 const Tile* T(const Plan& P, const Range& r) { return P.dT + r.off; }
 
 void enq_idwt(const Plan& P, const LaunchArgs& a, int src, int out, int iter) {
-  launch_idwt_res(a, T(P, P.idwt_res), P.idwt_res.n, src, out, iter);
+  if (P.idwt_split)
+    launch_idwt_res4(a, T(P, P.idwt_res4), P.idwt_res4.n, src, out, iter);
+  else
+    launch_idwt_res(a, T(P, P.idwt_res), P.idwt_res.n, src, out, iter);
   for (size_t s = 0; s < P.idwt_glob.size(); ++s)
     launch_idwt_glob(a, T(P, P.idwt_glob[s]), P.idwt_glob[s].n, src, out, iter, (int)s);
 }
@@ -1672,8 +1692,10 @@ fewha_status fewha_set_tuning(fewha_ctx* c, const fewha_tuning* t) {
   CHECK_CTX(c);
   if (c->finalized) return fail(c, FEWHA_ESTATE, "set_tuning after finalize");
   if (!t) return fail(c, FEWHA_EINVAL, "set_tuning: null tuning");
-  for (int i = 0; i < 5; ++i)
+  for (int i = 0; i < 4; ++i)
     if (t->reserved[i]) return fail(c, FEWHA_EINVAL, "set_tuning: reserved fields must be zero");
+  if (t->res_split != 0 && t->res_split != 1 && t->res_split != 4)
+    return fail(c, FEWHA_EINVAL, "set_tuning: res_split must be 0, 1 or 4");
   if (t->streams != 0 && t->streams != 1)
     return fail(c, FEWHA_EINVAL, "set_tuning: a context runs one stream (streams 0 or 1)");
   if (t->dwt_resident != 0 && t->dwt_resident != 32 && t->dwt_resident != 64 && t->dwt_resident != 128)
@@ -1682,6 +1704,7 @@ fewha_status fewha_set_tuning(fewha_ctx* c, const fewha_tuning* t) {
     return fail(c, FEWHA_EINVAL, "set_tuning: pt_rows must be 0, 4 or 8");
   c->m.tune_res = t->dwt_resident;
   c->m.tune_pt_rows = t->pt_rows;
+  c->m.tune_split = t->res_split;
   return FEWHA_OK;
 }
 
@@ -1695,7 +1718,7 @@ fewha_status fewha_finalize(fewha_ctx* c) {
   if (c->device >= 0) {
     std::vector<const HostModel*> ms{&c->m};
     s = build_plan(c->plan, ms, c->device, c->m.tune_res > 0 ? c->m.tune_res : kResMax,
-                   c->m.tune_pt_rows > 0 ? c->m.tune_pt_rows : 4, c->err);
+                   c->m.tune_pt_rows > 0 ? c->m.tune_pt_rows : 4, c->m.tune_split, c->err);
     if (s != FEWHA_OK) return s;
     if ((s = setup_noalloc(*c->plan, c->err)) != FEWHA_OK ||
         (s = setup_streamed(*c->plan, c->m.n_slopes, (int)c->m.wfs.size(), c->err)) != FEWHA_OK) {
@@ -1975,7 +1998,8 @@ fewha_status fewha_batch_create(fewha_batch** out, fewha_ctx* const* ctxs, int n
 fewha_status fewha_batch_create_tuned(fewha_batch** out, fewha_ctx* const* ctxs, int n, const fewha_tuning* t) {
   if (!out || !ctxs || n < 1) return FEWHA_EINVAL;
   if (t && (t->dwt_resident < 0 || t->pt_rows < 0 || t->streams < 0 || t->streams > 4 || t->streams > n ||
-            t->reserved[0] || t->reserved[1] || t->reserved[2] || t->reserved[3] || t->reserved[4]))
+            (t->res_split != 0 && t->res_split != 1 && t->res_split != 4) || t->reserved[0] || t->reserved[1] ||
+            t->reserved[2] || t->reserved[3]))
     return FEWHA_EINVAL;
   *out = nullptr;
   int dev = -1;
@@ -1991,7 +2015,8 @@ fewha_status fewha_batch_create_tuned(fewha_batch** out, fewha_ctx* const* ctxs,
   b->ctxs.assign(ctxs, ctxs + n);
   const int res = (t && t->dwt_resident > 0) ? t->dwt_resident : kResMax;
   const int rows = (t && t->pt_rows > 0) ? t->pt_rows : 4;
-  fewha_status s = build_plan(b->plan, ms, dev, res, rows, b->err);
+  const int split = t ? t->res_split : 0;
+  fewha_status s = build_plan(b->plan, ms, dev, res, rows, split, b->err);
   if (s != FEWHA_OK) {
     delete b;
     return s;
@@ -2013,7 +2038,7 @@ fewha_status fewha_batch_create_tuned(fewha_batch** out, fewha_ctx* const* ctxs,
       const int k0 = (int)((long)n * q / parts), k1 = (int)((long)n * (q + 1) / parts);
       b->part_first.push_back(k0);
       std::vector<const HostModel*> mq(ms.begin() + k0, ms.begin() + k1);
-      if ((s = build_plan(b->parts[q], mq, dev, res, rows, b->err)) != FEWHA_OK) return undo(s);
+      if ((s = build_plan(b->parts[q], mq, dev, res, rows, split, b->err)) != FEWHA_OK) return undo(s);
       if (hipStreamCreateWithFlags(&b->part_stream[q], hipStreamNonBlocking) != hipSuccess ||
           hipEventCreateWithFlags(&b->part_done[q], hipEventDisableTiming) != hipSuccess)
         return undo(FEWHA_EDEVICE);
@@ -2184,8 +2209,13 @@ fewha_status fewha_batch_time_stage(fewha_batch* b, int stage, int reps, double*
   auto run = [&]() {
     switch (stage) {
       case FEWHA_STAGE_IDWT_RES:
-        launch_idwt_res(a, T(P, P.idwt_res), P.idwt_res.n, SRC_PUPD, OUT_PHI, it);
-        wg = P.idwt_res.n;
+        if (P.idwt_split) {
+          launch_idwt_res4(a, T(P, P.idwt_res4), P.idwt_res4.n, SRC_PUPD, OUT_PHI, it);
+          wg = P.idwt_res4.n;
+        } else {
+          launch_idwt_res(a, T(P, P.idwt_res), P.idwt_res.n, SRC_PUPD, OUT_PHI, it);
+          wg = P.idwt_res.n;
+        }
         break;
       case FEWHA_STAGE_IDWT_GLOB:
         wg = 0;

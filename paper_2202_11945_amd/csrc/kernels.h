@@ -46,6 +46,8 @@ struct LaunchArgs {
 };
 
 void launch_idwt_res(const LaunchArgs& a, const Tile* tiles, int ntiles, int src_mode, int out_mode, int iter);
+// the resident inverse levels over four workgroups per (problem, layer): tile.tx = quadrant
+void launch_idwt_res4(const LaunchArgs& a, const Tile* tiles, int ntiles, int src_mode, int out_mode, int iter);
 void launch_idwt_glob(const LaunchArgs& a, const Tile* tiles, int ntiles, int src_mode, int out_mode, int iter,
                       int step);
 void launch_fdwt_glob(const LaunchArgs& a, const Tile* tiles, int ntiles, int epi, int iter, int step);

@@ -509,6 +509,137 @@ __device__ __forceinline__ void syn_run(const float* a_src, const float* d_src, 
   }
 }
 
+// ------------------------------------- inverse DWT, resident part in quarters
+// The same levels as k_idwt_res over four workgroups per (problem, layer),
+// so that a batch launch fills the chip: every workgroup synthesizes the
+// levels below the top one (output side R/2 and less) itself in LDS, then
+// the top level (output side R) for one quadrant of the output, R/2 x R/2,
+// from a window of the top level's four bands (the lower levels' result and
+// the three detail quadrants, 2 coefficients of halo before each direction,
+// periodic).  A coefficient of the lower block is owned (its search
+// direction stored) by quarter 0, a top-level detail coefficient by the
+// quarter whose output it falls under.  Needs R >= 2 (n >> levels): at
+// least one resident level.
+template <int RMAX>
+__global__ __launch_bounds__(512) void k_idwt_res4(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
+                                                   const Tile* tiles, Filter F, int src_mode, int out_mode,
+                                                   int iter) {
+  constexpr int HMAX = RMAX / 2;           // side of the lower block
+  constexpr int S = HMAX + 1;              // LDS stride of the lower levels
+  constexpr int QHM = HMAX / 2 + 2;        // band window side
+  constexpr int WS = 2 * QHM + 1;          // window / column-pass stride
+  constexpr int YN = HMAX * WS > HMAX * S ? HMAX * WS : HMAX * S;
+  __shared__ float X[HMAX * S];            // lower levels (ping), then the lower block's result
+  __shared__ float Y[YN];                  // lower levels (pong), then the column pass
+  __shared__ float Wn[2 * QHM * WS];       // the top level's window of four bands
+  const Tile t = my_tile(tiles);
+  const ProbDev& pr = P[t.prob];
+  const LayerDev& ly = LD[t.mask];
+  const IoDev& io = IO[t.prob];
+  PSrc ps = make_psrc(pr, io, src_mode, iter, 0.f);
+  const int n = ly.n, R = ly.res, h = R >> 1, lh = __builtin_ctz(h), off = ly.off;
+  const int m0 = n >> ly.levels;
+  const int qy = t.tx >> 1, qx = t.tx & 1;  // output quadrant
+  const int qh = (h >> 1) + 2;              // window side of each band
+  const int nt = blockDim.x;
+  const bool lower_owner = t.tx == 0;
+  // one round of loads, all in flight together: the lower block (h x h, the
+  // Mallat layout's top-left: coarse block and the detail quadrants of every
+  // level below the top), then the three detail windows of the top level
+  // under this quadrant (qh^2 each); element e of a thread is threadIdx.x + u nt
+  constexpr int kUL = (HMAX * HMAX + 3 * QHM * QHM + 511) / 512;
+  const int nlow = h * h, nwin = qh * qh, ntot = nlow + 3 * nwin;
+  const float rq = 1.0f / (float)qh, rw = 1.0f / (float)nwin;
+  CoefLoad v[kUL];
+  int pos[kUL], dst[kUL];
+  unsigned owned = 0;  // bit u: this thread's window entry u is a coefficient of its own quadrant
+#pragma unroll
+  for (int u = 0; u < kUL; ++u) {
+    const int e = threadIdx.x + u * nt;
+    pos[u] = -1;
+    dst[u] = 0;
+    if (e < nlow) {
+      pos[u] = off + (e >> lh) * n + (e & (h - 1));
+      dst[u] = (e >> lh) * S + (e & (h - 1));
+    } else if (e < ntot) {
+      const int w = e - nlow;
+      int b = (int)((float)w * rw), i = w - b * nwin;  // band b: (0, 1), (1, 0), (1, 1)
+      if (i >= nwin) { ++b; i -= nwin; }
+      if (i < 0) { --b; i += nwin; }
+      int iy = (int)((float)i * rq), ix = i - iy * qh;
+      if (ix >= qh) { ++iy; ix -= qh; }
+      if (ix < 0) { --iy; ix += qh; }
+      const int by = (b + 1) >> 1, bx = (b + 1) & 1;
+      pos[u] = off + (by * h + ((qy * (h >> 1) - 2 + iy) & (h - 1))) * n + bx * h +
+               ((qx * (h >> 1) - 2 + ix) & (h - 1));
+      dst[u] = (by * qh + iy) * WS + bx * qh + ix;
+      if (iy >= 2 && ix >= 2) owned |= 1u << u;
+    }
+    if (pos[u] >= 0) v[u] = coef_fetch(ps, pos[u]);
+  }
+  ps.beta = wave_beta(pr, ps.mode, iter);  // every lane of every wave is here
+#pragma unroll
+  for (int u = 0; u < kUL; ++u) {
+    if (pos[u] < 0) continue;
+    if ((int)threadIdx.x + u * nt < nlow)
+      X[dst[u]] = coef_finish(ps, pos[u], v[u], lower_owner);
+    else
+      Wn[dst[u]] = coef_finish(ps, pos[u], v[u], (owned >> u) & 1u);
+  }
+  __syncthreads();
+  for (int m = 2 * m0; m <= h; m <<= 1) {
+    syn_pass<S>(X, Y, m, F);  // columns: X[t][c] -> Y[c][t]
+    __syncthreads();
+    syn_pass<S>(Y, X, m, F);  // rows: Y[c][r] -> X[r][c]
+    __syncthreads();
+  }
+  // the coarse band of the top level's window from the lower block's result
+  for (int e = threadIdx.x; e < nwin; e += nt) {
+    const int iy = e / qh, ix = e - iy * qh;
+    Wn[iy * WS + ix] = X[((qy * (h >> 1) - 2 + iy) & (h - 1)) * S + ((qx * (h >> 1) - 2 + ix) & (h - 1))];
+  }
+  __syncthreads();
+  // columns: one window column and a run of 4 output pairs per task
+  constexpr int kRun = 4;
+  const int wcols = 2 * qh;
+  for (int task = threadIdx.x; task < wcols * (h / 2 / kRun); task += nt) {
+    const int lx = task % wcols, t0p = (task / wcols) * kRun;
+    syn_run<kRun>(Wn + lx, Wn + qh * WS + lx, WS, t0p, F, Y + 2 * t0p * WS + lx, WS);
+  }
+  __syncthreads();
+  // rows, straight to the output quadrant (the layer, or the coarse block of
+  // the first global level)
+  const bool final_level = (n == R);
+  const OutDst od = out_dst(pr, io, out_mode);
+  const gptr_w nxt = (gptr_w)(pr.tmpa + ly.tmp_off);  // stride R
+  const int r0 = qy * h, c0 = qx * h;
+  for (int e0 = threadIdx.x; e0 < h * h; e0 += kU * nt) {
+    OutLoad o[kU];
+    if (final_level) {
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int e = e0 + u * nt;
+        if (e < h * h) o[u] = out_fetch(od, off + (r0 + (e >> lh)) * n + c0 + (e & (h - 1)));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * nt;
+      if (e >= h * h) break;
+      const int lt = e >> lh, ls = e & (h - 1);
+      const int par = ls & 1, k = ((ls - par) >> 1) + 2;
+      const float* Br = Y + lt * WS;
+      const float acc = F.h[par] * Br[k] + F.h[par + 2] * Br[k - 1] + F.h[par + 4] * Br[k - 2] +
+                        F.g[par] * Br[qh + k] + F.g[par + 2] * Br[qh + k - 1] + F.g[par + 4] * Br[qh + k - 2];
+      const int row = r0 + lt, col = c0 + ls;
+      if (final_level)
+        out_finish(od, off + row * n + col, acc * ly.inv_delta, o[u]);
+      else
+        nxt[row * R + col] = acc;
+    }
+  }
+}
+
 // ----------------------------------------------- inverse DWT, one global level
 // (Both global-level kernels are held to 64 VGPRs, 8 waves per SIMD: a batch
 // launch of 2048 tiles then runs in a single round of workgroups.)
@@ -2173,6 +2304,15 @@ void launch_idwt_res(const LaunchArgs& a, const Tile* tiles, int ntiles, int src
     k_idwt_res<64><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, src_mode, out_mode, iter);
   else
     k_idwt_res<128><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, src_mode, out_mode, iter);
+}
+void launch_idwt_res4(const LaunchArgs& a, const Tile* tiles, int ntiles, int src_mode, int out_mode, int iter) {
+  if (ntiles <= 0) return;
+  if (a.res_max <= 32)
+    k_idwt_res4<32><<<ntiles, 512, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, src_mode, out_mode, iter);
+  else if (a.res_max <= 64)
+    k_idwt_res4<64><<<ntiles, 512, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, src_mode, out_mode, iter);
+  else
+    k_idwt_res4<128><<<ntiles, 512, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, src_mode, out_mode, iter);
 }
 void launch_idwt_glob(const LaunchArgs& a, const Tile* tiles, int ntiles, int src_mode, int out_mode, int iter,
                       int step) {

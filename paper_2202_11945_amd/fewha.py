@@ -50,6 +50,7 @@ def _tuning(tuning):
         t.dwt_resident = int(tuning.get("dwt_resident", 0))
         t.pt_rows = int(tuning.get("pt_rows", 0))
         t.streams = int(tuning.get("streams", 0))
+        t.res_split = int(tuning.get("res_split", 0))
     else:
         t.dwt_resident = int(tuning)
     return t

@@ -12,17 +12,23 @@ def tuner(lib, tmp_path, monkeypatch):
     monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "cache.json"))
     monkeypatch.setattr(autotune, "signature", lambda ctxs, iters: "dev|iters%d|shape" % iters)
     monkeypatch.setattr(autotune, "admissible", lambda ctxs, candidates=autotune.CANDIDATES: [32, 64, 128])
+    monkeypatch.setattr(autotune, "split_allowed", lambda ctxs, res: False)
     return autotune
 
 
-def fake_times(table, streams=None):
-    """Stand-in timer: table[(R, rows)] for one stream, streams[s] for s > 1."""
+def fake_times(table, streams=None, quarters=None):
+    """Stand-in timer: table[(R, rows)] for one stream, streams[s] for s > 1,
+    quarters for the resident inverse levels in four workgroups per layer."""
     calls = []
 
     def time_plan(ctxs, iters, tuning, steps=10, warmup=3):
         ns = tuning.get("streams", 1)
         calls.append((tuning["dwt_resident"], tuning["pt_rows"], ns))
-        return table[(tuning["dwt_resident"], tuning["pt_rows"])] if ns == 1 else streams[ns]
+        if ns > 1:
+            return streams[ns]
+        if tuning.get("res_split", 0) == 4:
+            return quarters
+        return table[(tuning["dwt_resident"], tuning["pt_rows"])]
     return time_plan, calls
 
 
@@ -86,3 +92,17 @@ def test_cache_key_follows_geometry_and_sources(lib, monkeypatch):
     assert len({base, key(moved), key(higher)}) == 3
     monkeypatch.setattr(autotune, "source_hash", lambda: "0" * 16)
     assert key(get_config("small")) != base
+
+
+def test_resident_split_is_tuned_for_the_best_shape(tuner, monkeypatch):
+    # one workgroup per layer is the default; four are kept only when
+    # clearly faster, and the streams are then timed with that choice
+    monkeypatch.setattr(tuner, "split_allowed", lambda ctxs, res: True)
+    table = {(r, p): 1000.0 for r in (32, 64, 128) for p in (4, 8)}
+    tp, calls = fake_times(table, {2: 2000.0}, quarters=900.0)
+    monkeypatch.setattr(tuner, "time_plan", tp)
+    rec = tuner.tune([None, None], 4, use_cache=False)
+    assert rec["res_split"] == 4 and rec["split_us"] == {"0": 1000.0, "4": 900.0} and rec["streams"] == 1
+    tp, _ = fake_times(table, {2: 2000.0}, quarters=995.0)
+    monkeypatch.setattr(tuner, "time_plan", tp)
+    assert tuner.tune([None, None], 4, use_cache=False)["res_split"] == 0

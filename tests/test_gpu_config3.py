@@ -66,12 +66,17 @@ def test_batch_of_64_uneven_problems(gpu_lib):
     batch.reconstruct(slopes, states, lays, iters=6, use_graph=True)  # frame 2, warm
     torch.cuda.synchronize()
     print("[gpu-config3] single contexts", flush=True)
-    for k, c in enumerate(ctxs):
+    # single contexts with the batch's launch shapes (other shapes sum in
+    # another order and are checked against the oracle on their own)
+    shapes = {k: tune[k] for k in ("dwt_resident", "pt_rows", "res_split")}
+    for k, cfg in enumerate(cfgs):
+        c = gpu_lib.Context(cfg, device=0, tuning=shapes)
         st = before[k].clone()
         ly = torch.empty(c.n_coeff, device="cuda")
         c.reconstruct(slopes[k], st, ly, iters=6)
         torch.cuda.synchronize()
         assert torch.equal(st, states[k]) and torch.equal(ly, lays[k]), k
+        c.close()
     for k in CHECKED:
         print("[gpu-config3] oracle member", k, flush=True)
         S = _member_system(cfgs[k], unit_dd[0 if k < 32 else 32])

@@ -19,7 +19,9 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("name,res", [("small", 32), ("mid", 32), ("maory_like", 32), ("maory_like", 64),
                                       ("small", {"pt_rows": 8}), ("maory_like", {"dwt_resident": 64, "pt_rows": 8}),
-                                      ("small_fit", {"pt_rows": 8})])
+                                      ("small_fit", {"pt_rows": 8}), ("maory_like", {"res_split": 1}),
+                                      ("small", {"res_split": 1}), ("maory_like", {"dwt_resident": 64, "res_split": 4}),
+                                      ("mid", {"dwt_resident": 32, "res_split": 4})])
 def test_frame_parity_with_resident_side(gpu_lib, systems, name, res):
     import torch
     S = systems(name)
