@@ -396,7 +396,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   // ---- descriptors and tile lists ----
   struct ProbLayout {
     size_t phi, phiadj, tmpa, tmpb, sd, vadj, part, p0, p1, q, dots, jinv, itab, ftab, cmap, cinv, gl;
-    size_t sstate, gphi, glam, gslots, gitab, gftab;
+    size_t sstate, gphi, glam, gslots, gitab, gftab, amap;
     size_t a64, b64, sd64, u64, rslots, cinv64, ftab64, rbuf, x64;
     size_t apdir, aqdir, aslots, afac;
   };
@@ -680,6 +680,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     pl_.itab = cv.take(sizeof(int) * tab_tot);
     pl_.ftab = cv.take(sizeof(float) * tab_tot);
     pl_.cmap = cv.take(sizeof(int) * m_tot);
+    pl_.amap = cv.take(std::max(m_tot, 1));
     pl_.cinv = cv.take(sizeof(float) * 3 * (size_t)m_tot);
     pl_.gl = cv.take(sizeof(GLPar) * (size_t)G * L);
     pl_.sstate = cv.take(sizeof(float) * 3 * (size_t)pd.n_c);
@@ -918,6 +919,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     pd.itab = (const int*)(base + l.itab);
     pd.ftab = (const float*)(base + l.ftab);
     pd.cmap = (const int*)(base + l.cmap);
+    pd.amap = (const unsigned char*)(base + l.amap);
     pd.cinv = (const float*)(base + l.cinv);
     pd.gl = (const GLPar*)(base + l.gl);
     pd.gphi = (float*)(base + l.gphi);
@@ -953,6 +955,11 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
       HIP_TRY(hipMemcpy(base + l.ftab, ftab[k].data(), sizeof(float) * ftab[k].size(), hipMemcpyHostToDevice));
     }
     HIP_TRY(hipMemcpy(base + l.cmap, cmap[k].data(), sizeof(int) * cmap[k].size(), hipMemcpyHostToDevice));
+    {
+      std::vector<unsigned char> act(cmap[k].size());
+      for (size_t e = 0; e < act.size(); ++e) act[e] = cmap[k][e] >= 0 ? 1 : 0;
+      if (!act.empty()) HIP_TRY(hipMemcpy(base + l.amap, act.data(), act.size(), hipMemcpyHostToDevice));
+    }
     HIP_TRY(hipMemcpy(base + l.cinv, cinv[k].data(), sizeof(float) * cinv[k].size(), hipMemcpyHostToDevice));
   }
   for (size_t i = 0; i < fits.size(); ++i) {

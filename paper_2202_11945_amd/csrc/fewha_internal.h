@@ -191,6 +191,7 @@ struct ProbDev {
   const int* itab;       // int tables
   const float* ftab;     // float tables
   const int* cmap;       // compact-index maps
+  const unsigned char* amap;  // active flags (1 byte per subaperture, the maps' layout)
   const float* cinv;     // 2x2 inverse noise blocks
   const GLPar* gl;       // [sensor][layer] propagation parameters
   // parameter gradients

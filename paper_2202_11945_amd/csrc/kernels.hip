@@ -1102,10 +1102,17 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
   const int i = i0 + li, j = j0 + lj;
   const bool own = threadIdx.x < kTileS * kTileS && i < N && j < N;
   typedef const int __attribute__((address_space(1)))* gptr_i;
+  typedef const unsigned char __attribute__((address_space(1)))* gptr_u8;
   int ci = -1;
+  bool isact = false;
   float dsx = 0.f, dsy = 0.f, cb0 = 0.f, cb1 = 0.f, cb2 = 0.f;
   if (own) {
-    ci = ((gptr_i)pr.cmap)[w.m_off + i * N + j];
+    if (mode == PG_COMPACT || mode == PG_POL_IN) {  // the compact slope index
+      ci = ((gptr_i)pr.cmap)[w.m_off + i * N + j];
+      isact = ci >= 0;
+    } else {  // the active flag alone
+      isact = ((gptr_u8)pr.amap)[w.m_off + i * N + j] != 0;
+    }
     if (mode == PG_RESID_IN) {  // data residual s - A phi (s placed by the slopes input kernel)
       const gptr_f sd = (gptr_f)(pr.sd + w.s_off);
       dsx = sd[i * N + j];
@@ -1204,7 +1211,7 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
   }
   __syncthreads();
   float sx = 0.f, sy = 0.f, cx = 0.f, cy = 0.f;
-  const bool act = own && ci >= 0;
+  const bool act = own && isact;
   if (act) {
     const float v00 = V[li * CW + lj], v01 = V[li * CW + lj + 1];
     const float v10 = V[(li + 1) * CW + lj], v11 = V[(li + 1) * CW + lj + 1];
@@ -1343,7 +1350,8 @@ __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* 
   const bool weighted = mode == GT_WEIGHTED;
   const int ci0 = t.ty * kGtS, cj0 = t.tx * kGtS;
   const gptr_f sd = (gptr_f)(pr.sd + w.s_off);
-  const gptr_i cmap = (gptr_i)(pr.cmap + w.m_off);
+  typedef const unsigned char __attribute__((address_space(1)))* gptr_u8;
+  const gptr_u8 amap = (gptr_u8)(pr.amap + w.m_off);
   bool act[kR];
   float sx[kR], sy[kR], cb0[kR], cb1[kR], cb2[kR];
 #pragma unroll
@@ -1355,7 +1363,7 @@ __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* 
       const int li = e / SW, lj = e - li * SW;
       const int i = ci0 - 1 + li, j = cj0 - 1 + lj;  // subaperture
       if (i >= 0 && j >= 0 && i < N && j < N) {
-        act[u] = cmap[i * N + j] >= 0;
+        act[u] = amap[i * N + j] != 0;
         sx[u] = sd[i * N + j];
         sy[u] = sd[N * N + i * N + j];
         if (weighted && w.blocks) {
