@@ -231,6 +231,17 @@ FEWHA_API fewha_status fewha_rhs(fewha_ctx* ctx, const float* slopes, float* b);
 FEWHA_API fewha_status fewha_reconstruct(fewha_ctx* ctx, const float* slopes, float* state,
                                          float* layers_out, float* dm_out, int iters);
 
+/* Restart from the true residual every `every` frames (0 = never, the
+ * default): frame f (counted from 0 by the context's calls to
+ * fewha_reconstruct / fewha_reconstruct_streamed) with f > 0 and f a
+ * multiple of `every` takes r0 = b' - M c instead of Algorithm 1's
+ * recurrence r0 = (b' - b) + r, which equals it in exact arithmetic but
+ * accumulates rounding over a long sequence; it costs one more application
+ * of M.  fewha_set_frame_count sets the count (e.g. when a sequence resumes
+ * from a saved state in a new context). */
+FEWHA_API fewha_status fewha_set_refresh(fewha_ctx* ctx, int every);
+FEWHA_API fewha_status fewha_set_frame_count(fewha_ctx* ctx, long frames);
+
 /* fewha_reconstruct for slopes in HOST memory that arrive sensor group by
  * sensor group (pipelining, Sec. 4.3): the sensors are split into `chunks`
  * contiguous groups (1 <= chunks <= min(G, 64)); each group's slopes are
@@ -260,7 +271,7 @@ FEWHA_API fewha_status fewha_reconstruct_streamed(fewha_ctx* ctx, const float* h
  * and must be ordered by the caller.  FEWHA_EINVAL if the context's frame
  * needs more than 16 MiB of work buffers (about 2.9 MB for the 39 m
  * MAORY-like system, 8.6 MB for 9 layers of up to 256 x 256) or uses the
- * DM fitting step. */
+ * DM fitting step, augmentation or the true-residual restart. */
 FEWHA_API fewha_status fewha_reconstruct_noalloc(fewha_ctx* ctx, const float* slopes, float* state,
                                                  float* layers_out, float* dm_out, int iters);
 
@@ -333,6 +344,11 @@ FEWHA_API fewha_status fewha_batch_set_stream(fewha_batch* b, void* hip_stream);
 FEWHA_API fewha_status fewha_batch_reconstruct(fewha_batch* b, const float* const* slopes,
                                                float* const* state, float* const* layers_out,
                                                float* const* dm_out, int iters, int use_graph);
+
+/* The true-residual restart schedule of a batch (as fewha_set_refresh, one
+ * count for the batch's calls to fewha_batch_reconstruct). */
+FEWHA_API fewha_status fewha_batch_set_refresh(fewha_batch* b, int every);
+FEWHA_API fewha_status fewha_batch_set_frame_count(fewha_batch* b, long frames);
 
 /* Batched forms of the calls above: one entry of each host array of device
  * pointers per problem (same layouts and rules).  The batched solves iterate

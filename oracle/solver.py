@@ -119,9 +119,11 @@ class State:
         return st
 
 
-def frame(system, state, s, iters=None, gain=None):
+def frame(system, state, s, iters=None, gain=None, refresh=False):
     """One time step (open or closed loop, F = I); returns (new_state,
-    layers phi = W^{-1} c)."""
+    layers phi = W^{-1} c).  refresh: start from the true residual
+    b - M c^(i) instead of the recurrence (b - b^(i)) + r^(i) (the two agree
+    in exact arithmetic when r^(i) is the previous step's residual)."""
     cfg = system.cfg
     iters = cfg["iters"] if iters is None else iters
     gain = cfg["gain"] if gain is None else gain
@@ -129,7 +131,7 @@ def frame(system, state, s, iters=None, gain=None):
     if closed:  # pseudo-open-loop measurement (two-step delay)
         s = np.asarray(s, dtype=np.float64) + system.apply_A(state.a_prev)
     b = system.rhs(s)
-    r0 = (b - state.b) + state.r
+    r0 = b - system.apply_M(state.c) if refresh else (b - state.b) + state.r
     J = system.preconditioner()
     keep = cfg.get("augment", 0)
     new = State(len(state.c), len(state.a), keep)

@@ -67,6 +67,10 @@ _SIGS = {
     "fewha_set_control": (c_int, [_P, c_double]),
     "fewha_set_loop": (c_int, [_P, c_int]),
     "fewha_set_augmentation": (c_int, [_P, c_int]),
+    "fewha_set_refresh": (c_int, [_P, c_int]),
+    "fewha_set_frame_count": (c_int, [_P, c_long]),
+    "fewha_batch_set_refresh": (c_int, [_P, c_int]),
+    "fewha_batch_set_frame_count": (c_int, [_P, c_long]),
     "fewha_set_photons": (c_int, [_P, c_int, POINTER(c_double)]),
     "fewha_set_fitting": (c_int, [_P, c_int, POINTER(fewha_dm_desc), c_int, POINTER(c_double), c_int, c_int,
                                   c_double]),

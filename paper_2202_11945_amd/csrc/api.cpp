@@ -56,6 +56,7 @@ struct Plan {
   WfsDev* dW = nullptr;
   IoDev* dIO = nullptr;
   IoDev* dIOprof = nullptr;
+  IoDev* dIO2 = nullptr;   // per-call table of a frame's true-residual restart (M c into q)
   Tile* dT = nullptr;
   std::vector<ProbDev> hP;
   std::vector<LayerDev> hL;
@@ -876,6 +877,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   const size_t oW = cv.take(sizeof(WfsDev) * P.hW.size());
   const size_t oIO = cv.take(sizeof(IoDev) * P.nprob_all);
   const size_t oIOp = cv.take(sizeof(IoDev) * P.nprob_all);
+  const size_t oIO2 = cv.take(sizeof(IoDev) * P.nprob_all);
   const size_t oGIO = cv.take(sizeof(GradIo) * P.nprob_all);
   // at least 64 hat entries and 8 band records: the padded prefetch addresses
   hats.hats.resize(std::max<size_t>(hats.hats.size(), 64), HatEnt{0, {0.f, 0.f, 0.f}});
@@ -998,6 +1000,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   P.dW = (WfsDev*)(base + oW);
   P.dIO = (IoDev*)(base + oIO);
   P.dIOprof = (IoDev*)(base + oIOp);
+  P.dIO2 = (IoDev*)(base + oIO2);
   P.dGIO = (GradIo*)(base + oGIO);
   P.dHat = (const HatEnt*)(base + oHat);
   P.nHat = (int)hats.hats.size();
@@ -1182,6 +1185,16 @@ fewha_status take_numeric(Plan& P, std::string& err) {
   return FEWHA_ENUMERIC;
 }
 
+// The true-residual restart's table: in = each problem's state (c first), out = its q.
+fewha_status upload_refresh_io(Plan& P, const std::vector<IoDev>& io, hipStream_t s, std::string& err) {
+  std::vector<IoDev> t(P.nprob);
+  for (int k = 0; k < P.nprob; ++k) {
+    t[k].in = io[k].state;
+    t[k].out = P.hP[k].q;
+  }
+  return upload_io(P, t, s, P.dIO2, err);
+}
+
 LaunchArgs args(const Plan& P, hipStream_t s, const IoDev* io) {
   LaunchArgs a;
   a.P = P.dP;
@@ -1224,18 +1237,32 @@ void enq_apply_M_core(const Plan& P, const LaunchArgs& a) {
   enq_adjoint(P, a, GT_WEIGHTED, PT_PHIADJ);
 }
 
-// One frame after its slopes are in the dense grid with their tip/tilt partials.
-void enq_frame_body(const Plan& P, const LaunchArgs& a, int iters);
+// One frame after its slopes are in the dense grid with their tip/tilt
+// partials; refresh: restart from the true residual b' - M c (q = M c from
+// enq_refresh_mc) instead of Algorithm 1's recurrence (b' - b) + r.
+void enq_frame_body(const Plan& P, const LaunchArgs& a, int iters, bool refresh);
 
-void enq_reconstruct(const Plan& P, const LaunchArgs& a, int iters) {
-  launch_slopes_in(a, T(P, P.sin_frame), P.sin_frame.n);  // open loop: the measured slopes
-  launch_pgamma(a, T(P, P.pg_pol), P.pg_pol.n, PG_POL_IN);  // closed loop: s + Gamma P a^(i-1)
-  enq_frame_body(P, a, iters);
+// q = M c of every problem (the state's c): the operator chain on the second
+// per-call table (in = state, out = q), before the frame's slopes take the
+// dense grid.
+void enq_refresh_mc(const Plan& P, const LaunchArgs& a) {
+  LaunchArgs b = a;
+  b.IO = P.dIO2;
+  enq_idwt(P, b, SRC_IN, OUT_PHI, 0);
+  enq_apply_M_core(P, b);
+  enq_fdwt(P, b, EPI_APPLYM, 0);
 }
 
-void enq_frame_body(const Plan& P, const LaunchArgs& a, int iters) {
+void enq_reconstruct(const Plan& P, const LaunchArgs& a, int iters, bool refresh = false) {
+  if (refresh) enq_refresh_mc(P, a);
+  launch_slopes_in(a, T(P, P.sin_frame), P.sin_frame.n);  // open loop: the measured slopes
+  launch_pgamma(a, T(P, P.pg_pol), P.pg_pol.n, PG_POL_IN);  // closed loop: s + Gamma P a^(i-1)
+  enq_frame_body(P, a, iters, refresh);
+}
+
+void enq_frame_body(const Plan& P, const LaunchArgs& a, int iters, bool refresh) {
   enq_adjoint(P, a, GT_WEIGHTED, PT_PHIADJ);
-  enq_fdwt(P, a, EPI_RHS, 0);
+  enq_fdwt(P, a, refresh ? EPI_RHSQ : EPI_RHS, 0);
   // augmented PCG (Sec. 3.3): start projected against the previous frame's directions
   launch_aug_gram(a, T(P, P.aug), P.aug.n);
   launch_aug_init(a, T(P, P.aug), P.aug.n);
@@ -1506,6 +1533,8 @@ struct fewha_ctx {
   int device = -1;
   hipStream_t stream = nullptr;
   bool finalized = false;
+  long frames = 0;        // frames reconstructed so far (the restart schedule's clock)
+  int refresh_every = 0;  // restart from the true residual every this many frames (0 = never)
   std::string err;
   HostModel m;
   Plan* plan = nullptr;
@@ -1516,6 +1545,8 @@ struct fewha_batch {
   Plan* plan = nullptr;
   hipStream_t stream = nullptr;
   std::string err;
+  long frames = 0;        // as fewha_ctx, for every problem of the batch
+  int refresh_every = 0;
   // frame path in parts (tuning streams > 1): contiguous slices of the
   // problem list, each with its own plan and stream; fork / join events
   std::vector<Plan*> parts;
@@ -1776,6 +1807,10 @@ fewha_status fewha_get_table(const fewha_ctx* c, int which, double* out, long n)
   return FEWHA_OK;
 }
 
+// Frame f (0-based) restarts from the true residual when f > 0 and f is a
+// multiple of the refresh period.
+static bool refresh_due(long frames, int every) { return every > 0 && frames > 0 && frames % every == 0; }
+
 static fewha_status ready(fewha_ctx* c) {
   if (!c) return FEWHA_EINVAL;
   if (!c->finalized) return fail(c, FEWHA_ESTATE, "context not finalized");
@@ -1865,9 +1900,26 @@ fewha_status fewha_reconstruct(fewha_ctx* c, const float* slopes, float* state, 
   io[0].layers_out = layers_out;
   io[0].dm_out = dm_out;
   if ((s = upload_io(P, io, c->stream, P.dIO, c->err)) != FEWHA_OK) return s;
+  const bool refresh = refresh_due(c->frames, c->refresh_every);
+  if (refresh && (s = upload_refresh_io(P, io, c->stream, c->err)) != FEWHA_OK) return s;
   LaunchArgs a = args(P, c->stream, P.dIO);
-  enq_reconstruct(P, a, iters);
+  enq_reconstruct(P, a, iters, refresh);
+  ++c->frames;
   return finish(c);
+}
+
+fewha_status fewha_set_refresh(fewha_ctx* c, int every) {
+  CHECK_CTX(c);
+  if (every < 0) return fail(c, FEWHA_EINVAL, "set_refresh: every must be >= 0");
+  c->refresh_every = every;
+  return FEWHA_OK;
+}
+
+fewha_status fewha_set_frame_count(fewha_ctx* c, long frames) {
+  CHECK_CTX(c);
+  if (frames < 0) return fail(c, FEWHA_EINVAL, "set_frame_count: frames must be >= 0");
+  c->frames = frames;
+  return FEWHA_OK;
 }
 
 fewha_status fewha_reconstruct_noalloc(fewha_ctx* c, const float* slopes, float* state, float* layers_out,
@@ -1878,8 +1930,9 @@ fewha_status fewha_reconstruct_noalloc(fewha_ctx* c, const float* slopes, float*
   if (iters < 0 || iters > kMaxIters) return fail(c, FEWHA_EINVAL, "reconstruct_noalloc: iters must lie in [0, 256]");
   if (((uintptr_t)state & 15) != 0) return fail(c, FEWHA_EINVAL, "reconstruct_noalloc: state must be 16-byte aligned");
   Plan& P = *c->plan;
-  if (c->m.fit.on || c->m.aug_keep > 0)
-    return fail(c, FEWHA_EINVAL, "reconstruct_noalloc: not available with the DM fitting step or augmentation");
+  if (c->m.fit.on || c->m.aug_keep > 0 || c->refresh_every > 0)
+    return fail(c, FEWHA_EINVAL,
+                "reconstruct_noalloc: not available with the DM fitting step, augmentation or residual refresh");
   if (P.na_bytes > kNoAllocBytes)
     return fail(c, FEWHA_EINVAL, "reconstruct_noalloc: the frame needs " + std::to_string(P.na_bytes) +
                                      " bytes of scratch; the static scratch holds " + std::to_string(kNoAllocBytes));
@@ -1901,6 +1954,7 @@ fewha_status fewha_reconstruct_noalloc(fewha_ctx* c, const float* slopes, float*
   LaunchArgs a = args(P, c->stream, P.na_io);
   a.P = P.dPna;
   enq_reconstruct(P, a, iters);
+  ++c->frames;
   return finish(c);
 }
 
@@ -1935,7 +1989,10 @@ fewha_status fewha_reconstruct_streamed(fewha_ctx* c, const float* host_slopes, 
   io[0].layers_out = layers_out;
   io[0].dm_out = dm_out;
   if ((s = upload_io(P, io, st, P.dIO, err)) != FEWHA_OK) return s;
+  const bool refresh = refresh_due(c->frames, c->refresh_every);
+  if (refresh && (s = upload_refresh_io(P, io, st, err)) != FEWHA_OK) return s;
   const LaunchArgs a = args(P, st, P.dIO);
+  if (refresh) enq_refresh_mc(P, a);
   // closed loop: the mirrors' part of the pseudo-open-loop slopes while the measurement arrives
   if (m.closed) launch_pgamma(a, T(P, P.pg), P.pg.n, PG_APREV);
   for (int q = 0; q < chunks; ++q) {
@@ -1943,7 +2000,8 @@ fewha_status fewha_reconstruct_streamed(fewha_ctx* c, const float* host_slopes, 
     HIP_TRY(hipStreamWaitEvent(st, P.chunk_ev[q], 0));
     launch_slopes_in(a, T(P, P.sin) + P.sin_g[g0], P.sin_g[g1] - P.sin_g[g0], m.closed ? 1 : 0);
   }
-  enq_frame_body(P, a, iters);
+  enq_frame_body(P, a, iters, refresh);
+  ++c->frames;
   return finish(c);
 }
 
@@ -2065,25 +2123,27 @@ fewha_status fewha_batch_set_stream(fewha_batch* b, void* s) {
 // captured graph of `iters` iterations (captured on first use) or the plain
 // launches.
 static fewha_status run_frame(Plan& P, hipStream_t st, const std::vector<IoDev>& io, int iters, int use_graph,
-                              std::string& err) {
+                              bool refresh, std::string& err) {
   fewha_status s = upload_io(P, io, st, P.dIO, err);
   if (s != FEWHA_OK) return s;
+  if (refresh && (s = upload_refresh_io(P, io, st, err)) != FEWHA_OK) return s;
   P.last_io = io;
   P.ran = true;
   if (!use_graph) {
-    enq_reconstruct(P, args(P, st, P.dIO), iters);
+    enq_reconstruct(P, args(P, st, P.dIO), iters, refresh);
     return FEWHA_OK;
   }
-  auto it = P.graphs.find(iters);
+  const int key = 2 * iters + (refresh ? 1 : 0);  // one graph per iteration count and restart kind
+  auto it = P.graphs.find(key);
   if (it == P.graphs.end()) {
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
     HIP_TRY(hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal));
-    enq_reconstruct(P, args(P, P.cap_stream, P.dIO), iters);
+    enq_reconstruct(P, args(P, P.cap_stream, P.dIO), iters, refresh);
     HIP_TRY(hipStreamEndCapture(P.cap_stream, &g));
     HIP_TRY(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-    P.graph_defs[iters] = g;
-    it = P.graphs.emplace(iters, ge).first;
+    P.graph_defs[key] = g;
+    it = P.graphs.emplace(key, ge).first;
   }
   HIP_TRY(hipGraphLaunch(it->second, st));
   return FEWHA_OK;
@@ -2109,8 +2169,9 @@ fewha_status fewha_batch_reconstruct(fewha_batch* b, const float* const* slopes,
   }
   HIP_TRY(hipSetDevice(P.device));
   fewha_status s;
+  const bool refresh = refresh_due(b->frames, b->refresh_every);
   if (b->parts.empty()) {
-    if ((s = run_frame(P, b->stream, io, iters, use_graph, err)) != FEWHA_OK) return s;
+    if ((s = run_frame(P, b->stream, io, iters, use_graph, refresh, err)) != FEWHA_OK) return s;
   } else {
     // fork: every part waits for the work queued before this call
     HIP_TRY(hipEventRecord(b->fork, b->stream));
@@ -2118,7 +2179,7 @@ fewha_status fewha_batch_reconstruct(fewha_batch* b, const float* const* slopes,
       Plan& Q = *b->parts[q];
       const std::vector<IoDev> ioq(io.begin() + b->part_first[q], io.begin() + b->part_first[q] + Q.nprob);
       HIP_TRY(hipStreamWaitEvent(b->part_stream[q], b->fork, 0));
-      if ((s = run_frame(Q, b->part_stream[q], ioq, iters, use_graph, err)) != FEWHA_OK) return s;
+      if ((s = run_frame(Q, b->part_stream[q], ioq, iters, use_graph, refresh, err)) != FEWHA_OK) return s;
       HIP_TRY(hipEventRecord(b->part_done[q], b->part_stream[q]));
     }
     // join: work queued after this call waits for every part
@@ -2126,8 +2187,21 @@ fewha_status fewha_batch_reconstruct(fewha_batch* b, const float* const* slopes,
     P.last_io = io;  // stage timing runs the whole batch's plan on these buffers
     P.ran = true;
   }
+  ++b->frames;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return bfail(b, FEWHA_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  return FEWHA_OK;
+}
+
+fewha_status fewha_batch_set_refresh(fewha_batch* b, int every) {
+  if (!b || every < 0) return FEWHA_EINVAL;
+  b->refresh_every = every;
+  return FEWHA_OK;
+}
+
+fewha_status fewha_batch_set_frame_count(fewha_batch* b, long frames) {
+  if (!b || frames < 0) return FEWHA_EINVAL;
+  b->frames = frames;
   return FEWHA_OK;
 }
 

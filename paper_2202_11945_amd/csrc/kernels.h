@@ -12,7 +12,7 @@ enum { SRC_IN = 0, SRC_STATE_C = 1, SRC_PUPD0 = 2, SRC_PUPD = 3, SRC_PJ = 4 };
 // destination of the inverse transform
 enum { OUT_PHI = 0, OUT_USER = 1, OUT_FIT = 2 };
 // epilogue of the forward transform
-enum { EPI_APPLYM = 0, EPI_PCG = 1, EPI_RHS = 2, EPI_PLAIN = 3 };
+enum { EPI_APPLYM = 0, EPI_PCG = 1, EPI_RHS = 2, EPI_PLAIN = 3, EPI_RHSQ = 4 };
 // propagation + Shack-Hartmann output
 //   PG_COMPACT : io.in -> compact slopes in io.out      (A x)
 //   PG_DENSE   : phi -> dense slopes + tip/tilt partials (inside M)

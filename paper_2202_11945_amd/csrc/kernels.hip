@@ -254,6 +254,7 @@ __device__ __forceinline__ void out_finish(const OutDst& d, int e, float v, cons
 //   EPI_APPLYM: out = v + alpha D x            (M x)
 //   EPI_PCG   : q = v + alpha D p, += p q      (M p and pi)
 //   EPI_RHS   : b' = v, r0 = (b' - b) + r      (warm restart), += r0 J^{-1} r0
+//   EPI_RHSQ  : b' = v, r0 = b' - q            (restart from the true residual, q = M c), += r0 J^{-1} r0
 //   EPI_PLAIN : out = v                        (right-hand side only)
 struct EpiLoad {
   float x0, x1, x2;
@@ -267,6 +268,9 @@ __device__ __forceinline__ EpiLoad epi_fetch(const ProbDev& pr, const IoDev& io,
   } else if (epi == EPI_RHS) {
     l.x0 = ((gptr_f)io.state)[pr.n_c + e];
     l.x1 = ((gptr_f)io.state)[2L * pr.n_c + e];
+    l.x2 = ((gptr_f)pr.jinv)[e];
+  } else if (epi == EPI_RHSQ) {
+    l.x0 = ((gptr_f)pr.q)[e];
     l.x2 = ((gptr_f)pr.jinv)[e];
   }
   return l;
@@ -293,8 +297,8 @@ __device__ __forceinline__ void epi_finish(const EpiDst& dst, int epi, int e, fl
     const float qe = v + ad * l.x0;
     dst.q[e] = qe;
     acc += (double)l.x0 * (double)qe;
-  } else if (epi == EPI_RHS) {
-    const float r0 = (v - l.x0) + l.x1;
+  } else if (epi == EPI_RHS || epi == EPI_RHSQ) {
+    const float r0 = epi == EPI_RHS ? (v - l.x0) + l.x1 : v - l.x0;
     dst.b[e] = v;
     dst.r[e] = r0;
     acc += (double)r0 * (double)r0 * (double)l.x2;
@@ -855,7 +859,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     for (int k = 0; k < 4; ++k)
       if (epos[k] >= 0) epi_finish(dst, epi, epos[k], ad, eval[k], el[k], acc);
   }
-  if (epi == EPI_PCG || epi == EPI_RHS) {
+  if (epi == EPI_PCG || epi == EPI_RHS || epi == EPI_RHSQ) {
     const double s = block_sum(acc, sh, nt);
     if (threadIdx.x == 0) ((gptr_wd)pr.dots)[(long)dot_group_of(epi, iter) * pr.n_dots + t.slot] = s;
   }
@@ -1042,7 +1046,7 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
     const EpiLoad l = epi_fetch(pr, io, EPI, iter, pos);
     epi_finish(dst, EPI, pos, adll, A[r * S + c] * ly.inv_delta, l, acc);
   }
-  if (EPI == EPI_PCG || EPI == EPI_RHS) {
+  if (EPI == EPI_PCG || EPI == EPI_RHS || EPI == EPI_RHSQ) {
     const double s = block_sum(acc, sh, nt);
     if (threadIdx.x == 0) ((gptr_wd)pr.dots)[(long)dot_group_of(EPI, iter) * pr.n_dots + t.slot] = s;
   }
@@ -2336,6 +2340,7 @@ static void launch_fdwt_res_r(const LaunchArgs& a, const Tile* tiles, int ntiles
     case EPI_APPLYM: k_fdwt_res<RMAX, EPI_APPLYM><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, iter); break;
     case EPI_PCG: k_fdwt_res<RMAX, EPI_PCG><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, iter); break;
     case EPI_RHS: k_fdwt_res<RMAX, EPI_RHS><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, iter); break;
+    case EPI_RHSQ: k_fdwt_res<RMAX, EPI_RHSQ><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, iter); break;
     default: k_fdwt_res<RMAX, EPI_PLAIN><<<ntiles, 1024, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, iter); break;
   }
 }

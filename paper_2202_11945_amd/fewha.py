@@ -194,6 +194,13 @@ class Context:
                                       _ptr(layers_out, self.n_coeff), _ptr(dm_out, self.n_act), int(iters)),
                self.h)
 
+    def fewha_set_refresh(self, every):
+        """Restart from the true residual every `every` frames (0 = never)."""
+        _check(_abi.fewha_set_refresh(self.h, int(every)), self.h)
+
+    def fewha_set_frame_count(self, frames):
+        _check(_abi.fewha_set_frame_count(self.h, int(frames)), self.h)
+
     def fewha_reconstruct_streamed(self, host_slopes, state, layers_out=None, dm_out=None, iters=None, chunks=1):
         """fewha_reconstruct from slopes in a host float32 tensor (pinned for
         asynchronous copies), taken in by `chunks` sensor groups as they
@@ -275,6 +282,8 @@ class Context:
     reconstruct = fewha_reconstruct
     reconstruct_noalloc = fewha_reconstruct_noalloc
     reconstruct_streamed = fewha_reconstruct_streamed
+    set_refresh = fewha_set_refresh
+    set_frame_count = fewha_set_frame_count
 
 
 class Batch:
@@ -311,6 +320,12 @@ class Batch:
             self.h, arr(slopes, [c.n_slopes for c in self.ctxs]), arr(states, [c.n_state for c in self.ctxs]),
             arr(layers_out, [c.n_coeff for c in self.ctxs]), arr(dm_out, [c.n_act for c in self.ctxs]),
             int(iters), 1 if use_graph else 0), batch_handle=self.h)
+
+    def fewha_batch_set_refresh(self, every):
+        _check(_abi.fewha_batch_set_refresh(self.h, int(every)), batch_handle=self.h)
+
+    def fewha_batch_set_frame_count(self, frames):
+        _check(_abi.fewha_batch_set_frame_count(self.h, int(frames)), batch_handle=self.h)
 
     def fewha_batch_time_stage(self, stage, reps=20):
         us, wg = c_double(), c_long()
@@ -379,6 +394,8 @@ class Batch:
 
     reconstruct = fewha_batch_reconstruct
     time_stage = fewha_batch_time_stage
+    set_refresh = fewha_batch_set_refresh
+    set_frame_count = fewha_batch_set_frame_count
     solve = fewha_batch_solve
     solve_map = fewha_batch_solve_map
     apply_Winv = fewha_batch_apply_Winv

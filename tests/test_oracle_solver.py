@@ -118,3 +118,16 @@ def test_zero_right_hand_side_gives_zero(systems):
     st = State(S.geom.n_coeff, S.geom.n_coeff)
     st1, phi = frame(S, st, np.zeros(S.A.shape[0]), iters=4)
     assert not np.any(st1.pack()) and not np.any(phi)
+
+
+def test_true_residual_restart_agrees_with_the_recurrence(systems):
+    # Algorithm 1's r0 = (b^(i+1) - b^(i)) + r^(i) equals b^(i+1) - M c^(i) when
+    # r^(i) is the previous step's residual: a restarted step is the same step
+    S = systems("small")
+    st = State(S.geom.n_coeff, S.geom.n_coeff)
+    for k in range(3):
+        st, _ = frame(S, st, _slopes(S, k))
+    a, pa = frame(S, st, _slopes(S, 3))
+    b, pb = frame(S, st, _slopes(S, 3), refresh=True)
+    for u, v in ((a.c, b.c), (a.r, b.r), (pa, pb)):
+        assert np.linalg.norm(u - v) <= 1e-9 * np.linalg.norm(u)
