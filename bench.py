@@ -166,7 +166,7 @@ def measured_traffic(stage, batch, tuning):
     for f in ("kernels.hip", "kernels.h", "fewha_internal.h", "api.cpp"):
         h.update(open(os.path.join(ROOT, "paper_2202_11945_amd", "csrc", f), "rb").read())
     sha = h.hexdigest()[:16]
-    tune = "%d/%d" % (tuning["dwt_resident"], tuning["pt_rows"])
+    tune = "%d/%d/%d" % (tuning["dwt_resident"], tuning["pt_rows"], tuning.get("res_split", 0))
     prof = os.path.join(ROOT, "profiles", "stages_maory_like_b%d_bytes.md" % batch)
     if not os.path.exists(prof):
         return None

@@ -26,6 +26,8 @@ def main():
     ap.add_argument("--pt-rows", type=int, default=0, help="node rows per thread of P^T (0 = default)")
     ap.add_argument("--split", type=int, default=0, help="resident inverse levels: 0 default, 1 or 4 workgroups")
     ap.add_argument("--tuned", action="store_true", help="launch shapes from the autotuner (as bench.py)")
+    ap.add_argument("--latency-frames", type=int, default=0,
+                    help="then this many single frames of one problem (graph replays, synchronized each)")
     a = ap.parse_args()
     import torch
 
@@ -51,6 +53,18 @@ def main():
     for sid, name in enumerate(fw._abi.STAGES):
         us, wg = batch.time_stage(sid, reps=a.reps)
         print("stage %-10s %9.2f us  workgroups %d" % (name, us, wg), flush=True)
+    if a.latency_frames > 0:
+        single = fw.Batch([ctxs[0]], tuning=tuning)
+        st = torch.zeros(ctxs[0].n_state, device=dev)
+        for _ in range(3):
+            single.reconstruct([slopes[0]], [st], iters=a.iters, use_graph=True)
+        torch.cuda.synchronize()
+        print("single frames start", flush=True)
+        for _ in range(a.latency_frames):
+            single.reconstruct([slopes[0]], [st], iters=a.iters, use_graph=True)
+            torch.cuda.synchronize()
+        print("single frames done", flush=True)
+        single.close()
     x = torch.empty(64 * 2 ** 20, dtype=torch.float32, device=dev).fill_(1.0)
     y = torch.empty_like(x)
     for _ in range(3):
