@@ -48,10 +48,13 @@ def test_elongated_block_noise(gpu_lib):
 
 
 def test_paper_maory_geometry(gpu_lib):
+    # the paper's runs take 2 (augmented) and 4 iterations per frame: both,
+    # the second a warm frame from the first one's state
     cfg = get_config("paper_maory")
     S = system("paper_maory", cfg)
     ctx = _ops(gpu_lib, S, cfg, 2)
-    _check_frame(gpu_lib, S, ctx, np.zeros(5 * S.geom.n_coeff, np.float32), synth_slopes(S, 0))
+    g = _check_frame(gpu_lib, S, ctx, np.zeros(5 * S.geom.n_coeff, np.float32), synth_slopes(S, 0), iters=2)
+    _check_frame(gpu_lib, S, ctx, g.pack().astype(np.float32), synth_slopes(S, 1), iters=4)
 
 
 def test_vlt_like_geometry(gpu_lib):
