@@ -48,6 +48,7 @@ struct Plan {
   int nprob = 0;
   int res_max = kResMax;  // resident transform side (tuning)
   int pt_rows = 4;        // node rows per thread of the propagation adjoint (tuning)
+  bool pt_wide = false;   // some (sensor, layer) pair has K > 3 corners per node (wide band records)
   std::vector<const HostModel*> models;
   void* arena = nullptr;
   size_t arena_bytes = 0;
@@ -156,47 +157,70 @@ void destroy_plan(Plan* p) {
 // the node (t = t0 + k rho within one node spacing, found in FP64) and their
 // weights 1 - rho |k - c| with c = (p - t0) / rho, the transpose of the
 // forward interpolation weights.
+struct NodeHat {
+  int lo;
+  float w[kWideMaxK];
+};
+std::vector<NodeHat> node_hats(const GLPar& gp, int n, int axis) {
+  const int K = gp.kmax;
+  const double t0 = axis == 0 ? gp.t0y : gp.t0x;
+  std::vector<NodeHat> out;
+  for (int p = 0; p < n; ++p) {
+    const double c = ((double)p - t0) * gp.inv_rho;
+    const int lo = std::max((int)std::floor(c - gp.inv_rho) + 1, 0);
+    const int hi = std::min((int)std::ceil(c + gp.inv_rho) - 1, gp.nc - 1);
+    // no corner (outside the footprint, or between corners when rho > 2):
+    // weights 0 on the valid corners at floor(c), so that lo never
+    // decreases along the axis
+    NodeHat e{std::max(0, std::min((int)std::floor(c), gp.nc - K)), {}};
+    if (hi >= lo) {
+      const int base = std::max(0, std::min(lo, gp.nc - K));
+      e.lo = base;
+      for (int k = 0; k < K; ++k) {
+        const int corner = base + k;
+        if (corner >= lo && corner <= hi)
+          e.w[k] = (float)std::max(0.0, 1.0 - gp.rho * std::fabs((double)corner - c));
+      }
+    }
+    out.push_back(e);
+  }
+  return out;
+}
+
+// Hat entries per node: one, two for a wide pair (K > 3).
+int hat_per_node(int K) { return K > 3 ? 2 : 1; }
+
 void append_hats(GLPar& gp, int n, std::vector<HatEnt>& out) {
   gp.hat_off = (int)out.size();
-  const int K = gp.kmax;
-  for (int axis = 0; axis < 2; ++axis) {
-    const double t0 = axis == 0 ? gp.t0y : gp.t0x;
-    for (int p = 0; p < n; ++p) {
-      const double c = ((double)p - t0) * gp.inv_rho;
-      const int lo = std::max((int)std::floor(c - gp.inv_rho) + 1, 0);
-      const int hi = std::min((int)std::ceil(c + gp.inv_rho) - 1, gp.nc - 1);
-      // no corner (outside the footprint, or between corners when rho > 2):
-      // weights 0 on the valid corners at floor(c), so that lo never
-      // decreases along the axis
-      HatEnt e{std::max(0, std::min((int)std::floor(c), gp.nc - K)), {0.f, 0.f, 0.f}};
-      if (hi >= lo) {
-        const int base = std::max(0, std::min(lo, gp.nc - K));
-        e.lo = base;
-        for (int k = 0; k < K; ++k) {
-          const int corner = base + k;
-          if (corner >= lo && corner <= hi)
-            e.w[k] = (float)std::max(0.0, 1.0 - gp.rho * std::fabs((double)corner - c));
-        }
-      }
-      out.push_back(e);
-    }
-  }
+  const int per = hat_per_node(gp.kmax);
+  for (int axis = 0; axis < 2; ++axis)
+    for (const NodeHat& e : node_hats(gp, n, axis))
+      for (int h = 0; h < per; ++h) out.push_back(HatEnt{e.lo, {e.w[3 * h], e.w[3 * h + 1], e.w[3 * h + 2]}});
 }
 
 // Propagation-adjoint tables of one (sensor, layer) pair: hat tables with K =
-// 2 or 3 corners per node and axis when the corner spacing is at least 2/3 of
+// 2 .. 6 corners per node and axis when the corner spacing is at least 1/3 of
 // the node spacing, and one band record per kBandRows node rows, whose corner
-// rows must fit pt_band(K, kBandRows); otherwise kmax = 0, the general
-// gather.  Pairs of the same geometry (every problem of a batch of one
-// system) share one copy of the tables.
+// rows must fit pt_band(K, kBandRows) (K <= 3) or pt_band_wide(K); otherwise
+// kmax = 0, the general gather.  Pairs of the same geometry (every problem of
+// a batch of one system) share one copy of the tables.
 struct HatTables {
   std::vector<HatEnt> hats;
   std::vector<BandRec> bands;
   std::map<std::tuple<double, double, double, int, int>, std::array<int, 3>> seen;  // -> kmax, hat_off, band_off
 };
 
+int kmax_of(double rho) {
+  if (rho >= 1.0) return 2;
+  if (rho >= 2.0 / 3.0) return 3;
+  if (rho >= 0.5) return 4;
+  if (rho >= 0.4) return 5;
+  if (rho >= 1.0 / 3.0) return 6;
+  return 0;
+}
+
 void set_hats(GLPar& gp, int n, HatTables& T) {
-  gp.kmax = gp.rho >= 1.0 ? 2 : (gp.rho >= 2.0 / 3.0 ? 3 : 0);
+  gp.kmax = kmax_of(gp.rho);
   gp.hat_off = gp.band_off = -1;
   if (gp.kmax > 0 && gp.nc < gp.kmax) gp.kmax = 0;  // tiny sensor
   if (gp.kmax == 0) return;
@@ -208,12 +232,13 @@ void set_hats(GLPar& gp, int n, HatTables& T) {
     gp.band_off = hit->second[2];
     return;
   }
-  const int K = gp.kmax, SB = pt_band(K, kBandRows);
-  append_hats(gp, n, T.hats);
+  const int K = gp.kmax;
+  const bool wide = K > 3;
+  const int SB = wide ? pt_band_wide(K) : pt_band(K, kBandRows);
+  const std::vector<NodeHat> rows = node_hats(gp, n, 0);
   std::vector<BandRec> recs;
   bool fits = true;
   for (int p = 0; p < n && fits; p += kBandRows) {
-    const HatEnt* rows = T.hats.data() + gp.hat_off;
     const int last = std::min(p + kBandRows - 1, n - 1);
     const int ilo = rows[p].lo;
     if (rows[last].lo + K - ilo > SB) {
@@ -221,12 +246,12 @@ void set_hats(GLPar& gp, int n, HatTables& T) {
       break;
     }
     const int cnt = std::min(kBandRows, n - p);  // node rows of the group inside the layer
-    BandRec r{};
     bool zero = true;
     for (int u = 0; u < cnt; ++u)
       for (int k = 0; k < K; ++k) zero = zero && rows[p + u].w[k] == 0.f;
-    // step pattern: every node row inside the layer, steps of K - 2 or K - 1
-    int pat = cnt == kBandRows ? 0 : -1;
+    // step pattern (narrow pairs): every node row inside the layer, steps of
+    // K - 2 or K - 1
+    int pat = (cnt == kBandRows && !wide) ? 0 : -1;
     for (int u = 1; u < kBandRows && pat >= 0; ++u) {
       const int step = rows[p + u].lo - rows[p + u - 1].lo - (K - 2);
       if (step == 1)
@@ -237,26 +262,32 @@ void set_hats(GLPar& gp, int n, HatTables& T) {
     // first band row: the group's first corner, or (dense records) moved up
     // so that the band stays inside the grid where it can
     const int base = pat >= 0 ? ilo : std::max(0, std::min(ilo, gp.nc - SB));
-    r.so0 = base * gp.nc * (int)sizeof(float);
-    r.pat = zero ? kPatZero : (pat >= 0 ? pat : kPatDense);
-    r.nrows = std::min(SB, gp.nc - base);
-    for (int u = 0; u < cnt; ++u)
+    BandRec r{};
+    BandRecW rw{};
+    r.so0 = rw.so0 = base * gp.nc * (int)sizeof(float);
+    r.pat = rw.pat = zero ? kPatZero : (pat >= 0 ? pat : kPatDense);
+    r.nrows = rw.nrows = std::min(SB, gp.nc - base);
+    for (int u = 0; u < cnt && fits; ++u)
       for (int k = 0; k < K; ++k) {
         const int s = rows[p + u].lo + k - base;
         if (s < 0 || s >= r.nrows) {
           fits = false;
           break;
         }
-        r.wk[u][k] = rows[p + u].w[k];
-        r.w[u][s] = rows[p + u].w[k];
+        if (wide) {
+          rw.w[u][s] = rows[p + u].w[k];
+        } else {
+          r.wk[u][k] = rows[p + u].w[k];
+          r.w[u][s] = rows[p + u].w[k];
+        }
       }
+    if (wide) std::memcpy(&r, &rw, sizeof(r));
     recs.push_back(r);
   }
   if (!fits) {
-    T.hats.resize(gp.hat_off);
     gp.kmax = 0;
-    gp.hat_off = -1;
   } else {
+    append_hats(gp, n, T.hats);
     gp.band_off = (int)T.bands.size();
     T.bands.insert(T.bands.end(), recs.begin(), recs.end());
   }
@@ -276,14 +307,16 @@ bool pair_meets_tile(const GLPar& gp, const HatTables& T, int n, int p0, int ph,
     auto meets = [&](double t0, int a, int ext) { return a + ext - 1 >= t0 - 2.0 && a <= t0 + span + 2.0; };
     return meets(gp.t0y, p0, ph) && meets(gp.t0x, q0, qw);
   }
+  const int per = hat_per_node(gp.kmax);
   auto any = [&](int first, int a, int ext) {
-    for (int p = a; p < std::min(a + ext, n); ++p) {
-      const HatEnt& e = T.hats[(size_t)first + p];
-      if (e.w[0] != 0.f || e.w[1] != 0.f || e.w[2] != 0.f) return true;
-    }
+    for (int p = a; p < std::min(a + ext, n); ++p)
+      for (int h = 0; h < per; ++h) {
+        const HatEnt& e = T.hats[(size_t)first + per * p + h];
+        if (e.w[0] != 0.f || e.w[1] != 0.f || e.w[2] != 0.f) return true;
+      }
     return false;
   };
-  return any(gp.hat_off, p0, ph) && any(gp.hat_off + n, q0, qw);
+  return any(gp.hat_off, p0, ph) && any(gp.hat_off + per * n, q0, qw);
 }
 
 // Longest first within each XCD's run of a launch's tiles: workgroup b runs
@@ -314,12 +347,13 @@ struct PtLists {
     if (use.size() > 63) return {-1, 0};  // a wave reads its tile's list (and the pad) from 64 lanes
     for (int g : use) {
       const GLPar& gp = gl[(size_t)g * L + item];
-      PtEnt e{gp.v_off, gp.nc << 2 | gp.kmax, 0, 0};
+      PtEnt e{gp.v_off, gp.nc << 3 | gp.kmax, 0, 0};
       if (gp.kmax > 0) {
-        e.hx = gp.hat_off + n + tx * kPtW;
+        const int per = hat_per_node(gp.kmax);
+        e.hx = gp.hat_off + per * (n + tx * kPtW);
         e.band = gp.band_off + ty * pt_rows;  // kBandRows rows per record, 4 pt_rows rows per tile
       } else {
-        e.nck = (g * L + item) << 2;
+        e.nck = (g * L + item) << 3;
       }
       key.insert(key.end(), {e.v_off, e.nck, e.hx, e.band});
     }
@@ -879,6 +913,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   const size_t oIOp = cv.take(sizeof(IoDev) * P.nprob_all);
   const size_t oIO2 = cv.take(sizeof(IoDev) * P.nprob_all);
   const size_t oGIO = cv.take(sizeof(GradIo) * P.nprob_all);
+  for (const auto& kv : hats.seen) P.pt_wide = P.pt_wide || kv.second[0] > 3;
   // at least 64 hat entries and 8 band records: the padded prefetch addresses
   hats.hats.resize(std::max<size_t>(hats.hats.size(), 64), HatEnt{0, {0.f, 0.f, 0.f}});
   hats.bands.resize(std::max<size_t>(hats.bands.size(), 8), BandRec{});
@@ -1205,6 +1240,7 @@ LaunchArgs args(const Plan& P, hipStream_t s, const IoDev* io) {
   a.stream = s;
   a.res_max = P.res_max;
   a.pt_rows = P.pt_rows;
+  a.pt_wide = P.pt_wide ? 1 : 0;
   a.hats = P.dHat;
   a.n_hats = P.nHat;
   a.bands = P.dBand;

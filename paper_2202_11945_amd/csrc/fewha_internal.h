@@ -27,6 +27,13 @@ constexpr int kPtW = 64;          // propagation adjoint tile: 64 node columns (
 constexpr int pt_band(int K, int rpt) { return K == 2 ? rpt + 2 : (3 * (rpt - 1)) / 2 + K + 2; }
 constexpr int kBandRows = 4;                    // node rows of one band record
 constexpr int kBandMax = pt_band(3, kBandRows);  // corner rows of the widest band
+// Sensors sampling a layer finer than 2/3 of its spacing (rho in [1/3, 2/3))
+// have K = 4, 5 or 6 corners per node and axis ("wide" pairs).  Consecutive
+// first corners then differ by at most ceil(1 / rho), so kBandRows node rows
+// touch at most ceil(3 / rho) + K corner rows: 10, 13 or 15.
+constexpr int kWideMaxK = 6;
+constexpr int pt_band_wide(int K) { return K == 4 ? 10 : (K == 5 ? 13 : 15); }
+constexpr int kBandWideMax = pt_band_wide(kWideMaxK);
 constexpr int kUpdChunk = 2048;   // coefficients per workgroup of the vector update
 constexpr int kDotRing = 256;     // PCG iterations whose inner products are kept (ring, power of two)
 constexpr int kGradChunk = 2048;  // coefficients per workgroup of the prior-term reductions
@@ -105,7 +112,8 @@ struct WfsDev {
 // sensor sits at t = t0 + k rho along each axis (rho = cone factor x pitch /
 // layer spacing) and its bilinear weight on node p is the hat function
 // max(0, 1 - |t - p|).  kmax = most corners within one node spacing of a
-// node along an axis (2 when rho >= 1, 3 when rho >= 2/3, 0 = finer).
+// node along an axis (2 when rho >= 1, 3 when rho >= 2/3, 4, 5, 6 when rho >=
+// 1/2, 2/5, 1/3; 0 = finer, or a band that does not fit: general gather).
 struct GLPar {
   double t0y, t0x, rho, inv_rho;
   int nc, v_off, kmax;
@@ -117,7 +125,9 @@ struct GLPar {
 // The corners of one node along one axis: corner lo + k has weight w[k]
 // (k < K = kmax; lo clamped so that lo + K - 1 < nc, unused weights 0);
 // a node that no corner's cell touches has all weights 0 and lo =
-// clamp(floor(c), 0, nc - K), so lo never decreases along an axis.
+// clamp(floor(c), 0, nc - K), so lo never decreases along an axis.  A wide
+// pair (K > 3) has two entries per node: the second holds w[3 .. 5] (its lo
+// repeats the first's).
 struct HatEnt {
   int lo;
   float w[3];
@@ -145,13 +155,22 @@ struct BandRec {
   int pad2_[12];
 };
 static_assert(sizeof(BandRec) == 256, "band record: 64 dwords");
+// The band record of a wide pair, in the same 256 bytes of the band array:
+// always dense (pat kPatDense or kPatZero), node row u weighting band row s
+// by w[u][s].
+struct BandRecW {
+  int so0, pat, nrows, pad_;
+  float w[kBandRows][kBandWideMax];
+};
+static_assert(sizeof(BandRecW) == sizeof(BandRec), "wide band record: 64 dwords");
 
 // One sensor of a propagation-adjoint tile's list (the sensors whose
 // footprint meets the tile, in sensor order), all a wave needs for it:
 //   v_off : the sensor's corner grid in the problem's corner array
-//   nck   : K > 0: corner grid side nc << 2 | K;
-//           K = 0 (general gather): index of the pair's GLPar << 2
-//   hx    : K > 0: hat-table index of the tile's first node column, else 0
+//   nck   : K > 0: corner grid side nc << 3 | K;
+//           K = 0 (general gather): index of the pair's GLPar << 3
+//   hx    : K > 0: hat-table index of the tile's first node column (its
+//           first entry: two per node of a wide pair), else 0
 //   band  : K > 0: band record of the tile's first kBandRows node rows, else 0
 // Every list ends with one more entry {0, 2, 0, 0} that is never run (the
 // sensor loop prefetches one entry ahead); the hat and band arrays hold at

@@ -43,6 +43,7 @@ struct LaunchArgs {
   const BandRec* bands;   // band records of the propagation adjoint (plan-wide)
   const PtEnt* pents;     // sensor lists of the propagation-adjoint tiles (plan-wide)
   int pt_rows;         // node rows per thread of the propagation adjoint (4 or 8)
+  int pt_wide;         // 1: some pair has K > 3 corners per node (the kernel with wide records)
 };
 
 void launch_idwt_res(const LaunchArgs& a, const Tile* tiles, int ntiles, int src_mode, int out_mode, int iter);

@@ -1460,8 +1460,9 @@ __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* 
 // row whose hat covers it; a record's step pattern fixes at compile time
 // which band rows each node row reads.  A tile lists only the sensors with a
 // nonzero hat in its rows and columns.  Sensors sampling the layer finer than
-// 2/3 of its spacing, or whose band would exceed the register budget (kmax =
-// 0), take a general loop.  No atomics: every node is written once.
+// 2/3 of its spacing (K = 4 .. 6) take dense band records of up to 15 rows;
+// finer than 1/3, or with a band that would not fit (kmax = 0), a general
+// loop.  No atomics: every node is written once.
 template <int RPT>
 __device__ __forceinline__ void pt_general(const GLPar& gp, const float* vadj, int q, int p0, int n,
                                            float acc[RPT]) {
@@ -1630,6 +1631,63 @@ __device__ __forceinline__ void pt_sensor(const float* vsens, int nc, const Band
   }
 }
 
+// One sensor of a wide pair (K = 4 .. 6 corners per node, corner spacing
+// from 1/3 to 2/3 of the node spacing): every record dense, its band rows
+// interpolated along x with the column hat's K weights (wx), then node row u
+// sums them with the record's weights w[u][s] as scalar operands.  Rows past
+// the record's nrows lie outside the grid and have zero weights.
+template <int K>
+__device__ __forceinline__ void pt_wide_record(__amdgpu_buffer_rsrc_t rs, int vo, int rowb, const BandHdr& h,
+                                               const BandRec* rec, const float wx[K], float acc[kBandRows]) {
+  typedef const __attribute__((address_space(4))) BandRecW* crec;
+  constexpr int SB = pt_band_wide(K);
+  if (h.pat == kPatZero) return;
+  float v[SB][K];
+#pragma unroll
+  for (int s = 0; s < SB; ++s) {
+    if (s < h.nrows) {
+      pt_row<K>(rs, vo, h.so0 + s * rowb, v[s]);
+    } else {
+#pragma unroll
+      for (int b = 0; b < K; ++b) v[s][b] = 0.f;
+    }
+  }
+  float r[SB];
+#pragma unroll
+  for (int s = 0; s < SB; ++s) {
+    float t = wx[0] * v[s][0];
+#pragma unroll
+    for (int b = 1; b < K; ++b) t = fmaf(wx[b], v[s][b], t);
+    r[s] = t;
+  }
+  const crec br = (crec)rec;
+#pragma unroll
+  for (int u = 0; u < kBandRows; ++u) {
+    float t = 0.f;
+#pragma unroll
+    for (int s = 0; s < SB; ++s) t = fmaf(br->w[u][s], r[s], t);
+    acc[u] += t;
+  }
+}
+
+template <int K, int RPT>
+__device__ __forceinline__ void pt_sensor_wide(const float* vsens, int nc, const BandRec* rec, const BandHdr& h,
+                                               const HatEnt& hx, const HatEnt& hx2, int ngrp, float acc[RPT]) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)vsens, (short)0, nc * nc * (int)sizeof(float), 0x00020000);
+  const int vo = hx.lo * (int)sizeof(float);
+  const int rowb = nc * (int)sizeof(float);
+  float wx[K];
+#pragma unroll
+  for (int b = 0; b < K; ++b) wx[b] = b < 3 ? hx.w[b] : hx2.w[b - 3];
+  pt_wide_record<K>(rs, vo, rowb, h, rec, wx, acc);
+#pragma unroll
+  for (int j = 1; j < RPT / kBandRows; ++j) {
+    if (j >= ngrp) break;
+    pt_wide_record<K>(rs, vo, rowb, load_hdr(rec + j), rec + j, wx, acc + j * kBandRows);
+  }
+}
+
 // Tile = 4 RPT node rows x 64 node columns; wave w owns the RPT rows from
 // p0 = 4 RPT ty + RPT w (RPT / kBandRows band records).  The tile's sensor
 // list (the sensors whose footprint meets it, at most 63, built on the host,
@@ -1637,7 +1695,9 @@ __device__ __forceinline__ void pt_sensor(const float* vsens, int nc, const Band
 // readlane.  The sensor loop is software-pipelined: the column hat and
 // band-record head of the next sensor are requested, unconditionally, before
 // the current sensor's loads.
-template <int RPT>
+// WIDE: the instantiation with the wide-pair path (more registers), launched
+// only for plans that have wide pairs.
+template <int RPT, bool WIDE>
 __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD, const WfsDev* WD, const IoDev* IO,
                                             const Tile* tiles, const HatEnt* __restrict__ hats, int n_hats,
                                             const BandRec* __restrict__ bands, const PtEnt* __restrict__ ents,
@@ -1679,8 +1739,10 @@ __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD
   const __amdgpu_buffer_rsrc_t hrs =
       __builtin_amdgcn_make_buffer_rsrc((void*)hats, (short)0, n_hats * (int)sizeof(HatEnt), 0x00020000);
   const int hlane = (qc - t.tx * kPtW) * (int)sizeof(HatEnt);
+  // a wide pair's node has two hat entries
+  auto lane_off = [&](const PtEnt& e) { return (WIDE && (e.nck & 7) > 3) ? 2 * hlane : hlane; };
   auto fetch = [&](const PtEnt& e, HatEnt& hx, BandHdr& hd) {  // valid for every entry (see PtEnt)
-    const auto h = __builtin_amdgcn_raw_buffer_load_b128(hrs, hlane, e.hx * (int)sizeof(HatEnt), 0);
+    const auto h = __builtin_amdgcn_raw_buffer_load_b128(hrs, lane_off(e), e.hx * (int)sizeof(HatEnt), 0);
     hx.lo = (int)h[0];
     hx.w[0] = __uint_as_float(h[1]);
     hx.w[1] = __uint_as_float(h[2]);
@@ -1688,15 +1750,27 @@ __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD
     hd = load_hdr(bands + e.band + wrec);
   };
   auto sensor = [&](const PtEnt& cur, const HatEnt& hx, const BandHdr& hd) {
-    const int K = cur.nck & 3, nc = cur.nck >> 2;
+    const int K = cur.nck & 7, nc = cur.nck >> 3;
     const float* vs = pr.vadj + cur.v_off;
     const BandRec* rec = bands + cur.band + wrec;
-    if (K == 0)
-      pt_general<RPT>(load_glpar(pr.gl + (cur.nck >> 2)), pr.vadj, qc, p0, n, acc);
-    else if (K == 2)
+    if (K == 0) {
+      pt_general<RPT>(load_glpar(pr.gl + (cur.nck >> 3)), pr.vadj, qc, p0, n, acc);
+    } else if (K == 2) {
       pt_sensor<2, RPT>(vs, nc, rec, hd, hx, ngrp, acc);
-    else
+    } else if (!WIDE || K == 3) {
       pt_sensor<3, RPT>(vs, nc, rec, hd, hx, ngrp, acc);
+    } else if constexpr (WIDE) {
+      // the second half of the column hat (weights 3 .. 5)
+      const auto h2 = __builtin_amdgcn_raw_buffer_load_b128(hrs, 2 * hlane + (int)sizeof(HatEnt),
+                                                            cur.hx * (int)sizeof(HatEnt), 0);
+      const HatEnt hx2{0, {__uint_as_float(h2[1]), __uint_as_float(h2[2]), __uint_as_float(h2[3])}};
+      if (K == 4)
+        pt_sensor_wide<4, RPT>(vs, nc, rec, hd, hx, hx2, ngrp, acc);
+      else if (K == 5)
+        pt_sensor_wide<5, RPT>(vs, nc, rec, hd, hx, hx2, ngrp, acc);
+      else
+        pt_sensor_wide<6, RPT>(vs, nc, rec, hd, hx, hx2, ngrp, acc);
+    }
   };
   HatEnt hx, hxn;
   BandHdr hd, hdn;
@@ -2364,10 +2438,20 @@ void launch_gammaT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode)
 }
 void launch_pT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
   if (ntiles <= 0) return;
-  if (a.pt_rows == 8)
-    k_pT<8><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.n_hats, a.bands, a.pents, mode);
-  else
-    k_pT<4><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.n_hats, a.bands, a.pents, mode);
+  if (a.pt_wide) {
+    if (a.pt_rows == 8)
+      k_pT<8, true><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.n_hats, a.bands, a.pents,
+                                                  mode);
+    else
+      k_pT<4, true><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.n_hats, a.bands, a.pents,
+                                                  mode);
+  } else if (a.pt_rows == 8) {
+    k_pT<8, false><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.n_hats, a.bands, a.pents,
+                                                 mode);
+  } else {
+    k_pT<4, false><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.n_hats, a.bands, a.pents,
+                                                 mode);
+  }
 }
 void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter) {
   if (ntiles > 0) k_update<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles, iter);

@@ -120,6 +120,27 @@ def test_small_grids_and_single_node_coarse_block(gpu_lib):
     _check_frame(gpu_lib, S, ctx, np.zeros(5 * S.geom.n_coeff, np.float32), synth_slopes(S, 0))
 
 
+def _fine_sensors():
+    """Two 32 x 32 layers (0.5 m spacing) under NGS of 16, 28, 36, 44 and 52
+    subapertures over 8 m: corner spacings of 1.0, 0.57, 0.44, 0.36 and 0.31
+    node spacings, i.e. K = 2, 4, 5 and 6 corners per node (dense band
+    records of up to 15 rows, also at the grid edges) and one pair finer than
+    1/3 (general gather); off-axis, so the corners sit between nodes."""
+    from synthetic.configs import ARCSEC, _ngs
+    cfg = get_config("tiny")
+    cfg["wfs"] = [_ngs((0.0, 0.0), 16, 0.1), _ngs((20 * ARCSEC, -10 * ARCSEC), 28, 0.1),
+                  _ngs((-15 * ARCSEC, 25 * ARCSEC), 36, 0.1), _ngs((5 * ARCSEC, 30 * ARCSEC), 44, 0.1),
+                  _ngs((-25 * ARCSEC, -5 * ARCSEC), 52, 0.1)]
+    return cfg
+
+
+def test_fine_sensors_wide_bands(gpu_lib):
+    cfg = _fine_sensors()
+    S = system("fine_sensors", cfg)
+    ctx = _ops(gpu_lib, S, cfg, 8)
+    _check_frame(gpu_lib, S, ctx, np.zeros(5 * S.geom.n_coeff, np.float32), synth_slopes(S, 0))
+
+
 def test_large_nine_layers_with_elongation(gpu_lib):
     # the frame with F = I (the fitted frame of this system is covered with the fitting tests)
     cfg = get_config("large")
