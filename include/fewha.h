@@ -280,17 +280,33 @@ FEWHA_API fewha_status fewha_reconstruct_noalloc(fewha_ctx* ctx, const float* sl
 /* Solve M x = rhs (eq. fewha, wavelet domain) to a relative residual
  * ||rhs - M x||_2 / ||rhs||_2 <= rtol.  Mixed-precision iterative refinement:
  * x = 0, then sweeps of { r = rhs - M x evaluated in double precision;
- * M d = r by the Jacobi-preconditioned CG of Algorithm 1 in FP32 (run to a
+ * M d = r by the preconditioned CG of Algorithm 1 in FP32 (run to a
  * reduction of its J^{-1}-weighted residual, checked every 16 iterations);
  * x += d }, the iterate accumulated in double precision and rounded to float
- * once at the end.  rhs and x: N_c floats, device.  max_iters in [0, 2^24]
- * bounds the total CG iterations; iters_done and rel_res (host, may be NULL)
- * receive that total and the final residual ratio of the double-precision
- * iterate (the sweeps also stop when one no longer halves it).  Synchronizes
- * the context stream after every sweep and CG check.  A zero rhs returns
- * x = 0 after 0 iterations. */
+ * once at the end.  The preconditioner is Jacobi plus a coarse-level
+ * correction (fewha_set_solve_coarse).  rhs and x: N_c floats, device.
+ * max_iters in [0, 2^24] bounds the total CG iterations; iters_done and
+ * rel_res (host, may be NULL) receive that total and the final residual
+ * ratio of the double-precision iterate (the sweeps also stop when one no
+ * longer halves it).  Synchronizes the context stream after every sweep and
+ * CG check.  A zero rhs returns x = 0 after 0 iterations.  FEWHA_ESTATE on a
+ * context with augmentation (fewha_set_augmentation). */
 FEWHA_API fewha_status fewha_solve(fewha_ctx* ctx, const float* rhs, float* x, int max_iters,
                                    double rtol, int* iters_done, double* rel_res);
+
+/* Preconditioner of the converged solves (fewha_solve, fewha_solve_map and
+ * their batched forms; the frame path keeps Algorithm 1's Jacobi PCG):
+ *   z = J^{-1} r + Z E^{-1} Z^T r,   E = Z^T M Z,
+ * with Z selecting the top-left side x side block of every layer's Mallat
+ * coefficients (the coarsest levels; side halved until a problem has at
+ * most 1024 such unknowns).  side: 0 (Jacobi only) or a power of two up to
+ * 64; default 16.  The first solve after a change builds E with one
+ * application of M per coarse unknown (the instances of one context in a
+ * batch share the work) and inverts it on the host in double precision; a
+ * system whose E is not positive definite keeps Jacobi.  It allocates
+ * device memory of about 4 m^2 bytes per distinct system plus 4 N_c bytes
+ * per problem (m = coarse unknowns). */
+FEWHA_API fewha_status fewha_set_solve_coarse(fewha_ctx* ctx, int side);
 
 /* As fewha_solve for rhs = W^{-T} A^T C_hat^{-1} slopes + W^{-T} g_layers
  * (either may be NULL): the MAP solution of eq. fewha for given slopes
@@ -349,6 +365,8 @@ FEWHA_API fewha_status fewha_batch_reconstruct(fewha_batch* b, const float* cons
  * count for the batch's calls to fewha_batch_reconstruct). */
 FEWHA_API fewha_status fewha_batch_set_refresh(fewha_batch* b, int every);
 FEWHA_API fewha_status fewha_batch_set_frame_count(fewha_batch* b, long frames);
+/* The converged solves' preconditioner of a batch (as fewha_set_solve_coarse). */
+FEWHA_API fewha_status fewha_batch_set_solve_coarse(fewha_batch* b, int side);
 
 /* Batched forms of the calls above: one entry of each host array of device
  * pointers per problem (same layouts and rules).  The batched solves iterate

@@ -68,6 +68,8 @@ _SIGS = {
     "fewha_set_loop": (c_int, [_P, c_int]),
     "fewha_set_augmentation": (c_int, [_P, c_int]),
     "fewha_set_refresh": (c_int, [_P, c_int]),
+    "fewha_set_solve_coarse": (c_int, [_P, c_int]),
+    "fewha_batch_set_solve_coarse": (c_int, [_P, c_int]),
     "fewha_set_frame_count": (c_int, [_P, c_long]),
     "fewha_batch_set_refresh": (c_int, [_P, c_int]),
     "fewha_batch_set_frame_count": (c_int, [_P, c_long]),

@@ -116,6 +116,15 @@ struct Plan {
   ProbDev* dPna = nullptr;                   // in the arena, nprob_all records
   IoDev* na_io = nullptr;                    // per-call table at the start of the scratch
   size_t na_bytes = 0;                       // scratch the plan's frame needs
+  // coarse-level correction of the converged solves, set up by the first
+  // solve after a change of its side (0: Jacobi only)
+  int coarse_side = kCoarseSide;
+  bool coarse_ready = false;
+  void* coarse_mem = nullptr;                // E^{-1}, indices, zc, slots, descriptors, tiles
+  const CoarseDev* dC = nullptr;
+  const Tile* dCT = nullptr;
+  int n_coarse_tiles = 0;
+  std::vector<int> coarse_m;                 // per problem: coarse unknowns (0: not corrected)
 };
 
 #define HIP_TRY(expr)                                                          \
@@ -148,6 +157,7 @@ void destroy_plan(Plan* p) {
   if (p->t1) (void)hipEventDestroy(p->t1);
   if (p->rho_host) (void)hipHostFree(p->rho_host);
   if (p->numflag) (void)hipHostFree(p->numflag);
+  if (p->coarse_mem) (void)hipFree(p->coarse_mem);
   if (p->arena) (void)hipFree(p->arena);
   delete p;
 }
@@ -1343,11 +1353,233 @@ fewha_status read_rho(Plan& P, hipStream_t st, int grp, int count_k, std::vector
   return FEWHA_OK;
 }
 
+// ---- coarse-level correction of the converged solves ----
+
+// Coarse unknowns of problem k: the top-left s x s block of every layer's
+// coefficients (s = min(side, n_l)), the side halved until the problem has
+// at most kCoarseMax of them.
+std::vector<int> coarse_indices(const Plan& P, int k, int side) {
+  const ProbDev& pd = P.hP[k];
+  for (int s = side; s >= 1; s /= 2) {
+    std::vector<int> idx;
+    for (int l = 0; l < pd.L; ++l) {
+      const LayerDev& ly = P.hL[pd.layer0 + l];
+      const int sl = std::min(s, ly.n);
+      for (int i = 0; i < sl; ++i)
+        for (int j = 0; j < sl; ++j) idx.push_back(ly.off + i * ly.n + j);
+    }
+    if ((int)idx.size() <= kCoarseMax) return idx;
+  }
+  return {};
+}
+
+// E^{-1} in FP32 from the symmetric part of E (FP64 Cholesky L L^T, then
+// L^{-T} L^{-1}); false when E is not numerically positive definite.
+bool spd_inverse(const std::vector<float>& E, int m, std::vector<float>& out) {
+  std::vector<double> A((size_t)m * m);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) A[(size_t)i * m + j] = 0.5 * ((double)E[(size_t)i * m + j] + (double)E[(size_t)j * m + i]);
+  for (int j = 0; j < m; ++j) {
+    double d = A[(size_t)j * m + j];
+    for (int k = 0; k < j; ++k) d -= A[(size_t)j * m + k] * A[(size_t)j * m + k];
+    if (!(d > 0.0) || !std::isfinite(d)) return false;
+    d = std::sqrt(d);
+    A[(size_t)j * m + j] = d;
+#pragma omp parallel for schedule(static)
+    for (int i = j + 1; i < m; ++i) {
+      double v = A[(size_t)i * m + j];
+      for (int k = 0; k < j; ++k) v -= A[(size_t)i * m + k] * A[(size_t)j * m + k];
+      A[(size_t)i * m + j] = v / d;
+    }
+  }
+  // row c of Lt holds column c of L^{-1} (entries c .. m - 1)
+  std::vector<double> Lt((size_t)m * m, 0.0);
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int c = 0; c < m; ++c) {
+    double* x = &Lt[(size_t)c * m];
+    for (int i = c; i < m; ++i) {
+      double v = i == c ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) v -= A[(size_t)i * m + k] * x[k];
+      x[i] = v / A[(size_t)i * m + i];
+    }
+  }
+  out.assign((size_t)m * m, 0.f);
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double v = 0.0;
+      for (int k = i; k < m; ++k) v += Lt[(size_t)i * m + k] * Lt[(size_t)j * m + k];
+      out[(size_t)i * m + j] = out[(size_t)j * m + i] = (float)v;
+    }
+  return true;
+}
+
+// Builds the coarse-level correction of every problem: E = Z^T M Z column by
+// column (M applied by the plan's own kernels to unit vectors; the instances
+// of one system in a batch probe different columns in the same launch), E^{-1}
+// on the host, and the device records of the solve kernels.  A system whose
+// E is not positive definite is left uncorrected (m = 0: plain Jacobi).
+fewha_status setup_coarse(Plan& P, hipStream_t st, std::string& err) {
+  if (P.coarse_ready) return FEWHA_OK;
+  if (P.coarse_mem) {
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipFree(P.coarse_mem));
+    P.coarse_mem = nullptr;
+  }
+  P.dC = nullptr;
+  P.dCT = nullptr;
+  P.n_coarse_tiles = 0;
+  P.coarse_m.assign(P.nprob, 0);
+  if (P.coarse_side <= 0) {
+    P.coarse_ready = true;
+    return FEWHA_OK;
+  }
+  const int np = P.nprob;
+  // systems: problems built from one configured context share M
+  std::vector<int> sys(np), rank(np);
+  std::vector<int> first, count;
+  for (int k = 0; k < np; ++k) {
+    int s = -1;
+    for (size_t q = 0; q < first.size(); ++q)
+      if (P.models[first[q]] == P.models[k]) s = (int)q;
+    if (s < 0) {
+      s = (int)first.size();
+      first.push_back(k);
+      count.push_back(0);
+    }
+    sys[k] = s;
+    rank[k] = count[s]++;
+  }
+  const int ns = (int)first.size();
+  std::vector<std::vector<int>> idx(ns);
+  for (int s = 0; s < ns; ++s) idx[s] = coarse_indices(P, first[s], P.coarse_side);
+  // temporary set-up memory: E per system, a unit vector and M e_j per problem, probe records
+  size_t tb = 0;
+  auto grab = [&](size_t& at, size_t bytes) {
+    at = tb;
+    tb += (bytes + 255) & ~size_t(255);
+  };
+  std::vector<size_t> oE(ns), oIdxT(ns), oIn(np), oOut(np);
+  for (int s = 0; s < ns; ++s) {
+    grab(oE[s], sizeof(float) * idx[s].size() * idx[s].size());
+    grab(oIdxT[s], sizeof(int) * std::max<size_t>(idx[s].size(), 1));
+  }
+  for (int k = 0; k < np; ++k) {
+    grab(oIn[k], sizeof(float) * P.hP[k].n_c);
+    grab(oOut[k], sizeof(float) * P.hP[k].n_c);
+  }
+  size_t oQ;
+  grab(oQ, sizeof(CoarseProbe) * np);
+  char* tmp = nullptr;
+  HIP_TRY(hipMalloc((void**)&tmp, tb));
+  auto release = [&]() { (void)hipFree(tmp); };
+  std::vector<CoarseProbe> hq(np);
+  std::vector<IoDev> io(np);
+  int rounds = 0;
+  hipError_t e = hipSuccess;
+  for (int s = 0; s < ns && e == hipSuccess; ++s)
+    e = hipMemcpyAsync(tmp + oIdxT[s], idx[s].data(), sizeof(int) * idx[s].size(), hipMemcpyHostToDevice, st);
+  for (int k = 0; k < np && e == hipSuccess; ++k) {
+    const int s = sys[k], m = (int)idx[s].size();
+    hq[k] = CoarseProbe{(float*)(tmp + oIn[k]), (const float*)(tmp + oOut[k]), (const int*)(tmp + oIdxT[s]),
+                        (float*)(tmp + oE[s]), m, rank[k], count[s], 0};
+    rounds = std::max(rounds, cdiv(m, count[s]));
+    io[k] = IoDev{};
+    io[k].in = hq[k].in;
+    io[k].out = (float*)(tmp + oOut[k]);
+    e = hipMemsetAsync(tmp + oIn[k], 0, sizeof(float) * P.hP[k].n_c, st);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(tmp + oQ, hq.data(), sizeof(CoarseProbe) * np, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) {
+    release();
+    err = std::string("coarse set-up: ") + hipGetErrorString(e);
+    return FEWHA_EDEVICE;
+  }
+  fewha_status fs = upload_io(P, io, st, P.dIO, err);
+  if (fs != FEWHA_OK) {
+    release();
+    return fs;
+  }
+  const LaunchArgs a = args(P, st, P.dIO);
+  const CoarseProbe* dQ = (const CoarseProbe*)(tmp + oQ);
+  for (int t = 0; t < rounds; ++t) {
+    launch_coarse_probe(dQ, np, t, false, st);
+    enq_idwt(P, a, SRC_IN, OUT_PHI, 0);
+    enq_apply_M_core(P, a);
+    enq_fdwt(P, a, EPI_APPLYM, 0);
+    launch_coarse_probe(dQ, np, t, true, st);
+  }
+  e = hipGetLastError();
+  std::vector<std::vector<float>> Einv(ns);
+  for (int s = 0; s < ns && e == hipSuccess; ++s) {
+    const int m = (int)idx[s].size();
+    std::vector<float> E((size_t)m * m);
+    e = hipMemcpyAsync(E.data(), tmp + oE[s], sizeof(float) * E.size(), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess && !spd_inverse(E, m, Einv[s])) {
+      Einv[s].clear();
+      idx[s].clear();
+    }
+  }
+  release();
+  if (e != hipSuccess) {
+    err = std::string("coarse set-up: ") + hipGetErrorString(e);
+    return FEWHA_EDEVICE;
+  }
+  // persistent memory: per system E^{-1} and indices; per problem zc and slots; records, tiles
+  tb = 0;
+  std::vector<size_t> oEi(ns), oIdx(ns), oZ(np), oS(np);
+  std::vector<Tile> tiles;
+  std::vector<CoarseDev> hc(np);
+  for (int s = 0; s < ns; ++s) {
+    grab(oEi[s], sizeof(float) * std::max<size_t>(Einv[s].size(), 1));
+    grab(oIdx[s], sizeof(int) * std::max<size_t>(idx[s].size(), 1));
+  }
+  for (int k = 0; k < np; ++k) {
+    const int m = (int)idx[sys[k]].size(), nb = cdiv(m, kCoarseRows);
+    grab(oZ[k], sizeof(float) * P.hP[k].n_c);
+    grab(oS[k], sizeof(double) * kDotRing * std::max(nb, 1));
+    for (int b = 0; b < nb; ++b) tiles.push_back(Tile{k, 0, b, 0, b, 0, 0, 0});
+    P.coarse_m[k] = m;
+  }
+  size_t oC, oT;
+  grab(oC, sizeof(CoarseDev) * np);
+  grab(oT, sizeof(Tile) * std::max<size_t>(tiles.size(), 1));
+  char* mem = nullptr;
+  HIP_TRY(hipMalloc((void**)&mem, tb));
+  P.coarse_mem = mem;
+  for (int k = 0; k < np; ++k) {
+    const int s = sys[k], m = (int)idx[s].size();
+    hc[k] = CoarseDev{(const float*)(mem + oEi[s]), (const int*)(mem + oIdx[s]), (float*)(mem + oZ[k]),
+                      (double*)(mem + oS[k]), m, cdiv(m, kCoarseRows), {0, 0}};
+    HIP_TRY(hipMemsetAsync(mem + oZ[k], 0, sizeof(float) * P.hP[k].n_c, st));
+    HIP_TRY(hipMemsetAsync(mem + oS[k], 0, sizeof(double) * kDotRing * std::max(hc[k].n_slots, 1), st));
+  }
+  for (int s = 0; s < ns; ++s)
+    if (!idx[s].empty()) {
+      HIP_TRY(hipMemcpyAsync(mem + oEi[s], Einv[s].data(), sizeof(float) * Einv[s].size(), hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(mem + oIdx[s], idx[s].data(), sizeof(int) * idx[s].size(), hipMemcpyHostToDevice, st));
+    }
+  HIP_TRY(hipMemcpyAsync(mem + oC, hc.data(), sizeof(CoarseDev) * np, hipMemcpyHostToDevice, st));
+  if (!tiles.empty())
+    HIP_TRY(hipMemcpyAsync(mem + oT, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));  // the host vectors above go out of scope
+  P.dC = (const CoarseDev*)(mem + oC);
+  P.dCT = (const Tile*)(mem + oT);
+  P.n_coarse_tiles = (int)tiles.size();
+  P.coarse_ready = true;
+  return FEWHA_OK;
+}
+
 // Correction solve M d = r (r in P.rbuf) by the FP32 Jacobi-preconditioned CG
 // of Algorithm 1 from d = 0: the same kernels as a frame, one launch per
 // stage and iteration over all problems; every kSolveCheck iterations the
 // host reads rho_k and stops once sqrt(rho_k / rho_0) <= tol for every
-// problem.  d is left in the x part of P.sstate.
+// problem.  d is left in the x part of P.sstate.  With the coarse-level
+// correction set up (setup_coarse), z = J^{-1} r + Z E^{-1} Z^T r: p_k is
+// formed by k_coarse_p and rho_k includes (Z^T r)^T E^{-1} Z^T r; the
+// convergence test keeps the Jacobi-weighted residual r^T J^{-1} r.
 fewha_status pcg_core(Plan& P, hipStream_t st, int max_iters, double tol, int& iters, std::string& err) {
   std::vector<IoDev> io(P.nprob);
   for (int k = 0; k < P.nprob; ++k) {
@@ -1357,7 +1589,9 @@ fewha_status pcg_core(Plan& P, hipStream_t st, int max_iters, double tol, int& i
   fewha_status s = upload_io(P, io, st, P.dIO, err);
   if (s != FEWHA_OK) return s;
   const LaunchArgs a = args(P, st, P.dIO);
+  const CoarseDev* C = P.n_coarse_tiles > 0 ? P.dC : nullptr;
   launch_solve_init(a, T(P, P.sinit), P.sinit.n);
+  if (C) launch_coarse(a, C, P.dCT, P.n_coarse_tiles, 0);
   std::vector<double> rho0, rho;
   if ((s = read_rho(P, st, 0, 0, rho0, err)) != FEWHA_OK) return s;
   auto worst = [&](const std::vector<double>& r) {
@@ -1371,10 +1605,12 @@ fewha_status pcg_core(Plan& P, hipStream_t st, int max_iters, double tol, int& i
   while (k < max_iters && rel > tol) {
     const int kend = std::min(max_iters, k + kSolveCheck);
     for (; k < kend; ++k) {
-      enq_idwt(P, a, k == 0 ? SRC_PUPD0 : SRC_PUPD, OUT_PHI, k);
+      if (C) launch_coarse_p(a, C, T(P, P.upd), P.upd.n, k);  // p_k with the coarse correction
+      enq_idwt(P, a, C ? SRC_PJ : (k == 0 ? SRC_PUPD0 : SRC_PUPD), OUT_PHI, k);
       enq_apply_M_core(P, a);
       enq_fdwt(P, a, EPI_PCG, k);
-      launch_update(a, T(P, P.upd), P.upd.n, k);
+      launch_update(a, T(P, P.upd), P.upd.n, k, C);
+      if (C) launch_coarse(a, C, P.dCT, P.n_coarse_tiles, k + 1);
     }
     HIP_TRY(hipGetLastError());
     if ((s = read_rho(P, st, 2 * (k & (kDotRing - 1)), k, rho, err)) != FEWHA_OK) return s;
@@ -1405,8 +1641,15 @@ fewha_status run_solve(Plan& P, hipStream_t st, const std::vector<const float*>&
       err = "solve: null x (problem " + std::to_string(k) + ")";
       return FEWHA_EINVAL;
     }
+  for (int k = 0; k < P.nprob; ++k)
+    if (P.hP[k].aug_keep > 0) {
+      err = "solve: not available with augmentation (the augmented PCG keeps a frame's directions); "
+            "use a context without it";
+      return FEWHA_ESTATE;
+    }
   HIP_TRY(hipSetDevice(P.device));
   fewha_status s;
+  if ((s = setup_coarse(P, st, err)) != FEWHA_OK) return s;
   std::vector<IoDev> io(P.nprob);
   auto stage = [&](auto fill) -> fewha_status {
     for (int k = 0; k < P.nprob; ++k) {
@@ -1571,6 +1814,7 @@ struct fewha_ctx {
   bool finalized = false;
   long frames = 0;        // frames reconstructed so far (the restart schedule's clock)
   int refresh_every = 0;  // restart from the true residual every this many frames (0 = never)
+  int coarse_side = kCoarseSide;  // coarse-level correction of the converged solves (0 = Jacobi only)
   std::string err;
   HostModel m;
   Plan* plan = nullptr;
@@ -1794,6 +2038,7 @@ fewha_status fewha_finalize(fewha_ctx* c) {
     s = build_plan(c->plan, ms, c->device, c->m.tune_res > 0 ? c->m.tune_res : kResMax,
                    c->m.tune_pt_rows > 0 ? c->m.tune_pt_rows : 4, c->m.tune_split, c->err);
     if (s != FEWHA_OK) return s;
+    c->plan->coarse_side = c->coarse_side;
     if ((s = setup_noalloc(*c->plan, c->err)) != FEWHA_OK ||
         (s = setup_streamed(*c->plan, c->m.n_slopes, (int)c->m.wfs.size(), c->err)) != FEWHA_OK) {
       destroy_plan(c->plan);
@@ -1948,6 +2193,20 @@ fewha_status fewha_set_refresh(fewha_ctx* c, int every) {
   CHECK_CTX(c);
   if (every < 0) return fail(c, FEWHA_EINVAL, "set_refresh: every must be >= 0");
   c->refresh_every = every;
+  return FEWHA_OK;
+}
+
+static bool coarse_side_ok(int side) { return side == 0 || (side >= 1 && side <= 64 && (side & (side - 1)) == 0); }
+
+fewha_status fewha_set_solve_coarse(fewha_ctx* c, int side) {
+  CHECK_CTX(c);
+  if (!coarse_side_ok(side))
+    return fail(c, FEWHA_EINVAL, "set_solve_coarse: side must be 0 or a power of two up to 64");
+  c->coarse_side = side;
+  if (c->plan && c->plan->coarse_side != side) {
+    c->plan->coarse_side = side;
+    c->plan->coarse_ready = false;
+  }
   return FEWHA_OK;
 }
 
@@ -2232,6 +2491,19 @@ fewha_status fewha_batch_reconstruct(fewha_batch* b, const float* const* slopes,
 fewha_status fewha_batch_set_refresh(fewha_batch* b, int every) {
   if (!b || every < 0) return FEWHA_EINVAL;
   b->refresh_every = every;
+  return FEWHA_OK;
+}
+
+fewha_status fewha_batch_set_solve_coarse(fewha_batch* b, int side) {
+  if (!b || !b->plan) return FEWHA_EINVAL;
+  if (!coarse_side_ok(side)) {
+    b->err = "batch_set_solve_coarse: side must be 0 or a power of two up to 64";
+    return FEWHA_EINVAL;
+  }
+  if (b->plan->coarse_side != side) {
+    b->plan->coarse_side = side;
+    b->plan->coarse_ready = false;
+  }
   return FEWHA_OK;
 }
 

@@ -271,6 +271,37 @@ struct IoDev {
   const float* rg;     // FP64 residual: layer-domain term of the right-hand side W^{-T} g (or NULL)
 };
 
+// Coarse-level correction of the converged solves (fewha_solve and its
+// kin; never the frame path, which is Algorithm 1's Jacobi PCG).  Z selects
+// the top-left s x s block of every layer's Mallat layout (the coarsest
+// levels, s = 16 by default, smaller when the problem would exceed
+// kCoarseMax unknowns), E = Z^T M Z, and the preconditioner is
+//   z = J^{-1} r + Z E^{-1} Z^T r,
+// Jacobi plus an exact solve on the coarse block (additive two-level form).
+// The weakly observed low-order modes of the layers, which keep Jacobi PCG
+// slow, are resolved by the coarse solve.
+constexpr int kCoarseSide = 16;   // default coarse block side per layer
+constexpr int kCoarseMax = 1024;  // most coarse unknowns of one problem
+constexpr int kCoarseRows = 64;   // rows of E^{-1} per workgroup of k_coarse
+struct CoarseDev {
+  const float* einv;  // E^{-1}, m x m row-major (one copy per distinct system)
+  const int* idx;     // the m coarse coefficients: index in the problem's vector
+  float* zc;          // N_c floats: E^{-1} Z^T r at the coarse indices, 0 elsewhere
+  double* slots;      // kDotRing x n_slots: partials of (Z^T r)^T E^{-1} Z^T r
+  int m, n_slots;     // n_slots = workgroups of k_coarse of the problem
+  int pad_[2];
+};
+// Set-up of E: round t probes column t count + rank of the system's E with
+// a unit vector in `in` (every instance of one system in a batch probes its
+// own columns); M e_j comes back in `out`.
+struct CoarseProbe {
+  float* in;
+  const float* out;
+  const int* idx;
+  float* E;  // m x m, column j = Z^T M e_j (owned by the system's first instance)
+  int m, rank, count, pad_;
+};
+
 // Work item of a tiled launch: problem, item (layer or sensor), tile
 // row/column, and the slot of the partial it produces.  Some kinds carry
 // more, so that their descriptor loads need not wait for the problem's:

@@ -59,7 +59,14 @@ void launch_pgamma(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode)
 void launch_slopes_in(const LaunchArgs& a, const Tile* tiles, int ntiles, int add = 0);
 void launch_gammaT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode);
 void launch_pT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode);
-void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter);
+// C: the coarse-level correction of a converged solve (rho includes it), else null
+void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter, const CoarseDev* C = nullptr);
+// converged solves' coarse-level correction: y = E^{-1} Z^T r_k (tiles: problem x row block)
+void launch_coarse(const LaunchArgs& a, const CoarseDev* C, const Tile* tiles, int ntiles, int k);
+// p_k = J^{-1} r_k + Z y + beta_k p_{k-1} over the vector-update chunks
+void launch_coarse_p(const LaunchArgs& a, const CoarseDev* C, const Tile* tiles, int ntiles, int iter);
+// set-up of E = Z^T M Z, round t: unit vectors (store = false) or columns (store = true)
+void launch_coarse_probe(const CoarseProbe* Q, int nprob, int t, bool store, hipStream_t s);
 void launch_solve_init(const LaunchArgs& a, const Tile* tiles, int ntiles);
 void launch_grad_height(const LaunchArgs& a, const Tile* tiles, int ntiles, int term);
 void launch_grad_prior(const LaunchArgs& a, const GradIo* g, const Tile* tiles, int ntiles);

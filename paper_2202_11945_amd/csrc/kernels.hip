@@ -2074,7 +2074,16 @@ __global__ __launch_bounds__(256) void k_aug_store(const ProbDev* P, const IoDev
 // ------------------------------------------------------------ PCG update
 // a = rho_k / pi_k; x += a p; r -= a q; partial rho_{k+1} = r^T J^{-1} r.
 // 2048 coefficients per workgroup as float4: 2 per thread, loads first.
-__global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* IO, const Tile* tiles, int iter) {
+// rho_k with the coarse-level correction of the converged solves:
+// r^T z = r^T J^{-1} r + (Z^T r)^T E^{-1} Z^T r (the second part from k_coarse).
+__device__ __forceinline__ double coarse_rho(const CoarseDev* C, int prob, int k) {
+  if (!C) return 0.0;
+  const CoarseDev& c = C[prob];
+  return wave_sum_slots(c.slots + (long)(k & (kDotRing - 1)) * c.n_slots, c.n_slots);
+}
+
+__global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* IO, const Tile* tiles, int iter,
+                                                const CoarseDev* C) {
   __shared__ double sh[4];
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
@@ -2102,7 +2111,7 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
   }
   // alpha = rho_k / pi_k, summed by every wave itself in the same fixed order
   // (no barrier) while its loads are in flight
-  const double rho = rho_sum(pr, iter);
+  const double rho = rho_sum(pr, iter) + coarse_rho(C, t.prob, iter);
   const double pi = wave_sum_slots(dot_group(pr, pi_grp(iter)), pr.n_slots_fdwt);
   const float a = (float)((pi > 0.0) ? rho / pi : 0.0);
   // breakdown: a nonzero residual with p^T M p <= 0 (M is positive definite,
@@ -2192,6 +2201,97 @@ __global__ __launch_bounds__(256) void k_solve_init(const ProbDev* P, const IoDe
   }
   const double s = block_sum(acc, sh, blockDim.x);
   if (threadIdx.x == 0) pr.dots[(long)rho_grp(0) * pr.n_dots + t.slot] = s;
+}
+
+// Coarse-level correction, per problem and block of kCoarseRows outputs:
+// y = E^{-1} Z^T r on those outputs, stored at their coarse indices of zc,
+// and the block's partial of (Z^T r)^T y into slot (k, block); r is r_k of
+// the solve's state.  E^{-1} is symmetric, so output i sums column i, read
+// along rows: lane = output (coalesced), the 4 waves split the rows and
+// their partial sums are added in a fixed order.  Z^T r is gathered into
+// LDS by every block.
+__global__ __launch_bounds__(256) void k_coarse(const ProbDev* P, const IoDev* IO, const CoarseDev* C,
+                                                const Tile* tiles, int k) {
+  typedef const int __attribute__((address_space(1)))* gptr_i;
+  __shared__ float rc[kCoarseMax];
+  __shared__ float part[4][kCoarseRows];
+  const Tile t = my_tile(tiles);
+  const ProbDev& pr = P[t.prob];
+  const CoarseDev& c = C[t.prob];
+  const int m = c.m;
+  const gptr_f r = (gptr_f)(IO[t.prob].state + 2L * pr.n_c);
+  const gptr_i idx = (gptr_i)c.idx;
+  for (int j = threadIdx.x; j < m; j += 256) rc[j] = r[idx[j]];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = t.ty * kCoarseRows + lane;
+  const int ic = min(i, m - 1);  // lanes past the last output read a valid column
+  const int per = (m + 3) / 4, j0 = wv * per, j1 = min(j0 + per, m);
+  const gptr_f col = (gptr_f)(c.einv + ic);
+  float acc = 0.f;
+  int j = j0;
+  for (; j + 8 <= j1; j += 8) {
+    float e[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) e[u] = col[(long)(j + u) * m];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = fmaf(e[u], rc[j + u], acc);
+  }
+  for (; j < j1; ++j) acc = fmaf(col[(long)j * m], rc[j], acc);
+  part[wv][lane] = acc;
+  __syncthreads();
+  if (wv == 0) {
+    const float y = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+    double d = 0.0;
+    if (i < m) {
+      ((gptr_w)c.zc)[idx[i]] = y;
+      d = (double)rc[i] * (double)y;
+    }
+    d = wave_sum(d);
+    if (lane == 0) ((gptr_wd)c.slots)[(long)(k & (kDotRing - 1)) * c.n_slots + t.ty] = d;
+  }
+}
+
+// Search direction of the coarse-corrected solve, over the vector-update
+// chunks: p_k = J^{-1} r_k + zc + beta_k p_{k-1} (beta_0 = 0), with rho
+// including the coarse part; the inverse transform then reads p_k (SRC_PJ).
+__global__ __launch_bounds__(256) void k_coarse_p(const ProbDev* P, const IoDev* IO, const CoarseDev* C,
+                                                  const Tile* tiles, int iter) {
+  const Tile t = my_tile(tiles);
+  const ProbDev& pr = P[t.prob];
+  float beta = 0.f;
+  if (iter > 0) {
+    const double rk = rho_sum(pr, iter) + coarse_rho(C, t.prob, iter);
+    const double rkm = rho_sum(pr, iter - 1) + coarse_rho(C, t.prob, iter - 1);
+    beta = (float)(rkm != 0.0 ? rk / rkm : 0.0);
+  }
+  const int e0 = t.ty * kUpdChunk, e1 = min(e0 + kUpdChunk, pr.n_c);
+  const gptr_f r = (gptr_f)(IO[t.prob].state + 2L * pr.n_c);
+  const gptr_f jv = (gptr_f)pr.jinv;
+  const gptr_f zc = (gptr_f)C[t.prob].zc;
+  const gptr_f pold = (gptr_f)p_loc(pr, iter - 1);
+  const gptr_w pnew = (gptr_w)p_loc(pr, iter);
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
+    const float z = fmaf(r[e], jv[e], zc[e]);
+    pnew[e] = iter > 0 ? fmaf(beta, pold[e], z) : z;
+  }
+}
+
+// Set-up of E = Z^T M Z, round t: every problem sets its unit vector to the
+// column it probes in this round (and clears the previous round's).
+__global__ void k_coarse_unit(const CoarseProbe* Q, int t) {
+  const CoarseProbe& q = Q[blockIdx.x];
+  if (threadIdx.x != 0) return;
+  const int prev = (t - 1) * q.count + q.rank, col = t * q.count + q.rank;
+  if (t > 0 && prev < q.m) ((gptr_w)q.in)[q.idx[prev]] = 0.f;
+  if (col < q.m) ((gptr_w)q.in)[q.idx[col]] = 1.f;
+}
+// ... and stores Z^T M e_col as column col of its system's E.
+__global__ void k_coarse_col(const CoarseProbe* Q, int t) {
+  const CoarseProbe& q = Q[blockIdx.x];
+  const int col = t * q.count + q.rank;
+  if (col >= q.m) return;
+  for (int i = threadIdx.x; i < q.m; i += blockDim.x) ((gptr_w)q.E)[(long)i * q.m + col] = q.out[q.idx[i]];
 }
 
 // ------------------------------------------------- parameter gradients
@@ -2453,8 +2553,21 @@ void launch_pT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
                                                  mode);
   }
 }
-void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter) {
-  if (ntiles > 0) k_update<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles, iter);
+void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter, const CoarseDev* C) {
+  if (ntiles > 0) k_update<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles, iter, C);
+}
+void launch_coarse(const LaunchArgs& a, const CoarseDev* C, const Tile* tiles, int ntiles, int k) {
+  if (ntiles > 0) k_coarse<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, C, tiles, k);
+}
+void launch_coarse_p(const LaunchArgs& a, const CoarseDev* C, const Tile* tiles, int ntiles, int iter) {
+  if (ntiles > 0) k_coarse_p<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, C, tiles, iter);
+}
+void launch_coarse_probe(const CoarseProbe* Q, int nprob, int t, bool store, hipStream_t s) {
+  if (nprob <= 0) return;
+  if (store)
+    k_coarse_col<<<nprob, 256, 0, s>>>(Q, t);
+  else
+    k_coarse_unit<<<nprob, 64, 0, s>>>(Q, t);
 }
 void launch_solve_init(const LaunchArgs& a, const Tile* tiles, int ntiles) {
   if (ntiles > 0) k_solve_init<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles);

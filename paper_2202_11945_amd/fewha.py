@@ -194,6 +194,10 @@ class Context:
                                       _ptr(layers_out, self.n_coeff), _ptr(dm_out, self.n_act), int(iters)),
                self.h)
 
+    def fewha_set_solve_coarse(self, side):
+        """Coarse-level correction of the converged solves (0: Jacobi only)."""
+        _check(_abi.fewha_set_solve_coarse(self.h, int(side)), self.h)
+
     def fewha_set_refresh(self, every):
         """Restart from the true residual every `every` frames (0 = never)."""
         _check(_abi.fewha_set_refresh(self.h, int(every)), self.h)
@@ -283,6 +287,7 @@ class Context:
     reconstruct_noalloc = fewha_reconstruct_noalloc
     reconstruct_streamed = fewha_reconstruct_streamed
     set_refresh = fewha_set_refresh
+    set_solve_coarse = fewha_set_solve_coarse
     set_frame_count = fewha_set_frame_count
 
 
@@ -320,6 +325,9 @@ class Batch:
             self.h, arr(slopes, [c.n_slopes for c in self.ctxs]), arr(states, [c.n_state for c in self.ctxs]),
             arr(layers_out, [c.n_coeff for c in self.ctxs]), arr(dm_out, [c.n_act for c in self.ctxs]),
             int(iters), 1 if use_graph else 0), batch_handle=self.h)
+
+    def fewha_batch_set_solve_coarse(self, side):
+        _check(_abi.fewha_batch_set_solve_coarse(self.h, int(side)), batch_handle=self.h)
 
     def fewha_batch_set_refresh(self, every):
         _check(_abi.fewha_batch_set_refresh(self.h, int(every)), batch_handle=self.h)
@@ -395,6 +403,7 @@ class Batch:
     reconstruct = fewha_batch_reconstruct
     time_stage = fewha_batch_time_stage
     set_refresh = fewha_batch_set_refresh
+    set_solve_coarse = fewha_batch_set_solve_coarse
     set_frame_count = fewha_batch_set_frame_count
     solve = fewha_batch_solve
     solve_map = fewha_batch_solve_map

@@ -190,3 +190,16 @@ def test_loop_and_photon_arguments(lib):
     with pytest.raises(lib.FewhaError) as e:
         lib.Context(cfg, device=-1)
     assert e.value.status == -1
+
+
+def test_solve_coarse_side_is_validated(lib):
+    from ctypes import byref
+    a = lib._abi
+    h = c_void_p()
+    assert a.fewha_create(byref(h), -1) == 0
+    for side in (0, 1, 8, 16, 64):
+        assert a.fewha_set_solve_coarse(h, side) == 0
+    for side in (-1, 3, 12, 128):
+        assert a.fewha_set_solve_coarse(h, side) == -1
+    assert a.fewha_batch_set_solve_coarse(None, 16) == -1
+    a.fewha_destroy(h)
