@@ -37,7 +37,7 @@ def parse():
     p.add_argument("--batch", type=int, default=64, help="independent MAORY-like frame sequences")
     p.add_argument("--iters", type=int, default=4)
     p.add_argument("--pool", type=int, default=8, help="distinct input frames per sequence")
-    p.add_argument("--latency-frames", type=int, default=200)
+    p.add_argument("--latency-frames", type=int, default=1000)
     p.add_argument("--no-tune", action="store_true", help="default launch shapes instead of the autotuner's")
     p.add_argument("--grad-frames", type=int, default=16,
                    help="frames of the forward + implicit-backward leg (0 = skip)")
@@ -157,6 +157,48 @@ def algorithmic_bytes(cfg, n_slopes, n_corners, res=128):
     }
 
 
+def path_bytes(n_c, n_corners, n_slopes, iters):
+    """Algorithmic bytes of one whole frame (FP32, each operator of the
+    paper's factorisation reads its input once and writes its output once):
+    B_frame = B_rhs + iters (B_apply + B_vec) + B_out with
+      B_apply = 4 (6 N_c + 4 sum V + 2 sum S)   one application of M
+      B_vec   = 4 * 15 N_c                       PCG vector work of an iteration
+      B_rhs   = 4 (2 sum S + 2 sum V + 7 N_c)    right-hand side and warm restart
+      B_out   = 4 * 5 N_c                        W^{-1} and the control update
+    (sum V: corner values, sum S: active slopes; the DM-fitting CG of the
+    9-layer system is not counted)."""
+    b_apply = 4 * (6 * n_c + 4 * n_corners + 2 * n_slopes)
+    b_vec = 4 * 15 * n_c
+    b_rhs = 4 * (2 * n_slopes + 2 * n_corners + 7 * n_c)
+    return b_rhs + iters * (b_apply + b_vec) + 4 * 5 * n_c
+
+
+def path_rate(bytes_per_frame, frames_per_s, peaks):
+    """A frame rate as whole-path GB/s and its fractions of the HBM peak and
+    of the measured copy rates."""
+    gbs = bytes_per_frame * frames_per_s / 1e9
+    out = {"GBs": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS}
+    if peaks:
+        out["frac_of_measured_hbm_copy"] = gbs / peaks["hbm_copy_GBs"]
+        out["frac_of_measured_mall_copy"] = gbs / peaks["mall_copy_GBs"]
+    return out
+
+
+def launches_per_frame(cfg, res, iters):
+    """Kernel launches of one open-loop frame of one problem (plain PCG):
+    slope input, sensor adjoint, propagation adjoint and forward transform
+    for the right-hand side; per iteration the inverse transform, the
+    propagation and sensor stages, the forward transform and the update;
+    the final inverse transform.  A transform is one resident launch plus
+    one launch per level of output side above the resident side res."""
+    g = max(sum(1 for k in range(1, 16) if res < 2 ** k <= l["n"]) for l in cfg["layers"])
+    return 3 + (1 + g) + iters * (2 * (1 + g) + 4) + (1 + g)
+
+
+def corner_count(cfg):
+    return sum((w["n_subap"] + 1) ** 2 for w in cfg["wfs"])
+
+
 def measured_traffic(stage, batch, tuning):
     """Bytes per launch of a stage from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, or None when it was taken on other kernel code, another
@@ -249,7 +291,7 @@ def stage_roofline(fw, batch, ctxs, tuning, iters, peaks, reps=50):
     return stage_us, roof, stage_frac
 
 
-def config3_leg(fw, peaks, replays=100):
+def config3_leg(fw, peaks, replays=1000):
     """The batched workload of uneven sizes: 64 independent reconstructions
     (32 MAORY-like, 32 VLT-like, each with its own Cn2 weights, r0 and sigma),
     6 PCG iterations, one graph replay per step, autotuned launch shapes."""
@@ -302,6 +344,8 @@ def config3_leg(fw, peaks, replays=100):
                        "64x64), own Cn2 / r0 / sigma each, 6 PCG iterations, one graph replay per step",
            "frames_per_s": len(ctxs) / dt, "ms_per_step": dt * 1e3, "steps": replays,
            "plain_path_frames_per_s": plain, "speedup_vs_plain": len(ctxs) / dt / plain, "tuning": tune}
+    step_bytes = sum(path_bytes(c.n_coeff, corner_count(cfg), c.n_slopes, 6) for c, cfg in zip(ctxs, cfgs))
+    out["path_roofline"] = dict(path_rate(step_bytes, 1.0 / dt, peaks), bytes_per_replay=step_bytes)
     if tb is None:  # stage times need the single-stream plan: time a copy built with streams = 1
         tb = fw.Batch(ctxs, tuning=dict(tune, streams=1))
         tb.reconstruct([pool[k][0] for k in range(len(ctxs))], [s.clone() for s in states], iters=6,
@@ -318,7 +362,7 @@ def config3_leg(fw, peaks, replays=100):
     return out
 
 
-def config5_leg(fw, replays=5, B=32):
+def config5_leg(fw, peaks, replays=5, B=32):
     """The large workload: 9 layers (0-20 km, 256 x 256 above 10 km), 6 LGS
     80x80 with 2x2 spot-elongation noise blocks, 20 PCG iterations, then the
     fitting CG onto 3 DMs over 9 directions; 32 independent frame sequences
@@ -344,28 +388,30 @@ def config5_leg(fw, replays=5, B=32):
         batch.reconstruct([slopes[(i + k) % 2] for k in range(B)], states, iters=20, use_graph=True)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / replays
+    fb = path_bytes(ctx.n_coeff, corner_count(cfg), ctx.n_slopes, 20)
     batch.close()
     ctx.close()
     return {"workload": "9 layers (0-20 km; 128x128 up to 10 km, 256x256 above), 6 LGS 80x80 with 2x2 "
                         "elongation noise blocks, 20 PCG iterations, fitting CG (10 iterations) onto 3 DMs over "
                         "9 directions; %d sequences per graph replay" % B,
-            "frames_per_s": B / dt, "ms_per_step": dt * 1e3, "steps": replays, "context_setup_s": setup_s}
+            "frames_per_s": B / dt, "ms_per_step": dt * 1e3, "steps": replays, "context_setup_s": setup_s,
+            "path_roofline": dict(path_rate(fb, B / dt, peaks), bytes_per_frame=fb,
+                                  note="the fitting CG's bytes are not counted")}
 
 
 def latency(run, nf):
     """p50 / p99 of per-call device time (HIP events around each call on the
-    current stream, synchronized after each) and the back-to-back rate."""
+    current stream, synchronized after each) over frames nf/10 .. nf - 1 of
+    a sequence of nf frames (the first tenth is the warm-up: frames 100..999
+    of 1000 by default), and the back-to-back rate."""
     import torch
-    for i in range(10):
-        run(i)
-    torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nf)]
     for i in range(nf):
         ev[i][0].record()
         run(i)
         ev[i][1].record()
         torch.cuda.synchronize()
-    per_frame = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)
+    per_frame = sorted(a.elapsed_time(b) * 1e3 for a, b in ev[nf // 10:])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(nf):
@@ -375,7 +421,7 @@ def latency(run, nf):
             "back_to_back_us": (time.perf_counter() - t0) / nf * 1e6}
 
 
-def paper_maory_leg(fw, nf=100):
+def paper_maory_leg(fw, nf=1000):
     """The paper's own MAORY system (37 m, 11 % obstruction, 6 LGS 74x74 + 3
     NGS, layers 128/64/64 at 0/4/12.7 km): single-frame latency of the graph
     path (autotuned) at 2 and 4 PCG iterations, beside the paper's 1.48 ms."""
@@ -396,9 +442,12 @@ def paper_maory_leg(fw, nf=100):
         b = fw.Batch([ctx], tuning=tune)
         st = torch.zeros(ctx.n_state, device="cuda")
         lay = torch.empty(ctx.n_coeff, device="cuda")
-        out["iters_%d" % iters] = dict(latency(lambda i: b.reconstruct([slopes[pool_index(i, 4)]], [st], [lay],
-                                                                       iters=iters, use_graph=True), nf),
-                                       tuning={k: tune[k] for k in ("dwt_resident", "pt_rows")})
+        lat = latency(lambda i: b.reconstruct([slopes[pool_index(i, 4)]], [st], [lay], iters=iters,
+                                              use_graph=True), nf)
+        fb = path_bytes(ctx.n_coeff, corner_count(cfg), ctx.n_slopes, iters)
+        out["iters_%d" % iters] = dict(lat, tuning={k: tune[k] for k in ("dwt_resident", "pt_rows")},
+                                       speedup_vs_paper=1480.0 / lat["p50_us"] if iters == 2 else None,
+                                       bytes_per_frame=fb, path_GBs=fb / lat["p50_us"] / 1e3)
         b.close()
     ctx.close()
     return out
@@ -650,6 +699,7 @@ def main():
     dom = roof["kernel"]
     roof["traffic"] = measured_traffic(dom, nb_prob, tune_t)
 
+    frame_b = path_bytes(c0.n_coeff, corner_count(cfg), c0.n_slopes, args.iters)
     extra = {}
     if not args.no_extra:
         pool_host = [pool[0][f].cpu().pin_memory() for f in range(args.pool)]
@@ -657,7 +707,7 @@ def main():
                           ("streamed_slopes_us", lambda: streamed_leg(fw, c0, pool_host, args.iters)),
                           ("paper_maory", lambda: paper_maory_leg(fw)),
                           ("batched_uneven_64", lambda: config3_leg(fw, peaks)),
-                          ("large_9_layers", lambda: config5_leg(fw))):
+                          ("large_9_layers", lambda: config5_leg(fw, peaks))):
             t_leg = time.time()
             extra[name] = leg()
             print("[bench] %s leg: %.1f s" % (name, time.time() - t_leg), file=sys.stderr, flush=True)
@@ -688,6 +738,13 @@ def main():
                                "%d independent sequences per step, %s, graph replays"
                                % (args.iters, B, split["timed"]),
                    "batch": B, "iters": args.iters, "n_coeff": c0.n_coeff, "n_slopes": c0.n_slopes},
+        "path_roofline": {
+            "accounting": "B_frame = B_rhs + iters (B_apply + B_vec) + B_out, every operator's input read once "
+                          "and output written once (FP32)",
+            "bytes_per_frame": frame_b,
+            "batched": path_rate(frame_b, value, peaks),
+            "single_frame_graph_p50": path_rate(frame_b, 1e6 / lat_graph["p50_us"], peaks),
+            "launches_per_frame_single": launches_per_frame(cfg, tune_1["dwt_resident"], args.iters)},
         "latency_graph_us": lat_graph,
         "latency_plain_us": lat_plain,
         "batched_nograph_frames_per_s": B / dt_nograph,

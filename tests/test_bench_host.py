@@ -77,3 +77,20 @@ def test_traffic_only_for_matching_sources_and_shapes():
     # other launch shapes or batch sizes never borrow it
     assert bench.measured_traffic("P_T", 32, {"dwt_resident": 64, "pt_rows": 8}) is None
     assert bench.measured_traffic("P_T", 48, tune) is None
+
+
+def test_whole_path_bytes_and_launch_count():
+    # B_frame = B_rhs + iters (B_apply + B_vec) + B_out for the MAORY-like
+    # frame at 4 iterations, the 9-layer frame at 20 and the paper's MAORY at
+    # 2 (42.7 MB, 616 MB, 7.8 MB), from the operator counts N_c, sum V, sum S
+    assert bench.path_bytes(98304, 39393, 53736, 4) == 4 * (2 * 53736 + 2 * 39393 + 7 * 98304) + 4 * (
+        4 * (6 * 98304 + 4 * 39393 + 2 * 53736) + 4 * 15 * 98304) + 4 * 5 * 98304
+    assert round(bench.path_bytes(98304, 39393, 53736, 4) / 1e6, 1) == 42.7
+    assert round(bench.path_bytes(344064, 39366, 53712, 20) / 1e6) == 616
+    assert round(bench.path_bytes(24576, 33777, 46056, 2) / 1e6, 1) == 7.8
+    cfg = get_config("maory_like")
+    assert bench.corner_count(cfg) == 39393
+    # one frame of one MAORY-like problem: 39 launches with resident side 128
+    # (the count the single-frame kernel trace shows), 49 with 64
+    assert bench.launches_per_frame(cfg, 128, 4) == 39
+    assert bench.launches_per_frame(cfg, 64, 4) == 49
