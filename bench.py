@@ -208,7 +208,8 @@ def measured_traffic(stage, batch, tuning):
     for f in ("kernels.hip", "kernels.h", "fewha_internal.h", "api.cpp"):
         h.update(open(os.path.join(ROOT, "paper_2202_11945_amd", "csrc", f), "rb").read())
     sha = h.hexdigest()[:16]
-    tune = "%d/%d/%d" % (tuning["dwt_resident"], tuning["pt_rows"], tuning.get("res_split", 0))
+    tune = "%d/%d/%d/%d" % (tuning["dwt_resident"], tuning["pt_rows"], tuning.get("res_split", 0),
+                            tuning.get("pt_split", 0))
     prof = os.path.join(ROOT, "profiles", "stages_maory_like_b%d_bytes.md" % batch)
     if not os.path.exists(prof):
         return None
@@ -445,10 +446,22 @@ def paper_maory_leg(fw, nf=1000):
         lat = latency(lambda i: b.reconstruct([slopes[pool_index(i, 4)]], [st], [lay], iters=iters,
                                               use_graph=True), nf)
         fb = path_bytes(ctx.n_coeff, corner_count(cfg), ctx.n_slopes, iters)
-        out["iters_%d" % iters] = dict(lat, tuning={k: tune[k] for k in ("dwt_resident", "pt_rows")},
+        out["iters_%d" % iters] = dict(lat, tuning={k: tune[k] for k in ("dwt_resident", "pt_rows", "pt_split")},
                                        speedup_vs_paper=1480.0 / lat["p50_us"] if iters == 2 else None,
                                        bytes_per_frame=fb, path_GBs=fb / lat["p50_us"] / 1e3)
         b.close()
+    # the paper's own setting: 2 iterations of the augmented PCG (the
+    # previous frame's 2 directions), the like-for-like comparison
+    ca = fw.Context(dict(cfg, augment=2), device=0)
+    tune = autotune.tune([ca], 2)
+    b = fw.Batch([ca], tuning=tune)
+    st = torch.zeros(ca.n_state, device="cuda")
+    lay = torch.empty(ca.n_coeff, device="cuda")
+    lat = latency(lambda i: b.reconstruct([slopes[pool_index(i, 4)]], [st], [lay], iters=2, use_graph=True), nf)
+    out["iters_2_augmented"] = dict(lat, tuning={k: tune[k] for k in ("dwt_resident", "pt_rows", "pt_split")},
+                                    speedup_vs_paper=1480.0 / lat["p50_us"])
+    b.close()
+    ca.close()
     ctx.close()
     return out
 
@@ -485,29 +498,30 @@ def augmentation_leg(fw, cfg, pool_dev, n_frames=16, iters=2, keep=2, nf=100):
     import torch
     ctx_p = fw.Context(dict(cfg, iters=iters), device=0)
     ctx_a = fw.Context(dict(cfg, iters=iters, augment=keep), device=0)
-    st_p = torch.zeros(ctx_p.n_state, device="cuda")
-    st_a = torch.zeros(ctx_a.n_state, device="cuda")
+    runs = {"plain": (ctx_p, iters), "augmented": (ctx_a, iters), "plain_%d_iterations" % (2 * iters): (ctx_p, 2 * iters)}
+    st = {name: torch.zeros(c.n_state, device="cuda") for name, (c, _) in runs.items()}
     n = ctx_p.n_coeff
-    err = {"plain": [], "augmented": []}
+    err = {name: [] for name in runs}
     for k in range(n_frames):
         s = pool_dev[pool_index(k, len(pool_dev))]
-        ctx_p.reconstruct(s, st_p, iters=iters)
-        ctx_a.reconstruct(s, st_a, iters=iters)
+        for name, (c, it) in runs.items():
+            c.reconstruct(s, st[name], iters=it)
         cstar, _, _ = ctx_p.solve_map(slopes=s, rtol=1e-7, max_iters=20000)
         mstar = ctx_p.apply_M(cstar)
         norm = float(torch.dot(cstar.double(), mstar.double()))
-        for name, st in (("plain", st_p), ("augmented", st_a)):
-            e = st[:n] - cstar
+        for name in runs:
+            e = st[name][:n] - cstar
             err[name].append((float(torch.dot(e.double(), ctx_p.apply_M(e).double())) / norm) ** 0.5)
     out = {"workload": "MAORY-like, one frozen-flow sequence of %d frames, %d warm PCG iterations per frame; "
-                       "augmented: the previous frame's %d directions" % (n_frames, iters, keep),
+                       "augmented: the previous frame's %d directions; plain PCG also at %d iterations"
+                       % (n_frames, iters, keep, 2 * iters),
            "m_norm_error_plain": err["plain"], "m_norm_error_augmented": err["augmented"],
            "mean_error_frames_4_on": {k: sum(v[4:]) / len(v[4:]) for k, v in err.items()}}
-    for name, c in (("plain", ctx_p), ("augmented", ctx_a)):
+    for name, (c, it) in runs.items():
         b = fw.Batch([c])
-        st = torch.zeros(c.n_state, device="cuda")
-        out["latency_us_" + name] = latency(lambda i: b.reconstruct([pool_dev[pool_index(i, len(pool_dev))]], [st],
-                                                                    iters=iters, use_graph=True), nf)
+        s1 = torch.zeros(c.n_state, device="cuda")
+        out["latency_us_" + name] = latency(lambda i: b.reconstruct([pool_dev[pool_index(i, len(pool_dev))]], [s1],
+                                                                    iters=it, use_graph=True), nf)
         b.close()
     ctx_p.close()
     ctx_a.close()

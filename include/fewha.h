@@ -429,13 +429,19 @@ FEWHA_API void fewha_batch_destroy(fewha_batch* b);
  * output, so that a launch spreads over more compute units; 4 needs every
  * layer's resident side to be at least 16 with at least one resident level
  * (else FEWHA_EINVAL when the plan is built).
+ * pt_split: 1 = the propagation adjoint's tiles are 4 node rows x 64
+ * columns and each tile's sensor list is split over its 4 waves (sensor i
+ * to wave i mod 4, the partial sums added in a fixed order), a quarter of
+ * the serial chain of sensors per wave; for launches with few tiles, such
+ * as one problem's frame.  Needs pt_rows 0 or 4.  0 = default (off).
  * reserved: zero. */
 typedef struct {
   int dwt_resident;
   int pt_rows;
   int streams;
   int res_split;
-  int reserved[4];
+  int pt_split;
+  int reserved[3];
 } fewha_tuning;
 
 /* Tuning of a context's own plan; before fewha_finalize. */

@@ -1,6 +1,6 @@
 """Autotuner of a plan's launch shapes.
 
-Four tunables:
+Five tunables:
 
 * the resident transform side R (32, 64 or 128): the resident DWT kernels
   keep every level up to R x R in one workgroup's LDS, and the levels above R
@@ -9,9 +9,12 @@ Four tunables:
   levels over many more workgroups at the cost of one launch per extra level.
 * the node rows per thread of the propagation adjoint (4 or 8): more rows
   put more independent loads in flight per thread, at more registers.
-* for the best of those, the resident inverse levels in one workgroup per
-  layer (the default) or in four (each synthesizing the lower levels itself
-  and one quadrant of the top level);
+* for the best of those, the propagation adjoint's sensor lists split over
+  the waves of 4-row tiles (pt_split), which shortens each wave's serial
+  chain of sensors where a launch has few tiles;
+* then the resident inverse levels in one workgroup per layer (the default)
+  or in four (each synthesizing the lower levels itself and one quadrant of
+  the top level);
 * then the number of streams a batch's frame runs on
   (1 or 2 parts of the problem list, each on its own stream, so that the
   stages of one part overlap those of the other).
@@ -127,7 +130,8 @@ def time_plan(ctxs, iters, tuning, steps=10, warmup=3):
 
 def tune(ctxs, iters, steps=10, use_cache=True):
     """Best launch shapes for a batch of these contexts; returns
-    {"dwt_resident": R, "pt_rows": r, "streams": s, "us": {"R/r": us per step},
+    {"dwt_resident": R, "pt_rows": r, "pt_split": 0 or 1, "res_split": 0 or 4,
+     "streams": s, "us": {"R/r": us per step}, "pt_split_us", "split_us",
      "streams_us": {"s": us per step}, "cached": bool}."""
     key = signature(ctxs, iters)
     db = _load() if use_cache else {}
@@ -143,10 +147,16 @@ def tune(ctxs, iters, steps=10, use_cache=True):
     default = (max(admissible(ctxs)), PT_ROWS[0])
     if us[best] > (1.0 - MARGIN) * us[default]:
         best = default
-    shape = {"dwt_resident": best[0], "pt_rows": best[1]}
+    shape = {"dwt_resident": best[0], "pt_rows": best[1], "pt_split": 0}
+    # the propagation adjoint's sensor lists split over the waves (4 rows
+    # per thread) against the best unsplit shape
+    pts_us = {0: us[best], 1: time_plan(ctxs, iters, {"dwt_resident": best[0], "pt_rows": 4, "pt_split": 1},
+                                        steps=steps)}
+    if pts_us[1] <= (1.0 - MARGIN) * pts_us[0]:
+        shape = {"dwt_resident": best[0], "pt_rows": 4, "pt_split": 1}
     # then the resident inverse levels in four workgroups per layer against
     # the default one
-    split_us = {0: us[best]}
+    split_us = {0: min(pts_us[shape["pt_split"]], us[best])}
     if split_allowed(ctxs, best[0]):
         split_us[4] = time_plan(ctxs, iters, dict(shape, res_split=4), steps=steps)
     split = min(split_us, key=split_us.get)
@@ -159,8 +169,10 @@ def tune(ctxs, iters, steps=10, use_cache=True):
     streams = min(sus, key=sus.get)
     if sus[streams] > (1.0 - MARGIN) * sus[1]:
         streams = 1
-    rec = {"dwt_resident": best[0], "pt_rows": best[1], "res_split": split, "streams": streams,
+    rec = {"dwt_resident": shape["dwt_resident"], "pt_rows": shape["pt_rows"], "pt_split": shape["pt_split"],
+           "res_split": split, "streams": streams,
            "us": {"%d/%d" % k: round(t, 3) for k, t in us.items()},
+           "pt_split_us": {"%d" % k: round(t, 3) for k, t in pts_us.items()},
            "split_us": {"%d" % k: round(t, 3) for k, t in split_us.items()},
            "streams_us": {"%d" % k: round(t, 3) for k, t in sus.items()}}
     if use_cache:

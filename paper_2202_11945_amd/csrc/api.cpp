@@ -49,6 +49,7 @@ struct Plan {
   int res_max = kResMax;  // resident transform side (tuning)
   int pt_rows = 4;        // node rows per thread of the propagation adjoint (tuning)
   bool pt_wide = false;   // some (sensor, layer) pair has K > 3 corners per node (wide band records)
+  bool pt_split = false;  // propagation-adjoint tiles of one band record, sensors split over the waves
   std::vector<const HostModel*> models;
   void* arena = nullptr;
   size_t arena_bytes = 0;
@@ -352,7 +353,7 @@ struct PtLists {
   // tile (ty, tx) of a layer with n node rows and columns, pair parameters
   // gl[g * L + item] for the sensors g in `use`: returns {offset, count}
   std::pair<int, int> add(const std::vector<GLPar>& gl, int L, int item, const std::vector<int>& use, int n,
-                          int ty, int tx, int pt_rows) {
+                          int ty, int tx, int recs_per_tile) {
     std::vector<int> key;
     if (use.size() > 63) return {-1, 0};  // a wave reads its tile's list (and the pad) from 64 lanes
     for (int g : use) {
@@ -361,7 +362,7 @@ struct PtLists {
       if (gp.kmax > 0) {
         const int per = hat_per_node(gp.kmax);
         e.hx = gp.hat_off + per * (n + tx * kPtW);
-        e.band = gp.band_off + ty * pt_rows;  // kBandRows rows per record, 4 pt_rows rows per tile
+        e.band = gp.band_off + ty * recs_per_tile;  // kBandRows rows per record
       } else {
         e.nck = (g * L + item) << 3;
       }
@@ -389,13 +390,21 @@ struct Carver {
 };
 
 fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models, int device, int res,
-                        int pt_rows, int split, std::string& err) {
+                        int pt_rows, int split, int pt_split, std::string& err) {
   if (res != 32 && res != 64 && res != 128) {
     err = "tuning: the resident transform side must be 32, 64 or 128";
     return FEWHA_EINVAL;
   }
   if (pt_rows != 4 && pt_rows != 8) {
     err = "tuning: the propagation adjoint takes 4 or 8 node rows per thread";
+    return FEWHA_EINVAL;
+  }
+  if (pt_split != 0 && pt_split != 1) {
+    err = "tuning: pt_split must be 0 or 1";
+    return FEWHA_EINVAL;
+  }
+  if (pt_split && pt_rows != 4) {
+    err = "tuning: split propagation-adjoint tiles take 4 node rows per thread";
     return FEWHA_EINVAL;
   }
   // quarters need at least one resident level of output side >= 16 on every layer
@@ -409,7 +418,9 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     err = "tuning: four workgroups per layer need every layer's resident side >= 16 and >= 2 (n >> levels)";
     return FEWHA_EINVAL;
   }
-  const int kPtH = 4 * pt_rows;  // node rows of a propagation-adjoint tile
+  // node rows of a propagation-adjoint tile, and its band records per wave
+  const int kPtH = pt_split ? kBandRows : 4 * pt_rows;
+  const int pt_recs = pt_split ? 1 : pt_rows;
   for (const HostModel* m : models)
     for (const LayerHost& lh : m->layers)
       if ((lh.d.n >> lh.d.levels) > res) {
@@ -425,6 +436,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   P.device = device;
   P.res_max = res;
   P.pt_rows = pt_rows;
+  P.pt_split = pt_split != 0;
   P.idwt_split = split == 4;
   P.nprob = (int)models.size();
   P.models = models;
@@ -696,7 +708,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
           for (int g = 0; g < G; ++g)
             if (pair_meets_tile(glp[k][(size_t)g * L + l], hats, n, ty * kPtH, kPtH, tx * kPtW, kPtW))
               use.push_back(g);
-          const auto li = ptl.add(glp[k], L, l, use, n, ty, tx, pt_rows);
+          const auto li = ptl.add(glp[k], L, l, use, n, ty, tx, pt_recs);
           if (li.first < 0) {
             err = "more than 63 sensors meet one propagation-adjoint tile";
             return FEWHA_EINVAL;
@@ -860,7 +872,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
           for (int d = 0; d < K; ++d)
             if (pair_meets_tile(fl.glp[(size_t)d * nd + q], hats, na, ty * kPtH, kPtH, tx * kPtW, kPtW))
               use.push_back(d);
-          const auto li = ptl.add(fl.glp, nd, q, use, na, ty, tx, pt_rows);
+          const auto li = ptl.add(fl.glp, nd, q, use, na, ty, tx, pt_recs);
           if (li.first < 0) {
             err = "more than 63 fitting directions";
             return FEWHA_EINVAL;
@@ -1251,6 +1263,7 @@ LaunchArgs args(const Plan& P, hipStream_t s, const IoDev* io) {
   a.res_max = P.res_max;
   a.pt_rows = P.pt_rows;
   a.pt_wide = P.pt_wide ? 1 : 0;
+  a.pt_split = P.pt_split ? 1 : 0;
   a.hats = P.dHat;
   a.n_hats = P.nHat;
   a.bands = P.dBand;
@@ -2010,8 +2023,11 @@ fewha_status fewha_set_tuning(fewha_ctx* c, const fewha_tuning* t) {
   CHECK_CTX(c);
   if (c->finalized) return fail(c, FEWHA_ESTATE, "set_tuning after finalize");
   if (!t) return fail(c, FEWHA_EINVAL, "set_tuning: null tuning");
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 3; ++i)
     if (t->reserved[i]) return fail(c, FEWHA_EINVAL, "set_tuning: reserved fields must be zero");
+  if (t->pt_split != 0 && t->pt_split != 1) return fail(c, FEWHA_EINVAL, "set_tuning: pt_split must be 0 or 1");
+  if (t->pt_split && t->pt_rows == 8)
+    return fail(c, FEWHA_EINVAL, "set_tuning: pt_split needs pt_rows 0 or 4");
   if (t->res_split != 0 && t->res_split != 1 && t->res_split != 4)
     return fail(c, FEWHA_EINVAL, "set_tuning: res_split must be 0, 1 or 4");
   if (t->streams != 0 && t->streams != 1)
@@ -2023,6 +2039,7 @@ fewha_status fewha_set_tuning(fewha_ctx* c, const fewha_tuning* t) {
   c->m.tune_res = t->dwt_resident;
   c->m.tune_pt_rows = t->pt_rows;
   c->m.tune_split = t->res_split;
+  c->m.tune_pt_split = t->pt_split;
   return FEWHA_OK;
 }
 
@@ -2036,7 +2053,7 @@ fewha_status fewha_finalize(fewha_ctx* c) {
   if (c->device >= 0) {
     std::vector<const HostModel*> ms{&c->m};
     s = build_plan(c->plan, ms, c->device, c->m.tune_res > 0 ? c->m.tune_res : kResMax,
-                   c->m.tune_pt_rows > 0 ? c->m.tune_pt_rows : 4, c->m.tune_split, c->err);
+                   c->m.tune_pt_rows > 0 ? c->m.tune_pt_rows : 4, c->m.tune_split, c->m.tune_pt_split, c->err);
     if (s != FEWHA_OK) return s;
     c->plan->coarse_side = c->coarse_side;
     if ((s = setup_noalloc(*c->plan, c->err)) != FEWHA_OK ||
@@ -2358,8 +2375,8 @@ fewha_status fewha_batch_create(fewha_batch** out, fewha_ctx* const* ctxs, int n
 fewha_status fewha_batch_create_tuned(fewha_batch** out, fewha_ctx* const* ctxs, int n, const fewha_tuning* t) {
   if (!out || !ctxs || n < 1) return FEWHA_EINVAL;
   if (t && (t->dwt_resident < 0 || t->pt_rows < 0 || t->streams < 0 || t->streams > 4 || t->streams > n ||
-            (t->res_split != 0 && t->res_split != 1 && t->res_split != 4) || t->reserved[0] || t->reserved[1] ||
-            t->reserved[2] || t->reserved[3]))
+            (t->res_split != 0 && t->res_split != 1 && t->res_split != 4) || (t->pt_split != 0 && t->pt_split != 1) ||
+            (t->pt_split && t->pt_rows == 8) || t->reserved[0] || t->reserved[1] || t->reserved[2]))
     return FEWHA_EINVAL;
   *out = nullptr;
   int dev = -1;
@@ -2376,7 +2393,8 @@ fewha_status fewha_batch_create_tuned(fewha_batch** out, fewha_ctx* const* ctxs,
   const int res = (t && t->dwt_resident > 0) ? t->dwt_resident : kResMax;
   const int rows = (t && t->pt_rows > 0) ? t->pt_rows : 4;
   const int split = t ? t->res_split : 0;
-  fewha_status s = build_plan(b->plan, ms, dev, res, rows, split, b->err);
+  const int pt_split = t ? t->pt_split : 0;
+  fewha_status s = build_plan(b->plan, ms, dev, res, rows, split, pt_split, b->err);
   if (s != FEWHA_OK) {
     delete b;
     return s;
@@ -2398,7 +2416,7 @@ fewha_status fewha_batch_create_tuned(fewha_batch** out, fewha_ctx* const* ctxs,
       const int k0 = (int)((long)n * q / parts), k1 = (int)((long)n * (q + 1) / parts);
       b->part_first.push_back(k0);
       std::vector<const HostModel*> mq(ms.begin() + k0, ms.begin() + k1);
-      if ((s = build_plan(b->parts[q], mq, dev, res, rows, split, b->err)) != FEWHA_OK) return undo(s);
+      if ((s = build_plan(b->parts[q], mq, dev, res, rows, split, pt_split, b->err)) != FEWHA_OK) return undo(s);
       if (hipStreamCreateWithFlags(&b->part_stream[q], hipStreamNonBlocking) != hipSuccess ||
           hipEventCreateWithFlags(&b->part_done[q], hipEventDisableTiming) != hipSuccess)
         return undo(FEWHA_EDEVICE);

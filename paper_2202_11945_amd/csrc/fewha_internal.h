@@ -396,7 +396,8 @@ struct HostModel {
   FitHost fit;
   int tune_res = 0;  // resident transform side of the context's own plan (0 = default)
   int tune_pt_rows = 0;  // node rows per thread of the propagation adjoint (0 = default)
-  int tune_split = 0;    // resident inverse levels: 0 = quarters where possible, 1 = one workgroup per layer, 4 = quarters
+  int tune_split = 0;    // resident inverse levels: 0 or 1 = one workgroup per layer, 4 = quarters
+  int tune_pt_split = 0; // 1: propagation-adjoint tiles of one band record, sensors split over the waves
   long n_act() const { return fit.on ? fit.n_act : n_c; }
   // [c | b | r | a_prev | a], then with augmentation the previous directions,
   // their images and a count (4 floats, keeping 16-byte alignment)

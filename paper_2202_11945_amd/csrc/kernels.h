@@ -44,6 +44,7 @@ struct LaunchArgs {
   const PtEnt* pents;     // sensor lists of the propagation-adjoint tiles (plan-wide)
   int pt_rows;         // node rows per thread of the propagation adjoint (4 or 8)
   int pt_wide;         // 1: some pair has K > 3 corners per node (the kernel with wide records)
+  int pt_split;        // 1: tiles of one band record, the sensor list split over the waves
 };
 
 void launch_idwt_res(const LaunchArgs& a, const Tile* tiles, int ntiles, int src_mode, int out_mode, int iter);

@@ -1696,13 +1696,18 @@ __device__ __forceinline__ void pt_sensor_wide(const float* vsens, int nc, const
 // band-record head of the next sensor are requested, unconditionally, before
 // the current sensor's loads.
 // WIDE: the instantiation with the wide-pair path (more registers), launched
-// only for plans that have wide pairs.
-template <int RPT, bool WIDE>
+// only for plans that have wide pairs.  SPLIT (RPT = kBandRows): a tile is one
+// band record's kBandRows node rows x 64 columns, and its sensor list is
+// split over the 4 waves (sensor i to wave i mod 4), whose sums are added in
+// LDS in wave order: a quarter of the serial sensor chain per wave, for
+// launches with few tiles (single frames).
+template <int RPT, bool WIDE, bool SPLIT>
 __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD, const WfsDev* WD, const IoDev* IO,
                                             const Tile* tiles, const HatEnt* __restrict__ hats, int n_hats,
                                             const BandRec* __restrict__ bands, const PtEnt* __restrict__ ents,
                                             int mode) {
   static_assert(RPT % kBandRows == 0, "whole band records per wave");
+  static_assert(!SPLIT || RPT == kBandRows, "split tiles are one band record");
   typedef const int __attribute__((address_space(1)))* gptr_i;
   const Tile t = my_tile(tiles);
   const ProbDev& pr = P[t.prob];
@@ -1724,13 +1729,13 @@ __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD
                  __builtin_amdgcn_readlane(m2, i), __builtin_amdgcn_readlane(m3, i)};
   };
   const int q = t.tx * kPtW + lane;
-  const int p0 = t.ty * 4 * RPT + wv * RPT;
-  if (p0 >= n) return;  // wave-uniform (no barriers in this kernel)
+  const int p0 = SPLIT ? t.ty * kBandRows : t.ty * 4 * RPT + wv * RPT;
+  if (p0 >= n) return;  // wave-uniform (SPLIT: the tile's rows, uniform over the workgroup)
   // lanes past the layer's last column run the sensor loop on that column
   // (every lane stays active for the readlane reads of the list) and store
   // nothing
   const int qc = min(q, n - 1);
-  const int wrec = wv * (RPT / kBandRows);  // this wave's first record past the tile's
+  const int wrec = SPLIT ? 0 : wv * (RPT / kBandRows);  // this wave's first record past the tile's
   const int ngrp = min(RPT / kBandRows, (n - p0 + kBandRows - 1) / kBandRows);  // records inside the layer
   float acc[RPT];
 #pragma unroll
@@ -1774,16 +1779,26 @@ __global__ __launch_bounds__(256) void k_pT(const ProbDev* P, const LayerDev* LD
   };
   HatEnt hx, hxn;
   BandHdr hd, hdn;
-  fetch(ent(0), hx, hd);
-  for (int i = 0; i < ne; ++i) {
-    fetch(ent(i + 1), hxn, hdn);  // issued first: the waits for this sensor's loads cover it
+  constexpr int step = SPLIT ? 4 : 1;
+  const int i0 = SPLIT ? wv : 0;
+  fetch(ent(min(i0, ne)), hx, hd);
+  for (int i = i0; i < ne; i += step) {
+    fetch(ent(min(i + step, ne)), hxn, hdn);  // issued first: the waits for this sensor's loads cover it
     sensor(ent(i), hx, hd);
     hx = hxn;
     hd = hdn;
   }
   const IoDev& io = IO[t.prob];
   const gptr_w dst = (gptr_w)((mode == PT_USER) ? io.out : pr.phiadj);
-  if (q < n) {
+  if constexpr (SPLIT) {
+    __shared__ float red[4][kBandRows][64];
+#pragma unroll
+    for (int u = 0; u < kBandRows; ++u) red[wv][u][lane] = acc[u];
+    __syncthreads();
+    const int p = p0 + wv;  // wave w stores node row p0 + w
+    if (q < n && p < n)
+      dst[loff + p * n + q] = ((red[0][wv][lane] + red[1][wv][lane]) + red[2][wv][lane]) + red[3][wv][lane];
+  } else if (q < n) {
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
       const int p = p0 + u;
@@ -2538,20 +2553,25 @@ void launch_gammaT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode)
 }
 void launch_pT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
   if (ntiles <= 0) return;
-  if (a.pt_wide) {
-    if (a.pt_rows == 8)
-      k_pT<8, true><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.n_hats, a.bands, a.pents,
-                                                  mode);
+#define FEWHA_PT(RPT, WIDE, SPLIT)                                                                      \
+  k_pT<RPT, WIDE, SPLIT><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.n_hats, a.bands, \
+                                                       a.pents, mode)
+  if (a.pt_split) {
+    if (a.pt_wide)
+      FEWHA_PT(4, true, true);
     else
-      k_pT<4, true><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.n_hats, a.bands, a.pents,
-                                                  mode);
+      FEWHA_PT(4, false, true);
+  } else if (a.pt_wide) {
+    if (a.pt_rows == 8)
+      FEWHA_PT(8, true, false);
+    else
+      FEWHA_PT(4, true, false);
   } else if (a.pt_rows == 8) {
-    k_pT<8, false><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.n_hats, a.bands, a.pents,
-                                                 mode);
+    FEWHA_PT(8, false, false);
   } else {
-    k_pT<4, false><<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.hats, a.n_hats, a.bands, a.pents,
-                                                 mode);
+    FEWHA_PT(4, false, false);
   }
+#undef FEWHA_PT
 }
 void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter, const CoarseDev* C) {
   if (ntiles > 0) k_update<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles, iter, C);

@@ -16,9 +16,11 @@ def tuner(lib, tmp_path, monkeypatch):
     return autotune
 
 
-def fake_times(table, streams=None, quarters=None):
+def fake_times(table, streams=None, quarters=None, pt_split=None):
     """Stand-in timer: table[(R, rows)] for one stream, streams[s] for s > 1,
-    quarters for the resident inverse levels in four workgroups per layer."""
+    quarters for the resident inverse levels in four workgroups per layer,
+    pt_split for the propagation adjoint's split sensor lists (default: the
+    same as unsplit)."""
     calls = []
 
     def time_plan(ctxs, iters, tuning, steps=10, warmup=3):
@@ -28,6 +30,8 @@ def fake_times(table, streams=None, quarters=None):
             return streams[ns]
         if tuning.get("res_split", 0) == 4:
             return quarters
+        if tuning.get("pt_split", 0) == 1 and pt_split is not None:
+            return pt_split
         return table[(tuning["dwt_resident"], tuning["pt_rows"])]
     return time_plan, calls
 
@@ -39,7 +43,7 @@ def test_clear_winner_is_taken_and_cached(tuner, monkeypatch):
     monkeypatch.setattr(tuner, "time_plan", tp)
     rec = tuner.tune([None], 4)
     assert (rec["dwt_resident"], rec["pt_rows"], rec["cached"]) == (64, 4, False)
-    assert len(calls) == 6
+    assert len(calls) == 7 and rec["pt_split"] == 0
     # a fresh module state reads the same file: no timing at all
     calls.clear()
     again = tuner.tune([None], 4)
@@ -62,7 +66,7 @@ def test_streams_are_tuned_after_the_shapes(tuner, monkeypatch):
     monkeypatch.setattr(tuner, "time_plan", tp)
     rec = tuner.tune([None, None], 4, use_cache=False)
     assert (rec["dwt_resident"], rec["pt_rows"], rec["streams"]) == (128, 4, 2)
-    assert calls[-1] == (128, 4, 2) and len(calls) == 7
+    assert calls[-1] == (128, 4, 2) and len(calls) == 8
     assert rec["streams_us"] == {"1": 1000.0, "2": 900.0}
     # a near tie keeps one stream; a single problem is not split at all
     tp, _ = fake_times(table, {2: 995.0})
@@ -70,7 +74,7 @@ def test_streams_are_tuned_after_the_shapes(tuner, monkeypatch):
     assert tuner.tune([None, None], 4, use_cache=False)["streams"] == 1
     tp, calls = fake_times(table)
     monkeypatch.setattr(tuner, "time_plan", tp)
-    assert tuner.tune([None], 4, use_cache=False)["streams"] == 1 and len(calls) == 6
+    assert tuner.tune([None], 4, use_cache=False)["streams"] == 1 and len(calls) == 7
 
 
 def test_cache_key_follows_geometry_and_sources(lib, monkeypatch):
@@ -106,3 +110,19 @@ def test_resident_split_is_tuned_for_the_best_shape(tuner, monkeypatch):
     tp, _ = fake_times(table, {2: 2000.0}, quarters=995.0)
     monkeypatch.setattr(tuner, "time_plan", tp)
     assert tuner.tune([None, None], 4, use_cache=False)["res_split"] == 0
+
+
+def test_split_sensor_lists_are_tuned_for_the_best_shape(tuner, monkeypatch):
+    # split propagation-adjoint tiles (4 rows per thread) are kept only when
+    # clearly faster than the best unsplit shape; the streams then use them
+    table = {(r, p): 1000.0 for r in (32, 64, 128) for p in (4, 8)}
+    table[(64, 8)] = 950.0
+    tp, calls = fake_times(table, {2: 2000.0}, pt_split=900.0)
+    monkeypatch.setattr(tuner, "time_plan", tp)
+    rec = tuner.tune([None, None], 4, use_cache=False)
+    assert (rec["dwt_resident"], rec["pt_rows"], rec["pt_split"]) == (64, 4, 1)
+    assert rec["pt_split_us"] == {"0": 950.0, "1": 900.0} and calls[6] == (64, 4, 1)
+    tp, _ = fake_times(table, {2: 2000.0}, pt_split=940.0)  # 1 % faster: within the margin
+    monkeypatch.setattr(tuner, "time_plan", tp)
+    rec = tuner.tune([None, None], 4, use_cache=False)
+    assert (rec["dwt_resident"], rec["pt_rows"], rec["pt_split"]) == (64, 8, 0)

@@ -21,7 +21,10 @@ pytestmark = pytest.mark.gpu
                                       ("small", {"pt_rows": 8}), ("maory_like", {"dwt_resident": 64, "pt_rows": 8}),
                                       ("small_fit", {"pt_rows": 8}), ("maory_like", {"res_split": 1}),
                                       ("small", {"res_split": 1}), ("maory_like", {"dwt_resident": 64, "res_split": 4}),
-                                      ("mid", {"dwt_resident": 32, "res_split": 4})])
+                                      ("mid", {"dwt_resident": 32, "res_split": 4}),
+                                      ("maory_like", {"pt_split": 1}), ("small_fit", {"pt_split": 1}),
+                                      ("mid", {"dwt_resident": 32, "pt_split": 1}),
+                                      ("paper_maory", {"pt_split": 1})])
 def test_frame_parity_with_resident_side(gpu_lib, systems, name, res):
     import torch
     S = systems(name)
@@ -38,13 +41,14 @@ def test_frame_parity_with_resident_side(gpu_lib, systems, name, res):
     ctx.close()
 
 
-def test_tuned_mixed_batch(gpu_lib):
+@pytest.mark.parametrize("tuning", [32, {"dwt_resident": 64, "pt_split": 1}])
+def test_tuned_mixed_batch(gpu_lib, tuning):
     import torch
     cfgs = batch_mix(1, 1, 4)
     systems = [System(c) for c in cfgs]
     ctxs = [gpu_lib.Context(c, device=0) for c in cfgs]
-    print("\n[gpu-tune] mixed batch, resident 32", flush=True)
-    batch = gpu_lib.Batch(ctxs, tuning=32)
+    print("\n[gpu-tune] mixed batch, tuning", tuning, flush=True)
+    batch = gpu_lib.Batch(ctxs, tuning=tuning)
     slopes = [to_dev(synth_slopes(S, k)) for k, S in enumerate(systems)]
     states = [torch.zeros(c.n_state, device="cuda") for c in ctxs]
     lays = [torch.empty(c.n_coeff, device="cuda") for c in ctxs]
