@@ -296,3 +296,26 @@ def test_param_grads_refuses_stencil_outside_layer(gpu_lib):
         ctx.param_grads(to_dev(np.zeros(ctx.n_slopes)), to_dev(np.zeros(n)), to_dev(np.zeros(n)))
     assert e.value.status == -5
     ctx.close()
+
+
+@pytest.mark.parametrize("res", [128, 32])
+def test_transforms_at_the_largest_layer_side(gpu_lib, res):
+    # one 2048 x 2048 layer (the largest side the library takes), 8 levels:
+    # with resident side 128 four global levels (2048 .. 256), with 32 six;
+    # W^{-1} = delta^{-1} W^T and W^{-T} = delta^{-1} W (A7) against the
+    # oracle's dense-matrix transforms, element by element
+    from oracle.wavelet import daubechies_filter, dwt2, idwt2
+    from parity import check_blocks
+    cfg = get_config("tiny")
+    cfg["layers"] = [{"h": 0.0, "n": 2048, "levels": 8, "cn2": 1.0}]
+    step("W^-1 / W^-T at 2048 x 2048, resident side %d" % res)
+    ctx = gpu_lib.Context(cfg, device=0, tuning=res)
+    n = 2048
+    delta = cfg["domain_side"] / n
+    h = daubechies_filter(3)
+    c = random_vector(n * n, 540)
+    ref = idwt2(c.reshape(n, n), 8, h).ravel() / delta
+    check_blocks(to_host(ctx.apply_Winv(to_dev(c))), ref, [0, n * n], OP_TOL, "W^-1 c (2048)")
+    ref = dwt2(c.reshape(n, n), 8, h).ravel() / delta
+    check_blocks(to_host(ctx.apply_WinvT(to_dev(c))), ref, [0, n * n], OP_TOL, "W^-T phi (2048)")
+    ctx.close()
