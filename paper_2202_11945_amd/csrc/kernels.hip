@@ -82,13 +82,57 @@ __device__ __forceinline__ T block_sum(T v, T* sh, int nthreads) {
   return r;
 }
 
-// Sum of n slots by one wave in a fixed order (lane-strided partial sums,
-// then a fixed shuffle tree); the value of lane 0 is the result, identical in
-// every workgroup that sums the same slots.
+// Sums of slot groups by one wave in a fixed order: lane l adds slots l,
+// l + 64, l + 128, ... in turn, then a fixed shuffle tree; the result,
+// identical in every workgroup that sums the same slots, is in every lane.
+// Two phases, so that a kernel can put the slot loads in flight before its
+// own loads and reduce them while those are in flight: slots_issue requests
+// the first H slots of every lane of every group (up to 64 H per group)
+// together; slots_reduce adds them (and, for longer groups, the rest in a
+// loop).
+template <int G, int H>
+struct SlotLoads {
+  double v[G][H];
+};
+template <int G, int H>
+__device__ __forceinline__ void slots_issue(const double* const (&s)[G], const int (&n)[G], SlotLoads<G, H>& L) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+#pragma unroll
+    for (int u = 0; u < H; ++u) L.v[g][u] = 0.0;
+    if (n[g] > 0) {  // wave-uniform; a group of no slots may have no storage
+#pragma unroll
+      for (int u = 0; u < H; ++u) L.v[g][u] = ((gptr_d)s[g])[min(lane + 64 * u, n[g] - 1)];
+    }
+  }
+}
+template <int G, int H>
+__device__ __forceinline__ void slots_reduce(const double* const (&s)[G], const int (&n)[G], const SlotLoads<G, H>& L,
+                                             double (&out)[G]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    double a = 0.0;
+#pragma unroll
+    for (int u = 0; u < H; ++u)
+      if (lane + 64 * u < n[g]) a += L.v[g][u];
+    for (int i = lane + 64 * H; i < n[g]; i += 64) a += ((gptr_d)s[g])[i];
+    out[g] = wave_sum(a);
+  }
+}
+template <int G, int H = 4>
+__device__ __forceinline__ void wave_sum_slots_n(const double* const (&s)[G], const int (&n)[G], double (&out)[G]) {
+  SlotLoads<G, H> L;
+  slots_issue<G, H>(s, n, L);
+  slots_reduce<G, H>(s, n, L, out);
+}
 __device__ __forceinline__ double wave_sum_slots(const double* s, int n) {
-  double a = 0.0;
-  for (int i = threadIdx.x & 63; i < n; i += 64) a += ((gptr_d)s)[i];
-  return wave_sum(a);
+  const double* const ss[1] = {s};
+  const int nn[1] = {n};
+  double o[1];
+  wave_sum_slots_n<1>(ss, nn, o);
+  return o[0];
 }
 
 // XCD-aware work distribution.  Workgroups are dispatched round-robin over
@@ -129,10 +173,28 @@ __device__ __forceinline__ float* q_loc(const ProbDev& pr, int j) {
 }
 // rho_k = r_k^T J^{-1} r_k, summed by a wave in a fixed order; a problem with
 // augmentation forms rho_0 of its projected residual in slots of its own.
+__device__ __forceinline__ const double* rho_slots(const ProbDev& pr, int k, int& n) {
+  if (k == 0 && pr.aug_keep > 0) {
+    n = pr.n_slots_upd;
+    return pr.aug_slots + (long)kAugRho0 * pr.n_slots_upd;
+  }
+  n = rho_count(pr, k);
+  return dot_group(pr, rho_grp(k));
+}
 __device__ __forceinline__ double rho_sum(const ProbDev& pr, int k) {
-  if (k == 0 && pr.aug_keep > 0)
-    return wave_sum_slots(pr.aug_slots + (long)kAugRho0 * pr.n_slots_upd, pr.n_slots_upd);
-  return wave_sum_slots(dot_group(pr, rho_grp(k)), rho_count(pr, k));
+  int n;
+  const double* s = rho_slots(pr, k, n);
+  return wave_sum_slots(s, n);
+}
+// rho_k and rho_{k-1} with their loads in flight together
+__device__ __forceinline__ void rho_sum2(const ProbDev& pr, int k, double& rk, double& rkm) {
+  int n0, n1;
+  const double* const s[2] = {rho_slots(pr, k, n0), rho_slots(pr, k - 1, n1)};
+  const int n[2] = {n0, n1};
+  double o[2];
+  wave_sum_slots_n<2>(s, n, o);
+  rk = o[0];
+  rkm = o[1];
 }
 
 // Search-direction source of the inverse transform (fused p update).
@@ -187,9 +249,31 @@ __device__ __forceinline__ float coef_finish(const PSrc& s, int e, const CoefLoa
 // coefficient loads are in flight, so both latencies overlap
 __device__ __forceinline__ float wave_beta(const ProbDev& pr, int mode, int iter) {
   if (mode != SRC_PUPD) return 0.f;
-  const double rk = rho_sum(pr, iter);
-  const double rkm = rho_sum(pr, iter - 1);
+  double rk, rkm;
+  rho_sum2(pr, iter, rk, rkm);
   return (float)((rkm != 0.0) ? rk / rkm : 0.0);
+}
+// The same beta in two phases (see slots_issue): beta_issue before a
+// kernel's coefficient loads, beta_reduce once they are in flight.
+template <int H>
+struct BetaLoads {
+  const double* s[2];
+  int n[2];
+  SlotLoads<2, H> L;
+};
+template <int H>
+__device__ __forceinline__ void beta_issue(const ProbDev& pr, int mode, int iter, BetaLoads<H>& b) {
+  if (mode != SRC_PUPD) return;
+  b.s[0] = rho_slots(pr, iter, b.n[0]);
+  b.s[1] = rho_slots(pr, iter - 1, b.n[1]);
+  slots_issue<2, H>(b.s, b.n, b.L);
+}
+template <int H>
+__device__ __forceinline__ float beta_reduce(int mode, const BetaLoads<H>& b) {
+  if (mode != SRC_PUPD) return 0.f;
+  double o[2];
+  slots_reduce<2, H>(b.s, b.n, b.L, o);
+  return (float)((o[1] != 0.0) ? o[0] / o[1] : 0.0);
 }
 
 // Final output of the inverse transform: phi = delta^{-1} W^T c, optionally
@@ -435,6 +519,8 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
   // the coarse block and the detail quadrants of all resident levels) in one
   // pass, so that all global loads of the block are in flight together
   constexpr int kUL = 16;
+  BetaLoads<2> bl;
+  beta_issue<2>(pr, ps.mode, iter, bl);
   for (int e0 = threadIdx.x; e0 < R * R; e0 += kUL * nt) {
     CoefLoad v[kUL];
 #pragma unroll
@@ -442,7 +528,7 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
       const int e = e0 + u * nt;
       if (e < R * R) v[u] = coef_fetch(ps, off + (e >> lr) * n + (e & (R - 1)));
     }
-    if (e0 == threadIdx.x) ps.beta = wave_beta(pr, ps.mode, iter);
+    if (e0 == threadIdx.x) ps.beta = beta_reduce<2>(ps.mode, bl);
 #pragma unroll
     for (int u = 0; u < kUL; ++u) {
       const int e = e0 + u * nt;
@@ -557,6 +643,8 @@ __global__ __launch_bounds__(512) void k_idwt_res4(const ProbDev* P, const Layer
   CoefLoad v[kUL];
   int pos[kUL], dst[kUL];
   unsigned owned = 0;  // bit u: this thread's window entry u is a coefficient of its own quadrant
+  BetaLoads<2> bl;
+  beta_issue<2>(pr, ps.mode, iter, bl);
 #pragma unroll
   for (int u = 0; u < kUL; ++u) {
     const int e = threadIdx.x + u * nt;
@@ -581,7 +669,7 @@ __global__ __launch_bounds__(512) void k_idwt_res4(const ProbDev* P, const Layer
     }
     if (pos[u] >= 0) v[u] = coef_fetch(ps, pos[u]);
   }
-  ps.beta = wave_beta(pr, ps.mode, iter);  // every lane of every wave is here
+  ps.beta = beta_reduce<2>(ps.mode, bl);  // every lane of every wave is here
 #pragma unroll
   for (int u = 0; u < kUL; ++u) {
     if (pos[u] < 0) continue;
@@ -691,6 +779,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   } else {
     CoefLoad v[kRounds];
     int gpos[kRounds];
+    BetaLoads<1> bl;
+    beta_issue<1>(pr, ps.mode, iter, bl);
 #pragma unroll
     for (int u = 0; u < kRounds; ++u) {
       const int e = lane + 64 * u;
@@ -700,7 +790,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         v[u] = coef_fetch(ps, gpos[u]);
       }
     }
-    ps.beta = wave_beta(pr, ps.mode, iter);
+    ps.beta = beta_reduce<1>(ps.mode, bl);
 #pragma unroll
     for (int u = 0; u < kRounds; ++u) {
       const int e = lane + 64 * u;
@@ -2040,7 +2130,8 @@ __global__ __launch_bounds__(256) void k_aug_p(const ProbDev* P, const IoDev* IO
     aug_solve(f, w.m, tv, mu);
     double beta = 0.0;
     if (iter > 0) {
-      const double rk = rho_sum(pr, iter), rkm = rho_sum(pr, iter - 1);
+      double rk, rkm;
+      rho_sum2(pr, iter, rk, rkm);
       beta = rkm != 0.0 ? rk / rkm : 0.0;
     }
     if (threadIdx.x == 0) {
@@ -2090,11 +2181,10 @@ __global__ __launch_bounds__(256) void k_aug_store(const ProbDev* P, const IoDev
 // a = rho_k / pi_k; x += a p; r -= a q; partial rho_{k+1} = r^T J^{-1} r.
 // 2048 coefficients per workgroup as float4: 2 per thread, loads first.
 // rho_k with the coarse-level correction of the converged solves:
-// r^T z = r^T J^{-1} r + (Z^T r)^T E^{-1} Z^T r (the second part from k_coarse).
-__device__ __forceinline__ double coarse_rho(const CoarseDev* C, int prob, int k) {
-  if (!C) return 0.0;
-  const CoarseDev& c = C[prob];
-  return wave_sum_slots(c.slots + (long)(k & (kDotRing - 1)) * c.n_slots, c.n_slots);
+// r^T z = r^T J^{-1} r + (Z^T r)^T E^{-1} Z^T r (the second part's slots,
+// written by k_coarse).
+__device__ __forceinline__ const double* coarse_slots(const CoarseDev& c, int k) {
+  return c.slots + (long)(k & (kDotRing - 1)) * c.n_slots;
 }
 
 __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* IO, const Tile* tiles, int iter,
@@ -2113,6 +2203,15 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
   double acc = 0.0;
   constexpr int V = kUpdChunk / 4 / 256;  // float4 per thread
   v4f xp[V], pp[V], rr[V], qq[V], jj[V], rnv[V];
+  // rho_k (plus the coarse correction's part in a converged solve) and pi_k:
+  // slot loads first, summed by every wave itself in the same fixed order
+  // (no barrier) while its vector loads are in flight
+  int nr;
+  const double* sr = rho_slots(pr, iter, nr);
+  const double* const sl[3] = {sr, dot_group(pr, pi_grp(iter)), C ? coarse_slots(C[t.prob], iter) : sr};
+  const int nn[3] = {nr, pr.n_slots_fdwt, C ? C[t.prob].n_slots : 0};
+  SlotLoads<3, 2> sloads;
+  slots_issue<3, 2>(sl, nn, sloads);
 #pragma unroll
   for (int u = 0; u < V; ++u) {
     const int e = e0 + threadIdx.x + u * 256;
@@ -2124,10 +2223,10 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
       jj[u] = jv[e];
     }
   }
-  // alpha = rho_k / pi_k, summed by every wave itself in the same fixed order
-  // (no barrier) while its loads are in flight
-  const double rho = rho_sum(pr, iter) + coarse_rho(C, t.prob, iter);
-  const double pi = wave_sum_slots(dot_group(pr, pi_grp(iter)), pr.n_slots_fdwt);
+  // alpha = rho_k / pi_k
+  double o[3];
+  slots_reduce<3, 2>(sl, nn, sloads, o);
+  const double rho = o[0] + o[2], pi = o[1];
   const float a = (float)((pi > 0.0) ? rho / pi : 0.0);
   // breakdown: a nonzero residual with p^T M p <= 0 (M is positive definite,
   // so only rounding or non-finite inputs get here), or a negative or
@@ -2276,8 +2375,14 @@ __global__ __launch_bounds__(256) void k_coarse_p(const ProbDev* P, const IoDev*
   const ProbDev& pr = P[t.prob];
   float beta = 0.f;
   if (iter > 0) {
-    const double rk = rho_sum(pr, iter) + coarse_rho(C, t.prob, iter);
-    const double rkm = rho_sum(pr, iter - 1) + coarse_rho(C, t.prob, iter - 1);
+    int n0, n1;
+    const CoarseDev& c = C[t.prob];
+    const double* const sl[4] = {rho_slots(pr, iter, n0), coarse_slots(c, iter), rho_slots(pr, iter - 1, n1),
+                                 coarse_slots(c, iter - 1)};
+    const int nn[4] = {n0, c.n_slots, n1, c.n_slots};
+    double o[4];
+    wave_sum_slots_n<4>(sl, nn, o);
+    const double rk = o[0] + o[1], rkm = o[2] + o[3];
     beta = (float)(rkm != 0.0 ? rk / rkm : 0.0);
   }
   const int e0 = t.ty * kUpdChunk, e1 = min(e0 + kUpdChunk, pr.n_c);
