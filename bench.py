@@ -208,8 +208,8 @@ def measured_traffic(stage, batch, tuning):
     for f in ("kernels.hip", "kernels.h", "fewha_internal.h", "api.cpp"):
         h.update(open(os.path.join(ROOT, "paper_2202_11945_amd", "csrc", f), "rb").read())
     sha = h.hexdigest()[:16]
-    tune = "%d/%d/%d/%d" % (tuning["dwt_resident"], tuning["pt_rows"], tuning.get("res_split", 0),
-                            tuning.get("pt_split", 0))
+    tune = "%d/%d/%d/%d/%d" % (tuning["dwt_resident"], tuning["pt_rows"], tuning.get("res_split", 0),
+                               tuning.get("pt_split", 0), tuning.get("glob_fuse", 0))
     prof = os.path.join(ROOT, "profiles", "stages_maory_like_b%d_bytes.md" % batch)
     if not os.path.exists(prof):
         return None
@@ -446,7 +446,7 @@ def paper_maory_leg(fw, nf=1000):
         lat = latency(lambda i: b.reconstruct([slopes[pool_index(i, 4)]], [st], [lay], iters=iters,
                                               use_graph=True), nf)
         fb = path_bytes(ctx.n_coeff, corner_count(cfg), ctx.n_slopes, iters)
-        out["iters_%d" % iters] = dict(lat, tuning={k: tune[k] for k in ("dwt_resident", "pt_rows", "pt_split")},
+        out["iters_%d" % iters] = dict(lat, tuning={k: tune[k] for k in ("dwt_resident", "pt_rows", "pt_split", "glob_fuse")},
                                        speedup_vs_paper=1480.0 / lat["p50_us"] if iters == 2 else None,
                                        bytes_per_frame=fb, path_GBs=fb / lat["p50_us"] / 1e3)
         b.close()
@@ -458,7 +458,7 @@ def paper_maory_leg(fw, nf=1000):
     st = torch.zeros(ca.n_state, device="cuda")
     lay = torch.empty(ca.n_coeff, device="cuda")
     lat = latency(lambda i: b.reconstruct([slopes[pool_index(i, 4)]], [st], [lay], iters=2, use_graph=True), nf)
-    out["iters_2_augmented"] = dict(lat, tuning={k: tune[k] for k in ("dwt_resident", "pt_rows", "pt_split")},
+    out["iters_2_augmented"] = dict(lat, tuning={k: tune[k] for k in ("dwt_resident", "pt_rows", "pt_split", "glob_fuse")},
                                     speedup_vs_paper=1480.0 / lat["p50_us"])
     b.close()
     ca.close()

@@ -434,6 +434,11 @@ FEWHA_API void fewha_batch_destroy(fewha_batch* b);
  * to wave i mod 4, the partial sums added in a fixed order), a quarter of
  * the serial chain of sensors per wave; for launches with few tiles, such
  * as one problem's frame.  Needs pt_rows 0 or 4.  0 = default (off).
+ * glob_fuse: 1 = a layer with two or more global levels (side above twice
+ * dwt_resident) runs its last two inverse levels in one launch: each output
+ * tile synthesizes the part of the inner level it needs itself (about 27 %
+ * more inner-level work, one launch fewer per inverse transform).  0 =
+ * default (off).
  * reserved: zero. */
 typedef struct {
   int dwt_resident;
@@ -441,7 +446,8 @@ typedef struct {
   int streams;
   int res_split;
   int pt_split;
-  int reserved[3];
+  int glob_fuse;
+  int reserved[2];
 } fewha_tuning;
 
 /* Tuning of a context's own plan; before fewha_finalize. */

@@ -35,7 +35,7 @@ class fewha_dm_desc(ctypes.Structure):
 
 class fewha_tuning(ctypes.Structure):
     _fields_ = [("dwt_resident", c_int), ("pt_rows", c_int), ("streams", c_int), ("res_split", c_int),
-                ("pt_split", c_int), ("reserved", c_int * 3)]
+                ("pt_split", c_int), ("glob_fuse", c_int), ("reserved", c_int * 2)]
 
 
 class FewhaError(RuntimeError):

@@ -1,6 +1,6 @@
 """Autotuner of a plan's launch shapes.
 
-Five tunables:
+Six tunables:
 
 * the resident transform side R (32, 64 or 128): the resident DWT kernels
   keep every level up to R x R in one workgroup's LDS, and the levels above R
@@ -12,6 +12,9 @@ Five tunables:
 * for the best of those, the propagation adjoint's sensor lists split over
   the waves of 4-row tiles (pt_split), which shortens each wave's serial
   chain of sensors where a launch has few tiles;
+* fused global levels (glob_fuse): a layer with two or more levels above
+  the resident side runs its top two levels as one launch per transform,
+  timed for every resident side where that applies;
 * then the resident inverse levels in one workgroup per layer (the default)
   or in four (each synthesizing the lower levels itself and one quadrant of
   the top level);
@@ -68,6 +71,12 @@ def split_allowed(ctxs, res):
             if R < 16 or R < 2 * (l["n"] >> l["levels"]):
                 return False
     return True
+
+
+def fusable(ctxs, res):
+    """Whether some layer has two or more global levels at resident side res
+    (side above 2 res), so that glob_fuse changes the plan."""
+    return any(l["n"] > 2 * res for c in ctxs for l in c.cfg["layers"])
 
 
 def signature(ctxs, iters, device_name=None):
@@ -130,8 +139,9 @@ def time_plan(ctxs, iters, tuning, steps=10, warmup=3):
 
 def tune(ctxs, iters, steps=10, use_cache=True):
     """Best launch shapes for a batch of these contexts; returns
-    {"dwt_resident": R, "pt_rows": r, "pt_split": 0 or 1, "res_split": 0 or 4,
-     "streams": s, "us": {"R/r": us per step}, "pt_split_us", "split_us",
+    {"dwt_resident": R, "pt_rows": r, "pt_split": 0 or 1, "glob_fuse": 0 or 1,
+     "res_split": 0 or 4, "streams": s, "us": {"R/r": us per step},
+     "pt_split_us", "glob_fuse_us", "split_us",
      "streams_us": {"s": us per step}, "cached": bool}."""
     key = signature(ctxs, iters)
     db = _load() if use_cache else {}
@@ -154,10 +164,23 @@ def tune(ctxs, iters, steps=10, use_cache=True):
                                         steps=steps)}
     if pts_us[1] <= (1.0 - MARGIN) * pts_us[0]:
         shape = {"dwt_resident": best[0], "pt_rows": 4, "pt_split": 1}
+    shape["glob_fuse"] = 0
+    # fused global levels, at every resident side where a layer has two or
+    # more global levels, with the propagation adjoint's shape just chosen
+    cur = pts_us[shape["pt_split"]]
+    fuse_us = {}
+    for r in admissible(ctxs):
+        if fusable(ctxs, r):
+            fuse_us[r] = time_plan(ctxs, iters, dict(shape, dwt_resident=r, glob_fuse=1), steps=steps)
+    if fuse_us:
+        rf = min(fuse_us, key=fuse_us.get)
+        if fuse_us[rf] <= (1.0 - MARGIN) * cur:
+            shape = dict(shape, dwt_resident=rf, glob_fuse=1)
+            cur = fuse_us[rf]
     # then the resident inverse levels in four workgroups per layer against
     # the default one
-    split_us = {0: min(pts_us[shape["pt_split"]], us[best])}
-    if split_allowed(ctxs, best[0]):
+    split_us = {0: cur}
+    if split_allowed(ctxs, shape["dwt_resident"]):
         split_us[4] = time_plan(ctxs, iters, dict(shape, res_split=4), steps=steps)
     split = min(split_us, key=split_us.get)
     if split_us[split] > (1.0 - MARGIN) * split_us[0]:
@@ -170,9 +193,10 @@ def tune(ctxs, iters, steps=10, use_cache=True):
     if sus[streams] > (1.0 - MARGIN) * sus[1]:
         streams = 1
     rec = {"dwt_resident": shape["dwt_resident"], "pt_rows": shape["pt_rows"], "pt_split": shape["pt_split"],
-           "res_split": split, "streams": streams,
+           "glob_fuse": shape["glob_fuse"], "res_split": split, "streams": streams,
            "us": {"%d/%d" % k: round(t, 3) for k, t in us.items()},
            "pt_split_us": {"%d" % k: round(t, 3) for k, t in pts_us.items()},
+           "glob_fuse_us": {"%d" % k: round(t, 3) for k, t in fuse_us.items()},
            "split_us": {"%d" % k: round(t, 3) for k, t in split_us.items()},
            "streams_us": {"%d" % k: round(t, 3) for k, t in sus.items()}}
     if use_cache:

@@ -50,6 +50,7 @@ struct Plan {
   int pt_rows = 4;        // node rows per thread of the propagation adjoint (tuning)
   bool pt_wide = false;   // some (sensor, layer) pair has K > 3 corners per node (wide band records)
   bool pt_split = false;  // propagation-adjoint tiles of one band record, sensors split over the waves
+  bool glob_fuse = false; // some inverse global tiles run a layer's last two levels (k_idwt_glob2)
   std::vector<const HostModel*> models;
   void* arena = nullptr;
   size_t arena_bytes = 0;
@@ -390,7 +391,7 @@ struct Carver {
 };
 
 fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models, int device, int res,
-                        int pt_rows, int split, int pt_split, std::string& err) {
+                        int pt_rows, int split, int pt_split, int glob_fuse, std::string& err) {
   if (res != 32 && res != 64 && res != 128) {
     err = "tuning: the resident transform side must be 32, 64 or 128";
     return FEWHA_EINVAL;
@@ -405,6 +406,10 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   }
   if (pt_split && pt_rows != 4) {
     err = "tuning: split propagation-adjoint tiles take 4 node rows per thread";
+    return FEWHA_EINVAL;
+  }
+  if (glob_fuse != 0 && glob_fuse != 1) {
+    err = "tuning: glob_fuse must be 0 or 1";
     return FEWHA_EINVAL;
   }
   // quarters need at least one resident level of output side >= 16 on every layer
@@ -621,9 +626,26 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
         if (ld.n_glob_levels <= s) continue;
         const int mf = ld.n >> s;  // forward: input side
         const int tq = (mf / 2) / 16;
-        for (int ty = 0; ty < tq; ++ty)
-          for (int tx = 0; tx < tq; ++tx) t_fdwt_glob[s].push_back({k, l, ty, tx, slot++, ilog2i(mf), pd.layer0 + l, 0});
-        const int mi = ld.res << (s + 1);  // inverse: output side
+        // with glob_fuse a layer's first two global levels are one tile at
+        // step 0 (its inner coarse block goes where step 1 would put it)
+        const bool ffuse = glob_fuse && ld.n_glob_levels >= 2;
+        if (!(ffuse && s == 1))
+          for (int ty = 0; ty < tq; ++ty)
+            for (int tx = 0; tx < tq; ++tx)
+              t_fdwt_glob[s].push_back({k, l, ty, tx, slot++, ilog2i(mf), pd.layer0 + l, (ffuse && s == 0) ? 1 : 0});
+        // inverse: output side; with glob_fuse a layer's last two global
+        // levels are one tile of its full side at the inner level's step
+        // (reading that step's scratch), and its last step has no tiles
+        const int ng = ld.n_glob_levels;
+        if (glob_fuse && ng >= 2 && s >= ng - 2) {
+          if (s == ng - 1) continue;
+          for (int ty = 0; ty < ld.n / 32; ++ty)
+            for (int tx = 0; tx < ld.n / 32; ++tx)
+              t_idwt_glob[s].push_back({k, l, ty, tx, 0, ilog2i(ld.n), pd.layer0 + l, 1});
+          P.glob_fuse = true;
+          continue;
+        }
+        const int mi = ld.res << (s + 1);
         const int ti = mi / 32;
         for (int ty = 0; ty < ti; ++ty)
           for (int tx = 0; tx < ti; ++tx) t_idwt_glob[s].push_back({k, l, ty, tx, 0, ilog2i(mi), pd.layer0 + l, 0});
@@ -1264,6 +1286,7 @@ LaunchArgs args(const Plan& P, hipStream_t s, const IoDev* io) {
   a.pt_rows = P.pt_rows;
   a.pt_wide = P.pt_wide ? 1 : 0;
   a.pt_split = P.pt_split ? 1 : 0;
+  a.glob_fuse = P.glob_fuse ? 1 : 0;
   a.hats = P.dHat;
   a.n_hats = P.nHat;
   a.bands = P.dBand;
@@ -2023,8 +2046,9 @@ fewha_status fewha_set_tuning(fewha_ctx* c, const fewha_tuning* t) {
   CHECK_CTX(c);
   if (c->finalized) return fail(c, FEWHA_ESTATE, "set_tuning after finalize");
   if (!t) return fail(c, FEWHA_EINVAL, "set_tuning: null tuning");
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 2; ++i)
     if (t->reserved[i]) return fail(c, FEWHA_EINVAL, "set_tuning: reserved fields must be zero");
+  if (t->glob_fuse != 0 && t->glob_fuse != 1) return fail(c, FEWHA_EINVAL, "set_tuning: glob_fuse must be 0 or 1");
   if (t->pt_split != 0 && t->pt_split != 1) return fail(c, FEWHA_EINVAL, "set_tuning: pt_split must be 0 or 1");
   if (t->pt_split && t->pt_rows == 8)
     return fail(c, FEWHA_EINVAL, "set_tuning: pt_split needs pt_rows 0 or 4");
@@ -2040,6 +2064,7 @@ fewha_status fewha_set_tuning(fewha_ctx* c, const fewha_tuning* t) {
   c->m.tune_pt_rows = t->pt_rows;
   c->m.tune_split = t->res_split;
   c->m.tune_pt_split = t->pt_split;
+  c->m.tune_glob_fuse = t->glob_fuse;
   return FEWHA_OK;
 }
 
@@ -2053,7 +2078,8 @@ fewha_status fewha_finalize(fewha_ctx* c) {
   if (c->device >= 0) {
     std::vector<const HostModel*> ms{&c->m};
     s = build_plan(c->plan, ms, c->device, c->m.tune_res > 0 ? c->m.tune_res : kResMax,
-                   c->m.tune_pt_rows > 0 ? c->m.tune_pt_rows : 4, c->m.tune_split, c->m.tune_pt_split, c->err);
+                   c->m.tune_pt_rows > 0 ? c->m.tune_pt_rows : 4, c->m.tune_split, c->m.tune_pt_split,
+                   c->m.tune_glob_fuse, c->err);
     if (s != FEWHA_OK) return s;
     c->plan->coarse_side = c->coarse_side;
     if ((s = setup_noalloc(*c->plan, c->err)) != FEWHA_OK ||
@@ -2376,7 +2402,8 @@ fewha_status fewha_batch_create_tuned(fewha_batch** out, fewha_ctx* const* ctxs,
   if (!out || !ctxs || n < 1) return FEWHA_EINVAL;
   if (t && (t->dwt_resident < 0 || t->pt_rows < 0 || t->streams < 0 || t->streams > 4 || t->streams > n ||
             (t->res_split != 0 && t->res_split != 1 && t->res_split != 4) || (t->pt_split != 0 && t->pt_split != 1) ||
-            (t->pt_split && t->pt_rows == 8) || t->reserved[0] || t->reserved[1] || t->reserved[2]))
+            (t->pt_split && t->pt_rows == 8) || (t->glob_fuse != 0 && t->glob_fuse != 1) || t->reserved[0] ||
+            t->reserved[1]))
     return FEWHA_EINVAL;
   *out = nullptr;
   int dev = -1;
@@ -2394,7 +2421,8 @@ fewha_status fewha_batch_create_tuned(fewha_batch** out, fewha_ctx* const* ctxs,
   const int rows = (t && t->pt_rows > 0) ? t->pt_rows : 4;
   const int split = t ? t->res_split : 0;
   const int pt_split = t ? t->pt_split : 0;
-  fewha_status s = build_plan(b->plan, ms, dev, res, rows, split, pt_split, b->err);
+  const int glob_fuse = t ? t->glob_fuse : 0;
+  fewha_status s = build_plan(b->plan, ms, dev, res, rows, split, pt_split, glob_fuse, b->err);
   if (s != FEWHA_OK) {
     delete b;
     return s;
@@ -2416,7 +2444,8 @@ fewha_status fewha_batch_create_tuned(fewha_batch** out, fewha_ctx* const* ctxs,
       const int k0 = (int)((long)n * q / parts), k1 = (int)((long)n * (q + 1) / parts);
       b->part_first.push_back(k0);
       std::vector<const HostModel*> mq(ms.begin() + k0, ms.begin() + k1);
-      if ((s = build_plan(b->parts[q], mq, dev, res, rows, split, pt_split, b->err)) != FEWHA_OK) return undo(s);
+      if ((s = build_plan(b->parts[q], mq, dev, res, rows, split, pt_split, glob_fuse, b->err)) != FEWHA_OK)
+        return undo(s);
       if (hipStreamCreateWithFlags(&b->part_stream[q], hipStreamNonBlocking) != hipSuccess ||
           hipEventCreateWithFlags(&b->part_done[q], hipEventDisableTiming) != hipSuccess)
         return undo(FEWHA_EDEVICE);

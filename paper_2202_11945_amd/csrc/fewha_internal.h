@@ -398,6 +398,7 @@ struct HostModel {
   int tune_pt_rows = 0;  // node rows per thread of the propagation adjoint (0 = default)
   int tune_split = 0;    // resident inverse levels: 0 or 1 = one workgroup per layer, 4 = quarters
   int tune_pt_split = 0; // 1: propagation-adjoint tiles of one band record, sensors split over the waves
+  int tune_glob_fuse = 0; // 1: a layer's last two global inverse levels in one tile
   long n_act() const { return fit.on ? fit.n_act : n_c; }
   // [c | b | r | a_prev | a], then with augmentation the previous directions,
   // their images and a count (4 floats, keeping 16-byte alignment)

@@ -45,6 +45,7 @@ struct LaunchArgs {
   int pt_rows;         // node rows per thread of the propagation adjoint (4 or 8)
   int pt_wide;         // 1: some pair has K > 3 corners per node (the kernel with wide records)
   int pt_split;        // 1: tiles of one band record, the sensor list split over the waves
+  int glob_fuse;       // 1: the last two global levels of a layer run as one tile (inverse transform)
 };
 
 void launch_idwt_res(const LaunchArgs& a, const Tile* tiles, int ntiles, int src_mode, int out_mode, int iter);

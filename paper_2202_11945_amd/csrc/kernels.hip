@@ -742,12 +742,23 @@ constexpr int kGT = 32;           // output tile side
 constexpr int kGH = kGT / 2 + 2;  // coefficients per band and direction (18)
 constexpr int kGW = 2 * kGH;      // 36
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_idwt_glob(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
-                                                   const Tile* tiles, Filter F, int src_mode, int out_mode,
-                                                   int iter, int step) {
-  __shared__ float A[kGW * (kGW + 1)];
-  __shared__ float B[kGT * (kGW + 1)];
-  const Tile t = my_tile(tiles);
+// The two synthesis passes of a global level's output tile from its window
+// of four bands in A (coarse block at band (0, 0)): columns into B, then rows
+// to the output (the layers, or the next level's coarse block in scratch).
+struct GlobOut {
+  int n, off, m, t0, s0;
+  float inv_delta;
+  gptr_w nxt;  // the next level's coarse block in scratch (stride m)
+};
+__device__ __forceinline__ void idwt_glob_passes(const ProbDev& pr, const IoDev& io, const Filter& F, int out_mode,
+                                                 const GlobOut& g, float* A, float* B);
+
+// One output tile of one global level: the window's bands from scratch (the
+// coarse block) and the coefficient source (with the fused p update), then
+// the passes.
+__device__ __forceinline__ void idwt_glob_tile(const ProbDev* P, const LayerDev* LD, const IoDev* IO, const Tile& t,
+                                               const Filter& F, int src_mode, int out_mode, int iter, int step,
+                                               float* A, float* B) {
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[t.mask];  // the global layer index, carried by the tile
   const IoDev& io = IO[t.prob];
@@ -756,10 +767,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   const int m = 1 << t.level, half = m >> 1;
   const int t0 = t.ty * kGT, s0 = t.tx * kGT;
   const gptr_f ll = (gptr_f)(((step & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off);  // stride half
-  const gptr_w nxt = (gptr_w)(((step & 1) ? pr.tmpa : pr.tmpb) + ly.tmp_off);  // stride m
+  const GlobOut g{n, off, m, t0, s0, ly.inv_delta, (gptr_w)(((step & 1) ? pr.tmpa : pr.tmpb) + ly.tmp_off)};
   const int kr0 = (t0 >> 1) - 2, kc0 = (s0 >> 1) - 2;
   const int W1 = kGW + 1;
-  const int nt = blockDim.x;
   // the window's four bands, one per wave (so no wave mixes the coarse
   // block with the coefficient source): wave 0 the coarse block (scratch),
   // waves 1 .. 3 the detail quadrants (by, bx) = (0, 1), (1, 0), (1, 1)
@@ -809,6 +819,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     }
   }
   __syncthreads();
+  idwt_glob_passes(pr, io, F, out_mode, g, A, B);
+}
+
+__device__ __forceinline__ void idwt_glob_passes(const ProbDev& pr, const IoDev& io, const Filter& F, int out_mode,
+                                                 const GlobOut& g, float* A, float* B) {
+  const int n = g.n, off = g.off, m = g.m, t0 = g.t0, s0 = g.s0;
+  const gptr_w nxt = g.nxt;
+  const int W1 = kGW + 1;
+  const int nt = blockDim.x;
   // columns: one input column and a run of 4 output pairs per task (the
   // taps of consecutive pairs overlap, so a run reads 12 taps, not 48)
   constexpr int kRun = 4;
@@ -838,11 +857,147 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                         F.g[par] * Br[kGH + k] + F.g[par + 2] * Br[kGH + k - 1] + F.g[par + 4] * Br[kGH + k - 2];
       const int row = t0 + lt, col = s0 + ls;
       if (final_level)
-        out_finish(od, off + row * n + col, acc * ly.inv_delta, o[u]);
+        out_finish(od, off + row * n + col, acc * g.inv_delta, o[u]);
       else
         nxt[row * m + col] = acc;
     }
   }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_idwt_glob(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
+                                                   const Tile* tiles, Filter F, int src_mode, int out_mode,
+                                                   int iter, int step) {
+  __shared__ float A[kGW * (kGW + 1)];
+  __shared__ float B[kGT * (kGW + 1)];
+  const Tile t = my_tile(tiles);
+  idwt_glob_tile(P, LD, IO, t, F, src_mode, out_mode, iter, step, A, B);
+}
+
+// The last two global levels of a layer in one tile (output side m = n, the
+// layer's own side): the inner level (output side m/2) is synthesized in LDS
+// for the 18 x 18 window of its output that the outer level's tile needs,
+// from 11 x 11 windows of its four bands (coarse block from scratch, detail
+// quadrants from the coefficient source with the fused p update), then the
+// outer level as a single-level tile.  Neighbouring tiles recompute the
+// overlap of their inner windows (about 27 % more inner-level work) and save
+// a launch; each inner coefficient's p is written by the tile whose 8 x 8
+// stride it falls in (window entries 3 .. 10 in each direction).
+constexpr int kGI = kGH / 2 + 2;  // inner band window side (11)
+constexpr int kGIW = 2 * kGI;     // 22
+
+__device__ __forceinline__ void idwt_glob2_tile(const ProbDev* P, const LayerDev* LD, const IoDev* IO, const Tile& t,
+                                                const Filter& F, int src_mode, int out_mode, int iter, int step,
+                                                float* A, float* B, float* A2, float* B2) {
+  const ProbDev& pr = P[t.prob];
+  const LayerDev& ly = LD[t.mask];
+  const IoDev& io = IO[t.prob];
+  PSrc ps = make_psrc(pr, io, src_mode, iter, 0.f);
+  const int n = ly.n, off = ly.off;
+  const int m = 1 << t.level, half = m >> 1, quart = m >> 2;
+  const int t0 = t.ty * kGT, s0 = t.tx * kGT;
+  // the inner level's coarse block (side quart) in this step's scratch
+  const gptr_f ll = (gptr_f)(((step & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off);
+  const GlobOut g{n, off, m, t0, s0, ly.inv_delta, (gptr_w)(((step & 1) ? pr.tmpa : pr.tmpb) + ly.tmp_off)};
+  const int kr0 = (t0 >> 1) - 2, kc0 = (s0 >> 1) - 2;  // outer band window origin (mod half)
+  const int jr0 = (kr0 >> 1) - 2, jc0 = (kc0 >> 1) - 2;  // inner band window origin (mod quart)
+  const int W1 = kGW + 1, W2 = kGIW + 1;
+  const int nt = blockDim.x;
+  constexpr int kIB = kGI * kGI, kIR = (kIB + 63) / 64;    // inner band entries, rounds per lane
+  constexpr int kBand = kGH * kGH, kRounds = (kBand + 63) / 64;
+  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int by = wv >> 1, bx = wv & 1;
+  // wave 0: the inner coarse window; waves 1 .. 3: the inner and the outer
+  // detail windows of band (by, bx), all loads in flight together
+  float ival[kIR];
+  if (wv == 0) {
+#pragma unroll
+    for (int u = 0; u < kIR; ++u) {
+      const int e = lane + 64 * u;
+      if (e < kIB) {
+        const int iy = e / kGI, ix = e - iy * kGI;
+        ival[u] = ll[((jr0 + iy) & (quart - 1)) * quart + ((jc0 + ix) & (quart - 1))];
+      }
+    }
+  } else {
+    CoefLoad iv[kIR], ov[kRounds];
+    int ipos[kIR], opos[kRounds];
+    BetaLoads<1> bl;
+    beta_issue<1>(pr, ps.mode, iter, bl);
+#pragma unroll
+    for (int u = 0; u < kIR; ++u) {
+      const int e = lane + 64 * u;
+      if (e < kIB) {
+        const int iy = e / kGI, ix = e - iy * kGI;
+        ipos[u] = off + (by * quart + ((jr0 + iy) & (quart - 1))) * n + bx * quart + ((jc0 + ix) & (quart - 1));
+        iv[u] = coef_fetch(ps, ipos[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kRounds; ++u) {
+      const int e = lane + 64 * u;
+      if (e < kBand) {
+        const int iy = e / kGH, ix = e - iy * kGH;
+        opos[u] = off + (by * half + ((kr0 + iy) & (half - 1))) * n + bx * half + ((kc0 + ix) & (half - 1));
+        ov[u] = coef_fetch(ps, opos[u]);
+      }
+    }
+    ps.beta = beta_reduce<1>(ps.mode, bl);
+#pragma unroll
+    for (int u = 0; u < kIR; ++u) {
+      const int e = lane + 64 * u;
+      if (e < kIB) {
+        const int iy = e / kGI, ix = e - iy * kGI;
+        ival[u] = coef_finish(ps, ipos[u], iv[u], iy >= 3 && ix >= 3);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kRounds; ++u) {
+      const int e = lane + 64 * u;
+      if (e < kBand) {
+        const int iy = e / kGH, ix = e - iy * kGH;
+        A[(by * kGH + iy) * W1 + bx * kGH + ix] = coef_finish(ps, opos[u], ov[u], iy >= 2 && ix >= 2);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kIR; ++u) {
+    const int e = lane + 64 * u;
+    if (e < kIB) {
+      const int iy = e / kGI, ix = e - iy * kGI;
+      A2[(by * kGI + iy) * W2 + bx * kGI + ix] = ival[u];
+    }
+  }
+  __syncthreads();
+  // inner level, columns: 22 columns x 9 output pairs (runs of 3) -> B2 rows 0 .. 17
+  for (int task = threadIdx.x; task < kGIW * 3; task += nt) {
+    const int c = task % kGIW, p0 = (task / kGIW) * 3;
+    syn_run<3>(A2 + c, A2 + kGI * W2 + c, W2, p0, F, B2 + 2 * p0 * W2 + c, W2);
+  }
+  __syncthreads();
+  // inner level, rows: 18 rows x 9 output pairs -> the outer window's coarse band
+  for (int task = threadIdx.x; task < kGH * 3; task += nt) {
+    const int r = task % kGH, p0 = (task / kGH) * 3;
+    syn_run<3>(B2 + r * W2, B2 + r * W2 + kGI, 1, p0, F, A + r * W1 + 2 * p0, 1);
+  }
+  __syncthreads();
+  idwt_glob_passes(pr, io, F, out_mode, g, A, B);
+}
+
+// A launch of global-level tiles of which some are fused pairs of levels
+// (tile pad1 = 1): plans with fused tiles launch this kernel instead of
+// k_idwt_glob.
+__global__ __launch_bounds__(256) void k_idwt_glob2(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
+                                                    const Tile* tiles, Filter F, int src_mode, int out_mode, int iter,
+                                                    int step) {
+  __shared__ float A[kGW * (kGW + 1)];
+  __shared__ float B[kGT * (kGW + 1)];
+  __shared__ float A2[kGIW * (kGIW + 1)];
+  __shared__ float B2[kGH * (kGIW + 1)];
+  const Tile t = my_tile(tiles);
+  if (t.pad1)
+    idwt_glob2_tile(P, LD, IO, t, F, src_mode, out_mode, iter, step, A, B, A2, B2);
+  else
+    idwt_glob_tile(P, LD, IO, t, F, src_mode, out_mode, iter, step, A, B);
 }
 
 // ------------------------------------------------ forward DWT, one global level
@@ -851,12 +1006,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 constexpr int kFT = 16;           // output coefficients per direction
 constexpr int kFW = 2 * kFT + 4;  // 36 input samples per direction
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_fdwt_glob(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
-                                                   const Tile* tiles, Filter F, int epi, int iter, int step) {
-  __shared__ float X[kFW * (kFW + 1)];
-  __shared__ float Rw[kFW * (2 * kFT + 1)];
-  __shared__ double sh[4];
-  const Tile t = my_tile(tiles);
+__device__ __forceinline__ void fdwt_glob_tile(const ProbDev* P, const LayerDev* LD, const IoDev* IO, const Tile t,
+                                               const Filter F, int epi, int iter, int step, float* X, float* Rw,
+                                               double* sh) {
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[t.mask];  // the global layer index, carried by the tile
   const IoDev& io = IO[t.prob];
@@ -953,6 +1105,168 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     const double s = block_sum(acc, sh, nt);
     if (threadIdx.x == 0) ((gptr_wd)pr.dots)[(long)dot_group_of(epi, iter) * pr.n_dots + t.slot] = s;
   }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_fdwt_glob(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
+                                                   const Tile* tiles, Filter F, int epi, int iter, int step) {
+  __shared__ float X[kFW * (kFW + 1)];
+  __shared__ float Rw[kFW * (2 * kFT + 1)];
+  __shared__ double sh[4];
+  const Tile t = my_tile(tiles);
+  fdwt_glob_tile(P, LD, IO, t, F, epi, iter, step, X, Rw, sh);
+}
+
+// The first two global levels of a layer in one tile (input side m = n, the
+// layer's own side, at step 0): the outer level (m -> m/2) is analysed for
+// the 20 x 20 window of its coarse output that the inner level (m/2 -> m/4)
+// needs, plus its own 16 x 16 x 3 detail outputs, from a 44 x 44 input
+// window; the inner level gives 8 x 8 outputs of each band.  Both levels'
+// details take the epilogue; the inner coarse block goes to scratch where
+// the inner level's own launch would have put it.  Each output is the same
+// sum as in the single-level tiles (about 56 % more outer coarse work, one
+// launch fewer per forward transform).
+constexpr int kF2 = 8;                 // inner outputs per band and direction
+constexpr int kF1C = 2 * kF2 + 4;      // outer coarse values per direction (20)
+constexpr int kF2W = 2 * kF1C + 4;     // input samples per direction (44)
+
+__device__ __forceinline__ void fdwt_glob2_tile(const ProbDev* P, const LayerDev* LD, const IoDev* IO, const Tile& t,
+                                                const Filter& F, int epi, int iter, int step, float* X, float* R1,
+                                                float* X2, float* R2, double* sh) {
+  const ProbDev& pr = P[t.prob];
+  const LayerDev& ly = LD[t.mask];
+  const IoDev& io = IO[t.prob];
+  const int n = ly.n, off = ly.off;
+  const int m = 1 << t.level, half = m >> 1, quart = m >> 2;
+  const gptr_f in = (gptr_f)((step == 0) ? pr.phiadj + off : (((step & 1) ? pr.tmpa : pr.tmpb) + ly.tmp_off));
+  const int istride = (step == 0) ? n : m;
+  const gptr_w llout = (gptr_w)((((step + 1) & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off);  // stride quart
+  const int k0 = t.ty * kFT, l0 = t.tx * kFT;  // outer detail outputs (and coarse window) origin
+  const int k2 = t.ty * kF2, l2 = t.tx * kF2;  // inner outputs origin
+  const int XW = kF2W + 1, R1W = kF1C + kFT + 1, X2W = kF1C + 1, R2W = 2 * kF2 + 1;
+  const int nt = blockDim.x;
+  // epilogue positions and operands, requested before the input window:
+  // outer details e < 768 (band e / 256: (y low, x high), (y high, x low),
+  // (y high, x high)), three per thread; inner details e < 192, one per thread
+  int p1[3], p2;
+  EpiLoad e1[3], e2;
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int e = threadIdx.x + u * nt, b = e >> 8, lk = (e & 255) >> 4, lc = e & 15;
+    p1[u] = off + ((b >= 1) * half + k0 + lk) * n + (b != 1) * half + l0 + lc;
+    e1[u] = epi_fetch(pr, io, epi, iter, p1[u]);
+  }
+  {
+    const int e = threadIdx.x, b = e >> 6, lk = (e & 63) >> 3, lc = e & 7;
+    p2 = e < 192 ? off + ((b >= 1) * quart + k2 + lk) * n + (b != 1) * quart + l2 + lc : -1;
+    if (p2 >= 0) e2 = epi_fetch(pr, io, epi, iter, p2);
+  }
+  constexpr int kIn = kF2W * kF2W, kUI = (kIn + 255) / 256;
+  {
+    float v[kUI];
+#pragma unroll
+    for (int u = 0; u < kUI; ++u) {
+      const int e = threadIdx.x + u * nt;
+      if (e < kIn) {
+        const int ry = e / kF2W, rx = e - ry * kF2W;
+        v[u] = in[((2 * k0 + ry) & (m - 1)) * istride + ((2 * l0 + rx) & (m - 1))];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUI; ++u) {
+      const int e = threadIdx.x + u * nt;
+      if (e < kIn) {
+        const int ry = e / kF2W, rx = e - ry * kF2W;
+        X[ry * XW + rx] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  // outer rows (along x): 44 rows x (20 low, 16 high)
+  for (int e = threadIdx.x; e < kF2W * (kF1C + kFT); e += nt) {
+    const int ry = e / (kF1C + kFT), c = e - ry * (kF1C + kFT);
+    const bool hi = c >= kF1C;
+    const int lk = hi ? c - kF1C : c;
+    const float* xr = X + ry * XW + 2 * lk;
+    float a = 0.f;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) a += (hi ? F.g[i] : F.h[i]) * xr[i];
+    R1[ry * R1W + c] = a;
+  }
+  __syncthreads();
+  double acc = 0.0;
+  const EpiDst dst = epi_dst(pr, io, iter);
+  // outer columns: the 20 x 20 coarse window for the inner level ...
+  for (int e = threadIdx.x; e < kF1C * kF1C; e += nt) {
+    const int lk = e / kF1C, lc = e - lk * kF1C;
+    float a = 0.f;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) a += F.h[i] * R1[(2 * lk + i) * R1W + lc];
+    X2[lk * X2W + lc] = a;
+  }
+  // ... and the outer details with the epilogue
+  {
+    const float ad = ly.alpha_d[t.level - 1];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int e = threadIdx.x + u * nt, b = e >> 8, lk = (e & 255) >> 4, lc = e & 15;
+      const int col = b == 1 ? lc : kF1C + lc;  // x low (b = 1) or x high
+      float d = 0.f;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) d += (b == 0 ? F.h[i] : F.g[i]) * R1[(2 * lk + i) * R1W + col];
+      epi_finish(dst, epi, p1[u], ad, d * ly.inv_delta, e1[u], acc);
+    }
+  }
+  __syncthreads();
+  // inner rows: 20 rows x (8 low, 8 high)
+  for (int e = threadIdx.x; e < kF1C * 2 * kF2; e += nt) {
+    const int ry = e / (2 * kF2), c = e - ry * (2 * kF2);
+    const bool hi = c >= kF2;
+    const int lk = hi ? c - kF2 : c;
+    const float* xr = X2 + ry * X2W + 2 * lk;
+    float a = 0.f;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) a += (hi ? F.g[i] : F.h[i]) * xr[i];
+    R2[ry * R2W + c] = a;
+  }
+  __syncthreads();
+  // inner columns: the coarse block to scratch, the details with the epilogue
+  {
+    const float ad = ly.alpha_d[t.level - 2];
+    if (threadIdx.x < 4 * kF2 * kF2) {
+      const int e = threadIdx.x, b = e >> 6, lk = (e & 63) >> 3, lc = e & 7;
+      // b = 0 .. 2: the details as above; b = 3: the coarse block
+      const int col = (b == 1 || b == 3) ? lc : kF2 + lc;
+      const bool yhi = b == 1 || b == 2;
+      float v = 0.f;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) v += (yhi ? F.g[i] : F.h[i]) * R2[(2 * lk + i) * R2W + col];
+      if (b == 3)
+        llout[(k2 + lk) * quart + l2 + lc] = v;
+      else
+        epi_finish(dst, epi, p2, ad, v * ly.inv_delta, e2, acc);
+    }
+  }
+  if (epi == EPI_PCG || epi == EPI_RHS || epi == EPI_RHSQ) {
+    const double s = block_sum(acc, sh, nt);
+    if (threadIdx.x == 0) ((gptr_wd)pr.dots)[(long)dot_group_of(epi, iter) * pr.n_dots + t.slot] = s;
+  }
+}
+
+// A launch of forward global-level tiles of which some are fused pairs of
+// levels (tile pad1 = 1): plans with fused tiles launch this kernel instead
+// of k_fdwt_glob.
+__global__ __launch_bounds__(256) void k_fdwt_glob2(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
+                                                    const Tile* tiles, Filter F, int epi, int iter, int step) {
+  __shared__ float X[kF2W * (kF2W + 1)];
+  __shared__ float R1[kF2W * (kF1C + kFT + 1)];
+  __shared__ float X2[kF1C * (kF1C + 1)];
+  __shared__ float R2[kF1C * (2 * kF2 + 1)];
+  __shared__ double sh[4];
+  const Tile t = my_tile(tiles);
+  if (t.pad1)
+    fdwt_glob2_tile(P, LD, IO, t, F, epi, iter, step, X, R1, X2, R2, sh);
+  else
+    fdwt_glob_tile(P, LD, IO, t, F, epi, iter, step, X, R1, sh);
 }
 
 // ------------------------------------------------ forward DWT, resident part
@@ -2622,11 +2936,18 @@ void launch_idwt_res4(const LaunchArgs& a, const Tile* tiles, int ntiles, int sr
 }
 void launch_idwt_glob(const LaunchArgs& a, const Tile* tiles, int ntiles, int src_mode, int out_mode, int iter,
                       int step) {
-  if (ntiles > 0)
+  if (ntiles <= 0) return;
+  if (a.glob_fuse)
+    k_idwt_glob2<<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, src_mode, out_mode, iter, step);
+  else
     k_idwt_glob<<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, src_mode, out_mode, iter, step);
 }
 void launch_fdwt_glob(const LaunchArgs& a, const Tile* tiles, int ntiles, int epi, int iter, int step) {
-  if (ntiles > 0) k_fdwt_glob<<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter, step);
+  if (ntiles <= 0) return;
+  if (a.glob_fuse)
+    k_fdwt_glob2<<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter, step);
+  else
+    k_fdwt_glob<<<ntiles, 256, 0, a.stream>>>(a.P, a.L, a.IO, tiles, a.F, epi, iter, step);
 }
 template <int RMAX>
 static void launch_fdwt_res_r(const LaunchArgs& a, const Tile* tiles, int ntiles, int epi, int iter) {

@@ -44,8 +44,8 @@ def _ptr64(t, n):
 
 def _tuning(tuning):
     """fewha_tuning from an int (the resident transform side) or a dict with
-    keys dwt_resident, pt_rows, streams, res_split and pt_split (missing =
-    default)."""
+    keys dwt_resident, pt_rows, streams, res_split, pt_split and glob_fuse
+    (missing = default)."""
     t = _abi.fewha_tuning()
     if isinstance(tuning, dict):
         t.dwt_resident = int(tuning.get("dwt_resident", 0))
@@ -53,6 +53,7 @@ def _tuning(tuning):
         t.streams = int(tuning.get("streams", 0))
         t.res_split = int(tuning.get("res_split", 0))
         t.pt_split = int(tuning.get("pt_split", 0))
+        t.glob_fuse = int(tuning.get("glob_fuse", 0))
     else:
         t.dwt_resident = int(tuning)
     return t

@@ -26,6 +26,7 @@ def main():
     ap.add_argument("--pt-rows", type=int, default=0, help="node rows per thread of P^T (0 = default)")
     ap.add_argument("--split", type=int, default=0, help="resident inverse levels: 0 default, 1 or 4 workgroups")
     ap.add_argument("--pt-split", type=int, default=0, help="propagation adjoint: 1 = sensor lists split over waves")
+    ap.add_argument("--glob-fuse", type=int, default=0, help="1 = a layer's top two global levels in one launch")
     ap.add_argument("--tuned", action="store_true", help="launch shapes from the autotuner (as bench.py)")
     ap.add_argument("--latency-frames", type=int, default=0,
                     help="then this many single frames of one problem (graph replays, synchronized each)")
@@ -37,13 +38,15 @@ def main():
 
     cfg = get_config(a.config)
     ctxs = [fw.Context(cfg, device=0) for _ in range(a.batch)]
-    tuning = {"dwt_resident": a.res, "pt_rows": a.pt_rows, "res_split": a.split, "pt_split": a.pt_split}
+    tuning = {"dwt_resident": a.res, "pt_rows": a.pt_rows, "res_split": a.split, "pt_split": a.pt_split,
+              "glob_fuse": a.glob_fuse}
     if a.tuned:
         from paper_2202_11945_amd import autotune
         rec = autotune.tune(ctxs, a.iters)
-        tuning = {k: rec[k] for k in ("dwt_resident", "pt_rows", "res_split", "pt_split")}
-    print("tuning %d/%d/%d/%d batch %d" % (tuning["dwt_resident"] or 128, tuning["pt_rows"] or 4, tuning["res_split"],
-                                           tuning["pt_split"], a.batch), flush=True)
+        tuning = {k: rec[k] for k in ("dwt_resident", "pt_rows", "res_split", "pt_split", "glob_fuse")}
+    print("tuning %d/%d/%d/%d/%d batch %d" % (tuning["dwt_resident"] or 128, tuning["pt_rows"] or 4,
+                                              tuning["res_split"], tuning["pt_split"], tuning["glob_fuse"], a.batch),
+          flush=True)
     batch = fw.Batch(ctxs, tuning=tuning)
     dev = torch.device("cuda:0")
     slopes = [torch.from_numpy(random_vector(ctxs[0].n_slopes, 5, k)).to(dev) for k in range(a.batch)]

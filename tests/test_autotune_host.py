@@ -13,10 +13,11 @@ def tuner(lib, tmp_path, monkeypatch):
     monkeypatch.setattr(autotune, "signature", lambda ctxs, iters: "dev|iters%d|shape" % iters)
     monkeypatch.setattr(autotune, "admissible", lambda ctxs, candidates=autotune.CANDIDATES: [32, 64, 128])
     monkeypatch.setattr(autotune, "split_allowed", lambda ctxs, res: False)
+    monkeypatch.setattr(autotune, "fusable", lambda ctxs, res: False)
     return autotune
 
 
-def fake_times(table, streams=None, quarters=None, pt_split=None):
+def fake_times(table, streams=None, quarters=None, pt_split=None, fuse=None):
     """Stand-in timer: table[(R, rows)] for one stream, streams[s] for s > 1,
     quarters for the resident inverse levels in four workgroups per layer,
     pt_split for the propagation adjoint's split sensor lists (default: the
@@ -30,6 +31,8 @@ def fake_times(table, streams=None, quarters=None, pt_split=None):
             return streams[ns]
         if tuning.get("res_split", 0) == 4:
             return quarters
+        if tuning.get("glob_fuse", 0) == 1 and fuse is not None:
+            return fuse[tuning["dwt_resident"]]
         if tuning.get("pt_split", 0) == 1 and pt_split is not None:
             return pt_split
         return table[(tuning["dwt_resident"], tuning["pt_rows"])]
@@ -126,3 +129,20 @@ def test_split_sensor_lists_are_tuned_for_the_best_shape(tuner, monkeypatch):
     monkeypatch.setattr(tuner, "time_plan", tp)
     rec = tuner.tune([None, None], 4, use_cache=False)
     assert (rec["dwt_resident"], rec["pt_rows"], rec["pt_split"]) == (64, 8, 0)
+
+
+def test_fused_global_levels_are_tuned_per_resident_side(tuner, monkeypatch):
+    # fusion is timed at every resident side where a layer has two or more
+    # global levels (here 32 and 64), with the shapes chosen so far, and the
+    # fastest is kept when clearly faster
+    monkeypatch.setattr(tuner, "fusable", lambda ctxs, res: res < 128)
+    table = {(r, p): 1000.0 for r in (32, 64, 128) for p in (4, 8)}
+    tp, calls = fake_times(table, {2: 2000.0}, fuse={32: 950.0, 64: 900.0})
+    monkeypatch.setattr(tuner, "time_plan", tp)
+    rec = tuner.tune([None, None], 4, use_cache=False)
+    assert (rec["dwt_resident"], rec["glob_fuse"]) == (64, 1)
+    assert rec["glob_fuse_us"] == {"32": 950.0, "64": 900.0}
+    tp, _ = fake_times(table, {2: 2000.0}, fuse={32: 990.0, 64: 995.0})  # within the margin
+    monkeypatch.setattr(tuner, "time_plan", tp)
+    rec = tuner.tune([None, None], 4, use_cache=False)
+    assert (rec["dwt_resident"], rec["glob_fuse"]) == (128, 0)

@@ -71,12 +71,13 @@ def test_traffic_only_for_matching_sources_and_shapes():
     rows = [l.split() for l in open(prof) if l.split()[:1] == ["TRAFFIC"]]
     assert {r[1] for r in rows} == set(bench.STAGES)
     got = bench.measured_traffic("P_T", 32, tune)
-    expected = [float(r[3]) for r in rows if r[1] == "P_T" and r[5] == "128/4/0/0"]
+    expected = [float(r[3]) for r in rows if r[1] == "P_T" and r[5] == "128/4/0/0/0"]
     # the summary is taken on the committed kernel sources: then it is reported
     assert got is None or [got] == expected
     # other launch shapes or batch sizes never borrow it
     assert bench.measured_traffic("P_T", 32, {"dwt_resident": 64, "pt_rows": 8}) is None
     assert bench.measured_traffic("P_T", 32, dict(tune, pt_split=1)) is None
+    assert bench.measured_traffic("P_T", 32, dict(tune, glob_fuse=1)) is None
     assert bench.measured_traffic("P_T", 48, tune) is None
 
 

@@ -298,7 +298,7 @@ def test_param_grads_refuses_stencil_outside_layer(gpu_lib):
     ctx.close()
 
 
-@pytest.mark.parametrize("res", [128, 32])
+@pytest.mark.parametrize("res", [128, 32, {"dwt_resident": 32, "glob_fuse": 1}])
 def test_transforms_at_the_largest_layer_side(gpu_lib, res):
     # one 2048 x 2048 layer (the largest side the library takes), 8 levels:
     # with resident side 128 four global levels (2048 .. 256), with 32 six;
@@ -308,7 +308,7 @@ def test_transforms_at_the_largest_layer_side(gpu_lib, res):
     from parity import check_blocks
     cfg = get_config("tiny")
     cfg["layers"] = [{"h": 0.0, "n": 2048, "levels": 8, "cn2": 1.0}]
-    step("W^-1 / W^-T at 2048 x 2048, resident side %d" % res)
+    step("W^-1 / W^-T at 2048 x 2048, tuning %s" % res)
     ctx = gpu_lib.Context(cfg, device=0, tuning=res)
     n = 2048
     delta = cfg["domain_side"] / n

@@ -24,7 +24,11 @@ pytestmark = pytest.mark.gpu
                                       ("mid", {"dwt_resident": 32, "res_split": 4}),
                                       ("maory_like", {"pt_split": 1}), ("small_fit", {"pt_split": 1}),
                                       ("mid", {"dwt_resident": 32, "pt_split": 1}),
-                                      ("paper_maory", {"pt_split": 1})])
+                                      ("paper_maory", {"pt_split": 1}),
+                                      ("maory_like", {"dwt_resident": 64, "glob_fuse": 1}),
+                                      ("maory_like", {"dwt_resident": 32, "glob_fuse": 1, "pt_split": 1}),
+                                      ("mid", {"dwt_resident": 32, "glob_fuse": 1}),
+                                      ("paper_maory", {"dwt_resident": 32, "glob_fuse": 1})])
 def test_frame_parity_with_resident_side(gpu_lib, systems, name, res):
     import torch
     S = systems(name)
@@ -41,7 +45,7 @@ def test_frame_parity_with_resident_side(gpu_lib, systems, name, res):
     ctx.close()
 
 
-@pytest.mark.parametrize("tuning", [32, {"dwt_resident": 64, "pt_split": 1}])
+@pytest.mark.parametrize("tuning", [32, {"dwt_resident": 64, "pt_split": 1}, {"dwt_resident": 32, "glob_fuse": 1}])
 def test_tuned_mixed_batch(gpu_lib, tuning):
     import torch
     cfgs = batch_mix(1, 1, 4)

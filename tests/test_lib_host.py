@@ -132,8 +132,10 @@ def test_tuning_arguments_are_validated(lib):
     for bad in (16, 96, -1, 256):
         assert _abi.fewha_set_tuning(h, byref(_tuning(bad))) == -1
     t = _tuning(32)
-    t.reserved[2] = 1
+    t.reserved[1] = 1
     assert _abi.fewha_set_tuning(h, byref(t)) == -1
+    assert _abi.fewha_set_tuning(h, byref(_tuning({"glob_fuse": 2}))) == -1
+    assert _abi.fewha_set_tuning(h, byref(_tuning({"glob_fuse": 1}))) == 0
     for bad in ({"pt_split": 2}, {"pt_split": -1}, {"pt_split": 1, "pt_rows": 8}):
         assert _abi.fewha_set_tuning(h, byref(_tuning(bad))) == -1
     for ok in ({"pt_split": 1}, {"pt_split": 1, "pt_rows": 4}, {"pt_split": 0, "pt_rows": 8}):
