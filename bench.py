@@ -184,14 +184,18 @@ def path_rate(bytes_per_frame, frames_per_s, peaks):
     return out
 
 
-def launches_per_frame(cfg, res, iters):
+def launches_per_frame(cfg, res, iters, fuse=False):
     """Kernel launches of one open-loop frame of one problem (plain PCG):
     slope input, sensor adjoint, propagation adjoint and forward transform
     for the right-hand side; per iteration the inverse transform, the
     propagation and sensor stages, the forward transform and the update;
     the final inverse transform.  A transform is one resident launch plus
-    one launch per level of output side above the resident side res."""
-    g = max(sum(1 for k in range(1, 16) if res < 2 ** k <= l["n"]) for l in cfg["layers"])
+    one launch per level of output side above the resident side res (with
+    fused global levels, a layer's top two such levels are one launch)."""
+    def glob(l):
+        ng = sum(1 for k in range(1, 16) if res < 2 ** k <= l["n"])
+        return ng - 1 if fuse and ng >= 2 else ng
+    g = max(glob(l) for l in cfg["layers"])
     return 3 + (1 + g) + iters * (2 * (1 + g) + 4) + (1 + g)
 
 
@@ -494,7 +498,7 @@ def augmentation_leg(fw, cfg, pool_dev, n_frames=16, iters=2, keep=2, nf=100):
     augmented PCG (Sec. 3.3), on one MAORY-like frozen-flow sequence: the
     M-norm error of c against the converged MAP solution of each frame
     (fewha_solve_map, refined to 1e-7), and the single-frame latency of both
-    (graph path)."""
+    (graph path, autotuned launch shapes)."""
     import torch
     ctx_p = fw.Context(dict(cfg, iters=iters), device=0)
     ctx_a = fw.Context(dict(cfg, iters=iters, augment=keep), device=0)
@@ -517,8 +521,9 @@ def augmentation_leg(fw, cfg, pool_dev, n_frames=16, iters=2, keep=2, nf=100):
                        % (n_frames, iters, keep, 2 * iters),
            "m_norm_error_plain": err["plain"], "m_norm_error_augmented": err["augmented"],
            "mean_error_frames_4_on": {k: sum(v[4:]) / len(v[4:]) for k, v in err.items()}}
+    from paper_2202_11945_amd import autotune
     for name, (c, it) in runs.items():
-        b = fw.Batch([c])
+        b = fw.Batch([c], tuning=autotune.tune([c], it))
         s1 = torch.zeros(c.n_state, device="cuda")
         out["latency_us_" + name] = latency(lambda i: b.reconstruct([pool_dev[pool_index(i, len(pool_dev))]], [s1],
                                                                     iters=it, use_graph=True), nf)
@@ -758,7 +763,8 @@ def main():
             "bytes_per_frame": frame_b,
             "batched": path_rate(frame_b, value, peaks),
             "single_frame_graph_p50": path_rate(frame_b, 1e6 / lat_graph["p50_us"], peaks),
-            "launches_per_frame_single": launches_per_frame(cfg, tune_1["dwt_resident"], args.iters)},
+            "launches_per_frame_single": launches_per_frame(cfg, tune_1["dwt_resident"], args.iters,
+                                                            bool(tune_1.get("glob_fuse", 0)))},
         "latency_graph_us": lat_graph,
         "latency_plain_us": lat_plain,
         "batched_nograph_frames_per_s": B / dt_nograph,

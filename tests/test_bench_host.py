@@ -96,3 +96,6 @@ def test_whole_path_bytes_and_launch_count():
     # (the count the single-frame kernel trace shows), 49 with 64
     assert bench.launches_per_frame(cfg, 128, 4) == 39
     assert bench.launches_per_frame(cfg, 64, 4) == 49
+    # fused global levels: the 256 x 256 layer's two global levels are one launch
+    assert bench.launches_per_frame(cfg, 64, 4, fuse=True) == 39
+    assert bench.launches_per_frame(cfg, 32, 4, fuse=True) == 49
