@@ -16,13 +16,19 @@ from test_gpu_parity import FRAME_ETOL, LAYER_TOL, OP_TOL, synth_slopes, to_dev,
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("name,keep,iters", [("small", 2, 2), ("small", 4, 4), ("maory_like", 4, 4)])
-def test_augmented_frames(gpu_lib, name, keep, iters):
+@pytest.mark.parametrize("name,keep,iters,tuning", [("small", 2, 2, None), ("small", 4, 4, None),
+                                                    ("maory_like", 4, 4, None),
+                                                    ("maory_like", 2, 2, {"dwt_resident": 64, "pt_split": 1,
+                                                                          "glob_fuse": 1})])
+def test_augmented_frames(gpu_lib, name, keep, iters, tuning):
+    # the last case in the single-frame launch shapes (fused global levels,
+    # split propagation-adjoint tiles), whose transform kernels form the
+    # augmented directions' inverse transforms too
     import torch
-    print("\n[gpu-aug]", name, keep, iters, flush=True)
+    print("\n[gpu-aug]", name, keep, iters, tuning, flush=True)
     cfg = get_config(name, augment=keep, iters=iters)
     S = System(cfg)
-    ctx = gpu_lib.Context(cfg, device=0)
+    ctx = gpu_lib.Context(cfg, device=0, tuning=tuning)
     n = S.geom.n_coeff
     assert ctx.n_state == 5 * n + 2 * keep * n + 4
     st = torch.zeros(ctx.n_state, device="cuda")

@@ -28,7 +28,8 @@ pytestmark = pytest.mark.gpu
                                       ("maory_like", {"dwt_resident": 64, "glob_fuse": 1}),
                                       ("maory_like", {"dwt_resident": 32, "glob_fuse": 1, "pt_split": 1}),
                                       ("mid", {"dwt_resident": 32, "glob_fuse": 1}),
-                                      ("paper_maory", {"dwt_resident": 32, "glob_fuse": 1})])
+                                      ("paper_maory", {"dwt_resident": 32, "glob_fuse": 1}),
+                                      ("maory_like", {"dwt_resident": 64, "glob_fuse": 1, "res_split": 4})])
 def test_frame_parity_with_resident_side(gpu_lib, systems, name, res):
     import torch
     S = systems(name)
