@@ -246,7 +246,7 @@ FEWHA_API fewha_status fewha_set_frame_count(fewha_ctx* ctx, long frames);
  * sensor group (pipelining, Sec. 4.3): the sensors are split into `chunks`
  * contiguous groups (1 <= chunks <= min(G, 64)); each group's slopes are
  * copied to the device on a copy stream of the context, and the frame takes
- * in each group (dense grid, tip/tilt partial sums) as soon as its copy is
+ * in each group (slope buffer, tip/tilt partial sums) as soon as its copy is
  * done.  In closed loop the mirrors' part of the pseudo-open-loop slopes,
  * Gamma a^(i-1), needs no measurement and runs while the copies are in
  * flight.  Results are bitwise those of fewha_reconstruct on the same
@@ -260,7 +260,7 @@ FEWHA_API fewha_status fewha_reconstruct_streamed(fewha_ctx* ctx, const float* h
  * cannot allocate device memory: code under HIP graph capture, tight
  * real-time serving loops, harnesses that forbid hipMalloc.  Same arguments,
  * kernels and results (bitwise) as fewha_reconstruct; the frame's work
- * buffers (layers, adjoint, dense slopes, corner grids, search directions,
+ * buffers (layers, adjoint, slopes, corner grids, search directions,
  * M p, inner-product slots) and the per-call pointer table live in one
  * static device array of the library (16 MiB, one copy per device, held
  * until the process ends) instead of the context's work space.  The call

@@ -86,6 +86,7 @@ struct Plan {
   int nHat = 0;                              // entries of dHat
   const BandRec* dBand = nullptr;            // band records of the propagation adjoint
   const PtEnt* dPtE = nullptr;               // sensor lists of the propagation-adjoint tiles
+  const int2* dGtr = nullptr;                // window rows of the Shack-Hartmann adjoint tiles
   std::vector<float*> sstate;                // per problem: [x | unused | r] of a solve
   double* rho_host = nullptr;                // pinned readback: 2 n_dots doubles per problem
   std::vector<long> rho_off;
@@ -458,7 +459,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   // ---- descriptors and tile lists ----
   struct ProbLayout {
     size_t phi, phiadj, tmpa, tmpb, sd, vadj, part, p0, p1, q, dots, jinv, itab, ftab, cmap, cinv, gl;
-    size_t sstate, gphi, glam, gslots, gitab, gftab, amap;
+    size_t sstate, gphi, glam, gslots, gitab, gftab, amap, srow;
     size_t a64, b64, sd64, u64, rslots, cinv64, ftab64, rbuf, x64;
     size_t apdir, aqdir, aslots, afac;
   };
@@ -474,6 +475,9 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   std::vector<std::vector<Tile>> t_idwt_glob, t_fdwt_glob;
   // host table images per problem (copied after allocation)
   std::vector<std::vector<int>> itab(P.nprob), cmap(P.nprob), gitab(P.nprob);
+  std::vector<std::vector<int>> srow(P.nprob);  // row bases of the row-span slope layout
+  std::vector<int2> gtrows;                     // Shack-Hartmann adjoint tiles' window rows (plan-wide)
+  static_assert(kGtS == 32, "a window row's 33 active flags: 32 bits and the base's low bit");
   std::vector<std::vector<float>> ftab(P.nprob), cinv(P.nprob), jinv(P.nprob), gftab(P.nprob);
   std::vector<std::vector<GLPar>> glp(P.nprob);
   for (int k = 0; k < P.nprob; ++k) {
@@ -512,12 +516,31 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
       ld.inv_delta64 = 1.0 / lh.delta;
       P.hL.push_back(ld);
     }
-    int s_tot = 0, v_tot = 0, m_tot = 0, part_tot = 0, tab_tot = 0, gtab_tot = 0;
+    int s_tot = 0, v_tot = 0, m_tot = 0, part_tot = 0, tab_tot = 0, gtab_tot = 0, sp_tot = 0;
+    srow[k].clear();
     for (int g = 0; g < G; ++g) {
       const WfsHost& wh = m.wfs[g];
       WfsDev wd{};
       wd.N = wh.d.n_subap;
       wd.nc = wd.N + 1;
+      // row-span slope layout: row i keeps its columns lo_i .. hi_i (first
+      // and last active subaperture), rows packed in order; inactive
+      // subapertures inside a span (a central obstruction) keep a slot
+      wd.rb_off = (int)srow[k].size();
+      int len = 0;
+      for (int i = 0; i < wd.N; ++i) {
+        int lo = wd.N, hi = -1;
+        for (int j = 0; j < wd.N; ++j)
+          if (wh.cmap[(size_t)i * wd.N + j] >= 0) {
+            lo = std::min(lo, j);
+            hi = j;
+          }
+        srow[k].push_back(hi >= lo ? len - lo : 0);
+        if (hi >= lo) len += hi - lo + 1;
+      }
+      wd.sp_off = sp_tot;
+      wd.sp_len = len;
+      sp_tot += 2 * len;
       wd.lgs = wh.d.kind == FEWHA_LGS;
       wd.tt = wd.lgs && wh.d.tt_removal;
       wd.blocks = wd.lgs && m.alpha_eta > 0.0;
@@ -712,9 +735,33 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
           t_sin.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
           if (!m.closed) t_sinf.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
         }
+      // Shack-Hartmann adjoint tiles: kGtS x kGtS corners over a window of
+      // kGtS + 1 subaperture rows and columns; per window row the span base
+      // and the active flags of the window's columns (tile.level: the first
+      // row's entry)
       const int tc = cdiv(wd.nc, kGtS);
+      const WfsHost& wh = m.wfs[g];
       for (int ty = 0; ty < tc; ++ty)
-        for (int tx = 0; tx < tc; ++tx) t_gt.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
+        for (int tx = 0; tx < tc; ++tx) {
+          t_gt.push_back({k, g, ty, tx, pd.wfs0 + g, (int)gtrows.size(), pd.layer0, 0});
+          for (int li = 0; li <= kGtS; ++li) {
+            const int i = ty * kGtS - 1 + li;
+            int base = 0, top = 0;
+            unsigned bits = 0;
+            if (i >= 0 && i < wd.N) {
+              base = srow[k][wd.rb_off + i];
+              for (int lj = 0; lj <= kGtS; ++lj) {
+                const int j = tx * kGtS - 1 + lj;
+                if (j < 0 || j >= wd.N || wh.cmap[(size_t)i * wd.N + j] < 0) continue;
+                if (lj < 32)
+                  bits |= 1u << lj;
+                else
+                  top = 1;
+              }
+            }
+            gtrows.push_back(make_int2(base * 2 + top, (int)bits));
+          }
+        }
       const int tc16 = cdiv(wd.nc, kTileS);
       for (int ty = 0; ty < tc16; ++ty)
         for (int tx = 0; tx < tc16; ++tx) t_r64gt.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
@@ -748,7 +795,8 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     pl_.phiadj = cv.take(nc4);
     pl_.tmpa = cv.take(sizeof(float) * std::max(tmp_total, 1));
     pl_.tmpb = cv.take(sizeof(float) * std::max(tmp_total, 1));
-    pl_.sd = cv.take(sizeof(float) * s_tot);
+    pl_.sd = cv.take(sizeof(float) * std::max(sp_tot, 1));
+    pl_.srow = cv.take(sizeof(int) * std::max<size_t>(srow[k].size(), 1));
     pl_.vadj = cv.take(sizeof(float) * v_tot);
     pl_.part = cv.take(sizeof(float) * part_tot);
     pl_.p0 = cv.take(nc4);
@@ -964,6 +1012,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   const size_t oHat = cv.take(sizeof(HatEnt) * hats.hats.size());
   const size_t oBand = cv.take(sizeof(BandRec) * hats.bands.size());
   const size_t oPtE = cv.take(sizeof(PtEnt) * std::max<size_t>(ptl.ents.size(), 1));
+  const size_t oGtr = cv.take(sizeof(int2) * std::max<size_t>(gtrows.size(), 1));
   const size_t oF = cv.take(sizeof(FitDev) * std::max<size_t>(hF.size(), 1));
   const size_t oPna = cv.take(sizeof(ProbDev) * P.nprob_all);
   const size_t oT = cv.take(sizeof(Tile) * std::max<size_t>(P.hT.size(), 1));
@@ -1001,6 +1050,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     pd.ftab = (const float*)(base + l.ftab);
     pd.cmap = (const int*)(base + l.cmap);
     pd.amap = (const unsigned char*)(base + l.amap);
+    pd.srow = (const int*)(base + l.srow);
     pd.cinv = (const float*)(base + l.cinv);
     pd.gl = (const GLPar*)(base + l.gl);
     pd.gphi = (float*)(base + l.gphi);
@@ -1042,6 +1092,8 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
       if (!act.empty()) HIP_TRY(hipMemcpy(base + l.amap, act.data(), act.size(), hipMemcpyHostToDevice));
     }
     HIP_TRY(hipMemcpy(base + l.cinv, cinv[k].data(), sizeof(float) * cinv[k].size(), hipMemcpyHostToDevice));
+    if (!srow[k].empty())
+      HIP_TRY(hipMemcpy(base + l.srow, srow[k].data(), sizeof(int) * srow[k].size(), hipMemcpyHostToDevice));
   }
   for (size_t i = 0; i < fits.size(); ++i) {
     const FitLayout& fl = fits[i];
@@ -1088,6 +1140,9 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     HIP_TRY(hipMemcpy(base + oHat, hats.hats.data(), sizeof(HatEnt) * hats.hats.size(), hipMemcpyHostToDevice));
   if (!hats.bands.empty())
     HIP_TRY(hipMemcpy(base + oBand, hats.bands.data(), sizeof(BandRec) * hats.bands.size(), hipMemcpyHostToDevice));
+  P.dGtr = (const int2*)(base + oGtr);
+  if (!gtrows.empty())
+    HIP_TRY(hipMemcpy(base + oGtr, gtrows.data(), sizeof(int2) * gtrows.size(), hipMemcpyHostToDevice));
   P.dPtE = (const PtEnt*)(base + oPtE);
   if (!ptl.ents.empty())
     HIP_TRY(hipMemcpy(base + oPtE, ptl.ents.data(), sizeof(PtEnt) * ptl.ents.size(), hipMemcpyHostToDevice));
@@ -1166,7 +1221,7 @@ fewha_status noalloc_scratch(int device, unsigned char** out, std::string& err) 
 }
 
 // Problem records of plan P whose frame work buffers (layers, adjoint,
-// coarse-block scratch, dense slopes, corner grids, tip/tilt partials,
+// coarse-block scratch, slope buffer, corner grids, tip/tilt partials,
 // search directions, M p, inner-product slots) are carved from the static
 // scratch after a 256-byte per-call table; the tables stay in the arena.
 // Every buffer is written before it is read within a frame, so the scratch
@@ -1193,7 +1248,7 @@ fewha_status setup_noalloc(Plan& P, std::string& err) {
     }
     for (int g = 0; g < pd.G; ++g) {
       const WfsDev& wd = P.hW[pd.wfs0 + g];
-      sd = std::max(sd, sizeof(float) * (size_t)(wd.s_off + 2 * wd.N * wd.N));
+      sd = std::max(sd, sizeof(float) * (size_t)(wd.sp_off + 2 * wd.sp_len));
       vadj = std::max(vadj, sizeof(float) * (size_t)(wd.v_off + wd.nc * wd.nc));
       part = std::max(part, sizeof(float) * (size_t)(wd.part_off + 4 * wd.n_tiles_s));
     }
@@ -1291,6 +1346,7 @@ LaunchArgs args(const Plan& P, hipStream_t s, const IoDev* io) {
   a.n_hats = P.nHat;
   a.bands = P.dBand;
   a.pents = P.dPtE;
+  a.gtrows = P.dGtr;
   return a;
 }
 
@@ -1309,7 +1365,7 @@ void enq_fdwt(const Plan& P, const LaunchArgs& a, int epi, int iter) {
     launch_fdwt_glob(a, T(P, P.fdwt_glob[s]), P.fdwt_glob[s].n, epi, iter, (int)s);
   launch_fdwt_res(a, T(P, P.fdwt_res), P.fdwt_res.n, epi, iter);
 }
-// A^T C_hat^{-1} (dense slopes in the work buffer) -> phiadj
+// A^T C_hat^{-1} (slopes in the work buffer) -> phiadj
 void enq_adjoint(const Plan& P, const LaunchArgs& a, int gt_mode, int pt_mode) {
   launch_gammaT(a, T(P, P.gt), P.gt.n, gt_mode);
   launch_pT(a, T(P, P.pt), P.pt.n, pt_mode);
@@ -1319,14 +1375,14 @@ void enq_apply_M_core(const Plan& P, const LaunchArgs& a) {
   enq_adjoint(P, a, GT_WEIGHTED, PT_PHIADJ);
 }
 
-// One frame after its slopes are in the dense grid with their tip/tilt
+// One frame after its slopes are in the slope buffer with their tip/tilt
 // partials; refresh: restart from the true residual b' - M c (q = M c from
 // enq_refresh_mc) instead of Algorithm 1's recurrence (b' - b) + r.
 void enq_frame_body(const Plan& P, const LaunchArgs& a, int iters, bool refresh);
 
 // q = M c of every problem (the state's c): the operator chain on the second
 // per-call table (in = state, out = q), before the frame's slopes take the
-// dense grid.
+// slope buffer.
 void enq_refresh_mc(const Plan& P, const LaunchArgs& a) {
   LaunchArgs b = a;
   b.IO = P.dIO2;

@@ -80,7 +80,7 @@ struct WfsDev {
   int lgs, tt;          // laser guide star, tip/tilt removal
   int blocks;           // 1 = 2x2 block noise weights present
   int n_active;
-  int s_off;            // dense slopes: [s^x N*N | s^y N*N] at s_off
+  int s_off;            // dense FP64 slopes of the refined solves' residual: [s^x N*N | s^y N*N] at s_off
   int v_off;            // corner grids: nc*nc at v_off
   int cs_off;           // compact slopes of this sensor within the problem's slope vector
   int m_off;            // N*N compact-index map at m_off (-1 = inactive)
@@ -91,7 +91,9 @@ struct WfsDev {
   int tab_off;          // per layer: interp/adjacency tables at tab_off + l * tab_stride
   int tab_stride;
   int gtab_off;         // per layer: derivative tables at gtab_off + l * 4 nc (gitab / gftab)
-  int pad0;
+  int sp_off;           // FP32 slopes in row-span layout: [s^x | s^y] at sp_off, sp_len entries each,
+  int sp_len;           //   row i holding its columns lo_i .. hi_i (the first and last active ones)
+  int rb_off;           // row bases at rb_off of the problem's srow: subaperture (i, j) at srow[rb_off + i] + j
   float inv_sigma2;
   float inv_nM;
   float sum_cinv[4];    // sum over the mask of the 2x2 inverse blocks (row-major)
@@ -199,7 +201,7 @@ struct ProbDev {
   float* phiadj;   // A^T ... result N_c
   float* tmpa;     // coarse-block scratch (ping)
   float* tmpb;     // coarse-block scratch (pong)
-  float* sd;       // dense slopes
+  float* sd;       // slopes of the sensor stages (row-span layout, WfsDev::sp_off)
   float* vadj;     // corner-grid adjoint values
   float* part;     // tip/tilt partial sums
   float* pbuf0;    // search direction (ping)
@@ -211,6 +213,7 @@ struct ProbDev {
   const float* ftab;     // float tables
   const int* cmap;       // compact-index maps
   const unsigned char* amap;  // active flags (1 byte per subaperture, the maps' layout)
+  const int* srow;       // row bases of the row-span slope layout (WfsDev::rb_off)
   const float* cinv;     // 2x2 inverse noise blocks
   const GLPar* gl;       // [sensor][layer] propagation parameters
   // parameter gradients
@@ -224,7 +227,7 @@ struct ProbDev {
   // FP64 residual b - M x of refined solves
   double* a64;           // N_c: coefficients -> layers -> adjoint -> coefficients
   double* b64;           // N_c: pass scratch
-  double* sd64;          // dense slopes, as sd
+  double* sd64;          // slopes on the dense N x N grids (WfsDev::s_off)
   double* u64;           // corner grids, as vadj
   double* rslots;        // [upd slot][2]: sum r^2, sum b^2
   const double* cinv64;  // 2x2 inverse noise blocks, as cinv

@@ -15,12 +15,12 @@ enum { OUT_PHI = 0, OUT_USER = 1, OUT_FIT = 2 };
 enum { EPI_APPLYM = 0, EPI_PCG = 1, EPI_RHS = 2, EPI_PLAIN = 3, EPI_RHSQ = 4 };
 // propagation + Shack-Hartmann output
 //   PG_COMPACT : io.in -> compact slopes in io.out      (A x)
-//   PG_DENSE   : phi -> dense slopes + tip/tilt partials (inside M)
-//   PG_DENSE_IN: io.in -> dense slopes + partials
-//   PG_RESID_IN: dense slopes -= Gamma P io.in, + partials (data residual s - A x)
-//   PG_POL_IN  : dense slopes = compact io.in + Gamma P a_prev (state), + partials
+//   PG_DENSE   : phi -> slope buffer (row-span layout) + tip/tilt partials (inside M)
+//   PG_DENSE_IN: io.in -> slope buffer + partials
+//   PG_RESID_IN: slope buffer -= Gamma P io.in, + partials (data residual s - A x)
+//   PG_POL_IN  : slope buffer = compact io.in + Gamma P a_prev (state), + partials
 //                (closed loop: pseudo-open-loop slopes, two-step delay)
-//   PG_APREV   : dense slopes = Gamma P a_prev (state), + partials (the mirrors'
+//   PG_APREV   : slope buffer = Gamma P a_prev (state), + partials (the mirrors'
 //                part of the pseudo-open-loop slopes, before the measurement arrives)
 enum { PG_COMPACT = 0, PG_DENSE = 1, PG_DENSE_IN = 2, PG_RESID_IN = 3, PG_POL_IN = 4, PG_APREV = 5 };
 // Shack-Hartmann adjoint weighting
@@ -42,6 +42,8 @@ struct LaunchArgs {
   int n_hats;             // entries of hats
   const BandRec* bands;   // band records of the propagation adjoint (plan-wide)
   const PtEnt* pents;     // sensor lists of the propagation-adjoint tiles (plan-wide)
+  const int2* gtrows;     // Shack-Hartmann adjoint tiles: per window row (span base << 1 | active flag
+                          // of window column 32, active flags of window columns 0 .. 31), at tile.level
   int pt_rows;         // node rows per thread of the propagation adjoint (4 or 8)
   int pt_wide;         // 1: some pair has K > 3 corners per node (the kernel with wide records)
   int pt_split;        // 1: tiles of one band record, the sensor list split over the waves
@@ -56,8 +58,8 @@ void launch_idwt_glob(const LaunchArgs& a, const Tile* tiles, int ntiles, int sr
 void launch_fdwt_glob(const LaunchArgs& a, const Tile* tiles, int ntiles, int epi, int iter, int step);
 void launch_fdwt_res(const LaunchArgs& a, const Tile* tiles, int ntiles, int epi, int iter);
 void launch_pgamma(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode);
-// compact slopes io.in -> dense grid + tip/tilt partials; add = 1: added to the
-// dense grid's current values (closed loop after PG_APREV)
+// compact slopes io.in -> slope buffer + tip/tilt partials; add = 1: added to the
+// buffer's current values (closed loop after PG_APREV)
 void launch_slopes_in(const LaunchArgs& a, const Tile* tiles, int ntiles, int add = 0);
 void launch_gammaT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode);
 void launch_pT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode);

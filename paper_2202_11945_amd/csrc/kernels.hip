@@ -1511,7 +1511,7 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
   const bool own = threadIdx.x < kTileS * kTileS && i < N && j < N;
   typedef const int __attribute__((address_space(1)))* gptr_i;
   typedef const unsigned char __attribute__((address_space(1)))* gptr_u8;
-  int ci = -1;
+  int ci = -1, si = 0;
   bool isact = false;
   float dsx = 0.f, dsy = 0.f, cb0 = 0.f, cb1 = 0.f, cb2 = 0.f;
   if (own) {
@@ -1521,10 +1521,12 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
     } else {  // the active flag alone
       isact = ((gptr_u8)pr.amap)[w.m_off + i * N + j] != 0;
     }
+    si = ((gptr_i)pr.srow)[w.rb_off + i] + j;  // row-span position (valid when active)
     if (mode == PG_RESID_IN) {  // data residual s - A phi (s placed by the slopes input kernel)
-      const gptr_f sd = (gptr_f)(pr.sd + w.s_off);
-      dsx = sd[i * N + j];
-      dsy = sd[N * N + i * N + j];
+      const gptr_f sd = (gptr_f)(pr.sd + w.sp_off);
+      const int sc = min(max(si, 0), w.sp_len - 1);  // in range whatever the flag (used only when active)
+      dsx = sd[sc];
+      dsy = sd[w.sp_len + sc];
     } else if (mode == PG_POL_IN && ci >= 0) {  // measured slopes of the active subaperture
       dsx = ((gptr_f)io.in)[w.cs_off + ci];
       dsy = ((gptr_f)io.in)[w.cs_off + w.n_active + ci];
@@ -1644,9 +1646,9 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
     }
     return;
   }
-  if (own) {
-    ((gptr_w)pr.sd)[w.s_off + i * N + j] = sx;
-    ((gptr_w)pr.sd)[w.s_off + N * N + i * N + j] = sy;
+  if (act) {
+    ((gptr_w)pr.sd)[w.sp_off + si] = sx;
+    ((gptr_w)pr.sd)[w.sp_off + w.sp_len + si] = sy;
   }
   float a[4] = {sx, sy, cx, cy};
   block_sum4(a, sh, kSensThreads / 64);
@@ -1659,7 +1661,7 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
   }
 }
 
-// Compact input slopes -> dense grid, and the tip/tilt partial sums of every
+// Compact input slopes -> the row-span slope buffer, and the tip/tilt partial sums of every
 // 16 x 16 subaperture tile (the tiles of the propagation stage, whose sums
 // the sensor adjoint reads).  A workgroup takes 2 x 2 such tiles, thread t
 // subaperture (t / 16, t mod 16) of each, so all its loads are in flight
@@ -1677,23 +1679,25 @@ __global__ __launch_bounds__(256) void k_slopes_in(const ProbDev* P, const WfsDe
   const gptr_i cmap = (gptr_i)(pr.cmap + w.m_off);
   const gptr_f in = (gptr_f)io.in;
   const gptr_f cinv = (gptr_f)(pr.cinv + w.cinv_off);
-  const gptr_w sd = (gptr_w)(pr.sd + w.s_off);
+  const gptr_w sd = (gptr_w)(pr.sd + w.sp_off);
+  const gptr_i srow = (gptr_i)(pr.srow + w.rb_off);
   const int cs0 = w.cs_off, cs1 = w.cs_off + w.n_active;
-  int pos[4], ci[4];
+  int pos[4], ci[4], si[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int i = (2 * t.ty + (u >> 1)) * kTileS + li, j = (2 * t.tx + (u & 1)) * kTileS + lj;
     pos[u] = (i < N && j < N) ? i * N + j : -1;
     ci[u] = pos[u] >= 0 ? cmap[pos[u]] : -1;
+    si[u] = pos[u] >= 0 ? srow[i] + j : 0;  // row-span position (valid when active)
   }
   float sx[4], sy[4], c0[4], c1[4], c2[4], ox[4], oy[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     sx[u] = sy[u] = c0[u] = c1[u] = c2[u] = ox[u] = oy[u] = 0.f;
     if (ci[u] >= 0) {
-      if (add) {  // the mirrors' slope response already in the dense grid (closed loop)
-        ox[u] = ((gptr_f)sd)[pos[u]];
-        oy[u] = ((gptr_f)sd)[N * N + pos[u]];
+      if (add) {  // the mirrors' slope response already in the slope buffer (closed loop)
+        ox[u] = ((gptr_f)sd)[si[u]];
+        oy[u] = ((gptr_f)sd)[w.sp_len + si[u]];
       }
       sx[u] = in[cs0 + ci[u]];
       sy[u] = in[cs1 + ci[u]];
@@ -1715,9 +1719,9 @@ __global__ __launch_bounds__(256) void k_slopes_in(const ProbDev* P, const WfsDe
     a[4 * u + 1] = sy[u];
     a[4 * u + 2] = c0[u] * sx[u] + c1[u] * sy[u];
     a[4 * u + 3] = c1[u] * sx[u] + c2[u] * sy[u];
-    if (pos[u] >= 0) {
-      sd[pos[u]] = sx[u];
-      sd[N * N + pos[u]] = sy[u];
+    if (ci[u] >= 0) {
+      sd[si[u]] = sx[u];
+      sd[w.sp_len + si[u]] = sy[u];
     }
   }
   block_sumk<16>(a, sh, 4);
@@ -1738,12 +1742,15 @@ __global__ __launch_bounds__(256) void k_slopes_in(const ProbDev* P, const WfsDe
 // ------------------------------------- noise weighting + Shack-Hartmann adjoint
 // Tile of 32x32 corners (4 per thread); the weighted slopes of the 33x33
 // subapertures that touch them are formed in LDS (thread t takes window
-// entries t, t + 256, ...), all their loads in flight together:
+// entries t, t + 256, ...), all their loads in flight together.  The
+// window's rows come from the tile's row table (span base, active flags),
+// read with the tile, so only active subapertures' slopes are loaded:
 // C_hat^{-1} = (I - T) C^{-1} (I - T) for LGS with tip/tilt removal (means
 // from the per-tile partial sums, Sec. 3.2), C^{-1} otherwise; GT_PLAIN
 // applies Gamma^T alone.  The subaperture operands are requested before the
 // means are reduced.
-__global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* WD, const Tile* tiles, int mode) {
+__global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* WD, const Tile* tiles,
+                                                const int2* rows, int mode) {
   constexpr int SW = kGtS + 1;                    // subaperture window of the tile
   constexpr int kR = (SW * SW + 255) / 256;       // window elements per thread
   constexpr int kC = kGtS * kGtS / 256;           // corners per thread
@@ -1757,9 +1764,16 @@ __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* 
   const int N = w.N, nc = w.nc;
   const bool weighted = mode == GT_WEIGHTED;
   const int ci0 = t.ty * kGtS, cj0 = t.tx * kGtS;
-  const gptr_f sd = (gptr_f)(pr.sd + w.s_off);
-  typedef const unsigned char __attribute__((address_space(1)))* gptr_u8;
-  const gptr_u8 amap = (gptr_u8)(pr.amap + w.m_off);
+  const gptr_f sd = (gptr_f)(pr.sd + w.sp_off);
+  typedef int v2i __attribute__((ext_vector_type(2)));
+  typedef const v2i __attribute__((address_space(1)))* gptr_i2;
+  v2i rw[kR];
+#pragma unroll
+  for (int u = 0; u < kR; ++u) {
+    const int e = threadIdx.x + u * 256;
+    rw[u] = v2i{0, 0};
+    if (e < SW * SW) rw[u] = ((gptr_i2)rows)[t.level + e / SW];
+  }
   bool act[kR];
   float sx[kR], sy[kR], cb0[kR], cb1[kR], cb2[kR];
 #pragma unroll
@@ -1770,10 +1784,14 @@ __global__ __launch_bounds__(256) void k_gammaT(const ProbDev* P, const WfsDev* 
     if (e < SW * SW) {
       const int li = e / SW, lj = e - li * SW;
       const int i = ci0 - 1 + li, j = cj0 - 1 + lj;  // subaperture
+      // flags of columns 0 .. 31 in .y, of column 32 in bit 0 of .x (inactive outside the grid)
+      act[u] = lj < 32 ? ((unsigned)rw[u].y >> lj) & 1u : rw[u].x & 1;
+      if (act[u]) {
+        const int si = (rw[u].x >> 1) + j;  // row-span position
+        sx[u] = sd[si];
+        sy[u] = sd[w.sp_len + si];
+      }
       if (i >= 0 && j >= 0 && i < N && j < N) {
-        act[u] = amap[i * N + j] != 0;
-        sx[u] = sd[i * N + j];
-        sy[u] = sd[N * N + i * N + j];
         if (weighted && w.blocks) {
           const gptr_f cb = (gptr_f)(pr.cinv + w.cinv_off + 3 * (i * N + j));
           cb0[u] = cb[0];
@@ -2975,7 +2993,7 @@ void launch_slopes_in(const LaunchArgs& a, const Tile* tiles, int ntiles, int ad
   if (ntiles > 0) k_slopes_in<<<ntiles, 256, 0, a.stream>>>(a.P, a.W, a.IO, tiles, add);
 }
 void launch_gammaT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
-  if (ntiles > 0) k_gammaT<<<ntiles, 256, 0, a.stream>>>(a.P, a.W, tiles, mode);
+  if (ntiles > 0) k_gammaT<<<ntiles, 256, 0, a.stream>>>(a.P, a.W, tiles, a.gtrows, mode);
 }
 void launch_pT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
   if (ntiles <= 0) return;
