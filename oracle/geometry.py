@@ -4,7 +4,8 @@
   x_j = -D/2 + j d, y_i = -D/2 + i d (i, j = 0..N); subaperture (i, j) spans
   corners (i..i+1, j..j+1); rows = y, columns = x, row-major.
 * Active subaperture: its centre lies in the annulus [sqrt(obs) D/2, D/2]
-  (obs = obstructed area fraction).
+  (obs = obstructed area fraction), unless the sensor's configuration gives
+  its own N x N mask (the set M_g of the slope model is then that mask).
 * Layer l: n_l x n_l nodes on a centred square of side L; delta_l = L/n_l;
   node (p, q) at (x, y) = (-L/2 + q delta_l, -L/2 + p delta_l).
 """
@@ -43,7 +44,9 @@ class Geometry:
     def __init__(self, cfg):
         self.cfg = cfg
         self.D = cfg["D"]
-        self.masks = [subap_mask(self.D, w["n_subap"], cfg["obstruction"]) for w in cfg["wfs"]]
+        self.masks = [np.asarray(w["mask"], dtype=bool).reshape(w["n_subap"], w["n_subap"])
+                      if w.get("mask") is not None else subap_mask(self.D, w["n_subap"], cfg["obstruction"])
+                      for w in cfg["wfs"]]
         self.n_active = [int(m.sum()) for m in self.masks]
         self.n_slopes = [2 * a for a in self.n_active]
         self.delta = layer_spacing(cfg)

@@ -39,6 +39,38 @@ def _ops(gpu_lib, S, cfg, key):
     return ctx
 
 
+def _irregular_masks(cfg, key):
+    """Configured masks with holes on every LGS: the annulus minus a random
+    fifth of its subapertures, a whole row, a gap that leaves a row two runs,
+    and rows whose active span starts or ends at the sensor adjoint's
+    32-column tile edge (a tile window's halo column)."""
+    from oracle.geometry import subap_mask
+    rng = np.random.default_rng(key)
+    for w in cfg["wfs"]:
+        if w["kind"] != "lgs":
+            continue
+        N = w["n_subap"]
+        m = subap_mask(cfg["D"], N, cfg["obstruction"]) & (rng.random((N, N)) > 0.2)
+        m[N // 3, :] = False
+        m[N // 2, 5:N // 2] = False
+        m[N // 4, :31] = False
+        m[N // 4 + 1, 33:] = False
+        m[N // 4 + 2, :32] = False
+        m[N // 4 + 3, 32:] = False
+        w["mask"] = m.astype(np.uint8)
+
+
+def test_irregular_masks(gpu_lib):
+    # the sensor stages' row-span slope layout and the adjoint tiles' row
+    # tables on masks with holes, split rows and spans at tile edges
+    cfg = get_config("maory_like")
+    _irregular_masks(cfg, 7)
+    S = system("maory_like_holes", cfg)
+    assert S.geom.n_active[0] < 4476 * 0.85
+    ctx = _ops(gpu_lib, S, cfg, 9)
+    _check_frame(gpu_lib, S, ctx, np.zeros(5 * S.geom.n_coeff, np.float32), synth_slopes(S, 0))
+
+
 def test_elongated_block_noise(gpu_lib):
     cfg = get_config("small")
     cfg["noise"]["alpha_eta"] = 0.6

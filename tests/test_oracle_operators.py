@@ -22,6 +22,36 @@ def test_mask_hand_counts():
     assert np.array_equal(m, m.T) and np.array_equal(m, m[::-1]) and np.array_equal(m, m[:, ::-1])
 
 
+def test_configured_mask_selects_subapertures():
+    # a sensor's configured mask replaces the annulus rule (the set M_g of
+    # Sec. 2): the annulus itself as a mask gives the same A, and a mask with
+    # subapertures removed gives exactly the rows of the kept ones, in the
+    # same row-major order, for s^x and s^y
+    base = get_config("small")
+    S0 = System(base)
+    N = base["wfs"][0]["n_subap"]
+    ann = subap_mask(base["D"], N, base["obstruction"])
+    same = get_config("small")
+    same["wfs"][0]["mask"] = ann.astype(np.uint8)
+    assert (System(same).A != S0.A).nnz == 0
+    m = ann.copy()
+    m[3, :] = False          # a whole row
+    m[10, 2:9] = False       # a gap: the row keeps two runs
+    m[[5, 7, 14], [12, 4, 9]] = False
+    cut = get_config("small")
+    cut["wfs"][0]["mask"] = m.astype(np.uint8)
+    S1 = System(cut)
+    nM0, nM1 = int(ann.sum()), int(m.sum())
+    assert S1.geom.n_active[0] == nM1 and S1.geom.slope_off[1] == 2 * nM1
+    keep = m[ann]  # kept subapertures among the annulus's, row-major
+    A0 = S0.A.tocsr()[:2 * nM0].toarray()
+    A1 = S1.A.tocsr()[:2 * nM1].toarray()
+    assert np.array_equal(A1[:nM1], A0[:nM0][keep])
+    assert np.array_equal(A1[nM1:], A0[nM0:][keep])
+    # the other sensors are untouched
+    assert (S1.A.tocsr()[2 * nM1:] != S0.A.tocsr()[2 * nM0:]).nnz == 0
+
+
 def _corner_field(N, D, f):
     x = corners_1d(D, N)
     X, Y = np.meshgrid(x, x)  # X along columns j, Y along rows i
