@@ -181,11 +181,6 @@ __device__ __forceinline__ const double* rho_slots(const ProbDev& pr, int k, int
   n = rho_count(pr, k);
   return dot_group(pr, rho_grp(k));
 }
-__device__ __forceinline__ double rho_sum(const ProbDev& pr, int k) {
-  int n;
-  const double* s = rho_slots(pr, k, n);
-  return wave_sum_slots(s, n);
-}
 // rho_k and rho_{k-1} with their loads in flight together
 __device__ __forceinline__ void rho_sum2(const ProbDev& pr, int k, double& rk, double& rkm) {
   int n0, n1;
@@ -244,17 +239,10 @@ __device__ __forceinline__ float coef_finish(const PSrc& s, int e, const CoefLoa
   return p;
 }
 
-// beta_k = rho_k / rho_{k-1}, summed by every wave itself in the same fixed
-// order (no barrier, identical in every wave); called after the wave's
-// coefficient loads are in flight, so both latencies overlap
-__device__ __forceinline__ float wave_beta(const ProbDev& pr, int mode, int iter) {
-  if (mode != SRC_PUPD) return 0.f;
-  double rk, rkm;
-  rho_sum2(pr, iter, rk, rkm);
-  return (float)((rkm != 0.0) ? rk / rkm : 0.0);
-}
-// The same beta in two phases (see slots_issue): beta_issue before a
-// kernel's coefficient loads, beta_reduce once they are in flight.
+// beta_k = rho_k / rho_{k-1} in two phases (see slots_issue): beta_issue
+// before a kernel's coefficient loads, beta_reduce once they are in flight;
+// every wave sums the slots itself in the same fixed order (no barrier, the
+// same value in every wave).
 template <int H>
 struct BetaLoads {
   const double* s[2];
