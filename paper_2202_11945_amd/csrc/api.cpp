@@ -1409,7 +1409,10 @@ void enq_frame_body(const Plan& P, const LaunchArgs& a, int iters, bool refresh)
     enq_idwt(P, a, k == 0 ? SRC_PUPD0 : SRC_PUPD, OUT_PHI, k);
     enq_apply_M_core(P, a);
     enq_fdwt(P, a, EPI_PCG, k);
-    launch_update(a, T(P, P.upd), P.upd.n, k);
+    // x updates in pairs of steps (bitwise the sequential ones): even steps
+    // leave theirs to the next, odd steps take both; a last even step its own
+    const int xm = (k & 1) ? UPD_X_PAIR : (k + 1 < iters ? UPD_X_DEFER : UPD_X_ONE);
+    launch_update(a, T(P, P.upd), P.upd.n, k, nullptr, xm);
   }
   launch_aug_store(a, T(P, P.aug), P.aug.n, iters);  // the next frame's W and A W
   enq_idwt(P, a, SRC_STATE_C, OUT_FIT, 0);

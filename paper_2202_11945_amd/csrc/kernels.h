@@ -63,8 +63,13 @@ void launch_pgamma(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode)
 void launch_slopes_in(const LaunchArgs& a, const Tile* tiles, int ntiles, int add = 0);
 void launch_gammaT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode);
 void launch_pT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode);
+// x update of a PCG step: x += a_k p_k (ONE); none, left to the next step
+// (DEFER); x += a_{k-1} p_{k-1} + a_k p_k, the previous step's deferred one
+// first (PAIR; iter >= 1, C null)
+enum { UPD_X_ONE = 0, UPD_X_DEFER = 1, UPD_X_PAIR = 2 };
 // C: the coarse-level correction of a converged solve (rho includes it), else null
-void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter, const CoarseDev* C = nullptr);
+void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter, const CoarseDev* C = nullptr,
+                   int xm = UPD_X_ONE);
 // converged solves' coarse-level correction: y = E^{-1} Z^T r_k (tiles: problem x row block)
 void launch_coarse(const LaunchArgs& a, const CoarseDev* C, const Tile* tiles, int ntiles, int k);
 // p_k = J^{-1} r_k + Z y + beta_k p_{k-1} over the vector-update chunks

@@ -2507,6 +2507,14 @@ __device__ __forceinline__ const double* coarse_slots(const CoarseDev& c, int k)
   return c.slots + (long)(k & (kDotRing - 1)) * c.n_slots;
 }
 
+// XM: the x update of this step.  UPD_X_ONE: x += a_k p_k.  A frame takes
+// two steps' x updates in one pass (the search directions p_{k-1} and p_k
+// are both still held): UPD_X_DEFER leaves x for the next step, which as
+// UPD_X_PAIR forms x += a_{k-1} p_{k-1}, then += a_k p_k: the same two
+// rounded products and sums in the same order (bitwise the same x), with
+// a_{k-1} summed again from the same slots; 8 of every 56 bytes per
+// coefficient less over the pair.
+template <int XM>
 __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* IO, const Tile* tiles, int iter,
                                                 const CoarseDev* C) {
   __shared__ double sh[4];
@@ -2514,6 +2522,7 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
   const ProbDev& pr = P[t.prob];
   const IoDev& io = IO[t.prob];
   const gptr_f4 p = (gptr_f4)p_loc(pr, iter);
+  const gptr_f4 pm = (gptr_f4)p_loc(pr, iter - 1);
   const gptr_f4 q = (gptr_f4)q_loc(pr, iter);
   const gptr_f4 jv = (gptr_f4)pr.jinv;
   const gptr_w4 x = (gptr_w4)io.state;
@@ -2522,32 +2531,41 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
   const int e1 = min(e0 + kUpdChunk / 4, pr.n_c / 4);
   double acc = 0.0;
   constexpr int V = kUpdChunk / 4 / 256;  // float4 per thread
-  v4f xp[V], pp[V], rr[V], qq[V], jj[V], rnv[V];
-  // rho_k (plus the coarse correction's part in a converged solve) and pi_k:
-  // slot loads first, summed by every wave itself in the same fixed order
-  // (no barrier) while its vector loads are in flight
-  int nr;
+  v4f xp[V], pp[V], pq[V], rr[V], qq[V], jj[V], rnv[V];
+  // rho_k (plus the coarse correction's part in a converged solve) and pi_k
+  // (for a pair also rho_{k-1} and pi_{k-1}): slot loads first, summed by
+  // every wave itself in the same fixed order (no barrier) while its vector
+  // loads are in flight
+  int nr, nrm = 0;
   const double* sr = rho_slots(pr, iter, nr);
-  const double* const sl[3] = {sr, dot_group(pr, pi_grp(iter)), C ? coarse_slots(C[t.prob], iter) : sr};
-  const int nn[3] = {nr, pr.n_slots_fdwt, C ? C[t.prob].n_slots : 0};
-  SlotLoads<3, 2> sloads;
-  slots_issue<3, 2>(sl, nn, sloads);
+  const double* srm = XM == UPD_X_PAIR ? rho_slots(pr, iter - 1, nrm) : sr;
+  const double* const sl[5] = {sr, dot_group(pr, pi_grp(iter)), C ? coarse_slots(C[t.prob], iter) : sr, srm,
+                               XM == UPD_X_PAIR ? dot_group(pr, pi_grp(iter - 1)) : sr};
+  const int nn[5] = {nr, pr.n_slots_fdwt, C ? C[t.prob].n_slots : 0, nrm, XM == UPD_X_PAIR ? pr.n_slots_fdwt : 0};
+  SlotLoads<5, 2> sloads;
+  slots_issue<5, 2>(sl, nn, sloads);
 #pragma unroll
   for (int u = 0; u < V; ++u) {
     const int e = e0 + threadIdx.x + u * 256;
     if (e < e1) {
-      xp[u] = x[e];
-      pp[u] = p[e];
+      if (XM != UPD_X_DEFER) {
+        xp[u] = x[e];
+        pp[u] = p[e];
+      }
+      if (XM == UPD_X_PAIR) pq[u] = pm[e];
       rr[u] = r[e];
       qq[u] = q[e];
       jj[u] = jv[e];
     }
   }
   // alpha = rho_k / pi_k
-  double o[3];
-  slots_reduce<3, 2>(sl, nn, sloads, o);
+  double o[5];
+  slots_reduce<5, 2>(sl, nn, sloads, o);
   const double rho = o[0] + o[2], pi = o[1];
   const float a = (float)((pi > 0.0) ? rho / pi : 0.0);
+  // a_{k-1} as the previous step formed it (a frame's steps have no coarse part)
+  const double rhom = o[3] + 0.0, pim = o[4];
+  const float am = (float)((pim > 0.0) ? rhom / pim : 0.0);
   // breakdown: a nonzero residual with p^T M p <= 0 (M is positive definite,
   // so only rounding or non-finite inputs get here), or a negative or
   // non-finite rho; the step then leaves x and r unchanged (alpha = 0) and
@@ -2559,15 +2577,23 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
     const int e = e0 + threadIdx.x + u * 256;
     if (e < e1) {
       v4f xn, rn;
-      xn.x = fmaf(a, pp[u].x, xp[u].x);
-      xn.y = fmaf(a, pp[u].y, xp[u].y);
-      xn.z = fmaf(a, pp[u].z, xp[u].z);
-      xn.w = fmaf(a, pp[u].w, xp[u].w);
+      if (XM == UPD_X_PAIR) {
+        xp[u].x = fmaf(am, pq[u].x, xp[u].x);
+        xp[u].y = fmaf(am, pq[u].y, xp[u].y);
+        xp[u].z = fmaf(am, pq[u].z, xp[u].z);
+        xp[u].w = fmaf(am, pq[u].w, xp[u].w);
+      }
+      if (XM != UPD_X_DEFER) {
+        xn.x = fmaf(a, pp[u].x, xp[u].x);
+        xn.y = fmaf(a, pp[u].y, xp[u].y);
+        xn.z = fmaf(a, pp[u].z, xp[u].z);
+        xn.w = fmaf(a, pp[u].w, xp[u].w);
+        x[e] = xn;
+      }
       rn.x = fmaf(-a, qq[u].x, rr[u].x);
       rn.y = fmaf(-a, qq[u].y, rr[u].y);
       rn.z = fmaf(-a, qq[u].z, rr[u].z);
       rn.w = fmaf(-a, qq[u].w, rr[u].w);
-      x[e] = xn;
       r[e] = rn;
       rnv[u] = rn;
       acc += (double)rn.x * (double)rn.x * (double)jj[u].x;
@@ -3005,8 +3031,14 @@ void launch_pT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
   }
 #undef FEWHA_PT
 }
-void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter, const CoarseDev* C) {
-  if (ntiles > 0) k_update<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles, iter, C);
+void launch_update(const LaunchArgs& a, const Tile* tiles, int ntiles, int iter, const CoarseDev* C, int xm) {
+  if (ntiles <= 0) return;
+  if (xm == UPD_X_DEFER)
+    k_update<UPD_X_DEFER><<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles, iter, C);
+  else if (xm == UPD_X_PAIR)
+    k_update<UPD_X_PAIR><<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles, iter, C);
+  else
+    k_update<UPD_X_ONE><<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, tiles, iter, C);
 }
 void launch_coarse(const LaunchArgs& a, const CoarseDev* C, const Tile* tiles, int ntiles, int k) {
   if (ntiles > 0) k_coarse<<<ntiles, 256, 0, a.stream>>>(a.P, a.IO, C, tiles, k);
