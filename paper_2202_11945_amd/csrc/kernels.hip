@@ -2522,7 +2522,7 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
   const ProbDev& pr = P[t.prob];
   const IoDev& io = IO[t.prob];
   const gptr_f4 p = (gptr_f4)p_loc(pr, iter);
-  const gptr_f4 pm = (gptr_f4)p_loc(pr, iter - 1);
+  const gptr_f4 pm = (gptr_f4)p_loc(pr, XM == UPD_X_PAIR ? iter - 1 : iter);  // p_{k-1}: pairs only
   const gptr_f4 q = (gptr_f4)q_loc(pr, iter);
   const gptr_f4 jv = (gptr_f4)pr.jinv;
   const gptr_w4 x = (gptr_w4)io.state;
