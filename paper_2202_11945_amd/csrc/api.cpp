@@ -87,6 +87,7 @@ struct Plan {
   const BandRec* dBand = nullptr;            // band records of the propagation adjoint
   const PtEnt* dPtE = nullptr;               // sensor lists of the propagation-adjoint tiles
   const int2* dGtr = nullptr;                // window rows of the Shack-Hartmann adjoint tiles
+  const int2* dPgr = nullptr;                // tables of the propagation-stage tiles
   std::vector<float*> sstate;                // per problem: [x | unused | r] of a solve
   double* rho_host = nullptr;                // pinned readback: 2 n_dots doubles per problem
   std::vector<long> rho_off;
@@ -477,6 +478,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   std::vector<std::vector<int>> itab(P.nprob), cmap(P.nprob), gitab(P.nprob);
   std::vector<std::vector<int>> srow(P.nprob);  // row bases of the row-span slope layout
   std::vector<int2> gtrows;                     // Shack-Hartmann adjoint tiles' window rows (plan-wide)
+  std::vector<int2> pgrows;                     // propagation-stage tiles' tables (plan-wide)
   static_assert(kGtS == 32, "a window row's 33 active flags: 32 bits and the base's low bit");
   std::vector<std::vector<float>> ftab(P.nprob), cinv(P.nprob), jinv(P.nprob), gftab(P.nprob);
   std::vector<std::vector<GLPar>> glp(P.nprob);
@@ -723,10 +725,30 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     for (int g = 0; g < G; ++g) t_r64wfs.push_back({k, g, 0, 0, 0, 0, 0, 0});
     for (int g = 0; g < G; ++g) {
       const WfsDev& wd = P.hW[pd.wfs0 + g];
+      // propagation-stage tiles with their own tables (per layer the window's
+      // 17 corner rows, then its 17 columns: cell index and fraction)
       for (int ty = 0; ty < wd.tiles_side; ++ty)
         for (int tx = 0; tx < wd.tiles_side; ++tx) {
-          t_pg.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
-          if (m.closed) t_pgpol.push_back({k, g, ty, tx, pd.wfs0 + g, 0, pd.layer0, 0});
+          const int off = (int)pgrows.size();
+          t_pg.push_back({k, g, ty, tx, pd.wfs0 + g, off, pd.layer0, 0});
+          if (m.closed) t_pgpol.push_back({k, g, ty, tx, pd.wfs0 + g, off, pd.layer0, 0});
+          for (int l = 0; l < L; ++l) {
+            const GLTables& tb = m.tab[g][l];
+            auto entry = [](int cell, double f) {
+              const float ff = (float)f;
+              int bits;
+              std::memcpy(&bits, &ff, sizeof bits);
+              return make_int2(cell, bits);
+            };
+            for (int c = 0; c <= kTileS; ++c) {
+              const int ic = ty * kTileS + c;
+              pgrows.push_back(ic < wd.nc ? entry(tb.q0y[ic], tb.wy[ic]) : make_int2(0, 0));
+            }
+            for (int c = 0; c <= kTileS; ++c) {
+              const int jc = tx * kTileS + c;
+              pgrows.push_back(jc < wd.nc ? entry(tb.q0x[jc], tb.wx[jc]) : make_int2(0, 0));
+            }
+          }
         }
       const int sg = cdiv(wd.tiles_side, 2);
       if (k == 0) P.sin_g.push_back((int)t_sin.size());
@@ -1013,6 +1035,7 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
   const size_t oBand = cv.take(sizeof(BandRec) * hats.bands.size());
   const size_t oPtE = cv.take(sizeof(PtEnt) * std::max<size_t>(ptl.ents.size(), 1));
   const size_t oGtr = cv.take(sizeof(int2) * std::max<size_t>(gtrows.size(), 1));
+  const size_t oPgr = cv.take(sizeof(int2) * std::max<size_t>(pgrows.size(), 1));
   const size_t oF = cv.take(sizeof(FitDev) * std::max<size_t>(hF.size(), 1));
   const size_t oPna = cv.take(sizeof(ProbDev) * P.nprob_all);
   const size_t oT = cv.take(sizeof(Tile) * std::max<size_t>(P.hT.size(), 1));
@@ -1140,6 +1163,9 @@ fewha_status build_plan(Plan*& out, const std::vector<const HostModel*>& models,
     HIP_TRY(hipMemcpy(base + oHat, hats.hats.data(), sizeof(HatEnt) * hats.hats.size(), hipMemcpyHostToDevice));
   if (!hats.bands.empty())
     HIP_TRY(hipMemcpy(base + oBand, hats.bands.data(), sizeof(BandRec) * hats.bands.size(), hipMemcpyHostToDevice));
+  P.dPgr = (const int2*)(base + oPgr);
+  if (!pgrows.empty())
+    HIP_TRY(hipMemcpy(base + oPgr, pgrows.data(), sizeof(int2) * pgrows.size(), hipMemcpyHostToDevice));
   P.dGtr = (const int2*)(base + oGtr);
   if (!gtrows.empty())
     HIP_TRY(hipMemcpy(base + oGtr, gtrows.data(), sizeof(int2) * gtrows.size(), hipMemcpyHostToDevice));
@@ -1347,6 +1373,7 @@ LaunchArgs args(const Plan& P, hipStream_t s, const IoDev* io) {
   a.bands = P.dBand;
   a.pents = P.dPtE;
   a.gtrows = P.dGtr;
+  a.pgrows = P.dPgr;
   return a;
 }
 

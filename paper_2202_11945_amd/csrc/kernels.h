@@ -42,6 +42,8 @@ struct LaunchArgs {
   int n_hats;             // entries of hats
   const BandRec* bands;   // band records of the propagation adjoint (plan-wide)
   const PtEnt* pents;     // sensor lists of the propagation-adjoint tiles (plan-wide)
+  const int2* pgrows;     // propagation-stage tiles: per layer, (cell row, fraction) of the 17 window rows,
+                          // then (cell column, fraction) of the 17 columns, at tile.level
   const int2* gtrows;     // Shack-Hartmann adjoint tiles: per window row (span base << 1 | active flag
                           // of window column 32, active flags of window columns 0 .. 31), at tile.level
   int pt_rows;         // node rows per thread of the propagation adjoint (4 or 8)

@@ -1476,11 +1476,16 @@ static_assert((kTileS + 1) * (kTileS + 1) <= 2 * kSensThreads, "17 x 17 window i
 // Tile of 16x16 subapertures of one sensor: v on the 17x17 corners is the
 // sum over layers of the bilinear interpolant (LGS cone factor in the
 // tables), then s^x, s^y per active subaperture (Sec. 2).  The subaperture
-// operands are requested first; the layers go in groups of four (all table
+// operands are requested first; the layers go in groups of three (all table
 // loads of a group, then all node loads), so a corner waits on two memory
-// round trips per four layers.
+// round trips per three layers.  The tables are the tile's own (rows, at
+// tile.level: per layer the 17 window rows' (cell row, fraction), then the
+// 17 columns'), addressed from the tile alone, so they are requested with
+// the descriptors.
+constexpr int kLG = 3;  // layers per group of table and node loads
+template <int mode>
 __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_pgamma(const ProbDev* P, const LayerDev* LD, const WfsDev* WD,
-                                                         const IoDev* IO, const Tile* tiles, int mode) {
+                                                         const IoDev* IO, const Tile* tiles, const int2* rows) {
   constexpr int CW = kTileS + 1;
   __shared__ float V[CW * CW];
   __shared__ float sh[4 * (kSensThreads / 64)];
@@ -1540,13 +1545,11 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
     const int lci = e / CW, lcj = e - lci * CW;
     const int ic = i0 + lci, jc = j0 + lcj;
     cin[u] = e < CW * CW && ic < nc && jc < nc;
-    vi[u] = ic * (int)sizeof(float);
-    vj[u] = jc * (int)sizeof(float);
+    vi[u] = lci * (int)sizeof(int2);         // the corner's row entry of a layer's tables
+    vj[u] = (CW + lcj) * (int)sizeof(int2);  // and its column entry
   }
-  const __amdgpu_buffer_rsrc_t irs =
-      __builtin_amdgcn_make_buffer_rsrc((void*)(pr.itab + w.tab_off), (short)0, 0x7fffffff, 0x00020000);
-  const __amdgpu_buffer_rsrc_t frs =
-      __builtin_amdgcn_make_buffer_rsrc((void*)(pr.ftab + w.tab_off), (short)0, 0x7fffffff, 0x00020000);
+  const __amdgpu_buffer_rsrc_t trs =  // this tile's tables
+      __builtin_amdgcn_make_buffer_rsrc((void*)(rows + t.level), (short)0, 0x7fffffff, 0x00020000);
   const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc((void*)phi, (short)0, 0x7fffffff, 0x00020000);
   auto ld = [](__amdgpu_buffer_rsrc_t rs, int vo, int so) {  // so: wave-uniform (stated, or the
     return __builtin_amdgcn_raw_buffer_load_b32(rs, vo, __builtin_amdgcn_readfirstlane(so), 0);  // load loops)
@@ -1554,35 +1557,37 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
   float v[kCorn];
 #pragma unroll
   for (int u = 0; u < kCorn; ++u) v[u] = 0.f;
-  for (int l0 = 0; l0 < pr.L; l0 += 4) {
-    int lof[4], nl[4], tb[4];
+  for (int l0 = 0; l0 < pr.L; l0 += kLG) {
+    int lof[kLG], nl[kLG];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kLG; ++k) {
       const int l = min(l0 + k, pr.L - 1);
       const LayerDev& ly = LD[t.mask + l];
       lof[k] = ly.off;
       nl[k] = ly.n;
-      tb[k] = l * w.tab_stride * (int)sizeof(float);
     }
-    int cell[kCorn][4];
-    float wy[kCorn][4], wx[kCorn][4];
+    int cell[kCorn][kLG];
+    float wy[kCorn][kLG], wx[kCorn][kLG];
 #pragma unroll
     for (int u = 0; u < kCorn; ++u)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < kLG; ++k) {
         cell[u][k] = 0;
         wy[u][k] = wx[u][k] = 0.f;
         if (cin[u] && l0 + k < pr.L) {
-          cell[u][k] = lof[k] + (int)ld(irs, vi[u], tb[k]) * nl[k] + (int)ld(irs, vj[u], tb[k] + nc * (int)sizeof(float));
-          wy[u][k] = __uint_as_float(ld(frs, vi[u], tb[k] + 2 * nc * (int)sizeof(float)));
-          wx[u][k] = __uint_as_float(ld(frs, vj[u], tb[k] + 3 * nc * (int)sizeof(float)));
+          const int so = (l0 + k) * 2 * CW * (int)sizeof(int2);
+          const auto ry = __builtin_amdgcn_raw_buffer_load_b64(trs, vi[u], __builtin_amdgcn_readfirstlane(so), 0);
+          const auto rx = __builtin_amdgcn_raw_buffer_load_b64(trs, vj[u], __builtin_amdgcn_readfirstlane(so), 0);
+          cell[u][k] = lof[k] + (int)ry[0] * nl[k] + (int)rx[0];
+          wy[u][k] = __uint_as_float(ry[1]);
+          wx[u][k] = __uint_as_float(rx[1]);
         }
       }
-    float nd[kCorn][4][4];
+    float nd[kCorn][kLG][4];
 #pragma unroll
     for (int u = 0; u < kCorn; ++u)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < kLG; ++k) {
         nd[u][k][0] = nd[u][k][1] = nd[u][k][2] = nd[u][k][3] = 0.f;
         if (cin[u] && l0 + k < pr.L) {
           const int vo = cell[u][k] * (int)sizeof(float), so = nl[k] * (int)sizeof(float);
@@ -1595,7 +1600,7 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
 #pragma unroll
     for (int u = 0; u < kCorn; ++u)
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
+      for (int k = 0; k < kLG; ++k)
         if (cin[u] && l0 + k < pr.L) {
           const float top = (1.f - wx[u][k]) * nd[u][k][0] + wx[u][k] * nd[u][k][1];
           const float bot = (1.f - wx[u][k]) * nd[u][k][2] + wx[u][k] * nd[u][k][3];
@@ -3001,7 +3006,17 @@ void launch_fdwt_res(const LaunchArgs& a, const Tile* tiles, int ntiles, int epi
     launch_fdwt_res_r<128>(a, tiles, ntiles, epi, iter);
 }
 void launch_pgamma(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
-  if (ntiles > 0) k_pgamma<<<ntiles, kSensThreads, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, mode);
+  if (ntiles <= 0) return;
+#define FEWHA_PG(M) k_pgamma<M><<<ntiles, kSensThreads, 0, a.stream>>>(a.P, a.L, a.W, a.IO, tiles, a.pgrows)
+  switch (mode) {
+    case PG_COMPACT: FEWHA_PG(PG_COMPACT); break;
+    case PG_DENSE: FEWHA_PG(PG_DENSE); break;
+    case PG_DENSE_IN: FEWHA_PG(PG_DENSE_IN); break;
+    case PG_RESID_IN: FEWHA_PG(PG_RESID_IN); break;
+    case PG_POL_IN: FEWHA_PG(PG_POL_IN); break;
+    default: FEWHA_PG(PG_APREV); break;
+  }
+#undef FEWHA_PG
 }
 void launch_slopes_in(const LaunchArgs& a, const Tile* tiles, int ntiles, int add) {
   if (ntiles > 0) k_slopes_in<<<ntiles, 256, 0, a.stream>>>(a.P, a.W, a.IO, tiles, add);
