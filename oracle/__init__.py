@@ -31,6 +31,8 @@ Parity status per function:
   the closed forms, invariants and brute-force checks in tests/test_oracle_*.py.
 * D (the diagonal prior): the paper does not print its formula (it cites
   another paper).  The von Karman spectrum evaluated at the level frequency
-  2^j / L is used.  Its level ratios are pinned in the Kolmogorov limit, its
-  absolute scale is parity unpinned.
+  2^j / L is used.  Its level ratios are pinned in the Kolmogorov limit, and
+  the spectrum's absolute scale and outer-scale term by the textbook
+  Kolmogorov structure function and von Karman phase variance; which
+  frequency stands for level j (2^j / L) is parity unpinned.
 """

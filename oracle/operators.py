@@ -143,7 +143,8 @@ def tt_vectors(nM):
 def prior_diagonal(cfg, l):
     """D_l over the Mallat positions of layer l: the inverse von Karman
     spectrum 0.023 gamma_l r0^{-5/3} (f^2 + L0^{-2})^{-11/6} at the level
-    frequency f_j = 2^j / L (parity unpinned: formula not in the paper)."""
+    frequency f_j = 2^j / L (the formula is not in the paper: the spectrum is
+    pinned by turbulence statistics, the level frequency is parity unpinned)."""
     layer = cfg["layers"][l]
     pr = cfg["prior"]
     j = level_index(layer["n"], layer["levels"])

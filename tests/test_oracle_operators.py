@@ -217,6 +217,45 @@ def test_elongated_noise_blocks_sherman_morrison():
                        sig2 * (1.0 + kap * np.sum(beta * beta, 1))[:, None] * beta)
 
 
+def _prior_psd(f, r0, L0):
+    # the oracle's spectrum at one frequency: a 2 x 2 layer with one level has
+    # every coefficient at f = 1 / domain side, and D = 1 / psd there
+    from oracle.operators import prior_diagonal
+    cfg = {"layers": [{"n": 2, "levels": 1, "cn2": 1.0, "h": 0.0}],
+           "prior": {"r0": r0, "L0": L0, "alpha": 1.0, "tau": 0.0}, "domain_side": 1.0 / f}
+    return 1.0 / prior_diagonal(cfg, 0)[0]
+
+
+def test_prior_scale_gives_the_kolmogorov_structure_function():
+    # The absolute scale of the prior: the oracle's spectrum, sampled at many
+    # level frequencies and integrated into the phase structure function
+    # D(r) = 4 pi int (1 - J0(2 pi f r)) psd(f) f df, gives the Kolmogorov
+    # 6.88 (r / r0)^(5/3) for r << L0 (a textbook constant, not the oracle's
+    # formula): this pins the spectral constant and frequencies in cycles per
+    # metre (an angular frequency would be off by (2 pi)^(5/3)).
+    from scipy.special import j0
+    r0 = 0.15
+    f = np.logspace(-7, 5, 6001)
+    psd = np.array([_prior_psd(x, r0, 1e6) for x in f])
+    lnf = np.log(f)
+    for r in (0.02, 0.05, 0.1):
+        D = np.trapezoid(4 * np.pi * (1 - j0(2 * np.pi * f * r)) * psd * f * f, lnf)
+        assert abs(D / (6.88 * (r / r0) ** (5.0 / 3.0)) - 1.0) < 5e-3
+
+
+def test_prior_outer_scale_gives_the_von_karman_variance():
+    # The L0 term: the phase variance int psd 2 pi f df of the oracle's
+    # spectrum is the von Karman 0.0863 (L0 / r0)^(5/3) (textbook), for
+    # outer scales from 10 to 100 m
+    r0 = 0.157
+    f = np.logspace(-7, 5, 6001)
+    lnf = np.log(f)
+    for L0 in (10.0, 25.0, 100.0):
+        psd = np.array([_prior_psd(x, r0, L0) for x in f])
+        var = np.trapezoid(2 * np.pi * psd * f * f, lnf)
+        assert abs(var / (0.0863 * (L0 / r0) ** (5.0 / 3.0)) - 1.0) < 1e-2
+
+
 def test_prior_level_ratio_kolmogorov_limit(systems):
     cfg = get_config("small")
     cfg["prior"]["L0"] = 1e12
