@@ -487,6 +487,8 @@ __device__ __forceinline__ void syn_pass_out(const float* src, int m, const Filt
 // The LDS rows have the odd stride S = RMAX + 1 and the column pass writes its
 // result transposed (Bt[c][t] = x[t][c]), so both passes walk their lines
 // with lanes on consecutive words and strided writes free of bank conflicts.
+// Every global load of the block is issued in one round, before the inner
+// products of beta are reduced.
 template <int RMAX>
 __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const LayerDev* LD, const IoDev* IO,
                                                    const Tile* tiles, Filter F, int src_mode, int out_mode,
@@ -504,24 +506,35 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
   const int off = ly.off;
   const int nt = blockDim.x;
   // every resident coefficient (the R x R top-left block of the Mallat layout:
-  // the coarse block and the detail quadrants of all resident levels) in one
-  // pass, so that all global loads of the block are in flight together
-  constexpr int kUL = 16;
+  // the coarse block and the detail quadrants of all resident levels), kUL
+  // per thread at 1024 threads per workgroup (the launch shape)
+  constexpr int kUL = RMAX * RMAX / 1024 > 0 ? RMAX * RMAX / 1024 : 1;
   BetaLoads<2> bl;
   beta_issue<2>(pr, ps.mode, iter, bl);
-  for (int e0 = threadIdx.x; e0 < R * R; e0 += kUL * nt) {
-    CoefLoad v[kUL];
+  // Loads without branches: every path issues the same loads in the same
+  // order, so that beta's inner products are summed while the block's loads
+  // are in flight (a load under a condition makes the compiler wait for all
+  // of them first).  Indices past the block are clamped; in a plain source
+  // mode all three loads read the source, without p_old the third reads r.
+  const bool plain = ps.mode == SRC_IN || ps.mode == SRC_STATE_C || ps.mode == SRC_PJ;
+  const gptr_f la = (gptr_f)(plain ? ps.src : ps.r);
+  const gptr_f lb = plain ? la : (gptr_f)ps.jinv;
+  const gptr_f lc = ps.mode == SRC_PUPD ? (gptr_f)ps.pold : la;
+  CoefLoad v[kUL];
 #pragma unroll
-    for (int u = 0; u < kUL; ++u) {
-      const int e = e0 + u * nt;
-      if (e < R * R) v[u] = coef_fetch(ps, off + (e >> lr) * n + (e & (R - 1)));
-    }
-    if (e0 == threadIdx.x) ps.beta = beta_reduce<2>(ps.mode, bl);
+  for (int u = 0; u < kUL; ++u) {
+    const int e = min((int)threadIdx.x + u * nt, R * R - 1), g = off + (e >> lr) * n + (e & (R - 1));
+    v[u] = CoefLoad{la[g], lb[g], lc[g]};
+  }
+  ps.beta = beta_reduce<2>(ps.mode, bl);
 #pragma unroll
-    for (int u = 0; u < kUL; ++u) {
-      const int e = e0 + u * nt;
-      if (e < R * R) A[(e >> lr) * S + (e & (R - 1))] = coef_finish(ps, off + (e >> lr) * n + (e & (R - 1)), v[u], true);
-    }
+  for (int u = 0; u < kUL; ++u) {
+    const int e = threadIdx.x + u * nt;
+    if (e < R * R) A[(e >> lr) * S + (e & (R - 1))] = coef_finish(ps, off + (e >> lr) * n + (e & (R - 1)), v[u], true);
+  }
+  for (int e = threadIdx.x + kUL * nt; e < R * R; e += nt) {  // workgroups under 1024 threads only
+    const int g = off + (e >> lr) * n + (e & (R - 1));
+    A[(e >> lr) * S + (e & (R - 1))] = coef_finish(ps, g, coef_fetch(ps, g), true);
   }
   __syncthreads();
   // the last rows pass stores the output itself (layers, caller buffer, or
