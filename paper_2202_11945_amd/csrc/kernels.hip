@@ -115,8 +115,14 @@ __device__ __forceinline__ void slots_reduce(const double* const (&s)[G], const 
   for (int g = 0; g < G; ++g) {
     double a = 0.0;
 #pragma unroll
-    for (int u = 0; u < H; ++u)
-      if (lane + 64 * u < n[g]) a += L.v[g][u];
+    for (int u = 0; u < H; ++u) {
+      // an opaque copy: without it the compiler folds the first addition
+      // into slots_issue's branch, right behind its load, and waits there
+      // for the slot before the kernel's own loads are requested
+      double x = L.v[g][u];
+      asm volatile("" : "+v"(x));
+      if (lane + 64 * u < n[g]) a += x;
+    }
     for (int i = lane + 64 * H; i < n[g]; i += 64) a += ((gptr_d)s[g])[i];
     out[g] = wave_sum(a);
   }
@@ -238,6 +244,22 @@ __device__ __forceinline__ float coef_finish(const PSrc& s, int e, const CoefLoa
   if (owner) ((gptr_w)s.pnew)[e] = p;
   return p;
 }
+
+// Coefficient loads without branches: every path issues the same loads in
+// the same order, so the compiler's wait for the loads a kernel needs first
+// leaves the later ones in flight (with a load under a condition, or a mode
+// branch around it, it waits for all of them).  In a plain source mode all
+// three pointers are the source; without p_old the third is r again (the
+// repeated loads hit the same cache lines).
+struct CoefPtrs {
+  gptr_f a, b, c;
+};
+__device__ __forceinline__ CoefPtrs coef_ptrs(const PSrc& s) {
+  const bool plain = s.mode == SRC_IN || s.mode == SRC_STATE_C || s.mode == SRC_PJ;
+  const gptr_f a = (gptr_f)(plain ? s.src : s.r);
+  return CoefPtrs{a, plain ? a : (gptr_f)s.jinv, s.mode == SRC_PUPD ? (gptr_f)s.pold : a};
+}
+__device__ __forceinline__ CoefLoad coef_load(const CoefPtrs& p, int e) { return CoefLoad{p.a[e], p.b[e], p.c[e]}; }
 
 // beta_k = rho_k / rho_{k-1} in two phases (see slots_issue): beta_issue
 // before a kernel's coefficient loads, beta_reduce once they are in flight;
@@ -511,20 +533,14 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
   constexpr int kUL = RMAX * RMAX / 1024 > 0 ? RMAX * RMAX / 1024 : 1;
   BetaLoads<2> bl;
   beta_issue<2>(pr, ps.mode, iter, bl);
-  // Loads without branches: every path issues the same loads in the same
-  // order, so that beta's inner products are summed while the block's loads
-  // are in flight (a load under a condition makes the compiler wait for all
-  // of them first).  Indices past the block are clamped; in a plain source
-  // mode all three loads read the source, without p_old the third reads r.
-  const bool plain = ps.mode == SRC_IN || ps.mode == SRC_STATE_C || ps.mode == SRC_PJ;
-  const gptr_f la = (gptr_f)(plain ? ps.src : ps.r);
-  const gptr_f lb = plain ? la : (gptr_f)ps.jinv;
-  const gptr_f lc = ps.mode == SRC_PUPD ? (gptr_f)ps.pold : la;
+  // loads without branches (indices past the block clamped), so that beta's
+  // inner products are summed while the block's loads are in flight
+  const CoefPtrs cp = coef_ptrs(ps);
   CoefLoad v[kUL];
 #pragma unroll
   for (int u = 0; u < kUL; ++u) {
-    const int e = min((int)threadIdx.x + u * nt, R * R - 1), g = off + (e >> lr) * n + (e & (R - 1));
-    v[u] = CoefLoad{la[g], lb[g], lc[g]};
+    const int e = min((int)threadIdx.x + u * nt, R * R - 1);
+    v[u] = coef_load(cp, off + (e >> lr) * n + (e & (R - 1)));
   }
   ps.beta = beta_reduce<2>(ps.mode, bl);
 #pragma unroll
@@ -777,29 +793,27 @@ __device__ __forceinline__ void idwt_glob_tile(const ProbDev* P, const LayerDev*
   constexpr int kBand = kGH * kGH, kRounds = (kBand + 63) / 64;
   const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int by = wv >> 1, bx = wv & 1;
+  // loads without branches (window entries past the band clamped)
   float val[kRounds];
   if (wv == 0) {
 #pragma unroll
     for (int u = 0; u < kRounds; ++u) {
-      const int e = lane + 64 * u;
-      if (e < kBand) {
-        const int iy = e / kGH, ix = e - iy * kGH;
-        val[u] = ll[((kr0 + iy) & (half - 1)) * half + ((kc0 + ix) & (half - 1))];
-      }
+      const int e = min(lane + 64 * u, kBand - 1);
+      const int iy = e / kGH, ix = e - iy * kGH;
+      val[u] = ll[((kr0 + iy) & (half - 1)) * half + ((kc0 + ix) & (half - 1))];
     }
   } else {
     CoefLoad v[kRounds];
     int gpos[kRounds];
     BetaLoads<1> bl;
     beta_issue<1>(pr, ps.mode, iter, bl);
+    const CoefPtrs cp = coef_ptrs(ps);
 #pragma unroll
     for (int u = 0; u < kRounds; ++u) {
-      const int e = lane + 64 * u;
-      if (e < kBand) {
-        const int iy = e / kGH, ix = e - iy * kGH;
-        gpos[u] = off + (by * half + ((kr0 + iy) & (half - 1))) * n + bx * half + ((kc0 + ix) & (half - 1));
-        v[u] = coef_fetch(ps, gpos[u]);
-      }
+      const int e = min(lane + 64 * u, kBand - 1);
+      const int iy = e / kGH, ix = e - iy * kGH;
+      gpos[u] = off + (by * half + ((kr0 + iy) & (half - 1))) * n + bx * half + ((kc0 + ix) & (half - 1));
+      v[u] = coef_load(cp, gpos[u]);
     }
     ps.beta = beta_reduce<1>(ps.mode, bl);
 #pragma unroll
@@ -909,38 +923,34 @@ __device__ __forceinline__ void idwt_glob2_tile(const ProbDev* P, const LayerDev
   const int by = wv >> 1, bx = wv & 1;
   // wave 0: the inner coarse window; waves 1 .. 3: the inner and the outer
   // detail windows of band (by, bx), all loads in flight together
+  // loads without branches (window entries past the bands clamped)
   float ival[kIR];
   if (wv == 0) {
 #pragma unroll
     for (int u = 0; u < kIR; ++u) {
-      const int e = lane + 64 * u;
-      if (e < kIB) {
-        const int iy = e / kGI, ix = e - iy * kGI;
-        ival[u] = ll[((jr0 + iy) & (quart - 1)) * quart + ((jc0 + ix) & (quart - 1))];
-      }
+      const int e = min(lane + 64 * u, kIB - 1);
+      const int iy = e / kGI, ix = e - iy * kGI;
+      ival[u] = ll[((jr0 + iy) & (quart - 1)) * quart + ((jc0 + ix) & (quart - 1))];
     }
   } else {
     CoefLoad iv[kIR], ov[kRounds];
     int ipos[kIR], opos[kRounds];
     BetaLoads<1> bl;
     beta_issue<1>(pr, ps.mode, iter, bl);
+    const CoefPtrs cp = coef_ptrs(ps);
 #pragma unroll
     for (int u = 0; u < kIR; ++u) {
-      const int e = lane + 64 * u;
-      if (e < kIB) {
-        const int iy = e / kGI, ix = e - iy * kGI;
-        ipos[u] = off + (by * quart + ((jr0 + iy) & (quart - 1))) * n + bx * quart + ((jc0 + ix) & (quart - 1));
-        iv[u] = coef_fetch(ps, ipos[u]);
-      }
+      const int e = min(lane + 64 * u, kIB - 1);
+      const int iy = e / kGI, ix = e - iy * kGI;
+      ipos[u] = off + (by * quart + ((jr0 + iy) & (quart - 1))) * n + bx * quart + ((jc0 + ix) & (quart - 1));
+      iv[u] = coef_load(cp, ipos[u]);
     }
 #pragma unroll
     for (int u = 0; u < kRounds; ++u) {
-      const int e = lane + 64 * u;
-      if (e < kBand) {
-        const int iy = e / kGH, ix = e - iy * kGH;
-        opos[u] = off + (by * half + ((kr0 + iy) & (half - 1))) * n + bx * half + ((kc0 + ix) & (half - 1));
-        ov[u] = coef_fetch(ps, opos[u]);
-      }
+      const int e = min(lane + 64 * u, kBand - 1);
+      const int iy = e / kGH, ix = e - iy * kGH;
+      opos[u] = off + (by * half + ((kr0 + iy) & (half - 1))) * n + bx * half + ((kc0 + ix) & (half - 1));
+      ov[u] = coef_load(cp, opos[u]);
     }
     ps.beta = beta_reduce<1>(ps.mode, bl);
 #pragma unroll
@@ -1007,9 +1017,13 @@ __global__ __launch_bounds__(256) void k_idwt_glob2(const ProbDev* P, const Laye
 constexpr int kFT = 16;           // output coefficients per direction
 constexpr int kFW = 2 * kFT + 4;  // 36 input samples per direction
 
+// EK: the epilogue as a compile-time constant (the PCG one, so that its
+// loads are straight-line code), or -1 to take it from epi.
+template <int EK>
 __device__ __forceinline__ void fdwt_glob_tile(const ProbDev* P, const LayerDev* LD, const IoDev* IO, const Tile t,
-                                               const Filter F, int epi, int iter, int step, float* X, float* Rw,
+                                               const Filter F, int epi_arg, int iter, int step, float* X, float* Rw,
                                                double* sh) {
+  const int epi = EK >= 0 ? EK : epi_arg;
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[t.mask];  // the global layer index, carried by the tile
   const IoDev& io = IO[t.prob];
@@ -1023,7 +1037,7 @@ __device__ __forceinline__ void fdwt_glob_tile(const ProbDev* P, const LayerDev*
   const int nt = blockDim.x;
   // epilogue positions and operands of this thread's outputs (the 512
   // (row, column) pairs of the column pass, 2 per thread, up to 2 outputs
-  // each), requested before the input window so both latencies overlap
+  // each), requested with the input window so both latencies overlap
   int epos[4];
   EpiLoad el[4];
 #pragma unroll
@@ -1036,26 +1050,31 @@ __device__ __forceinline__ void fdwt_glob_tile(const ProbDev* P, const LayerDev*
     epos[2 * u] = xd ? off + row * n + (half + col) : -1;  // the a output is a detail only right of the coarse block
     epos[2 * u + 1] = off + (half + row) * n + (xd * half + col);
   }
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    if (epos[k] >= 0) el[k] = epi_fetch(pr, io, epi, iter, epos[k]);
-  for (int e0 = threadIdx.x; e0 < kFW * kFW; e0 += kUG * nt) {
+  // loads without branches, the window's first (so that the compiler's wait
+  // for the window leaves the epilogue operands in flight): window entries
+  // past the window are clamped, a missing a output reads the line of the
+  // thread's d output
+  {
     float v[kUG];
 #pragma unroll
     for (int u = 0; u < kUG; ++u) {
-      const int e = e0 + u * nt;
-      if (e < kFW * kFW) {
-        const int ry = e / kFW, rx = e - ry * kFW;
-        v[u] = in[((2 * k0 + ry) & (m - 1)) * istride + ((2 * l0 + rx) & (m - 1))];
-      }
+      const int e = min((int)threadIdx.x + u * nt, kFW * kFW - 1);
+      const int ry = e / kFW, rx = e - ry * kFW;
+      v[u] = in[((2 * k0 + ry) & (m - 1)) * istride + ((2 * l0 + rx) & (m - 1))];
     }
 #pragma unroll
+    for (int k = 0; k < 4; ++k) el[k] = epi_fetch(pr, io, epi, iter, epos[k] >= 0 ? epos[k] : epos[k | 1]);
+#pragma unroll
     for (int u = 0; u < kUG; ++u) {
-      const int e = e0 + u * nt;
+      const int e = threadIdx.x + u * nt;
       if (e < kFW * kFW) {
         const int ry = e / kFW, rx = e - ry * kFW;
         X[ry * XW + rx] = v[u];
       }
+    }
+    for (int e = threadIdx.x + kUG * nt; e < kFW * kFW; e += nt) {  // workgroups under 256 threads only
+      const int ry = e / kFW, rx = e - ry * kFW;
+      X[ry * XW + rx] = in[((2 * k0 + ry) & (m - 1)) * istride + ((2 * l0 + rx) & (m - 1))];
     }
   }
   __syncthreads();
@@ -1114,7 +1133,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   __shared__ float Rw[kFW * (2 * kFT + 1)];
   __shared__ double sh[4];
   const Tile t = my_tile(tiles);
-  fdwt_glob_tile(P, LD, IO, t, F, epi, iter, step, X, Rw, sh);
+  if (epi == EPI_PCG)
+    fdwt_glob_tile<EPI_PCG>(P, LD, IO, t, F, epi, iter, step, X, Rw, sh);
+  else
+    fdwt_glob_tile<-1>(P, LD, IO, t, F, epi, iter, step, X, Rw, sh);
 }
 
 // The first two global levels of a layer in one tile (input side m = n, the
@@ -1130,9 +1152,11 @@ constexpr int kF2 = 8;                 // inner outputs per band and direction
 constexpr int kF1C = 2 * kF2 + 4;      // outer coarse values per direction (20)
 constexpr int kF2W = 2 * kF1C + 4;     // input samples per direction (44)
 
+template <int EK>  // as in fdwt_glob_tile
 __device__ __forceinline__ void fdwt_glob2_tile(const ProbDev* P, const LayerDev* LD, const IoDev* IO, const Tile& t,
-                                                const Filter& F, int epi, int iter, int step, float* X, float* R1,
+                                                const Filter& F, int epi_arg, int iter, int step, float* X, float* R1,
                                                 float* X2, float* R2, double* sh) {
+  const int epi = EK >= 0 ? EK : epi_arg;
   const ProbDev& pr = P[t.prob];
   const LayerDev& ly = LD[t.mask];
   const IoDev& io = IO[t.prob];
@@ -1145,32 +1169,34 @@ __device__ __forceinline__ void fdwt_glob2_tile(const ProbDev* P, const LayerDev
   const int k2 = t.ty * kF2, l2 = t.tx * kF2;  // inner outputs origin
   const int XW = kF2W + 1, R1W = kF1C + kFT + 1, X2W = kF1C + 1, R2W = 2 * kF2 + 1;
   const int nt = blockDim.x;
-  // epilogue positions and operands, requested before the input window:
+  // epilogue positions and operands, requested with the input window:
   // outer details e < 768 (band e / 256: (y low, x high), (y high, x low),
-  // (y high, x high)), three per thread; inner details e < 192, one per thread
+  // (y high, x high)), three per thread; inner details e < 192, one per
+  // thread.  Loads without branches, the window's first, so that the
+  // compiler's wait for the window leaves the epilogue operands in flight (a
+  // thread without an inner output reads the line of its first outer one;
+  // window entries past the window are clamped).
   int p1[3], p2;
   EpiLoad e1[3], e2;
-#pragma unroll
-  for (int u = 0; u < 3; ++u) {
-    const int e = threadIdx.x + u * nt, b = e >> 8, lk = (e & 255) >> 4, lc = e & 15;
-    p1[u] = off + ((b >= 1) * half + k0 + lk) * n + (b != 1) * half + l0 + lc;
-    e1[u] = epi_fetch(pr, io, epi, iter, p1[u]);
-  }
-  {
-    const int e = threadIdx.x, b = e >> 6, lk = (e & 63) >> 3, lc = e & 7;
-    p2 = e < 192 ? off + ((b >= 1) * quart + k2 + lk) * n + (b != 1) * quart + l2 + lc : -1;
-    if (p2 >= 0) e2 = epi_fetch(pr, io, epi, iter, p2);
-  }
   constexpr int kIn = kF2W * kF2W, kUI = (kIn + 255) / 256;
   {
     float v[kUI];
 #pragma unroll
     for (int u = 0; u < kUI; ++u) {
-      const int e = threadIdx.x + u * nt;
-      if (e < kIn) {
-        const int ry = e / kF2W, rx = e - ry * kF2W;
-        v[u] = in[((2 * k0 + ry) & (m - 1)) * istride + ((2 * l0 + rx) & (m - 1))];
-      }
+      const int e = min((int)threadIdx.x + u * nt, kIn - 1);
+      const int ry = e / kF2W, rx = e - ry * kF2W;
+      v[u] = in[((2 * k0 + ry) & (m - 1)) * istride + ((2 * l0 + rx) & (m - 1))];
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int e = threadIdx.x + u * nt, b = e >> 8, lk = (e & 255) >> 4, lc = e & 15;
+      p1[u] = off + ((b >= 1) * half + k0 + lk) * n + (b != 1) * half + l0 + lc;
+      e1[u] = epi_fetch(pr, io, epi, iter, p1[u]);
+    }
+    {
+      const int e = threadIdx.x, b = e >> 6, lk = (e & 63) >> 3, lc = e & 7;
+      p2 = e < 192 ? off + ((b >= 1) * quart + k2 + lk) * n + (b != 1) * quart + l2 + lc : -1;
+      e2 = epi_fetch(pr, io, epi, iter, p2 >= 0 ? p2 : p1[0]);
     }
 #pragma unroll
     for (int u = 0; u < kUI; ++u) {
@@ -1179,6 +1205,10 @@ __device__ __forceinline__ void fdwt_glob2_tile(const ProbDev* P, const LayerDev
         const int ry = e / kF2W, rx = e - ry * kF2W;
         X[ry * XW + rx] = v[u];
       }
+    }
+    for (int e = threadIdx.x + kUI * nt; e < kIn; e += nt) {  // workgroups under 256 threads only
+      const int ry = e / kF2W, rx = e - ry * kF2W;
+      X[ry * XW + rx] = in[((2 * k0 + ry) & (m - 1)) * istride + ((2 * l0 + rx) & (m - 1))];
     }
   }
   __syncthreads();
@@ -1264,10 +1294,17 @@ __global__ __launch_bounds__(256) void k_fdwt_glob2(const ProbDev* P, const Laye
   __shared__ float R2[kF1C * (2 * kF2 + 1)];
   __shared__ double sh[4];
   const Tile t = my_tile(tiles);
-  if (t.pad1)
-    fdwt_glob2_tile(P, LD, IO, t, F, epi, iter, step, X, R1, X2, R2, sh);
-  else
-    fdwt_glob_tile(P, LD, IO, t, F, epi, iter, step, X, R1, sh);
+  if (epi == EPI_PCG) {
+    if (t.pad1)
+      fdwt_glob2_tile<EPI_PCG>(P, LD, IO, t, F, epi, iter, step, X, R1, X2, R2, sh);
+    else
+      fdwt_glob_tile<EPI_PCG>(P, LD, IO, t, F, epi, iter, step, X, R1, sh);
+  } else {
+    if (t.pad1)
+      fdwt_glob2_tile<-1>(P, LD, IO, t, F, epi, iter, step, X, R1, X2, R2, sh);
+    else
+      fdwt_glob_tile<-1>(P, LD, IO, t, F, epi, iter, step, X, R1, sh);
+  }
 }
 
 // ------------------------------------------------ forward DWT, resident part
@@ -1323,15 +1360,20 @@ struct LevelOps<1> {};
 template <int M, int EPI>
 __device__ __forceinline__ void epi_fetch_level(const ProbDev& pr, const IoDev& io, int iter, int off, int n, int R,
                                                 int m0, EpiLoad* l) {
+  // Loads without branches, so that the compiler's waits for one level's
+  // operands leave the later levels' in flight: a thread without an output
+  // at this level (or a level that is not resident) reads the layer's first
+  // coefficient, and the unused first operand of a column in the coarse half
+  // reads the line of its second.
   constexpr int NP = ana_np(M), half = M / 2;
-  if (EPI != EPI_PLAIN && M <= R && M > m0 && (int)threadIdx.x < M * (half / NP)) {
-    const int c = threadIdx.x & (M - 1), K0 = ((int)threadIdx.x >> ilog2c(M)) * NP;
+  if (EPI == EPI_PLAIN) return;
+  const bool act = M <= R && M > m0 && (int)threadIdx.x < M * (half / NP);
+  const int c = threadIdx.x & (M - 1), K0 = ((int)threadIdx.x >> ilog2c(M)) * NP;
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const int k = K0 + p;
-      l[2 * p] = c >= half ? epi_fetch(pr, io, EPI, iter, off + k * n + c) : EpiLoad{0.f, 0.f, 0.f};
-      l[2 * p + 1] = epi_fetch(pr, io, EPI, iter, off + (half + k) * n + c);
-    }
+  for (int p = 0; p < NP; ++p) {
+    const int k = K0 + p;
+    l[2 * p] = epi_fetch(pr, io, EPI, iter, act ? off + (c >= half ? k : half + k) * n + c : off);
+    l[2 * p + 1] = epi_fetch(pr, io, EPI, iter, act ? off + (half + k) * n + c : off);
   }
 }
 template <int M, int EPI>
@@ -1410,28 +1452,37 @@ __global__ __launch_bounds__(1024) void k_fdwt_res(const ProbDev* P, const Layer
   const gptr_f in = (gptr_f)((ng == 0) ? pr.phiadj + off : ((((ng - 1) & 1) ? pr.tmpb : pr.tmpa) + ly.tmp_off));
   const int istride = (ng == 0) ? n : R;
   const int m0 = n >> ly.levels;
-  constexpr int kUL = 16;  // the whole block's loads in flight together
-  for (int e0 = threadIdx.x; e0 < R * R; e0 += kUL * nt) {
-    float v[kUL];
+  // the whole block's loads in flight together, kUL per thread at 1024
+  // threads per workgroup (the launch shape), without branches (indices
+  // past the block clamped): with a load under a condition the compiler
+  // waited for each before the next
+  constexpr int kUL = RMAX * RMAX / 1024 > 0 ? RMAX * RMAX / 1024 : 1;
+  float v[kUL];
+#pragma unroll
+  for (int u = 0; u < kUL; ++u) {
+    const int e = min((int)threadIdx.x + u * nt, R * R - 1);
+    v[u] = in[(e >> lr) * istride + (e & (R - 1))];
+  }
+  auto block_to_lds = [&]() {
 #pragma unroll
     for (int u = 0; u < kUL; ++u) {
-      const int e = e0 + u * nt;
-      if (e < R * R) v[u] = in[(e >> lr) * istride + (e & (R - 1))];
-    }
-#pragma unroll
-    for (int u = 0; u < kUL; ++u) {
-      const int e = e0 + u * nt;
+      const int e = threadIdx.x + u * nt;
       if (e < R * R) A[(e >> lr) * S + (e & (R - 1))] = v[u];
     }
-  }
+    for (int e = threadIdx.x + kUL * nt; e < R * R; e += nt)  // workgroups under 1024 threads only
+      A[(e >> lr) * S + (e & (R - 1))] = in[(e >> lr) * istride + (e & (R - 1))];
+  };
   double acc = 0.0;
   const EpiDst dst = epi_dst(pr, io, iter);
   if constexpr (EPI == EPI_PCG) {
-    LevelOps<RMAX> ops;  // requested before the barrier: one memory round trip for every level
+    // every level's operands requested with the block: one memory round trip
+    LevelOps<RMAX> ops;
     epi_fetch_levels<RMAX, EPI>(pr, io, iter, off, n, R, m0, ops);
+    block_to_lds();
     __syncthreads();
     epi_levels<RMAX, S, EPI>(ly, dst, A, B, R, m0, F, ops, acc);
   } else {
+    block_to_lds();
     {
       OneLevelOps<RMAX> top;
       epi_fetch_level<RMAX, EPI>(pr, io, iter, off, n, R, m0, top.l);
@@ -2562,19 +2613,19 @@ __global__ __launch_bounds__(256) void k_update(const ProbDev* P, const IoDev* I
   const int nn[5] = {nr, pr.n_slots_fdwt, C ? C[t.prob].n_slots : 0, nrm, XM == UPD_X_PAIR ? pr.n_slots_fdwt : 0};
   SlotLoads<5, 2> sloads;
   slots_issue<5, 2>(sl, nn, sloads);
+  // loads without branches (indices clamped to the chunk), so that the slot
+  // sums below wait only for the slots
 #pragma unroll
   for (int u = 0; u < V; ++u) {
-    const int e = e0 + threadIdx.x + u * 256;
-    if (e < e1) {
-      if (XM != UPD_X_DEFER) {
-        xp[u] = x[e];
-        pp[u] = p[e];
-      }
-      if (XM == UPD_X_PAIR) pq[u] = pm[e];
-      rr[u] = r[e];
-      qq[u] = q[e];
-      jj[u] = jv[e];
+    const int e = min(e0 + (int)threadIdx.x + u * 256, e1 - 1);
+    if (XM != UPD_X_DEFER) {
+      xp[u] = x[e];
+      pp[u] = p[e];
     }
+    if (XM == UPD_X_PAIR) pq[u] = pm[e];
+    rr[u] = r[e];
+    qq[u] = q[e];
+    jj[u] = jv[e];
   }
   // alpha = rho_k / pi_k
   double o[5];
