@@ -1568,45 +1568,53 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
   const bool own = threadIdx.x < kTileS * kTileS && i < N && j < N;
   typedef const int __attribute__((address_space(1)))* gptr_i;
   typedef const unsigned char __attribute__((address_space(1)))* gptr_u8;
-  int ci = -1, si = 0;
-  bool isact = false;
-  float dsx = 0.f, dsy = 0.f, cb0 = 0.f, cb1 = 0.f, cb2 = 0.f;
-  if (own) {
-    if (mode == PG_COMPACT || mode == PG_POL_IN) {  // the compact slope index
-      ci = ((gptr_i)pr.cmap)[w.m_off + i * N + j];
-      isact = ci >= 0;
-    } else {  // the active flag alone
-      isact = ((gptr_u8)pr.amap)[w.m_off + i * N + j] != 0;
-    }
-    si = ((gptr_i)pr.srow)[w.rb_off + i] + j;  // row-span position (valid when active)
-    if (mode == PG_RESID_IN) {  // data residual s - A phi (s placed by the slopes input kernel)
-      const gptr_f sd = (gptr_f)(pr.sd + w.sp_off);
-      const int sc = min(max(si, 0), w.sp_len - 1);  // in range whatever the flag (used only when active)
-      dsx = sd[sc];
-      dsy = sd[w.sp_len + sc];
-    } else if (mode == PG_POL_IN && ci >= 0) {  // measured slopes of the active subaperture
-      dsx = ((gptr_f)io.in)[w.cs_off + ci];
-      dsy = ((gptr_f)io.in)[w.cs_off + w.n_active + ci];
-    }
-    if (w.blocks) {
-      const gptr_f cb = (gptr_f)(pr.cinv + w.cinv_off + 3 * (i * N + j));
-      cb0 = cb[0];
-      cb1 = cb[1];
-      cb2 = cb[2];
-    }
+  // Loads without branches (a subaperture past the grid reads the grid's
+  // last one, used only when owned; without 2 x 2 blocks the block loads read
+  // the layers' first values, unused), so that the compiler does not wait for
+  // them before the table loads below are requested.
+  const int ib = min(i, N - 1), jb = min(j, N - 1);
+  int ci = -1;
+  bool isact;
+  if (mode == PG_COMPACT || mode == PG_POL_IN) {  // the compact slope index
+    const int cv = ((gptr_i)pr.cmap)[w.m_off + ib * N + jb];
+    ci = own ? cv : -1;
+    isact = ci >= 0;
+  } else {  // the active flag alone
+    const int av = ((gptr_u8)pr.amap)[w.m_off + ib * N + jb];
+    isact = own & (av != 0);
   }
+  const int si = ((gptr_i)pr.srow)[w.rb_off + ib] + j;  // row-span position (valid when active)
+  float dsx = 0.f, dsy = 0.f;
+  if (mode == PG_RESID_IN) {  // data residual s - A phi (s placed by the slopes input kernel)
+    const gptr_f sd = (gptr_f)(pr.sd + w.sp_off);
+    const int sc = min(max(si, 0), w.sp_len - 1);  // in range whatever the flag (used only when active)
+    dsx = sd[sc];
+    dsy = sd[w.sp_len + sc];
+  } else if (mode == PG_POL_IN) {  // measured slopes of the active subaperture
+    const int cc = max(ci, 0);
+    dsx = ((gptr_f)io.in)[w.cs_off + cc];
+    dsy = ((gptr_f)io.in)[w.cs_off + w.n_active + cc];
+  }
+  const gptr_f cb = (gptr_f)(w.blocks ? pr.cinv + w.cinv_off + 3 * (ib * N + jb) : phi);
+  const float cb0 = cb[0], cb1 = cb[1], cb2 = cb[2];
   // corners: thread t takes window corners t and t + 256 (the second only for
   // t < 33); the loads of both go out together.  Raw buffer loads: lane
   // offsets from the corner (ic, jc) and the cell, wave-uniform offsets from
   // the layer, so no per-load address arithmetic (no range limit: the tables
   // and cells are valid by construction).
+  // The table and node loads are issued without branches, so that the
+  // compiler's waits for one group's tables leave nothing else behind them:
+  // a thread's second corner past the window reads the window's last
+  // corner's entries, a group's layers past the last read the last layer
+  // (both then add nothing), and corners outside the grid have table
+  // entries (0, 0), the layer's first cell.
   constexpr int kCorn = (CW * CW + kSensThreads - 1) / kSensThreads;
   int vi[kCorn], vj[kCorn];
   bool cin[kCorn];
 #pragma unroll
   for (int u = 0; u < kCorn; ++u) {
-    const int e = threadIdx.x + u * kSensThreads;
-    const int lci = e / CW, lcj = e - lci * CW;
+    const int e = threadIdx.x + u * kSensThreads, ec = min(e, CW * CW - 1);
+    const int lci = ec / CW, lcj = ec - lci * CW;
     const int ic = i0 + lci, jc = j0 + lcj;
     cin[u] = e < CW * CW && ic < nc && jc < nc;
     vi[u] = lci * (int)sizeof(int2);         // the corner's row entry of a layer's tables
@@ -1618,59 +1626,62 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
   auto ld = [](__amdgpu_buffer_rsrc_t rs, int vo, int so) {  // so: wave-uniform (stated, or the
     return __builtin_amdgcn_raw_buffer_load_b32(rs, vo, __builtin_amdgcn_readfirstlane(so), 0);  // load loops)
   };
+  // the corner values, KC corners per thread: wave 0 takes the window's
+  // second corners as well (its first 33 lanes), the other waves one each
   float v[kCorn];
 #pragma unroll
   for (int u = 0; u < kCorn; ++u) v[u] = 0.f;
-  for (int l0 = 0; l0 < pr.L; l0 += kLG) {
-    int lof[kLG], nl[kLG];
-#pragma unroll
-    for (int k = 0; k < kLG; ++k) {
-      const int l = min(l0 + k, pr.L - 1);
-      const LayerDev& ly = LD[t.mask + l];
-      lof[k] = ly.off;
-      nl[k] = ly.n;
-    }
-    int cell[kCorn][kLG];
-    float wy[kCorn][kLG], wx[kCorn][kLG];
-#pragma unroll
-    for (int u = 0; u < kCorn; ++u)
+  auto corners = [&](auto kc) {
+    constexpr int KC = decltype(kc)::value;
+    for (int l0 = 0; l0 < pr.L; l0 += kLG) {
+      int lof[kLG], nl[kLG];
 #pragma unroll
       for (int k = 0; k < kLG; ++k) {
-        cell[u][k] = 0;
-        wy[u][k] = wx[u][k] = 0.f;
-        if (cin[u] && l0 + k < pr.L) {
-          const int so = (l0 + k) * 2 * CW * (int)sizeof(int2);
+        const int l = min(l0 + k, pr.L - 1);
+        const LayerDev& ly = LD[t.mask + l];
+        lof[k] = ly.off;
+        nl[k] = ly.n;
+      }
+      int cell[KC][kLG];
+      float wy[KC][kLG], wx[KC][kLG];
+#pragma unroll
+      for (int u = 0; u < KC; ++u)
+#pragma unroll
+        for (int k = 0; k < kLG; ++k) {
+          const int so = min(l0 + k, pr.L - 1) * 2 * CW * (int)sizeof(int2);
           const auto ry = __builtin_amdgcn_raw_buffer_load_b64(trs, vi[u], __builtin_amdgcn_readfirstlane(so), 0);
           const auto rx = __builtin_amdgcn_raw_buffer_load_b64(trs, vj[u], __builtin_amdgcn_readfirstlane(so), 0);
           cell[u][k] = lof[k] + (int)ry[0] * nl[k] + (int)rx[0];
           wy[u][k] = __uint_as_float(ry[1]);
           wx[u][k] = __uint_as_float(rx[1]);
         }
-      }
-    float nd[kCorn][kLG][4];
+      float nd[KC][kLG][4];
 #pragma unroll
-    for (int u = 0; u < kCorn; ++u)
+      for (int u = 0; u < KC; ++u)
 #pragma unroll
-      for (int k = 0; k < kLG; ++k) {
-        nd[u][k][0] = nd[u][k][1] = nd[u][k][2] = nd[u][k][3] = 0.f;
-        if (cin[u] && l0 + k < pr.L) {
+        for (int k = 0; k < kLG; ++k) {
           const int vo = cell[u][k] * (int)sizeof(float), so = nl[k] * (int)sizeof(float);
           nd[u][k][0] = __uint_as_float(ld(prs, vo, 0));
           nd[u][k][1] = __uint_as_float(ld(prs, vo + (int)sizeof(float), 0));
           nd[u][k][2] = __uint_as_float(ld(prs, vo, so));
           nd[u][k][3] = __uint_as_float(ld(prs, vo + (int)sizeof(float), so));
         }
-      }
 #pragma unroll
-    for (int u = 0; u < kCorn; ++u)
+      for (int u = 0; u < KC; ++u)
 #pragma unroll
-      for (int k = 0; k < kLG; ++k)
-        if (cin[u] && l0 + k < pr.L) {
+        for (int k = 0; k < kLG; ++k) {
           const float top = (1.f - wx[u][k]) * nd[u][k][0] + wx[u][k] * nd[u][k][1];
           const float bot = (1.f - wx[u][k]) * nd[u][k][2] + wx[u][k] * nd[u][k][3];
-          v[u] += (1.f - wy[u][k]) * top + wy[u][k] * bot;
+          const float vn = v[u] + ((1.f - wy[u][k]) * top + wy[u][k] * bot);
+          v[u] = cin[u] && l0 + k < pr.L ? vn : v[u];
         }
-  }
+    }
+  };
+  static_assert(kCorn == 2 && CW * CW - kSensThreads <= 64, "second corners in wave 0 only");
+  if (__builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) == 0)
+    corners(std::integral_constant<int, 2>{});
+  else
+    corners(std::integral_constant<int, 1>{});
 #pragma unroll
   for (int u = 0; u < kCorn; ++u) {
     const int e = threadIdx.x + u * kSensThreads;
@@ -1723,8 +1734,9 @@ __global__ __launch_bounds__(kSensThreads) __attribute__((amdgpu_waves_per_eu(8)
 // the sensor adjoint reads).  A workgroup takes 2 x 2 such tiles, thread t
 // subaperture (t / 16, t mod 16) of each, so all its loads are in flight
 // together; each tile's sums are formed as over a workgroup of its own.
+template <int ADD>  // add the mirrors' slope response already in the slope buffer (closed loop)
 __global__ __launch_bounds__(256) void k_slopes_in(const ProbDev* P, const WfsDev* WD, const IoDev* IO,
-                                                   const Tile* tiles, int add) {
+                                                   const Tile* tiles) {
   __shared__ float sh[16 * 4];
   typedef const int __attribute__((address_space(1)))* gptr_i;
   const Tile t = my_tile(tiles);
@@ -1739,36 +1751,60 @@ __global__ __launch_bounds__(256) void k_slopes_in(const ProbDev* P, const WfsDe
   const gptr_w sd = (gptr_w)(pr.sd + w.sp_off);
   const gptr_i srow = (gptr_i)(pr.srow + w.rb_off);
   const int cs0 = w.cs_off, cs1 = w.cs_off + w.n_active;
+  // Loads without per-subaperture branches (indices past the grid or of an
+  // inactive subaperture clamped, their values unused), so that the
+  // compiler's waits do not hold each map load before the next is requested.
   int pos[4], ci[4], si[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int i = (2 * t.ty + (u >> 1)) * kTileS + li, j = (2 * t.tx + (u & 1)) * kTileS + lj;
-    pos[u] = (i < N && j < N) ? i * N + j : -1;
-    ci[u] = pos[u] >= 0 ? cmap[pos[u]] : -1;
-    si[u] = pos[u] >= 0 ? srow[i] + j : 0;  // row-span position (valid when active)
+    const bool in_grid = i < N && j < N;
+    const int ib = min(i, N - 1), jb = min(j, N - 1);
+    const int cv = cmap[ib * N + jb], sr = srow[ib];
+    pos[u] = in_grid ? i * N + j : -1;
+    ci[u] = in_grid ? cv : -1;
+    si[u] = min(max(sr + j, 0), w.sp_len - 1);  // row-span position (the right one when active)
   }
+  // the slopes (and their mirror part) first; the 2 x 2 blocks, under a
+  // branch of their own, last, so that its waits hold nothing else back
   float sx[4], sy[4], c0[4], c1[4], c2[4], ox[4], oy[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    sx[u] = sy[u] = c0[u] = c1[u] = c2[u] = ox[u] = oy[u] = 0.f;
-    if (ci[u] >= 0) {
-      if (add) {  // the mirrors' slope response already in the slope buffer (closed loop)
-        ox[u] = ((gptr_f)sd)[si[u]];
-        oy[u] = ((gptr_f)sd)[w.sp_len + si[u]];
-      }
-      sx[u] = in[cs0 + ci[u]];
-      sy[u] = in[cs1 + ci[u]];
-      if (w.blocks) {
-        c0[u] = cinv[3 * pos[u]];
-        c1[u] = cinv[3 * pos[u] + 1];
-        c2[u] = cinv[3 * pos[u] + 2];
-      }
+    const int cc = max(ci[u], 0);
+    sx[u] = in[cs0 + cc];
+    sy[u] = in[cs1 + cc];
+    ox[u] = oy[u] = 0.f;
+    if (ADD) {
+      ox[u] = ((gptr_f)sd)[si[u]];
+      oy[u] = ((gptr_f)sd)[w.sp_len + si[u]];
     }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) c0[u] = c1[u] = c2[u] = 0.f;
+  if (w.blocks) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int pc = 3 * max(pos[u], 0);
+      c0[u] = cinv[pc];
+      c1[u] = cinv[pc + 1];
+      c2[u] = cinv[pc + 2];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const bool act = ci[u] >= 0;
+    sx[u] = act ? sx[u] : 0.f;
+    sy[u] = act ? sy[u] : 0.f;
+    ox[u] = act ? ox[u] : 0.f;
+    oy[u] = act ? oy[u] : 0.f;
+    c0[u] = act ? c0[u] : 0.f;
+    c1[u] = act ? c1[u] : 0.f;
+    c2[u] = act ? c2[u] : 0.f;
   }
   float a[16];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    if (add) {  // s + Gamma P a^(i-1), the sum the propagation kernel forms in one pass
+    if (ADD) {  // s + Gamma P a^(i-1), the sum the propagation kernel forms in one pass
       sx[u] = sx[u] + ox[u];
       sy[u] = sy[u] + oy[u];
     }
@@ -3083,7 +3119,11 @@ void launch_pgamma(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode)
 #undef FEWHA_PG
 }
 void launch_slopes_in(const LaunchArgs& a, const Tile* tiles, int ntiles, int add) {
-  if (ntiles > 0) k_slopes_in<<<ntiles, 256, 0, a.stream>>>(a.P, a.W, a.IO, tiles, add);
+  if (ntiles <= 0) return;
+  if (add)
+    k_slopes_in<1><<<ntiles, 256, 0, a.stream>>>(a.P, a.W, a.IO, tiles);
+  else
+    k_slopes_in<0><<<ntiles, 256, 0, a.stream>>>(a.P, a.W, a.IO, tiles);
 }
 void launch_gammaT(const LaunchArgs& a, const Tile* tiles, int ntiles, int mode) {
   if (ntiles > 0) k_gammaT<<<ntiles, 256, 0, a.stream>>>(a.P, a.W, tiles, a.gtrows, mode);
