@@ -503,6 +503,50 @@ __device__ __forceinline__ void syn_pass_out(const float* src, int m, const Filt
   }
 }
 
+// The same passes for a level side M known at compile time: NP output
+// pairs per task (one task per thread at 1024 threads), so a thread's taps
+// are read in one straight sequence (with the run length chosen at run time
+// the compiler waited for the first LDS reads before issuing the rest).
+template <int S, int M>
+__device__ __forceinline__ void syn_pass_m(const float* src, float* dst, const Filter& F) {
+  constexpr int half = M / 2, np = M * half / 1024 > 1 ? M * half / 1024 : 1, nch = half / np;
+  constexpr int lm = __builtin_ctz(M);
+  static_assert(np <= 8, "at most 8 output pairs per task");
+  for (int task = threadIdx.x; task < M * nch; task += blockDim.x) {
+    const int l = task & (M - 1), K0 = (task >> lm) * np;
+    syn_line<np, S>(src + l, half, K0, F, dst + l * S + 2 * K0);
+  }
+}
+template <int S, int M>
+__device__ __forceinline__ void syn_pass_out_m(const float* src, const Filter& F, float* g, int gs, float scale,
+                                               bool vec) {
+  constexpr int half = M / 2, np = M * half / 1024 > 1 ? M * half / 1024 : 1, nch = half / np;
+  constexpr int lm = __builtin_ctz(M);
+  static_assert(np <= 8, "at most 8 output pairs per task");
+  typedef v4f __attribute__((address_space(1)))* gw4;
+  typedef float __attribute__((address_space(1)))* gw1;
+  for (int task = threadIdx.x; task < M * nch; task += blockDim.x) {
+    const int l = task & (M - 1), K0 = (task >> lm) * np;
+    float o[2 * np];
+    syn_line<np, S>(src + l, half, K0, F, o);
+    float* dst = g + (long)l * gs + 2 * K0;
+    if (np >= 2 && vec) {
+#pragma unroll
+      for (int i = 0; i < np / 2; ++i)
+        ((gw4)dst)[i] = v4f{o[4 * i] * scale, o[4 * i + 1] * scale, o[4 * i + 2] * scale, o[4 * i + 3] * scale};
+    } else {
+#pragma unroll
+      for (int i = 0; i < 2 * np; ++i) ((gw1)dst)[i] = o[i] * scale;
+    }
+  }
+}
+// f(std::integral_constant<int, M>) for M = M0, 2 M0, ..., MMAX in turn.
+template <int M, int MMAX, class Fn>
+__device__ __forceinline__ void for_sides(Fn&& f) {
+  f(std::integral_constant<int, M>{});
+  if constexpr (M < MMAX) for_sides<2 * M, MMAX>(f);
+}
+
 // One workgroup per (problem, layer): all synthesis levels whose output side
 // is at most the layer's resident side R (<= RMAX, the LDS capacity of the
 // instantiation) run in LDS.  Columns then rows, periodic, Mallat layout.
@@ -561,16 +605,19 @@ __global__ __launch_bounds__(1024) void k_idwt_res(const ProbDev* P, const Layer
   float* gout = n != R ? pr.tmpa + ly.tmp_off : ((out_mode == OUT_PHI ? pr.phi : io.out) + off);
   const int gs = n != R ? R : n;
   const bool vec = (((uintptr_t)gout) & 15) == 0;
-  for (int m = 2 * m0; m <= R; m <<= 1) {
-    syn_pass<S>(A, B, m, F);  // columns (along y): A[t][c] -> B[c][t]
+  const float oscale = n != R ? 1.f : ly.inv_delta;
+  for_sides<2, RMAX>([&](auto side) {  // the levels of output side M = 2 m0 .. R
+    constexpr int M = decltype(side)::value;
+    if (M < 2 * m0 || M > R) return;
+    syn_pass_m<S, M>(A, B, F);  // columns (along y): A[t][c] -> B[c][t]
     __syncthreads();
-    if (m == R && direct) {
-      syn_pass_out<S>(B, m, F, gout, gs, n != R ? 1.f : ly.inv_delta, vec);
+    if (M == R && direct) {
+      syn_pass_out_m<S, M>(B, F, gout, gs, oscale, vec);
     } else {
-      syn_pass<S>(B, A, m, F);  // rows (along x): B[c][r] = row r of the level -> A[r][c]
+      syn_pass_m<S, M>(B, A, F);  // rows (along x): B[c][r] = row r of the level -> A[r][c]
       __syncthreads();
     }
-  }
+  });
   if (direct) return;
   if (n == R) {
     const OutDst od = out_dst(pr, io, out_mode);
