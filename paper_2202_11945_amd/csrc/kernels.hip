@@ -909,19 +909,29 @@ __device__ __forceinline__ void idwt_glob_passes(const ProbDev& pr, const IoDev&
         o[u] = out_fetch(od, off + (t0 + (e >> 5)) * n + s0 + (e & 31));
       }
     }
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    // the outputs in pairs, both taps' reads ahead of the store branch
+    // (with the branch after every output, the compiler waited for each
+    // output's LDS reads before issuing the next's)
+    auto row_out = [&](int u) {
       const int e = e0 + u * nt;
       const int lt = e >> 5, ls = e & 31;
       const int par = ls & 1, k = ((ls - par) >> 1) + 2;
       const float* Br = B + lt * W1;
-      const float acc = F.h[par] * Br[k] + F.h[par + 2] * Br[k - 1] + F.h[par + 4] * Br[k - 2] +
-                        F.g[par] * Br[kGH + k] + F.g[par + 2] * Br[kGH + k - 1] + F.g[par + 4] * Br[kGH + k - 2];
-      const int row = t0 + lt, col = s0 + ls;
-      if (final_level)
-        out_finish(od, off + row * n + col, acc * g.inv_delta, o[u]);
-      else
-        nxt[row * m + col] = acc;
+      return F.h[par] * Br[k] + F.h[par + 2] * Br[k - 1] + F.h[par + 4] * Br[k - 2] + F.g[par] * Br[kGH + k] +
+             F.g[par + 2] * Br[kGH + k - 1] + F.g[par + 4] * Br[kGH + k - 2];
+    };
+    static_assert(kU % 2 == 0, "outputs in pairs");
+#pragma unroll
+    for (int u = 0; u < kU; u += 2) {
+      const float a[2] = {row_out(u), row_out(u + 1)};
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int e = e0 + (u + v) * nt;
+        if (final_level)
+          out_finish(od, off + (t0 + (e >> 5)) * n + s0 + (e & 31), a[v] * g.inv_delta, o[u + v]);
+        else
+          nxt[(t0 + (e >> 5)) * m + s0 + (e & 31)] = a[v];
+      }
     }
   }
 }
